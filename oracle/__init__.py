@@ -1,0 +1,195 @@
+"""FP64 CPU oracle for the differentiable tile-splatting step (test infrastructure).
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
+import this package.  It shares no code with the HIP path: the C library in
+``gs_oracle.c`` is compiled with gcc, and this module only marshals NumPy
+arrays into it.  Every input arrives as FP32 from the seeded generators and
+is widened exactly to FP64 here.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gs_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+TILE = 16
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (IEEE FP64, no fast-math, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=False)
+        _lib = ctypes.CDLL(_LIB)
+        _lib.or_bin_count.restype = ctypes.c_int64
+        _lib.or_tile_rect.restype = ctypes.c_int64
+        _lib.or_tile_rect.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int64,
+                                      ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+    return _lib
+
+
+def _p(a):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None else ctypes.c_void_p(0)
+
+
+def _d(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def cam_array(cam) -> np.ndarray:
+    """Flatten a camera into the oracle's double[22] layout (exact widening)."""
+    return np.concatenate([
+        np.array([cam.fx, cam.fy, cam.cx, cam.cy, cam.near_z, cam.tan_half_fov_x, cam.tan_half_fov_y],
+                 np.float32).astype(np.float64),
+        np.asarray(cam.R_cw, np.float32).astype(np.float64).reshape(9),
+        np.asarray(cam.t_cw, np.float32).astype(np.float64).reshape(3),
+        np.asarray(cam.bg, np.float32).astype(np.float64).reshape(3)])
+
+
+def num_threads() -> int:
+    return int(_load().or_num_threads())
+
+
+def sh_basis(deg: int, d) -> tuple[np.ndarray, np.ndarray]:
+    """Real SH basis Y_j(d) (j < (deg+1)^2) and its gradient dY_j/dd."""
+    d = _d(d).reshape(3)
+    nc = (deg + 1) ** 2
+    Y = np.zeros(nc)
+    G = np.zeros((nc, 3))
+    _load().or_sh_basis(ctypes.c_int(deg), _p(d), _p(Y), _p(G))
+    return Y, G
+
+
+def tile_rect(u: float, v: float, r: int, W: int, H: int):
+    rect = np.zeros(4, np.int32)
+    cnt = _load().or_tile_rect(float(u), float(v), int(r), int(W), int(H), _p(rect))
+    return int(cnt), rect
+
+
+def project(scene, cam):
+    """Per-Gaussian projection in FP64.  Returns dict with rec[n][9]
+    (u, v, A, B, C, o, r, g, b), depth, radius, rect[n][4], tiles_touched, flags."""
+    n = scene.n
+    means, ls, q, lg, sh = (_d(scene.means), _d(scene.log_scales), _d(scene.quats),
+                            _d(scene.logits), _d(scene.sh))
+    rec = np.zeros((n, 9))
+    depth = np.zeros(n)
+    radius = np.zeros(n, np.int32)
+    rect = np.zeros((n, 4), np.int32)
+    tt = np.zeros(n, np.int64)
+    flags = np.zeros(n, np.uint8)
+    ca = cam_array(cam)
+    rc = _load().or_project(ctypes.c_int64(n), ctypes.c_int(scene.sh_degree), _p(means), _p(ls), _p(q),
+                            _p(lg), _p(sh), _p(ca), ctypes.c_int(cam.width), ctypes.c_int(cam.height),
+                            _p(rec), _p(depth), _p(radius), _p(rect), _p(tt), _p(flags))
+    if rc != 0:
+        raise ValueError(f"or_project failed: {rc}")
+    return dict(rec=rec, depth=depth, radius=radius, rect=rect, tiles_touched=tt, flags=flags)
+
+
+def bin_sort(u, v, radius, depth_f32, W: int, H: int):
+    """Tile binning and (tile, depth bits, index) sort on FP32-valued inputs.
+    Returns (point_list uint32[K], ranges uint32[T][2], tiles_touched int64[n], offsets int64[n])."""
+    u = _d(u); v = _d(v)
+    radius = np.ascontiguousarray(radius, np.int32)
+    bits = np.ascontiguousarray(np.asarray(depth_f32, np.float32)).view(np.uint32)
+    n = u.shape[0]
+    tt = np.zeros(n, np.int64)
+    off = np.zeros(n, np.int64)
+    lib = _load()
+    K = lib.or_bin_count(ctypes.c_int64(n), _p(u), _p(v), _p(radius), ctypes.c_int(W), ctypes.c_int(H),
+                         _p(tt), _p(off))
+    ntiles = ((W + TILE - 1) // TILE) * ((H + TILE - 1) // TILE)
+    pl = np.zeros(max(K, 1), np.uint32)
+    ranges = np.zeros((ntiles, 2), np.uint32)
+    rc = lib.or_bin_sort(ctypes.c_int64(n), _p(u), _p(v), _p(radius), _p(bits), ctypes.c_int(W),
+                         ctypes.c_int(H), ctypes.c_int64(K), _p(pl), _p(ranges))
+    if rc != 0:
+        raise RuntimeError(f"or_bin_sort failed: {rc}")
+    return pl[:K], ranges, tt, off
+
+
+def render_fwd(rec, point_list, ranges, cam, margin: float = 1e-4, tile_mask=None):
+    """Front-to-back compositing per pixel.  Returns image[3][H][W], final_T[H][W],
+    n_contrib[H][W] (int32) and per-pixel decision flags."""
+    W, H = cam.width, cam.height
+    rec = _d(rec)
+    pl = np.ascontiguousarray(point_list, np.uint32)
+    rg = np.ascontiguousarray(ranges, np.uint32)
+    bg = np.asarray(cam.bg, np.float32).astype(np.float64)
+    image = np.zeros((3, H, W))
+    fT = np.zeros((H, W))
+    nc = np.zeros((H, W), np.int32)
+    fl = np.zeros((H, W), np.uint8)
+    tm = None if tile_mask is None else np.ascontiguousarray(tile_mask, np.uint8)
+    _load().or_render_fwd(ctypes.c_int(W), ctypes.c_int(H), _p(rec), _p(pl if pl.size else np.zeros(1, np.uint32)),
+                          _p(rg), _p(bg), ctypes.c_double(margin), _p(tm), _p(image), _p(fT), _p(nc), _p(fl))
+    return image, fT, nc, fl
+
+
+def render_bwd(rec, point_list, ranges, cam, dL_dimage, tile_mask=None):
+    """Gradient of sum(dL_dimage * image) w.r.t. the records: g2d[n][9]."""
+    W, H = cam.width, cam.height
+    rec = _d(rec)
+    n = rec.shape[0]
+    pl = np.ascontiguousarray(point_list, np.uint32)
+    rg = np.ascontiguousarray(ranges, np.uint32)
+    bg = np.asarray(cam.bg, np.float32).astype(np.float64)
+    G = _d(dL_dimage)
+    g2d = np.zeros((n, 9))
+    tm = None if tile_mask is None else np.ascontiguousarray(tile_mask, np.uint8)
+    _load().or_render_bwd(ctypes.c_int(W), ctypes.c_int(H), ctypes.c_int64(n), _p(rec),
+                          _p(pl if pl.size else np.zeros(1, np.uint32)), _p(rg), _p(bg), _p(G), _p(tm), _p(g2d))
+    return g2d
+
+
+def project_bwd(scene, cam, g2d):
+    """Chain rule from record gradients g2d[n][9] to the raw parameters."""
+    n = scene.n
+    means, ls, q, lg, sh = (_d(scene.means), _d(scene.log_scales), _d(scene.quats),
+                            _d(scene.logits), _d(scene.sh))
+    g = dict(means=np.zeros_like(means), log_scales=np.zeros_like(ls), quats=np.zeros_like(q),
+             logits=np.zeros_like(lg), sh=np.zeros_like(sh))
+    ca = cam_array(cam)
+    rc = _load().or_project_bwd(ctypes.c_int64(n), ctypes.c_int(scene.sh_degree), _p(means), _p(ls), _p(q),
+                                _p(lg), _p(sh), _p(ca), _p(_d(g2d)), _p(g["means"]), _p(g["log_scales"]),
+                                _p(g["quats"]), _p(g["logits"]), _p(g["sh"]))
+    if rc != 0:
+        raise ValueError(f"or_project_bwd failed: {rc}")
+    return g
+
+
+def forward(scene, cam, margin: float = 1e-4):
+    """Whole forward in FP64: project -> bin/sort on the FP64 projection -> render.
+    The sort key is the FP64 depth rounded to FP32 bits (the binning reading)."""
+    pr = project(scene, cam)
+    rec = pr["rec"]
+    pl, ranges, tt, off = bin_sort(rec[:, 0], rec[:, 1], pr["radius"], pr["depth"].astype(np.float32),
+                                   cam.width, cam.height)
+    image, fT, nc, fl = render_fwd(rec, pl, ranges, cam, margin)
+    return dict(proj=pr, point_list=pl, ranges=ranges, image=image, final_T=fT, n_contrib=nc, pix_flags=fl)
+
+
+def backward(scene, cam, fwd, dL_dimage):
+    """Whole backward in FP64 from dL/dimage to the raw parameters."""
+    g2d = render_bwd(fwd["proj"]["rec"], fwd["point_list"], fwd["ranges"], cam, dL_dimage)
+    grads = project_bwd(scene, cam, g2d)
+    grads["g2d"] = g2d
+    return grads

@@ -1,0 +1,711 @@
+/*
+ * gs_oracle.c -- plain FP64 CPU oracle for the differentiable tile-splatting
+ * step of 3D Gaussian Splatting (BalanceGS, arXiv 2510.14564, Sec. II-A).
+ *
+ * TEST INFRASTRUCTURE.  Only the tests, the smoke check and the CPU-baseline
+ * leg of the benchmark may load this library.  It shares no code, header,
+ * table or constant with the HIP path; the two meet only through the seeded
+ * input arrays.  It is deliberately plain: one Gaussian or one pixel at a time,
+ * no blocking and no fusion; OpenMP only spreads independent items over cores.
+ *
+ * What it computes (each function cites the passage it follows):
+ *   - the Gaussian kernel G(x) = exp(-1/2 (x-mu)^T Sigma^-1 (x-mu))   (Sec. II-A)
+ *   - EWA projection Sigma' = J W Sigma W^T J^T                        (Sec. II-A)
+ *   - colour from SH coefficients                                      (Sec. I, Sec. II-A)
+ *   - 16x16 pixel tiles sharing one Gaussian list                      (Sec. IV-C.1)
+ *   - Gaussians sorted by depth per tile                               (Sec. II-A)
+ *   - front-to-back blending C = sum c_i a_i prod_{j<i}(1 - a_j)       (Sec. II-A)
+ *   - the exact analytic derivative of all of the above (training).
+ * The paper is silent on the parameterisation, the Jacobian's form, the
+ * low-pass dilation, the radius rule, the tile rectangle, tie-breaks, the
+ * alpha thresholds and the SH basis; the readings used are spelled out next to
+ * the code that applies them.
+ *
+ * Camera array (double[22]):
+ *   0 fx, 1 fy, 2 cx, 3 cy, 4 near_z, 5 tan_half_fov_x, 6 tan_half_fov_y,
+ *   7..15 R_cw row-major, 16..18 t_cw, 19..21 bg.
+ * Record array (double[n][9]): u, v, A, B, C, opacity, r, g, b.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_TILE 16
+#define OR_ALPHA_MIN (1.0 / 255.0)
+#define OR_ALPHA_MAX 0.99
+#define OR_T_MIN 1e-4
+#define OR_DILATION 0.3
+#define OR_SLOPE_LIMIT 1.3
+#define OR_RADIUS_MAX 4194304.0 /* 2^22 px: larger footprints are culled */
+
+/* ------------------------------------------------------------------ helpers */
+
+static int64_t floor_div(int64_t a, int64_t b) { /* b > 0, rounds toward -inf */
+    int64_t q = a / b;
+    if ((a % b != 0) && (a < 0)) q -= 1;
+    return q;
+}
+
+/* Rotation matrix of a unit quaternion (w, x, y, z), row-major. */
+static void quat_to_rot(const double q[4], double R[9]) {
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z);     R[2] = 2 * (x * z + w * y);
+    R[3] = 2 * (x * y + w * z);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+    R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
+}
+
+/* d R / d q_k for a quaternion q (no normalisation), row-major 3x3 each. */
+static void quat_rot_jac(const double q[4], double dR[4][9]) {
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    /* d/dw */
+    double a[9] = {0, -2 * z, 2 * y, 2 * z, 0, -2 * x, -2 * y, 2 * x, 0};
+    /* d/dx */
+    double b[9] = {0, 2 * y, 2 * z, 2 * y, -4 * x, -2 * w, 2 * z, 2 * w, -4 * x};
+    /* d/dy */
+    double c[9] = {-4 * y, 2 * x, 2 * w, 2 * x, 0, 2 * z, -2 * w, 2 * z, -4 * y};
+    /* d/dz */
+    double d[9] = {-4 * z, -2 * w, 2 * x, 2 * w, -4 * z, 2 * y, 2 * x, 2 * y, 0};
+    memcpy(dR[0], a, sizeof a); memcpy(dR[1], b, sizeof b);
+    memcpy(dR[2], c, sizeof c); memcpy(dR[3], d, sizeof d);
+}
+
+/* ------------------------------------------------------------- SH basis ---
+ * Real spherical harmonics with the Condon-Shortley phase kept, ordered by l
+ * then m = -l..l (reading of "SH coefficients", Sec. I / Sec. II-A):
+ *   m = 0 : N_l^0 P_l(z)
+ *   m > 0 : sqrt2 N_l^m (-1)^m P_l^(m)(z) Re((x + i y)^m)
+ *   m < 0 : sqrt2 N_l^|m| (-1)^|m| P_l^(|m|)(z) Im((x + i y)^|m|)
+ * with N_l^m = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!) and P_l^(k) the k-th
+ * derivative of the Legendre polynomial, from Rodrigues' formula
+ * P_l = 1/(2^l l!) d^l/dz^l (z^2 - 1)^l.  For a unit direction (x, y, z),
+ * (1 - z^2)^(m/2) e^{i m phi} = (x + i y)^m, which gives the polynomial form.
+ * Every constant is derived here at run time; none is typed in.
+ */
+#define OR_MAXL 3
+static double g_legendre[OR_MAXL + 1][2 * OR_MAXL + 2]; /* coefficients of P_l in z^k */
+static double g_norm[OR_MAXL + 1][OR_MAXL + 1];          /* N_l^m */
+static int g_sh_ready = 0;
+
+static double factorial(int k) { double f = 1; for (int i = 2; i <= k; ++i) f *= i; return f; }
+
+static void sh_init(void) {
+    if (g_sh_ready) return;
+    for (int l = 0; l <= OR_MAXL; ++l) {
+        /* (z^2 - 1)^l = sum_j C(l,j) (-1)^(l-j) z^(2j) */
+        double poly[2 * OR_MAXL + 2];
+        memset(poly, 0, sizeof poly);
+        for (int j = 0; j <= l; ++j)
+            poly[2 * j] = factorial(l) / (factorial(j) * factorial(l - j)) * (((l - j) & 1) ? -1.0 : 1.0);
+        /* differentiate l times */
+        for (int t = 0; t < l; ++t)
+            for (int k = 0; k < 2 * OR_MAXL + 1; ++k) poly[k] = (k + 1) * poly[k + 1];
+        double s = 1.0 / (pow(2.0, l) * factorial(l));
+        for (int k = 0; k < 2 * OR_MAXL + 2; ++k) g_legendre[l][k] = poly[k] * s;
+        for (int m = 0; m <= l; ++m)
+            g_norm[l][m] = sqrt((2.0 * l + 1.0) / (4.0 * M_PI) * factorial(l - m) / factorial(l + m));
+    }
+    g_sh_ready = 1;
+}
+
+/* k-th derivative of P_l at z */
+static double legendre_deriv(int l, int k, double z) {
+    double acc = 0.0;
+    for (int p = 2 * OR_MAXL + 1; p >= k; --p) {
+        double c = g_legendre[l][p];
+        for (int t = 0; t < k; ++t) c *= (double)(p - t);
+        acc = acc * z + c;   /* Horner in z over powers p-k */
+    }
+    return acc;
+}
+
+/* (x + i y)^m and its partial derivatives in x and y */
+static void cpow_xy(double x, double y, int m, double* re, double* im) {
+    double r = 1.0, i = 0.0;
+    for (int k = 0; k < m; ++k) { double nr = r * x - i * y; double ni = r * y + i * x; r = nr; i = ni; }
+    *re = r; *im = i;
+}
+
+/* Y_j(d) for j < (deg+1)^2 and, if grad != NULL, dY_j/dd (3 per j). */
+static void sh_eval(int deg, const double d[3], double* Y, double* grad) {
+    sh_init();
+    double x = d[0], y = d[1], z = d[2];
+    int j = 0;
+    for (int l = 0; l <= deg; ++l) {
+        for (int m = -l; m <= l; ++m, ++j) {
+            int am = m < 0 ? -m : m;
+            double K = (am == 0 ? 1.0 : sqrt(2.0)) * g_norm[l][am] * ((am & 1) ? -1.0 : 1.0);
+            double P = legendre_deriv(l, am, z);
+            double dP = legendre_deriv(l, am + 1, z);
+            double re, im, re1 = 0, im1 = 0;
+            cpow_xy(x, y, am, &re, &im);
+            if (am > 0) cpow_xy(x, y, am - 1, &re1, &im1);
+            double ang, dang_dx, dang_dy;
+            if (m >= 0) { ang = re; dang_dx = am * re1; dang_dy = -am * im1; }
+            else        { ang = im; dang_dx = am * im1; dang_dy = am * re1; }
+            Y[j] = K * P * ang;
+            if (grad) {
+                grad[3 * j + 0] = K * P * dang_dx;
+                grad[3 * j + 1] = K * P * dang_dy;
+                grad[3 * j + 2] = K * dP * ang;
+            }
+        }
+    }
+}
+
+/* exported for the basis pins */
+void or_sh_basis(int deg, const double* d, double* Y, double* grad) { sh_eval(deg, d, Y, grad); }
+
+/* -------------------------------------------------------- tile rectangle ---
+ * Reading of "16x16 pixel blocks that share the same set of Gaussians"
+ * (Sec. IV-C.1): a Gaussian belongs to every tile that meets the closed square
+ * [u-r, u+r] x [v-r, v+r]; tile (tx, ty) covers pixels [16tx, 16tx+16) x
+ * [16ty, 16ty+16).  With r an integer, floor((u +- r)/16) equals
+ * floor((floor(u) +- r)/16), which is evaluated in integers.  Returns the
+ * number of tiles and writes x0, x1, y0, y1.
+ */
+static int64_t tile_rect(double u, double v, int64_t r, int W, int H, int32_t rect[4]) {
+    int64_t tx = (W + OR_TILE - 1) / OR_TILE, ty = (H + OR_TILE - 1) / OR_TILE;
+    rect[0] = 0; rect[1] = -1; rect[2] = 0; rect[3] = -1;
+    if (r <= 0 || !isfinite(u) || !isfinite(v)) return 0;
+    if (u < -(double)r || u >= (double)(OR_TILE * tx + r)) return 0;
+    if (v < -(double)r || v >= (double)(OR_TILE * ty + r)) return 0;
+    int64_t fu = (int64_t)floor(u), fv = (int64_t)floor(v);
+    int64_t x0 = floor_div(fu - r, OR_TILE), x1 = floor_div(fu + r, OR_TILE);
+    int64_t y0 = floor_div(fv - r, OR_TILE), y1 = floor_div(fv + r, OR_TILE);
+    if (x0 < 0) x0 = 0;
+    if (y0 < 0) y0 = 0;
+    if (x1 > tx - 1) x1 = tx - 1;
+    if (y1 > ty - 1) y1 = ty - 1;
+    if (x0 > x1 || y0 > y1) return 0;
+    rect[0] = (int32_t)x0; rect[1] = (int32_t)x1; rect[2] = (int32_t)y0; rect[3] = (int32_t)y1;
+    return (x1 - x0 + 1) * (y1 - y0 + 1);
+}
+
+int64_t or_tile_rect(double u, double v, int64_t r, int W, int H, int32_t* rect) {
+    return tile_rect(u, v, r, W, H, rect);
+}
+
+/* ---------------------------------------------------------- projection ----
+ * Per Gaussian (Sec. II-A):
+ *   opacity o = sigmoid(logit); q^ = q/|q|; Sigma = R(q^) diag(e^s)^2 R(q^)^T
+ *   t = W mu + t_cw with W = R_cw (viewing transform)
+ *   J = [[fx/tz, 0, -fx sx/tz], [0, fy/tz, -fy sy/tz]] with slopes
+ *       s = clamp(t_xy/tz, +-1.3 tan_half_fov) (first-order pinhole Jacobian)
+ *   Sigma' = J W Sigma W^T J^T + 0.3 I  (low-pass dilation, a reading)
+ *   conic = Sigma'^-1 (A, B, C) = (S11, -S01, S00)/det, culled if det <= 0
+ *   r = ceil(3 sqrt(lambda_max)), lambda_max = m + sqrt(max(0.1, m^2 - det))
+ *   (u, v) = (fx tx/tz + cx, fy ty/tz + cy)
+ *   colour_k = max(0, sum_j Y_j(d) f_jk + 1/2), d = unit(mu - camera centre)
+ * Culled (radius 0, no tiles): tz <= near_z, non-finite values, det <= 0,
+ * radius above 2^22 px.
+ * flags bit0: 3 sqrt(lambda_max) lies within a relative 2e-5 of an integer
+ * (an FP32 evaluation may round the radius the other way);
+ * flags bit1: tz within a relative 1e-5 of near_z; bit2: a slope within 1e-5 of
+ * its clamp; bit3: an SH colour within 1e-6 of its clamp at 0.
+ */
+typedef struct {
+    double o, qn[4], qnorm, R[9], S[3], Sigma[9];
+    double t[3], sx, sy, clampx, clampy, J[6], T[6], Sp[3] /*a b c*/, det;
+    double d[3], dirlen, Y[16], raw[3];
+    int culled, radius;
+} or_gauss_state;
+
+static int project_one(int deg, const double* p_mean, const double* p_ls, const double* p_q, double logit,
+                       const double* p_sh /* [nc][3] gathered */, const double* cam,
+                       or_gauss_state* st, double rec[9], double* depth, uint8_t* flag) {
+    const double fx = cam[0], fy = cam[1], cx = cam[2], cy = cam[3], near_z = cam[4];
+    const double* W = cam + 7; const double* tcw = cam + 16;
+    memset(st, 0, sizeof *st);
+    *flag = 0;
+    for (int k = 0; k < 9; ++k) rec[k] = 0.0;
+    *depth = 0.0;
+    st->culled = 1;
+
+    st->o = 1.0 / (1.0 + exp(-logit));
+    double qn2 = p_q[0] * p_q[0] + p_q[1] * p_q[1] + p_q[2] * p_q[2] + p_q[3] * p_q[3];
+    st->qnorm = sqrt(qn2);
+    for (int k = 0; k < 4; ++k) st->qn[k] = p_q[k] / st->qnorm;
+    quat_to_rot(st->qn, st->R);
+    for (int k = 0; k < 3; ++k) st->S[k] = exp(p_ls[k]);
+    /* Sigma = R S S^T R^T */
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double s = 0;
+            for (int k = 0; k < 3; ++k) s += st->R[3 * i + k] * st->S[k] * st->S[k] * st->R[3 * j + k];
+            st->Sigma[3 * i + j] = s;
+        }
+    for (int i = 0; i < 3; ++i)
+        st->t[i] = W[3 * i] * p_mean[0] + W[3 * i + 1] * p_mean[1] + W[3 * i + 2] * p_mean[2] + tcw[i];
+    double tz = st->t[2];
+    if (!(tz > near_z) || !isfinite(tz)) {
+        if (isfinite(tz) && fabs(tz - near_z) <= 1e-5 * near_z) *flag |= 2;
+        return 0;
+    }
+    if (fabs(tz - near_z) <= 1e-5 * near_z) *flag |= 2;
+    double limx = OR_SLOPE_LIMIT * cam[5], limy = OR_SLOPE_LIMIT * cam[6];
+    double rx = st->t[0] / tz, ry = st->t[1] / tz;
+    st->sx = rx; st->sy = ry; st->clampx = 0; st->clampy = 0;
+    if (rx > limx) { st->sx = limx; st->clampx = 1; }
+    if (rx < -limx) { st->sx = -limx; st->clampx = 1; }
+    if (ry > limy) { st->sy = limy; st->clampy = 1; }
+    if (ry < -limy) { st->sy = -limy; st->clampy = 1; }
+    if (fabs(fabs(rx) - limx) <= 1e-5 * limx || fabs(fabs(ry) - limy) <= 1e-5 * limy) *flag |= 4;
+    st->J[0] = fx / tz; st->J[1] = 0; st->J[2] = -fx * st->sx / tz;
+    st->J[3] = 0; st->J[4] = fy / tz; st->J[5] = -fy * st->sy / tz;
+    /* T = J W (2x3) */
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 3; ++j)
+            st->T[3 * i + j] = st->J[3 * i] * W[j] + st->J[3 * i + 1] * W[3 + j] + st->J[3 * i + 2] * W[6 + j];
+    /* Sigma' = T Sigma T^T */
+    double Sp[4];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+            double s = 0;
+            for (int k = 0; k < 3; ++k)
+                for (int l = 0; l < 3; ++l) s += st->T[3 * i + k] * st->Sigma[3 * k + l] * st->T[3 * j + l];
+            Sp[2 * i + j] = s;
+        }
+    double a = Sp[0] + OR_DILATION, b = Sp[1], c = Sp[3] + OR_DILATION;
+    st->Sp[0] = a; st->Sp[1] = b; st->Sp[2] = c;
+    double det = a * c - b * b;
+    st->det = det;
+    if (!(det > 0.0) || !isfinite(det)) return 0;
+    double A = c / det, B = -b / det, C = a / det;
+    double mid = 0.5 * (a + c);
+    double lam = mid + sqrt(fmax(0.1, mid * mid - det));
+    double r3 = 3.0 * sqrt(lam);
+    if (!isfinite(r3) || r3 > OR_RADIUS_MAX) return 0;
+    double rr = ceil(r3);
+    if (fabs(r3 - nearbyint(r3)) <= 2e-5 * fmax(1.0, r3)) *flag |= 1;
+    double u = fx * st->t[0] / tz + cx, v = fy * st->t[1] / tz + cy;
+    /* colour */
+    double cc[3];
+    for (int i = 0; i < 3; ++i) cc[i] = -(W[i] * tcw[0] + W[3 + i] * tcw[1] + W[6 + i] * tcw[2]);
+    double dir[3] = {p_mean[0] - cc[0], p_mean[1] - cc[1], p_mean[2] - cc[2]};
+    st->dirlen = sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+    for (int k = 0; k < 3; ++k) st->d[k] = dir[k] / st->dirlen;
+    int nc = (deg + 1) * (deg + 1);
+    sh_eval(deg, st->d, st->Y, NULL);
+    double rgb[3];
+    for (int ch = 0; ch < 3; ++ch) {
+        double s = 0.0;
+        for (int j = 0; j < nc; ++j) s += st->Y[j] * p_sh[3 * j + ch];
+        st->raw[ch] = s + 0.5;
+        rgb[ch] = st->raw[ch] > 0.0 ? st->raw[ch] : 0.0;
+        if (fabs(st->raw[ch]) <= 1e-6) *flag |= 8;
+    }
+    rec[0] = u; rec[1] = v; rec[2] = A; rec[3] = B; rec[4] = C; rec[5] = st->o;
+    rec[6] = rgb[0]; rec[7] = rgb[1]; rec[8] = rgb[2];
+    for (int k = 0; k < 9; ++k)
+        if (!isfinite(rec[k])) { for (int q = 0; q < 9; ++q) rec[q] = 0.0; return 0; }
+    *depth = tz;
+    st->culled = 0;
+    st->radius = (int)rr;
+    return (int)rr;
+}
+
+static void gather_params(int64_t n, int64_t i, int deg, const double* means, const double* ls,
+                          const double* quats, const double* sh,
+                          double m[3], double s[3], double q[4], double* shg) {
+    for (int k = 0; k < 3; ++k) { m[k] = means[k * n + i]; s[k] = ls[k * n + i]; }
+    for (int k = 0; k < 4; ++k) q[k] = quats[k * n + i];
+    int nc = (deg + 1) * (deg + 1);
+    for (int j = 0; j < nc; ++j)
+        for (int ch = 0; ch < 3; ++ch) shg[3 * j + ch] = sh[(3 * j + ch) * n + i];
+}
+
+/* Project every Gaussian.  rect is [n][4] (x0, x1, y0, y1); tiles_touched[n]. */
+int or_project(int64_t n, int deg, const double* means, const double* log_scales, const double* quats,
+               const double* logits, const double* sh, const double* cam, int W, int H,
+               double* rec, double* depth, int32_t* radius, int32_t* rect, int64_t* tiles_touched,
+               uint8_t* flags) {
+    if (n < 0 || deg < 0 || deg > OR_MAXL || W <= 0 || H <= 0) return -1;
+    sh_init();
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double m[3], s[3], q[4], shg[48];
+        or_gauss_state st;
+        gather_params(n, i, deg, means, log_scales, quats, sh, m, s, q, shg);
+        uint8_t fl;
+        int r = project_one(deg, m, s, q, logits[i], shg, cam, &st, rec + 9 * i, depth + i, &fl);
+        radius[i] = r;
+        flags[i] = fl;
+        tiles_touched[i] = tile_rect(rec[9 * i], rec[9 * i + 1], r, W, H, rect + 4 * i);
+        if (tiles_touched[i] == 0) radius[i] = r; /* radius kept; no tiles */
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------ bin + sort ---
+ * Sec. II-A: the Gaussians contributing to a pixel are taken in depth order;
+ * Sec. IV-C.1: 16x16 tiles share one list.  Readings: entries are emitted in
+ * index order (rows y0..y1, columns x0..x1 within a row) at the exclusive
+ * prefix sum of tiles_touched, then sorted by (tile, FP32 depth bits, index),
+ * which is a total order; empty tiles get (S_t, S_t).
+ */
+typedef struct { uint32_t tile, key, idx; } or_entry;
+
+static int entry_cmp(const void* pa, const void* pb) {
+    const or_entry* a = (const or_entry*)pa;
+    const or_entry* b = (const or_entry*)pb;
+    if (a->tile != b->tile) return a->tile < b->tile ? -1 : 1;
+    if (a->key != b->key) return a->key < b->key ? -1 : 1;
+    if (a->idx != b->idx) return a->idx < b->idx ? -1 : 1;
+    return 0;
+}
+
+/* Number of (tile, Gaussian) pairs for the given FP32-valued projection. */
+int64_t or_bin_count(int64_t n, const double* u, const double* v, const int32_t* radius, int W, int H,
+                     int64_t* tiles_touched, int64_t* offsets) {
+    int64_t total = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t rect[4];
+        tiles_touched[i] = tile_rect(u[i], v[i], radius[i], W, H, rect);
+        offsets[i] = total;
+        total += tiles_touched[i];
+    }
+    return total;
+}
+
+/* point_list[K], ranges[T][2]; depth_bits are the FP32 bit patterns of depth. */
+int or_bin_sort(int64_t n, const double* u, const double* v, const int32_t* radius,
+                const uint32_t* depth_bits, int W, int H, int64_t K,
+                uint32_t* point_list, uint32_t* ranges) {
+    int64_t tx = (W + OR_TILE - 1) / OR_TILE, ty = (H + OR_TILE - 1) / OR_TILE;
+    int64_t ntiles = tx * ty;
+    or_entry* e = (or_entry*)malloc(sizeof(or_entry) * (size_t)(K > 0 ? K : 1));
+    if (!e) return -2;
+    int64_t off = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t rect[4];
+        int64_t cnt = tile_rect(u[i], v[i], radius[i], W, H, rect);
+        if (cnt == 0) continue;
+        for (int y = rect[2]; y <= rect[3]; ++y)
+            for (int x = rect[0]; x <= rect[1]; ++x) {
+                if (off >= K) { free(e); return -3; }
+                e[off].tile = (uint32_t)(y * tx + x);
+                e[off].key = depth_bits[i];
+                e[off].idx = (uint32_t)i;
+                ++off;
+            }
+    }
+    if (off != K) { free(e); return -3; }
+    qsort(e, (size_t)K, sizeof(or_entry), entry_cmp);
+    for (int64_t m = 0; m < K; ++m) point_list[m] = e[m].idx;
+    /* ranges by linear scan */
+    int64_t m = 0;
+    for (int64_t t = 0; t < ntiles; ++t) {
+        ranges[2 * t] = (uint32_t)m;
+        while (m < K && e[m].tile == (uint32_t)t) ++m;
+        ranges[2 * t + 1] = (uint32_t)m;
+    }
+    free(e);
+    return 0;
+}
+
+/* ------------------------------------------------------- forward render ---
+ * Sec. II-A blending, per pixel, over the tile's depth-sorted list:
+ *   power = -1/2 (A dx^2 + C dy^2) - B dx dy, (dx, dy) = (u, v) - pixel centre,
+ *   with the pixel centre at (x + 0.5, y + 0.5) (reading);
+ *   alpha = min(0.99, o e^power); entries with power > 0 or alpha < 1/255 are
+ *   skipped; if T (1 - alpha) < 1e-4 the walk stops before blending (reading);
+ *   otherwise C += c alpha T, T *= (1 - alpha), n_contrib = position + 1.
+ *   out = C + T bg.
+ * Pixel flags: bit0 alpha within rel. `margin` of 1/255, bit1 T' within rel.
+ * `margin` of 1e-4, bit2 o e^power within rel. `margin` of 0.99.
+ * tile_mask (optional): only tiles with a non-zero byte are rendered.
+ */
+int or_render_fwd(int W, int H, const double* rec, const uint32_t* point_list, const uint32_t* ranges,
+                  const double* bg, double margin, const uint8_t* tile_mask,
+                  double* image, double* final_T, int32_t* n_contrib, uint8_t* pix_flags) {
+    int64_t tx = (W + OR_TILE - 1) / OR_TILE, ty = (H + OR_TILE - 1) / OR_TILE;
+    int64_t HW = (int64_t)W * H;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < tx * ty; ++t) {
+        if (tile_mask && !tile_mask[t]) continue;
+        int64_t x0 = (t % tx) * OR_TILE, y0 = (t / tx) * OR_TILE;
+        uint32_t s = ranges[2 * t], e = ranges[2 * t + 1];
+        for (int64_t py = y0; py < y0 + OR_TILE && py < H; ++py)
+            for (int64_t px = x0; px < x0 + OR_TILE && px < W; ++px) {
+                double T = 1.0, acc[3] = {0, 0, 0};
+                int32_t nc = 0;
+                uint8_t fl = 0;
+                double cxp = px + 0.5, cyp = py + 0.5;
+                for (uint32_t m = s; m < e; ++m) {
+                    const double* g = rec + 9 * (int64_t)point_list[m];
+                    double dx = g[0] - cxp, dy = g[1] - cyp;
+                    double power = -0.5 * (g[2] * dx * dx + g[4] * dy * dy) - g[3] * dx * dy;
+                    if (power > 0.0) continue;
+                    double og = g[5] * exp(power);
+                    if (fabs(og - OR_ALPHA_MAX) <= margin * OR_ALPHA_MAX) fl |= 4;
+                    double alpha = og < OR_ALPHA_MAX ? og : OR_ALPHA_MAX;
+                    if (fabs(alpha - OR_ALPHA_MIN) <= margin * OR_ALPHA_MIN) fl |= 1;
+                    if (alpha < OR_ALPHA_MIN) continue;
+                    double Tn = T * (1.0 - alpha);
+                    if (fabs(Tn - OR_T_MIN) <= margin * OR_T_MIN) fl |= 2;
+                    if (Tn < OR_T_MIN) break;
+                    for (int ch = 0; ch < 3; ++ch) acc[ch] += g[6 + ch] * alpha * T;
+                    T = Tn;
+                    nc = (int32_t)(m - s + 1);
+                }
+                int64_t p = py * W + px;
+                for (int ch = 0; ch < 3; ++ch) image[ch * HW + p] = acc[ch] + T * bg[ch];
+                final_T[p] = T;
+                n_contrib[p] = nc;
+                if (pix_flags) pix_flags[p] = fl;
+            }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------ backward render ---
+ * Exact derivative of the blending above with the set of blended entries held
+ * fixed (skips and the stop are piecewise-constant decisions).  For blended
+ * entry m of a pixel with upstream gradient G:
+ *   dL/dc_m   = alpha_m T_m G
+ *   dL/dalpha = sum_k G_k (c_mk T_m - S_mk/(1 - alpha_m)),
+ *               S_m = sum_{j>m, blended} c_j alpha_j T_j + T_final bg
+ *   alpha = o e^power (unclamped branch): dL/do = e^power dL/dalpha,
+ *   dL/dpower = alpha dL/dalpha; on the clamped branch both are 0.
+ *   dL/du = dL/dpower (-A dx - B dy), dL/dv = dL/dpower (-B dx - C dy)
+ *   dL/dA = -dx^2/2 dL/dpower, dL/dB = -dx dy dL/dpower, dL/dC = -dy^2/2 dL/dpower
+ * The oracle recomputes the forward per pixel itself, keeps the blended list,
+ * and forms S_m as an explicit suffix sum.  g2d is [n][9] in record order
+ * (u, v, A, B, C, o, r, g, b) and is overwritten.
+ */
+int or_render_bwd(int W, int H, int64_t n, const double* rec, const uint32_t* point_list,
+                  const uint32_t* ranges, const double* bg, const double* dL_dimage,
+                  const uint8_t* tile_mask, double* g2d) {
+    int64_t tx = (W + OR_TILE - 1) / OR_TILE, ty = (H + OR_TILE - 1) / OR_TILE;
+    int64_t HW = (int64_t)W * H;
+    memset(g2d, 0, sizeof(double) * 9 * (size_t)n);
+#pragma omp parallel
+    {
+        int cap = 1024;
+        uint32_t* lst = (uint32_t*)malloc(sizeof(uint32_t) * cap);
+        double* al = (double*)malloc(sizeof(double) * cap);
+        double* Ts = (double*)malloc(sizeof(double) * cap);
+        double* ex = (double*)malloc(sizeof(double) * cap);
+        double* dxs = (double*)malloc(sizeof(double) * cap);
+        double* dys = (double*)malloc(sizeof(double) * cap);
+        uint8_t* clamped = (uint8_t*)malloc(cap);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t t = 0; t < tx * ty; ++t) {
+            if (tile_mask && !tile_mask[t]) continue;
+            int64_t x0 = (t % tx) * OR_TILE, y0 = (t / tx) * OR_TILE;
+            uint32_t s = ranges[2 * t], e = ranges[2 * t + 1];
+            if ((int64_t)(e - s) > cap) {
+                cap = (int)(e - s);
+                lst = (uint32_t*)realloc(lst, sizeof(uint32_t) * cap);
+                al = (double*)realloc(al, sizeof(double) * cap);
+                Ts = (double*)realloc(Ts, sizeof(double) * cap);
+                ex = (double*)realloc(ex, sizeof(double) * cap);
+                dxs = (double*)realloc(dxs, sizeof(double) * cap);
+                dys = (double*)realloc(dys, sizeof(double) * cap);
+                clamped = (uint8_t*)realloc(clamped, cap);
+            }
+            for (int64_t py = y0; py < y0 + OR_TILE && py < H; ++py)
+                for (int64_t px = x0; px < x0 + OR_TILE && px < W; ++px) {
+                    int64_t p = py * W + px;
+                    double G[3] = {dL_dimage[p], dL_dimage[HW + p], dL_dimage[2 * HW + p]};
+                    double cxp = px + 0.5, cyp = py + 0.5;
+                    /* forward walk, remembering the blended entries */
+                    int nb = 0;
+                    double T = 1.0;
+                    for (uint32_t m = s; m < e; ++m) {
+                        const double* g = rec + 9 * (int64_t)point_list[m];
+                        double dx = g[0] - cxp, dy = g[1] - cyp;
+                        double power = -0.5 * (g[2] * dx * dx + g[4] * dy * dy) - g[3] * dx * dy;
+                        if (power > 0.0) continue;
+                        double eg = exp(power);
+                        double og = g[5] * eg;
+                        double alpha = og < OR_ALPHA_MAX ? og : OR_ALPHA_MAX;
+                        if (alpha < OR_ALPHA_MIN) continue;
+                        double Tn = T * (1.0 - alpha);
+                        if (Tn < OR_T_MIN) break;
+                        lst[nb] = point_list[m]; al[nb] = alpha; Ts[nb] = T; ex[nb] = eg;
+                        dxs[nb] = dx; dys[nb] = dy; clamped[nb] = !(og < OR_ALPHA_MAX);
+                        ++nb;
+                        T = Tn;
+                    }
+                    /* suffix sums S_m, walking back */
+                    double S[3] = {T * bg[0], T * bg[1], T * bg[2]};
+                    for (int k = nb - 1; k >= 0; --k) {
+                        const double* g = rec + 9 * (int64_t)lst[k];
+                        double a = al[k], Tm = Ts[k];
+                        double dc[3], dalpha = 0.0;
+                        for (int ch = 0; ch < 3; ++ch) {
+                            dc[ch] = a * Tm * G[ch];
+                            dalpha += G[ch] * (g[6 + ch] * Tm - S[ch] / (1.0 - a));
+                        }
+                        double dpow = 0.0, dop = 0.0;
+                        if (!clamped[k]) { dop = ex[k] * dalpha; dpow = a * dalpha; }
+                        double dx = dxs[k], dy = dys[k];
+                        double gr[9];
+                        gr[0] = dpow * (-g[2] * dx - g[3] * dy);
+                        gr[1] = dpow * (-g[3] * dx - g[4] * dy);
+                        gr[2] = -0.5 * dx * dx * dpow;
+                        gr[3] = -dx * dy * dpow;
+                        gr[4] = -0.5 * dy * dy * dpow;
+                        gr[5] = dop;
+                        gr[6] = dc[0]; gr[7] = dc[1]; gr[8] = dc[2];
+                        double* out = g2d + 9 * (int64_t)lst[k];
+                        for (int q = 0; q < 9; ++q) {
+#pragma omp atomic
+                            out[q] += gr[q];
+                        }
+                        for (int ch = 0; ch < 3; ++ch) S[ch] += g[6 + ch] * a * Tm;
+                    }
+                }
+        }
+        free(lst); free(al); free(Ts); free(ex); free(dxs); free(dys); free(clamped);
+    }
+    return 0;
+}
+
+/* ----------------------------------------------------- projection backward --
+ * Exact chain rule through the projection above, per Gaussian, from the
+ * record gradient g2d[9] to the raw parameters.  Steps:
+ *   colour: clamp mask, dL/df_jk = Y_j(d) dL/dc_k, dL/dd = sum f_jk grad Y_j,
+ *           then mu via (I - d d^T)/|mu - c|;
+ *   opacity: dL/dlogit = dL/do o (1 - o);
+ *   conic: d(S^-1) = -S^-1 dS S^-1 with the symmetric conic gradient
+ *          [[gA, gB/2], [gB/2, gC]];
+ *   Sigma' = T Sigma T^T (T = J W): dL/dSigma = T^T G T, dL/dT = 2 G T Sigma;
+ *   dL/dJ = dL/dT W^T; J(t) with the clamp mask on the slopes; u, v -> t;
+ *   t = W mu + t_cw -> dL/dmu += W^T dL/dt;
+ *   Sigma = M M^T, M = R S: dL/dM = 2 dL/dSigma M, dL/ds_i = (R^T dL/dM)_ii S_i,
+ *   dL/dR = dL/dM S, dL/dq^ through R(q^), dL/dq = (I - q^ q^^T) dL/dq^ / |q|.
+ * Culled Gaussians get zero gradients.  Outputs use the parameter layouts.
+ */
+int or_project_bwd(int64_t n, int deg, const double* means, const double* log_scales, const double* quats,
+                   const double* logits, const double* sh, const double* cam, const double* g2d,
+                   double* g_means, double* g_log_scales, double* g_quats, double* g_logits, double* g_sh) {
+    if (n < 0 || deg < 0 || deg > OR_MAXL) return -1;
+    sh_init();
+    const double fx = cam[0], fy = cam[1];
+    const double* W = cam + 7;
+    int nc = (deg + 1) * (deg + 1);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double m[3], s[3], q[4], shg[48], rec[9], depth;
+        uint8_t fl;
+        or_gauss_state st;
+        gather_params(n, i, deg, means, log_scales, quats, sh, m, s, q, shg);
+        project_one(deg, m, s, q, logits[i], shg, cam, &st, rec, &depth, &fl);
+        double gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gl = 0;
+        double gsh[48];
+        memset(gsh, 0, sizeof gsh);
+        if (!st.culled) {
+            const double* g = g2d + 9 * i;
+            /* colour */
+            double Y[16], dY[48];
+            sh_eval(deg, st.d, Y, dY);
+            double gd[3] = {0, 0, 0};
+            for (int ch = 0; ch < 3; ++ch) {
+                double gc = st.raw[ch] >= 0.0 ? g[6 + ch] : 0.0;
+                for (int j = 0; j < nc; ++j) {
+                    gsh[3 * j + ch] = Y[j] * gc;
+                    for (int k = 0; k < 3; ++k) gd[k] += gc * shg[3 * j + ch] * dY[3 * j + k];
+                }
+            }
+            double dd = st.d[0] * gd[0] + st.d[1] * gd[1] + st.d[2] * gd[2];
+            for (int k = 0; k < 3; ++k) gm[k] += (gd[k] - st.d[k] * dd) / st.dirlen;
+            /* opacity */
+            gl = g[5] * st.o * (1.0 - st.o);
+            /* conic -> Sigma' : dL/dS' = -S'^-1 Gc S'^-1 */
+            double Ci[4] = {rec[2], rec[3], rec[3], rec[4]};
+            double Gc[4] = {g[2], 0.5 * g[3], 0.5 * g[3], g[4]};
+            double tmp[4], GS[4];
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) tmp[2 * a + b] = Ci[2 * a] * Gc[b] + Ci[2 * a + 1] * Gc[2 + b];
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) GS[2 * a + b] = -(tmp[2 * a] * Ci[b] + tmp[2 * a + 1] * Ci[2 + b]);
+            /* dL/dSigma = T^T GS T ; dL/dT = 2 GS T Sigma */
+            double gSig[9], gT[6];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) {
+                    double acc = 0;
+                    for (int k = 0; k < 2; ++k)
+                        for (int l = 0; l < 2; ++l) acc += st.T[3 * k + a] * GS[2 * k + l] * st.T[3 * l + b];
+                    gSig[3 * a + b] = acc;
+                }
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 3; ++b) {
+                    double acc = 0;
+                    for (int k = 0; k < 2; ++k)
+                        for (int l = 0; l < 3; ++l) acc += GS[2 * a + k] * st.T[3 * k + l] * st.Sigma[3 * l + b];
+                    gT[3 * a + b] = 2.0 * acc;
+                }
+            /* dL/dJ = dL/dT W^T */
+            double gJ[6];
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 3; ++b)
+                    gJ[3 * a + b] = gT[3 * a] * W[3 * b] + gT[3 * a + 1] * W[3 * b + 1] + gT[3 * a + 2] * W[3 * b + 2];
+            /* J(t): J00 = fx/tz, J02 = -fx sx/tz, J11 = fy/tz, J12 = -fy sy/tz */
+            double tz = st.t[2];
+            double gt[3] = {0, 0, 0};
+            gt[2] += gJ[0] * (-fx / (tz * tz)) + gJ[4] * (-fy / (tz * tz));
+            gt[2] += gJ[2] * (fx * st.sx / (tz * tz)) + gJ[5] * (fy * st.sy / (tz * tz));
+            double gsx = gJ[2] * (-fx / tz), gsy = gJ[5] * (-fy / tz);
+            if (!st.clampx) { gt[0] += gsx / tz; gt[2] += gsx * (-st.t[0] / (tz * tz)); }
+            if (!st.clampy) { gt[1] += gsy / tz; gt[2] += gsy * (-st.t[1] / (tz * tz)); }
+            /* u, v */
+            gt[0] += g[0] * fx / tz;
+            gt[1] += g[1] * fy / tz;
+            gt[2] += -g[0] * fx * st.t[0] / (tz * tz) - g[1] * fy * st.t[1] / (tz * tz);
+            for (int k = 0; k < 3; ++k) gm[k] += W[k] * gt[0] + W[3 + k] * gt[1] + W[6 + k] * gt[2];
+            /* Sigma = M M^T, M = R S */
+            double M[9], gM[9];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) M[3 * a + b] = st.R[3 * a + b] * st.S[b];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) {
+                    double acc = 0;
+                    for (int k = 0; k < 3; ++k) acc += (gSig[3 * a + k] + gSig[3 * k + a]) * M[3 * k + b];
+                    gM[3 * a + b] = acc; /* (G + G^T) M, = 2 G M for symmetric G */
+                }
+            for (int k = 0; k < 3; ++k) {
+                double acc = 0;
+                for (int a = 0; a < 3; ++a) acc += st.R[3 * a + k] * gM[3 * a + k];
+                gs[k] = acc * st.S[k];
+            }
+            double gR[9];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) gR[3 * a + b] = gM[3 * a + b] * st.S[b];
+            double dR[4][9];
+            quat_rot_jac(st.qn, dR);
+            double gqn[4];
+            for (int k = 0; k < 4; ++k) {
+                double acc = 0;
+                for (int e = 0; e < 9; ++e) acc += gR[e] * dR[k][e];
+                gqn[k] = acc;
+            }
+            double qd = 0;
+            for (int k = 0; k < 4; ++k) qd += st.qn[k] * gqn[k];
+            for (int k = 0; k < 4; ++k) gq[k] = (gqn[k] - st.qn[k] * qd) / st.qnorm;
+        }
+        for (int k = 0; k < 3; ++k) { g_means[k * n + i] = gm[k]; g_log_scales[k * n + i] = gs[k]; }
+        for (int k = 0; k < 4; ++k) g_quats[k * n + i] = gq[k];
+        g_logits[i] = gl;
+        for (int j = 0; j < nc; ++j)
+            for (int ch = 0; ch < 3; ++ch) g_sh[(3 * j + ch) * n + i] = gsh[3 * j + ch];
+    }
+    return 0;
+}
+
+int or_num_threads(void) {
+    int t = 1;
+#ifdef _OPENMP
+#pragma omp parallel
+    {
+#pragma omp single
+        t = omp_get_num_threads();
+    }
+#endif
+    return t;
+}
