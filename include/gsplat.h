@@ -1,0 +1,206 @@
+/*
+ * gsplat.h -- C ABI of the MI355X (gfx950) differentiable tile-splatting library
+ * (libgsplat.so).  It implements the per-iteration hot path of 3D Gaussian
+ * Splatting training that BalanceGS (arXiv 2510.14564) accelerates: projection
+ * of 3D Gaussians to 2D conics with SH colour, binning into 16x16 tiles with a
+ * depth sort, front-to-back compositing, and the matching backward pass.
+ *
+ * Conventions shared by every call:
+ *  - Every array pointer is a DEVICE pointer owned by the caller; the library
+ *    never frees or retains it.  Descriptor structs (gs_camera, gs_gaussians,
+ *    ...) live in HOST memory and are read during the call only.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the default stream)
+ *    and is asynchronous, except gs_bin_sort, which synchronises `stream` once
+ *    to read the number of (tile, Gaussian) pairs.
+ *  - Arrays are structure-of-arrays with the Gaussian index fastest, so that
+ *    consecutive threads read consecutive addresses.
+ *  - Gradient outputs are overwritten, never accumulated.
+ *  - Every call returns a gs_status.  Argument checks run before any HIP call,
+ *    so a GS_ERR_INVALID_ARG return never touches the device.  The message of
+ *    the last failure on the calling thread is available from gs_last_error().
+ *  - Scalars are FP32; index and count arrays are uint32/int32.
+ */
+#ifndef GSPLAT_MI355_H
+#define GSPLAT_MI355_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void* gs_stream; /* hipStream_t */
+
+typedef enum {
+  GS_OK = 0,
+  GS_ERR_INVALID_ARG = -1, /* bad pointer, size, degree, camera or workspace */
+  GS_ERR_CAPACITY = -2,    /* output capacity too small; required size reported */
+  GS_ERR_HIP = -3,         /* a HIP runtime call or kernel launch failed */
+  GS_ERR_UNSUPPORTED = -4  /* a valid but unimplemented combination */
+} gs_status;
+
+#define GS_TILE 16        /* tile edge in pixels: 16x16 pixel blocks share one list (Sec. IV-C.1) */
+#define GS_REC_FLOATS 12  /* floats per projected record (48 bytes, 16-byte aligned) */
+#define GS_G2D 9          /* per-Gaussian gradients of one record: u v A B C o r g b */
+#define GS_MLP_LATENT 16  /* learned-colour latent width */
+#define GS_MLP_HIDDEN 64
+#define GS_MLP_PARAMS 6467 /* 64*32 + 64 + 64*64 + 64 + 3*64 + 3 */
+
+/* Pinhole camera.  Pixel (x, y) is sampled at (x + 0.5, y + 0.5); the
+ * principal point is (cx, cy).  R_cw (row-major) and t_cw map world points
+ * into the camera frame (x right, y down, z forward): t = R_cw mu + t_cw; this
+ * is the viewing transform W of Sec. II-A.  Gaussians with camera depth
+ * t_z <= near_z are culled.  tan_half_fov_* bound the image-plane slopes used
+ * in the projective Jacobian J (clamped to 1.3x the half field of view).  bg is
+ * the background colour added with the remaining transmittance. */
+typedef struct {
+  int32_t width, height;
+  float fx, fy, cx, cy;
+  float near_z;
+  float tan_half_fov_x, tan_half_fov_y;
+  float R_cw[9];
+  float t_cw[3];
+  float bg[3];
+} gs_camera;
+
+/* Gaussian set (Sec. II-A: centre mu, covariance Sigma from scale and
+ * rotation, opacity, SH colour).  Device arrays, index fastest:
+ *   means[3][n], log_scales[3][n]  (Sigma = R(q) diag(exp(s))^2 R(q)^T),
+ *   quats[4][n] (w, x, y, z; normalised inside), logits[n] (o = sigmoid),
+ *   sh[(D+1)^2][3][n] real SH coefficients, coefficient j / channel c at
+ *   sh[(3j + c) n + i], D = sh_degree in 0..3 (colour_mode 0).
+ * colour_mode 1 (learned colour decoder) replaces sh by latents (bf16 bit
+ * patterns, [n][16]) and mlp (bf16 bit patterns of the decoder parameters,
+ * GS_MLP_PARAMS values in the order W1[64][32], b1[64], W2[64][64], b2[64],
+ * W3[3][64], b3[3]); sh must then be NULL and sh_degree is ignored. */
+typedef struct {
+  int64_t n;
+  int32_t sh_degree;
+  int32_t colour_mode;
+  const float* means;
+  const float* log_scales;
+  const float* quats;
+  const float* logits;
+  const float* sh;
+  const uint16_t* latents;
+  const uint16_t* mlp;
+} gs_gaussians;
+
+/* Output of gs_project, input of the later stages.
+ *   records[n][12]: u, v, A, B | C, opacity, r, g | b, depth, 0, 0
+ *     (u, v) = projected centre in pixels, (A, B, C) = conic = inverse of the
+ *     2D covariance Sigma' = J W Sigma W^T J^T + 0.3 I (Sec. II-A), opacity,
+ *     colour (r, g, b).  One interleaved 48-byte record per Gaussian so that the
+ *     per-tile gathers read whole records (the interleaved colour layout of
+ *     Sec. V).
+ *   depth[n]: camera-space t_z (the sort key, Sec. II-A "sorted by depth").
+ *   radius[n]: ceil(3 sqrt(lambda_max(Sigma'))) pixels, 0 when culled.
+ *   tiles_touched[n]: number of 16x16 tiles met by the square of half-width
+ *     radius around (u, v), 0 when culled or off-screen. */
+typedef struct {
+  float* records;
+  float* depth;
+  int32_t* radius;
+  uint32_t* tiles_touched;
+} gs_projected;
+
+/* Gradients with respect to the raw parameters, same layouts as gs_gaussians,
+ * FP32.  For colour_mode 1, latents is float[n][16] and mlp float[GS_MLP_PARAMS];
+ * pointers of the other mode must be NULL. */
+typedef struct {
+  float* means;
+  float* log_scales;
+  float* quats;
+  float* logits;
+  float* sh;
+  float* latents;
+  float* mlp;
+} gs_gaussians_grad;
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* gs_last_error(void);
+
+/* Library version string. */
+const char* gs_version(void);
+
+/* Projection (Sec. II-A): per Gaussian, opacity, covariance from scale and
+ * rotation, EWA projection Sigma' = J W Sigma W^T J^T with the first-order
+ * pinhole Jacobian J plus a 0.3 px^2 low-pass dilation, conic with a
+ * determinant guard, 3-sigma radius, tile count, and colour: real SH of degree
+ * sh_degree evaluated at the unit camera-to-Gaussian direction, plus 0.5,
+ * clamped at 0 (colour_mode 0), or the learned decoder (colour_mode 1).
+ * Culled Gaussians (t_z <= near_z, non-finite values, det <= 0, radius above
+ * 2^22) get a zero record, radius 0 and tiles_touched 0.
+ * Errors: INVALID_ARG for n < 0, NULL arrays (when n > 0), sh_degree outside
+ * 0..3, an unknown colour_mode, a non-positive or non-finite camera. */
+gs_status gs_project(const gs_gaussians* g, const gs_camera* cam, gs_projected* out, gs_stream stream);
+
+/* Workspace bytes for gs_bin_sort with n Gaussians and up to `capacity`
+ * (tile, Gaussian) pairs.  Host-only; never touches the device. */
+gs_status gs_bin_sort_workspace(int64_t n, int64_t capacity, const gs_camera* cam, size_t* bytes);
+
+/* Tile binning and depth sort (Sec. II-A "sorted by depth", Sec. IV-C.1 16x16
+ * tiles).  Every Gaussian emits one entry per tile its square meets; entries
+ * are ordered by (tile, FP32 bit pattern of depth, Gaussian index), a total
+ * order, so the result is unique and bit-reproducible.
+ *   point_list[capacity]: Gaussian index of each entry, in that order.
+ *   ranges[T][2]: [start, end) of tile t's entries (empty tiles get
+ *     (S_t, S_t)), T = ceil(W/16) * ceil(H/16), tiles row-major.
+ *   *k_out: number of entries K.
+ * Synchronises `stream` once (to read K).  If K > capacity it returns
+ * GS_ERR_CAPACITY with *k_out = K and point_list/ranges undefined; the caller
+ * grows the buffers (and the workspace) and calls again.
+ * ws must hold gs_bin_sort_workspace(n, capacity) bytes, 256-byte aligned. */
+gs_status gs_bin_sort(int64_t n, const gs_projected* proj, const gs_camera* cam, void* ws, size_t ws_bytes,
+                      uint32_t* point_list, int64_t capacity, uint32_t* ranges, int64_t* k_out,
+                      gs_stream stream);
+
+/* Forward compositing (Sec. II-A, C = sum_i c_i alpha_i prod_{j<i} (1 - alpha_j)
+ * over the tile's depth-ordered list).  Per pixel: power = -1/2 (A dx^2 +
+ * C dy^2) - B dx dy, alpha = min(0.99, o exp(power)); entries with power > 0 or
+ * alpha < 1/255 are skipped; the walk stops before an entry that would take
+ * the transmittance below 1e-4.  Outputs image[3][H][W] = colour + T bg,
+ * final_T[H][W] and n_contrib[H][W] (1 + position in the tile list of the last
+ * blended entry, 0 if none).  Deterministic. */
+gs_status gs_render_fwd(int64_t n, const gs_projected* proj, const uint32_t* point_list, const uint32_t* ranges,
+                        int64_t k, const gs_camera* cam, float* image, float* final_T, uint32_t* n_contrib,
+                        gs_stream stream);
+
+/* Workspace bytes for gs_render_bwd (depends on n and K). Host-only. */
+gs_status gs_render_bwd_workspace(int64_t n, int64_t k, const gs_camera* cam, int32_t deterministic, size_t* bytes);
+
+/* Backward of the compositing: exact derivative of the forward above with its
+ * skip/stop decisions held fixed.  The per-pixel transmittance is recomputed
+ * front to back from the records (never stored per pair); the light behind an
+ * entry comes from the forward image.  Inputs: the forward's image, final_T and
+ * n_contrib, and dL_dimage[3][H][W].  Output g2d[9][n] = dL/d(u, v, A, B, C,
+ * opacity, r, g, b) per Gaussian, overwritten.  deterministic = 1 sums the
+ * per-(tile, Gaussian) partials in a fixed order (bit-reproducible); 0 uses
+ * device atomics.  ws as sized by gs_render_bwd_workspace. */
+gs_status gs_render_bwd(int64_t n, const gs_projected* proj, const uint32_t* point_list, const uint32_t* ranges,
+                        int64_t k, const gs_camera* cam, const float* image, const float* final_T,
+                        const uint32_t* n_contrib, const float* dL_dimage, float* g2d, void* ws, size_t ws_bytes,
+                        int32_t deterministic, gs_stream stream);
+
+/* Backward of the projection: chain rule from g2d[9][n] to the raw parameters
+ * (means, log_scales, quats, logits, sh) through the steps of gs_project.
+ * The forward quantities are recomputed from the parameters.  Culled Gaussians
+ * get zero gradients.  colour_mode 1 also needs the decoder: it fills
+ * grad->latents and grad->mlp and the direction's share of grad->means. */
+gs_status gs_project_bwd(const gs_gaussians* g, const gs_camera* cam, const float* g2d, gs_gaussians_grad* grad,
+                         gs_stream stream);
+
+/* L1 photometric loss over `count` floats: *loss = mean |img - target| (device
+ * scalar) and, if grad != NULL, grad = sign(img - target) / count.  partials
+ * is caller scratch of GS_L1_PARTIALS floats.  The sum is taken in a fixed
+ * order, so the loss is deterministic. */
+#define GS_L1_PARTIALS 1024
+gs_status gs_l1_loss(const float* img, const float* target, int64_t count, float* loss, float* grad,
+                     float* partials, gs_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSPLAT_MI355_H */

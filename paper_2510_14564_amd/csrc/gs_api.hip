@@ -1,0 +1,201 @@
+// C ABI entry points of libgsplat: argument validation (before any HIP call),
+// camera set-up and dispatch to the kernel launchers.
+#include <math.h>
+
+#include <string>
+
+#include "gs_internal.h"
+
+namespace gs {
+
+static thread_local std::string t_error;
+
+void set_error(const std::string& msg) { t_error = msg; }
+
+gs_status fail(gs_status code, const std::string& msg) {
+  set_error(msg);
+  return code;
+}
+
+gs_status check_hip(hipError_t e, const char* what) {
+  if (e == hipSuccess) return GS_OK;
+  return fail(GS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+gs_status check_launch(const char* what) { return check_hip(hipGetLastError(), what); }
+
+gs_status validate_camera(const gs_camera* c) {
+  if (!c) return fail(GS_ERR_INVALID_ARG, "camera is NULL");
+  if (c->width <= 0 || c->height <= 0) return fail(GS_ERR_INVALID_ARG, "camera width/height must be positive");
+  if (c->width > 32768 || c->height > 32768) return fail(GS_ERR_INVALID_ARG, "camera larger than 32768 px");
+  const float vals[] = {c->fx, c->fy, c->cx, c->cy, c->near_z, c->tan_half_fov_x, c->tan_half_fov_y};
+  for (float v : vals)
+    if (!isfinite(v)) return fail(GS_ERR_INVALID_ARG, "camera has a non-finite intrinsic");
+  if (!(c->fx > 0.f) || !(c->fy > 0.f) || !(c->near_z > 0.f) || !(c->tan_half_fov_x > 0.f) ||
+      !(c->tan_half_fov_y > 0.f))
+    return fail(GS_ERR_INVALID_ARG, "camera fx, fy, near_z and tan_half_fov must be positive");
+  for (int i = 0; i < 9; ++i)
+    if (!isfinite(c->R_cw[i])) return fail(GS_ERR_INVALID_ARG, "camera R_cw is not finite");
+  for (int i = 0; i < 3; ++i)
+    if (!isfinite(c->t_cw[i]) || !isfinite(c->bg[i])) return fail(GS_ERR_INVALID_ARG, "camera t_cw/bg not finite");
+  return GS_OK;
+}
+
+DevCam make_devcam(const gs_camera& c) {
+  DevCam d;
+  d.width = c.width;
+  d.height = c.height;
+  d.tiles_x = (c.width + kTile - 1) / kTile;
+  d.tiles_y = (c.height + kTile - 1) / kTile;
+  d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
+  d.near_z = c.near_z;
+  d.lim_x = kSlopeLimit * c.tan_half_fov_x;
+  d.lim_y = kSlopeLimit * c.tan_half_fov_y;
+  for (int i = 0; i < 9; ++i) d.R[i] = c.R_cw[i];
+  for (int i = 0; i < 3; ++i) { d.t[i] = c.t_cw[i]; d.bg[i] = c.bg[i]; }
+  // camera centre -R^T t, formed in double and rounded once
+  for (int i = 0; i < 3; ++i) {
+    const double v = -(static_cast<double>(c.R_cw[i]) * c.t_cw[0] + static_cast<double>(c.R_cw[3 + i]) * c.t_cw[1] +
+                       static_cast<double>(c.R_cw[6 + i]) * c.t_cw[2]);
+    d.centre[i] = static_cast<float>(v);
+  }
+  return d;
+}
+
+static gs_status validate_gaussians(const gs_gaussians* g, const char* fn) {
+  const std::string f(fn);
+  if (!g) return fail(GS_ERR_INVALID_ARG, f + ": gaussians is NULL");
+  if (g->n < 0) return fail(GS_ERR_INVALID_ARG, f + ": n < 0");
+  if (g->n > (int64_t(1) << 30)) return fail(GS_ERR_INVALID_ARG, f + ": n above 2^30");
+  if (g->colour_mode != 0 && g->colour_mode != 1) return fail(GS_ERR_INVALID_ARG, f + ": unknown colour_mode");
+  if (g->colour_mode == 0 && (g->sh_degree < 0 || g->sh_degree > 3))
+    return fail(GS_ERR_INVALID_ARG, f + ": sh_degree must be in 0..3");
+  if (g->n > 0) {
+    if (!g->means || !g->log_scales || !g->quats || !g->logits)
+      return fail(GS_ERR_INVALID_ARG, f + ": NULL parameter array");
+    if (g->colour_mode == 0 && !g->sh) return fail(GS_ERR_INVALID_ARG, f + ": sh is NULL");
+    if (g->colour_mode == 1) return fail(GS_ERR_UNSUPPORTED, f + ": learned colour is not available in this call");
+  }
+  return GS_OK;
+}
+
+static gs_status validate_projected(const gs_projected* p, int64_t n, const char* fn) {
+  const std::string f(fn);
+  if (!p) return fail(GS_ERR_INVALID_ARG, f + ": projected is NULL");
+  if (n > 0 && (!p->records || !p->depth || !p->radius || !p->tiles_touched))
+    return fail(GS_ERR_INVALID_ARG, f + ": NULL projected array");
+  if (reinterpret_cast<uintptr_t>(p->records) % 16 != 0)
+    return fail(GS_ERR_INVALID_ARG, f + ": records must be 16-byte aligned");
+  return GS_OK;
+}
+
+}  // namespace gs
+
+using namespace gs;
+
+extern "C" {
+
+const char* gs_last_error(void) { return t_error.c_str(); }
+
+const char* gs_version(void) { return "gsplat-mi355 0.1 (gfx950)"; }
+
+gs_status gs_project(const gs_gaussians* g, const gs_camera* cam, gs_projected* out, gs_stream stream) {
+  set_error("");
+  gs_status st;
+  if ((st = validate_gaussians(g, "gs_project")) != GS_OK) return st;
+  if ((st = validate_camera(cam)) != GS_OK) return st;
+  if ((st = validate_projected(out, g->n, "gs_project")) != GS_OK) return st;
+  return launch_project(*g, make_devcam(*cam), *out, static_cast<hipStream_t>(stream));
+}
+
+gs_status gs_bin_sort_workspace(int64_t n, int64_t capacity, const gs_camera* cam, size_t* bytes) {
+  set_error("");
+  gs_status st;
+  if ((st = validate_camera(cam)) != GS_OK) return st;
+  if (n < 0 || capacity < 0 || !bytes) return fail(GS_ERR_INVALID_ARG, "gs_bin_sort_workspace: bad n/capacity/bytes");
+  const DevCam d = make_devcam(*cam);
+  *bytes = binsort_workspace(n, capacity, d.tiles_x * d.tiles_y);
+  return GS_OK;
+}
+
+gs_status gs_bin_sort(int64_t n, const gs_projected* proj, const gs_camera* cam, void* ws, size_t ws_bytes,
+                      uint32_t* point_list, int64_t capacity, uint32_t* ranges, int64_t* k_out, gs_stream stream) {
+  set_error("");
+  gs_status st;
+  if (n < 0 || n > (int64_t(1) << 30)) return fail(GS_ERR_INVALID_ARG, "gs_bin_sort: bad n");
+  if ((st = validate_camera(cam)) != GS_OK) return st;
+  if ((st = validate_projected(proj, n, "gs_bin_sort")) != GS_OK) return st;
+  if (!k_out || !ranges || capacity < 0 || (capacity > 0 && !point_list) || (!ws && ws_bytes > 0))
+    return fail(GS_ERR_INVALID_ARG, "gs_bin_sort: NULL output or negative capacity");
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(GS_ERR_INVALID_ARG, "gs_bin_sort: ws not 256-aligned");
+  const DevCam d = make_devcam(*cam);
+  if (ws_bytes < binsort_workspace(n, capacity, d.tiles_x * d.tiles_y))
+    return fail(GS_ERR_INVALID_ARG, "gs_bin_sort: workspace too small");
+  return run_bin_sort(n, *proj, d, ws, ws_bytes, point_list, capacity, ranges, k_out,
+                      static_cast<hipStream_t>(stream));
+}
+
+gs_status gs_render_fwd(int64_t n, const gs_projected* proj, const uint32_t* point_list, const uint32_t* ranges,
+                        int64_t k, const gs_camera* cam, float* image, float* final_T, uint32_t* n_contrib,
+                        gs_stream stream) {
+  set_error("");
+  gs_status st;
+  if (n < 0 || k < 0) return fail(GS_ERR_INVALID_ARG, "gs_render_fwd: negative n or k");
+  if ((st = validate_camera(cam)) != GS_OK) return st;
+  if ((st = validate_projected(proj, n, "gs_render_fwd")) != GS_OK) return st;
+  if (!ranges || !image || !final_T || !n_contrib || (k > 0 && !point_list))
+    return fail(GS_ERR_INVALID_ARG, "gs_render_fwd: NULL array");
+  return launch_render_fwd(*proj, point_list, ranges, make_devcam(*cam), image, final_T, n_contrib,
+                           static_cast<hipStream_t>(stream));
+}
+
+gs_status gs_render_bwd_workspace(int64_t n, int64_t k, const gs_camera* cam, int32_t deterministic, size_t* bytes) {
+  set_error("");
+  gs_status st;
+  if ((st = validate_camera(cam)) != GS_OK) return st;
+  if (n < 0 || k < 0 || !bytes) return fail(GS_ERR_INVALID_ARG, "gs_render_bwd_workspace: bad arguments");
+  const DevCam d = make_devcam(*cam);
+  *bytes = render_bwd_workspace(n, k, d.tiles_x * d.tiles_y, deterministic);
+  return GS_OK;
+}
+
+gs_status gs_render_bwd(int64_t n, const gs_projected* proj, const uint32_t* point_list, const uint32_t* ranges,
+                        int64_t k, const gs_camera* cam, const float* image, const float* final_T,
+                        const uint32_t* n_contrib, const float* dL_dimage, float* g2d, void* ws, size_t ws_bytes,
+                        int32_t deterministic, gs_stream stream) {
+  set_error("");
+  gs_status st;
+  if (n < 0 || k < 0) return fail(GS_ERR_INVALID_ARG, "gs_render_bwd: negative n or k");
+  if ((st = validate_camera(cam)) != GS_OK) return st;
+  if ((st = validate_projected(proj, n, "gs_render_bwd")) != GS_OK) return st;
+  if (!ranges || !image || !final_T || !n_contrib || !dL_dimage || (n > 0 && !g2d) || (k > 0 && !point_list))
+    return fail(GS_ERR_INVALID_ARG, "gs_render_bwd: NULL array");
+  const DevCam d = make_devcam(*cam);
+  if (ws_bytes < render_bwd_workspace(n, k, d.tiles_x * d.tiles_y, deterministic) || (!ws && ws_bytes > 0))
+    return fail(GS_ERR_INVALID_ARG, "gs_render_bwd: workspace too small");
+  if (n == 0) return GS_OK;
+  return launch_render_bwd(n, *proj, point_list, ranges, k, d, image, final_T, n_contrib, dL_dimage, g2d, ws,
+                           ws_bytes, deterministic, static_cast<hipStream_t>(stream));
+}
+
+gs_status gs_project_bwd(const gs_gaussians* g, const gs_camera* cam, const float* g2d, gs_gaussians_grad* grad,
+                         gs_stream stream) {
+  set_error("");
+  gs_status st;
+  if ((st = validate_gaussians(g, "gs_project_bwd")) != GS_OK) return st;
+  if ((st = validate_camera(cam)) != GS_OK) return st;
+  if (!grad) return fail(GS_ERR_INVALID_ARG, "gs_project_bwd: grad is NULL");
+  if (g->n > 0 && (!g2d || !grad->means || !grad->log_scales || !grad->quats || !grad->logits || !grad->sh))
+    return fail(GS_ERR_INVALID_ARG, "gs_project_bwd: NULL gradient array");
+  return launch_project_bwd(*g, make_devcam(*cam), g2d, *grad, static_cast<hipStream_t>(stream));
+}
+
+gs_status gs_l1_loss(const float* img, const float* target, int64_t count, float* loss, float* grad,
+                     float* partials, gs_stream stream) {
+  set_error("");
+  if (count <= 0 || !img || !target || !loss || !partials)
+    return fail(GS_ERR_INVALID_ARG, "gs_l1_loss: bad arguments");
+  return launch_l1(img, target, count, loss, grad, partials, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

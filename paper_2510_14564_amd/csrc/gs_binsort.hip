@@ -1,0 +1,404 @@
+// Tile binning and depth sort.
+//
+// Paper: Sec. II-A (the Gaussians that reach a pixel are blended in depth
+// order) and Sec. IV-C.1 (16x16 pixel tiles share one Gaussian list).  The
+// required order of the (tile, Gaussian) entries is (tile, FP32 depth bits,
+// Gaussian index).  Instead of radix-sorting K 64-bit keys (about 6 passes over
+// K entries), the path
+//   1. sorts the N Gaussians by depth bits with a stable LSD radix sort that
+//      starts from index order, which yields (depth bits, index) order;
+//   2. emits every Gaussian's tiles in that rank order at the exclusive prefix
+//      sum of its tile counts;
+//   3. stably sorts the K entries by tile id (ceil(log2 T) bits, 1-2 passes).
+// Stability makes step 3 keep the (depth, index) order inside each tile, so
+// the result equals the full sort bit for bit.
+#include "gs_internal.h"
+
+namespace gs {
+
+constexpr int kRsThreads = 256;
+constexpr int kRsItems = 16;
+constexpr int kRsChunk = kRsThreads * kRsItems;  // keys per block
+constexpr int kScanItems = 16;
+constexpr int kScanChunk = 256 * kScanItems;
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const unsigned lane = __lane_id();
+  return (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+}
+
+// Lanes of this wave whose `digit` (nbits wide) equals ours, among `active`.
+__device__ __forceinline__ uint64_t match_digit(uint32_t digit, int nbits, bool valid) {
+  uint64_t peers = __ballot(valid);
+  for (int b = 0; b < nbits; ++b) {
+    const bool bit = (digit >> b) & 1u;
+    const uint64_t m = __ballot(bit);
+    peers &= bit ? m : ~m;
+  }
+  return peers;
+}
+
+// --------------------------------------------------------------- device scan
+// Exclusive prefix sum of uint32 values: per-block sums, one-block scan of the
+// sums (which also yields the 64-bit total), then per-block scan + offset.
+
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* lds, uint32_t& total) {
+  // 256 threads, lds >= 256 words
+  const int tid = threadIdx.x;
+  lds[tid] = v;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const uint32_t t = (tid >= off) ? lds[tid - off] : 0u;
+    __syncthreads();
+    lds[tid] += t;
+    __syncthreads();
+  }
+  total = lds[255];
+  const uint32_t incl = lds[tid];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ __launch_bounds__(256) void k_scan_sums(const uint32_t* __restrict__ in, int64_t n,
+                                                   uint32_t* __restrict__ sums) {
+  __shared__ uint32_t red[256];
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanChunk;
+  uint32_t s = 0;
+  for (int j = 0; j < kScanItems; ++j) {
+    const int64_t idx = base + j * 256 + threadIdx.x;
+    if (idx < n) s += in[idx];
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sums[blockIdx.x] = red[0];
+}
+
+// One block: exclusive scan of `nb` block sums in place; total (64-bit) out.
+__global__ __launch_bounds__(256) void k_scan_top(uint32_t* __restrict__ sums, int nb,
+                                                  unsigned long long* __restrict__ total) {
+  __shared__ uint32_t lds[256];
+  uint64_t carry = 0;
+  for (int base = 0; base < nb; base += 256) {
+    const int idx = base + threadIdx.x;
+    const uint32_t v = idx < nb ? sums[idx] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan(v, lds, tot);
+    if (idx < nb) sums[idx] = static_cast<uint32_t>(carry) + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0 && total) *total = carry;
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__ in, int64_t n,
+                                                    const uint32_t* __restrict__ sums, uint32_t* __restrict__ out) {
+  __shared__ uint32_t lds[256];
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanChunk;
+  // blocked arrangement: thread t owns items [t*16, t*16+16) of the chunk
+  uint32_t v[kScanItems];
+  uint32_t s = 0;
+  const int64_t my = base + static_cast<int64_t>(threadIdx.x) * kScanItems;
+  for (int j = 0; j < kScanItems; ++j) {
+    const int64_t idx = my + j;
+    v[j] = idx < n ? in[idx] : 0u;
+    s += v[j];
+  }
+  uint32_t tot;
+  uint32_t run = block_exclusive_scan(s, lds, tot) + sums[blockIdx.x];
+  for (int j = 0; j < kScanItems; ++j) {
+    const int64_t idx = my + j;
+    if (idx < n) out[idx] = run;
+    run += v[j];
+  }
+}
+
+struct ScanWs {
+  uint32_t* sums;
+  unsigned long long* total;
+};
+
+static size_t scan_ws_words(int64_t n) { return static_cast<size_t>(ceil_div(n > 0 ? n : 1, kScanChunk)); }
+
+static gs_status device_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, ScanWs ws, hipStream_t s) {
+  const int nb = static_cast<int>(ceil_div(n > 0 ? n : 1, kScanChunk));
+  k_scan_sums<<<nb, 256, 0, s>>>(in, n, ws.sums);
+  k_scan_top<<<1, 256, 0, s>>>(ws.sums, nb, ws.total);
+  k_scan_apply<<<nb, 256, 0, s>>>(in, n, ws.sums, out);
+  return check_launch("device_exclusive_scan");
+}
+
+// ---------------------------------------------------------------- radix sort
+// One stable LSD pass on (key, value) pairs over `nbits` bits at `shift`.
+// Block b owns keys [b*4096, (b+1)*4096), taken in 16 rounds of 256; within a
+// round, wave w's keys precede wave w+1's and lanes are in order, so ranks
+// computed round by round preserve the input order of equal digits.
+
+__global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint32_t* __restrict__ keys, int64_t count,
+                                                        int shift, int nbits, uint32_t* __restrict__ hist,
+                                                        int nblocks) {
+  __shared__ uint32_t cnt[256];
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t mask = (1u << nbits) - 1u;
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kRsChunk;
+  for (int j = 0; j < kRsItems; ++j) {
+    const int64_t idx = base + j * kRsThreads + threadIdx.x;
+    const bool valid = idx < count;
+    const uint32_t d = valid ? ((keys[idx] >> shift) & mask) : 0u;
+    const uint64_t peers = match_digit(d, nbits, valid);
+    if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&cnt[d], static_cast<uint32_t>(__popcll(peers)));
+  }
+  __syncthreads();
+  if (threadIdx.x <= mask) hist[static_cast<int64_t>(threadIdx.x) * nblocks + blockIdx.x] = cnt[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* __restrict__ keys_in,
+                                                           const uint32_t* __restrict__ vals_in,
+                                                           uint32_t* __restrict__ keys_out,
+                                                           uint32_t* __restrict__ vals_out, int64_t count,
+                                                           int shift, int nbits,
+                                                           const uint32_t* __restrict__ hist_scan, int nblocks) {
+  __shared__ uint32_t sk[kRsChunk];
+  __shared__ uint32_t sv[kRsChunk];
+  __shared__ uint32_t running[256];
+  __shared__ uint32_t wcnt[4][256];
+  __shared__ uint32_t dstart[256];
+  __shared__ uint32_t gbase[256];
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const uint32_t mask = (1u << nbits) - 1u;
+  running[tid] = 0;
+  wcnt[0][tid] = 0; wcnt[1][tid] = 0; wcnt[2][tid] = 0; wcnt[3][tid] = 0;
+  gbase[tid] = (static_cast<uint32_t>(tid) <= mask) ? hist_scan[static_cast<int64_t>(tid) * nblocks + blockIdx.x] : 0u;
+  __syncthreads();
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kRsChunk;
+  uint32_t k[kRsItems], v[kRsItems], lr[kRsItems];
+#pragma unroll
+  for (int j = 0; j < kRsItems; ++j) {
+    const int64_t idx = base + j * kRsThreads + tid;
+    const bool valid = idx < count;
+    k[j] = valid ? keys_in[idx] : 0u;
+    v[j] = valid ? vals_in[idx] : 0u;
+  }
+#pragma unroll
+  for (int j = 0; j < kRsItems; ++j) {
+    const int64_t idx = base + j * kRsThreads + tid;
+    const bool valid = idx < count;
+    const uint32_t d = (k[j] >> shift) & mask;
+    const uint64_t peers = match_digit(d, nbits, valid);
+    const uint64_t below = peers & lanemask_lt();
+    if (valid && below == 0) wcnt[wave][d] = static_cast<uint32_t>(__popcll(peers));
+    __syncthreads();
+    if (valid) {
+      uint32_t off = running[d];
+      for (int w = 0; w < wave; ++w) off += wcnt[w][d];
+      lr[j] = off + static_cast<uint32_t>(__popcll(below));
+    }
+    __syncthreads();
+    running[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
+    wcnt[0][tid] = 0; wcnt[1][tid] = 0; wcnt[2][tid] = 0; wcnt[3][tid] = 0;
+    __syncthreads();
+  }
+  // block-local digit starts
+  uint32_t tot;
+  const uint32_t ds = block_exclusive_scan(running[tid], &wcnt[0][0], tot);
+  dstart[tid] = ds;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kRsItems; ++j) {
+    const int64_t idx = base + j * kRsThreads + tid;
+    if (idx < count) {
+      const uint32_t d = (k[j] >> shift) & mask;
+      const uint32_t pos = dstart[d] + lr[j];
+      sk[pos] = k[j];
+      sv[pos] = v[j];
+    }
+  }
+  __syncthreads();
+  const int64_t nvalid = min(static_cast<int64_t>(kRsChunk), count - base);
+  for (int p = tid; p < nvalid; p += kRsThreads) {
+    const uint32_t key = sk[p];
+    const uint32_t d = (key >> shift) & mask;
+    const uint32_t g = gbase[d] + (static_cast<uint32_t>(p) - dstart[d]);
+    keys_out[g] = key;
+    vals_out[g] = sv[p];
+  }
+}
+
+// Sorts `count` pairs over key bits [0, total_bits) in passes of <= 8 bits.
+// Input in (ka, va); the sorted result ends in (ka, va) if the pass count is
+// even, else in (kb, vb).  Returns the number of passes.
+static gs_status radix_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int64_t count,
+                                  int total_bits, uint32_t* hist, ScanWs sws, hipStream_t s, int* passes_out) {
+  int passes = 0;
+  if (count > 0) {
+    const int nblocks = static_cast<int>(ceil_div(count, kRsChunk));
+    for (int shift = 0; shift < total_bits; shift += 8) {
+      const int nbits = min(8, total_bits - shift);
+      const int64_t nh = static_cast<int64_t>(1 << nbits) * nblocks;
+      k_rs_hist<<<nblocks, kRsThreads, 0, s>>>(ka, count, shift, nbits, hist, nblocks);
+      gs_status st = device_exclusive_scan(hist, hist, nh, sws, s);
+      if (st != GS_OK) return st;
+      k_rs_scatter<<<nblocks, kRsThreads, 0, s>>>(ka, va, kb, vb, count, shift, nbits, hist, nblocks);
+      st = check_launch("k_rs_scatter");
+      if (st != GS_OK) return st;
+      uint32_t* t = ka; ka = kb; kb = t;
+      t = va; va = vb; vb = t;
+      ++passes;
+    }
+  }
+  *passes_out = passes;
+  return GS_OK;
+}
+
+static int sort_passes(int bits) { return (bits + 7) / 8; }
+
+// ------------------------------------------------------------- bin kernels
+
+__global__ __launch_bounds__(256) void k_depth_keys(int n, const float* __restrict__ depth,
+                                                    uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  keys[i] = __float_as_uint(depth[i]);
+  vals[i] = static_cast<uint32_t>(i);
+}
+
+__global__ __launch_bounds__(256) void k_gather_counts(int n, const uint32_t* __restrict__ order,
+                                                       const uint32_t* __restrict__ tiles_touched,
+                                                       uint32_t* __restrict__ out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  out[r] = tiles_touched[order[r]];
+}
+
+// One thread per Gaussian in depth-rank order writes its tiles row-major.
+__global__ __launch_bounds__(256) void k_emit(int n, const uint32_t* __restrict__ order,
+                                              const uint32_t* __restrict__ offsets,
+                                              const float4* __restrict__ records, const int* __restrict__ radius,
+                                              int tiles_x, int tiles_y, uint32_t* __restrict__ tile_keys,
+                                              uint32_t* __restrict__ gids) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const uint32_t gid = order[r];
+  const float4 rec = records[3 * gid];
+  int x0, x1, y0, y1;
+  const int cnt = tile_rect(rec.x, rec.y, radius[gid], tiles_x, tiles_y, x0, x1, y0, y1);
+  if (cnt == 0) return;
+  uint32_t o = offsets[r];
+  for (int y = y0; y <= y1; ++y)
+    for (int x = x0; x <= x1; ++x) {
+      tile_keys[o] = static_cast<uint32_t>(y * tiles_x + x);
+      gids[o] = gid;
+      ++o;
+    }
+}
+
+// ranges[t] = [lower_bound(t), lower_bound(t + 1)) over the sorted tile ids.
+__global__ __launch_bounds__(256) void k_ranges(int ntiles, const uint32_t* __restrict__ tiles, uint32_t K,
+                                                uint2* __restrict__ ranges) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntiles) return;
+  auto lb = [&](uint32_t key) {
+    uint32_t lo = 0, hi = K;
+    while (lo < hi) {
+      const uint32_t mid = lo + ((hi - lo) >> 1);
+      if (tiles[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+  };
+  ranges[t] = make_uint2(lb(static_cast<uint32_t>(t)), lb(static_cast<uint32_t>(t + 1)));
+}
+
+static int bits_for(int64_t values) {  // bits needed to represent 0..values-1
+  int b = 0;
+  while ((int64_t(1) << b) < values) ++b;
+  return b < 1 ? 1 : b;
+}
+
+struct BinWs {
+  uint32_t *dk0, *dv0, *dk1, *dv1, *cnt, *offs;
+  uint32_t *ek0, *ek1, *ev1;
+  uint32_t* hist;
+  ScanWs scan;
+};
+
+static BinWs carve_bin(void* ws, int64_t n, int64_t cap, size_t* used) {
+  Carver c(ws);
+  BinWs b;
+  const size_t N = static_cast<size_t>(n > 0 ? n : 1), C = static_cast<size_t>(cap > 0 ? cap : 1);
+  b.dk0 = c.take<uint32_t>(N); b.dv0 = c.take<uint32_t>(N);
+  b.dk1 = c.take<uint32_t>(N); b.dv1 = c.take<uint32_t>(N);
+  b.cnt = c.take<uint32_t>(N); b.offs = c.take<uint32_t>(N);
+  b.ek0 = c.take<uint32_t>(C); b.ek1 = c.take<uint32_t>(C); b.ev1 = c.take<uint32_t>(C);
+  const int64_t maxn = std::max<int64_t>(std::max<int64_t>(n, cap), 1);
+  const size_t hist_words = 256 * static_cast<size_t>(ceil_div(maxn, kRsChunk));
+  b.hist = c.take<uint32_t>(hist_words);
+  b.scan.sums = c.take<uint32_t>(scan_ws_words(std::max<int64_t>(static_cast<int64_t>(hist_words), maxn)));
+  b.scan.total = c.take<unsigned long long>(1);
+  *used = c.off + 256;
+  return b;
+}
+
+size_t binsort_workspace(int64_t n, int64_t capacity, int ntiles) {
+  (void)ntiles;
+  size_t used = 0;
+  carve_bin(nullptr, n, capacity, &used);
+  return used;
+}
+
+gs_status run_bin_sort(int64_t n64, const gs_projected& proj, const DevCam& cam, void* ws, size_t ws_bytes,
+                       uint32_t* point_list, int64_t capacity, uint32_t* ranges, int64_t* k_out, hipStream_t s) {
+  const int n = static_cast<int>(n64);
+  const int ntiles = cam.tiles_x * cam.tiles_y;
+  size_t need = 0;
+  BinWs b = carve_bin(ws, n64, capacity, &need);
+  if (ws_bytes < need) return fail(GS_ERR_INVALID_ARG, "gs_bin_sort: workspace too small");
+  gs_status st;
+  int64_t K = 0;
+  if (n > 0) {
+    const unsigned g = static_cast<unsigned>(ceil_div(n, 256));
+    k_depth_keys<<<g, 256, 0, s>>>(n, proj.depth, b.dk0, b.dv0);
+    int passes = 0;
+    if ((st = radix_sort_pairs(b.dk0, b.dv0, b.dk1, b.dv1, n, 32, b.hist, b.scan, s, &passes)) != GS_OK) return st;
+    const uint32_t* order = (passes % 2 == 0) ? b.dv0 : b.dv1;
+    k_gather_counts<<<g, 256, 0, s>>>(n, order, proj.tiles_touched, b.cnt);
+    if ((st = device_exclusive_scan(b.cnt, b.offs, n, b.scan, s)) != GS_OK) return st;
+    unsigned long long total = 0;
+    if ((st = check_hip(hipMemcpyAsync(&total, b.scan.total, sizeof(total), hipMemcpyDeviceToHost, s),
+                        "hipMemcpyAsync(K)")) != GS_OK) return st;
+    if ((st = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize")) != GS_OK) return st;
+    K = static_cast<int64_t>(total);
+    *k_out = K;
+    if (K >= (int64_t(1) << 32)) return fail(GS_ERR_UNSUPPORTED, "gs_bin_sort: more than 2^32 entries");
+    if (K > capacity) return fail(GS_ERR_CAPACITY, "gs_bin_sort: capacity too small");
+    if (K > 0) {
+      const int tbits = bits_for(ntiles);
+      const int tp = sort_passes(tbits);
+      // choose the emit target so that the last pass lands in point_list
+      uint32_t* ka = b.ek0;
+      uint32_t* va = (tp % 2 == 0) ? point_list : b.ev1;
+      uint32_t* kb = b.ek1;
+      uint32_t* vb = (tp % 2 == 0) ? b.ev1 : point_list;
+      k_emit<<<g, 256, 0, s>>>(n, order, b.offs, reinterpret_cast<const float4*>(proj.records), proj.radius,
+                               cam.tiles_x, cam.tiles_y, ka, va);
+      if ((st = check_launch("k_emit")) != GS_OK) return st;
+      int p2 = 0;
+      if ((st = radix_sort_pairs(ka, va, kb, vb, K, tbits, b.hist, b.scan, s, &p2)) != GS_OK) return st;
+      const uint32_t* sorted_tiles = (p2 % 2 == 0) ? ka : kb;
+      k_ranges<<<static_cast<unsigned>(ceil_div(ntiles, 256)), 256, 0, s>>>(
+          ntiles, sorted_tiles, static_cast<uint32_t>(K), reinterpret_cast<uint2*>(ranges));
+      return check_launch("k_ranges");
+    }
+  } else {
+    *k_out = 0;
+  }
+  // K == 0: every tile is empty
+  if ((st = check_hip(hipMemsetAsync(ranges, 0, sizeof(uint32_t) * 2 * static_cast<size_t>(ntiles), s),
+                      "hipMemsetAsync(ranges)")) != GS_OK) return st;
+  return GS_OK;
+}
+
+}  // namespace gs

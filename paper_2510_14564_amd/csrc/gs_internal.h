@@ -1,0 +1,116 @@
+// Internal declarations shared by the HIP translation units of libgsplat.
+// Nothing here is part of the public ABI (include/gsplat.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <string>
+
+#include "gsplat.h"
+
+namespace gs {
+
+constexpr int kTile = GS_TILE;
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kAlphaMax = 0.99f;
+constexpr float kTMin = 1e-4f;
+constexpr float kDilation = 0.3f;
+constexpr float kSlopeLimit = 1.3f;
+constexpr float kRadiusMax = 4194304.0f;  // 2^22 px
+
+// Camera as the kernels see it (passed by value).
+struct DevCam {
+  int width, height, tiles_x, tiles_y;
+  float fx, fy, cx, cy, near_z, lim_x, lim_y;
+  float R[9];
+  float t[3];
+  float centre[3];  // camera centre in world space, -R^T t
+  float bg[3];
+};
+
+DevCam make_devcam(const gs_camera& c);
+
+// thread-local error message
+void set_error(const std::string& msg);
+gs_status fail(gs_status code, const std::string& msg);
+gs_status check_hip(hipError_t e, const char* what);
+gs_status check_launch(const char* what);
+gs_status validate_camera(const gs_camera* cam);
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Aligned carve-out of a caller-supplied workspace.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = reinterpret_cast<T*>(base ? base + off : nullptr);
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+// ------------------------------------------------------------------ device
+
+// floor division toward -inf by a positive constant
+__device__ __forceinline__ int floordiv_tile(int a) {
+  return (a >= 0) ? (a / kTile) : -((-a + kTile - 1) / kTile);
+}
+
+// Tile rectangle of the closed square [u - r, u + r] x [v - r, v + r]
+// intersected with the tile grid, in integers after one floor of u and v.
+// Returns the tile count (0 if none) and the inclusive bounds.
+__device__ __forceinline__ int tile_rect(float u, float v, int r, int tx, int ty, int& x0, int& x1, int& y0,
+                                         int& y1) {
+  x0 = 0; x1 = -1; y0 = 0; y1 = -1;
+  if (r <= 0 || !isfinite(u) || !isfinite(v)) return 0;
+  const float fr = static_cast<float>(r);
+  if (u < -fr || u >= static_cast<float>(kTile * tx + r)) return 0;
+  if (v < -fr || v >= static_cast<float>(kTile * ty + r)) return 0;
+  const int fu = static_cast<int>(floorf(u)), fv = static_cast<int>(floorf(v));
+  x0 = max(0, floordiv_tile(fu - r));
+  x1 = min(tx - 1, floordiv_tile(fu + r));
+  y0 = max(0, floordiv_tile(fv - r));
+  y1 = min(ty - 1, floordiv_tile(fv + r));
+  if (x0 > x1 || y0 > y1) return 0;
+  return (x1 - x0 + 1) * (y1 - y0 + 1);
+}
+
+// Map a linear block index to a work index so that consecutive work items land
+// on the same XCD (blocks are dispatched round-robin over the 8 XCDs).
+__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
+  constexpr int kXcd = 8;
+  const int per = nblocks / kXcd;
+  const int rem = nblocks % kXcd;
+  const int xcd = bid % kXcd;
+  const int local = bid / kXcd;
+  // XCDs [0, rem) own per+1 items, the rest own per items
+  const int start = xcd * per + min(xcd, rem);
+  return start + local;
+}
+
+}  // namespace gs
+
+// Launchers implemented in the kernel translation units.
+namespace gs {
+gs_status launch_project(const gs_gaussians& g, const DevCam& cam, gs_projected& out, hipStream_t s);
+gs_status launch_project_bwd(const gs_gaussians& g, const DevCam& cam, const float* g2d, gs_gaussians_grad& grad,
+                             hipStream_t s);
+size_t binsort_workspace(int64_t n, int64_t capacity, int ntiles);
+gs_status run_bin_sort(int64_t n, const gs_projected& proj, const DevCam& cam, void* ws, size_t ws_bytes,
+                       uint32_t* point_list, int64_t capacity, uint32_t* ranges, int64_t* k_out, hipStream_t s);
+gs_status launch_render_fwd(const gs_projected& proj, const uint32_t* point_list, const uint32_t* ranges,
+                            const DevCam& cam, float* image, float* final_T, uint32_t* n_contrib, hipStream_t s);
+size_t render_bwd_workspace(int64_t n, int64_t k, int ntiles, int deterministic);
+gs_status launch_render_bwd(int64_t n, const gs_projected& proj, const uint32_t* point_list, const uint32_t* ranges,
+                            int64_t k, const DevCam& cam, const float* image, const float* final_T,
+                            const uint32_t* n_contrib, const float* dL_dimage, float* g2d, void* ws,
+                            size_t ws_bytes, int deterministic, hipStream_t s);
+gs_status launch_l1(const float* img, const float* target, int64_t count, float* loss, float* grad, float* partials,
+                    hipStream_t s);
+}  // namespace gs

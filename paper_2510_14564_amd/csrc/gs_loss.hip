@@ -1,0 +1,53 @@
+// Photometric L1 loss of a rendered image against a target, and its gradient.
+// The loss is a device scalar: per-block partial sums, then one block sums the
+// partials in a fixed order (deterministic).
+#include "gs_internal.h"
+
+namespace gs {
+
+constexpr int kL1Blocks = GS_L1_PARTIALS;
+
+__global__ __launch_bounds__(256) void k_l1_partial(const float* __restrict__ img, const float* __restrict__ tgt,
+                                                    int64_t count, float inv_count, float* __restrict__ grad,
+                                                    float* __restrict__ partial) {
+  __shared__ float red[256];
+  float s = 0.0f;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < count;
+       i += static_cast<int64_t>(gridDim.x) * 256) {
+    const float d = img[i] - tgt[i];
+    s += fabsf(d);
+    if (grad) grad[i] = d > 0.0f ? inv_count : (d < 0.0f ? -inv_count : 0.0f);
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_l1_final(const float* __restrict__ partial, int nb, float inv_count,
+                                                  float* __restrict__ loss) {
+  __shared__ float red[256];
+  float s = 0.0f;
+  for (int i = threadIdx.x; i < nb; i += 256) s += partial[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *loss = red[0] * inv_count;
+}
+
+gs_status launch_l1(const float* img, const float* target, int64_t count, float* loss, float* grad,
+                    float* partials, hipStream_t s) {
+  const int nb = static_cast<int>(std::min<int64_t>(kL1Blocks, ceil_div(count, 256)));
+  const float inv = 1.0f / static_cast<float>(count);
+  k_l1_partial<<<nb, 256, 0, s>>>(img, target, count, inv, grad, partials);
+  k_l1_final<<<1, 256, 0, s>>>(partials, nb, inv, loss);
+  return check_launch("k_l1");
+}
+
+}  // namespace gs

@@ -1,0 +1,452 @@
+// Projection of 3D Gaussians to 2D conics with SH colour, and its backward.
+//
+// Paper: Sec. II-A -- the Gaussian kernel G(x), the EWA projection
+// Sigma' = J W Sigma W^T J^T and colour from SH coefficients.  One thread per
+// Gaussian; parameters are structure-of-arrays so a wave reads 64 consecutive
+// floats per field (256-byte coalesced loads).  The kernel is HBM-bound: it
+// reads 44 + 12 (D+1)^2 bytes and writes 60 bytes per Gaussian.
+#include "gs_internal.h"
+
+namespace gs {
+
+// Real SH basis, Condon-Shortley phase kept, ordered by l then m = -l..l.
+// Constants are the closed-form normalisations:
+//   l=0: 1/(2 sqrt(pi));  l=1: sqrt(3/(4 pi));
+//   l=2: (1/2) sqrt(15/pi), (1/4) sqrt(5/pi), (1/4) sqrt(15/pi);
+//   l=3: (1/4) sqrt(35/(2 pi)), (1/2) sqrt(105/pi), (1/4) sqrt(21/(2 pi)),
+//        (1/4) sqrt(7/pi), (1/4) sqrt(105/pi).
+constexpr float kSH0 = 0.28209479177387814f;
+constexpr float kSH1 = 0.48860251190291992f;
+constexpr float kSH2a = 1.0925484305920792f;
+constexpr float kSH2c = 0.31539156525252005f;
+constexpr float kSH2e = 0.54627421529603959f;
+constexpr float kSH3a = 0.59004358992664352f;
+constexpr float kSH3b = 2.8906114426405538f;
+constexpr float kSH3c = 0.45704579946446572f;
+constexpr float kSH3d = 0.37317633259011540f;
+constexpr float kSH3f = 1.4453057213202769f;
+
+__device__ __forceinline__ void sh_basis(int deg, float x, float y, float z, float* Y) {
+  Y[0] = kSH0;
+  if (deg < 1) return;
+  Y[1] = -kSH1 * y;
+  Y[2] = kSH1 * z;
+  Y[3] = -kSH1 * x;
+  if (deg < 2) return;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  Y[4] = kSH2a * x * y;
+  Y[5] = -kSH2a * y * z;
+  Y[6] = kSH2c * (2.0f * zz - xx - yy);
+  Y[7] = -kSH2a * x * z;
+  Y[8] = kSH2e * (xx - yy);
+  if (deg < 3) return;
+  Y[9] = -kSH3a * y * (3.0f * xx - yy);
+  Y[10] = kSH3b * x * y * z;
+  Y[11] = -kSH3c * y * (4.0f * zz - xx - yy);
+  Y[12] = kSH3d * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+  Y[13] = -kSH3c * x * (4.0f * zz - xx - yy);
+  Y[14] = kSH3f * z * (xx - yy);
+  Y[15] = -kSH3a * x * (xx - 3.0f * yy);
+}
+
+// g = sum_j w_j grad Y_j(d) for the Cartesian forms above.
+__device__ __forceinline__ void sh_basis_vjp(int deg, float x, float y, float z, const float* w, float& gx,
+                                             float& gy, float& gz) {
+  gx = gy = gz = 0.0f;
+  if (deg < 1) return;
+  gy += -kSH1 * w[1];
+  gz += kSH1 * w[2];
+  gx += -kSH1 * w[3];
+  if (deg < 2) return;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  gx += kSH2a * y * w[4];             gy += kSH2a * x * w[4];
+  gy += -kSH2a * z * w[5];            gz += -kSH2a * y * w[5];
+  gx += -2.0f * kSH2c * x * w[6];     gy += -2.0f * kSH2c * y * w[6];   gz += 4.0f * kSH2c * z * w[6];
+  gx += -kSH2a * z * w[7];            gz += -kSH2a * x * w[7];
+  gx += 2.0f * kSH2e * x * w[8];      gy += -2.0f * kSH2e * y * w[8];
+  if (deg < 3) return;
+  gx += -6.0f * kSH3a * x * y * w[9];
+  gy += -kSH3a * (3.0f * xx - 3.0f * yy) * w[9];
+  gx += kSH3b * y * z * w[10];  gy += kSH3b * x * z * w[10];  gz += kSH3b * x * y * w[10];
+  gx += 2.0f * kSH3c * x * y * w[11];
+  gy += -kSH3c * (4.0f * zz - xx - 3.0f * yy) * w[11];
+  gz += -8.0f * kSH3c * y * z * w[11];
+  gx += -6.0f * kSH3d * x * z * w[12];
+  gy += -6.0f * kSH3d * y * z * w[12];
+  gz += kSH3d * (6.0f * zz - 3.0f * xx - 3.0f * yy) * w[12];
+  gx += -kSH3c * (4.0f * zz - 3.0f * xx - yy) * w[13];
+  gy += 2.0f * kSH3c * x * y * w[13];
+  gz += -8.0f * kSH3c * x * z * w[13];
+  gx += 2.0f * kSH3f * x * z * w[14];
+  gy += -2.0f * kSH3f * y * z * w[14];
+  gz += kSH3f * (xx - yy) * w[14];
+  gx += -kSH3a * (3.0f * xx - 3.0f * yy) * w[15];
+  gy += 6.0f * kSH3a * x * y * w[15];
+}
+
+// Geometry of one Gaussian, shared by the forward and the backward so both
+// see the same FP32 values.
+struct Geo {
+  float o;
+  float qn[4], qinv;       // unit quaternion and 1/|q|
+  float R[9], S[3];        // rotation, scales
+  float Sig[6];            // 3D covariance xx xy xz yy yz zz
+  float t[3];              // camera-space centre
+  float sx, sy;            // (possibly clamped) slopes
+  bool clx, cly;
+  float T[6];              // J W, 2x3 row-major
+  float a, b, c;           // Sigma' (dilated)
+  float det, A, B, C;
+  int radius;
+  float u, v;
+};
+
+// Returns false if the Gaussian is culled.
+__device__ __forceinline__ bool project_geometry(const float m[3], const float s[3], const float q[4], float logit,
+                                                 const DevCam& cam, Geo& g) {
+  g.o = 1.0f / (1.0f + expf(-logit));
+  const float qq = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+  const float qlen = sqrtf(qq);
+  g.qinv = 1.0f / qlen;
+  const float w = q[0] * g.qinv, x = q[1] * g.qinv, y = q[2] * g.qinv, z = q[3] * g.qinv;
+  g.qn[0] = w; g.qn[1] = x; g.qn[2] = y; g.qn[3] = z;
+  float* R = g.R;
+  R[0] = 1.0f - 2.0f * (y * y + z * z); R[1] = 2.0f * (x * y - w * z);        R[2] = 2.0f * (x * z + w * y);
+  R[3] = 2.0f * (x * y + w * z);        R[4] = 1.0f - 2.0f * (x * x + z * z); R[5] = 2.0f * (y * z - w * x);
+  R[6] = 2.0f * (x * z - w * y);        R[7] = 2.0f * (y * z + w * x);        R[8] = 1.0f - 2.0f * (x * x + y * y);
+  g.S[0] = expf(s[0]); g.S[1] = expf(s[1]); g.S[2] = expf(s[2]);
+  // M = R S ; Sigma = M M^T
+  float M[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) M[3 * i + j] = R[3 * i + j] * g.S[j];
+  g.Sig[0] = M[0] * M[0] + M[1] * M[1] + M[2] * M[2];
+  g.Sig[1] = M[0] * M[3] + M[1] * M[4] + M[2] * M[5];
+  g.Sig[2] = M[0] * M[6] + M[1] * M[7] + M[2] * M[8];
+  g.Sig[3] = M[3] * M[3] + M[4] * M[4] + M[5] * M[5];
+  g.Sig[4] = M[3] * M[6] + M[4] * M[7] + M[5] * M[8];
+  g.Sig[5] = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
+  const float* W = cam.R;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) g.t[i] = W[3 * i] * m[0] + W[3 * i + 1] * m[1] + W[3 * i + 2] * m[2] + cam.t[i];
+  const float tz = g.t[2];
+  if (!(tz > cam.near_z) || !isfinite(tz)) return false;
+  const float itz = 1.0f / tz;
+  const float rx = g.t[0] * itz, ry = g.t[1] * itz;
+  g.sx = fminf(fmaxf(rx, -cam.lim_x), cam.lim_x);
+  g.sy = fminf(fmaxf(ry, -cam.lim_y), cam.lim_y);
+  g.clx = (rx > cam.lim_x) || (rx < -cam.lim_x);
+  g.cly = (ry > cam.lim_y) || (ry < -cam.lim_y);
+  // J = [[fx/tz, 0, -fx sx/tz], [0, fy/tz, -fy sy/tz]];  T = J W
+  const float j00 = cam.fx * itz, j02 = -cam.fx * g.sx * itz;
+  const float j11 = cam.fy * itz, j12 = -cam.fy * g.sy * itz;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    g.T[k] = j00 * W[k] + j02 * W[6 + k];
+    g.T[3 + k] = j11 * W[3 + k] + j12 * W[6 + k];
+  }
+  // Sigma' = T Sigma T^T (symmetric Sigma stored as 6 values)
+  const float* Sg = g.Sig;
+  float P0[3], P1[3];  // T Sigma rows
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const float* Tr = g.T + 3 * r;
+    float* P = r ? P1 : P0;
+    P[0] = Tr[0] * Sg[0] + Tr[1] * Sg[1] + Tr[2] * Sg[2];
+    P[1] = Tr[0] * Sg[1] + Tr[1] * Sg[3] + Tr[2] * Sg[4];
+    P[2] = Tr[0] * Sg[2] + Tr[1] * Sg[4] + Tr[2] * Sg[5];
+  }
+  g.a = P0[0] * g.T[0] + P0[1] * g.T[1] + P0[2] * g.T[2] + kDilation;
+  g.b = P0[0] * g.T[3] + P0[1] * g.T[4] + P0[2] * g.T[5];
+  g.c = P1[0] * g.T[3] + P1[1] * g.T[4] + P1[2] * g.T[5] + kDilation;
+  g.det = fmaf(g.a, g.c, -g.b * g.b);
+  if (!(g.det > 0.0f) || !isfinite(g.det)) return false;
+  const float idet = 1.0f / g.det;
+  g.A = g.c * idet; g.B = -g.b * idet; g.C = g.a * idet;
+  // largest eigenvalue: mid + sqrt(max(0.1, ((a-c)/2)^2 + b^2)), cancellation-free
+  const float mid = 0.5f * (g.a + g.c);
+  const float h = 0.5f * (g.a - g.c);
+  const float lam = mid + sqrtf(fmaxf(0.1f, h * h + g.b * g.b));
+  const float r3 = 3.0f * sqrtf(lam);
+  if (!(r3 <= kRadiusMax)) return false;
+  g.radius = static_cast<int>(ceilf(r3));
+  g.u = cam.fx * g.t[0] * itz + cam.cx;
+  g.v = cam.fy * g.t[1] * itz + cam.cy;
+  return isfinite(g.u) && isfinite(g.v) && isfinite(g.A) && isfinite(g.B) && isfinite(g.C) && isfinite(g.o);
+}
+
+__device__ __forceinline__ void view_dir(const float m[3], const DevCam& cam, float d[3], float& len) {
+  const float dx = m[0] - cam.centre[0], dy = m[1] - cam.centre[1], dz = m[2] - cam.centre[2];
+  len = sqrtf(dx * dx + dy * dy + dz * dz);
+  const float il = 1.0f / len;
+  d[0] = dx * il; d[1] = dy * il; d[2] = dz * il;
+}
+
+template <int DEG>
+__global__ __launch_bounds__(256) void k_project(int n, const float* __restrict__ means,
+                                                 const float* __restrict__ log_scales,
+                                                 const float* __restrict__ quats, const float* __restrict__ logits,
+                                                 const float* __restrict__ sh, DevCam cam,
+                                                 float4* __restrict__ records, float* __restrict__ depth,
+                                                 int* __restrict__ radius, uint32_t* __restrict__ tiles_touched) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  constexpr int NC = (DEG + 1) * (DEG + 1);
+  float m[3], s[3], q[4];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) { m[k] = means[k * n + i]; s[k] = log_scales[k * n + i]; }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) q[k] = quats[k * n + i];
+  const float logit = logits[i];
+  Geo g;
+  bool live = project_geometry(m, s, q, logit, cam, g);
+  float rgb[3] = {0.0f, 0.0f, 0.0f};
+  if (live) {
+    float d[3], len;
+    view_dir(m, cam, d, len);
+    float Y[16];
+    sh_basis(DEG, d[0], d[1], d[2], Y);
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      float acc = 0.0f;
+#pragma unroll
+      for (int j = 0; j < NC; ++j) acc += Y[j] * sh[(3 * j + ch) * n + i];
+      rgb[ch] = fmaxf(acc + 0.5f, 0.0f);
+    }
+    live = isfinite(rgb[0]) && isfinite(rgb[1]) && isfinite(rgb[2]);
+  }
+  float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
+  int rad = 0;
+  uint32_t cnt = 0;
+  float dep = 0.0f;
+  if (live) {
+    r0 = make_float4(g.u, g.v, g.A, g.B);
+    r1 = make_float4(g.C, g.o, rgb[0], rgb[1]);
+    r2 = make_float4(rgb[2], g.t[2], 0.0f, 0.0f);
+    rad = g.radius;
+    dep = g.t[2];
+    int x0, x1, y0, y1;
+    cnt = static_cast<uint32_t>(tile_rect(g.u, g.v, rad, cam.tiles_x, cam.tiles_y, x0, x1, y0, y1));
+  }
+  records[3 * i] = r0;
+  records[3 * i + 1] = r1;
+  records[3 * i + 2] = r2;
+  depth[i] = dep;
+  radius[i] = rad;
+  tiles_touched[i] = cnt;
+}
+
+gs_status launch_project(const gs_gaussians& g, const DevCam& cam, gs_projected& out, hipStream_t s) {
+  const int n = static_cast<int>(g.n);
+  if (n == 0) return GS_OK;
+  const dim3 block(256), grid(static_cast<unsigned>(ceil_div(n, 256)));
+  float4* rec = reinterpret_cast<float4*>(out.records);
+  switch (g.sh_degree) {
+    case 0: k_project<0><<<grid, block, 0, s>>>(n, g.means, g.log_scales, g.quats, g.logits, g.sh, cam, rec,
+                                                 out.depth, out.radius, out.tiles_touched); break;
+    case 1: k_project<1><<<grid, block, 0, s>>>(n, g.means, g.log_scales, g.quats, g.logits, g.sh, cam, rec,
+                                                 out.depth, out.radius, out.tiles_touched); break;
+    case 2: k_project<2><<<grid, block, 0, s>>>(n, g.means, g.log_scales, g.quats, g.logits, g.sh, cam, rec,
+                                                 out.depth, out.radius, out.tiles_touched); break;
+    default: k_project<3><<<grid, block, 0, s>>>(n, g.means, g.log_scales, g.quats, g.logits, g.sh, cam, rec,
+                                                  out.depth, out.radius, out.tiles_touched); break;
+  }
+  return check_launch("k_project");
+}
+
+// ------------------------------------------------------------------ backward
+//
+// Chain rule through project_geometry and the SH colour, per Gaussian.
+//   conic -> Sigma':  dL/dSigma' = -K Gc K with K = [[A, B], [B, C]] and
+//                     Gc = [[gA, gB/2], [gB/2, gC]];
+//   Sigma' = T Sigma T^T:  dL/dSigma = T^T G' T,  dL/dT = 2 G' T Sigma;
+//   T = J W:  dL/dJ = dL/dT W^T;  J(t) with the slope clamp;
+//   Sigma = M M^T, M = R S:  dL/dM = 2 dL/dSigma M,
+//                     dL/ds_k = S_k (R^T dL/dM)_kk,  dL/dR = dL/dM S;
+//   R(q^) -> q^ -> q through the normalisation.
+template <int DEG>
+__global__ __launch_bounds__(256) void k_project_bwd(int n, const float* __restrict__ means,
+                                                     const float* __restrict__ log_scales,
+                                                     const float* __restrict__ quats,
+                                                     const float* __restrict__ logits,
+                                                     const float* __restrict__ sh, DevCam cam,
+                                                     const float* __restrict__ g2d, float* __restrict__ g_means,
+                                                     float* __restrict__ g_scales, float* __restrict__ g_quats,
+                                                     float* __restrict__ g_logits, float* __restrict__ g_sh) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  constexpr int NC = (DEG + 1) * (DEG + 1);
+  float m[3], s[3], q[4];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) { m[k] = means[k * n + i]; s[k] = log_scales[k * n + i]; }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) q[k] = quats[k * n + i];
+  const float logit = logits[i];
+  Geo g;
+  bool live = project_geometry(m, s, q, logit, cam, g);
+  float d[3] = {0, 0, 0}, len = 1.0f;
+  float Y[16];
+  float raw[3] = {0, 0, 0};
+  float f[NC][3];
+#pragma unroll
+  for (int j = 0; j < NC; ++j)
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) f[j][ch] = sh[(3 * j + ch) * n + i];
+  if (live) {
+    view_dir(m, cam, d, len);
+    sh_basis(DEG, d[0], d[1], d[2], Y);
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      float acc = 0.0f;
+#pragma unroll
+      for (int j = 0; j < NC; ++j) acc += Y[j] * f[j][ch];
+      raw[ch] = acc + 0.5f;
+    }
+    live = isfinite(raw[0]) && isfinite(raw[1]) && isfinite(raw[2]);
+  }
+  if (!live) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { g_means[k * n + i] = 0.0f; g_scales[k * n + i] = 0.0f; }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) g_quats[k * n + i] = 0.0f;
+    g_logits[i] = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 3 * NC; ++j) g_sh[j * n + i] = 0.0f;
+    return;
+  }
+  float G[GS_G2D];
+#pragma unroll
+  for (int k = 0; k < GS_G2D; ++k) G[k] = g2d[k * n + i];
+  float gm[3] = {0.0f, 0.0f, 0.0f};
+
+  // ---- colour
+  float gc[3];
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) gc[ch] = raw[ch] >= 0.0f ? G[6 + ch] : 0.0f;
+  float wj[16];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) g_sh[(3 * j + ch) * n + i] = Y[j] * gc[ch];
+    wj[j] = gc[0] * f[j][0] + gc[1] * f[j][1] + gc[2] * f[j][2];
+  }
+  if (DEG > 0) {
+    float gd[3];
+    sh_basis_vjp(DEG, d[0], d[1], d[2], wj, gd[0], gd[1], gd[2]);
+    const float dd = d[0] * gd[0] + d[1] * gd[1] + d[2] * gd[2];
+    const float il = 1.0f / len;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) gm[k] += (gd[k] - d[k] * dd) * il;
+  }
+
+  // ---- opacity
+  g_logits[i] = G[5] * g.o * (1.0f - g.o);
+
+  // ---- conic -> Sigma' (symmetric gradient ga, gb, gc2; gb per off-diagonal entry)
+  const float A = g.A, B = g.B, C = g.C;
+  const float gA = G[2], gB = G[3], gC = G[4];
+  const float ga = -(gA * A * A + gB * A * B + gC * B * B);
+  const float gb = -(gA * A * B + 0.5f * gB * (A * C + B * B) + gC * B * C);
+  const float gcc = -(gA * B * B + gB * B * C + gC * C * C);
+
+  // ---- Sigma' = T Sigma T^T
+  const float* T = g.T;
+  // dL/dSigma = T^T G' T (3x3 symmetric)
+  float GT0[3], GT1[3];  // rows of G' T
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    GT0[k] = ga * T[k] + gb * T[3 + k];
+    GT1[k] = gb * T[k] + gcc * T[3 + k];
+  }
+  float gS[9];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) gS[3 * a + b] = T[a] * GT0[b] + T[3 + a] * GT1[b];
+  // dL/dT = 2 G' T Sigma
+  const float* Sg = g.Sig;
+  const float Sfull[9] = {Sg[0], Sg[1], Sg[2], Sg[1], Sg[3], Sg[4], Sg[2], Sg[4], Sg[5]};
+  float gT[6];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    gT[b] = 2.0f * (GT0[0] * Sfull[b] + GT0[1] * Sfull[3 + b] + GT0[2] * Sfull[6 + b]);
+    gT[3 + b] = 2.0f * (GT1[0] * Sfull[b] + GT1[1] * Sfull[3 + b] + GT1[2] * Sfull[6 + b]);
+  }
+  // dL/dJ = dL/dT W^T ; only J00, J02, J11, J12 are non-zero entries of J
+  const float* W = cam.R;
+  const float gJ00 = gT[0] * W[0] + gT[1] * W[1] + gT[2] * W[2];
+  const float gJ02 = gT[0] * W[6] + gT[1] * W[7] + gT[2] * W[8];
+  const float gJ11 = gT[3] * W[3] + gT[4] * W[4] + gT[5] * W[5];
+  const float gJ12 = gT[3] * W[6] + gT[4] * W[7] + gT[5] * W[8];
+  const float tz = g.t[2];
+  const float itz = 1.0f / tz, itz2 = itz * itz;
+  float gt[3] = {0.0f, 0.0f, 0.0f};
+  // J00 = fx/tz, J11 = fy/tz
+  gt[2] += -(gJ00 * cam.fx + gJ11 * cam.fy) * itz2;
+  // J02 = -fx sx/tz, J12 = -fy sy/tz  (sx = tx/tz unless clamped)
+  gt[2] += (gJ02 * cam.fx * g.sx + gJ12 * cam.fy * g.sy) * itz2;
+  const float gsx = -gJ02 * cam.fx * itz, gsy = -gJ12 * cam.fy * itz;
+  if (!g.clx) { gt[0] += gsx * itz; gt[2] -= gsx * g.t[0] * itz2; }
+  if (!g.cly) { gt[1] += gsy * itz; gt[2] -= gsy * g.t[1] * itz2; }
+  // (u, v) = (fx tx/tz + cx, fy ty/tz + cy)
+  gt[0] += G[0] * cam.fx * itz;
+  gt[1] += G[1] * cam.fy * itz;
+  gt[2] -= (G[0] * cam.fx * g.t[0] + G[1] * cam.fy * g.t[1]) * itz2;
+  // t = W mu + t_cw
+#pragma unroll
+  for (int k = 0; k < 3; ++k) gm[k] += W[k] * gt[0] + W[3 + k] * gt[1] + W[6 + k] * gt[2];
+
+  // ---- Sigma = M M^T, M = R S
+  const float* R = g.R;
+  float M[9];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) M[3 * a + b] = R[3 * a + b] * g.S[b];
+  float gM[9];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+      gM[3 * a + b] = 2.0f * (gS[3 * a] * M[b] + gS[3 * a + 1] * M[3 + b] + gS[3 * a + 2] * M[6 + b]);
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    g_scales[k * n + i] = g.S[k] * (R[k] * gM[k] + R[3 + k] * gM[3 + k] + R[6 + k] * gM[6 + k]);
+  float gR[9];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) gR[3 * a + b] = gM[3 * a + b] * g.S[b];
+  const float w = g.qn[0], x = g.qn[1], y = g.qn[2], z = g.qn[3];
+  float gq[4];
+  gq[0] = 2.0f * (z * (gR[3] - gR[1]) + y * (gR[2] - gR[6]) + x * (gR[7] - gR[5]));
+  gq[1] = 2.0f * (y * (gR[3] + gR[1]) + z * (gR[6] + gR[2]) + w * (gR[7] - gR[5])) - 4.0f * x * (gR[4] + gR[8]);
+  gq[2] = 2.0f * (x * (gR[3] + gR[1]) + w * (gR[2] - gR[6]) + z * (gR[7] + gR[5])) - 4.0f * y * (gR[0] + gR[8]);
+  gq[3] = 2.0f * (w * (gR[3] - gR[1]) + x * (gR[6] + gR[2]) + y * (gR[7] + gR[5])) - 4.0f * z * (gR[0] + gR[4]);
+  const float qd = w * gq[0] + x * gq[1] + y * gq[2] + z * gq[3];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) g_quats[k * n + i] = (gq[k] - g.qn[k] * qd) * g.qinv;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) g_means[k * n + i] = gm[k];
+}
+
+gs_status launch_project_bwd(const gs_gaussians& g, const DevCam& cam, const float* g2d, gs_gaussians_grad& gr,
+                             hipStream_t s) {
+  const int n = static_cast<int>(g.n);
+  if (n == 0) return GS_OK;
+  const dim3 block(256), grid(static_cast<unsigned>(ceil_div(n, 256)));
+#define GS_PB(D)                                                                                                \
+  k_project_bwd<D><<<grid, block, 0, s>>>(n, g.means, g.log_scales, g.quats, g.logits, g.sh, cam, g2d, gr.means, \
+                                          gr.log_scales, gr.quats, gr.logits, gr.sh)
+  switch (g.sh_degree) {
+    case 0: GS_PB(0); break;
+    case 1: GS_PB(1); break;
+    case 2: GS_PB(2); break;
+    default: GS_PB(3); break;
+  }
+#undef GS_PB
+  return check_launch("k_project_bwd");
+}
+
+}  // namespace gs

@@ -1,0 +1,230 @@
+"""ctypes binding of libgsplat.so (include/gsplat.h).
+
+Argument marshalling only: every step runs in the HIP kernels behind the C ABI.
+Tensors are PyTorch device tensors (ROCm); PyTorch provides device memory and
+the current HIP stream.  Importing this module loads the library and raises
+if it is missing -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgsplat.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2510_14564_amd.build` "
+                      "(or __graft_entry__.build()) before using the HIP path")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+TILE = 16
+REC_FLOATS = 12
+G2D = 9
+L1_PARTIALS = 1024
+MLP_PARAMS = 6467
+
+GS_OK, GS_ERR_INVALID_ARG, GS_ERR_CAPACITY, GS_ERR_HIP, GS_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
+STATUS_NAMES = {0: "GS_OK", -1: "GS_ERR_INVALID_ARG", -2: "GS_ERR_CAPACITY", -3: "GS_ERR_HIP",
+                -4: "GS_ERR_UNSUPPORTED"}
+
+# every symbol declared in include/gsplat.h
+EXPORTS = ("gs_last_error", "gs_version", "gs_project", "gs_bin_sort_workspace", "gs_bin_sort",
+           "gs_render_fwd", "gs_render_bwd_workspace", "gs_render_bwd", "gs_project_bwd", "gs_l1_loss")
+
+
+class GsError(RuntimeError):
+    def __init__(self, status: int, fn: str, msg: str):
+        super().__init__(f"{fn} -> {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("fx", ctypes.c_float), ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("near_z", ctypes.c_float), ("tan_half_fov_x", ctypes.c_float), ("tan_half_fov_y", ctypes.c_float),
+                ("R_cw", ctypes.c_float * 9), ("t_cw", ctypes.c_float * 3), ("bg", ctypes.c_float * 3)]
+
+
+class Gaussians(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("sh_degree", ctypes.c_int32), ("colour_mode", ctypes.c_int32),
+                ("means", ctypes.c_void_p), ("log_scales", ctypes.c_void_p), ("quats", ctypes.c_void_p),
+                ("logits", ctypes.c_void_p), ("sh", ctypes.c_void_p), ("latents", ctypes.c_void_p),
+                ("mlp", ctypes.c_void_p)]
+
+
+class Projected(ctypes.Structure):
+    _fields_ = [("records", ctypes.c_void_p), ("depth", ctypes.c_void_p), ("radius", ctypes.c_void_p),
+                ("tiles_touched", ctypes.c_void_p)]
+
+
+class GaussiansGrad(ctypes.Structure):
+    _fields_ = [("means", ctypes.c_void_p), ("log_scales", ctypes.c_void_p), ("quats", ctypes.c_void_p),
+                ("logits", ctypes.c_void_p), ("sh", ctypes.c_void_p), ("latents", ctypes.c_void_p),
+                ("mlp", ctypes.c_void_p)]
+
+
+_vp, _i64, _i32, _sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+_P = ctypes.POINTER
+_sigs = {
+    "gs_last_error": ([], ctypes.c_char_p),
+    "gs_version": ([], ctypes.c_char_p),
+    "gs_project": ([_P(Gaussians), _P(Camera), _P(Projected), _vp], ctypes.c_int),
+    "gs_bin_sort_workspace": ([_i64, _i64, _P(Camera), _P(_sz)], ctypes.c_int),
+    "gs_bin_sort": ([_i64, _P(Projected), _P(Camera), _vp, _sz, _vp, _i64, _vp, _P(_i64), _vp], ctypes.c_int),
+    "gs_render_fwd": ([_i64, _P(Projected), _vp, _vp, _i64, _P(Camera), _vp, _vp, _vp, _vp], ctypes.c_int),
+    "gs_render_bwd_workspace": ([_i64, _i64, _P(Camera), _i32, _P(_sz)], ctypes.c_int),
+    "gs_render_bwd": ([_i64, _P(Projected), _vp, _vp, _i64, _P(Camera), _vp, _vp, _vp, _vp, _vp, _vp, _sz, _i32,
+                       _vp], ctypes.c_int),
+    "gs_project_bwd": ([_P(Gaussians), _P(Camera), _vp, _P(GaussiansGrad), _vp], ctypes.c_int),
+    "gs_l1_loss": ([_vp, _vp, _i64, _vp, _vp, _vp, _vp], ctypes.c_int),
+}
+for _name, (_args, _res) in _sigs.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+
+def version() -> str:
+    return _lib.gs_version().decode()
+
+
+def last_error() -> str:
+    return _lib.gs_last_error().decode()
+
+
+def _check(status: int, fn: str):
+    if status != GS_OK:
+        raise GsError(status, fn, last_error())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def camera_struct(cam) -> Camera:
+    """ctypes camera from a scenes.Camera (or any object with the same fields)."""
+    c = Camera()
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    c.near_z = float(cam.near_z)
+    c.tan_half_fov_x, c.tan_half_fov_y = float(cam.tan_half_fov_x), float(cam.tan_half_fov_y)
+    for i, v in enumerate(list(map(float, cam.R_cw.reshape(9)))):
+        c.R_cw[i] = v
+    for i in range(3):
+        c.t_cw[i] = float(cam.t_cw[i])
+        c.bg[i] = float(cam.bg[i])
+    return c
+
+
+def n_tiles(cam) -> int:
+    return ((cam.width + TILE - 1) // TILE) * ((cam.height + TILE - 1) // TILE)
+
+
+def _check_f32(name, t, shape=None):
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+        raise TypeError(f"{name}: expected a contiguous float32 device tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: shape {tuple(t.shape)} != {tuple(shape)}")
+
+
+def gaussians_struct(means, log_scales, quats, logits, sh, sh_degree: int) -> Gaussians:
+    n = means.shape[1]
+    _check_f32("means", means, (3, n))
+    _check_f32("log_scales", log_scales, (3, n))
+    _check_f32("quats", quats, (4, n))
+    _check_f32("logits", logits, (n,))
+    _check_f32("sh", sh, ((sh_degree + 1) ** 2, 3, n))
+    g = Gaussians()
+    g.n, g.sh_degree, g.colour_mode = n, sh_degree, 0
+    g.means, g.log_scales, g.quats, g.logits, g.sh = (_ptr(means), _ptr(log_scales), _ptr(quats),
+                                                      _ptr(logits), _ptr(sh))
+    return g
+
+
+class ProjectedBuffers:
+    """Device buffers written by gs_project."""
+
+    def __init__(self, n: int, device):
+        self.n = n
+        self.records = torch.empty((n, REC_FLOATS), dtype=torch.float32, device=device)
+        self.depth = torch.empty(n, dtype=torch.float32, device=device)
+        self.radius = torch.empty(n, dtype=torch.int32, device=device)
+        self.tiles_touched = torch.empty(n, dtype=torch.int32, device=device)
+
+    def struct(self) -> Projected:
+        p = Projected()
+        p.records, p.depth, p.radius, p.tiles_touched = (_ptr(self.records), _ptr(self.depth), _ptr(self.radius),
+                                                         _ptr(self.tiles_touched))
+        return p
+
+
+# ------------------------------------------------------------------ entry points
+
+def project(gauss: Gaussians, cam: Camera, out: ProjectedBuffers, stream=None):
+    _check(_lib.gs_project(ctypes.byref(gauss), ctypes.byref(cam), ctypes.byref(out.struct()), _stream(stream)),
+           "gs_project")
+
+
+def bin_sort_workspace(n: int, capacity: int, cam: Camera) -> int:
+    b = ctypes.c_size_t(0)
+    _check(_lib.gs_bin_sort_workspace(n, capacity, ctypes.byref(cam), ctypes.byref(b)), "gs_bin_sort_workspace")
+    return int(b.value)
+
+
+def bin_sort(n: int, proj: ProjectedBuffers, cam: Camera, ws, point_list, ranges, stream=None) -> int:
+    """Returns K; raises GsError(GS_ERR_CAPACITY) with .required = K if point_list is too small."""
+    k = ctypes.c_int64(0)
+    st = _lib.gs_bin_sort(n, ctypes.byref(proj.struct()), ctypes.byref(cam), _ptr(ws), ws.numel() * ws.element_size(),
+                          _ptr(point_list), point_list.numel(), _ptr(ranges), ctypes.byref(k), _stream(stream))
+    if st == GS_ERR_CAPACITY:
+        e = GsError(st, "gs_bin_sort", last_error())
+        e.required = int(k.value)
+        raise e
+    _check(st, "gs_bin_sort")
+    return int(k.value)
+
+
+def render_fwd(n: int, proj: ProjectedBuffers, point_list, ranges, k: int, cam: Camera, image, final_T, n_contrib,
+               stream=None):
+    _check(_lib.gs_render_fwd(n, ctypes.byref(proj.struct()), _ptr(point_list), _ptr(ranges), k, ctypes.byref(cam),
+                              _ptr(image), _ptr(final_T), _ptr(n_contrib), _stream(stream)), "gs_render_fwd")
+
+
+def render_bwd_workspace(n: int, k: int, cam: Camera, deterministic: bool) -> int:
+    b = ctypes.c_size_t(0)
+    _check(_lib.gs_render_bwd_workspace(n, k, ctypes.byref(cam), int(deterministic), ctypes.byref(b)),
+           "gs_render_bwd_workspace")
+    return int(b.value)
+
+
+def render_bwd(n: int, proj: ProjectedBuffers, point_list, ranges, k: int, cam: Camera, image, final_T, n_contrib,
+               dL_dimage, g2d, ws, deterministic: bool = False, stream=None):
+    _check(_lib.gs_render_bwd(n, ctypes.byref(proj.struct()), _ptr(point_list), _ptr(ranges), k, ctypes.byref(cam),
+                              _ptr(image), _ptr(final_T), _ptr(n_contrib), _ptr(dL_dimage), _ptr(g2d), _ptr(ws),
+                              ws.numel() * ws.element_size(), int(deterministic), _stream(stream)), "gs_render_bwd")
+
+
+def project_bwd(gauss: Gaussians, cam: Camera, g2d, grads: dict, stream=None):
+    gg = GaussiansGrad()
+    gg.means, gg.log_scales, gg.quats, gg.logits, gg.sh = (_ptr(grads["means"]), _ptr(grads["log_scales"]),
+                                                           _ptr(grads["quats"]), _ptr(grads["logits"]),
+                                                           _ptr(grads["sh"]))
+    _check(_lib.gs_project_bwd(ctypes.byref(gauss), ctypes.byref(cam), _ptr(g2d), ctypes.byref(gg), _stream(stream)),
+           "gs_project_bwd")
+
+
+def l1_loss(img, target, loss, grad, partials, stream=None):
+    _check(_lib.gs_l1_loss(_ptr(img), _ptr(target), img.numel(), _ptr(loss), _ptr(grad), _ptr(partials),
+                           _stream(stream)), "gs_l1_loss")

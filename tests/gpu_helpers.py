@@ -1,0 +1,105 @@
+"""Shared helpers for the GPU parity tests: upload seeded inputs, run the HIP
+stages through the C ABI, and compare against the FP64 oracle."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import torch
+
+import oracle
+
+DEV = "cuda"
+
+# tolerances (parity section)
+PIX_ATOL = 1e-4          # pixels and final_T, absolute
+GRAD_RTOL = 1e-3         # gradients: |g - g*| <= 1e-3 max(|g*|, 1e-3 max|g*|)
+PROJ_RTOL = 2e-5         # projected quantities, relative to the field's scale
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def upload(scene):
+    return {k: to_dev(v) for k, v in scene.arrays().items()}
+
+
+def gpu_project(gs, scene, cam):
+    p = upload(scene)
+    g = gs.gaussians_struct(p["means"], p["log_scales"], p["quats"], p["logits"], p["sh"], scene.sh_degree)
+    out = gs.ProjectedBuffers(scene.n, DEV)
+    gs.project(g, gs.camera_struct(cam), out)
+    torch.cuda.synchronize()
+    return p, g, out
+
+
+def proj_host(out):
+    rec = out.records.cpu().numpy()
+    return dict(rec=rec, u=rec[:, 0], v=rec[:, 1], depth=out.depth.cpu().numpy(),
+                radius=out.radius.cpu().numpy(), tiles_touched=out.tiles_touched.cpu().numpy())
+
+
+def grad_close(got, want, rtol=GRAD_RTOL, name=""):
+    got = np.asarray(got, np.float64)
+    want = np.asarray(want, np.float64)
+    scale = np.abs(want).max() if want.size else 0.0
+    bound = rtol * np.maximum(np.abs(want), 1e-3 * scale)
+    err = np.abs(got - want)
+    bad = err > bound + 1e-30
+    if bad.any():
+        i = np.argmax(err - bound)
+        raise AssertionError(f"{name}: {bad.sum()}/{bad.size} outside tolerance; worst idx {np.unravel_index(i, want.shape)} "
+                             f"got {got.flat[i]!r} want {want.flat[i]!r} (scale {scale:.3e})")
+    return float((err / np.maximum(np.abs(want), 1e-3 * scale + 1e-30)).max()) if want.size else 0.0
+
+
+def gpu_bin_sort(gs, n, out, cam, capacity=None):
+    cs = gs.camera_struct(cam)
+    cap = capacity if capacity is not None else max(1024, int(out.tiles_touched.sum().item()))
+    ws = torch.empty(gs.bin_sort_workspace(n, cap, cs), dtype=torch.uint8, device=DEV)
+    pl = torch.empty(max(cap, 1), dtype=torch.int32, device=DEV)
+    ranges = torch.empty((gs.n_tiles(cam), 2), dtype=torch.int32, device=DEV)
+    k = gs.bin_sort(n, out, cs, ws, pl, ranges)
+    torch.cuda.synchronize()
+    return k, pl, ranges
+
+
+def gpu_render(gs, n, out, pl, ranges, k, cam):
+    cs = gs.camera_struct(cam)
+    H, W = cam.height, cam.width
+    image = torch.empty((3, H, W), dtype=torch.float32, device=DEV)
+    fT = torch.empty((H, W), dtype=torch.float32, device=DEV)
+    nc = torch.empty((H, W), dtype=torch.int32, device=DEV)
+    gs.render_fwd(n, out, pl, ranges, k, cs, image, fT, nc)
+    torch.cuda.synchronize()
+    return image, fT, nc
+
+
+def gpu_render_bwd(gs, n, out, pl, ranges, k, cam, image, fT, nc, G, deterministic=False):
+    cs = gs.camera_struct(cam)
+    g2d = torch.empty((gs.G2D, n), dtype=torch.float32, device=DEV)
+    ws = torch.empty(max(gs.render_bwd_workspace(n, k, cs, deterministic), 1), dtype=torch.uint8, device=DEV)
+    gs.render_bwd(n, out, pl, ranges, k, cs, image, fT, nc, G, g2d, ws, deterministic)
+    torch.cuda.synchronize()
+    return g2d
+
+
+def compare_render(image, fT, nc, o_img, o_T, o_nc, o_flags, mask=None):
+    """Pixels within PIX_ATOL except pixels the oracle flags as near a threshold;
+    n_contrib exact except flagged pixels.  Returns (max err, #flagged)."""
+    img = image.cpu().numpy().astype(np.float64)
+    T = fT.cpu().numpy().astype(np.float64)
+    n = nc.cpu().numpy()
+    ok = (o_flags == 0) if mask is None else ((o_flags == 0) & mask)
+    err_img = np.abs(img - o_img).max(axis=0)
+    assert (err_img[ok] <= PIX_ATOL).all(), f"max pixel err {err_img[ok].max()}"
+    assert (np.abs(T - o_T)[ok] <= PIX_ATOL).all(), f"max final_T err {np.abs(T - o_T)[ok].max()}"
+    mism = (n != o_nc) & ok
+    assert not mism.any(), f"{mism.sum()} unflagged n_contrib mismatches"
+    return float(err_img[ok].max()) if ok.any() else 0.0, int((o_flags != 0).sum())

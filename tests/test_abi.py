@@ -1,0 +1,128 @@
+"""C ABI checks that need no GPU: the library loads, exports every symbol that
+include/gsplat.h declares, and rejects bad arguments before any HIP call."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2510_14564_amd import scenes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def gs():
+    from paper_2510_14564_amd import gs as mod
+    return mod
+
+
+def _declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "gsplat.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(gs_\w+)\s*\(", txt, flags=re.M)))
+
+
+def test_every_declared_symbol_is_exported(gs):
+    decl = _declared_symbols()
+    assert len(decl) >= 10
+    for name in decl:
+        assert hasattr(gs._lib, name), name
+    assert set(decl) == set(gs.EXPORTS)
+
+
+def test_version_and_empty_error(gs):
+    assert "gfx950" in gs.version()
+    assert gs.last_error() == ""
+
+
+def _cam(gs, **over):
+    c = gs.camera_struct(scenes.config_camera(1))
+    for k, v in over.items():
+        setattr(c, k, v)
+    return c
+
+
+def _gauss(gs, n=10, deg=0, mode=0, null=False):
+    g = gs.Gaussians()
+    g.n, g.sh_degree, g.colour_mode = n, deg, mode
+    p = None if null else ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
+    g.means = g.log_scales = g.quats = g.logits = g.sh = p
+    return g
+
+
+def _proj(gs):
+    p = gs.Projected()
+    p.records = p.depth = p.radius = p.tiles_touched = ctypes.c_void_p(0x1000)
+    return p
+
+
+NULL = ctypes.c_void_p(0)
+
+
+@pytest.mark.parametrize("case", ["neg_n", "deg4", "mode7", "null_arrays", "cam_w0", "cam_nan", "cam_fx0"])
+def test_project_rejects_bad_arguments(gs, case):
+    g, c = _gauss(gs), _cam(gs)
+    if case == "neg_n":
+        g.n = -1
+    elif case == "deg4":
+        g.sh_degree = 4
+    elif case == "mode7":
+        g.colour_mode = 7
+    elif case == "null_arrays":
+        g = _gauss(gs, null=True)
+    elif case == "cam_w0":
+        c.width = 0
+    elif case == "cam_nan":
+        c.fx = float("nan")
+    elif case == "cam_fx0":
+        c.fx = 0.0
+    st = gs._lib.gs_project(ctypes.byref(g), ctypes.byref(c), ctypes.byref(_proj(gs)), NULL)
+    assert st == gs.GS_ERR_INVALID_ARG
+    assert gs.last_error() != ""
+
+
+def test_null_descriptors_rejected(gs):
+    c = _cam(gs)
+    assert gs._lib.gs_project(None, ctypes.byref(c), ctypes.byref(_proj(gs)), NULL) == gs.GS_ERR_INVALID_ARG
+    assert gs._lib.gs_project(ctypes.byref(_gauss(gs)), None, ctypes.byref(_proj(gs)), NULL) == gs.GS_ERR_INVALID_ARG
+
+
+def test_workspace_queries_are_host_only(gs):
+    c = _cam(gs)
+    b = ctypes.c_size_t(0)
+    assert gs._lib.gs_bin_sort_workspace(4096, 20000, ctypes.byref(c), ctypes.byref(b)) == gs.GS_OK
+    assert b.value > 4 * 20000
+    b2 = ctypes.c_size_t(0)
+    assert gs._lib.gs_bin_sort_workspace(4096, 40000, ctypes.byref(c), ctypes.byref(b2)) == gs.GS_OK
+    assert b2.value > b.value
+    assert gs._lib.gs_bin_sort_workspace(-1, 0, ctypes.byref(c), ctypes.byref(b)) == gs.GS_ERR_INVALID_ARG
+    assert gs._lib.gs_render_bwd_workspace(10, 10, ctypes.byref(c), 0, ctypes.byref(b)) == gs.GS_OK
+
+
+def test_bin_sort_rejects_small_workspace_and_bad_alignment(gs):
+    c = _cam(gs)
+    k = ctypes.c_int64(0)
+    st = gs._lib.gs_bin_sort(10, ctypes.byref(_proj(gs)), ctypes.byref(c), ctypes.c_void_p(0x1000), 16,
+                             ctypes.c_void_p(0x1000), 100, ctypes.c_void_p(0x1000), ctypes.byref(k), NULL)
+    assert st == gs.GS_ERR_INVALID_ARG
+    st = gs._lib.gs_bin_sort(10, ctypes.byref(_proj(gs)), ctypes.byref(c), ctypes.c_void_p(0x1004), 1 << 30,
+                             ctypes.c_void_p(0x1000), 100, ctypes.c_void_p(0x1000), ctypes.byref(k), NULL)
+    assert st == gs.GS_ERR_INVALID_ARG
+
+
+def test_render_calls_reject_nulls(gs):
+    c = _cam(gs)
+    st = gs._lib.gs_render_fwd(10, ctypes.byref(_proj(gs)), NULL, NULL, 5, ctypes.byref(c), NULL, NULL, NULL, NULL)
+    assert st == gs.GS_ERR_INVALID_ARG
+    st = gs._lib.gs_render_bwd(10, ctypes.byref(_proj(gs)), NULL, NULL, 5, ctypes.byref(c), NULL, NULL, NULL, NULL,
+                               NULL, NULL, 0, 0, NULL)
+    assert st == gs.GS_ERR_INVALID_ARG
+    assert gs._lib.gs_l1_loss(NULL, NULL, 0, NULL, NULL, NULL, NULL) == gs.GS_ERR_INVALID_ARG
+
+
+def test_camera_struct_layout_matches_header(gs):
+    # int32 x2 + float x7 + R[9] + t[3] + bg[3] = 2*4 + 22*4 bytes
+    assert ctypes.sizeof(gs.Camera) == 8 + 22 * 4
+    assert ctypes.sizeof(gs.Gaussians) == 8 + 4 + 4 + 7 * 8

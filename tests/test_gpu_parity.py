@@ -1,0 +1,173 @@
+"""Staged parity of the HIP path against the FP64 oracle (needs the GPU).
+
+Each stage feeds the oracle the HIP path's own FP32 outputs of the previous
+stage (widened exactly), so threshold decisions that FP32 and FP64 may take
+differently are located, flagged and counted rather than hidden:
+  1 project     : u, v, conic, opacity, colour, depth vs FP64 (relative 2e-5 of
+                  each field's scale); radius exact unless 3 sqrt(lambda) is
+                  within 2e-5 of an integer (flagged)
+  2 bin/sort    : tiles_touched, K, point_list and ranges bit-exact
+  3 render fwd  : pixels and final_T within 1e-4; n_contrib exact, except at
+                  pixels the oracle flags as within 1e-4 (relative) of the
+                  1/255, 1e-4 or 0.99 thresholds
+  4 render bwd  : per-Gaussian record gradients within 1e-3 relative (floor
+                  1e-3 of the largest magnitude); flagged pixels get dL = 0
+  5 project bwd : parameter gradients, same tolerance
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2510_14564_amd import scenes
+from gpu_helpers import (DEV, PROJ_RTOL, compare_render, gpu_bin_sort, gpu_project, gpu_render, gpu_render_bwd,
+                         grad_close, proj_host, say, to_dev)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2510_14564_amd import gs as mod
+    return mod
+
+
+def _case(name):
+    if name == "tiny":
+        return scenes.config_scene(1), scenes.config_camera(1)
+    if name == "tiny_bg":
+        return scenes.config_scene(1), scenes.config_camera(1, bg=(0.2, 0.5, 0.8))
+    if name == "ragged":
+        s = scenes.skewed_scene(20000, 77, n_clusters=16, log_scale_mean=-3.6, sh_degree=3)
+        return s, scenes.pinhole(100, 70, 60.0, np.eye(3), (0.05, -0.02, 3.0), bg=(0.1, 0.0, 0.3))
+    if name == "sh1_sh2":
+        s = scenes.uniform_scene(6000, 12, log_scale_mean=-3.2, sh_degree=2)
+        return s, scenes.orbit_camera(5, 32, 200, 136, 3.5, 60.0)
+    if name == "skewed":
+        return scenes.config_scene(2), scenes.config_camera(2)
+    raise KeyError(name)
+
+
+CASES = ["tiny", "tiny_bg", "ragged", "sh1_sh2", "skewed"]
+
+
+def _project_stage(gs, scene, cam):
+    p, g, out = gpu_project(gs, scene, cam)
+    h = proj_host(out)
+    o = oracle.project(scene, cam)
+    flag_r = (o["flags"] & 1) != 0
+    flag_cull = (o["flags"] & 2) != 0
+    live_g = h["radius"] > 0
+    live_o = o["radius"] > 0
+    assert np.array_equal(live_g[~flag_cull], live_o[~flag_cull]), "cull decisions differ"
+    both = live_g & live_o
+    ok_r = both & ~flag_r
+    assert np.array_equal(h["radius"][ok_r], o["radius"][ok_r]), "radius mismatch"
+    rg, ro = h["rec"][both], o["rec"][both]
+    for j, name in ((0, "u"), (1, "v")):
+        err = np.abs(rg[:, j] - ro[:, j])
+        assert (err <= PROJ_RTOL * np.maximum(1.0, np.abs(ro[:, j]))).all(), (name, err.max())
+    cs = np.abs(ro[:, 2:5]).max(axis=1, keepdims=True)
+    err = np.abs(rg[:, 2:5] - ro[:, 2:5]) / cs
+    assert (err <= PROJ_RTOL).all(), ("conic", err.max())
+    assert np.abs(rg[:, 5] - ro[:, 5]).max() <= 1e-6, "opacity"
+    assert np.abs(rg[:, 6:9] - ro[:, 6:9]).max() <= PROJ_RTOL, ("colour", np.abs(rg[:, 6:9] - ro[:, 6:9]).max())
+    dz = np.abs(h["depth"][both] - o["depth"][both]) / o["depth"][both]
+    assert dz.max() <= 1e-6, ("depth", dz.max())
+    # culled records are zero and have no tiles
+    assert (h["tiles_touched"][~live_g] == 0).all() and (h["rec"][~live_g] == 0).all()
+    say(f"  project: {both.sum()} live, {flag_r.sum()} radius-flagged")
+    return p, g, out, h, o
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_staged_parity(gs, name):
+    scene, cam = _case(name)
+    say(f"[parity {name}] n={scene.n} {cam.width}x{cam.height} deg={scene.sh_degree}")
+    p, g, out, h, o = _project_stage(gs, scene, cam)
+
+    # ---- 2: bin/sort bit-exact on the HIP path's FP32 projection
+    k, pl, ranges = gpu_bin_sort(gs, scene.n, out, cam)
+    o_pl, o_ranges, o_tt, _ = oracle.bin_sort(h["u"], h["v"], h["radius"], h["depth"], cam.width, cam.height)
+    assert np.array_equal(h["tiles_touched"].astype(np.int64), o_tt), "tiles_touched"
+    assert k == len(o_pl), (k, len(o_pl))
+    assert np.array_equal(pl[:k].cpu().numpy().view(np.uint32), o_pl), "point_list"
+    assert np.array_equal(ranges.cpu().numpy().view(np.uint32), o_ranges), "ranges"
+    nt = (o_ranges[:, 1] - o_ranges[:, 0]).astype(np.int64)
+    say(f"  bin/sort: K={k}, max list {nt.max()}, empty tiles {(nt == 0).sum()}")
+
+    # ---- 3: render forward
+    image, fT, nc = gpu_render(gs, scene.n, out, pl, ranges, k, cam)
+    o_img, o_T, o_nc, o_fl = oracle.render_fwd(h["rec"][:, :9], o_pl, o_ranges, cam, margin=1e-4)
+    err, nflag = compare_render(image, fT, nc, o_img, o_T, o_nc, o_fl)
+    say(f"  render fwd: max err {err:.2e}, flagged pixels {nflag}")
+
+    # ---- 4: render backward (flagged pixels carry no upstream gradient)
+    G = scenes.upstream_grad(cam, 1001)
+    G[:, o_fl != 0] = 0.0
+    g2d = gpu_render_bwd(gs, scene.n, out, pl, ranges, k, cam, image, fT, nc, to_dev(G))
+    o_g2d = oracle.render_bwd(h["rec"][:, :9], o_pl, o_ranges, cam, G)
+    g2d_h = g2d.cpu().numpy().T
+    worst = 0.0
+    for j, nm in enumerate("u v A B C o r g b".split()):
+        worst = max(worst, grad_close(g2d_h[:, j], o_g2d[:, j], name=f"g2d.{nm}"))
+    say(f"  render bwd: worst rel err {worst:.2e}")
+
+    # ---- 5: projection backward from the HIP path's g2d
+    grads = {kk: torch.empty_like(v) for kk, v in p.items()}
+    gs.project_bwd(g, gs.camera_struct(cam), g2d, grads)
+    torch.cuda.synchronize()
+    o_gr = oracle.project_bwd(scene, cam, g2d_h.astype(np.float64))
+    skip = (o["flags"] & 0b1110) != 0
+    worst = 0.0
+    for kk in ("means", "log_scales", "quats", "logits", "sh"):
+        got = grads[kk].cpu().numpy()
+        want = o_gr[kk]
+        sel = ~skip
+        worst = max(worst, grad_close(got[..., sel], want[..., sel], name=kk))
+    say(f"  project bwd: worst rel err {worst:.2e}")
+
+
+def test_empty_and_fully_culled_scenes(gs):
+    cam = scenes.config_camera(1, bg=(0.3, 0.2, 0.1))
+    for label, scene in (("empty", scenes.uniform_scene(0, 1)), ("behind", scenes.uniform_scene(300, 2))):
+        say(f"[edge {label}]")
+        if label == "behind":
+            scene.means[2] = -5.0
+        n = scene.n
+        out = gs.ProjectedBuffers(n, DEV)
+        if n:
+            p, g, out = gpu_project(gs, scene, cam)
+        k, pl, ranges = gpu_bin_sort(gs, n, out, cam, capacity=1024)
+        assert k == 0 and (ranges.cpu().numpy() == 0).all()
+        image, fT, nc = gpu_render(gs, n, out, pl, ranges, k, cam)
+        bg = np.asarray(cam.bg, np.float32)
+        assert np.array_equal(image.cpu().numpy(), np.broadcast_to(bg[:, None, None], (3, 128, 128)))
+        assert (fT.cpu().numpy() == 1).all() and (nc.cpu().numpy() == 0).all()
+
+
+def test_capacity_overflow_reports_required_size(gs):
+    scene, cam = _case("tiny")
+    p, g, out = gpu_project(gs, scene, cam)
+    with pytest.raises(gs.GsError) as ei:
+        gpu_bin_sort(gs, scene.n, out, cam, capacity=100)
+    assert ei.value.status == gs.GS_ERR_CAPACITY
+    want = int(out.tiles_touched.sum().item())
+    assert ei.value.required == want
+    k, pl, ranges = gpu_bin_sort(gs, scene.n, out, cam, capacity=want)
+    assert k == want
+
+
+def test_l1_loss(gs):
+    rng = np.random.default_rng(3)
+    a = rng.random((3, 37, 53), dtype=np.float32)
+    b = rng.random((3, 37, 53), dtype=np.float32)
+    from paper_2510_14564_amd.raster import l1_loss
+    loss, grad = l1_loss(to_dev(a), to_dev(b))
+    torch.cuda.synchronize()
+    want = np.abs(a.astype(np.float64) - b).mean()
+    assert abs(loss.item() - want) < 1e-6
+    assert np.array_equal(np.sign(grad.cpu().numpy()), np.sign(a - b))
+    assert np.allclose(np.abs(grad.cpu().numpy()), 1.0 / a.size)
