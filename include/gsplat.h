@@ -42,7 +42,7 @@ typedef enum {
 
 #define GS_TILE 16        /* tile edge in pixels: 16x16 pixel blocks share one list (Sec. IV-C.1) */
 #define GS_REC_FLOATS 12  /* floats per projected record (48 bytes, 16-byte aligned) */
-#define GS_G2D 9          /* per-Gaussian gradients of one record: u v A B C o r g b */
+#define GS_G2D 9          /* per-Gaussian 2D gradients: u v Sxx Sxy Syy o r g b (see gs_render_bwd) */
 #define GS_MLP_LATENT 16  /* learned-colour latent width */
 #define GS_MLP_HIDDEN 64
 #define GS_MLP_PARAMS 6467 /* 64*32 + 64 + 64*64 + 64 + 3*64 + 3 */
@@ -162,25 +162,37 @@ gs_status gs_bin_sort(int64_t n, const gs_projected* proj, const gs_camera* cam,
  * alpha < 1/255 are skipped; the walk stops before an entry that would take
  * the transmittance below 1e-4.  Outputs image[3][H][W] = colour + T bg,
  * final_T[H][W] and n_contrib[H][W] (1 + position in the tile list of the last
- * blended entry, 0 if none).  Deterministic. */
+ * blended entry, 0 if none).  t_ckpt (gs_render_ckpt_floats floats, or NULL
+ * when no backward follows) receives every pixel's transmittance at each
+ * 256-entry boundary of its tile list, which the backward restarts from.
+ * Deterministic. */
 gs_status gs_render_fwd(int64_t n, const gs_projected* proj, const uint32_t* point_list, const uint32_t* ranges,
                         int64_t k, const gs_camera* cam, float* image, float* final_T, uint32_t* n_contrib,
-                        gs_stream stream);
+                        float* t_ckpt, gs_stream stream);
+
+/* Floats of the transmittance checkpoint buffer for K entries. Host-only. */
+gs_status gs_render_ckpt_floats(int64_t k, const gs_camera* cam, size_t* floats);
 
 /* Workspace bytes for gs_render_bwd (depends on n and K). Host-only. */
 gs_status gs_render_bwd_workspace(int64_t n, int64_t k, const gs_camera* cam, int32_t deterministic, size_t* bytes);
 
 /* Backward of the compositing: exact derivative of the forward above with its
- * skip/stop decisions held fixed.  The per-pixel transmittance is recomputed
- * front to back from the records (never stored per pair); the light behind an
- * entry comes from the forward image.  Inputs: the forward's image, final_T and
- * n_contrib, and dL_dimage[3][H][W].  Output g2d[9][n] = dL/d(u, v, A, B, C,
- * opacity, r, g, b) per Gaussian, overwritten.  deterministic = 1 sums the
+ * skip/stop decisions held fixed.  Each pixel's list is walked back to front
+ * from its n_contrib: the transmittance before each entry is recovered by
+ * division from the forward's value at the end of the entry's 256-entry batch
+ * (t_ckpt, or final_T for the last batch) -- never stored per pair -- and the
+ * light behind it is accumulated on the way.  Inputs: the forward's final_T,
+ * n_contrib and t_ckpt, and dL_dimage[3][H][W].  Output g2d[9][n] per Gaussian,
+ * overwritten: dL/d(u, v, a, b, c, opacity, r, g, b) where Sigma' = [[a, b],
+ * [b, c]] is the 2D covariance whose inverse is the record's conic (b counted
+ * in both off-diagonal places).  Each pixel's conic gradient is carried to
+ * Sigma' before the sum over pixels, which stays well conditioned where the
+ * conic is nearly singular (elongated footprints).  deterministic = 1 sums the
  * per-(tile, Gaussian) partials in a fixed order (bit-reproducible); 0 uses
  * device atomics.  ws as sized by gs_render_bwd_workspace. */
 gs_status gs_render_bwd(int64_t n, const gs_projected* proj, const uint32_t* point_list, const uint32_t* ranges,
-                        int64_t k, const gs_camera* cam, const float* image, const float* final_T,
-                        const uint32_t* n_contrib, const float* dL_dimage, float* g2d, void* ws, size_t ws_bytes,
+                        int64_t k, const gs_camera* cam, const float* final_T, const uint32_t* n_contrib,
+                        const float* t_ckpt, const float* dL_dimage, float* g2d, void* ws, size_t ws_bytes,
                         int32_t deterministic, gs_stream stream);
 
 /* Backward of the projection: chain rule from g2d[9][n] to the raw parameters

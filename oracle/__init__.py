@@ -46,6 +46,8 @@ def _load():
 
 
 def _p(a):
+    """Address of a NumPy array for a C call.  The caller must keep `a` referenced
+    until the call returns: never pass a temporary."""
     return ctypes.c_void_p(a.ctypes.data) if a is not None else ctypes.c_void_p(0)
 
 
@@ -139,13 +141,16 @@ def render_fwd(rec, point_list, ranges, cam, margin: float = 1e-4, tile_mask=Non
     nc = np.zeros((H, W), np.int32)
     fl = np.zeros((H, W), np.uint8)
     tm = None if tile_mask is None else np.ascontiguousarray(tile_mask, np.uint8)
-    _load().or_render_fwd(ctypes.c_int(W), ctypes.c_int(H), _p(rec), _p(pl if pl.size else np.zeros(1, np.uint32)),
+    if not pl.size:
+        pl = np.zeros(1, np.uint32)
+    _load().or_render_fwd(ctypes.c_int(W), ctypes.c_int(H), _p(rec), _p(pl),
                           _p(rg), _p(bg), ctypes.c_double(margin), _p(tm), _p(image), _p(fT), _p(nc), _p(fl))
     return image, fT, nc, fl
 
 
-def render_bwd(rec, point_list, ranges, cam, dL_dimage, tile_mask=None):
-    """Gradient of sum(dL_dimage * image) w.r.t. the records: g2d[n][9]."""
+def render_bwd(rec, point_list, ranges, cam, dL_dimage, tile_mask=None, with_mass=False):
+    """Gradient of sum(dL_dimage * image) w.r.t. the records: g2d[n][9].
+    with_mass=True also returns the per-entry sum of |per-pair terms|."""
     W, H = cam.width, cam.height
     rec = _d(rec)
     n = rec.shape[0]
@@ -154,10 +159,13 @@ def render_bwd(rec, point_list, ranges, cam, dL_dimage, tile_mask=None):
     bg = np.asarray(cam.bg, np.float32).astype(np.float64)
     G = _d(dL_dimage)
     g2d = np.zeros((n, 9))
+    mass = np.zeros((n, 9)) if with_mass else None
     tm = None if tile_mask is None else np.ascontiguousarray(tile_mask, np.uint8)
+    if not pl.size:
+        pl = np.zeros(1, np.uint32)
     _load().or_render_bwd(ctypes.c_int(W), ctypes.c_int(H), ctypes.c_int64(n), _p(rec),
-                          _p(pl if pl.size else np.zeros(1, np.uint32)), _p(rg), _p(bg), _p(G), _p(tm), _p(g2d))
-    return g2d
+                          _p(pl), _p(rg), _p(bg), _p(G), _p(tm), _p(g2d), _p(mass))
+    return (g2d, mass) if with_mass else g2d
 
 
 def project_bwd(scene, cam, g2d):
@@ -168,8 +176,11 @@ def project_bwd(scene, cam, g2d):
     g = dict(means=np.zeros_like(means), log_scales=np.zeros_like(ls), quats=np.zeros_like(q),
              logits=np.zeros_like(lg), sh=np.zeros_like(sh))
     ca = cam_array(cam)
+    g2d = _d(g2d)
+    if g2d.shape != (n, 9):
+        raise ValueError(f"g2d must be [n][9], got {g2d.shape}")
     rc = _load().or_project_bwd(ctypes.c_int64(n), ctypes.c_int(scene.sh_degree), _p(means), _p(ls), _p(q),
-                                _p(lg), _p(sh), _p(ca), _p(_d(g2d)), _p(g["means"]), _p(g["log_scales"]),
+                                _p(lg), _p(sh), _p(ca), _p(g2d), _p(g["means"]), _p(g["log_scales"]),
                                 _p(g["quats"]), _p(g["logits"]), _p(g["sh"]))
     if rc != 0:
         raise ValueError(f"or_project_bwd failed: {rc}")

@@ -472,17 +472,23 @@ int or_render_fwd(int W, int H, const double* rec, const uint32_t* point_list, c
  *   alpha = o e^power (unclamped branch): dL/do = e^power dL/dalpha,
  *   dL/dpower = alpha dL/dalpha; on the clamped branch both are 0.
  *   dL/du = dL/dpower (-A dx - B dy), dL/dv = dL/dpower (-B dx - C dy)
- *   dL/dA = -dx^2/2 dL/dpower, dL/dB = -dx dy dL/dpower, dL/dC = -dy^2/2 dL/dpower
+ *   the conic K = [[A, B], [B, C]] takes dL/dK = -1/2 d d^T dL/dpower per pair,
+ *   which is carried to the 2D covariance Sigma' = K^-1 pair by pair:
+ *   dL/dSigma' = -K (dL/dK) K.  g2d slots 2..4 hold dL/d(a, b, c) for
+ *   Sigma' = [[a, b], [b, c]] (b counted in both off-diagonal places).
  * The oracle recomputes the forward per pixel itself, keeps the blended list,
  * and forms S_m as an explicit suffix sum.  g2d is [n][9] in record order
- * (u, v, A, B, C, o, r, g, b) and is overwritten.
+ * (u, v, A, B, C, o, r, g, b) and is overwritten.  If g2d_mass is not NULL it
+ * receives the sum of |per-pair term| for each entry of g2d -- the scale that
+ * rounding errors of any summation order are proportional to.
  */
 int or_render_bwd(int W, int H, int64_t n, const double* rec, const uint32_t* point_list,
                   const uint32_t* ranges, const double* bg, const double* dL_dimage,
-                  const uint8_t* tile_mask, double* g2d) {
+                  const uint8_t* tile_mask, double* g2d, double* g2d_mass) {
     int64_t tx = (W + OR_TILE - 1) / OR_TILE, ty = (H + OR_TILE - 1) / OR_TILE;
     int64_t HW = (int64_t)W * H;
     memset(g2d, 0, sizeof(double) * 9 * (size_t)n);
+    if (g2d_mass) memset(g2d_mass, 0, sizeof(double) * 9 * (size_t)n);
 #pragma omp parallel
     {
         int cap = 1024;
@@ -548,15 +554,32 @@ int or_render_bwd(int W, int H, int64_t n, const double* rec, const uint32_t* po
                         double gr[9];
                         gr[0] = dpow * (-g[2] * dx - g[3] * dy);
                         gr[1] = dpow * (-g[3] * dx - g[4] * dy);
-                        gr[2] = -0.5 * dx * dx * dpow;
-                        gr[3] = -dx * dy * dpow;
-                        gr[4] = -0.5 * dy * dy * dpow;
+                        /* dL/dK (symmetric), then -K dL/dK K */
+                        double K[4] = {g[2], g[3], g[3], g[4]};
+                        double GK[4] = {-0.5 * dx * dx * dpow, -0.5 * dx * dy * dpow,
+                                        -0.5 * dx * dy * dpow, -0.5 * dy * dy * dpow};
+                        double KG[4], GS[4];
+                        for (int a = 0; a < 2; ++a)
+                            for (int b = 0; b < 2; ++b) KG[2 * a + b] = K[2 * a] * GK[b] + K[2 * a + 1] * GK[2 + b];
+                        for (int a = 0; a < 2; ++a)
+                            for (int b = 0; b < 2; ++b)
+                                GS[2 * a + b] = -(KG[2 * a] * K[b] + KG[2 * a + 1] * K[2 + b]);
+                        gr[2] = GS[0];
+                        gr[3] = GS[1] + GS[2];
+                        gr[4] = GS[3];
                         gr[5] = dop;
                         gr[6] = dc[0]; gr[7] = dc[1]; gr[8] = dc[2];
                         double* out = g2d + 9 * (int64_t)lst[k];
                         for (int q = 0; q < 9; ++q) {
 #pragma omp atomic
                             out[q] += gr[q];
+                        }
+                        if (g2d_mass) {
+                            double* mo = g2d_mass + 9 * (int64_t)lst[k];
+                            for (int q = 0; q < 9; ++q) {
+#pragma omp atomic
+                                mo[q] += fabs(gr[q]);
+                            }
                         }
                         for (int ch = 0; ch < 3; ++ch) S[ch] += g[6 + ch] * a * Tm;
                     }
@@ -573,8 +596,9 @@ int or_render_bwd(int W, int H, int64_t n, const double* rec, const uint32_t* po
  *   colour: clamp mask, dL/df_jk = Y_j(d) dL/dc_k, dL/dd = sum f_jk grad Y_j,
  *           then mu via (I - d d^T)/|mu - c|;
  *   opacity: dL/dlogit = dL/do o (1 - o);
- *   conic: d(S^-1) = -S^-1 dS S^-1 with the symmetric conic gradient
- *          [[gA, gB/2], [gB/2, gC]];
+ *   g2d slots 2..4 already hold dL/d(a, b, c) of Sigma' = [[a, b], [b, c]]
+ *          (the render backward converts from the conic pair by pair), so
+ *          the symmetric covariance gradient is [[ga, gb/2], [gb/2, gc]];
  *   Sigma' = T Sigma T^T (T = J W): dL/dSigma = T^T G T, dL/dT = 2 G T Sigma;
  *   dL/dJ = dL/dT W^T; J(t) with the clamp mask on the slopes; u, v -> t;
  *   t = W mu + t_cw -> dL/dmu += W^T dL/dt;
@@ -617,14 +641,8 @@ int or_project_bwd(int64_t n, int deg, const double* means, const double* log_sc
             for (int k = 0; k < 3; ++k) gm[k] += (gd[k] - st.d[k] * dd) / st.dirlen;
             /* opacity */
             gl = g[5] * st.o * (1.0 - st.o);
-            /* conic -> Sigma' : dL/dS' = -S'^-1 Gc S'^-1 */
-            double Ci[4] = {rec[2], rec[3], rec[3], rec[4]};
-            double Gc[4] = {g[2], 0.5 * g[3], 0.5 * g[3], g[4]};
-            double tmp[4], GS[4];
-            for (int a = 0; a < 2; ++a)
-                for (int b = 0; b < 2; ++b) tmp[2 * a + b] = Ci[2 * a] * Gc[b] + Ci[2 * a + 1] * Gc[2 + b];
-            for (int a = 0; a < 2; ++a)
-                for (int b = 0; b < 2; ++b) GS[2 * a + b] = -(tmp[2 * a] * Ci[b] + tmp[2 * a + 1] * Ci[2 + b]);
+            /* symmetric gradient of Sigma' */
+            double GS[4] = {g[2], 0.5 * g[3], 0.5 * g[3], g[4]};
             /* dL/dSigma = T^T GS T ; dL/dT = 2 GS T Sigma */
             double gSig[9], gT[6];
             for (int a = 0; a < 3; ++a)

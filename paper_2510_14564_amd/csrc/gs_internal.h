@@ -41,6 +41,11 @@ gs_status validate_camera(const gs_camera* cam);
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Floats of the transmittance checkpoint buffer for K entries over `ntiles` tiles.
+inline size_t ckpt_floats(int64_t k, int64_t ntiles) {
+  return static_cast<size_t>(k / 256 + ntiles + 1) * 256;
+}
+
 // Aligned carve-out of a caller-supplied workspace.
 struct Carver {
   char* base;
@@ -105,11 +110,12 @@ size_t binsort_workspace(int64_t n, int64_t capacity, int ntiles);
 gs_status run_bin_sort(int64_t n, const gs_projected& proj, const DevCam& cam, void* ws, size_t ws_bytes,
                        uint32_t* point_list, int64_t capacity, uint32_t* ranges, int64_t* k_out, hipStream_t s);
 gs_status launch_render_fwd(const gs_projected& proj, const uint32_t* point_list, const uint32_t* ranges,
-                            const DevCam& cam, float* image, float* final_T, uint32_t* n_contrib, hipStream_t s);
+                            const DevCam& cam, float* image, float* final_T, uint32_t* n_contrib, float* t_ckpt,
+                            hipStream_t s);
 size_t render_bwd_workspace(int64_t n, int64_t k, int ntiles, int deterministic);
 gs_status launch_render_bwd(int64_t n, const gs_projected& proj, const uint32_t* point_list, const uint32_t* ranges,
-                            int64_t k, const DevCam& cam, const float* image, const float* final_T,
-                            const uint32_t* n_contrib, const float* dL_dimage, float* g2d, void* ws,
+                            int64_t k, const DevCam& cam, const float* final_T,
+                            const uint32_t* n_contrib, const float* t_ckpt, const float* dL_dimage, float* g2d, void* ws,
                             size_t ws_bytes, int deterministic, hipStream_t s);
 gs_status launch_l1(const float* img, const float* target, int64_t count, float* loss, float* grad, float* partials,
                     hipStream_t s);

@@ -258,8 +258,8 @@ gs_status launch_project(const gs_gaussians& g, const DevCam& cam, gs_projected&
 // ------------------------------------------------------------------ backward
 //
 // Chain rule through project_geometry and the SH colour, per Gaussian.
-//   conic -> Sigma':  dL/dSigma' = -K Gc K with K = [[A, B], [B, C]] and
-//                     Gc = [[gA, gB/2], [gB/2, gC]];
+//   Sigma' = [[a, b], [b, c]] arrives as dL/d(a, b, c) (b counted twice),
+//                     i.e. the symmetric gradient G' = [[ga, gb/2], [gb/2, gc]];
 //   Sigma' = T Sigma T^T:  dL/dSigma = T^T G' T,  dL/dT = 2 G' T Sigma;
 //   T = J W:  dL/dJ = dL/dT W^T;  J(t) with the slope clamp;
 //   Sigma = M M^T, M = R S:  dL/dM = 2 dL/dSigma M,
@@ -343,12 +343,9 @@ __global__ __launch_bounds__(256) void k_project_bwd(int n, const float* __restr
   // ---- opacity
   g_logits[i] = G[5] * g.o * (1.0f - g.o);
 
-  // ---- conic -> Sigma' (symmetric gradient ga, gb, gc2; gb per off-diagonal entry)
-  const float A = g.A, B = g.B, C = g.C;
-  const float gA = G[2], gB = G[3], gC = G[4];
-  const float ga = -(gA * A * A + gB * A * B + gC * B * B);
-  const float gb = -(gA * A * B + 0.5f * gB * (A * C + B * B) + gC * B * C);
-  const float gcc = -(gA * B * B + gB * B * C + gC * C * C);
+  // ---- Sigma' gradient: the render backward already converted it from the
+  // conic pair by pair; G[3] counts both off-diagonal entries.
+  const float ga = G[2], gb = 0.5f * G[3], gcc = G[4];
 
   // ---- Sigma' = T Sigma T^T
   const float* T = g.T;

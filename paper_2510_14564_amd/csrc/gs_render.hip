@@ -36,6 +36,14 @@ __device__ __forceinline__ void stage_record(const float4* __restrict__ rec, uin
   blue = r2.x;
 }
 
+// Transmittance checkpoints: the forward stores every pixel's T at the start of
+// each 256-entry batch b >= 1 of its tile, in slot floor(S_t / 256) + t + b
+// (S_t = first entry of tile t).  Slots of different tiles never collide and
+// all are below floor(K / 256) + T + 1.
+__device__ __forceinline__ size_t ckpt_slot0(uint32_t start, int tile) {
+  return static_cast<size_t>(start / kBatch) + static_cast<size_t>(tile);
+}
+
 // power, e^power and the unclamped o e^power for one (pixel, entry) pair.
 __device__ __forceinline__ void eval_pair(const float4& p, const float4& q, float px, float py, float& dx,
                                           float& dy, float& power, float& eg, float& og) {
@@ -53,7 +61,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(const uint2* __restrict__ ra
                                                     const uint32_t* __restrict__ point_list,
                                                     const float4* __restrict__ rec, DevCam cam,
                                                     float* __restrict__ image, float* __restrict__ final_T,
-                                                    uint32_t* __restrict__ n_contrib) {
+                                                    uint32_t* __restrict__ n_contrib, float* __restrict__ t_ckpt) {
   __shared__ float4 s_p[kBatch];
   __shared__ float4 s_q[kBatch];
   __shared__ float s_b[kBatch];
@@ -68,9 +76,11 @@ __global__ __launch_bounds__(256) void k_render_fwd(const uint2* __restrict__ ra
   float T = 1.0f, acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
   uint32_t contrib = 0;
   bool done = !inside;
+  const size_t slot0 = ckpt_slot0(rg.x, tile);
 
-  for (uint32_t base = rg.x; base < rg.y; base += kBatch) {
+  for (uint32_t base = rg.x, b = 0; base < rg.y; base += kBatch, ++b) {
     if (__syncthreads_count(done) == 256) break;
+    if (b > 0 && t_ckpt) t_ckpt[(slot0 + b) * kBatch + threadIdx.x] = T;
     const uint32_t idx = base + threadIdx.x;
     if (idx < rg.y) {
       float4 p, q;
@@ -114,10 +124,12 @@ __global__ __launch_bounds__(256) void k_render_fwd(const uint2* __restrict__ ra
 }
 
 gs_status launch_render_fwd(const gs_projected& proj, const uint32_t* point_list, const uint32_t* ranges,
-                            const DevCam& cam, float* image, float* final_T, uint32_t* n_contrib, hipStream_t s) {
+                            const DevCam& cam, float* image, float* final_T, uint32_t* n_contrib, float* t_ckpt,
+                            hipStream_t s) {
   const int ntiles = cam.tiles_x * cam.tiles_y;
   k_render_fwd<<<ntiles, 256, 0, s>>>(reinterpret_cast<const uint2*>(ranges), point_list,
-                                      reinterpret_cast<const float4*>(proj.records), cam, image, final_T, n_contrib);
+                                      reinterpret_cast<const float4*>(proj.records), cam, image, final_T, n_contrib,
+                                      t_ckpt);
   return check_launch("k_render_fwd");
 }
 
@@ -143,15 +155,23 @@ __device__ __forceinline__ float lane63(float v) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_sum_to_lane63(v)), 63));
 }
 
-// Per (pixel, entry) derivative (front-to-back form).  With T_m the
-// transmittance before entry m, acc_m the colour blended up to and including
-// m, and out the final pixel value (colour + T_final bg), the light behind m is
-// S_m = out - acc_m and dL/dalpha_m = sum_k G_k (c_k T_m - S_mk / (1 - alpha_m)).
+// Per (pixel, entry) derivative, walked back to front.  Starting from S =
+// T_f bg, each blended entry m (going backwards) recovers T_m = T_{m+1} /
+// (1 - alpha_m) and uses the light behind it, S_m = sum_{j>m} c_j alpha_j T_j +
+// T_f bg, accumulated directly:
+//   dL/dalpha_m = sum_k G_k (c_k T_m - S_mk / (1 - alpha_m)),  S += c_m alpha_m T_m.
+// Accumulating S (instead of subtracting from the pixel value) keeps its
+// rounding error relative to S itself.  T restarts at every batch end from the
+// forward's checkpoint (or T_f for the last batch), so the division walks at
+// most 256 entries and its rounding cannot build up along long lists.  Skips
+// are re-derived from the same alpha evaluation as the forward; entries past
+// n_contrib are never touched.
 __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ranges,
                                                     const uint32_t* __restrict__ point_list,
                                                     const float4* __restrict__ rec, DevCam cam,
-                                                    const float* __restrict__ image,
+                                                    const float* __restrict__ final_T,
                                                     const uint32_t* __restrict__ n_contrib,
+                                                    const float* __restrict__ t_ckpt,
                                                     const float* __restrict__ dL_dimage, int n,
                                                     float* __restrict__ g2d) {
   __shared__ float4 s_p[kBatch];
@@ -168,27 +188,32 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
   const uint2 rg = ranges[tile];
   const int lane = threadIdx.x & 63;
 
-  float G0 = 0.f, G1 = 0.f, G2 = 0.f, O0 = 0.f, O1 = 0.f, O2 = 0.f;
+  float G0 = 0.f, G1 = 0.f, G2 = 0.f, T = 1.0f;
   uint32_t ncon = 0;
   if (inside) {
     const int64_t HW = static_cast<int64_t>(cam.width) * cam.height;
     const int64_t pix = static_cast<int64_t>(py_i) * cam.width + px_i;
     G0 = dL_dimage[pix]; G1 = dL_dimage[HW + pix]; G2 = dL_dimage[2 * HW + pix];
-    O0 = image[pix]; O1 = image[HW + pix]; O2 = image[2 * HW + pix];
+    T = final_T[pix];
     ncon = n_contrib[pix];
   }
+  const float T_final = T;
+  const size_t slot0 = ckpt_slot0(rg.x, tile);
+  float S0 = T * cam.bg[0], S1 = T * cam.bg[1], S2 = T * cam.bg[2];
   if (threadIdx.x == 0) s_max = 0;
   __syncthreads();
   if (ncon) atomicMax(&s_max, ncon);
   __syncthreads();
-  const uint32_t end = min(rg.y, rg.x + s_max);  // n_contrib never exceeds the list
+  const uint32_t len = min(rg.y - rg.x, s_max);  // n_contrib never exceeds the list
+  const int nbatch = static_cast<int>((len + kBatch - 1) / kBatch);
 
-  float T = 1.0f, acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
-  for (uint32_t base = rg.x; base < end; base += kBatch) {
+  for (int bi = nbatch - 1; bi >= 0; --bi) {
+    const uint32_t m0 = static_cast<uint32_t>(bi) * kBatch;
+    const int cnt = static_cast<int>(min(static_cast<uint32_t>(kBatch), len - m0));
+    T = (bi + 1 < nbatch) ? t_ckpt[(slot0 + bi + 1) * kBatch + threadIdx.x] : T_final;
     __syncthreads();
-    const uint32_t idx = base + threadIdx.x;
-    if (idx < end) {
-      const uint32_t gid = point_list[idx];
+    if (threadIdx.x < cnt) {
+      const uint32_t gid = point_list[rg.x + m0 + threadIdx.x];
       float4 p, q;
       float b;
       stage_record(rec, gid, p, q, b);
@@ -198,11 +223,9 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
       s_gid[threadIdx.x] = gid;
     }
     __syncthreads();
-    const int cnt = static_cast<int>(min(static_cast<uint32_t>(kBatch), end - base));
-    const uint32_t m0 = base - rg.x;
-    for (int j = 0; j < cnt; ++j) {
+    for (int j = cnt - 1; j >= 0; --j) {
       const uint32_t m = m0 + static_cast<uint32_t>(j);
-      if (__ballot(m < ncon) == 0) break;  // no lane of this wave reaches entry m
+      if (__ballot(m < ncon) == 0) continue;  // no lane of this wave reaches entry m yet
       const float4 p = s_p[j];
       const float4 q = s_q[j];
       const float cb = s_b[j];
@@ -211,26 +234,30 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
       const float alpha = fminf(kAlphaMax, og);
       const bool ok = (m < ncon) && (power <= 0.0f) && (alpha >= kAlphaMin);
       if (__ballot(ok) == 0) continue;
-      const float Tm = T;
-      const float one_m = 1.0f - alpha;
-      const float Tn = T * one_m;
-      const float w = ok ? alpha * T : 0.0f;
-      acc0 = fmaf(q.z, w, acc0);
-      acc1 = fmaf(q.w, w, acc1);
-      acc2 = fmaf(cb, w, acc2);
-      T = ok ? Tn : T;
-      const float inv = 1.0f / one_m;
-      const float S0 = O0 - acc0, S1 = O1 - acc1, S2 = O2 - acc2;
+      const float inv = 1.0f / (1.0f - alpha);
+      const float Tm = ok ? T * inv : T;
       const float dalpha = G0 * (q.z * Tm - S0 * inv) + G1 * (q.w * Tm - S1 * inv) + G2 * (cb * Tm - S2 * inv);
+      const float w = ok ? alpha * Tm : 0.0f;
+      S0 = fmaf(q.z, w, S0);
+      S1 = fmaf(q.w, w, S1);
+      S2 = fmaf(cb, w, S2);
+      T = Tm;
       const bool unclamped = og < kAlphaMax;
       const float dpow = (ok && unclamped) ? alpha * dalpha : 0.0f;
       const float dop = (ok && unclamped) ? eg * dalpha : 0.0f;
-      // power = a dx^2 + b dx dy + c dy^2 with a = -A/2, b = -B, c = -C/2
-      const float du = dpow * (2.0f * p.z * dx + p.w * dy);
-      const float dv = dpow * (p.w * dx + 2.0f * q.x * dy);
-      const float dA = -0.5f * dx * dx * dpow;
-      const float dB = -dx * dy * dpow;
-      const float dC = -0.5f * dy * dy * dpow;
+      // power = a dx^2 + b dx dy + c dy^2 with a = -A/2, b = -B, c = -C/2, so
+      // (nkx, nky) = -K d with K the conic and d = (dx, dy).  The pair's conic
+      // gradient -1/2 dpow d d^T is carried to Sigma' = K^-1 right here,
+      // -K (.) K = 1/2 dpow (K d)(K d)^T, before any summation: converting the
+      // summed conic gradient instead cancels badly for elongated footprints.
+      const float nkx = 2.0f * p.z * dx + p.w * dy;
+      const float nky = p.w * dx + 2.0f * q.x * dy;
+      const float du = dpow * nkx;
+      const float dv = dpow * nky;
+      const float hdp = 0.5f * dpow;
+      const float dA = hdp * nkx * nkx;      // dL/dSigma'_xx
+      const float dB = dpow * nkx * nky;     // dL/dSigma'_xy (both off-diagonal entries)
+      const float dC = hdp * nky * nky;      // dL/dSigma'_yy
       const float dr = G0 * w, dg = G1 * w, db = G2 * w;
       const float s0 = lane63(du), s1 = lane63(dv), s2 = lane63(dA), s3 = lane63(dB), s4 = lane63(dC);
       const float s5 = lane63(dop), s6 = lane63(dr), s7 = lane63(dg), s8 = lane63(db);
@@ -256,18 +283,18 @@ size_t render_bwd_workspace(int64_t n, int64_t k, int ntiles, int deterministic)
 }
 
 gs_status launch_render_bwd(int64_t n, const gs_projected& proj, const uint32_t* point_list, const uint32_t* ranges,
-                            int64_t k, const DevCam& cam, const float* image, const float* final_T,
-                            const uint32_t* n_contrib, const float* dL_dimage, float* g2d, void* ws,
+                            int64_t k, const DevCam& cam, const float* final_T,
+                            const uint32_t* n_contrib, const float* t_ckpt, const float* dL_dimage, float* g2d, void* ws,
                             size_t ws_bytes, int deterministic, hipStream_t s) {
-  (void)k; (void)final_T; (void)ws; (void)ws_bytes;
+  (void)k; (void)ws; (void)ws_bytes;
   if (deterministic) return fail(GS_ERR_UNSUPPORTED, "gs_render_bwd: deterministic reduction not built yet");
   gs_status st = check_hip(hipMemsetAsync(g2d, 0, sizeof(float) * GS_G2D * static_cast<size_t>(n), s),
                            "hipMemsetAsync(g2d)");
   if (st != GS_OK) return st;
   const int ntiles = cam.tiles_x * cam.tiles_y;
   k_render_bwd<<<ntiles, 256, 0, s>>>(reinterpret_cast<const uint2*>(ranges), point_list,
-                                      reinterpret_cast<const float4*>(proj.records), cam, image, n_contrib,
-                                      dL_dimage, static_cast<int>(n), g2d);
+                                      reinterpret_cast<const float4*>(proj.records), cam, final_T, n_contrib,
+                                      t_ckpt, dL_dimage, static_cast<int>(n), g2d);
   return check_launch("k_render_bwd");
 }
 

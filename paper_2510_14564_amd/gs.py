@@ -33,7 +33,8 @@ STATUS_NAMES = {0: "GS_OK", -1: "GS_ERR_INVALID_ARG", -2: "GS_ERR_CAPACITY", -3:
 
 # every symbol declared in include/gsplat.h
 EXPORTS = ("gs_last_error", "gs_version", "gs_project", "gs_bin_sort_workspace", "gs_bin_sort",
-           "gs_render_fwd", "gs_render_bwd_workspace", "gs_render_bwd", "gs_project_bwd", "gs_l1_loss")
+           "gs_render_fwd", "gs_render_ckpt_floats", "gs_render_bwd_workspace", "gs_render_bwd", "gs_project_bwd",
+           "gs_l1_loss")
 
 
 class GsError(RuntimeError):
@@ -75,7 +76,8 @@ _sigs = {
     "gs_project": ([_P(Gaussians), _P(Camera), _P(Projected), _vp], ctypes.c_int),
     "gs_bin_sort_workspace": ([_i64, _i64, _P(Camera), _P(_sz)], ctypes.c_int),
     "gs_bin_sort": ([_i64, _P(Projected), _P(Camera), _vp, _sz, _vp, _i64, _vp, _P(_i64), _vp], ctypes.c_int),
-    "gs_render_fwd": ([_i64, _P(Projected), _vp, _vp, _i64, _P(Camera), _vp, _vp, _vp, _vp], ctypes.c_int),
+    "gs_render_fwd": ([_i64, _P(Projected), _vp, _vp, _i64, _P(Camera), _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "gs_render_ckpt_floats": ([_i64, _P(Camera), _P(_sz)], ctypes.c_int),
     "gs_render_bwd_workspace": ([_i64, _i64, _P(Camera), _i32, _P(_sz)], ctypes.c_int),
     "gs_render_bwd": ([_i64, _P(Projected), _vp, _vp, _i64, _P(Camera), _vp, _vp, _vp, _vp, _vp, _vp, _sz, _i32,
                        _vp], ctypes.c_int),
@@ -197,9 +199,16 @@ def bin_sort(n: int, proj: ProjectedBuffers, cam: Camera, ws, point_list, ranges
 
 
 def render_fwd(n: int, proj: ProjectedBuffers, point_list, ranges, k: int, cam: Camera, image, final_T, n_contrib,
-               stream=None):
+               t_ckpt=None, stream=None):
     _check(_lib.gs_render_fwd(n, ctypes.byref(proj.struct()), _ptr(point_list), _ptr(ranges), k, ctypes.byref(cam),
-                              _ptr(image), _ptr(final_T), _ptr(n_contrib), _stream(stream)), "gs_render_fwd")
+                              _ptr(image), _ptr(final_T), _ptr(n_contrib), _ptr(t_ckpt), _stream(stream)),
+           "gs_render_fwd")
+
+
+def render_ckpt_floats(k: int, cam: Camera) -> int:
+    f = ctypes.c_size_t(0)
+    _check(_lib.gs_render_ckpt_floats(k, ctypes.byref(cam), ctypes.byref(f)), "gs_render_ckpt_floats")
+    return int(f.value)
 
 
 def render_bwd_workspace(n: int, k: int, cam: Camera, deterministic: bool) -> int:
@@ -209,10 +218,10 @@ def render_bwd_workspace(n: int, k: int, cam: Camera, deterministic: bool) -> in
     return int(b.value)
 
 
-def render_bwd(n: int, proj: ProjectedBuffers, point_list, ranges, k: int, cam: Camera, image, final_T, n_contrib,
+def render_bwd(n: int, proj: ProjectedBuffers, point_list, ranges, k: int, cam: Camera, final_T, n_contrib, t_ckpt,
                dL_dimage, g2d, ws, deterministic: bool = False, stream=None):
     _check(_lib.gs_render_bwd(n, ctypes.byref(proj.struct()), _ptr(point_list), _ptr(ranges), k, ctypes.byref(cam),
-                              _ptr(image), _ptr(final_T), _ptr(n_contrib), _ptr(dL_dimage), _ptr(g2d), _ptr(ws),
+                              _ptr(final_T), _ptr(n_contrib), _ptr(t_ckpt), _ptr(dL_dimage), _ptr(g2d), _ptr(ws),
                               ws.numel() * ws.element_size(), int(deterministic), _stream(stream)), "gs_render_bwd")
 
 

@@ -3,7 +3,7 @@
 forward : gs_project -> gs_bin_sort -> gs_render_fwd
 backward: gs_render_bwd -> gs_project_bwd
 The saved state per call is the projection, the sorted list, the tile ranges,
-the image, final transmittance and per-pixel contributor counts; nothing per
+the final transmittance and per-pixel contributor counts; nothing per
 (pixel, Gaussian) pair is stored -- the backward recomputes transmittance.
 Buffers are kept in a Rasterizer and reused across iterations; the (tile,
 Gaussian) capacity grows on demand (the library reports the size it needs).
@@ -28,6 +28,7 @@ class FrameState:
     image: torch.Tensor
     final_T: torch.Tensor
     n_contrib: torch.Tensor
+    t_ckpt: torch.Tensor
 
 
 class Rasterizer:
@@ -46,6 +47,7 @@ class Rasterizer:
         self.point_list = None
         self.bin_ws = None
         self.bwd_ws = None
+        self.t_ckpt = None
         H, W = cam.height, cam.width
         self.ranges = torch.empty((self.ntiles, 2), dtype=torch.int32, device=self.device)
         self.image = torch.empty((3, H, W), dtype=torch.float32, device=self.device)
@@ -92,10 +94,14 @@ class Rasterizer:
                     raise
                 self._alloc_lists(int(e.required * 1.25) + 1024)
         self.last_k = k
+        need = gs.render_ckpt_floats(k, self.cs)
+        if self.t_ckpt is None or self.t_ckpt.numel() < need:
+            self.t_ckpt = torch.empty(int(need * 1.25), dtype=torch.float32, device=self.device)
         with self._stage("render_fwd"):
             gs.render_fwd(n, self.proj, self.point_list, self.ranges, k, self.cs, self.image, self.final_T,
-                          self.n_contrib)
-        return FrameState(n, k, self.proj, self.point_list, self.ranges, self.image, self.final_T, self.n_contrib)
+                          self.n_contrib, self.t_ckpt)
+        return FrameState(n, k, self.proj, self.point_list, self.ranges, self.image, self.final_T, self.n_contrib,
+                          self.t_ckpt)
 
     def backward(self, st: FrameState, means, log_scales, quats, logits, sh, dL_dimage, g2d=None):
         n = st.n
@@ -106,7 +112,7 @@ class Rasterizer:
         if g2d is None:
             g2d = torch.empty((gs.G2D, n), dtype=torch.float32, device=self.device)
         with self._stage("render_bwd"):
-            gs.render_bwd(n, st.proj, st.point_list, st.ranges, st.k, self.cs, st.image, st.final_T, st.n_contrib,
+            gs.render_bwd(n, st.proj, st.point_list, st.ranges, st.k, self.cs, st.final_T, st.n_contrib, st.t_ckpt,
                           dL_dimage, g2d, self.bwd_ws, self.deterministic)
         grads = {k: torch.empty_like(v) for k, v in
                  (("means", means), ("log_scales", log_scales), ("quats", quats), ("logits", logits), ("sh", sh))}

@@ -3,15 +3,18 @@
 Each stage feeds the oracle the HIP path's own FP32 outputs of the previous
 stage (widened exactly), so threshold decisions that FP32 and FP64 may take
 differently are located, flagged and counted rather than hidden:
-  1 project     : u, v, conic, opacity, colour, depth vs FP64 (relative 2e-5 of
-                  each field's scale); radius exact unless 3 sqrt(lambda) is
-                  within 2e-5 of an integer (flagged)
+  1 project     : u, v and depth within 4x their FP32 rounding bound; opacity
+                  and colour within 1e-6 / 2e-5; conic within 2e-5 + 4e-7 cond(Sigma') of its
+                  largest entry; radius exact unless 3 sqrt(lambda) is within
+                  2e-5 of an integer (flagged)
   2 bin/sort    : tiles_touched, K, point_list and ranges bit-exact
   3 render fwd  : pixels and final_T within 1e-4; n_contrib exact, except at
                   pixels the oracle flags as within 1e-4 (relative) of the
                   1/255, 1e-4 or 0.99 thresholds
-  4 render bwd  : per-Gaussian record gradients within 1e-3 relative (floor
-                  1e-3 of the largest magnitude); flagged pixels get dL = 0
+  4 render bwd  : per-Gaussian record gradients within 1e-3 relative, against
+                  max(|g*|, 1e-3 max|g*|, 1e-2 sum|terms|) -- a sum that cancels
+                  by over 100x is judged against its terms, which its rounding
+                  error scales with; flagged pixels get dL = 0
   5 project bwd : parameter gradients, same tolerance
 """
 import numpy as np
@@ -66,16 +69,32 @@ def _project_stage(gs, scene, cam):
     ok_r = both & ~flag_r
     assert np.array_equal(h["radius"][ok_r], o["radius"][ok_r]), "radius mismatch"
     rg, ro = h["rec"][both], o["rec"][both]
-    for j, name in ((0, "u"), (1, "v")):
+    # FP32 rounding bounds for t = W mu + t_cw and u = fx tx / tz + cx (4x safety):
+    #   |dt_i| <= 3 eps (sum_j |W_ij mu_j| + |t_i|),
+    #   |du| <= fx/tz |dtx| + |u - cx| (4 eps + |dtz|/tz) + eps (|u| + |cx|)
+    eps = 2.0 ** -24
+    W = np.asarray(cam.R_cw, np.float64)
+    mu = scene.means.astype(np.float64)[:, both]
+    tc = np.asarray(cam.t_cw, np.float64)
+    mag = np.abs(W) @ np.abs(mu) + np.abs(tc)[:, None]
+    dt = 3 * eps * mag
+    tz = o["depth"][both]
+    for j, name, f, c in ((0, "u", cam.fx, cam.cx), (1, "v", cam.fy, cam.cy)):
+        bound = f / tz * dt[j] + np.abs(ro[:, j] - c) * (4 * eps + dt[2] / tz) + eps * (np.abs(ro[:, j]) + c)
         err = np.abs(rg[:, j] - ro[:, j])
-        assert (err <= PROJ_RTOL * np.maximum(1.0, np.abs(ro[:, j]))).all(), (name, err.max())
-    cs = np.abs(ro[:, 2:5]).max(axis=1, keepdims=True)
-    err = np.abs(rg[:, 2:5] - ro[:, 2:5]) / cs
-    assert (err <= PROJ_RTOL).all(), ("conic", err.max())
+        assert (err <= 4 * bound).all(), (name, err.max(), (err / bound).max())
+    # the FP32 error of a 2x2 inverse grows with the condition number of Sigma'
+    A, B, C = ro[:, 2], ro[:, 3], ro[:, 4]
+    disc = np.sqrt(((A - C) / 2) ** 2 + B ** 2)
+    cond = ((A + C) / 2 + disc) / ((A + C) / 2 - disc)
+    cs = np.abs(ro[:, 2:5]).max(axis=1)
+    err = (np.abs(rg[:, 2:5] - ro[:, 2:5]).max(axis=1)) / cs
+    tol = PROJ_RTOL + 4e-7 * cond
+    assert (err <= tol).all(), ("conic", err.max(), (err / tol).max())
     assert np.abs(rg[:, 5] - ro[:, 5]).max() <= 1e-6, "opacity"
     assert np.abs(rg[:, 6:9] - ro[:, 6:9]).max() <= PROJ_RTOL, ("colour", np.abs(rg[:, 6:9] - ro[:, 6:9]).max())
-    dz = np.abs(h["depth"][both] - o["depth"][both]) / o["depth"][both]
-    assert dz.max() <= 1e-6, ("depth", dz.max())
+    dz = np.abs(h["depth"][both] - o["depth"][both])
+    assert (dz <= 4 * dt[2]).all(), ("depth", (dz / dt[2]).max())
     # culled records are zero and have no tiles
     assert (h["tiles_touched"][~live_g] == 0).all() and (h["rec"][~live_g] == 0).all()
     say(f"  project: {both.sum()} live, {flag_r.sum()} radius-flagged")
@@ -99,7 +118,7 @@ def test_staged_parity(gs, name):
     say(f"  bin/sort: K={k}, max list {nt.max()}, empty tiles {(nt == 0).sum()}")
 
     # ---- 3: render forward
-    image, fT, nc = gpu_render(gs, scene.n, out, pl, ranges, k, cam)
+    image, fT, nc, ck = gpu_render(gs, scene.n, out, pl, ranges, k, cam)
     o_img, o_T, o_nc, o_fl = oracle.render_fwd(h["rec"][:, :9], o_pl, o_ranges, cam, margin=1e-4)
     err, nflag = compare_render(image, fT, nc, o_img, o_T, o_nc, o_fl)
     say(f"  render fwd: max err {err:.2e}, flagged pixels {nflag}")
@@ -107,13 +126,16 @@ def test_staged_parity(gs, name):
     # ---- 4: render backward (flagged pixels carry no upstream gradient)
     G = scenes.upstream_grad(cam, 1001)
     G[:, o_fl != 0] = 0.0
-    g2d = gpu_render_bwd(gs, scene.n, out, pl, ranges, k, cam, image, fT, nc, to_dev(G))
-    o_g2d = oracle.render_bwd(h["rec"][:, :9], o_pl, o_ranges, cam, G)
+    g2d = gpu_render_bwd(gs, scene.n, out, pl, ranges, k, cam, fT, nc, ck, to_dev(G))
+    o_g2d, o_mass = oracle.render_bwd(h["rec"][:, :9], o_pl, o_ranges, cam, G, with_mass=True)
     g2d_h = g2d.cpu().numpy().T
     worst = 0.0
-    for j, nm in enumerate("u v A B C o r g b".split()):
-        worst = max(worst, grad_close(g2d_h[:, j], o_g2d[:, j], name=f"g2d.{nm}"))
-    say(f"  render bwd: worst rel err {worst:.2e}")
+    mass_used = {}
+    for j, nm in enumerate("u v Sxx Sxy Syy o r g b".split()):
+        worst = max(worst, grad_close(g2d_h[:, j], o_g2d[:, j], name=f"g2d.{nm}", mass=o_mass[:, j],
+                                      stats=mass_used))
+    say(f"  render bwd: worst rel err {worst:.2e}; entries judged against term mass: "
+        f"{sum(mass_used.values())} of {g2d_h.size}")
 
     # ---- 5: projection backward from the HIP path's g2d
     grads = {kk: torch.empty_like(v) for kk, v in p.items()}
@@ -142,7 +164,7 @@ def test_empty_and_fully_culled_scenes(gs):
             p, g, out = gpu_project(gs, scene, cam)
         k, pl, ranges = gpu_bin_sort(gs, n, out, cam, capacity=1024)
         assert k == 0 and (ranges.cpu().numpy() == 0).all()
-        image, fT, nc = gpu_render(gs, n, out, pl, ranges, k, cam)
+        image, fT, nc, _ = gpu_render(gs, n, out, pl, ranges, k, cam)
         bg = np.asarray(cam.bg, np.float32)
         assert np.array_equal(image.cpu().numpy(), np.broadcast_to(bg[:, None, None], (3, 128, 128)))
         assert (fT.cpu().numpy() == 1).all() and (nc.cpu().numpy() == 0).all()
