@@ -274,26 +274,59 @@ __global__ __launch_bounds__(256) void k_gather_counts(int n, const uint32_t* __
   out[r] = tiles_touched[order[r]];
 }
 
-// One thread per Gaussian in depth-rank order writes its tiles row-major.
+// Emit: a wave takes 64 consecutive depth ranks and writes all of their
+// (tile, Gaussian) entries cooperatively -- lane l writes entries l, l+64, ...
+// of the wave's contiguous output range -- so stores are coalesced and a
+// Gaussian covering thousands of tiles does not serialise one thread.  Each
+// Gaussian's tiles are written row-major over its rectangle.
 __global__ __launch_bounds__(256) void k_emit(int n, const uint32_t* __restrict__ order,
                                               const uint32_t* __restrict__ offsets,
                                               const float4* __restrict__ records, const int* __restrict__ radius,
                                               int tiles_x, int tiles_y, uint32_t* __restrict__ tile_keys,
                                               uint32_t* __restrict__ gids) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  const uint32_t gid = order[r];
-  const float4 rec = records[3 * gid];
-  int x0, x1, y0, y1;
-  const int cnt = tile_rect(rec.x, rec.y, radius[gid], tiles_x, tiles_y, x0, x1, y0, y1);
-  if (cnt == 0) return;
-  uint32_t o = offsets[r];
-  for (int y = y0; y <= y1; ++y)
-    for (int x = x0; x <= x1; ++x) {
-      tile_keys[o] = static_cast<uint32_t>(y * tiles_x + x);
-      gids[o] = gid;
-      ++o;
+  __shared__ uint32_t s_pre[4][65];   // exclusive prefix of entry counts within the wave, plus total
+  __shared__ uint32_t s_gid[4][64];
+  __shared__ int s_x0[4][64], s_y0[4][64], s_w[4][64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = (blockIdx.x * 4 + wave) * 64 + lane;
+  uint32_t cnt = 0, gid = 0;
+  int x0 = 0, x1 = -1, y0 = 0, y1 = -1;
+  if (r < n) {
+    gid = order[r];
+    const float4 rec = records[3 * gid];
+    cnt = static_cast<uint32_t>(tile_rect(rec.x, rec.y, radius[gid], tiles_x, tiles_y, x0, x1, y0, y1));
+  }
+  // inclusive scan of cnt over the wave (Hillis-Steele with shuffles)
+  uint32_t incl = cnt;
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t t = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += t;
+  }
+  s_pre[wave][lane] = incl - cnt;
+  if (lane == 63) s_pre[wave][64] = incl;
+  s_gid[wave][lane] = gid;
+  s_x0[wave][lane] = x0;
+  s_y0[wave][lane] = y0;
+  s_w[wave][lane] = x1 - x0 + 1;
+  __syncthreads();
+  const int r0 = (blockIdx.x * 4 + wave) * 64;
+  if (r0 >= n) return;
+  const uint32_t total = s_pre[wave][64];
+  const uint32_t base = offsets[r0];
+  for (uint32_t p = lane; p < total; p += 64) {
+    // owner: the last k with s_pre[k] <= p (binary search over 64 prefixes)
+    int lo = 0, hi = 63;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_pre[wave][mid] <= p) lo = mid; else hi = mid - 1;
     }
+    const uint32_t j = p - s_pre[wave][lo];
+    const uint32_t w = static_cast<uint32_t>(s_w[wave][lo]);
+    const uint32_t row = j / w, col = j - row * w;
+    tile_keys[base + p] = static_cast<uint32_t>((s_y0[wave][lo] + static_cast<int>(row)) * tiles_x +
+                                                s_x0[wave][lo] + static_cast<int>(col));
+    gids[base + p] = s_gid[wave][lo];
+  }
 }
 
 // ranges[t] = [lower_bound(t), lower_bound(t + 1)) over the sorted tile ids.
@@ -382,8 +415,9 @@ gs_status run_bin_sort(int64_t n64, const gs_projected& proj, const DevCam& cam,
       uint32_t* va = (tp % 2 == 0) ? point_list : b.ev1;
       uint32_t* kb = b.ek1;
       uint32_t* vb = (tp % 2 == 0) ? b.ev1 : point_list;
-      k_emit<<<g, 256, 0, s>>>(n, order, b.offs, reinterpret_cast<const float4*>(proj.records), proj.radius,
-                               cam.tiles_x, cam.tiles_y, ka, va);
+      k_emit<<<static_cast<unsigned>(ceil_div(n, 256)), 256, 0, s>>>(
+          n, order, b.offs, reinterpret_cast<const float4*>(proj.records), proj.radius, cam.tiles_x, cam.tiles_y, ka,
+          va);
       if ((st = check_launch("k_emit")) != GS_OK) return st;
       int p2 = 0;
       if ((st = radix_sort_pairs(ka, va, kb, vb, K, tbits, b.hist, b.scan, s, &p2)) != GS_OK) return st;

@@ -22,19 +22,9 @@
 namespace gs {
 
 constexpr int kBatch = 256;
-
-// Records are staged in LDS with the conic pre-scaled so that
-// power = a dx^2 + b dx dy + c dy^2:  p = (u, v, a = -A/2, b = -B),
-// q = (c = -C/2, opacity, r, g), blue separately.
-__device__ __forceinline__ void stage_record(const float4* __restrict__ rec, uint32_t gid, float4& p, float4& q,
-                                             float& blue) {
-  const float4 r0 = rec[3 * gid];
-  const float4 r1 = rec[3 * gid + 1];
-  const float4 r2 = rec[3 * gid + 2];
-  p = make_float4(r0.x, r0.y, -0.5f * r0.z, -r0.w);
-  q = make_float4(-0.5f * r1.x, r1.y, r1.z, r1.w);
-  blue = r2.x;
-}
+constexpr int kUnroll = 4;
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
 
 // Transmittance checkpoints: the forward stores every pixel's T at the start of
 // each 256-entry batch b >= 1 of its tile, in slot floor(S_t / 256) + t + b
@@ -44,14 +34,30 @@ __device__ __forceinline__ size_t ckpt_slot0(uint32_t start, int tile) {
   return static_cast<size_t>(start / kBatch) + static_cast<size_t>(tile);
 }
 
-// power, e^power and the unclamped o e^power for one (pixel, entry) pair.
+// Records are staged in LDS with the conic pre-scaled by -log2(e)/2 (and
+// -log2(e) off-diagonal) so that the base-2 exponent is
+//   p2 = a dx^2 + b dx dy + c dy^2 = power * log2(e),
+// and alpha's Gaussian factor is a single v_exp_f32: p = (u, v, a, b),
+// q = (c, opacity, r, g), blue separately.  Slots past the end of a batch
+// hold a null record (opacity 0), which every pixel skips.
+__device__ __forceinline__ void stage_record(const float4* __restrict__ rec, uint32_t gid, float4& p, float4& q,
+                                             float& blue) {
+  const float4 r0 = rec[3 * gid];
+  const float4 r1 = rec[3 * gid + 1];
+  const float4 r2 = rec[3 * gid + 2];
+  p = make_float4(r0.x, r0.y, -0.5f * kLog2e * r0.z, -kLog2e * r0.w);
+  q = make_float4(-0.5f * kLog2e * r1.x, r1.y, r1.z, r1.w);
+  blue = r2.x;
+}
+
+// p2 (base-2 power), 2^p2 and the unclamped o 2^p2 for one (pixel, entry) pair.
 __device__ __forceinline__ void eval_pair(const float4& p, const float4& q, float px, float py, float& dx,
-                                          float& dy, float& power, float& eg, float& og) {
+                                          float& dy, float& p2, float& eg, float& og) {
   dx = p.x - px;
   dy = p.y - py;
   const float dxx = dx * dx, dyy = dy * dy, dxy = dx * dy;
-  power = fmaf(p.z, dxx, fmaf(q.x, dyy, p.w * dxy));
-  eg = __expf(power);
+  p2 = fmaf(p.z, dxx, fmaf(q.x, dyy, p.w * dxy));
+  eg = __builtin_amdgcn_exp2f(p2);
   og = q.y * eg;
 }
 
@@ -84,32 +90,41 @@ __global__ __launch_bounds__(256) void k_render_fwd(const uint2* __restrict__ ra
     const uint32_t idx = base + threadIdx.x;
     if (idx < rg.y) {
       float4 p, q;
-      float b;
-      stage_record(rec, point_list[idx], p, q, b);
+      float bl;
+      stage_record(rec, point_list[idx], p, q, bl);
       s_p[threadIdx.x] = p;
       s_q[threadIdx.x] = q;
-      s_b[threadIdx.x] = b;
+      s_b[threadIdx.x] = bl;
+    } else {
+      s_p[threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
+      s_q[threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
+      s_b[threadIdx.x] = 0.f;
     }
     __syncthreads();
     const int cnt = static_cast<int>(min(static_cast<uint32_t>(kBatch), rg.y - base));
-    for (int j = 0; j < cnt; ++j) {
+    const uint32_t m0 = base - rg.x + 1u;
+    for (int j0 = 0; j0 < cnt; j0 += kUnroll) {
       if (__ballot(!done) == 0) break;  // whole wave finished: leave the batch
-      const float4 p = s_p[j];
-      const float4 q = s_q[j];
-      float dx, dy, power, eg, og;
-      eval_pair(p, q, px, py, dx, dy, power, eg, og);
-      const float alpha = fminf(kAlphaMax, og);
-      const bool ok = !done && (power <= 0.0f) && (alpha >= kAlphaMin);
-      const float Tn = T * (1.0f - alpha);
-      const bool stop = ok && (Tn < kTMin);
-      const bool blend = ok && !stop;
-      const float w = blend ? alpha * T : 0.0f;
-      acc0 = fmaf(q.z, w, acc0);
-      acc1 = fmaf(q.w, w, acc1);
-      acc2 = fmaf(s_b[j], w, acc2);
-      T = blend ? Tn : T;
-      contrib = blend ? (base + static_cast<uint32_t>(j) - rg.x + 1u) : contrib;
-      done = done || stop;
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int j = j0 + u;
+        const float4 p = s_p[j];
+        const float4 q = s_q[j];
+        float dx, dy, p2, eg, og;
+        eval_pair(p, q, px, py, dx, dy, p2, eg, og);
+        const float alpha = fminf(kAlphaMax, og);
+        const bool ok = !done && (p2 <= 0.0f) && (alpha >= kAlphaMin);
+        const float Tn = T * (1.0f - alpha);
+        const bool stop = ok && (Tn < kTMin);
+        const bool blend = ok && !stop;
+        const float w = blend ? alpha * T : 0.0f;
+        acc0 = fmaf(q.z, w, acc0);
+        acc1 = fmaf(q.w, w, acc1);
+        acc2 = fmaf(s_b[j], w, acc2);
+        T = blend ? Tn : T;
+        contrib = blend ? (m0 + static_cast<uint32_t>(j)) : contrib;
+        done = done || stop;
+      }
     }
   }
   if (inside) {
@@ -135,12 +150,12 @@ gs_status launch_render_fwd(const gs_projected& proj, const uint32_t* point_list
 
 // ------------------------------------------------------------------ backward
 
-// Sum over the 64 lanes of a wave with DPP; the total lands in lane 63.
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ float dpp_src(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
 }
 
+// Sum over the 64 lanes of a wave with DPP; the total lands in lane 63.
 __device__ __forceinline__ float wave_sum_to_lane63(float v) {
   v += dpp_src<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
   v += dpp_src<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
@@ -151,8 +166,35 @@ __device__ __forceinline__ float wave_sum_to_lane63(float v) {
   return v;
 }
 
-__device__ __forceinline__ float lane63(float v) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_sum_to_lane63(v)), 63));
+// Swap halves (32 lanes) / odd-even 16-lane rows between two registers and add:
+// the transpose-reduce steps that halve the number of registers per level.
+__device__ __forceinline__ float add_swap32(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float add_swap16(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Wave sums of eight values with a transpose-reduce: 18 instructions instead
+// of 8 x 6 DPP steps.  On return, lane 16 r + 8 h holds the total of value
+// kReduceSlot[2 r + h] (every lane of that 8-lane group holds it).
+constexpr int kReduceSlot[8] = {0, 4, 2, 6, 1, 5, 3, 7};
+__device__ __forceinline__ float wave_sum8(const float v[8], bool lo8) {
+  const float a01 = add_swap32(v[0], v[1]);   // lanes <32: v0 half sums, >=32: v1
+  const float a23 = add_swap32(v[2], v[3]);
+  const float a45 = add_swap32(v[4], v[5]);
+  const float a67 = add_swap32(v[6], v[7]);
+  const float b0 = add_swap16(a01, a23);      // rows: v0 v2 v1 v3 (quarter sums)
+  const float b1 = add_swap16(a45, a67);      // rows: v4 v6 v5 v7
+  const float keep = lo8 ? b0 : b1;
+  const float send = lo8 ? b1 : b0;
+  float c = keep + dpp_src<0x128, 0xF>(send); // row_ror:8 pairs lane i with i^8
+  c += dpp_src<0x141, 0xF>(c);                // row_half_mirror within 8 lanes
+  c += dpp_src<0xB1, 0xF>(c);                 // quad_perm [1,0,3,2]
+  c += dpp_src<0x4E, 0xF>(c);                 // quad_perm [2,3,0,1]
+  return c;
 }
 
 // Per (pixel, entry) derivative, walked back to front.  Starting from S =
@@ -165,7 +207,8 @@ __device__ __forceinline__ float lane63(float v) {
 // forward's checkpoint (or T_f for the last batch), so the division walks at
 // most 256 entries and its rounding cannot build up along long lists.  Skips
 // are re-derived from the same alpha evaluation as the forward; entries past
-// n_contrib are never touched.
+// n_contrib are never touched.  The nine per-pair gradients are summed over
+// the wave and added to the Gaussian's g2d entries by nine lanes at once.
 __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ranges,
                                                     const uint32_t* __restrict__ point_list,
                                                     const float4* __restrict__ rec, DevCam cam,
@@ -187,6 +230,10 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
   const float px = static_cast<float>(px_i) + 0.5f, py = static_cast<float>(py_i) + 0.5f;
   const uint2 rg = ranges[tile];
   const int lane = threadIdx.x & 63;
+  const bool lo8 = (lane & 8) == 0;
+  const int out_slot = (lane == 63) ? 8 : kReduceSlot[((lane >> 4) << 1) | ((lane >> 3) & 1)];
+  const bool writer = ((lane & 7) == 0) || lane == 63;
+  float* const g_out = g2d + static_cast<int64_t>(out_slot) * n;
 
   float G0 = 0.f, G1 = 0.f, G2 = 0.f, T = 1.0f;
   uint32_t ncon = 0;
@@ -215,11 +262,11 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
     if (threadIdx.x < cnt) {
       const uint32_t gid = point_list[rg.x + m0 + threadIdx.x];
       float4 p, q;
-      float b;
-      stage_record(rec, gid, p, q, b);
+      float bl;
+      stage_record(rec, gid, p, q, bl);
       s_p[threadIdx.x] = p;
       s_q[threadIdx.x] = q;
-      s_b[threadIdx.x] = b;
+      s_b[threadIdx.x] = bl;
       s_gid[threadIdx.x] = gid;
     }
     __syncthreads();
@@ -229,10 +276,10 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
       const float4 p = s_p[j];
       const float4 q = s_q[j];
       const float cb = s_b[j];
-      float dx, dy, power, eg, og;
-      eval_pair(p, q, px, py, dx, dy, power, eg, og);
+      float dx, dy, p2, eg, og;
+      eval_pair(p, q, px, py, dx, dy, p2, eg, og);
       const float alpha = fminf(kAlphaMax, og);
-      const bool ok = (m < ncon) && (power <= 0.0f) && (alpha >= kAlphaMin);
+      const bool ok = (m < ncon) && (p2 <= 0.0f) && (alpha >= kAlphaMin);
       if (__ballot(ok) == 0) continue;
       const float inv = 1.0f / (1.0f - alpha);
       const float Tm = ok ? T * inv : T;
@@ -243,36 +290,30 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
       S2 = fmaf(cb, w, S2);
       T = Tm;
       const bool unclamped = og < kAlphaMax;
+      // dL/dpower (natural-log power) and dL/do = e^power dL/dalpha
       const float dpow = (ok && unclamped) ? alpha * dalpha : 0.0f;
       const float dop = (ok && unclamped) ? eg * dalpha : 0.0f;
-      // power = a dx^2 + b dx dy + c dy^2 with a = -A/2, b = -B, c = -C/2, so
-      // (nkx, nky) = -K d with K the conic and d = (dx, dy).  The pair's conic
-      // gradient -1/2 dpow d d^T is carried to Sigma' = K^-1 right here,
-      // -K (.) K = 1/2 dpow (K d)(K d)^T, before any summation: converting the
-      // summed conic gradient instead cancels badly for elongated footprints.
+      // (nkx, nky) = log2(e) * (-K d) with K the conic and d = (dx, dy).  The
+      // pair's conic gradient -1/2 dpow d d^T is carried to Sigma' = K^-1
+      // right here, -K (.) K = 1/2 dpow (K d)(K d)^T, before any summation:
+      // converting the summed conic gradient cancels badly for elongated
+      // footprints.
       const float nkx = 2.0f * p.z * dx + p.w * dy;
       const float nky = p.w * dx + 2.0f * q.x * dy;
-      const float du = dpow * nkx;
-      const float dv = dpow * nky;
-      const float hdp = 0.5f * dpow;
-      const float dA = hdp * nkx * nkx;      // dL/dSigma'_xx
-      const float dB = dpow * nkx * nky;     // dL/dSigma'_xy (both off-diagonal entries)
-      const float dC = hdp * nky * nky;      // dL/dSigma'_yy
-      const float dr = G0 * w, dg = G1 * w, db = G2 * w;
-      const float s0 = lane63(du), s1 = lane63(dv), s2 = lane63(dA), s3 = lane63(dB), s4 = lane63(dC);
-      const float s5 = lane63(dop), s6 = lane63(dr), s7 = lane63(dg), s8 = lane63(db);
-      if (lane == 0) {
-        const uint32_t gid = s_gid[j];
-        unsafeAtomicAdd(&g2d[0 * static_cast<int64_t>(n) + gid], s0);
-        unsafeAtomicAdd(&g2d[1 * static_cast<int64_t>(n) + gid], s1);
-        unsafeAtomicAdd(&g2d[2 * static_cast<int64_t>(n) + gid], s2);
-        unsafeAtomicAdd(&g2d[3 * static_cast<int64_t>(n) + gid], s3);
-        unsafeAtomicAdd(&g2d[4 * static_cast<int64_t>(n) + gid], s4);
-        unsafeAtomicAdd(&g2d[5 * static_cast<int64_t>(n) + gid], s5);
-        unsafeAtomicAdd(&g2d[6 * static_cast<int64_t>(n) + gid], s6);
-        unsafeAtomicAdd(&g2d[7 * static_cast<int64_t>(n) + gid], s7);
-        unsafeAtomicAdd(&g2d[8 * static_cast<int64_t>(n) + gid], s8);
-      }
+      const float dq = dpow * kLn2;              // undoes the log2(e) scale once
+      const float hq = 0.5f * kLn2 * dq;         // ... and twice for the products
+      float v[8];
+      v[0] = dq * nkx;                           // dL/du
+      v[1] = dq * nky;                           // dL/dv
+      v[2] = hq * nkx * nkx;                     // dL/dSigma'_xx
+      v[3] = 2.0f * hq * nkx * nky;              // dL/dSigma'_xy (both entries)
+      v[4] = hq * nky * nky;                     // dL/dSigma'_yy
+      v[5] = dop;                                // dL/dopacity
+      v[6] = G0 * w;                             // dL/dr
+      v[7] = G1 * w;                             // dL/dg
+      const float red8 = wave_sum8(v, lo8);
+      const float red9 = wave_sum_to_lane63(G2 * w);  // dL/db
+      if (writer) unsafeAtomicAdd(&g_out[s_gid[j]], lane == 63 ? red9 : red8);
     }
   }
 }
