@@ -32,11 +32,22 @@ HBM_PEAK_GBS = 8000.0
 # FP32 VALU without packed math: 256 CUs x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
-# Algorithmic work per unit ("Measurement").
-PROJECT_BYTES_PER_G = {0: 44 + 12 + 48, 1: 44 + 48 + 48, 2: 44 + 108 + 48, 3: 44 + 192 + 48}
+# Algorithmic work per unit ("Measurement").  FLOPs count an FMA as
+# 2 and every other FP32 operation (including exp and reciprocal) as 1.
+#   projection: read 44 + 12 (D+1)^2 B of parameters, write the 36 B record +
+#               depth + radius + tile count per Gaussian
+#   projection backward: read parameters + 36 B of 2D gradients, write
+#               parameter gradients (44 + 12 (D+1)^2 B)
+#   forward compositing: 14 flop per examined pair (offset, quadratic form,
+#               exp, opacity, clamp, two skip tests) + 10 per blended pair
+#               (1 - alpha, T update, stop test, weight, three colour FMAs)
+#   backward compositing: 14 flop per walked pair (alpha re-evaluation) + 52
+#               per blended pair (T recovery, dL/dalpha, light behind, nine
+#               gradient terms and their nine sums over pixels)
+PROJECT_BYTES_PER_G = {d: 44 + 12 * (d + 1) ** 2 + 48 for d in range(4)}
 PROJECT_BWD_BYTES_PER_G = {d: 2 * (44 + 12 * (d + 1) ** 2) + 36 for d in range(4)}
-RENDER_BWD_FLOP_PER_PAIR = 92   # FMA = 2 flop; exp/rcp counted as 1
-RENDER_FWD_FLOP_PER_PAIR = 34
+FWD_FLOP_EXAMINED, FWD_FLOP_BLENDED = 14, 10
+BWD_FLOP_WALKED, BWD_FLOP_BLENDED = 14, 52
 
 
 def log(*a):
@@ -112,6 +123,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", type=int, default=3, choices=[1, 2, 3, 4])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--hbm-probe", action="store_true",
+                    help="also time a 2 GiB device-to-device copy (achievable HBM bandwidth, counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: only one GPU is supported in this build (got --gpus {args.gpus}); "
@@ -172,23 +185,30 @@ def main():
         ", ".join(f"{k} {v:.3f}" for k, v in stage_ms.items()))
 
     # algorithmic work of the timed steps (recounted untimed, same cameras)
-    pairs, ks = [], []
+    walked, examined, blended, ks = [], [], [], []
+    counts = torch.zeros(2, dtype=torch.int64, device=dev)
     for i in range(args.steps):
         cam = cams[(args.warmup + i) % ncam]
         rast.set_camera(cam)
         with torch.no_grad():
             st = rast.forward(params["means"], params["log_scales"], params["quats"], params["logits"],
                               params["sh"])
-        pairs.append(float(st.n_contrib.to(torch.int64).sum().item()))
+            gs.render_count(st.n, st.proj, st.point_list, st.ranges, st.k, rast.cs, counts)
+        walked.append(float(st.n_contrib.to(torch.int64).sum().item()))
+        c = counts.cpu().numpy()
+        examined.append(float(c[0]))
+        blended.append(float(c[1]))
         ks.append(st.k)
     torch.cuda.synchronize()
-    mean_pairs = float(np.mean(pairs))
+    p_walk, p_exam, p_blend = (float(np.mean(x)) for x in (walked, examined, blended))
+    fwd_flop = FWD_FLOP_EXAMINED * p_exam + FWD_FLOP_BLENDED * p_blend
+    bwd_flop = BWD_FLOP_WALKED * p_walk + BWD_FLOP_BLENDED * p_blend
     n = scene.n
     deg = scene.sh_degree
     rooflines = {
-        "render_bwd": {"bound": "alu", "achieved": RENDER_BWD_FLOP_PER_PAIR * mean_pairs / (stage_ms["render_bwd"] * 1e-3) / 1e12,
+        "render_bwd": {"bound": "alu", "achieved": bwd_flop / (stage_ms["render_bwd"] * 1e-3) / 1e12,
                        "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s"},
-        "render_fwd": {"bound": "alu", "achieved": RENDER_FWD_FLOP_PER_PAIR * mean_pairs / (stage_ms["render_fwd"] * 1e-3) / 1e12,
+        "render_fwd": {"bound": "alu", "achieved": fwd_flop / (stage_ms["render_fwd"] * 1e-3) / 1e12,
                        "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s"},
         "project": {"bound": "hbm", "achieved": PROJECT_BYTES_PER_G[deg] * n / (stage_ms["project"] * 1e-3) / 1e9,
                     "peak": HBM_PEAK_GBS, "unit": "GB/s"},
@@ -223,11 +243,28 @@ def main():
                    "gaussians": n, "width": W, "height": H, "sh_degree": deg, "colour": "sh",
                    "parallelism": "single GPU"},
         "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
-        "pairs_per_step": round(mean_pairs),
+        "pairs_per_step": {"examined_fwd": round(p_exam), "walked_bwd": round(p_walk), "blended": round(p_blend)},
         "k_per_step": round(float(np.mean(ks))),
         "roofline": roof,
         "rooflines": rooflines,
     }
+    if args.hbm_probe:
+        nbytes = 2 << 30
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        reps = 10
+        e0.record()
+        for _ in range(reps):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) / 1e3 / reps
+        result["hbm_probe"] = {"bytes_per_copy": 2 * nbytes, "GB/s": round(2 * nbytes / sec / 1e9, 1)}
+        del a, b
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle on a bounded sample) ...")
         cam0 = cams[0]

@@ -170,6 +170,14 @@ gs_status gs_render_fwd(int64_t n, const gs_projected* proj, const uint32_t* poi
                         int64_t k, const gs_camera* cam, float* image, float* final_T, uint32_t* n_contrib,
                         float* t_ckpt, gs_stream stream);
 
+/* Work counter for measurement: runs the forward's per-pixel decisions
+ * without producing an image and writes counts[0] = pairs whose alpha is
+ * evaluated before each pixel's walk ends, counts[1] = pairs blended (device
+ * uint64[2], overwritten).  Sum over pixels of n_contrib is the number of
+ * pairs the backward walks. */
+gs_status gs_render_count(int64_t n, const gs_projected* proj, const uint32_t* point_list, const uint32_t* ranges,
+                          int64_t k, const gs_camera* cam, uint64_t* counts, gs_stream stream);
+
 /* Floats of the transmittance checkpoint buffer for K entries. Host-only. */
 gs_status gs_render_ckpt_floats(int64_t k, const gs_camera* cam, size_t* floats);
 

@@ -149,6 +149,18 @@ gs_status gs_render_fwd(int64_t n, const gs_projected* proj, const uint32_t* poi
                            static_cast<hipStream_t>(stream));
 }
 
+gs_status gs_render_count(int64_t n, const gs_projected* proj, const uint32_t* point_list, const uint32_t* ranges,
+                          int64_t k, const gs_camera* cam, uint64_t* counts, gs_stream stream) {
+  set_error("");
+  gs_status st;
+  if (n < 0 || k < 0) return fail(GS_ERR_INVALID_ARG, "gs_render_count: negative n or k");
+  if ((st = validate_camera(cam)) != GS_OK) return st;
+  if ((st = validate_projected(proj, n, "gs_render_count")) != GS_OK) return st;
+  if (!ranges || !counts || (k > 0 && !point_list)) return fail(GS_ERR_INVALID_ARG, "gs_render_count: NULL array");
+  return launch_render_count(*proj, point_list, ranges, make_devcam(*cam),
+                             reinterpret_cast<unsigned long long*>(counts), static_cast<hipStream_t>(stream));
+}
+
 gs_status gs_render_ckpt_floats(int64_t k, const gs_camera* cam, size_t* floats) {
   set_error("");
   gs_status st;

@@ -112,6 +112,8 @@ gs_status run_bin_sort(int64_t n, const gs_projected& proj, const DevCam& cam, v
 gs_status launch_render_fwd(const gs_projected& proj, const uint32_t* point_list, const uint32_t* ranges,
                             const DevCam& cam, float* image, float* final_T, uint32_t* n_contrib, float* t_ckpt,
                             hipStream_t s);
+gs_status launch_render_count(const gs_projected& proj, const uint32_t* point_list, const uint32_t* ranges,
+                              const DevCam& cam, unsigned long long* counts, hipStream_t s);
 size_t render_bwd_workspace(int64_t n, int64_t k, int ntiles, int deterministic);
 gs_status launch_render_bwd(int64_t n, const gs_projected& proj, const uint32_t* point_list, const uint32_t* ranges,
                             int64_t k, const DevCam& cam, const float* final_T,

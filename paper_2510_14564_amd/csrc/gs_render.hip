@@ -63,11 +63,16 @@ __device__ __forceinline__ void eval_pair(const float4& p, const float4& q, floa
 
 // ------------------------------------------------------------------- forward
 
+// COUNT = true runs the same decisions but only counts, per pixel, the pairs
+// examined (alpha evaluated before the walk ends) and the pairs blended, and
+// adds them to counts[0], counts[1].
+template <bool COUNT>
 __global__ __launch_bounds__(256) void k_render_fwd(const uint2* __restrict__ ranges,
                                                     const uint32_t* __restrict__ point_list,
                                                     const float4* __restrict__ rec, DevCam cam,
                                                     float* __restrict__ image, float* __restrict__ final_T,
-                                                    uint32_t* __restrict__ n_contrib, float* __restrict__ t_ckpt) {
+                                                    uint32_t* __restrict__ n_contrib, float* __restrict__ t_ckpt,
+                                                    unsigned long long* __restrict__ counts) {
   __shared__ float4 s_p[kBatch];
   __shared__ float4 s_q[kBatch];
   __shared__ float s_b[kBatch];
@@ -80,13 +85,13 @@ __global__ __launch_bounds__(256) void k_render_fwd(const uint2* __restrict__ ra
   const uint2 rg = ranges[tile];
 
   float T = 1.0f, acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
-  uint32_t contrib = 0;
+  uint32_t contrib = 0, n_exam = 0, n_blend = 0;
   bool done = !inside;
   const size_t slot0 = ckpt_slot0(rg.x, tile);
 
   for (uint32_t base = rg.x, b = 0; base < rg.y; base += kBatch, ++b) {
     if (__syncthreads_count(done) == 256) break;
-    if (b > 0 && t_ckpt) t_ckpt[(slot0 + b) * kBatch + threadIdx.x] = T;
+    if (!COUNT && b > 0 && t_ckpt) t_ckpt[(slot0 + b) * kBatch + threadIdx.x] = T;
     const uint32_t idx = base + threadIdx.x;
     if (idx < rg.y) {
       float4 p, q;
@@ -123,9 +128,23 @@ __global__ __launch_bounds__(256) void k_render_fwd(const uint2* __restrict__ ra
         acc2 = fmaf(s_b[j], w, acc2);
         T = blend ? Tn : T;
         contrib = blend ? (m0 + static_cast<uint32_t>(j)) : contrib;
+        if (COUNT) {
+          n_exam += (!done && j < cnt) ? 1u : 0u;
+          n_blend += blend ? 1u : 0u;
+        }
         done = done || stop;
       }
     }
+  }
+  if (COUNT) {
+    __shared__ unsigned long long s_cnt[2];
+    if (threadIdx.x == 0) { s_cnt[0] = 0; s_cnt[1] = 0; }
+    __syncthreads();
+    atomicAdd(&s_cnt[0], static_cast<unsigned long long>(n_exam));
+    atomicAdd(&s_cnt[1], static_cast<unsigned long long>(n_blend));
+    __syncthreads();
+    if (threadIdx.x == 0) { atomicAdd(&counts[0], s_cnt[0]); atomicAdd(&counts[1], s_cnt[1]); }
+    return;
   }
   if (inside) {
     const int64_t HW = static_cast<int64_t>(cam.width) * cam.height;
@@ -142,10 +161,21 @@ gs_status launch_render_fwd(const gs_projected& proj, const uint32_t* point_list
                             const DevCam& cam, float* image, float* final_T, uint32_t* n_contrib, float* t_ckpt,
                             hipStream_t s) {
   const int ntiles = cam.tiles_x * cam.tiles_y;
-  k_render_fwd<<<ntiles, 256, 0, s>>>(reinterpret_cast<const uint2*>(ranges), point_list,
-                                      reinterpret_cast<const float4*>(proj.records), cam, image, final_T, n_contrib,
-                                      t_ckpt);
+  k_render_fwd<false><<<ntiles, 256, 0, s>>>(reinterpret_cast<const uint2*>(ranges), point_list,
+                                             reinterpret_cast<const float4*>(proj.records), cam, image, final_T,
+                                             n_contrib, t_ckpt, nullptr);
   return check_launch("k_render_fwd");
+}
+
+gs_status launch_render_count(const gs_projected& proj, const uint32_t* point_list, const uint32_t* ranges,
+                              const DevCam& cam, unsigned long long* counts, hipStream_t s) {
+  const int ntiles = cam.tiles_x * cam.tiles_y;
+  gs_status st = check_hip(hipMemsetAsync(counts, 0, 2 * sizeof(unsigned long long), s), "hipMemsetAsync(counts)");
+  if (st != GS_OK) return st;
+  k_render_fwd<true><<<ntiles, 256, 0, s>>>(reinterpret_cast<const uint2*>(ranges), point_list,
+                                            reinterpret_cast<const float4*>(proj.records), cam, nullptr, nullptr,
+                                            nullptr, nullptr, counts);
+  return check_launch("k_render_count");
 }
 
 // ------------------------------------------------------------------ backward

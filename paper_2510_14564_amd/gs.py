@@ -33,7 +33,7 @@ STATUS_NAMES = {0: "GS_OK", -1: "GS_ERR_INVALID_ARG", -2: "GS_ERR_CAPACITY", -3:
 
 # every symbol declared in include/gsplat.h
 EXPORTS = ("gs_last_error", "gs_version", "gs_project", "gs_bin_sort_workspace", "gs_bin_sort",
-           "gs_render_fwd", "gs_render_ckpt_floats", "gs_render_bwd_workspace", "gs_render_bwd", "gs_project_bwd",
+           "gs_render_fwd", "gs_render_count", "gs_render_ckpt_floats", "gs_render_bwd_workspace", "gs_render_bwd", "gs_project_bwd",
            "gs_l1_loss")
 
 
@@ -78,6 +78,7 @@ _sigs = {
     "gs_bin_sort": ([_i64, _P(Projected), _P(Camera), _vp, _sz, _vp, _i64, _vp, _P(_i64), _vp], ctypes.c_int),
     "gs_render_fwd": ([_i64, _P(Projected), _vp, _vp, _i64, _P(Camera), _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
     "gs_render_ckpt_floats": ([_i64, _P(Camera), _P(_sz)], ctypes.c_int),
+    "gs_render_count": ([_i64, _P(Projected), _vp, _vp, _i64, _P(Camera), _vp, _vp], ctypes.c_int),
     "gs_render_bwd_workspace": ([_i64, _i64, _P(Camera), _i32, _P(_sz)], ctypes.c_int),
     "gs_render_bwd": ([_i64, _P(Projected), _vp, _vp, _i64, _P(Camera), _vp, _vp, _vp, _vp, _vp, _vp, _sz, _i32,
                        _vp], ctypes.c_int),
@@ -203,6 +204,12 @@ def render_fwd(n: int, proj: ProjectedBuffers, point_list, ranges, k: int, cam: 
     _check(_lib.gs_render_fwd(n, ctypes.byref(proj.struct()), _ptr(point_list), _ptr(ranges), k, ctypes.byref(cam),
                               _ptr(image), _ptr(final_T), _ptr(n_contrib), _ptr(t_ckpt), _stream(stream)),
            "gs_render_fwd")
+
+
+def render_count(n: int, proj: ProjectedBuffers, point_list, ranges, k: int, cam: Camera, counts, stream=None):
+    """counts: device int64[2] <- (pairs examined, pairs blended) of the forward."""
+    _check(_lib.gs_render_count(n, ctypes.byref(proj.struct()), _ptr(point_list), _ptr(ranges), k, ctypes.byref(cam),
+                                _ptr(counts), _stream(stream)), "gs_render_count")
 
 
 def render_ckpt_floats(k: int, cam: Camera) -> int:
