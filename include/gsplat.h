@@ -88,12 +88,14 @@ typedef struct {
 } gs_gaussians;
 
 /* Output of gs_project, input of the later stages.
- *   records[n][12]: u, v, A, B | C, opacity, r, g | b, depth, 0, 0
+ *   records[n][12]: u, v, A, B | C, opacity, r, g | b, depth, ex, ey
  *     (u, v) = projected centre in pixels, (A, B, C) = conic = inverse of the
  *     2D covariance Sigma' = J W Sigma W^T J^T + 0.3 I (Sec. II-A), opacity,
  *     colour (r, g, b).  One interleaved 48-byte record per Gaussian so that the
  *     per-tile gathers read whole records (the interleaved colour layout of
- *     Sec. V).
+ *     Sec. V).  (ex, ey) are the half-extents of a box around (u, v) outside
+ *     which alpha < 1/255 everywhere (with a small safety margin); the
+ *     compositing kernels use it to skip whole waves of pixels.
  *   depth[n]: camera-space t_z (the sort key, Sec. II-A "sorted by depth").
  *   radius[n]: ceil(3 sqrt(lambda_max(Sigma'))) pixels, 0 when culled.
  *   tiles_touched[n]: number of 16x16 tiles met by the square of half-width

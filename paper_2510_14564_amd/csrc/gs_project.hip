@@ -176,6 +176,28 @@ __device__ __forceinline__ bool project_geometry(const float m[3], const float s
   return isfinite(g.u) && isfinite(g.v) && isfinite(g.A) && isfinite(g.B) && isfinite(g.C) && isfinite(g.o);
 }
 
+// Half-extents of the axis-aligned box around (u, v) outside which alpha is
+// below 1/255 at every point: alpha >= 1/255 needs d^T Sigma'^-1 d <= rho^2 =
+// 2 ln(255 o), an ellipse whose x and y half-extents are rho sqrt(Sigma'_xx)
+// and rho sqrt(Sigma'_yy).  The FP32 conic's quadratic form may differ from
+// the exact one by about 2 eps cond(Sigma') relative, so rho^2 gets 2 %
+// (covering cond up to 1e5) plus 2e-4 of slack and the extents 1e-3 px plus
+// 1e-6 |u| (rounding of pixel offsets): a pair whose pixel lies outside the
+// box is skipped by the per-pixel test anyway, so compositing may skip it
+// earlier without changing any result.  Footprints with cond above 1e5 get an
+// unbounded box; a Gaussian that can never reach 1/255 gets (-1, -1).
+__device__ __forceinline__ void alpha_support(const Geo& g, float& ex, float& ey) {
+  const float lo = logf(255.0f * g.o);
+  if (!(lo > 0.0f)) { ex = -1.0f; ey = -1.0f; return; }
+  const float mid = 0.5f * (g.a + g.c);
+  const float h = 0.5f * (g.a - g.c);
+  const float disc = sqrtf(h * h + g.b * g.b);
+  if (!((mid - disc) * 1e5f > mid + disc)) { ex = 3.0e38f; ey = 3.0e38f; return; }
+  const float rho2 = 2.0f * lo * 1.02f + 2e-4f;
+  ex = sqrtf(rho2 * g.a) + 1e-3f + 1e-6f * fabsf(g.u);
+  ey = sqrtf(rho2 * g.c) + 1e-3f + 1e-6f * fabsf(g.v);
+}
+
 __device__ __forceinline__ void view_dir(const float m[3], const DevCam& cam, float d[3], float& len) {
   const float dx = m[0] - cam.centre[0], dy = m[1] - cam.centre[1], dz = m[2] - cam.centre[2];
   len = sqrtf(dx * dx + dy * dy + dz * dz);
@@ -221,9 +243,11 @@ __global__ __launch_bounds__(256) void k_project(int n, const float* __restrict_
   uint32_t cnt = 0;
   float dep = 0.0f;
   if (live) {
+    float ex, ey;
+    alpha_support(g, ex, ey);
     r0 = make_float4(g.u, g.v, g.A, g.B);
     r1 = make_float4(g.C, g.o, rgb[0], rgb[1]);
-    r2 = make_float4(rgb[2], g.t[2], 0.0f, 0.0f);
+    r2 = make_float4(rgb[2], g.t[2], ex, ey);
     rad = g.radius;
     dep = g.t[2];
     int x0, x1, y0, y1;

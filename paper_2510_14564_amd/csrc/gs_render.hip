@@ -38,18 +38,8 @@ __device__ __forceinline__ size_t ckpt_slot0(uint32_t start, int tile) {
 // -log2(e) off-diagonal) so that the base-2 exponent is
 //   p2 = a dx^2 + b dx dy + c dy^2 = power * log2(e),
 // and alpha's Gaussian factor is a single v_exp_f32: p = (u, v, a, b),
-// q = (c, opacity, r, g), blue separately.  Slots past the end of a batch
-// hold a null record (opacity 0), which every pixel skips.
-__device__ __forceinline__ void stage_record(const float4* __restrict__ rec, uint32_t gid, float4& p, float4& q,
-                                             float& blue) {
-  const float4 r0 = rec[3 * gid];
-  const float4 r1 = rec[3 * gid + 1];
-  const float4 r2 = rec[3 * gid + 2];
-  p = make_float4(r0.x, r0.y, -0.5f * kLog2e * r0.z, -kLog2e * r0.w);
-  q = make_float4(-0.5f * kLog2e * r1.x, r1.y, r1.z, r1.w);
-  blue = r2.x;
-}
-
+// q = (c, opacity, r, g).  Slots past the end of a batch hold a null record
+// (opacity 0), which every pixel skips.
 // p2 (base-2 power), 2^p2 and the unclamped o 2^p2 for one (pixel, entry) pair.
 __device__ __forceinline__ void eval_pair(const float4& p, const float4& q, float px, float py, float& dx,
                                           float& dy, float& p2, float& eg, float& og) {
@@ -61,11 +51,87 @@ __device__ __forceinline__ void eval_pair(const float4& p, const float4& q, floa
   og = q.y * eg;
 }
 
+// Wave w of a tile's workgroup covers the 8x8 quadrant (w & 1, w >> 1); lane
+// l of it the pixel (l & 7, l >> 3) inside the quadrant.
+__device__ __forceinline__ void tile_pixel(int tid, int& lx, int& ly) {
+  const int w = tid >> 6, l = tid & 63;
+  lx = ((w & 1) << 3) + (l & 7);
+  ly = ((w >> 1) << 3) + (l >> 3);
+}
+
+// Quadrants of the tile whose pixel centres meet the record's alpha-support box
+// (bit w = quadrant of wave w).  Outside the box alpha < 1/255, so a wave whose
+// bit is clear would skip the entry at every pixel anyway.
+__device__ __forceinline__ uint32_t quad_mask(const float4& r0, const float4& r2, float x0, float y0) {
+  const float u = r0.x, v = r0.y, ex = r2.z, ey = r2.w;
+  if (!(ex >= 0.0f)) return 0u;
+  const bool xl = (u - ex <= x0 + 7.5f) && (u + ex >= x0 + 0.5f);
+  const bool xr = (u - ex <= x0 + 15.5f) && (u + ex >= x0 + 8.5f);
+  const bool yt = (v - ey <= y0 + 7.5f) && (v + ey >= y0 + 0.5f);
+  const bool yb = (v - ey <= y0 + 15.5f) && (v + ey >= y0 + 8.5f);
+  return (xl && yt ? 1u : 0u) | (xr && yt ? 2u : 0u) | (xl && yb ? 4u : 0u) | (xr && yb ? 8u : 0u);
+}
+
+constexpr int kNull = kBatch;           // LDS slot of a null record (opacity 0)
+constexpr int kListStride = kBatch + 4; // per-wave list of staged slots, padded to kUnroll
+
+// Shared per-batch staging: records (pre-scaled conic), colour + quadrant mask,
+// and each wave's list of the staged slots it must visit, in list order and
+// padded with the null slot to a multiple of kUnroll.
+struct Stage {
+  float4 p[kBatch + 1];
+  float4 q[kBatch + 1];
+  float2 c[kBatch + 1];                 // blue, quadrant mask bits
+  uint32_t gid[kBatch + 1];
+  alignas(16) uint32_t list[4][kListStride];
+  int len[4];
+};
+
+__device__ __forceinline__ void stage_batch(Stage& st, const float4* __restrict__ rec,
+                                            const uint32_t* __restrict__ point_list, uint32_t first, int cnt,
+                                            float x0, float y0) {
+  const int t = threadIdx.x;
+  if (t < cnt) {
+    const uint32_t gid = point_list[first + t];
+    const float4 r0 = rec[3 * gid];
+    const float4 r1 = rec[3 * gid + 1];
+    const float4 r2 = rec[3 * gid + 2];
+    st.p[t] = make_float4(r0.x, r0.y, -0.5f * kLog2e * r0.z, -kLog2e * r0.w);
+    st.q[t] = make_float4(-0.5f * kLog2e * r1.x, r1.y, r1.z, r1.w);
+    st.c[t] = make_float2(r2.x, __uint_as_float(quad_mask(r0, r2, x0, y0)));
+    st.gid[t] = gid;
+  } else {
+    st.p[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+    st.q[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+    st.c[t] = make_float2(0.f, __uint_as_float(0u));
+    st.gid[t] = 0u;
+  }
+}
+
+// Stream compaction of the staged batch for this wave (ballot + prefix count).
+// all = true keeps every staged entry (no culling).
+__device__ __forceinline__ void build_list(Stage& st, int cnt, bool all) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+  int L = 0;
+#pragma unroll
+  for (int r = 0; r < kBatch / 64; ++r) {
+    const int j = r * 64 + lane;
+    const bool in = (j < cnt) && (all || ((__float_as_uint(st.c[j].y) >> wave) & 1u));
+    const uint64_t bal = __ballot(in);
+    if (in) st.list[wave][L + __popcll(bal & below)] = static_cast<uint32_t>(j);
+    L += __popcll(bal);
+  }
+  const int Lp = (L + kUnroll - 1) & ~(kUnroll - 1);
+  if (lane < Lp - L) st.list[wave][L + lane] = kNull;
+  if (lane == 0) st.len[wave] = Lp;
+}
+
 // ------------------------------------------------------------------- forward
 
-// COUNT = true runs the same decisions but only counts, per pixel, the pairs
-// examined (alpha evaluated before the walk ends) and the pairs blended, and
-// adds them to counts[0], counts[1].
+// COUNT = true runs the same decisions on every entry (no culling) but only
+// counts, per pixel, the pairs examined (alpha evaluated before the walk ends)
+// and the pairs blended, and adds them to counts[0], counts[1].
 template <bool COUNT>
 __global__ __launch_bounds__(256) void k_render_fwd(const uint2* __restrict__ ranges,
                                                     const uint32_t* __restrict__ point_list,
@@ -73,16 +139,22 @@ __global__ __launch_bounds__(256) void k_render_fwd(const uint2* __restrict__ ra
                                                     float* __restrict__ image, float* __restrict__ final_T,
                                                     uint32_t* __restrict__ n_contrib, float* __restrict__ t_ckpt,
                                                     unsigned long long* __restrict__ counts) {
-  __shared__ float4 s_p[kBatch];
-  __shared__ float4 s_q[kBatch];
-  __shared__ float s_b[kBatch];
+  __shared__ Stage st;
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
-  const int px_i = tx * kTile + (threadIdx.x & 15);
-  const int py_i = ty * kTile + (threadIdx.x >> 4);
+  int lx, ly;
+  tile_pixel(threadIdx.x, lx, ly);
+  const int px_i = tx * kTile + lx, py_i = ty * kTile + ly;
   const bool inside = px_i < cam.width && py_i < cam.height;
   const float px = static_cast<float>(px_i) + 0.5f, py = static_cast<float>(py_i) + 0.5f;
+  const float x0 = static_cast<float>(tx * kTile), y0 = static_cast<float>(ty * kTile);
   const uint2 rg = ranges[tile];
+  const int wave = threadIdx.x >> 6;
+  if (threadIdx.x == 0) {
+    st.p[kNull] = make_float4(0.f, 0.f, 0.f, 0.f);
+    st.q[kNull] = make_float4(0.f, 0.f, 0.f, 0.f);
+    st.c[kNull] = make_float2(0.f, 0.f);
+  }
 
   float T = 1.0f, acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
   uint32_t contrib = 0, n_exam = 0, n_blend = 0;
@@ -92,29 +164,23 @@ __global__ __launch_bounds__(256) void k_render_fwd(const uint2* __restrict__ ra
   for (uint32_t base = rg.x, b = 0; base < rg.y; base += kBatch, ++b) {
     if (__syncthreads_count(done) == 256) break;
     if (!COUNT && b > 0 && t_ckpt) t_ckpt[(slot0 + b) * kBatch + threadIdx.x] = T;
-    const uint32_t idx = base + threadIdx.x;
-    if (idx < rg.y) {
-      float4 p, q;
-      float bl;
-      stage_record(rec, point_list[idx], p, q, bl);
-      s_p[threadIdx.x] = p;
-      s_q[threadIdx.x] = q;
-      s_b[threadIdx.x] = bl;
-    } else {
-      s_p[threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
-      s_q[threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
-      s_b[threadIdx.x] = 0.f;
-    }
-    __syncthreads();
     const int cnt = static_cast<int>(min(static_cast<uint32_t>(kBatch), rg.y - base));
+    stage_batch(st, rec, point_list, base, cnt, x0, y0);
+    __syncthreads();
+    build_list(st, cnt, COUNT);
+    __syncthreads();
     const uint32_t m0 = base - rg.x + 1u;
-    for (int j0 = 0; j0 < cnt; j0 += kUnroll) {
+    const int L = st.len[wave];
+    for (int i0 = 0; i0 < L; i0 += kUnroll) {
       if (__ballot(!done) == 0) break;  // whole wave finished: leave the batch
+      const uint4 jj = *reinterpret_cast<const uint4*>(&st.list[wave][i0]);
+      const uint32_t js[kUnroll] = {jj.x, jj.y, jj.z, jj.w};
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
-        const int j = j0 + u;
-        const float4 p = s_p[j];
-        const float4 q = s_q[j];
+        const uint32_t j = js[u];
+        const float4 p = st.p[j];
+        const float4 q = st.q[j];
+        const float cb = st.c[j].x;
         float dx, dy, p2, eg, og;
         eval_pair(p, q, px, py, dx, dy, p2, eg, og);
         const float alpha = fminf(kAlphaMax, og);
@@ -125,11 +191,11 @@ __global__ __launch_bounds__(256) void k_render_fwd(const uint2* __restrict__ ra
         const float w = blend ? alpha * T : 0.0f;
         acc0 = fmaf(q.z, w, acc0);
         acc1 = fmaf(q.w, w, acc1);
-        acc2 = fmaf(s_b[j], w, acc2);
+        acc2 = fmaf(cb, w, acc2);
         T = blend ? Tn : T;
-        contrib = blend ? (m0 + static_cast<uint32_t>(j)) : contrib;
+        contrib = blend ? (m0 + j) : contrib;
         if (COUNT) {
-          n_exam += (!done && j < cnt) ? 1u : 0u;
+          n_exam += (!done && j != kNull) ? 1u : 0u;
           n_blend += blend ? 1u : 0u;
         }
         done = done || stop;
@@ -138,10 +204,13 @@ __global__ __launch_bounds__(256) void k_render_fwd(const uint2* __restrict__ ra
   }
   if (COUNT) {
     __shared__ unsigned long long s_cnt[2];
+    __syncthreads();
     if (threadIdx.x == 0) { s_cnt[0] = 0; s_cnt[1] = 0; }
     __syncthreads();
-    atomicAdd(&s_cnt[0], static_cast<unsigned long long>(n_exam));
-    atomicAdd(&s_cnt[1], static_cast<unsigned long long>(n_blend));
+    if (inside) {
+      atomicAdd(&s_cnt[0], static_cast<unsigned long long>(n_exam));
+      atomicAdd(&s_cnt[1], static_cast<unsigned long long>(n_blend));
+    }
     __syncthreads();
     if (threadIdx.x == 0) { atomicAdd(&counts[0], s_cnt[0]); atomicAdd(&counts[1], s_cnt[1]); }
     return;
@@ -227,18 +296,20 @@ __device__ __forceinline__ float wave_sum8(const float v[8], bool lo8) {
   return c;
 }
 
-// Per (pixel, entry) derivative, walked back to front.  Starting from S =
-// T_f bg, each blended entry m (going backwards) recovers T_m = T_{m+1} /
-// (1 - alpha_m) and uses the light behind it, S_m = sum_{j>m} c_j alpha_j T_j +
-// T_f bg, accumulated directly:
+// Per (pixel, entry) derivative, walked back to front.  Starting from the light
+// S = T_f bg behind the last entry, each blended entry m (going backwards)
+// recovers T_m = T_{m+1} / (1 - alpha_m) and uses the light behind it,
+// S_m = sum_{j>m} c_j alpha_j T_j + T_f bg:
 //   dL/dalpha_m = sum_k G_k (c_k T_m - S_mk / (1 - alpha_m)),  S += c_m alpha_m T_m.
-// Accumulating S (instead of subtracting from the pixel value) keeps its
-// rounding error relative to S itself.  T restarts at every batch end from the
-// forward's checkpoint (or T_f for the last batch), so the division walks at
-// most 256 entries and its rounding cannot build up along long lists.  Skips
-// are re-derived from the same alpha evaluation as the forward; entries past
-// n_contrib are never touched.  The nine per-pair gradients are summed over
-// the wave and added to the Gaussian's g2d entries by nine lanes at once.
+// Only G.S enters, so the walk carries the scalar GS = G.S.  Accumulating it
+// (instead of subtracting from the pixel value) keeps its rounding error
+// relative to itself.  T restarts at every batch end from the forward's
+// checkpoint (or T_f for the last batch), so the division walks at most 256
+// entries and its rounding cannot build up along long lists.  Skips are
+// re-derived from the same alpha evaluation as the forward; entries past
+// n_contrib are never touched; a wave visits only the entries whose
+// alpha-support box meets its quadrant.  The nine per-pair gradients are summed
+// over the wave and added to the Gaussian's g2d entries by nine lanes at once.
 __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ranges,
                                                     const uint32_t* __restrict__ point_list,
                                                     const float4* __restrict__ rec, DevCam cam,
@@ -247,18 +318,18 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
                                                     const float* __restrict__ t_ckpt,
                                                     const float* __restrict__ dL_dimage, int n,
                                                     float* __restrict__ g2d) {
-  __shared__ float4 s_p[kBatch];
-  __shared__ float4 s_q[kBatch];
-  __shared__ float s_b[kBatch];
-  __shared__ uint32_t s_gid[kBatch];
+  __shared__ Stage st;
   __shared__ uint32_t s_max;
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
-  const int px_i = tx * kTile + (threadIdx.x & 15);
-  const int py_i = ty * kTile + (threadIdx.x >> 4);
+  int lx, ly;
+  tile_pixel(threadIdx.x, lx, ly);
+  const int px_i = tx * kTile + lx, py_i = ty * kTile + ly;
   const bool inside = px_i < cam.width && py_i < cam.height;
   const float px = static_cast<float>(px_i) + 0.5f, py = static_cast<float>(py_i) + 0.5f;
+  const float x0 = static_cast<float>(tx * kTile), y0 = static_cast<float>(ty * kTile);
   const uint2 rg = ranges[tile];
+  const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const bool lo8 = (lane & 8) == 0;
   const int out_slot = (lane == 63) ? 8 : kReduceSlot[((lane >> 4) << 1) | ((lane >> 3) & 1)];
@@ -276,7 +347,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
   }
   const float T_final = T;
   const size_t slot0 = ckpt_slot0(rg.x, tile);
-  float S0 = T * cam.bg[0], S1 = T * cam.bg[1], S2 = T * cam.bg[2];
+  float GS = T * (G0 * cam.bg[0] + G1 * cam.bg[1] + G2 * cam.bg[2]);
   if (threadIdx.x == 0) s_max = 0;
   __syncthreads();
   if (ncon) atomicMax(&s_max, ncon);
@@ -289,23 +360,18 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
     const int cnt = static_cast<int>(min(static_cast<uint32_t>(kBatch), len - m0));
     T = (bi + 1 < nbatch) ? t_ckpt[(slot0 + bi + 1) * kBatch + threadIdx.x] : T_final;
     __syncthreads();
-    if (threadIdx.x < cnt) {
-      const uint32_t gid = point_list[rg.x + m0 + threadIdx.x];
-      float4 p, q;
-      float bl;
-      stage_record(rec, gid, p, q, bl);
-      s_p[threadIdx.x] = p;
-      s_q[threadIdx.x] = q;
-      s_b[threadIdx.x] = bl;
-      s_gid[threadIdx.x] = gid;
-    }
+    stage_batch(st, rec, point_list, rg.x + m0, cnt, x0, y0);
     __syncthreads();
-    for (int j = cnt - 1; j >= 0; --j) {
-      const uint32_t m = m0 + static_cast<uint32_t>(j);
+    build_list(st, cnt, false);
+    __syncthreads();
+    for (int i = st.len[wave] - 1; i >= 0; --i) {
+      const uint32_t j = st.list[wave][i];
+      if (j == kNull) continue;
+      const uint32_t m = m0 + j;
       if (__ballot(m < ncon) == 0) continue;  // no lane of this wave reaches entry m yet
-      const float4 p = s_p[j];
-      const float4 q = s_q[j];
-      const float cb = s_b[j];
+      const float4 p = st.p[j];
+      const float4 q = st.q[j];
+      const float cb = st.c[j].x;
       float dx, dy, p2, eg, og;
       eval_pair(p, q, px, py, dx, dy, p2, eg, og);
       const float alpha = fminf(kAlphaMax, og);
@@ -313,11 +379,10 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
       if (__ballot(ok) == 0) continue;
       const float inv = 1.0f / (1.0f - alpha);
       const float Tm = ok ? T * inv : T;
-      const float dalpha = G0 * (q.z * Tm - S0 * inv) + G1 * (q.w * Tm - S1 * inv) + G2 * (cb * Tm - S2 * inv);
+      const float Gc = G0 * q.z + G1 * q.w + G2 * cb;
+      const float dalpha = Tm * Gc - inv * GS;
       const float w = ok ? alpha * Tm : 0.0f;
-      S0 = fmaf(q.z, w, S0);
-      S1 = fmaf(q.w, w, S1);
-      S2 = fmaf(cb, w, S2);
+      GS = fmaf(w, Gc, GS);
       T = Tm;
       const bool unclamped = og < kAlphaMax;
       // dL/dpower (natural-log power) and dL/do = e^power dL/dalpha
@@ -343,7 +408,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
       v[7] = G1 * w;                             // dL/dg
       const float red8 = wave_sum8(v, lo8);
       const float red9 = wave_sum_to_lane63(G2 * w);  // dL/db
-      if (writer) unsafeAtomicAdd(&g_out[s_gid[j]], lane == 63 ? red9 : red8);
+      if (writer) unsafeAtomicAdd(&g_out[st.gid[j]], lane == 63 ? red9 : red8);
     }
   }
 }
