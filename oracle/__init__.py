@@ -204,3 +204,55 @@ def backward(scene, cam, fwd, dL_dimage):
     grads = project_bwd(scene, cam, g2d)
     grads["g2d"] = g2d
     return grads
+
+
+# ------------------------------------------------------------ learned colour
+
+MLP_PARAMS = 6467
+MLP_SLICES = {"W1": (0, (64, 32)), "b1": (2048, (64,)), "W2": (2112, (64, 64)), "b2": (6208, (64,)),
+              "W3": (6272, (3, 64)), "b3": (6464, (3,))}
+
+
+def mlp_inputs(z, dirs):
+    """x[n*per][32] = [z_i; Y_0..15(d_ik)] for latents z[n][16] and unit directions dirs[n][per][3]."""
+    z = _d(z)
+    dirs = _d(dirs)
+    n, per = dirs.shape[0], dirs.shape[1]
+    x = np.zeros((n * per, 32))
+    _load().or_mlp_inputs(ctypes.c_int64(n), ctypes.c_int(per), _p(z), _p(dirs), _p(x))
+    return x
+
+
+def mlp_fwd(x, params, with_hidden=False):
+    """Decoder colours c[S][3] (and hidden activations) for inputs x[S][32]."""
+    x = _d(x)
+    P = _d(params)
+    assert P.shape == (MLP_PARAMS,)
+    S = x.shape[0]
+    out = np.zeros((S, 3))
+    h1 = np.zeros((S, 64)) if with_hidden else None
+    h2 = np.zeros((S, 64)) if with_hidden else None
+    _load().or_mlp_fwd(ctypes.c_int64(S), _p(x), _p(P), _p(out), _p(h1), _p(h2))
+    return (out, h1, h2) if with_hidden else out
+
+
+def mlp_bwd(x, params, dL_dc, with_dx=True):
+    """(dL/dparams[6467], dL/dx[S][32]) of sum(dL_dc * c(x))."""
+    x = _d(x)
+    P = _d(params)
+    G = _d(dL_dc)
+    S = x.shape[0]
+    dP = np.zeros(MLP_PARAMS)
+    dx = np.zeros((S, 32)) if with_dx else None
+    _load().or_mlp_bwd(ctypes.c_int64(S), _p(x), _p(P), _p(G), _p(dP), _p(dx))
+    return dP, dx
+
+
+def sh_colour(sh, deg, dirs):
+    """SH colour max(0, sum Y f + 1/2) of every Gaussian at its directions dirs[n][per][3]."""
+    sh = _d(sh)
+    dirs = _d(dirs)
+    n, per = dirs.shape[0], dirs.shape[1]
+    out = np.zeros((n, per, 3))
+    _load().or_sh_colour(ctypes.c_int64(n), ctypes.c_int(deg), _p(sh), _p(dirs), ctypes.c_int(per), _p(out))
+    return out

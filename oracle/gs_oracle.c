@@ -727,3 +727,145 @@ int or_num_threads(void) {
 #endif
     return t;
 }
+
+/* ======================================================= learned colour ===
+ * Learned colour decoder (not in the paper; the build's optional replacement
+ * of the SH colour read).  Per sample: x = [z (16 latent values); Y_0..15(d)]
+ * (the 16 real SH values of the view direction), then
+ *   h1 = ReLU(W1 x + b1) (64),  h2 = ReLU(W2 h1 + b2) (64),
+ *   c  = sigmoid(W3 h2 + b3) (3).
+ * Parameter vector (6467 values): W1[64][32], b1[64], W2[64][64], b2[64],
+ * W3[3][64], b3[3], row-major.  Plain matrix-vector products, one sample at a
+ * time; the caller widens the decoder's BF16 values exactly to FP64.
+ */
+#define OR_MLP_IN 32
+#define OR_MLP_H 64
+#define OR_MLP_OUT 3
+#define OR_W1 0
+#define OR_B1 (OR_W1 + OR_MLP_H * OR_MLP_IN)
+#define OR_W2 (OR_B1 + OR_MLP_H)
+#define OR_B2 (OR_W2 + OR_MLP_H * OR_MLP_H)
+#define OR_W3 (OR_B2 + OR_MLP_H)
+#define OR_B3 (OR_W3 + OR_MLP_OUT * OR_MLP_H)
+#define OR_MLP_NPARAM (OR_B3 + OR_MLP_OUT)
+
+static void mlp_forward_one(const double* x, const double* P, double* h1, double* h2, double* c) {
+    for (int o = 0; o < OR_MLP_H; ++o) {
+        double s = P[OR_B1 + o];
+        for (int i = 0; i < OR_MLP_IN; ++i) s += P[OR_W1 + o * OR_MLP_IN + i] * x[i];
+        h1[o] = s > 0.0 ? s : 0.0;
+    }
+    for (int o = 0; o < OR_MLP_H; ++o) {
+        double s = P[OR_B2 + o];
+        for (int i = 0; i < OR_MLP_H; ++i) s += P[OR_W2 + o * OR_MLP_H + i] * h1[i];
+        h2[o] = s > 0.0 ? s : 0.0;
+    }
+    for (int o = 0; o < OR_MLP_OUT; ++o) {
+        double s = P[OR_B3 + o];
+        for (int i = 0; i < OR_MLP_H; ++i) s += P[OR_W3 + o * OR_MLP_H + i] * h2[i];
+        c[o] = 1.0 / (1.0 + exp(-s));
+    }
+}
+
+int or_mlp_num_params(void) { return OR_MLP_NPARAM; }
+
+/* out[S][3]; h1, h2 ([S][64]) optional. */
+int or_mlp_fwd(int64_t S, const double* x, const double* P, double* out, double* h1o, double* h2o) {
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < S; ++s) {
+        double h1[OR_MLP_H], h2[OR_MLP_H];
+        mlp_forward_one(x + OR_MLP_IN * s, P, h1, h2, out + OR_MLP_OUT * s);
+        if (h1o) memcpy(h1o + OR_MLP_H * s, h1, sizeof h1);
+        if (h2o) memcpy(h2o + OR_MLP_H * s, h2, sizeof h2);
+    }
+    return 0;
+}
+
+/* Gradient of sum_s dL_dc[s] . c(x_s) with respect to the parameters
+ * (dP[6467], overwritten, summed over samples) and, if dx != NULL, the inputs
+ * (dx[S][32]).  Textbook backpropagation: sigmoid' = c (1 - c), ReLU' = [h > 0]. */
+int or_mlp_bwd(int64_t S, const double* x, const double* P, const double* dL_dc, double* dP, double* dx) {
+    memset(dP, 0, sizeof(double) * OR_MLP_NPARAM);
+#pragma omp parallel
+    {
+        double* acc = (double*)calloc(OR_MLP_NPARAM, sizeof(double));
+#pragma omp for schedule(static)
+        for (int64_t s = 0; s < S; ++s) {
+            const double* xs = x + OR_MLP_IN * s;
+            double h1[OR_MLP_H], h2[OR_MLP_H], c[OR_MLP_OUT];
+            mlp_forward_one(xs, P, h1, h2, c);
+            double g3[OR_MLP_OUT], g2[OR_MLP_H], g1[OR_MLP_H];
+            for (int o = 0; o < OR_MLP_OUT; ++o) g3[o] = dL_dc[OR_MLP_OUT * s + o] * c[o] * (1.0 - c[o]);
+            for (int o = 0; o < OR_MLP_OUT; ++o) {
+                acc[OR_B3 + o] += g3[o];
+                for (int i = 0; i < OR_MLP_H; ++i) acc[OR_W3 + o * OR_MLP_H + i] += g3[o] * h2[i];
+            }
+            for (int i = 0; i < OR_MLP_H; ++i) {
+                double t = 0.0;
+                for (int o = 0; o < OR_MLP_OUT; ++o) t += P[OR_W3 + o * OR_MLP_H + i] * g3[o];
+                g2[i] = h2[i] > 0.0 ? t : 0.0;
+            }
+            for (int o = 0; o < OR_MLP_H; ++o) {
+                acc[OR_B2 + o] += g2[o];
+                for (int i = 0; i < OR_MLP_H; ++i) acc[OR_W2 + o * OR_MLP_H + i] += g2[o] * h1[i];
+            }
+            for (int i = 0; i < OR_MLP_H; ++i) {
+                double t = 0.0;
+                for (int o = 0; o < OR_MLP_H; ++o) t += P[OR_W2 + o * OR_MLP_H + i] * g2[o];
+                g1[i] = h1[i] > 0.0 ? t : 0.0;
+            }
+            for (int o = 0; o < OR_MLP_H; ++o) {
+                acc[OR_B1 + o] += g1[o];
+                for (int i = 0; i < OR_MLP_IN; ++i) acc[OR_W1 + o * OR_MLP_IN + i] += g1[o] * xs[i];
+            }
+            if (dx) {
+                for (int i = 0; i < OR_MLP_IN; ++i) {
+                    double t = 0.0;
+                    for (int o = 0; o < OR_MLP_H; ++o) t += P[OR_W1 + o * OR_MLP_IN + i] * g1[o];
+                    dx[OR_MLP_IN * s + i] = t;
+                }
+            }
+        }
+#pragma omp critical
+        for (int k = 0; k < OR_MLP_NPARAM; ++k) dP[k] += acc[k];
+        free(acc);
+    }
+    return 0;
+}
+
+/* SH colour max(0, sum_j Y_j(d) f_j + 1/2) of Gaussian i at `per` given unit
+ * directions dirs[n][per][3] -> out[n][per][3] (the distillation target before
+ * clamping to [0, 1]). */
+int or_sh_colour(int64_t n, int deg, const double* sh, const double* dirs, int per, double* out) {
+    if (deg < 0 || deg > OR_MAXL) return -1;
+    sh_init();
+    int nc = (deg + 1) * (deg + 1);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double Y[16];
+        for (int k = 0; k < per; ++k) {
+            sh_eval(deg, dirs + 3 * (per * i + k), Y, NULL);
+            for (int ch = 0; ch < 3; ++ch) {
+                double s = 0.0;
+                for (int j = 0; j < nc; ++j) s += Y[j] * sh[(3 * j + ch) * n + i];
+                s += 0.5;
+                out[3 * (per * i + k) + ch] = s > 0.0 ? s : 0.0;
+            }
+        }
+    }
+    return 0;
+}
+
+/* Decoder inputs x[n*per][32] = [z_i (16); Y_0..15(d_ik)] for Gaussian i and
+ * its k-th unit direction. */
+int or_mlp_inputs(int64_t n, int per, const double* z, const double* dirs, double* x) {
+    sh_init();
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < per; ++k) {
+            double* xs = x + OR_MLP_IN * (per * i + k);
+            for (int j = 0; j < 16; ++j) xs[j] = z[16 * i + j];
+            sh_eval(3, dirs + 3 * (per * i + k), xs + 16, NULL);
+        }
+    return 0;
+}

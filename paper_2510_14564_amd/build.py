@@ -42,7 +42,7 @@ def _compile(src: str) -> str:
     cmd = [HIPCC, "-c", os.path.join(CSRC, src), "-o", obj] + COMMON + PER_FILE.get(src, [])
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
-        raise RuntimeError(f"hipcc failed for {src}:\n{res.stderr}")
+        raise RuntimeError(f"hipcc failed for {src}:\n" + "\n".join(res.stderr.splitlines()[:40]))
     if res.stderr.strip():
         # the host pass warns about the packed-fp32 feature; keep other warnings visible
         lines = [l for l in res.stderr.splitlines() if "packed-fp32-ops" not in l and l.strip()]

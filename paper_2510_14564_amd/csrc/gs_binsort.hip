@@ -17,8 +17,8 @@
 namespace gs {
 
 constexpr int kRsThreads = 256;
-constexpr int kRsItems = 16;
-constexpr int kRsChunk = kRsThreads * kRsItems;  // keys per block
+constexpr int kRsItemsN = 4;    // depth sort of N keys: 1024 keys per block (more blocks)
+constexpr int kRsItemsK = 16;   // tile sort of K entries: 4096 keys per block
 constexpr int kScanItems = 16;
 constexpr int kScanChunk = 256 * kScanItems;
 
@@ -132,19 +132,24 @@ static gs_status device_exclusive_scan(const uint32_t* in, uint32_t* out, int64_
 
 // ---------------------------------------------------------------- radix sort
 // One stable LSD pass on (key, value) pairs over `nbits` bits at `shift`.
-// Block b owns keys [b*4096, (b+1)*4096), taken in 16 rounds of 256; within a
-// round, wave w's keys precede wave w+1's and lanes are in order, so ranks
-// computed round by round preserve the input order of equal digits.
+// Block b owns keys [b*CHUNK, (b+1)*CHUNK); wave w of the block owns the
+// contiguous quarter [w*CHUNK/4, (w+1)*CHUNK/4) and walks it 64 keys at a
+// time.  A key's rank among equal digits is (keys of earlier waves) + (earlier
+// rounds of its wave) + (earlier lanes of its round), so the pass is stable.
+// Within a wave the running digit counters need no barrier (a wave's LDS
+// operations complete in order); the cross-wave offsets are combined once.
 
+template <int ITEMS>
 __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint32_t* __restrict__ keys, int64_t count,
                                                         int shift, int nbits, uint32_t* __restrict__ hist,
                                                         int nblocks) {
+  constexpr int CHUNK = kRsThreads * ITEMS;
   __shared__ uint32_t cnt[256];
   cnt[threadIdx.x] = 0;
   __syncthreads();
   const uint32_t mask = (1u << nbits) - 1u;
-  const int64_t base = static_cast<int64_t>(blockIdx.x) * kRsChunk;
-  for (int j = 0; j < kRsItems; ++j) {
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * CHUNK;
+  for (int j = 0; j < ITEMS; ++j) {
     const int64_t idx = base + j * kRsThreads + threadIdx.x;
     const bool valid = idx < count;
     const uint32_t d = valid ? ((keys[idx] >> shift) & mask) : 0u;
@@ -155,70 +160,72 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint32_t* __restri
   if (threadIdx.x <= mask) hist[static_cast<int64_t>(threadIdx.x) * nblocks + blockIdx.x] = cnt[threadIdx.x];
 }
 
+template <int ITEMS>
 __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* __restrict__ keys_in,
                                                            const uint32_t* __restrict__ vals_in,
                                                            uint32_t* __restrict__ keys_out,
                                                            uint32_t* __restrict__ vals_out, int64_t count,
                                                            int shift, int nbits,
                                                            const uint32_t* __restrict__ hist_scan, int nblocks) {
-  __shared__ uint32_t sk[kRsChunk];
-  __shared__ uint32_t sv[kRsChunk];
-  __shared__ uint32_t running[256];
-  __shared__ uint32_t wcnt[4][256];
-  __shared__ uint32_t dstart[256];
-  __shared__ uint32_t gbase[256];
+  constexpr int CHUNK = kRsThreads * ITEMS;
+  constexpr int PER_WAVE = CHUNK / 4;
+  __shared__ uint32_t sk[CHUNK];
+  __shared__ uint32_t sv[CHUNK];
+  __shared__ uint32_t wrun[4][256];   // per-wave running digit counts
+  __shared__ uint32_t dstart[256];    // block-local start of each digit
+  __shared__ uint32_t gbase[256];     // global start of each digit for this block
+  __shared__ uint32_t scan_tmp[256];
   const int tid = threadIdx.x;
-  const int wave = tid >> 6;
+  const int wave = tid >> 6, lane = tid & 63;
   const uint32_t mask = (1u << nbits) - 1u;
-  running[tid] = 0;
-  wcnt[0][tid] = 0; wcnt[1][tid] = 0; wcnt[2][tid] = 0; wcnt[3][tid] = 0;
+  wrun[0][tid] = 0; wrun[1][tid] = 0; wrun[2][tid] = 0; wrun[3][tid] = 0;
   gbase[tid] = (static_cast<uint32_t>(tid) <= mask) ? hist_scan[static_cast<int64_t>(tid) * nblocks + blockIdx.x] : 0u;
   __syncthreads();
-  const int64_t base = static_cast<int64_t>(blockIdx.x) * kRsChunk;
-  uint32_t k[kRsItems], v[kRsItems], lr[kRsItems];
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * CHUNK + static_cast<int64_t>(wave) * PER_WAVE;
+  const uint64_t below = lanemask_lt();
+  uint32_t k[ITEMS], v[ITEMS], lr[ITEMS];
 #pragma unroll
-  for (int j = 0; j < kRsItems; ++j) {
-    const int64_t idx = base + j * kRsThreads + tid;
+  for (int j = 0; j < ITEMS; ++j) {
+    const int64_t idx = base + j * 64 + lane;
     const bool valid = idx < count;
     k[j] = valid ? keys_in[idx] : 0u;
     v[j] = valid ? vals_in[idx] : 0u;
   }
 #pragma unroll
-  for (int j = 0; j < kRsItems; ++j) {
-    const int64_t idx = base + j * kRsThreads + tid;
+  for (int j = 0; j < ITEMS; ++j) {
+    const int64_t idx = base + j * 64 + lane;
     const bool valid = idx < count;
     const uint32_t d = (k[j] >> shift) & mask;
     const uint64_t peers = match_digit(d, nbits, valid);
-    const uint64_t below = peers & lanemask_lt();
-    if (valid && below == 0) wcnt[wave][d] = static_cast<uint32_t>(__popcll(peers));
-    __syncthreads();
-    if (valid) {
-      uint32_t off = running[d];
-      for (int w = 0; w < wave; ++w) off += wcnt[w][d];
-      lr[j] = off + static_cast<uint32_t>(__popcll(below));
-    }
-    __syncthreads();
-    running[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
-    wcnt[0][tid] = 0; wcnt[1][tid] = 0; wcnt[2][tid] = 0; wcnt[3][tid] = 0;
-    __syncthreads();
+    const uint32_t before = valid ? wrun[wave][d] : 0u;
+    lr[j] = before + static_cast<uint32_t>(__popcll(peers & below));
+    if (valid && (peers & below) == 0) wrun[wave][d] = before + static_cast<uint32_t>(__popcll(peers));
   }
-  // block-local digit starts
+  __syncthreads();
+  // per digit: offsets of waves 1..3 and the block total, then block-local starts
+  const uint32_t c0 = wrun[0][tid], c1 = wrun[1][tid], c2 = wrun[2][tid], c3 = wrun[3][tid];
   uint32_t tot;
-  const uint32_t ds = block_exclusive_scan(running[tid], &wcnt[0][0], tot);
+  const uint32_t ds = block_exclusive_scan(c0 + c1 + c2 + c3, scan_tmp, tot);
+  __syncthreads();
+  wrun[0][tid] = ds;
+  wrun[1][tid] = ds + c0;
+  wrun[2][tid] = ds + c0 + c1;
+  wrun[3][tid] = ds + c0 + c1 + c2;
   dstart[tid] = ds;
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < kRsItems; ++j) {
-    const int64_t idx = base + j * kRsThreads + tid;
+  for (int j = 0; j < ITEMS; ++j) {
+    const int64_t idx = base + j * 64 + lane;
     if (idx < count) {
       const uint32_t d = (k[j] >> shift) & mask;
-      const uint32_t pos = dstart[d] + lr[j];
+      const uint32_t pos = wrun[wave][d] + lr[j];
       sk[pos] = k[j];
       sv[pos] = v[j];
     }
   }
   __syncthreads();
-  const int64_t nvalid = min(static_cast<int64_t>(kRsChunk), count - base);
+  const int64_t bbase = static_cast<int64_t>(blockIdx.x) * CHUNK;
+  const int64_t nvalid = min(static_cast<int64_t>(CHUNK), count - bbase);
   for (int p = tid; p < nvalid; p += kRsThreads) {
     const uint32_t key = sk[p];
     const uint32_t d = (key >> shift) & mask;
@@ -228,21 +235,58 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* __res
   }
 }
 
+// Exclusive scan of up to kSmallScan values by one 1024-thread block.
+constexpr int kSmallScan = 1 << 17;
+__global__ __launch_bounds__(1024) void k_scan_small(const uint32_t* __restrict__ in, int n,
+                                                     uint32_t* __restrict__ out) {
+  __shared__ uint32_t part[1024];
+  const int per = (n + 1023) / 1024;
+  const int b = threadIdx.x * per;
+  uint32_t s = 0;
+  for (int i = 0; i < per; ++i) s += (b + i < n) ? in[b + i] : 0u;
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const uint32_t t = (threadIdx.x >= static_cast<unsigned>(off)) ? part[threadIdx.x - off] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += t;
+    __syncthreads();
+  }
+  uint32_t run = part[threadIdx.x] - s;
+  for (int i = 0; i < per; ++i) {
+    if (b + i < n) {
+      const uint32_t x = in[b + i];
+      out[b + i] = run;
+      run += x;
+    }
+  }
+}
+
+static gs_status scan_hist(uint32_t* hist, int64_t nh, ScanWs sws, hipStream_t s) {
+  if (nh <= kSmallScan) {
+    k_scan_small<<<1, 1024, 0, s>>>(hist, static_cast<int>(nh), hist);
+    return check_launch("k_scan_small");
+  }
+  return device_exclusive_scan(hist, hist, nh, sws, s);
+}
+
 // Sorts `count` pairs over key bits [0, total_bits) in passes of <= 8 bits.
 // Input in (ka, va); the sorted result ends in (ka, va) if the pass count is
 // even, else in (kb, vb).  Returns the number of passes.
+template <int ITEMS>
 static gs_status radix_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int64_t count,
                                   int total_bits, uint32_t* hist, ScanWs sws, hipStream_t s, int* passes_out) {
+  constexpr int CHUNK = kRsThreads * ITEMS;
   int passes = 0;
   if (count > 0) {
-    const int nblocks = static_cast<int>(ceil_div(count, kRsChunk));
+    const int nblocks = static_cast<int>(ceil_div(count, CHUNK));
     for (int shift = 0; shift < total_bits; shift += 8) {
       const int nbits = min(8, total_bits - shift);
       const int64_t nh = static_cast<int64_t>(1 << nbits) * nblocks;
-      k_rs_hist<<<nblocks, kRsThreads, 0, s>>>(ka, count, shift, nbits, hist, nblocks);
-      gs_status st = device_exclusive_scan(hist, hist, nh, sws, s);
+      k_rs_hist<ITEMS><<<nblocks, kRsThreads, 0, s>>>(ka, count, shift, nbits, hist, nblocks);
+      gs_status st = scan_hist(hist, nh, sws, s);
       if (st != GS_OK) return st;
-      k_rs_scatter<<<nblocks, kRsThreads, 0, s>>>(ka, va, kb, vb, count, shift, nbits, hist, nblocks);
+      k_rs_scatter<ITEMS><<<nblocks, kRsThreads, 0, s>>>(ka, va, kb, vb, count, shift, nbits, hist, nblocks);
       st = check_launch("k_rs_scatter");
       if (st != GS_OK) return st;
       uint32_t* t = ka; ka = kb; kb = t;
@@ -366,8 +410,9 @@ static BinWs carve_bin(void* ws, int64_t n, int64_t cap, size_t* used) {
   b.dk1 = c.take<uint32_t>(N); b.dv1 = c.take<uint32_t>(N);
   b.cnt = c.take<uint32_t>(N); b.offs = c.take<uint32_t>(N);
   b.ek0 = c.take<uint32_t>(C); b.ek1 = c.take<uint32_t>(C); b.ev1 = c.take<uint32_t>(C);
+  const size_t hist_words = 256 * static_cast<size_t>(std::max(ceil_div(std::max<int64_t>(n, 1), kRsThreads * kRsItemsN),
+                                                               ceil_div(std::max<int64_t>(cap, 1), kRsThreads * kRsItemsK)));
   const int64_t maxn = std::max<int64_t>(std::max<int64_t>(n, cap), 1);
-  const size_t hist_words = 256 * static_cast<size_t>(ceil_div(maxn, kRsChunk));
   b.hist = c.take<uint32_t>(hist_words);
   b.scan.sums = c.take<uint32_t>(scan_ws_words(std::max<int64_t>(static_cast<int64_t>(hist_words), maxn)));
   b.scan.total = c.take<unsigned long long>(1);
@@ -395,7 +440,8 @@ gs_status run_bin_sort(int64_t n64, const gs_projected& proj, const DevCam& cam,
     const unsigned g = static_cast<unsigned>(ceil_div(n, 256));
     k_depth_keys<<<g, 256, 0, s>>>(n, proj.depth, b.dk0, b.dv0);
     int passes = 0;
-    if ((st = radix_sort_pairs(b.dk0, b.dv0, b.dk1, b.dv1, n, 32, b.hist, b.scan, s, &passes)) != GS_OK) return st;
+    if ((st = radix_sort_pairs<kRsItemsN>(b.dk0, b.dv0, b.dk1, b.dv1, n, 32, b.hist, b.scan, s, &passes)) != GS_OK)
+      return st;
     const uint32_t* order = (passes % 2 == 0) ? b.dv0 : b.dv1;
     k_gather_counts<<<g, 256, 0, s>>>(n, order, proj.tiles_touched, b.cnt);
     if ((st = device_exclusive_scan(b.cnt, b.offs, n, b.scan, s)) != GS_OK) return st;
@@ -420,7 +466,7 @@ gs_status run_bin_sort(int64_t n64, const gs_projected& proj, const DevCam& cam,
           va);
       if ((st = check_launch("k_emit")) != GS_OK) return st;
       int p2 = 0;
-      if ((st = radix_sort_pairs(ka, va, kb, vb, K, tbits, b.hist, b.scan, s, &p2)) != GS_OK) return st;
+      if ((st = radix_sort_pairs<kRsItemsK>(ka, va, kb, vb, K, tbits, b.hist, b.scan, s, &p2)) != GS_OK) return st;
       const uint32_t* sorted_tiles = (p2 % 2 == 0) ? ka : kb;
       k_ranges<<<static_cast<unsigned>(ceil_div(ntiles, 256)), 256, 0, s>>>(
           ntiles, sorted_tiles, static_cast<uint32_t>(K), reinterpret_cast<uint2*>(ranges));

@@ -73,6 +73,12 @@ __device__ __forceinline__ uint32_t quad_mask(const float4& r0, const float4& r2
 }
 
 constexpr int kNull = kBatch;           // LDS slot of a null record (opacity 0)
+
+// A value every lane of the wave holds, moved to a scalar register so that
+// branches on it are scalar.
+__device__ __forceinline__ uint32_t uniform(uint32_t x) {
+  return static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(x)));
+}
 constexpr int kListStride = kBatch + 4; // per-wave list of staged slots, padded to kUnroll
 
 // Shared per-batch staging: records (pre-scaled conic), colour + quadrant mask,
@@ -174,7 +180,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(const uint2* __restrict__ ra
     for (int i0 = 0; i0 < L; i0 += kUnroll) {
       if (__ballot(!done) == 0) break;  // whole wave finished: leave the batch
       const uint4 jj = *reinterpret_cast<const uint4*>(&st.list[wave][i0]);
-      const uint32_t js[kUnroll] = {jj.x, jj.y, jj.z, jj.w};
+      const uint32_t js[kUnroll] = {uniform(jj.x), uniform(jj.y), uniform(jj.z), uniform(jj.w)};
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
         const uint32_t j = js[u];
@@ -365,7 +371,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
     build_list(st, cnt, false);
     __syncthreads();
     for (int i = st.len[wave] - 1; i >= 0; --i) {
-      const uint32_t j = st.list[wave][i];
+      const uint32_t j = uniform(st.list[wave][i]);
       if (j == kNull) continue;
       const uint32_t m = m0 + j;
       if (__ballot(m < ncon) == 0) continue;  // no lane of this wave reaches entry m yet
@@ -377,7 +383,9 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
       const float alpha = fminf(kAlphaMax, og);
       const bool ok = (m < ncon) && (p2 <= 0.0f) && (alpha >= kAlphaMin);
       if (__ballot(ok) == 0) continue;
-      const float inv = 1.0f / (1.0f - alpha);
+      // hardware reciprocal (1 ulp): T is re-anchored every 256 entries, so its
+      // rounding stays far below the tolerance of the recovered transmittance
+      const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
       const float Tm = ok ? T * inv : T;
       const float Gc = G0 * q.z + G1 * q.w + G2 * cb;
       const float dalpha = Tm * Gc - inv * GS;
@@ -393,16 +401,16 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
       // right here, -K (.) K = 1/2 dpow (K d)(K d)^T, before any summation:
       // converting the summed conic gradient cancels badly for elongated
       // footprints.
-      const float nkx = 2.0f * p.z * dx + p.w * dy;
-      const float nky = p.w * dx + 2.0f * q.x * dy;
+      const float nkx = fmaf(p.z + p.z, dx, p.w * dy);
+      const float nky = fmaf(q.x + q.x, dy, p.w * dx);
       const float dq = dpow * kLn2;              // undoes the log2(e) scale once
-      const float hq = 0.5f * kLn2 * dq;         // ... and twice for the products
+      const float hx = (0.5f * kLn2) * dq * nkx; // ... and twice for the products
       float v[8];
       v[0] = dq * nkx;                           // dL/du
       v[1] = dq * nky;                           // dL/dv
-      v[2] = hq * nkx * nkx;                     // dL/dSigma'_xx
-      v[3] = 2.0f * hq * nkx * nky;              // dL/dSigma'_xy (both entries)
-      v[4] = hq * nky * nky;                     // dL/dSigma'_yy
+      v[2] = hx * nkx;                           // dL/dSigma'_xx
+      v[3] = (hx + hx) * nky;                    // dL/dSigma'_xy (both entries)
+      v[4] = (0.5f * kLn2) * dq * nky * nky;     // dL/dSigma'_yy
       v[5] = dop;                                // dL/dopacity
       v[6] = G0 * w;                             // dL/dr
       v[7] = G1 * w;                             // dL/dg
