@@ -80,6 +80,9 @@ class StageTimer:
     def ms(self):
         return {k: [a.elapsed_time(b) for a, b in v] for k, v in self.events.items()}
 
+    def reset(self):
+        self.events = {}
+
 
 def cpu_baseline(scene, cam, target, tile_stride=8):
     """The FP64 oracle, as it stands, on a bounded sample of one step:
@@ -123,6 +126,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", type=int, default=3, choices=[1, 2, 3, 4])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mlp", action="store_true", help="skip the learned-colour timing")
     ap.add_argument("--hbm-probe", action="store_true",
                     help="also time a 2 GiB device-to-device copy (achievable HBM bandwidth, counter calibration)")
     args = ap.parse_args()
@@ -162,27 +166,56 @@ def main():
         img.backward(dimg)
         return loss
 
-    log(f"[bench] warmup {args.warmup} steps")
-    for i in range(args.warmup):
-        step(i)
-    torch.cuda.synchronize()
-    timer.enabled = True
-    log(f"[bench] timing {args.steps} steps")
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0.record()
-    wall0 = time.perf_counter()
-    for i in range(args.steps):
-        step(args.warmup + i)
-    t1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    timer.enabled = False
-    ms_step = t0.elapsed_time(t1) / args.steps
-    stage_ms = {k: float(np.mean(v)) for k, v in timer.ms().items()}
-    log(f"[bench] {ms_step:.3f} ms/step (wall {1e3 * wall / args.steps:.3f}); stages " +
-        ", ".join(f"{k} {v:.3f}" for k, v in stage_ms.items()))
+    def run_timed(step_fn, label):
+        log(f"[bench] {label}: warmup {args.warmup} steps")
+        for i in range(args.warmup):
+            step_fn(i)
+        torch.cuda.synchronize()
+        timer.reset()
+        timer.enabled = True
+        log(f"[bench] {label}: timing {args.steps} steps")
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0.record()
+        wall0 = time.perf_counter()
+        for i in range(args.steps):
+            step_fn(args.warmup + i)
+        t1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - wall0
+        timer.enabled = False
+        ms = t0.elapsed_time(t1) / args.steps
+        st_ms = {k: float(np.mean(v)) for k, v in timer.ms().items()}
+        log(f"[bench] {label}: {ms:.3f} ms/step (wall {1e3 * wall / args.steps:.3f}); stages " +
+            ", ".join(f"{k} {v:.3f}" for k, v in st_ms.items()))
+        return ms, st_ms
+
+    ms_step, stage_ms = run_timed(step, "SH colour")
+
+    # learned colour on the same scene, cameras and targets: random-init
+    # decoder (the step's cost does not depend on the weight values)
+    mlp_ms, mlp_stage_ms = None, None
+    if not args.no_mlp:
+        from paper_2510_14564_amd.decoder import Decoder
+        from paper_2510_14564_amd.raster import rasterize_learned
+        dec = Decoder(scene.n, device=dev, seed=cfg)
+        dec.latents.requires_grad_(True)
+        dec.params.requires_grad_(True)
+
+        def step_mlp(i):
+            cam = cams[i % ncam]
+            rast.set_camera(cam)
+            for p in list(params.values()) + [dec.latents, dec.params]:
+                p.grad = None
+            img = rasterize_learned(params["means"], params["log_scales"], params["quats"], params["logits"], dec,
+                                    rast)
+            with timer("l1_loss"):
+                loss, dimg = l1_loss(img, targets[i % ncam], partials)
+            img.backward(dimg)
+            return loss
+
+        mlp_ms, mlp_stage_ms = run_timed(step_mlp, "learned colour")
 
     # algorithmic work of the timed steps (recounted untimed, same cameras)
     walked, examined, blended, ks = [], [], [], []
@@ -248,6 +281,10 @@ def main():
         "roofline": roof,
         "rooflines": rooflines,
     }
+    if mlp_ms is not None:
+        result["learned_colour"] = {"ms_per_step": round(mlp_ms, 4),
+                                    "stages_ms": {k: round(v, 4) for k, v in mlp_stage_ms.items()},
+                                    "speedup_vs_sh": round(ms_step / mlp_ms, 4)}
     if args.hbm_probe:
         nbytes = 2 << 30
         a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)

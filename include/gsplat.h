@@ -71,9 +71,8 @@ typedef struct {
  *   sh[(D+1)^2][3][n] real SH coefficients, coefficient j / channel c at
  *   sh[(3j + c) n + i], D = sh_degree in 0..3 (colour_mode 0).
  * colour_mode 1 (learned colour decoder) replaces sh by latents (bf16 bit
- * patterns, [n][16]) and mlp (bf16 bit patterns of the decoder parameters,
- * GS_MLP_PARAMS values in the order W1[64][32], b1[64], W2[64][64], b2[64],
- * W3[3][64], b3[3]); sh must then be NULL and sh_degree is ignored. */
+ * patterns, [n][16], 16-byte aligned) and mlp (the decoder's packed operand
+ * image written by gs_mlp_pack); sh_degree is ignored. */
 typedef struct {
   int64_t n;
   int32_t sh_degree;
@@ -206,12 +205,71 @@ gs_status gs_render_bwd(int64_t n, const gs_projected* proj, const uint32_t* poi
                         int32_t deterministic, gs_stream stream);
 
 /* Backward of the projection: chain rule from g2d[9][n] to the raw parameters
- * (means, log_scales, quats, logits, sh) through the steps of gs_project.
- * The forward quantities are recomputed from the parameters.  Culled Gaussians
- * get zero gradients.  colour_mode 1 also needs the decoder: it fills
- * grad->latents and grad->mlp and the direction's share of grad->means. */
-gs_status gs_project_bwd(const gs_gaussians* g, const gs_camera* cam, const float* g2d, gs_gaussians_grad* grad,
-                         gs_stream stream);
+ * (means, log_scales, quats, logits, sh) through the steps of gs_project
+ * (Sec. II-A, the EWA projection and the SH colour).  The forward quantities
+ * are recomputed from the parameters.  Culled Gaussians get zero gradients.
+ * Every gradient array is overwritten.
+ * colour_mode 1 (learned colour) instead fills grad->latents [n][16] FP32,
+ * grad->mlp [GS_MLP_PARAMS] FP32 (summed over Gaussians in a fixed order) and
+ * adds the view direction's share to grad->means; grad->sh may be NULL.  It
+ * reads proj->radius (live = radius > 0, as in gs_project) and needs ws of
+ * gs_project_bwd_workspace bytes; colour_mode 0 ignores proj and ws (may be
+ * NULL / 0). */
+gs_status gs_project_bwd_workspace(const gs_gaussians* g, size_t* bytes);
+gs_status gs_project_bwd(const gs_gaussians* g, const gs_camera* cam, const gs_projected* proj, const float* g2d,
+                         gs_gaussians_grad* grad, void* ws, size_t ws_bytes, gs_stream stream);
+
+/* ---------------------------------------------------------- learned colour
+ * Optional decoder that replaces the SH colour read (not part of the paper):
+ * per sample, x = [z (16 BF16 latent values); Y_0..15(d)] with Y the real SH
+ * basis of degree 3 at the unit view direction d, then
+ *   h1 = ReLU(W1 x + b1) (64), h2 = ReLU(W2 h1 + b2) (64), c = sigmoid(W3 h2 + b3).
+ * Weights are BF16 (GS_MLP_PARAMS values, row-major, in the order W1[64][32],
+ * b1[64], W2[64][64], b2[64], W3[3][64], b3[3]); products run on the BF16
+ * matrix cores with FP32 accumulation; the SH encoding and hidden activations
+ * are rounded to BF16 before each product. */
+#define GS_MLP_PACKED_BYTES 31244
+
+/* Lay the BF16 parameters out as the matrix-core operand image used by every
+ * decoder kernel (GS_MLP_PACKED_BYTES bytes of device memory, 16-byte
+ * aligned).  Call again whenever the parameters change. */
+gs_status gs_mlp_pack(const uint16_t* params_bf16, void* packed, gs_stream stream);
+
+/* Decoder colours rgb[S][3] of S samples: sample s uses latent s / per
+ * (latents bf16 [S/per][16]) and the unit direction dirs[s][3]. */
+gs_status gs_mlp_fwd(int64_t S, int32_t per, const uint16_t* latents, const float* dirs, const void* packed,
+                     float* rgb, gs_stream stream);
+
+/* Workspace bytes of gs_mlp_bwd for S samples at `per` samples per latent. */
+gs_status gs_mlp_bwd_workspace(int64_t S, int32_t per, size_t* bytes);
+
+/* Backward of gs_mlp_fwd over the same samples (S a multiple of per, per a
+ * power of two up to 4096).  dL/drgb comes from dL_drgb[S][3], or, when
+ * dL_drgb is NULL, from the distillation loss
+ *   L = scale * sum_s |rgb_s - target_s|^2           (target[S][3])
+ * whose value goes to *loss (device scalar, may be NULL).  Outputs (FP32,
+ * overwritten): dlatents[S/per][16] and dparams[GS_MLP_PARAMS] in the
+ * parameter order of gs_mlp_pack.  Weight and latent gradients are summed in
+ * a fixed order: bit-reproducible for a given S.  The forward is recomputed
+ * (the same BF16 roundings as gs_mlp_fwd); products run on the BF16 matrix
+ * cores with FP32 accumulation. */
+gs_status gs_mlp_bwd(int64_t S, int32_t per, const uint16_t* latents, const float* dirs, const void* packed,
+                     const float* dL_drgb, const float* target, float scale, float* dlatents, float* dparams,
+                     float* loss, void* ws, size_t ws_bytes, gs_stream stream);
+
+/* SH colour of Gaussian s / per at the unit direction dirs[s][3]: the colour
+ * rule of gs_project (Sec. I, colour from SH coefficients; real basis, +0.5,
+ * clamped at 0), clamped to at most 1 as well if clamp01 != 0.  sh as in
+ * gs_gaussians ((deg+1)^2 x 3 x n).  The distillation target of the decoder. */
+gs_status gs_sh_colour(int64_t S, int32_t per, int64_t n, int32_t sh_degree, const float* sh, const float* dirs,
+                       int32_t clamp01, float* rgb, gs_stream stream);
+
+/* One Adam step (bias-corrected, step counted from 1) on n FP32 values:
+ *   m = b1 m + (1-b1) g,  v = b2 v + (1-b2) g^2,
+ *   p -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps),
+ * and, if param_bf16 != NULL, its BF16 copy (round to nearest even). */
+gs_status gs_adam_step(int64_t n, float* param, const float* grad, float* m, float* v, uint16_t* param_bf16,
+                       float lr, float beta1, float beta2, float eps, int32_t step, gs_stream stream);
 
 /* L1 photometric loss over `count` floats: *loss = mean |img - target| (device
  * scalar) and, if grad != NULL, grad = sign(img - target) / count.  partials

@@ -186,3 +186,29 @@ def render(scene, cam, requires_grad=False):
     key = pr["depth"].detach().numpy().astype(np.float32).astype(np.float64)
     img = composite(pr, cam, depth_key=key)
     return img, params, pr
+
+
+MLP_LAYOUT = (("W1", (64, 32)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)), ("W3", (3, 64)), ("b3", (3,)))
+
+
+def mlp_torch(x: torch.Tensor, P: torch.Tensor) -> torch.Tensor:
+    """Decoder colours sigmoid(W3 ReLU(W2 ReLU(W1 x + b1) + b2) + b3) for x[S][32],
+    parameters P[6467] in the order W1, b1, W2, b2, W3, b3 (row-major)."""
+    sl, off = {}, 0
+    for name, shape in MLP_LAYOUT:
+        size = int(np.prod(shape))
+        sl[name] = P[off:off + size].reshape(shape)
+        off += size
+    h1 = torch.relu(x @ sl["W1"].T + sl["b1"])
+    h2 = torch.relu(h1 @ sl["W2"].T + sl["b2"])
+    return torch.sigmoid(h2 @ sl["W3"].T + sl["b3"])
+
+
+def learned_colour(means: torch.Tensor, centre, z: torch.Tensor, P: torch.Tensor) -> torch.Tensor:
+    """Per-Gaussian decoder colour c[n][3] at the unit camera-to-Gaussian
+    direction: x = [z; Y_0..15(d)], d = (mean - centre) / |mean - centre|.
+    means[3][n], z[n][16].  Differentiable in means, z and P."""
+    v = means.T - torch.as_tensor(centre, dtype=means.dtype)
+    d = v / torch.linalg.norm(v, dim=1, keepdim=True)
+    x = torch.cat([z, sh_table(3, d)], dim=1)
+    return mlp_torch(x, P)

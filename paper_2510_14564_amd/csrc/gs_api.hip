@@ -2,6 +2,8 @@
 // camera set-up and dispatch to the kernel launchers.
 #include <math.h>
 
+#include <cmath>
+
 #include <string>
 
 #include "gs_internal.h"
@@ -74,7 +76,10 @@ static gs_status validate_gaussians(const gs_gaussians* g, const char* fn) {
     if (!g->means || !g->log_scales || !g->quats || !g->logits)
       return fail(GS_ERR_INVALID_ARG, f + ": NULL parameter array");
     if (g->colour_mode == 0 && !g->sh) return fail(GS_ERR_INVALID_ARG, f + ": sh is NULL");
-    if (g->colour_mode == 1) return fail(GS_ERR_UNSUPPORTED, f + ": learned colour is not available in this call");
+    if (g->colour_mode == 1 && (!g->latents || !g->mlp))
+      return fail(GS_ERR_INVALID_ARG, f + ": colour_mode 1 needs latents and the packed decoder");
+    if (g->colour_mode == 1 && reinterpret_cast<uintptr_t>(g->latents) % 16 != 0)
+      return fail(GS_ERR_INVALID_ARG, f + ": latents must be 16-byte aligned");
   }
   return GS_OK;
 }
@@ -200,16 +205,99 @@ gs_status gs_render_bwd(int64_t n, const gs_projected* proj, const uint32_t* poi
                            ws_bytes, deterministic, static_cast<hipStream_t>(stream));
 }
 
-gs_status gs_project_bwd(const gs_gaussians* g, const gs_camera* cam, const float* g2d, gs_gaussians_grad* grad,
-                         gs_stream stream) {
+gs_status gs_project_bwd_workspace(const gs_gaussians* g, size_t* bytes) {
+  set_error("");
+  if (!g || !bytes) return fail(GS_ERR_INVALID_ARG, "gs_project_bwd_workspace: NULL pointer");
+  if (g->n < 0 || g->n > (int64_t(1) << 30)) return fail(GS_ERR_INVALID_ARG, "gs_project_bwd_workspace: bad n");
+  *bytes = g->colour_mode == 1 ? mlp_bwd_workspace(g->n, 1) : 0;
+  return GS_OK;
+}
+
+gs_status gs_project_bwd(const gs_gaussians* g, const gs_camera* cam, const gs_projected* proj, const float* g2d,
+                         gs_gaussians_grad* grad, void* ws, size_t ws_bytes, gs_stream stream) {
   set_error("");
   gs_status st;
   if ((st = validate_gaussians(g, "gs_project_bwd")) != GS_OK) return st;
   if ((st = validate_camera(cam)) != GS_OK) return st;
   if (!grad) return fail(GS_ERR_INVALID_ARG, "gs_project_bwd: grad is NULL");
-  if (g->n > 0 && (!g2d || !grad->means || !grad->log_scales || !grad->quats || !grad->logits || !grad->sh))
+  const bool mlp = g->colour_mode == 1;
+  if (g->n > 0 && (!g2d || !grad->means || !grad->log_scales || !grad->quats || !grad->logits ||
+                   (!mlp && !grad->sh) || (mlp && (!grad->latents || !grad->mlp))))
     return fail(GS_ERR_INVALID_ARG, "gs_project_bwd: NULL gradient array");
-  return launch_project_bwd(*g, make_devcam(*cam), g2d, *grad, static_cast<hipStream_t>(stream));
+  if (mlp && g->n > 0) {
+    if (!proj || !proj->radius) return fail(GS_ERR_INVALID_ARG, "gs_project_bwd: colour_mode 1 needs proj->radius");
+    if (!ws || ws_bytes < mlp_bwd_workspace(g->n, 1))
+      return fail(GS_ERR_INVALID_ARG, "gs_project_bwd: workspace too small");
+  }
+  if (g->n == 0) return GS_OK;
+  return launch_project_bwd(*g, make_devcam(*cam), mlp ? proj->radius : nullptr, g2d, *grad, ws,
+                            static_cast<hipStream_t>(stream));
+}
+
+gs_status gs_mlp_pack(const uint16_t* params, void* packed, gs_stream stream) {
+  set_error("");
+  if (!params || !packed) return fail(GS_ERR_INVALID_ARG, "gs_mlp_pack: NULL pointer");
+  if (reinterpret_cast<uintptr_t>(packed) % 16 != 0) return fail(GS_ERR_INVALID_ARG, "gs_mlp_pack: packed not aligned");
+  return launch_mlp_pack(params, packed, static_cast<hipStream_t>(stream));
+}
+
+gs_status gs_mlp_fwd(int64_t S, int32_t per, const uint16_t* latents, const float* dirs, const void* packed,
+                     float* rgb, gs_stream stream) {
+  set_error("");
+  if (S < 0 || S > (int64_t(1) << 31) - 64 || per <= 0) return fail(GS_ERR_INVALID_ARG, "gs_mlp_fwd: bad S or per");
+  if (S > 0 && (!latents || !dirs || !packed || !rgb)) return fail(GS_ERR_INVALID_ARG, "gs_mlp_fwd: NULL pointer");
+  if (reinterpret_cast<uintptr_t>(latents) % 16 != 0 || reinterpret_cast<uintptr_t>(packed) % 16 != 0)
+    return fail(GS_ERR_INVALID_ARG, "gs_mlp_fwd: latents and packed must be 16-byte aligned");
+  return launch_mlp_fwd(S, per, latents, dirs, packed, rgb, static_cast<hipStream_t>(stream));
+}
+
+static bool pow2_per(int32_t per) { return per > 0 && per <= 4096 && (per & (per - 1)) == 0; }
+
+gs_status gs_mlp_bwd_workspace(int64_t S, int32_t per, size_t* bytes) {
+  set_error("");
+  if (!bytes || S < 0 || S > (int64_t(1) << 31) - 64 || !pow2_per(per))
+    return fail(GS_ERR_INVALID_ARG, "gs_mlp_bwd_workspace: bad arguments");
+  *bytes = mlp_bwd_workspace(S, per);
+  return GS_OK;
+}
+
+gs_status gs_mlp_bwd(int64_t S, int32_t per, const uint16_t* latents, const float* dirs, const void* packed,
+                     const float* dL_drgb, const float* target, float scale, float* dlatents, float* dparams,
+                     float* loss, void* ws, size_t ws_bytes, gs_stream stream) {
+  set_error("");
+  if (S < 0 || S > (int64_t(1) << 31) - 64 || !pow2_per(per) || S % per != 0)
+    return fail(GS_ERR_INVALID_ARG, "gs_mlp_bwd: S must be a multiple of per, per a power of two <= 4096");
+  if (!packed || !dparams || (S > 0 && (!latents || !dirs || !dlatents || (!dL_drgb && !target))))
+    return fail(GS_ERR_INVALID_ARG, "gs_mlp_bwd: NULL pointer");
+  if (reinterpret_cast<uintptr_t>(latents) % 16 != 0 || reinterpret_cast<uintptr_t>(packed) % 16 != 0)
+    return fail(GS_ERR_INVALID_ARG, "gs_mlp_bwd: latents and packed must be 16-byte aligned");
+  if (!std::isfinite(scale)) return fail(GS_ERR_INVALID_ARG, "gs_mlp_bwd: scale not finite");
+  if (!ws || ws_bytes < mlp_bwd_workspace(S, per)) return fail(GS_ERR_INVALID_ARG, "gs_mlp_bwd: workspace too small");
+  return launch_mlp_bwd(S, per, latents, dirs, packed, dL_drgb, dL_drgb ? nullptr : target, scale, dlatents, dparams,
+                        loss, ws, static_cast<hipStream_t>(stream));
+}
+
+gs_status gs_sh_colour(int64_t S, int32_t per, int64_t n, int32_t sh_degree, const float* sh, const float* dirs,
+                       int32_t clamp01, float* rgb, gs_stream stream) {
+  set_error("");
+  if (S < 0 || S > (int64_t(1) << 31) - 256 || per <= 0 || n < 0 || sh_degree < 0 || sh_degree > 3 ||
+      (S + per - 1) / per > n)
+    return fail(GS_ERR_INVALID_ARG, "gs_sh_colour: bad sizes");
+  if (S > 0 && (!sh || !dirs || !rgb)) return fail(GS_ERR_INVALID_ARG, "gs_sh_colour: NULL pointer");
+  return launch_sh_colour(S, per, n, sh_degree, sh, dirs, clamp01, rgb, static_cast<hipStream_t>(stream));
+}
+
+gs_status gs_adam_step(int64_t n, float* param, const float* grad, float* m, float* v, uint16_t* param_bf16,
+                       float lr, float beta1, float beta2, float eps, int32_t step, gs_stream stream) {
+  set_error("");
+  if (n < 0 || step < 1 || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) ||
+      !std::isfinite(lr) || !(eps > 0.0f))
+    return fail(GS_ERR_INVALID_ARG, "gs_adam_step: bad arguments");
+  if (n > 0 && (!param || !grad || !m || !v)) return fail(GS_ERR_INVALID_ARG, "gs_adam_step: NULL pointer");
+  const double bc1 = 1.0 - std::pow(static_cast<double>(beta1), step);
+  const double bc2 = 1.0 - std::pow(static_cast<double>(beta2), step);
+  return launch_adam(n, param, grad, m, v, param_bf16, lr, beta1, beta2, eps, static_cast<float>(bc1),
+                     static_cast<float>(bc2), static_cast<hipStream_t>(stream));
 }
 
 gs_status gs_l1_loss(const float* img, const float* target, int64_t count, float* loss, float* grad,

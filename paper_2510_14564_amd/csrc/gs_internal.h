@@ -104,8 +104,8 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
 // Launchers implemented in the kernel translation units.
 namespace gs {
 gs_status launch_project(const gs_gaussians& g, const DevCam& cam, gs_projected& out, hipStream_t s);
-gs_status launch_project_bwd(const gs_gaussians& g, const DevCam& cam, const float* g2d, gs_gaussians_grad& grad,
-                             hipStream_t s);
+gs_status launch_project_bwd(const gs_gaussians& g, const DevCam& cam, const int* radius, const float* g2d,
+                             gs_gaussians_grad& grad, void* ws, hipStream_t s);
 size_t binsort_workspace(int64_t n, int64_t capacity, int ntiles);
 gs_status run_bin_sort(int64_t n, const gs_projected& proj, const DevCam& cam, void* ws, size_t ws_bytes,
                        uint32_t* point_list, int64_t capacity, uint32_t* ranges, int64_t* k_out, hipStream_t s);
@@ -119,6 +119,23 @@ gs_status launch_render_bwd(int64_t n, const gs_projected& proj, const uint32_t*
                             int64_t k, const DevCam& cam, const float* final_T,
                             const uint32_t* n_contrib, const float* t_ckpt, const float* dL_dimage, float* g2d, void* ws,
                             size_t ws_bytes, int deterministic, hipStream_t s);
+gs_status launch_mlp_pack(const uint16_t* params, void* packed, hipStream_t s);
+gs_status launch_mlp_fwd(int64_t S, int per, const uint16_t* latents, const float* dirs, const void* packed,
+                         float* rgb, hipStream_t s);
+gs_status launch_mlp_render(int64_t n, const uint16_t* latents, const float* means, const int* radius,
+                            const DevCam& cam, const void* packed, float* records, hipStream_t s);
+size_t mlp_packed_bytes();
+size_t mlp_bwd_workspace(int64_t S, int per);
+gs_status launch_mlp_bwd(int64_t S, int per, const uint16_t* latents, const float* dirs, const void* packed,
+                         const float* dL_drgb, const float* target, float scale, float* dlat, float* dparams,
+                         float* loss, void* ws, hipStream_t s);
+gs_status launch_mlp_render_bwd(int64_t n, const uint16_t* latents, const float* means, const int* radius,
+                                const DevCam& cam, const void* packed, const float* g2d, float* dlat,
+                                float* dmeans, float* dparams, void* ws, hipStream_t s);
+gs_status launch_sh_colour(int64_t S, int per, int64_t n, int deg, const float* sh, const float* dirs, int clamp01,
+                           float* out, hipStream_t s);
+gs_status launch_adam(int64_t n, float* p, const float* g, float* m, float* v, uint16_t* pb, float lr, float b1,
+                      float b2, float eps, float bc1, float bc2, hipStream_t s);
 gs_status launch_l1(const float* img, const float* target, int64_t count, float* loss, float* grad, float* partials,
                     hipStream_t s);
 }  // namespace gs

@@ -6,83 +6,9 @@
 // floats per field (256-byte coalesced loads).  The kernel is HBM-bound: it
 // reads 44 + 12 (D+1)^2 bytes and writes 60 bytes per Gaussian.
 #include "gs_internal.h"
+#include "gs_sh.h"
 
 namespace gs {
-
-// Real SH basis, Condon-Shortley phase kept, ordered by l then m = -l..l.
-// Constants are the closed-form normalisations:
-//   l=0: 1/(2 sqrt(pi));  l=1: sqrt(3/(4 pi));
-//   l=2: (1/2) sqrt(15/pi), (1/4) sqrt(5/pi), (1/4) sqrt(15/pi);
-//   l=3: (1/4) sqrt(35/(2 pi)), (1/2) sqrt(105/pi), (1/4) sqrt(21/(2 pi)),
-//        (1/4) sqrt(7/pi), (1/4) sqrt(105/pi).
-constexpr float kSH0 = 0.28209479177387814f;
-constexpr float kSH1 = 0.48860251190291992f;
-constexpr float kSH2a = 1.0925484305920792f;
-constexpr float kSH2c = 0.31539156525252005f;
-constexpr float kSH2e = 0.54627421529603959f;
-constexpr float kSH3a = 0.59004358992664352f;
-constexpr float kSH3b = 2.8906114426405538f;
-constexpr float kSH3c = 0.45704579946446572f;
-constexpr float kSH3d = 0.37317633259011540f;
-constexpr float kSH3f = 1.4453057213202769f;
-
-__device__ __forceinline__ void sh_basis(int deg, float x, float y, float z, float* Y) {
-  Y[0] = kSH0;
-  if (deg < 1) return;
-  Y[1] = -kSH1 * y;
-  Y[2] = kSH1 * z;
-  Y[3] = -kSH1 * x;
-  if (deg < 2) return;
-  const float xx = x * x, yy = y * y, zz = z * z;
-  Y[4] = kSH2a * x * y;
-  Y[5] = -kSH2a * y * z;
-  Y[6] = kSH2c * (2.0f * zz - xx - yy);
-  Y[7] = -kSH2a * x * z;
-  Y[8] = kSH2e * (xx - yy);
-  if (deg < 3) return;
-  Y[9] = -kSH3a * y * (3.0f * xx - yy);
-  Y[10] = kSH3b * x * y * z;
-  Y[11] = -kSH3c * y * (4.0f * zz - xx - yy);
-  Y[12] = kSH3d * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
-  Y[13] = -kSH3c * x * (4.0f * zz - xx - yy);
-  Y[14] = kSH3f * z * (xx - yy);
-  Y[15] = -kSH3a * x * (xx - 3.0f * yy);
-}
-
-// g = sum_j w_j grad Y_j(d) for the Cartesian forms above.
-__device__ __forceinline__ void sh_basis_vjp(int deg, float x, float y, float z, const float* w, float& gx,
-                                             float& gy, float& gz) {
-  gx = gy = gz = 0.0f;
-  if (deg < 1) return;
-  gy += -kSH1 * w[1];
-  gz += kSH1 * w[2];
-  gx += -kSH1 * w[3];
-  if (deg < 2) return;
-  const float xx = x * x, yy = y * y, zz = z * z;
-  gx += kSH2a * y * w[4];             gy += kSH2a * x * w[4];
-  gy += -kSH2a * z * w[5];            gz += -kSH2a * y * w[5];
-  gx += -2.0f * kSH2c * x * w[6];     gy += -2.0f * kSH2c * y * w[6];   gz += 4.0f * kSH2c * z * w[6];
-  gx += -kSH2a * z * w[7];            gz += -kSH2a * x * w[7];
-  gx += 2.0f * kSH2e * x * w[8];      gy += -2.0f * kSH2e * y * w[8];
-  if (deg < 3) return;
-  gx += -6.0f * kSH3a * x * y * w[9];
-  gy += -kSH3a * (3.0f * xx - 3.0f * yy) * w[9];
-  gx += kSH3b * y * z * w[10];  gy += kSH3b * x * z * w[10];  gz += kSH3b * x * y * w[10];
-  gx += 2.0f * kSH3c * x * y * w[11];
-  gy += -kSH3c * (4.0f * zz - xx - 3.0f * yy) * w[11];
-  gz += -8.0f * kSH3c * y * z * w[11];
-  gx += -6.0f * kSH3d * x * z * w[12];
-  gy += -6.0f * kSH3d * y * z * w[12];
-  gz += kSH3d * (6.0f * zz - 3.0f * xx - 3.0f * yy) * w[12];
-  gx += -kSH3c * (4.0f * zz - 3.0f * xx - yy) * w[13];
-  gy += 2.0f * kSH3c * x * y * w[13];
-  gz += -8.0f * kSH3c * x * z * w[13];
-  gx += 2.0f * kSH3f * x * z * w[14];
-  gy += -2.0f * kSH3f * y * z * w[14];
-  gz += kSH3f * (xx - yy) * w[14];
-  gx += -kSH3a * (3.0f * xx - 3.0f * yy) * w[15];
-  gy += 6.0f * kSH3a * x * y * w[15];
-}
 
 // Geometry of one Gaussian, shared by the forward and the backward so both
 // see the same FP32 values.
@@ -198,12 +124,6 @@ __device__ __forceinline__ void alpha_support(const Geo& g, float& ex, float& ey
   ey = sqrtf(rho2 * g.c) + 1e-3f + 1e-6f * fabsf(g.v);
 }
 
-__device__ __forceinline__ void view_dir(const float m[3], const DevCam& cam, float d[3], float& len) {
-  const float dx = m[0] - cam.centre[0], dy = m[1] - cam.centre[1], dz = m[2] - cam.centre[2];
-  len = sqrtf(dx * dx + dy * dy + dz * dz);
-  const float il = 1.0f / len;
-  d[0] = dx * il; d[1] = dy * il; d[2] = dz * il;
-}
 
 template <int DEG>
 __global__ __launch_bounds__(256) void k_project(int n, const float* __restrict__ means,
@@ -214,7 +134,7 @@ __global__ __launch_bounds__(256) void k_project(int n, const float* __restrict_
                                                  int* __restrict__ radius, uint32_t* __restrict__ tiles_touched) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  constexpr int NC = (DEG + 1) * (DEG + 1);
+  constexpr int NC = DEG < 0 ? 0 : (DEG + 1) * (DEG + 1);
   float m[3], s[3], q[4];
 #pragma unroll
   for (int k = 0; k < 3; ++k) { m[k] = means[k * n + i]; s[k] = log_scales[k * n + i]; }
@@ -224,7 +144,7 @@ __global__ __launch_bounds__(256) void k_project(int n, const float* __restrict_
   Geo g;
   bool live = project_geometry(m, s, q, logit, cam, g);
   float rgb[3] = {0.0f, 0.0f, 0.0f};
-  if (live) {
+  if (live && DEG >= 0) {   // DEG < 0: the learned decoder writes the colour afterwards
     float d[3], len;
     view_dir(m, cam, d, len);
     float Y[16];
@@ -266,6 +186,13 @@ gs_status launch_project(const gs_gaussians& g, const DevCam& cam, gs_projected&
   if (n == 0) return GS_OK;
   const dim3 block(256), grid(static_cast<unsigned>(ceil_div(n, 256)));
   float4* rec = reinterpret_cast<float4*>(out.records);
+  if (g.colour_mode == 1) {
+    k_project<-1><<<grid, block, 0, s>>>(n, g.means, g.log_scales, g.quats, g.logits, nullptr, cam, rec, out.depth,
+                                         out.radius, out.tiles_touched);
+    gs_status st = check_launch("k_project");
+    if (st != GS_OK) return st;
+    return launch_mlp_render(n, g.latents, g.means, out.radius, cam, g.mlp, out.records, s);
+  }
   switch (g.sh_degree) {
     case 0: k_project<0><<<grid, block, 0, s>>>(n, g.means, g.log_scales, g.quats, g.logits, g.sh, cam, rec,
                                                  out.depth, out.radius, out.tiles_touched); break;
@@ -300,7 +227,10 @@ __global__ __launch_bounds__(256) void k_project_bwd(int n, const float* __restr
                                                      float* __restrict__ g_logits, float* __restrict__ g_sh) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  constexpr int NC = (DEG + 1) * (DEG + 1);
+  // DEG < 0: colour comes from the learned decoder, whose backward adds its
+  // share to dL/dmean afterwards; only the geometry is differentiated here.
+  constexpr int NC = DEG < 0 ? 0 : (DEG + 1) * (DEG + 1);
+  constexpr int NCA = NC > 0 ? NC : 1;
   float m[3], s[3], q[4];
 #pragma unroll
   for (int k = 0; k < 3; ++k) { m[k] = means[k * n + i]; s[k] = log_scales[k * n + i]; }
@@ -312,12 +242,12 @@ __global__ __launch_bounds__(256) void k_project_bwd(int n, const float* __restr
   float d[3] = {0, 0, 0}, len = 1.0f;
   float Y[16];
   float raw[3] = {0, 0, 0};
-  float f[NC][3];
+  float f[NCA][3];
 #pragma unroll
   for (int j = 0; j < NC; ++j)
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) f[j][ch] = sh[(3 * j + ch) * n + i];
-  if (live) {
+  if (live && DEG >= 0) {
     view_dir(m, cam, d, len);
     sh_basis(DEG, d[0], d[1], d[2], Y);
 #pragma unroll
@@ -345,6 +275,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(int n, const float* __restr
   float gm[3] = {0.0f, 0.0f, 0.0f};
 
   // ---- colour
+  if constexpr (DEG >= 0) {
   float gc[3];
 #pragma unroll
   for (int ch = 0; ch < 3; ++ch) gc[ch] = raw[ch] >= 0.0f ? G[6 + ch] : 0.0f;
@@ -362,6 +293,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(int n, const float* __restr
     const float il = 1.0f / len;
 #pragma unroll
     for (int k = 0; k < 3; ++k) gm[k] += (gd[k] - d[k] * dd) * il;
+  }
   }
 
   // ---- opacity
@@ -452,22 +384,28 @@ __global__ __launch_bounds__(256) void k_project_bwd(int n, const float* __restr
   for (int k = 0; k < 3; ++k) g_means[k * n + i] = gm[k];
 }
 
-gs_status launch_project_bwd(const gs_gaussians& g, const DevCam& cam, const float* g2d, gs_gaussians_grad& gr,
-                             hipStream_t s) {
+gs_status launch_project_bwd(const gs_gaussians& g, const DevCam& cam, const int* radius, const float* g2d,
+                             gs_gaussians_grad& gr, void* ws, hipStream_t s) {
   const int n = static_cast<int>(g.n);
   if (n == 0) return GS_OK;
   const dim3 block(256), grid(static_cast<unsigned>(ceil_div(n, 256)));
 #define GS_PB(D)                                                                                                \
   k_project_bwd<D><<<grid, block, 0, s>>>(n, g.means, g.log_scales, g.quats, g.logits, g.sh, cam, g2d, gr.means, \
                                           gr.log_scales, gr.quats, gr.logits, gr.sh)
-  switch (g.sh_degree) {
-    case 0: GS_PB(0); break;
-    case 1: GS_PB(1); break;
-    case 2: GS_PB(2); break;
-    default: GS_PB(3); break;
+  if (g.colour_mode == 1) {
+    GS_PB(-1);
+  } else {
+    switch (g.sh_degree) {
+      case 0: GS_PB(0); break;
+      case 1: GS_PB(1); break;
+      case 2: GS_PB(2); break;
+      default: GS_PB(3); break;
+    }
   }
 #undef GS_PB
-  return check_launch("k_project_bwd");
+  gs_status st = check_launch("k_project_bwd");
+  if (st != GS_OK || g.colour_mode != 1) return st;
+  return launch_mlp_render_bwd(n, g.latents, g.means, radius, cam, g.mlp, g2d, gr.latents, gr.means, gr.mlp, ws, s);
 }
 
 }  // namespace gs

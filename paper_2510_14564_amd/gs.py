@@ -26,6 +26,7 @@ REC_FLOATS = 12
 G2D = 9
 L1_PARTIALS = 1024
 MLP_PARAMS = 6467
+MLP_PACKED_BYTES = 31244
 
 GS_OK, GS_ERR_INVALID_ARG, GS_ERR_CAPACITY, GS_ERR_HIP, GS_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
 STATUS_NAMES = {0: "GS_OK", -1: "GS_ERR_INVALID_ARG", -2: "GS_ERR_CAPACITY", -3: "GS_ERR_HIP",
@@ -34,7 +35,8 @@ STATUS_NAMES = {0: "GS_OK", -1: "GS_ERR_INVALID_ARG", -2: "GS_ERR_CAPACITY", -3:
 # every symbol declared in include/gsplat.h
 EXPORTS = ("gs_last_error", "gs_version", "gs_project", "gs_bin_sort_workspace", "gs_bin_sort",
            "gs_render_fwd", "gs_render_count", "gs_render_ckpt_floats", "gs_render_bwd_workspace", "gs_render_bwd", "gs_project_bwd",
-           "gs_l1_loss")
+           "gs_project_bwd_workspace", "gs_l1_loss", "gs_mlp_pack", "gs_mlp_fwd", "gs_mlp_bwd_workspace",
+           "gs_mlp_bwd", "gs_sh_colour", "gs_adam_step")
 
 
 class GsError(RuntimeError):
@@ -82,8 +84,17 @@ _sigs = {
     "gs_render_bwd_workspace": ([_i64, _i64, _P(Camera), _i32, _P(_sz)], ctypes.c_int),
     "gs_render_bwd": ([_i64, _P(Projected), _vp, _vp, _i64, _P(Camera), _vp, _vp, _vp, _vp, _vp, _vp, _sz, _i32,
                        _vp], ctypes.c_int),
-    "gs_project_bwd": ([_P(Gaussians), _P(Camera), _vp, _P(GaussiansGrad), _vp], ctypes.c_int),
+    "gs_project_bwd_workspace": ([_P(Gaussians), _P(_sz)], ctypes.c_int),
+    "gs_project_bwd": ([_P(Gaussians), _P(Camera), _P(Projected), _vp, _P(GaussiansGrad), _vp, _sz, _vp],
+                       ctypes.c_int),
     "gs_l1_loss": ([_vp, _vp, _i64, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "gs_mlp_pack": ([_vp, _vp, _vp], ctypes.c_int),
+    "gs_mlp_fwd": ([_i64, _i32, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "gs_mlp_bwd_workspace": ([_i64, _i32, _P(_sz)], ctypes.c_int),
+    "gs_mlp_bwd": ([_i64, _i32, _vp, _vp, _vp, _vp, _vp, ctypes.c_float, _vp, _vp, _vp, _vp, _sz, _vp], ctypes.c_int),
+    "gs_sh_colour": ([_i64, _i32, _i64, _i32, _vp, _vp, _i32, _vp, _vp], ctypes.c_int),
+    "gs_adam_step": ([_i64, _vp, _vp, _vp, _vp, _vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                      _i32, _vp], ctypes.c_int),
 }
 for _name, (_args, _res) in _sigs.items():
     _f = getattr(_lib, _name)
@@ -232,15 +243,83 @@ def render_bwd(n: int, proj: ProjectedBuffers, point_list, ranges, k: int, cam: 
                               ws.numel() * ws.element_size(), int(deterministic), _stream(stream)), "gs_render_bwd")
 
 
-def project_bwd(gauss: Gaussians, cam: Camera, g2d, grads: dict, stream=None):
+def project_bwd_workspace(gauss: Gaussians) -> int:
+    b = ctypes.c_size_t(0)
+    _check(_lib.gs_project_bwd_workspace(ctypes.byref(gauss), ctypes.byref(b)), "gs_project_bwd_workspace")
+    return int(b.value)
+
+
+def _nbytes(t):
+    return 0 if t is None else t.numel() * t.element_size()
+
+
+def project_bwd(gauss: Gaussians, cam: Camera, g2d, grads: dict, proj: ProjectedBuffers = None, ws=None,
+                stream=None):
+    """grads: device tensors keyed like the parameters ("sh" for SH colour,
+    "latents" [n][16] and "mlp" [MLP_PARAMS] FP32 for the learned colour)."""
     gg = GaussiansGrad()
-    gg.means, gg.log_scales, gg.quats, gg.logits, gg.sh = (_ptr(grads["means"]), _ptr(grads["log_scales"]),
-                                                           _ptr(grads["quats"]), _ptr(grads["logits"]),
-                                                           _ptr(grads["sh"]))
-    _check(_lib.gs_project_bwd(ctypes.byref(gauss), ctypes.byref(cam), _ptr(g2d), ctypes.byref(gg), _stream(stream)),
-           "gs_project_bwd")
+    gg.means, gg.log_scales, gg.quats, gg.logits = (_ptr(grads["means"]), _ptr(grads["log_scales"]),
+                                                    _ptr(grads["quats"]), _ptr(grads["logits"]))
+    gg.sh, gg.latents, gg.mlp = _ptr(grads.get("sh")), _ptr(grads.get("latents")), _ptr(grads.get("mlp"))
+    ps = ctypes.byref(proj.struct()) if proj is not None else None
+    _check(_lib.gs_project_bwd(ctypes.byref(gauss), ctypes.byref(cam), ps, _ptr(g2d), ctypes.byref(gg), _ptr(ws),
+                               _nbytes(ws), _stream(stream)), "gs_project_bwd")
 
 
 def l1_loss(img, target, loss, grad, partials, stream=None):
     _check(_lib.gs_l1_loss(_ptr(img), _ptr(target), img.numel(), _ptr(loss), _ptr(grad), _ptr(partials),
                            _stream(stream)), "gs_l1_loss")
+
+
+# ------------------------------------------------------------ learned colour
+
+def mlp_pack(params_bf16, packed, stream=None):
+    """params_bf16: device int16/uint16 tensor of MLP_PARAMS bf16 bit patterns."""
+    _check(_lib.gs_mlp_pack(_ptr(params_bf16), _ptr(packed), _stream(stream)), "gs_mlp_pack")
+
+
+def mlp_fwd(S: int, per: int, latents_bf16, dirs, packed, rgb, stream=None):
+    _check(_lib.gs_mlp_fwd(S, per, _ptr(latents_bf16), _ptr(dirs), _ptr(packed), _ptr(rgb), _stream(stream)),
+           "gs_mlp_fwd")
+
+
+def gaussians_struct_mlp(means, log_scales, quats, logits, latents_bf16, packed) -> Gaussians:
+    n = means.shape[1]
+    _check_f32("means", means, (3, n))
+    _check_f32("log_scales", log_scales, (3, n))
+    _check_f32("quats", quats, (4, n))
+    _check_f32("logits", logits, (n,))
+    if tuple(latents_bf16.shape) != (n, 16) or latents_bf16.element_size() != 2:
+        raise ValueError("latents: expected a [n][16] 16-bit tensor of bf16 bit patterns")
+    g = Gaussians()
+    g.n, g.sh_degree, g.colour_mode = n, 0, 1
+    g.means, g.log_scales, g.quats, g.logits = _ptr(means), _ptr(log_scales), _ptr(quats), _ptr(logits)
+    g.sh = None
+    g.latents, g.mlp = _ptr(latents_bf16), _ptr(packed)
+    return g
+
+
+def mlp_bwd_workspace(S: int, per: int) -> int:
+    b = ctypes.c_size_t(0)
+    _check(_lib.gs_mlp_bwd_workspace(S, per, ctypes.byref(b)), "gs_mlp_bwd_workspace")
+    return int(b.value)
+
+
+def mlp_bwd(S: int, per: int, latents_bf16, dirs, packed, dlatents, dparams, ws, dL_drgb=None, target=None,
+            scale: float = 1.0, loss=None, stream=None):
+    """Decoder backward: dL/drgb given, or the distillation loss
+    scale * sum |rgb - target|^2 (value into `loss`)."""
+    _check(_lib.gs_mlp_bwd(S, per, _ptr(latents_bf16), _ptr(dirs), _ptr(packed), _ptr(dL_drgb), _ptr(target),
+                           float(scale), _ptr(dlatents), _ptr(dparams), _ptr(loss), _ptr(ws), _nbytes(ws),
+                           _stream(stream)), "gs_mlp_bwd")
+
+
+def sh_colour(S: int, per: int, n: int, sh_degree: int, sh, dirs, rgb, clamp01: bool = True, stream=None):
+    _check(_lib.gs_sh_colour(S, per, n, sh_degree, _ptr(sh), _ptr(dirs), int(clamp01), _ptr(rgb), _stream(stream)),
+           "gs_sh_colour")
+
+
+def adam_step(param, grad, m, v, lr: float, step: int, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,
+              param_bf16=None, stream=None):
+    _check(_lib.gs_adam_step(param.numel(), _ptr(param), _ptr(grad), _ptr(m), _ptr(v), _ptr(param_bf16), float(lr),
+                             float(beta1), float(beta2), float(eps), int(step), _stream(stream)), "gs_adam_step")

@@ -7,6 +7,8 @@ the final transmittance and per-pixel contributor counts; nothing per
 (pixel, Gaussian) pair is stored -- the backward recomputes transmittance.
 Buffers are kept in a Rasterizer and reused across iterations; the (tile,
 Gaussian) capacity grows on demand (the library reports the size it needs).
+The colour comes from SH coefficients (a tensor) or from the learned decoder
+(a decoder.LearnedColour: BF16 latents + packed weights, colour_mode 1).
 """
 from __future__ import annotations
 
@@ -16,6 +18,7 @@ import dataclasses
 import torch
 
 from . import gs
+from .decoder import LearnedColour
 
 
 @dataclasses.dataclass
@@ -47,6 +50,7 @@ class Rasterizer:
         self.point_list = None
         self.bin_ws = None
         self.bwd_ws = None
+        self.pbwd_ws = None
         self.t_ckpt = None
         H, W = cam.height, cam.width
         self.ranges = torch.empty((self.ntiles, 2), dtype=torch.int32, device=self.device)
@@ -78,10 +82,15 @@ class Rasterizer:
         self.cam = cam
         self.cs = gs.camera_struct(cam)
 
-    def forward(self, means, log_scales, quats, logits, sh) -> FrameState:
+    def _gauss(self, means, log_scales, quats, logits, colour) -> gs.Gaussians:
+        if isinstance(colour, LearnedColour):
+            return gs.gaussians_struct_mlp(means, log_scales, quats, logits, colour.latents_bf16, colour.packed)
+        return gs.gaussians_struct(means, log_scales, quats, logits, colour, self.sh_degree)
+
+    def forward(self, means, log_scales, quats, logits, colour) -> FrameState:
         n = means.shape[1]
         self._ensure(n)
-        g = gs.gaussians_struct(means, log_scales, quats, logits, sh, self.sh_degree)
+        g = self._gauss(means, log_scales, quats, logits, colour)
         with self._stage("project"):
             gs.project(g, self.cs, self.proj)
         while True:
@@ -103,7 +112,7 @@ class Rasterizer:
         return FrameState(n, k, self.proj, self.point_list, self.ranges, self.image, self.final_T, self.n_contrib,
                           self.t_ckpt)
 
-    def backward(self, st: FrameState, means, log_scales, quats, logits, sh, dL_dimage, g2d=None):
+    def backward(self, st: FrameState, means, log_scales, quats, logits, colour, dL_dimage, g2d=None):
         n = st.n
         dL_dimage = dL_dimage.contiguous()
         need = gs.render_bwd_workspace(n, st.k, self.cs, self.deterministic)
@@ -115,33 +124,57 @@ class Rasterizer:
             gs.render_bwd(n, st.proj, st.point_list, st.ranges, st.k, self.cs, st.final_T, st.n_contrib, st.t_ckpt,
                           dL_dimage, g2d, self.bwd_ws, self.deterministic)
         grads = {k: torch.empty_like(v) for k, v in
-                 (("means", means), ("log_scales", log_scales), ("quats", quats), ("logits", logits), ("sh", sh))}
-        g = gs.gaussians_struct(means, log_scales, quats, logits, sh, self.sh_degree)
+                 (("means", means), ("log_scales", log_scales), ("quats", quats), ("logits", logits))}
+        g = self._gauss(means, log_scales, quats, logits, colour)
+        ws = None
+        if isinstance(colour, LearnedColour):
+            grads["latents"] = torch.empty((n, 16), dtype=torch.float32, device=self.device)
+            grads["mlp"] = torch.empty(gs.MLP_PARAMS, dtype=torch.float32, device=self.device)
+            need = gs.project_bwd_workspace(g)
+            if self.pbwd_ws is None or self.pbwd_ws.numel() < need:
+                self.pbwd_ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+            ws = self.pbwd_ws
+        else:
+            grads["sh"] = torch.empty_like(colour)
         with self._stage("project_bwd"):
-            gs.project_bwd(g, self.cs, g2d, grads)
+            gs.project_bwd(g, self.cs, g2d, grads, proj=st.proj, ws=ws)
         return grads, g2d
 
 
 class _RasterizeFn(torch.autograd.Function):
+    """Inputs: the geometry tensors, then the colour's tensors -- (sh, None) for
+    SH colour, (latents FP32, weights FP32) for the learned colour, whose BF16
+    copies and packed weights come in `learned` (kept in sync by the caller)."""
+
     @staticmethod
-    def forward(ctx, means, log_scales, quats, logits, sh, rast: Rasterizer):
-        st = rast.forward(means, log_scales, quats, logits, sh)
-        ctx.rast = rast
-        ctx.st = st
-        ctx.save_for_backward(means, log_scales, quats, logits, sh)
+    def forward(ctx, means, log_scales, quats, logits, c0, c1, rast: Rasterizer, learned):
+        colour = learned if learned is not None else c0
+        st = rast.forward(means, log_scales, quats, logits, colour)
+        ctx.rast, ctx.st, ctx.colour = rast, st, colour
+        ctx.save_for_backward(means, log_scales, quats, logits)
         # the rasterizer reuses its image buffer next call: hand autograd a copy
         return st.image.clone()
 
     @staticmethod
     def backward(ctx, dL_dimage):
-        means, log_scales, quats, logits, sh = ctx.saved_tensors
-        grads, _ = ctx.rast.backward(ctx.st, means, log_scales, quats, logits, sh, dL_dimage)
-        return grads["means"], grads["log_scales"], grads["quats"], grads["logits"], grads["sh"], None
+        means, log_scales, quats, logits = ctx.saved_tensors
+        grads, _ = ctx.rast.backward(ctx.st, means, log_scales, quats, logits, ctx.colour, dL_dimage)
+        if isinstance(ctx.colour, LearnedColour):
+            gc0, gc1 = grads["latents"], grads["mlp"]
+        else:
+            gc0, gc1 = grads["sh"], None
+        return grads["means"], grads["log_scales"], grads["quats"], grads["logits"], gc0, gc1, None, None
 
 
 def rasterize(means, log_scales, quats, logits, sh, rast: Rasterizer):
     """Differentiable render of the Gaussians with the rasterizer's camera: image[3][H][W]."""
-    return _RasterizeFn.apply(means, log_scales, quats, logits, sh, rast)
+    return _RasterizeFn.apply(means, log_scales, quats, logits, sh, None, rast, None)
+
+
+def rasterize_learned(means, log_scales, quats, logits, dec, rast: Rasterizer):
+    """Same with the learned colour of a decoder.Decoder: gradients flow to
+    dec.latents and dec.params (FP32 masters) when they require grad."""
+    return _RasterizeFn.apply(means, log_scales, quats, logits, dec.latents, dec.params, rast, dec.colour())
 
 
 def l1_loss(img, target, partials=None):

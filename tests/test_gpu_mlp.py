@@ -1,0 +1,364 @@
+"""Parity of the learned colour decoder's matrix-core kernels with the FP64 oracle.
+
+Both sides use the same BF16 latents and weights (widened exactly to FP64 in
+the oracle).  The HIP path also rounds the SH encoding of the direction and
+both hidden activations to BF16 before each product and accumulates in FP32;
+the tolerance is the running error bound of exactly those roundings,
+propagated through |W| in FP64 (ReLU is 1-Lipschitz, the sigmoid 1/4).  The
+observed maximum error is printed.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2510_14564_amd import scenes
+from gpu_helpers import DEV, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -8      # bf16 relative rounding bound (half an ulp = 2^-9, doubled for safety)
+G32 = 2.0 ** -22   # FP32 accumulation, per term, with margin
+
+
+@pytest.fixture(scope="module")
+def gs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2510_14564_amd import gs as mod
+    return mod
+
+
+def kaiming_params(seed):
+    """Kaiming-uniform weights and small biases, rounded to bf16 bit patterns."""
+    rng = np.random.default_rng(seed)
+    P = np.zeros(oracle.MLP_PARAMS, np.float32)
+    for name, (off, shape) in oracle.MLP_SLICES.items():
+        size = int(np.prod(shape))
+        if name.startswith("W"):
+            bound = np.sqrt(6.0 / shape[1])
+            P[off:off + size] = rng.uniform(-bound, bound, size)
+        else:
+            P[off:off + size] = rng.uniform(-0.1, 0.1, size)
+    return scenes.bf16_bits(P)
+
+
+F32 = 2.0 ** -23   # FP32 rounding, doubled
+
+
+def _slices(P):
+    return {k: P[o:o + int(np.prod(s))].reshape(s) for k, (o, s) in oracle.MLP_SLICES.items()}
+
+
+def fwd_bounds(x, P, ex=None):
+    """Running error bound of the forward: pre-activation errors d1, d2, d3,
+    post-activation (BF16-rounded) errors e1, e2, colour error dc; plus the
+    FP64 quantities.  ex: bound on the input error (default: the SH half
+    rounded to BF16, latents exact)."""
+    sl = _slices(P)
+    ax = np.abs(x)
+    if ex is None:
+        ex = np.concatenate([np.zeros_like(ax[:, :16]), U * ax[:, 16:]], axis=1)
+    W1, W2, W3 = np.abs(sl["W1"]), np.abs(sl["W2"]), np.abs(sl["W3"])
+    a1 = x @ sl["W1"].T + sl["b1"]
+    h1 = np.maximum(a1, 0)
+    a2 = h1 @ sl["W2"].T + sl["b2"]
+    h2 = np.maximum(a2, 0)
+    a3 = h2 @ sl["W3"].T + sl["b3"]
+    c = 1 / (1 + np.exp(-a3))
+    d1 = ex @ W1.T + 32 * G32 * ((ax + ex) @ W1.T + np.abs(sl["b1"]))
+    e1 = d1 + U * (h1 + d1)
+    d2 = e1 @ W2.T + 64 * G32 * ((h1 + e1) @ W2.T + np.abs(sl["b2"]))
+    e2 = d2 + U * (h2 + d2)
+    d3 = e2 @ W3.T + 64 * G32 * ((h2 + e2) @ W3.T + np.abs(sl["b3"]))
+    dc = 0.25 * d3 + 2e-6
+    return dict(sl=sl, ax=ax, ex=ex, a1=a1, h1=h1, a2=a2, h2=h2, c=c, d1=d1, e1=e1, d2=d2, e2=e2, dc=dc)
+
+
+def error_bound(x, P):
+    """Per-sample, per-channel bound on |c_gpu - c_exact|."""
+    return fwd_bounds(x, P)["dc"]
+
+
+def bwd_bounds(x, P, G, eG=None, ex=None):
+    """Bounds on |dP_gpu - dP*| [6467] and |dx_gpu - dx*| [S][32] for the
+    backward of sum(G * c): the forward bound, BF16 rounding of every operand
+    the kernel feeds to the matrix cores (gradients and activations), FP32
+    accumulation, and -- where a pre-activation lies within its error bound of
+    0 -- the whole value of a ReLU gate that may have flipped.  eG bounds the
+    error of G itself (the distillation loss takes G from the kernel's own c)."""
+    f = fwd_bounds(x, P, ex)
+    sl, ax, ex, c, dc = f["sl"], f["ax"], f["ex"], f["c"], f["dc"]
+    W1, W2, W3 = np.abs(sl["W1"]), np.abs(sl["W2"]), np.abs(sl["W3"])
+    S = x.shape[0]
+    if eG is None:
+        eG = np.zeros_like(G)
+    s3 = c * (1 - c)
+    g3 = G * s3
+    eg3 = np.abs(G) * (dc + dc * dc) + eG * (s3 + dc + dc * dc) + 1e-6 * np.abs(g3)
+    eg3b = eg3 + U * (np.abs(g3) + eg3)
+    t2 = g3 @ sl["W3"]
+    et2 = eg3b @ W3 + 3 * G32 * (np.abs(g3) + eg3b) @ W3
+    g2 = t2 * (f["a2"] > 0)
+    eg2 = np.where(np.abs(f["a2"]) <= f["d2"], np.abs(t2) + et2, et2)
+    eg2b = eg2 + U * (np.abs(g2) + eg2)
+    t1 = g2 @ sl["W2"]
+    et1 = eg2b @ W2 + 64 * G32 * (np.abs(g2) + eg2b) @ W2
+    g1 = t1 * (f["a1"] > 0)
+    eg1 = np.where(np.abs(f["a1"]) <= f["d1"], np.abs(t1) + et1, et1)
+    eg1b = eg1 + U * (np.abs(g1) + eg1)
+    edx = eg1b @ W1 + 64 * G32 * (np.abs(g1) + eg1b) @ W1
+    acc = (S / 16 + 256) * F32
+    h1, e1, h2, e2 = f["h1"], f["e1"], f["h2"], f["e2"]
+    xs = ax + ex
+    eP = np.zeros(oracle.MLP_PARAMS)
+
+    def put(name, v):
+        off, shape = oracle.MLP_SLICES[name]
+        eP[off:off + int(np.prod(shape))] = v.reshape(-1)
+
+    ag1, ag2, ag3 = np.abs(g1), np.abs(g2), np.abs(g3)
+    put("W1", eg1b.T @ xs + ag1.T @ ex + acc * (ag1 + eg1b).T @ xs)
+    put("W2", eg2b.T @ (h1 + e1) + ag2.T @ e1 + acc * (ag2 + eg2b).T @ (h1 + e1))
+    put("W3", eg3b.T @ (h2 + e2) + ag3.T @ e2 + acc * (ag3 + eg3b).T @ (h2 + e2))
+    put("b1", eg1.sum(0) + acc * (ag1 + eg1).sum(0))
+    put("b2", eg2.sum(0) + acc * (ag2 + eg2).sum(0))
+    put("b3", eg3.sum(0) + acc * (ag3 + eg3).sum(0))
+    return eP + 1e-7, edx + 1e-7, c
+
+
+def reading18(got, want, floor=1e-2):
+    """Fraction of entries within floor * max(|g*|, 1e-3 max|g*|)."""
+    tol = floor * np.maximum(np.abs(want), 1e-3 * np.abs(want).max())
+    return float(np.mean(np.abs(got - want) <= tol))
+
+
+def _dirs(n, per, seed):
+    d = np.random.default_rng(seed).normal(size=(n, per, 3))
+    return (d / np.linalg.norm(d, axis=2, keepdims=True)).astype(np.float32)
+
+
+def _packed(gs, Pbits):
+    packed = torch.empty(gs.MLP_PACKED_BYTES // 4 + 4, dtype=torch.float32, device=DEV)
+    gs.mlp_pack(to_dev(Pbits.view(np.int16)), packed)
+    return packed
+
+
+@pytest.mark.parametrize("n,per", [(1, 1), (37, 3), (4096, 4), (20000, 1)])
+def test_mlp_forward_matches_oracle_within_bf16_bound(gs, n, per):
+    say(f"[mlp fwd] n={n} per={per}")
+    Pbits = kaiming_params(10 + n)
+    z = scenes.bf16_bits(np.random.default_rng(n).normal(0, 0.5, (n, 16)).astype(np.float32))
+    d = _dirs(n, per, 20 + n)
+    packed = _packed(gs, Pbits)
+    S = n * per
+    rgb = torch.empty((S, 3), dtype=torch.float32, device=DEV)
+    gs.mlp_fwd(S, per, to_dev(z.view(np.int16)), to_dev(d.reshape(S, 3)), packed, rgb)
+    torch.cuda.synchronize()
+    P = scenes.bf16_to_f32(Pbits).astype(np.float64)
+    x = oracle.mlp_inputs(scenes.bf16_to_f32(z).astype(np.float64), d.astype(np.float64))
+    want = oracle.mlp_fwd(x, P)
+    got = rgb.cpu().numpy().astype(np.float64)
+    err = np.abs(got - want)
+    bound = error_bound(x, P)
+    assert (err <= bound).all(), f"max err {err.max():.3e}, worst ratio {(err / bound).max():.2f}"
+    assert err.max() <= 1e-3
+    say(f"  max |err| {err.max():.2e}, max err/bound {(err / bound).max():.3f}")
+
+
+def test_mlp_zero_weights_give_sigmoid_bias(gs):
+    P = np.zeros(oracle.MLP_PARAMS, np.float32)
+    P[oracle.MLP_SLICES["b3"][0]:] = [-1.0, 0.25, 2.0]
+    Pbits = scenes.bf16_bits(P)
+    n = 100
+    z = scenes.bf16_bits(np.random.default_rng(1).normal(size=(n, 16)).astype(np.float32))
+    d = _dirs(n, 1, 2)
+    rgb = torch.empty((n, 3), dtype=torch.float32, device=DEV)
+    gs.mlp_fwd(n, 1, to_dev(z.view(np.int16)), to_dev(d.reshape(n, 3)), _packed(gs, Pbits), rgb)
+    want = 1.0 / (1.0 + np.exp(-scenes.bf16_to_f32(Pbits)[-3:].astype(np.float64)))
+    assert np.abs(rgb.cpu().numpy() - want).max() < 1e-6
+
+
+def test_project_with_learned_colour(gs):
+    """colour_mode 1: geometry identical to the SH projection, colour = decoder of
+    (latent, SH encoding of the camera-to-Gaussian direction) for live Gaussians."""
+    scene = scenes.config_scene(5, n=20000)
+    cam = scenes.config_camera(5)
+    say(f"[project learned colour] n={scene.n}")
+    Pbits = kaiming_params(5)
+    packed = _packed(gs, Pbits)
+    p = {k: to_dev(v) for k, v in scene.arrays().items()}
+    lat = to_dev(scene.latents.view(np.int16))
+    g = gs.gaussians_struct_mlp(p["means"], p["log_scales"], p["quats"], p["logits"], lat, packed)
+    out = gs.ProjectedBuffers(scene.n, DEV)
+    gs.project(g, gs.camera_struct(cam), out)
+    g_sh = gs.gaussians_struct(p["means"], p["log_scales"], p["quats"], p["logits"], p["sh"], scene.sh_degree)
+    out_sh = gs.ProjectedBuffers(scene.n, DEV)
+    gs.project(g_sh, gs.camera_struct(cam), out_sh)
+    torch.cuda.synchronize()
+    rec, rec_sh = out.records.cpu().numpy(), out_sh.records.cpu().numpy()
+    live = out.radius.cpu().numpy() > 0
+    assert np.array_equal(live, out_sh.radius.cpu().numpy() > 0)
+    geo = [0, 1, 2, 3, 4, 5, 9]
+    assert np.array_equal(rec[:, geo], rec_sh[:, geo])
+    assert (rec[~live] == 0).all()
+    # oracle colour at the FP64 view direction of each live Gaussian
+    ca = oracle.cam_array(cam)
+    centre = -(ca[7:16].reshape(3, 3).T @ ca[16:19])
+    dirs = scene.means.astype(np.float64).T - centre
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    x = oracle.mlp_inputs(scenes.bf16_to_f32(scene.latents).astype(np.float64), dirs[:, None, :])
+    P = scenes.bf16_to_f32(Pbits).astype(np.float64)
+    want = oracle.mlp_fwd(x, P)
+    err = np.abs(rec[live, 6:9] - want[live])
+    bound = error_bound(x, P)[live] + 1e-5     # + the FP32 view direction
+    assert (err <= bound).all(), (err.max(), (err / bound).max())
+    say(f"  live {live.sum()}, max colour err {err.max():.2e}")
+
+
+def _bwd_workspace(gs, S, per):
+    return torch.empty(gs.mlp_bwd_workspace(S, per), dtype=torch.uint8, device=DEV)
+
+
+def _check_grads(label, got_P, want_P, bP, got_z, want_z, bz):
+    errP, errz = np.abs(got_P - want_P), np.abs(got_z - want_z)
+    assert (errP <= bP).all(), f"{label} dP: worst err/bound {(errP / bP).max():.2f}"
+    assert (errz <= bz).all(), f"{label} dz: worst err/bound {(errz / bz).max():.2f}"
+    fP, fz = reading18(got_P, want_P), reading18(got_z, want_z)
+    say(f"  {label}: max err/bound dP {(errP / bP).max():.3f} dz {(errz / bz).max():.3f}; "
+        f"within 1e-2 rel: dP {fP:.4f} dz {fz:.4f}")
+    assert fP >= 0.99 and fz >= 0.99
+
+
+@pytest.mark.parametrize("n,per", [(1, 1), (37, 4), (300, 64), (5000, 1), (2000, 16)])
+def test_mlp_backward_matches_oracle_within_bound(gs, n, per):
+    say(f"[mlp bwd] n={n} per={per}")
+    Pbits = kaiming_params(30 + n)
+    z = scenes.bf16_bits(np.random.default_rng(n + 1).normal(0, 0.5, (n, 16)).astype(np.float32))
+    d = _dirs(n, per, 40 + n)
+    S = n * per
+    G = np.random.default_rng(n + 2).normal(size=(S, 3)).astype(np.float32)
+    packed = _packed(gs, Pbits)
+    dlat = torch.empty((n, 16), dtype=torch.float32, device=DEV)
+    dP = torch.empty(oracle.MLP_PARAMS, dtype=torch.float32, device=DEV)
+    ws = _bwd_workspace(gs, S, per)
+    zd, dd, Gd = to_dev(z.view(np.int16)), to_dev(d.reshape(S, 3)), to_dev(G)
+    gs.mlp_bwd(S, per, zd, dd, packed, dlat, dP, ws, dL_drgb=Gd)
+    torch.cuda.synchronize()
+    got_P, got_z = dP.cpu().numpy().astype(np.float64), dlat.cpu().numpy().astype(np.float64)
+    # bit-reproducible: a second call gives the same bits
+    gs.mlp_bwd(S, per, zd, dd, packed, dlat, dP, ws, dL_drgb=Gd)
+    torch.cuda.synchronize()
+    assert np.array_equal(dP.cpu().numpy(), got_P.astype(np.float32))
+    assert np.array_equal(dlat.cpu().numpy(), got_z.astype(np.float32))
+    P = scenes.bf16_to_f32(Pbits).astype(np.float64)
+    x = oracle.mlp_inputs(scenes.bf16_to_f32(z).astype(np.float64), d.astype(np.float64))
+    want_P, dx = oracle.mlp_bwd(x, P, G.astype(np.float64))
+    bP, bdx, _ = bwd_bounds(x, P, G.astype(np.float64))
+    want_z = dx[:, :16].reshape(n, per, 16).sum(1)
+    bz = bdx[:, :16].reshape(n, per, 16).sum(1) + per * F32 * np.abs(dx[:, :16]).reshape(n, per, 16).sum(1)
+    _check_grads(f"n={n} per={per}", got_P, want_P, bP, got_z, want_z, bz)
+
+
+def test_mlp_distillation_loss_and_gradient(gs):
+    """Loss mode: L = scale * sum |c - target|^2 with the gradient taken from
+    the kernel's own colours."""
+    n, per = 256, 64
+    S = n * per
+    say(f"[mlp distill loss] S={S}")
+    Pbits = kaiming_params(77)
+    z = scenes.bf16_bits(np.random.default_rng(78).normal(0, 0.5, (n, 16)).astype(np.float32))
+    d = _dirs(n, per, 79)
+    tgt = np.random.default_rng(80).uniform(0, 1, (S, 3)).astype(np.float32)
+    scale = 1.0 / S
+    packed = _packed(gs, Pbits)
+    dlat = torch.empty((n, 16), dtype=torch.float32, device=DEV)
+    dP = torch.empty(oracle.MLP_PARAMS, dtype=torch.float32, device=DEV)
+    loss = torch.empty(1, dtype=torch.float32, device=DEV)
+    gs.mlp_bwd(S, per, to_dev(z.view(np.int16)), to_dev(d.reshape(S, 3)), packed, dlat, dP,
+               _bwd_workspace(gs, S, per), target=to_dev(tgt), scale=scale, loss=loss)
+    torch.cuda.synchronize()
+    P = scenes.bf16_to_f32(Pbits).astype(np.float64)
+    x = oracle.mlp_inputs(scenes.bf16_to_f32(z).astype(np.float64), d.astype(np.float64))
+    c = oracle.mlp_fwd(x, P)
+    t = tgt.astype(np.float64)
+    dc = error_bound(x, P)
+    want_loss = scale * np.sum((c - t) ** 2)
+    bl = scale * np.sum(2 * np.abs(c - t) * dc + dc * dc) + S * 3 * F32 * want_loss
+    assert abs(loss.item() - want_loss) <= bl, (loss.item(), want_loss, bl)
+    G = 2 * scale * (c - t)
+    want_P, dx = oracle.mlp_bwd(x, P, G)
+    bP, bdx, _ = bwd_bounds(x, P, G, eG=2 * scale * dc)
+    want_z = dx[:, :16].reshape(n, per, 16).sum(1)
+    bz = bdx[:, :16].reshape(n, per, 16).sum(1) + per * F32 * np.abs(dx[:, :16]).reshape(n, per, 16).sum(1)
+    _check_grads("distill", dP.cpu().numpy().astype(np.float64), want_P, bP,
+                 dlat.cpu().numpy().astype(np.float64), want_z, bz)
+
+
+def test_project_bwd_learned_colour(gs):
+    """colour_mode 1 backward: geometry gradients as the SH path's (degree 0
+    carries no direction term), plus the decoder's latent, weight and
+    view-direction gradients, against the FP64 oracle / torch autograd."""
+    from oracle import brute
+    from gpu_helpers import grad_close
+    scene = scenes.config_scene(5, n=6000)
+    cam = scenes.config_camera(5)
+    n = scene.n
+    say(f"[project bwd learned colour] n={n}")
+    Pbits = kaiming_params(6)
+    packed = _packed(gs, Pbits)
+    p = {k: to_dev(v) for k, v in scene.arrays().items()}
+    lat = to_dev(scene.latents.view(np.int16))
+    g = gs.gaussians_struct_mlp(p["means"], p["log_scales"], p["quats"], p["logits"], lat, packed)
+    out = gs.ProjectedBuffers(n, DEV)
+    cs = gs.camera_struct(cam)
+    gs.project(g, cs, out)
+    g2d_h = np.random.default_rng(7).normal(size=(gs.G2D, n)).astype(np.float32)
+    grads = {kk: torch.empty_like(p[kk]) for kk in ("means", "log_scales", "quats", "logits")}
+    grads["latents"] = torch.empty((n, 16), dtype=torch.float32, device=DEV)
+    grads["mlp"] = torch.empty(oracle.MLP_PARAMS, dtype=torch.float32, device=DEV)
+    ws = torch.empty(gs.project_bwd_workspace(g), dtype=torch.uint8, device=DEV)
+    gs.project_bwd(g, cs, to_dev(g2d_h), grads, proj=out, ws=ws)
+    torch.cuda.synchronize()
+    live = out.radius.cpu().numpy() > 0
+    # geometry: the oracle's SH backward on a degree-0 copy (no direction term)
+    s0 = scenes.Scene(n, 0, scene.means, scene.log_scales, scene.quats, scene.logits,
+                      np.zeros((1, 3, n), np.float32))
+    geo = oracle.project_bwd(s0, cam, g2d_h.astype(np.float64))
+    o = oracle.project(s0, cam)
+    ok = (o["flags"] & 0b1110) == 0
+    for kk in ("log_scales", "quats", "logits"):
+        grad_close(grads[kk].cpu().numpy()[..., ok], geo[kk][..., ok], name=kk)
+    # decoder part through torch autograd in FP64 (live Gaussians only)
+    ca = oracle.cam_array(cam)
+    centre = -(ca[7:16].reshape(3, 3).T @ ca[16:19])
+    idx = np.nonzero(live)[0]
+    mt = torch.tensor(scene.means[:, idx].astype(np.float64), requires_grad=True)
+    zt = torch.tensor(scenes.bf16_to_f32(scene.latents[idx]).astype(np.float64), requires_grad=True)
+    P = scenes.bf16_to_f32(Pbits).astype(np.float64)
+    Pt = torch.tensor(P, requires_grad=True)
+    Gc = g2d_h[6:9, idx].T.astype(np.float64)
+    (brute.learned_colour(mt, centre, zt, Pt) * torch.tensor(Gc)).sum().backward()
+    dirs = scene.means[:, idx].astype(np.float64).T - centre
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    x = oracle.mlp_inputs(zt.detach().numpy(), dirs[:, None, :])
+    # the kernel's direction is FP32: widen the input bound of the SH half
+    ex = np.concatenate([np.zeros((len(idx), 16)), (U + 1e-5) * np.abs(x[:, 16:]) + 1e-6], axis=1)
+    bP, bdx, _ = bwd_bounds(x, P, Gc, ex=ex)
+    got_z = grads["latents"].cpu().numpy().astype(np.float64)
+    assert (got_z[~live] == 0).all()
+    _check_grads("learned colour", grads["mlp"].cpu().numpy().astype(np.float64), Pt.grad.numpy(), bP,
+                 got_z[idx], zt.grad.numpy(), bdx[:, :16])
+    # means: geometry (1e-3 relative) + the direction share, whose error is at
+    # most |grad Y_j| <= 10 on the unit sphere times the dL/dY bound, over |v|
+    share = mt.grad.numpy()
+    want_m = geo["means"].copy()
+    want_m[:, idx] += share
+    got_m = grads["means"].cpu().numpy().astype(np.float64)
+    ref = np.maximum(np.abs(geo["means"]), 1e-3 * np.abs(geo["means"]).max())
+    bound = 1e-3 * ref
+    vlen = np.linalg.norm(scene.means[:, idx].astype(np.float64).T - centre, axis=1)
+    bound[:, idx] += 1e-5 * np.abs(share) + (10 * bdx[:, 16:].sum(1) / vlen)[None, :]
+    err = np.abs(got_m - want_m)
+    assert (err[:, ok] <= bound[:, ok]).all(), (err[:, ok] / bound[:, ok]).max()
+    say(f"  means: max err/bound {(err[:, ok] / bound[:, ok]).max():.3f}")

@@ -110,3 +110,38 @@ def test_bf16_rounding_matches_torch():
     np.testing.assert_array_equal(bits, want)
     back = scenes.bf16_to_f32(bits)
     assert np.all(np.abs(back - x) <= np.abs(x) * 2.0 ** -8)
+
+
+def test_brute_learned_colour_matches_c_oracle_and_finite_differences():
+    """The torch route (brute.learned_colour) agrees with the C oracle's inputs,
+    forward and parameter/latent gradients, and its gradient in the means with
+    central differences of the C oracle's forward."""
+    rng = np.random.default_rng(13)
+    n = 12
+    means = rng.normal(size=(3, n))
+    centre = np.array([0.3, -0.2, -4.0])
+    z = rng.normal(0, 0.3, (n, 16))
+    P = _params(14)
+    G = rng.normal(size=(n, 3))
+    mt = torch.tensor(means, requires_grad=True)
+    zt = torch.tensor(z, requires_grad=True)
+    Pt = torch.tensor(P, requires_grad=True)
+    c = brute.learned_colour(mt, centre, zt, Pt)
+    dirs = (means.T - centre) / np.linalg.norm(means.T - centre, axis=1, keepdims=True)
+    x = oracle.mlp_inputs(z, dirs[:, None, :])
+    np.testing.assert_allclose(c.detach().numpy(), oracle.mlp_fwd(x, P), atol=1e-14)
+    (c * torch.tensor(G)).sum().backward()
+    dP, dx = oracle.mlp_bwd(x, P, G)
+    np.testing.assert_allclose(Pt.grad.numpy(), dP, rtol=1e-10, atol=1e-13)
+    np.testing.assert_allclose(zt.grad.numpy(), dx[:, :16], rtol=1e-10, atol=1e-13)
+
+    def f(m):
+        d = (m.T - centre) / np.linalg.norm(m.T - centre, axis=1, keepdims=True)
+        return np.sum(G * oracle.mlp_fwd(oracle.mlp_inputs(z, d[:, None, :]), P))
+    h = 1e-6
+    for k, i in ((0, 0), (1, 5), (2, 11)):
+        mp, mm = means.copy(), means.copy()
+        mp[k, i] += h
+        mm[k, i] -= h
+        fd = (f(mp) - f(mm)) / (2 * h)
+        assert abs(fd - mt.grad[k, i].item()) < 1e-6 * max(1.0, abs(fd)), (k, i, fd, mt.grad[k, i].item())
