@@ -157,6 +157,17 @@ gs_status gs_bin_sort(int64_t n, const gs_projected* proj, const gs_camera* cam,
                       uint32_t* point_list, int64_t capacity, uint32_t* ranges, int64_t* k_out,
                       gs_stream stream);
 
+/* Work split of the compositing kernels (Sec. IV: workload imbalance between
+ * dense and sparse tiles).  PLAIN: one workgroup per tile, tiles mapped so
+ * that neighbours share an XCD.  BALANCED: a plan built on the device from
+ * each tile's work count (list length for the forward, largest n_contrib for
+ * the backward) starts the heavy tiles -- above four times the mean count --
+ * first, largest first, and maps the rest as in PLAIN.  Per-tile arithmetic
+ * is identical, so both give the same image (bit for bit) and the same
+ * gradients up to the order of the atomic sums. */
+#define GS_SCHEDULE_PLAIN 0
+#define GS_SCHEDULE_BALANCED 1
+
 /* Forward compositing (Sec. II-A, C = sum_i c_i alpha_i prod_{j<i} (1 - alpha_j)
  * over the tile's depth-ordered list).  Per pixel: power = -1/2 (A dx^2 +
  * C dy^2) - B dx dy, alpha = min(0.99, o exp(power)); entries with power > 0 or
@@ -164,12 +175,13 @@ gs_status gs_bin_sort(int64_t n, const gs_projected* proj, const gs_camera* cam,
  * the transmittance below 1e-4.  Outputs image[3][H][W] = colour + T bg,
  * final_T[H][W] and n_contrib[H][W] (1 + position in the tile list of the last
  * blended entry, 0 if none).  t_ckpt (gs_render_ckpt_floats floats, or NULL
- * when no backward follows) receives every pixel's transmittance at each
- * 256-entry boundary of its tile list, which the backward restarts from.
+ * when no backward follows and schedule is PLAIN) receives every pixel's
+ * transmittance at each 256-entry boundary of its tile list, which the
+ * backward restarts from, the forward's tile plan and each tile's work count.
  * Deterministic. */
 gs_status gs_render_fwd(int64_t n, const gs_projected* proj, const uint32_t* point_list, const uint32_t* ranges,
                         int64_t k, const gs_camera* cam, float* image, float* final_T, uint32_t* n_contrib,
-                        float* t_ckpt, gs_stream stream);
+                        float* t_ckpt, int32_t schedule, gs_stream stream);
 
 /* Work counter for measurement: runs the forward's per-pixel decisions
  * without producing an image and writes counts[0] = pairs whose alpha is
@@ -198,11 +210,13 @@ gs_status gs_render_bwd_workspace(int64_t n, int64_t k, const gs_camera* cam, in
  * Sigma' before the sum over pixels, which stays well conditioned where the
  * conic is nearly singular (elongated footprints).  deterministic = 1 sums the
  * per-(tile, Gaussian) partials in a fixed order (bit-reproducible); 0 uses
- * device atomics.  ws as sized by gs_render_bwd_workspace. */
+ * device atomics.  ws as sized by gs_render_bwd_workspace (holds the
+ * backward's tile plan).  schedule as for gs_render_fwd; BALANCED plans from
+ * the work counts the forward left in t_ckpt. */
 gs_status gs_render_bwd(int64_t n, const gs_projected* proj, const uint32_t* point_list, const uint32_t* ranges,
                         int64_t k, const gs_camera* cam, const float* final_T, const uint32_t* n_contrib,
                         const float* t_ckpt, const float* dL_dimage, float* g2d, void* ws, size_t ws_bytes,
-                        int32_t deterministic, gs_stream stream);
+                        int32_t deterministic, int32_t schedule, gs_stream stream);
 
 /* Backward of the projection: chain rule from g2d[9][n] to the raw parameters
  * (means, log_scales, quats, logits, sh) through the steps of gs_project

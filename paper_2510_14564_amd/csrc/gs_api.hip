@@ -142,7 +142,7 @@ gs_status gs_bin_sort(int64_t n, const gs_projected* proj, const gs_camera* cam,
 
 gs_status gs_render_fwd(int64_t n, const gs_projected* proj, const uint32_t* point_list, const uint32_t* ranges,
                         int64_t k, const gs_camera* cam, float* image, float* final_T, uint32_t* n_contrib,
-                        float* t_ckpt, gs_stream stream) {
+                        float* t_ckpt, int32_t schedule, gs_stream stream) {
   set_error("");
   gs_status st;
   if (n < 0 || k < 0) return fail(GS_ERR_INVALID_ARG, "gs_render_fwd: negative n or k");
@@ -150,8 +150,12 @@ gs_status gs_render_fwd(int64_t n, const gs_projected* proj, const uint32_t* poi
   if ((st = validate_projected(proj, n, "gs_render_fwd")) != GS_OK) return st;
   if (!ranges || !image || !final_T || !n_contrib || (k > 0 && !point_list))
     return fail(GS_ERR_INVALID_ARG, "gs_render_fwd: NULL array");
-  return launch_render_fwd(*proj, point_list, ranges, make_devcam(*cam), image, final_T, n_contrib, t_ckpt,
-                           static_cast<hipStream_t>(stream));
+  if (schedule != GS_SCHEDULE_PLAIN && schedule != GS_SCHEDULE_BALANCED)
+    return fail(GS_ERR_INVALID_ARG, "gs_render_fwd: unknown schedule");
+  if (schedule == GS_SCHEDULE_BALANCED && !t_ckpt)
+    return fail(GS_ERR_INVALID_ARG, "gs_render_fwd: the balanced schedule keeps its plan in t_ckpt");
+  return launch_render_fwd(*proj, point_list, ranges, k, make_devcam(*cam), image, final_T, n_contrib, t_ckpt,
+                           schedule, static_cast<hipStream_t>(stream));
 }
 
 gs_status gs_render_count(int64_t n, const gs_projected* proj, const uint32_t* point_list, const uint32_t* ranges,
@@ -189,7 +193,7 @@ gs_status gs_render_bwd_workspace(int64_t n, int64_t k, const gs_camera* cam, in
 gs_status gs_render_bwd(int64_t n, const gs_projected* proj, const uint32_t* point_list, const uint32_t* ranges,
                         int64_t k, const gs_camera* cam, const float* final_T, const uint32_t* n_contrib,
                         const float* t_ckpt, const float* dL_dimage, float* g2d, void* ws, size_t ws_bytes,
-                        int32_t deterministic, gs_stream stream) {
+                        int32_t deterministic, int32_t schedule, gs_stream stream) {
   set_error("");
   gs_status st;
   if (n < 0 || k < 0) return fail(GS_ERR_INVALID_ARG, "gs_render_bwd: negative n or k");
@@ -198,11 +202,13 @@ gs_status gs_render_bwd(int64_t n, const gs_projected* proj, const uint32_t* poi
   if (!ranges || !final_T || !n_contrib || !t_ckpt || !dL_dimage || (n > 0 && !g2d) || (k > 0 && !point_list))
     return fail(GS_ERR_INVALID_ARG, "gs_render_bwd: NULL array");
   const DevCam d = make_devcam(*cam);
-  if (ws_bytes < render_bwd_workspace(n, k, d.tiles_x * d.tiles_y, deterministic) || (!ws && ws_bytes > 0))
+  if (schedule != GS_SCHEDULE_PLAIN && schedule != GS_SCHEDULE_BALANCED)
+    return fail(GS_ERR_INVALID_ARG, "gs_render_bwd: unknown schedule");
+  if (ws_bytes < render_bwd_workspace(n, k, d.tiles_x * d.tiles_y, deterministic) || !ws)
     return fail(GS_ERR_INVALID_ARG, "gs_render_bwd: workspace too small");
   if (n == 0) return GS_OK;
   return launch_render_bwd(n, *proj, point_list, ranges, k, d, final_T, n_contrib, t_ckpt, dL_dimage, g2d, ws,
-                           ws_bytes, deterministic, static_cast<hipStream_t>(stream));
+                           ws_bytes, deterministic, schedule, static_cast<hipStream_t>(stream));
 }
 
 gs_status gs_project_bwd_workspace(const gs_gaussians* g, size_t* bytes) {

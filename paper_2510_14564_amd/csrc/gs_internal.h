@@ -41,9 +41,12 @@ gs_status validate_camera(const gs_camera* cam);
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// Floats of the transmittance checkpoint buffer for K entries over `ntiles` tiles.
+// Transmittance checkpoint buffer for K entries over `ntiles` tiles: the
+// checkpoints, then the forward's tile plan, then each tile's work count
+// (largest n_contrib of its pixels), which the backward plans from.
+inline size_t ckpt_core_floats(int64_t k, int64_t ntiles) { return static_cast<size_t>(k / 256 + ntiles + 1) * 256; }
 inline size_t ckpt_floats(int64_t k, int64_t ntiles) {
-  return static_cast<size_t>(k / 256 + ntiles + 1) * 256;
+  return ckpt_core_floats(k, ntiles) + 16 + 4 * static_cast<size_t>(ntiles) + static_cast<size_t>(ntiles);
 }
 
 // Aligned carve-out of a caller-supplied workspace.
@@ -104,21 +107,25 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
 // Launchers implemented in the kernel translation units.
 namespace gs {
 gs_status launch_project(const gs_gaussians& g, const DevCam& cam, gs_projected& out, hipStream_t s);
+constexpr int kPlanHeader = 16;
+size_t plan_ints(int ntiles);
+gs_status launch_tile_plan(int ntiles, const uint32_t* ranges, const uint32_t* counts, float heavy_factor,
+                           int light_max, int32_t* plan, hipStream_t s);
 gs_status launch_project_bwd(const gs_gaussians& g, const DevCam& cam, const int* radius, const float* g2d,
                              gs_gaussians_grad& grad, void* ws, hipStream_t s);
 size_t binsort_workspace(int64_t n, int64_t capacity, int ntiles);
 gs_status run_bin_sort(int64_t n, const gs_projected& proj, const DevCam& cam, void* ws, size_t ws_bytes,
                        uint32_t* point_list, int64_t capacity, uint32_t* ranges, int64_t* k_out, hipStream_t s);
-gs_status launch_render_fwd(const gs_projected& proj, const uint32_t* point_list, const uint32_t* ranges,
+gs_status launch_render_fwd(const gs_projected& proj, const uint32_t* point_list, const uint32_t* ranges, int64_t k,
                             const DevCam& cam, float* image, float* final_T, uint32_t* n_contrib, float* t_ckpt,
-                            hipStream_t s);
+                            int schedule, hipStream_t s);
 gs_status launch_render_count(const gs_projected& proj, const uint32_t* point_list, const uint32_t* ranges,
                               const DevCam& cam, unsigned long long* counts, hipStream_t s);
 size_t render_bwd_workspace(int64_t n, int64_t k, int ntiles, int deterministic);
 gs_status launch_render_bwd(int64_t n, const gs_projected& proj, const uint32_t* point_list, const uint32_t* ranges,
                             int64_t k, const DevCam& cam, const float* final_T,
                             const uint32_t* n_contrib, const float* t_ckpt, const float* dL_dimage, float* g2d, void* ws,
-                            size_t ws_bytes, int deterministic, hipStream_t s);
+                            size_t ws_bytes, int deterministic, int schedule, hipStream_t s);
 gs_status launch_mlp_pack(const uint16_t* params, void* packed, hipStream_t s);
 gs_status launch_mlp_fwd(int64_t S, int per, const uint16_t* latents, const float* dirs, const void* packed,
                          float* rgb, hipStream_t s);

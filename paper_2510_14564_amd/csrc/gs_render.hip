@@ -81,6 +81,21 @@ __device__ __forceinline__ uint32_t uniform(uint32_t x) {
 }
 constexpr int kListStride = kBatch + 4; // per-wave list of staged slots, padded to kUnroll
 
+// Work-split threshold: a tile is heavy when its work count exceeds this
+// multiple of the mean count over all tiles (tuned by measurement).
+constexpr float kHeavyFactor = 4.0f;
+
+// Tile of workgroup `bid`.  Plain form: XCD-aware spatial map.  With a plan
+// (balanced form): heavy tiles first, largest first, one per workgroup in
+// dispatch order (so they spread over the XCDs and start at once), then the
+// others through the XCD-aware map of their own sequence.
+__device__ __forceinline__ int tile_of_block(const int32_t* __restrict__ plan, int bid, int ntiles) {
+  if (!plan) return xcd_remap(bid, ntiles);
+  const int H = plan[0];
+  const int32_t* order = plan + kPlanHeader;
+  return bid < H ? order[bid] : order[H + xcd_remap(bid - H, ntiles - H)];
+}
+
 // Shared per-batch staging: records (pre-scaled conic), colour + quadrant mask,
 // and each wave's list of the staged slots it must visit, in list order and
 // padded with the null slot to a multiple of kUnroll.
@@ -144,9 +159,12 @@ __global__ __launch_bounds__(256) void k_render_fwd(const uint2* __restrict__ ra
                                                     const float4* __restrict__ rec, DevCam cam,
                                                     float* __restrict__ image, float* __restrict__ final_T,
                                                     uint32_t* __restrict__ n_contrib, float* __restrict__ t_ckpt,
-                                                    unsigned long long* __restrict__ counts) {
+                                                    unsigned long long* __restrict__ counts,
+                                                    const int32_t* __restrict__ plan,
+                                                    uint32_t* __restrict__ tile_work) {
   __shared__ Stage st;
-  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  __shared__ uint32_t s_work;
+  const int tile = tile_of_block(plan, blockIdx.x, gridDim.x);
   const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
   int lx, ly;
   tile_pixel(threadIdx.x, lx, ly);
@@ -160,6 +178,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(const uint2* __restrict__ ra
     st.p[kNull] = make_float4(0.f, 0.f, 0.f, 0.f);
     st.q[kNull] = make_float4(0.f, 0.f, 0.f, 0.f);
     st.c[kNull] = make_float2(0.f, 0.f);
+    s_work = 0;
   }
 
   float T = 1.0f, acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
@@ -230,15 +249,36 @@ __global__ __launch_bounds__(256) void k_render_fwd(const uint2* __restrict__ ra
     final_T[pix] = T;
     n_contrib[pix] = contrib;
   }
+  if (tile_work) {
+    // the tile's backward work count: the largest n_contrib of its pixels
+    uint32_t mx = contrib;
+    for (int o = 32; o > 0; o >>= 1) mx = max(mx, static_cast<uint32_t>(__shfl_xor(static_cast<int>(mx), o, 64)));
+    if ((threadIdx.x & 63) == 0 && mx) atomicMax(&s_work, mx);
+    __syncthreads();
+    if (threadIdx.x == 0) tile_work[tile] = s_work;
+  }
 }
 
-gs_status launch_render_fwd(const gs_projected& proj, const uint32_t* point_list, const uint32_t* ranges,
+gs_status launch_render_fwd(const gs_projected& proj, const uint32_t* point_list, const uint32_t* ranges, int64_t k,
                             const DevCam& cam, float* image, float* final_T, uint32_t* n_contrib, float* t_ckpt,
-                            hipStream_t s) {
+                            int schedule, hipStream_t s) {
   const int ntiles = cam.tiles_x * cam.tiles_y;
+  int32_t* plan = nullptr;
+  uint32_t* tile_work = nullptr;
+  if (t_ckpt) {
+    float* tail = t_ckpt + ckpt_core_floats(k, ntiles);
+    plan = reinterpret_cast<int32_t*>(tail);
+    tile_work = reinterpret_cast<uint32_t*>(tail + plan_ints(ntiles));
+    if (schedule == 1) {
+      gs_status st = launch_tile_plan(ntiles, ranges, nullptr, kHeavyFactor, 0, plan, s);
+      if (st != GS_OK) return st;
+    } else {
+      plan = nullptr;
+    }
+  }
   k_render_fwd<false><<<ntiles, 256, 0, s>>>(reinterpret_cast<const uint2*>(ranges), point_list,
                                              reinterpret_cast<const float4*>(proj.records), cam, image, final_T,
-                                             n_contrib, t_ckpt, nullptr);
+                                             n_contrib, t_ckpt, nullptr, plan, tile_work);
   return check_launch("k_render_fwd");
 }
 
@@ -249,7 +289,7 @@ gs_status launch_render_count(const gs_projected& proj, const uint32_t* point_li
   if (st != GS_OK) return st;
   k_render_fwd<true><<<ntiles, 256, 0, s>>>(reinterpret_cast<const uint2*>(ranges), point_list,
                                             reinterpret_cast<const float4*>(proj.records), cam, nullptr, nullptr,
-                                            nullptr, nullptr, counts);
+                                            nullptr, nullptr, counts, nullptr, nullptr);
   return check_launch("k_render_count");
 }
 
@@ -323,10 +363,10 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
                                                     const uint32_t* __restrict__ n_contrib,
                                                     const float* __restrict__ t_ckpt,
                                                     const float* __restrict__ dL_dimage, int n,
-                                                    float* __restrict__ g2d) {
+                                                    float* __restrict__ g2d, const int32_t* __restrict__ plan) {
   __shared__ Stage st;
   __shared__ uint32_t s_max;
-  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int tile = tile_of_block(plan, blockIdx.x, gridDim.x);
   const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
   int lx, ly;
   tile_pixel(threadIdx.x, lx, ly);
@@ -422,23 +462,32 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
 }
 
 size_t render_bwd_workspace(int64_t n, int64_t k, int ntiles, int deterministic) {
-  (void)n; (void)k; (void)ntiles; (void)deterministic;
-  return 256;
+  (void)n; (void)k; (void)deterministic;
+  return 256 + sizeof(int32_t) * plan_ints(ntiles);
 }
 
 gs_status launch_render_bwd(int64_t n, const gs_projected& proj, const uint32_t* point_list, const uint32_t* ranges,
                             int64_t k, const DevCam& cam, const float* final_T,
                             const uint32_t* n_contrib, const float* t_ckpt, const float* dL_dimage, float* g2d, void* ws,
-                            size_t ws_bytes, int deterministic, hipStream_t s) {
-  (void)k; (void)ws; (void)ws_bytes;
+                            size_t ws_bytes, int deterministic, int schedule, hipStream_t s) {
+  (void)ws_bytes;
   if (deterministic) return fail(GS_ERR_UNSUPPORTED, "gs_render_bwd: deterministic reduction not built yet");
   gs_status st = check_hip(hipMemsetAsync(g2d, 0, sizeof(float) * GS_G2D * static_cast<size_t>(n), s),
                            "hipMemsetAsync(g2d)");
   if (st != GS_OK) return st;
   const int ntiles = cam.tiles_x * cam.tiles_y;
+  int32_t* plan = nullptr;
+  if (schedule == 1) {
+    // plan from the forward's per-tile work counts (largest n_contrib)
+    const float* tail = t_ckpt + ckpt_core_floats(k, ntiles);
+    const uint32_t* tile_work = reinterpret_cast<const uint32_t*>(tail + plan_ints(ntiles));
+    plan = reinterpret_cast<int32_t*>(static_cast<char*>(ws) + 256);
+    st = launch_tile_plan(ntiles, ranges, tile_work, kHeavyFactor, 0, plan, s);
+    if (st != GS_OK) return st;
+  }
   k_render_bwd<<<ntiles, 256, 0, s>>>(reinterpret_cast<const uint2*>(ranges), point_list,
                                       reinterpret_cast<const float4*>(proj.records), cam, final_T, n_contrib,
-                                      t_ckpt, dL_dimage, static_cast<int>(n), g2d);
+                                      t_ckpt, dL_dimage, static_cast<int>(n), g2d, plan);
   return check_launch("k_render_bwd");
 }
 

@@ -28,6 +28,7 @@ L1_PARTIALS = 1024
 MLP_PARAMS = 6467
 MLP_PACKED_BYTES = 31244
 
+SCHEDULE_PLAIN, SCHEDULE_BALANCED = 0, 1
 GS_OK, GS_ERR_INVALID_ARG, GS_ERR_CAPACITY, GS_ERR_HIP, GS_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
 STATUS_NAMES = {0: "GS_OK", -1: "GS_ERR_INVALID_ARG", -2: "GS_ERR_CAPACITY", -3: "GS_ERR_HIP",
                 -4: "GS_ERR_UNSUPPORTED"}
@@ -78,12 +79,13 @@ _sigs = {
     "gs_project": ([_P(Gaussians), _P(Camera), _P(Projected), _vp], ctypes.c_int),
     "gs_bin_sort_workspace": ([_i64, _i64, _P(Camera), _P(_sz)], ctypes.c_int),
     "gs_bin_sort": ([_i64, _P(Projected), _P(Camera), _vp, _sz, _vp, _i64, _vp, _P(_i64), _vp], ctypes.c_int),
-    "gs_render_fwd": ([_i64, _P(Projected), _vp, _vp, _i64, _P(Camera), _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "gs_render_fwd": ([_i64, _P(Projected), _vp, _vp, _i64, _P(Camera), _vp, _vp, _vp, _vp, _i32, _vp],
+                      ctypes.c_int),
     "gs_render_ckpt_floats": ([_i64, _P(Camera), _P(_sz)], ctypes.c_int),
     "gs_render_count": ([_i64, _P(Projected), _vp, _vp, _i64, _P(Camera), _vp, _vp], ctypes.c_int),
     "gs_render_bwd_workspace": ([_i64, _i64, _P(Camera), _i32, _P(_sz)], ctypes.c_int),
     "gs_render_bwd": ([_i64, _P(Projected), _vp, _vp, _i64, _P(Camera), _vp, _vp, _vp, _vp, _vp, _vp, _sz, _i32,
-                       _vp], ctypes.c_int),
+                       _i32, _vp], ctypes.c_int),
     "gs_project_bwd_workspace": ([_P(Gaussians), _P(_sz)], ctypes.c_int),
     "gs_project_bwd": ([_P(Gaussians), _P(Camera), _P(Projected), _vp, _P(GaussiansGrad), _vp, _sz, _vp],
                        ctypes.c_int),
@@ -211,10 +213,13 @@ def bin_sort(n: int, proj: ProjectedBuffers, cam: Camera, ws, point_list, ranges
 
 
 def render_fwd(n: int, proj: ProjectedBuffers, point_list, ranges, k: int, cam: Camera, image, final_T, n_contrib,
-               t_ckpt=None, stream=None):
+               t_ckpt=None, schedule=None, stream=None):
+    """schedule: SCHEDULE_BALANCED when t_ckpt is given, else SCHEDULE_PLAIN, unless set."""
+    if schedule is None:
+        schedule = SCHEDULE_BALANCED if t_ckpt is not None else SCHEDULE_PLAIN
     _check(_lib.gs_render_fwd(n, ctypes.byref(proj.struct()), _ptr(point_list), _ptr(ranges), k, ctypes.byref(cam),
-                              _ptr(image), _ptr(final_T), _ptr(n_contrib), _ptr(t_ckpt), _stream(stream)),
-           "gs_render_fwd")
+                              _ptr(image), _ptr(final_T), _ptr(n_contrib), _ptr(t_ckpt), int(schedule),
+                              _stream(stream)), "gs_render_fwd")
 
 
 def render_count(n: int, proj: ProjectedBuffers, point_list, ranges, k: int, cam: Camera, counts, stream=None):
@@ -237,10 +242,11 @@ def render_bwd_workspace(n: int, k: int, cam: Camera, deterministic: bool) -> in
 
 
 def render_bwd(n: int, proj: ProjectedBuffers, point_list, ranges, k: int, cam: Camera, final_T, n_contrib, t_ckpt,
-               dL_dimage, g2d, ws, deterministic: bool = False, stream=None):
+               dL_dimage, g2d, ws, deterministic: bool = False, schedule=SCHEDULE_BALANCED, stream=None):
     _check(_lib.gs_render_bwd(n, ctypes.byref(proj.struct()), _ptr(point_list), _ptr(ranges), k, ctypes.byref(cam),
                               _ptr(final_T), _ptr(n_contrib), _ptr(t_ckpt), _ptr(dL_dimage), _ptr(g2d), _ptr(ws),
-                              ws.numel() * ws.element_size(), int(deterministic), _stream(stream)), "gs_render_bwd")
+                              ws.numel() * ws.element_size(), int(deterministic), int(schedule), _stream(stream)),
+           "gs_render_bwd")
 
 
 def project_bwd_workspace(gauss: Gaussians) -> int:

@@ -37,8 +37,10 @@ class FrameState:
 class Rasterizer:
     """Holds device buffers for one camera resolution and one Gaussian count."""
 
-    def __init__(self, cam, sh_degree: int, device="cuda", deterministic: bool = False, capacity: int | None = None):
+    def __init__(self, cam, sh_degree: int, device="cuda", deterministic: bool = False, capacity: int | None = None,
+                 schedule: int = gs.SCHEDULE_BALANCED):
         self.cam = cam
+        self.schedule = schedule
         self.cs = gs.camera_struct(cam)
         self.sh_degree = sh_degree
         self.device = torch.device(device)
@@ -108,7 +110,7 @@ class Rasterizer:
             self.t_ckpt = torch.empty(int(need * 1.25), dtype=torch.float32, device=self.device)
         with self._stage("render_fwd"):
             gs.render_fwd(n, self.proj, self.point_list, self.ranges, k, self.cs, self.image, self.final_T,
-                          self.n_contrib, self.t_ckpt)
+                          self.n_contrib, self.t_ckpt, schedule=self.schedule)
         return FrameState(n, k, self.proj, self.point_list, self.ranges, self.image, self.final_T, self.n_contrib,
                           self.t_ckpt)
 
@@ -122,7 +124,7 @@ class Rasterizer:
             g2d = torch.empty((gs.G2D, n), dtype=torch.float32, device=self.device)
         with self._stage("render_bwd"):
             gs.render_bwd(n, st.proj, st.point_list, st.ranges, st.k, self.cs, st.final_T, st.n_contrib, st.t_ckpt,
-                          dL_dimage, g2d, self.bwd_ws, self.deterministic)
+                          dL_dimage, g2d, self.bwd_ws, self.deterministic, schedule=self.schedule)
         grads = {k: torch.empty_like(v) for k, v in
                  (("means", means), ("log_scales", log_scales), ("quats", quats), ("logits", logits))}
         g = self._gauss(means, log_scales, quats, logits, colour)

@@ -79,23 +79,23 @@ def gpu_bin_sort(gs, n, out, cam, capacity=None):
     return k, pl, ranges
 
 
-def gpu_render(gs, n, out, pl, ranges, k, cam):
+def gpu_render(gs, n, out, pl, ranges, k, cam, schedule=1):
     cs = gs.camera_struct(cam)
     H, W = cam.height, cam.width
     image = torch.empty((3, H, W), dtype=torch.float32, device=DEV)
     fT = torch.empty((H, W), dtype=torch.float32, device=DEV)
     nc = torch.empty((H, W), dtype=torch.int32, device=DEV)
     ck = torch.empty(gs.render_ckpt_floats(k, cs), dtype=torch.float32, device=DEV)
-    gs.render_fwd(n, out, pl, ranges, k, cs, image, fT, nc, ck)
+    gs.render_fwd(n, out, pl, ranges, k, cs, image, fT, nc, ck, schedule=schedule)
     torch.cuda.synchronize()
     return image, fT, nc, ck
 
 
-def gpu_render_bwd(gs, n, out, pl, ranges, k, cam, fT, nc, ck, G, deterministic=False):
+def gpu_render_bwd(gs, n, out, pl, ranges, k, cam, fT, nc, ck, G, deterministic=False, schedule=1):
     cs = gs.camera_struct(cam)
     g2d = torch.empty((gs.G2D, n), dtype=torch.float32, device=DEV)
     ws = torch.empty(max(gs.render_bwd_workspace(n, k, cs, deterministic), 1), dtype=torch.uint8, device=DEV)
-    gs.render_bwd(n, out, pl, ranges, k, cs, fT, nc, ck, G, g2d, ws, deterministic)
+    gs.render_bwd(n, out, pl, ranges, k, cs, fT, nc, ck, G, g2d, ws, deterministic, schedule=schedule)
     torch.cuda.synchronize()
     return g2d
 

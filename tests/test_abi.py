@@ -115,11 +115,17 @@ def test_bin_sort_rejects_small_workspace_and_bad_alignment(gs):
 def test_render_calls_reject_nulls(gs):
     c = _cam(gs)
     st = gs._lib.gs_render_fwd(10, ctypes.byref(_proj(gs)), NULL, NULL, 5, ctypes.byref(c), NULL, NULL, NULL, NULL,
-                               NULL)
+                               0, NULL)
     assert st == gs.GS_ERR_INVALID_ARG
     st = gs._lib.gs_render_bwd(10, ctypes.byref(_proj(gs)), NULL, NULL, 5, ctypes.byref(c), NULL, NULL, NULL,
-                               NULL, NULL, NULL, 0, 0, NULL)
+                               NULL, NULL, NULL, 0, 0, 0, NULL)
     assert st == gs.GS_ERR_INVALID_ARG
+    # an unknown schedule, and the balanced schedule without its plan storage
+    p = ctypes.c_void_p(0x1000)
+    for sched, ck in ((2, p), (-1, p), (gs.SCHEDULE_BALANCED, NULL)):
+        st = gs._lib.gs_render_fwd(10, ctypes.byref(_proj(gs)), p, p, 5, ctypes.byref(c), p, p, p, ck, sched, NULL)
+        assert st == gs.GS_ERR_INVALID_ARG, sched
+        assert "schedule" in gs.last_error()
     assert gs._lib.gs_l1_loss(NULL, NULL, 0, NULL, NULL, NULL, NULL) == gs.GS_ERR_INVALID_ARG
 
 
