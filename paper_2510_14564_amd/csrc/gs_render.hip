@@ -89,11 +89,49 @@ constexpr float kHeavyFactor = 4.0f;
 // (balanced form): heavy tiles first, largest first, one per workgroup in
 // dispatch order (so they spread over the XCDs and start at once), then the
 // others through the XCD-aware map of their own sequence.
+// Light tiles (no more than kLightMax entries to walk) go to the merged
+// kernels instead; -1 = nothing for this workgroup.
 __device__ __forceinline__ int tile_of_block(const int32_t* __restrict__ plan, int bid, int ntiles) {
   if (!plan) return xcd_remap(bid, ntiles);
-  const int H = plan[0];
+  const int H = plan[0], M = plan[1];
   const int32_t* order = plan + kPlanHeader;
-  return bid < H ? order[bid] : order[H + xcd_remap(bid - H, ntiles - H)];
+  if (bid < H) return order[bid];
+  return bid < H + M ? order[H + xcd_remap(bid - H, M)] : -1;
+}
+
+constexpr int kLightMax = 64;
+
+// Per-wave staging of a light tile's entries (one batch of at most 64).
+struct LightStage {
+  float4 p[kLightMax];
+  float4 q[kLightMax];
+  float2 c[kLightMax];                  // blue, quadrant mask bits
+  uint32_t gid[kLightMax];
+};
+
+// Light tile of wave `wave` of workgroup `bid`, or -1.
+__device__ __forceinline__ int light_tile(const int32_t* __restrict__ plan, int bid, int wave) {
+  const int H = plan[0], M = plan[1], L = plan[2];
+  const int i = bid * 4 + wave;
+  return i < L ? plan[kPlanHeader + H + M + i] : -1;
+}
+
+__device__ __forceinline__ void stage_light(LightStage& ls, const float4* __restrict__ rec,
+                                            const uint32_t* __restrict__ point_list, uint32_t first, int cnt,
+                                            float x0, float y0, int lane) {
+  if (lane < cnt) {
+    const uint32_t gid = point_list[first + lane];
+    const float4 r0 = rec[3 * gid];
+    const float4 r1 = rec[3 * gid + 1];
+    const float4 r2 = rec[3 * gid + 2];
+    ls.p[lane] = make_float4(r0.x, r0.y, -0.5f * kLog2e * r0.z, -kLog2e * r0.w);
+    ls.q[lane] = make_float4(-0.5f * kLog2e * r1.x, r1.y, r1.z, r1.w);
+    ls.c[lane] = make_float2(r2.x, __uint_as_float(quad_mask(r0, r2, x0, y0)));
+    ls.gid[lane] = gid;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Shared per-batch staging: records (pre-scaled conic), colour + quadrant mask,
@@ -150,6 +188,29 @@ __device__ __forceinline__ void build_list(Stage& st, int cnt, bool all) {
 
 // ------------------------------------------------------------------- forward
 
+// One (pixel, entry) step of the front-to-back walk; m1 = 1 + the entry's
+// position in the tile list.  Shared by every work-split form so that they
+// produce the same bits.  Returns whether the entry was blended.
+__device__ __forceinline__ bool fwd_pair(const float4& p, const float4& q, float cb, float px, float py, uint32_t m1,
+                                         float& T, float& acc0, float& acc1, float& acc2, uint32_t& contrib,
+                                         bool& done) {
+  float dx, dy, p2, eg, og;
+  eval_pair(p, q, px, py, dx, dy, p2, eg, og);
+  const float alpha = fminf(kAlphaMax, og);
+  const bool ok = !done && (p2 <= 0.0f) && (alpha >= kAlphaMin);
+  const float Tn = T * (1.0f - alpha);
+  const bool stop = ok && (Tn < kTMin);
+  const bool blend = ok && !stop;
+  const float w = blend ? alpha * T : 0.0f;
+  acc0 = fmaf(q.z, w, acc0);
+  acc1 = fmaf(q.w, w, acc1);
+  acc2 = fmaf(cb, w, acc2);
+  T = blend ? Tn : T;
+  contrib = blend ? m1 : contrib;
+  done = done || stop;
+  return blend;
+}
+
 // COUNT = true runs the same decisions on every entry (no culling) but only
 // counts, per pixel, the pairs examined (alpha evaluated before the walk ends)
 // and the pairs blended, and adds them to counts[0], counts[1].
@@ -165,6 +226,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(const uint2* __restrict__ ra
   __shared__ Stage st;
   __shared__ uint32_t s_work;
   const int tile = tile_of_block(plan, blockIdx.x, gridDim.x);
+  if (tile < 0) return;
   const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
   int lx, ly;
   tile_pixel(threadIdx.x, lx, ly);
@@ -203,27 +265,9 @@ __global__ __launch_bounds__(256) void k_render_fwd(const uint2* __restrict__ ra
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
         const uint32_t j = js[u];
-        const float4 p = st.p[j];
-        const float4 q = st.q[j];
-        const float cb = st.c[j].x;
-        float dx, dy, p2, eg, og;
-        eval_pair(p, q, px, py, dx, dy, p2, eg, og);
-        const float alpha = fminf(kAlphaMax, og);
-        const bool ok = !done && (p2 <= 0.0f) && (alpha >= kAlphaMin);
-        const float Tn = T * (1.0f - alpha);
-        const bool stop = ok && (Tn < kTMin);
-        const bool blend = ok && !stop;
-        const float w = blend ? alpha * T : 0.0f;
-        acc0 = fmaf(q.z, w, acc0);
-        acc1 = fmaf(q.w, w, acc1);
-        acc2 = fmaf(cb, w, acc2);
-        T = blend ? Tn : T;
-        contrib = blend ? (m0 + j) : contrib;
-        if (COUNT) {
-          n_exam += (!done && j != kNull) ? 1u : 0u;
-          n_blend += blend ? 1u : 0u;
-        }
-        done = done || stop;
+        if (COUNT) n_exam += (!done && j != kNull) ? 1u : 0u;
+        const bool blend = fwd_pair(st.p[j], st.q[j], st.c[j].x, px, py, m0 + j, T, acc0, acc1, acc2, contrib, done);
+        if (COUNT) n_blend += blend ? 1u : 0u;
       }
     }
   }
@@ -259,6 +303,71 @@ __global__ __launch_bounds__(256) void k_render_fwd(const uint2* __restrict__ ra
   }
 }
 
+
+// Forward of light tiles, merged four to a workgroup: one wave per tile, each
+// lane four pixels (the same lane position in each 8x8 quadrant).  The
+// entries of a pixel's quadrant are visited in list order through the same
+// fwd_pair as the one-workgroup-per-tile form, so the outputs are identical.
+__global__ __launch_bounds__(256) void k_render_fwd_light(const uint2* __restrict__ ranges,
+                                                          const uint32_t* __restrict__ point_list,
+                                                          const float4* __restrict__ rec, DevCam cam,
+                                                          float* __restrict__ image, float* __restrict__ final_T,
+                                                          uint32_t* __restrict__ n_contrib,
+                                                          const int32_t* __restrict__ plan,
+                                                          uint32_t* __restrict__ tile_work) {
+  __shared__ LightStage stage[4];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int tile = light_tile(plan, blockIdx.x, wave);
+  if (tile < 0) return;
+  LightStage& ls = stage[wave];
+  const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
+  const float x0 = static_cast<float>(tx * kTile), y0 = static_cast<float>(ty * kTile);
+  const uint2 rg = ranges[tile];
+  const int cnt = static_cast<int>(min(rg.y - rg.x, static_cast<uint32_t>(kLightMax)));
+  stage_light(ls, rec, point_list, rg.x, cnt, x0, y0, lane);
+  float T[4], a0[4], a1[4], a2[4], px[4], py[4];
+  uint32_t con[4];
+  bool done[4];
+  int pxi[4], pyi[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    pxi[k] = tx * kTile + ((k & 1) << 3) + (lane & 7);
+    pyi[k] = ty * kTile + ((k >> 1) << 3) + (lane >> 3);
+    px[k] = static_cast<float>(pxi[k]) + 0.5f;
+    py[k] = static_cast<float>(pyi[k]) + 0.5f;
+    T[k] = 1.0f; a0[k] = a1[k] = a2[k] = 0.0f; con[k] = 0;
+    done[k] = !(pxi[k] < cam.width && pyi[k] < cam.height);
+  }
+  for (int j = 0; j < cnt; ++j) {
+    const uint32_t mask = uniform(__float_as_uint(ls.c[j].y));
+    if (mask == 0) continue;
+    if (__ballot(!(done[0] && done[1] && done[2] && done[3])) == 0) break;
+    const float4 p = ls.p[j];
+    const float4 q = ls.q[j];
+    const float cb = ls.c[j].x;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if ((mask >> k) & 1u) fwd_pair(p, q, cb, px[k], py[k], static_cast<uint32_t>(j) + 1u, T[k], a0[k], a1[k], a2[k],
+                                      con[k], done[k]);
+  }
+  const int64_t HW = static_cast<int64_t>(cam.width) * cam.height;
+  uint32_t mx = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    mx = max(mx, con[k]);
+    if (pxi[k] < cam.width && pyi[k] < cam.height) {
+      const int64_t pix = static_cast<int64_t>(pyi[k]) * cam.width + pxi[k];
+      image[pix] = fmaf(T[k], cam.bg[0], a0[k]);
+      image[HW + pix] = fmaf(T[k], cam.bg[1], a1[k]);
+      image[2 * HW + pix] = fmaf(T[k], cam.bg[2], a2[k]);
+      final_T[pix] = T[k];
+      n_contrib[pix] = con[k];
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) mx = max(mx, static_cast<uint32_t>(__shfl_xor(static_cast<int>(mx), o, 64)));
+  if (lane == 0) tile_work[tile] = mx;
+}
+
 gs_status launch_render_fwd(const gs_projected& proj, const uint32_t* point_list, const uint32_t* ranges, int64_t k,
                             const DevCam& cam, float* image, float* final_T, uint32_t* n_contrib, float* t_ckpt,
                             int schedule, hipStream_t s) {
@@ -270,7 +379,12 @@ gs_status launch_render_fwd(const gs_projected& proj, const uint32_t* point_list
     plan = reinterpret_cast<int32_t*>(tail);
     tile_work = reinterpret_cast<uint32_t*>(tail + plan_ints(ntiles));
     if (schedule == 1) {
-      gs_status st = launch_tile_plan(ntiles, ranges, nullptr, kHeavyFactor, 0, plan, s);
+      gs_status st = launch_tile_plan(ntiles, ranges, nullptr, kHeavyFactor, kLightMax, plan, s);
+      if (st != GS_OK) return st;
+      k_render_fwd_light<<<static_cast<unsigned>(ceil_div(ntiles, 4)), 256, 0, s>>>(
+          reinterpret_cast<const uint2*>(ranges), point_list, reinterpret_cast<const float4*>(proj.records), cam,
+          image, final_T, n_contrib, plan, tile_work);
+      st = check_launch("k_render_fwd_light");
       if (st != GS_OK) return st;
     } else {
       plan = nullptr;
@@ -342,6 +456,44 @@ __device__ __forceinline__ float wave_sum8(const float v[8], bool lo8) {
   return c;
 }
 
+// Gradient terms of one (pixel, entry) pair of the back-to-front walk, after
+// the alpha evaluation: recovers T before the entry, updates the light behind
+// (as G.S) and writes the nine per-pair terms (all zero when !ok).
+__device__ __forceinline__ void bwd_terms(const float4& p, const float4& q, float cb, bool ok, float dx, float dy,
+                                          float alpha, float eg, float og, float G0, float G1, float G2, float& T,
+                                          float& GS, float v[9]) {
+  // hardware reciprocal (1 ulp): T is re-anchored every 256 entries, so its
+  // rounding stays far below the tolerance of the recovered transmittance
+  const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
+  const float Tm = ok ? T * inv : T;
+  const float Gc = G0 * q.z + G1 * q.w + G2 * cb;
+  const float dalpha = Tm * Gc - inv * GS;
+  const float w = ok ? alpha * Tm : 0.0f;
+  GS = fmaf(w, Gc, GS);
+  T = Tm;
+  const bool unclamped = og < kAlphaMax;
+  // dL/dpower (natural-log power) and dL/do = e^power dL/dalpha
+  const float dpow = (ok && unclamped) ? alpha * dalpha : 0.0f;
+  const float dop = (ok && unclamped) ? eg * dalpha : 0.0f;
+  // (nkx, nky) = log2(e) * (-K d) with K the conic and d = (dx, dy).  The
+  // pair's conic gradient -1/2 dpow d d^T is carried to Sigma' = K^-1 right
+  // here, -K (.) K = 1/2 dpow (K d)(K d)^T, before any summation: converting
+  // the summed conic gradient cancels badly for elongated footprints.
+  const float nkx = fmaf(p.z + p.z, dx, p.w * dy);
+  const float nky = fmaf(q.x + q.x, dy, p.w * dx);
+  const float dq = dpow * kLn2;              // undoes the log2(e) scale once
+  const float hx = (0.5f * kLn2) * dq * nkx; // ... and twice for the products
+  v[0] = dq * nkx;                           // dL/du
+  v[1] = dq * nky;                           // dL/dv
+  v[2] = hx * nkx;                           // dL/dSigma'_xx
+  v[3] = (hx + hx) * nky;                    // dL/dSigma'_xy (both entries)
+  v[4] = (0.5f * kLn2) * dq * nky * nky;     // dL/dSigma'_yy
+  v[5] = dop;                                // dL/dopacity
+  v[6] = G0 * w;                             // dL/dr
+  v[7] = G1 * w;                             // dL/dg
+  v[8] = G2 * w;                             // dL/db
+}
+
 // Per (pixel, entry) derivative, walked back to front.  Starting from the light
 // S = T_f bg behind the last entry, each blended entry m (going backwards)
 // recovers T_m = T_{m+1} / (1 - alpha_m) and uses the light behind it,
@@ -367,6 +519,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
   __shared__ Stage st;
   __shared__ uint32_t s_max;
   const int tile = tile_of_block(plan, blockIdx.x, gridDim.x);
+  if (tile < 0) return;
   const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
   int lx, ly;
   tile_pixel(threadIdx.x, lx, ly);
@@ -423,41 +576,90 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
       const float alpha = fminf(kAlphaMax, og);
       const bool ok = (m < ncon) && (p2 <= 0.0f) && (alpha >= kAlphaMin);
       if (__ballot(ok) == 0) continue;
-      // hardware reciprocal (1 ulp): T is re-anchored every 256 entries, so its
-      // rounding stays far below the tolerance of the recovered transmittance
-      const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
-      const float Tm = ok ? T * inv : T;
-      const float Gc = G0 * q.z + G1 * q.w + G2 * cb;
-      const float dalpha = Tm * Gc - inv * GS;
-      const float w = ok ? alpha * Tm : 0.0f;
-      GS = fmaf(w, Gc, GS);
-      T = Tm;
-      const bool unclamped = og < kAlphaMax;
-      // dL/dpower (natural-log power) and dL/do = e^power dL/dalpha
-      const float dpow = (ok && unclamped) ? alpha * dalpha : 0.0f;
-      const float dop = (ok && unclamped) ? eg * dalpha : 0.0f;
-      // (nkx, nky) = log2(e) * (-K d) with K the conic and d = (dx, dy).  The
-      // pair's conic gradient -1/2 dpow d d^T is carried to Sigma' = K^-1
-      // right here, -K (.) K = 1/2 dpow (K d)(K d)^T, before any summation:
-      // converting the summed conic gradient cancels badly for elongated
-      // footprints.
-      const float nkx = fmaf(p.z + p.z, dx, p.w * dy);
-      const float nky = fmaf(q.x + q.x, dy, p.w * dx);
-      const float dq = dpow * kLn2;              // undoes the log2(e) scale once
-      const float hx = (0.5f * kLn2) * dq * nkx; // ... and twice for the products
-      float v[8];
-      v[0] = dq * nkx;                           // dL/du
-      v[1] = dq * nky;                           // dL/dv
-      v[2] = hx * nkx;                           // dL/dSigma'_xx
-      v[3] = (hx + hx) * nky;                    // dL/dSigma'_xy (both entries)
-      v[4] = (0.5f * kLn2) * dq * nky * nky;     // dL/dSigma'_yy
-      v[5] = dop;                                // dL/dopacity
-      v[6] = G0 * w;                             // dL/dr
-      v[7] = G1 * w;                             // dL/dg
+      float v[9];
+      bwd_terms(p, q, cb, ok, dx, dy, alpha, eg, og, G0, G1, G2, T, GS, v);
       const float red8 = wave_sum8(v, lo8);
-      const float red9 = wave_sum_to_lane63(G2 * w);  // dL/db
+      const float red9 = wave_sum_to_lane63(v[8]);  // dL/db
       if (writer) unsafeAtomicAdd(&g_out[st.gid[j]], lane == 63 ? red9 : red8);
     }
+  }
+}
+
+
+// Backward of light tiles (the largest n_contrib at most kLightMax): one wave
+// per tile, four pixels per lane as in the forward.  Each lane adds its four
+// pixels' terms before the wave sum, so one reduction and one set of atomics
+// serve 256 pixels.
+__global__ __launch_bounds__(256) void k_render_bwd_light(const uint2* __restrict__ ranges,
+                                                          const uint32_t* __restrict__ point_list,
+                                                          const float4* __restrict__ rec, DevCam cam,
+                                                          const float* __restrict__ final_T,
+                                                          const uint32_t* __restrict__ n_contrib,
+                                                          const float* __restrict__ dL_dimage, int n,
+                                                          float* __restrict__ g2d, const int32_t* __restrict__ plan) {
+  __shared__ LightStage stage[4];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int tile = light_tile(plan, blockIdx.x, wave);
+  if (tile < 0) return;
+  LightStage& ls = stage[wave];
+  const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
+  const float x0 = static_cast<float>(tx * kTile), y0 = static_cast<float>(ty * kTile);
+  const uint2 rg = ranges[tile];
+  const bool lo8 = (lane & 8) == 0;
+  const int out_slot = (lane == 63) ? 8 : kReduceSlot[((lane >> 4) << 1) | ((lane >> 3) & 1)];
+  const bool writer = ((lane & 7) == 0) || lane == 63;
+  float* const g_out = g2d + static_cast<int64_t>(out_slot) * n;
+  const int64_t HW = static_cast<int64_t>(cam.width) * cam.height;
+  float G0[4], G1[4], G2[4], T[4], GS[4], px[4], py[4];
+  uint32_t ncon[4];
+  uint32_t mx = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int xi = tx * kTile + ((k & 1) << 3) + (lane & 7);
+    const int yi = ty * kTile + ((k >> 1) << 3) + (lane >> 3);
+    px[k] = static_cast<float>(xi) + 0.5f;
+    py[k] = static_cast<float>(yi) + 0.5f;
+    G0[k] = G1[k] = G2[k] = 0.0f; T[k] = 1.0f; ncon[k] = 0;
+    if (xi < cam.width && yi < cam.height) {
+      const int64_t pix = static_cast<int64_t>(yi) * cam.width + xi;
+      G0[k] = dL_dimage[pix]; G1[k] = dL_dimage[HW + pix]; G2[k] = dL_dimage[2 * HW + pix];
+      T[k] = final_T[pix];
+      ncon[k] = n_contrib[pix];
+    }
+    GS[k] = T[k] * (G0[k] * cam.bg[0] + G1[k] * cam.bg[1] + G2[k] * cam.bg[2]);
+    mx = max(mx, ncon[k]);
+  }
+  for (int o = 32; o > 0; o >>= 1) mx = max(mx, static_cast<uint32_t>(__shfl_xor(static_cast<int>(mx), o, 64)));
+  const int len = static_cast<int>(min(min(rg.y - rg.x, mx), static_cast<uint32_t>(kLightMax)));
+  stage_light(ls, rec, point_list, rg.x, len, x0, y0, lane);
+  for (int j = len - 1; j >= 0; --j) {
+    const uint32_t mask = uniform(__float_as_uint(ls.c[j].y));
+    if (mask == 0) continue;
+    const uint32_t m = static_cast<uint32_t>(j);
+    const float4 p = ls.p[j];
+    const float4 q = ls.q[j];
+    const float cb = ls.c[j].x;
+    float vs[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) vs[t] = 0.0f;
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (!((mask >> k) & 1u)) continue;
+      float dx, dy, p2, eg, og;
+      eval_pair(p, q, px[k], py[k], dx, dy, p2, eg, og);
+      const float alpha = fminf(kAlphaMax, og);
+      const bool ok = (m < ncon[k]) && (p2 <= 0.0f) && (alpha >= kAlphaMin);
+      float v[9];
+      bwd_terms(p, q, cb, ok, dx, dy, alpha, eg, og, G0[k], G1[k], G2[k], T[k], GS[k], v);
+#pragma unroll
+      for (int t = 0; t < 9; ++t) vs[t] += v[t];
+      any = any || ok;
+    }
+    if (__ballot(any) == 0) continue;
+    const float red8 = wave_sum8(vs, lo8);
+    const float red9 = wave_sum_to_lane63(vs[8]);
+    if (writer) unsafeAtomicAdd(&g_out[ls.gid[j]], lane == 63 ? red9 : red8);
   }
 }
 
@@ -482,7 +684,12 @@ gs_status launch_render_bwd(int64_t n, const gs_projected& proj, const uint32_t*
     const float* tail = t_ckpt + ckpt_core_floats(k, ntiles);
     const uint32_t* tile_work = reinterpret_cast<const uint32_t*>(tail + plan_ints(ntiles));
     plan = reinterpret_cast<int32_t*>(static_cast<char*>(ws) + 256);
-    st = launch_tile_plan(ntiles, ranges, tile_work, kHeavyFactor, 0, plan, s);
+    st = launch_tile_plan(ntiles, ranges, tile_work, kHeavyFactor, kLightMax, plan, s);
+    if (st != GS_OK) return st;
+    k_render_bwd_light<<<static_cast<unsigned>(ceil_div(ntiles, 4)), 256, 0, s>>>(
+        reinterpret_cast<const uint2*>(ranges), point_list, reinterpret_cast<const float4*>(proj.records), cam,
+        final_T, n_contrib, dL_dimage, static_cast<int>(n), g2d, plan);
+    st = check_launch("k_render_bwd_light");
     if (st != GS_OK) return st;
   }
   k_render_bwd<<<ntiles, 256, 0, s>>>(reinterpret_cast<const uint2*>(ranges), point_list,
