@@ -240,8 +240,11 @@ gs_status gs_project_bwd(const gs_gaussians* g, const gs_camera* cam, const gs_p
  *   h1 = ReLU(W1 x + b1) (64), h2 = ReLU(W2 h1 + b2) (64), c = sigmoid(W3 h2 + b3).
  * Weights are BF16 (GS_MLP_PARAMS values, row-major, in the order W1[64][32],
  * b1[64], W2[64][64], b2[64], W3[3][64], b3[3]); products run on the BF16
- * matrix cores with FP32 accumulation; the SH encoding and hidden activations
- * are rounded to BF16 before each product. */
+ * matrix cores with FP32 accumulation; the SH encoding and the hidden
+ * activations enter them as a pair of BF16 values (hi + lo, about 2^-17
+ * relative), so colours match the BF16-weight definition to near FP32
+ * accuracy.  In the backward, gradients entering products and the activations
+ * of the weight-gradient products are single BF16 values. */
 #define GS_MLP_PACKED_BYTES 31244
 
 /* Lay the BF16 parameters out as the matrix-core operand image used by every

@@ -5,7 +5,9 @@
 // Per sample, x = [z (16 latent values); Y_0..15(d)] (the real SH encoding of
 // the unit view direction), h1 = ReLU(W1 x + b1), h2 = ReLU(W2 h1 + b2),
 // c = sigmoid(W3 h2 + b3); W and z are BF16, every product is accumulated in
-// FP32.
+// FP32, and the view encoding and hidden activations enter the products as a
+// hi + lo pair of BF16 values (about 2^-17 relative), so the colour matches the
+// BF16-weight definition to near FP32 accuracy.
 //
 // A wave evaluates 16 samples at a time.  In the 16x16x32 MFMA, lane l holds
 // A[l % 16][8 (l / 16) + e], B[8 (l / 16) + e][l % 16] (e = 0..7) and
@@ -99,56 +101,75 @@ __device__ __forceinline__ void load_packed(MlpShared& sh, const uint4* __restri
   for (int i = threadIdx.x; i < kBiasFloats; i += blockDim.x) sh.bias[i] = bias[i];
 }
 
-// Read a D-layout result (4 row-blocks) back as the two B operands of the next
-// layer, after bias + ReLU and rounding to BF16.
-__device__ __forceinline__ void relu_to_b(const floatx4 h[4], const float* bias, int g, bf16x8& B0, bf16x8& B1) {
+// A value v carried as two BF16 operands, hi = bf16(v) and lo = bf16(v - hi):
+// hi + lo equals v to about 2^-17 relative, so products with the (exactly
+// BF16) weights keep activations and the view encoding at close to FP32
+// accuracy for twice the matrix-core work, which is not this kernel's bound.
+struct Split8 {
+  bf16x8 hi, lo;
+};
+
+__device__ __forceinline__ void split_put(Split8& s, int e, float v) {
+  const __bf16 h = static_cast<__bf16>(v);
+  s.hi[e] = h;
+  s.lo[e] = static_cast<__bf16>(v - static_cast<float>(h));
+}
+
+// Read a D-layout result (4 row-blocks) back as the split B operands of the
+// next layer, after bias + ReLU.
+__device__ __forceinline__ void relu_to_b(const floatx4 h[4], const float* bias, int g, Split8& B0, Split8& B1) {
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
     const int b0 = e >> 2, i = e & 3;
-    const float v0 = fmaxf(h[b0][i] + bias[16 * b0 + 4 * g + i], 0.0f);
-    const float v1 = fmaxf(h[2 + b0][i] + bias[16 * (2 + b0) + 4 * g + i], 0.0f);
-    B0[e] = static_cast<__bf16>(v0);
-    B1[e] = static_cast<__bf16>(v1);
+    split_put(B0, e, fmaxf(h[b0][i] + bias[16 * b0 + 4 * g + i], 0.0f));
+    split_put(B1, e, fmaxf(h[2 + b0][i] + bias[16 * (2 + b0) + 4 * g + i], 0.0f));
   }
 }
 
-// Layer-1 B operand of lane (g, sample s): latent values 8g..8g+7 (g < 2) or
-// the SH encoding values 8(g-2)..8(g-2)+7 of the view direction (g >= 2).
-__device__ __forceinline__ bf16x8 input_operand(int g, bool valid, const uint16_t* __restrict__ zrow,
+// Layer-1 B operand of lane (g, sample s): latent values 8g..8g+7 (g < 2,
+// exact BF16, lo = 0) or the SH encoding values 8(g-2)..8(g-2)+7 of the view
+// direction (g >= 2).
+__device__ __forceinline__ Split8 input_operand(int g, bool valid, const uint16_t* __restrict__ zrow,
                                                 const float d[3]) {
-  bf16x8 X;
+  Split8 X;
   if (g < 2) {
     uint4 raw = make_uint4(0, 0, 0, 0);
     if (valid) raw = *reinterpret_cast<const uint4*>(zrow + 8 * g);
-    __builtin_memcpy(&X, &raw, sizeof(X));
+    __builtin_memcpy(&X.hi, &raw, sizeof(X.hi));
+#pragma unroll
+    for (int e = 0; e < 8; ++e) X.lo[e] = static_cast<__bf16>(0.0f);
   } else {
     float Y[16];
     sh_basis(3, d[0], d[1], d[2], Y);
 #pragma unroll
-    for (int e = 0; e < 8; ++e) X[e] = static_cast<__bf16>(valid ? Y[8 * (g - 2) + e] : 0.0f);
+    for (int e = 0; e < 8; ++e) split_put(X, e, valid ? Y[8 * (g - 2) + e] : 0.0f);
   }
   return X;
 }
 
 struct MlpFwdState {
   floatx4 h1[4], h2[4], o;
-  bf16x8 X, B0, B1, C0, C1;
+  Split8 X, B0, B1, C0, C1;
 };
+
+__device__ __forceinline__ floatx4 mfma2(const uint4& a, const Split8& b, const floatx4& c) {
+  return mfma(a, b.lo, mfma(a, b.hi, c));
+}
 
 __device__ __forceinline__ void mlp_forward_group(const MlpShared& sh, int lane, MlpFwdState& st) {
   const int g = lane >> 4;
   const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int b = 0; b < 4; ++b) st.h1[b] = mfma(sh.ops[(kOpW1 + b) * 64 + lane], st.X, zero);
+  for (int b = 0; b < 4; ++b) st.h1[b] = mfma2(sh.ops[(kOpW1 + b) * 64 + lane], st.X, zero);
   relu_to_b(st.h1, sh.bias, g, st.B0, st.B1);
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
-    floatx4 acc = mfma(sh.ops[(kOpW2 + 2 * b) * 64 + lane], st.B0, zero);
-    st.h2[b] = mfma(sh.ops[(kOpW2 + 2 * b + 1) * 64 + lane], st.B1, acc);
+    floatx4 acc = mfma2(sh.ops[(kOpW2 + 2 * b) * 64 + lane], st.B0, zero);
+    st.h2[b] = mfma2(sh.ops[(kOpW2 + 2 * b + 1) * 64 + lane], st.B1, acc);
   }
   relu_to_b(st.h2, sh.bias + 64, g, st.C0, st.C1);
-  floatx4 acc = mfma(sh.ops[kOpW3 * 64 + lane], st.C0, zero);
-  st.o = mfma(sh.ops[(kOpW3 + 1) * 64 + lane], st.C1, acc);
+  floatx4 acc = mfma2(sh.ops[kOpW3 * 64 + lane], st.C0, zero);
+  st.o = mfma2(sh.ops[(kOpW3 + 1) * 64 + lane], st.C1, acc);
 }
 
 __device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + __expf(-x)); }
@@ -243,10 +264,13 @@ size_t mlp_packed_bytes() { return kOps * 64 * sizeof(uint4) + kBiasFloats * siz
 // with the packed transposed weights as A operands, so every gradient lands in
 // the D layout like the activations.  dx rows 0..15 are dL/dz, rows 16..31
 // dL/dY (the SH encoding), which the basis gradient carries to the direction.
-// Weight gradients contract over samples: each group's activations and
-// gradients go to LDS transposed ([unit][sample], BF16) and
+// The gradients entering the transposed products are hi + lo BF16 pairs as in
+// the forward.  Weight gradients contract over samples: each group's
+// activations and gradients go to LDS transposed ([unit][sample], hi and lo
+// planes) and
 //   dW1 += g1 x^T,  dW2 += g2 h1^T,  dW3 += g3 h2^T
-// run on v_mfma_f32_16x16x16_bf16 with K = the group's 16 samples (lane l holds
+// run on v_mfma_f32_16x16x16_bf16 as hi.hi + lo.hi + hi.lo (the lo.lo term,
+// about 2^-18 relative, is dropped) with K = the group's 16 samples (lane l holds
 // A[l % 16][4 (l / 16) + e] and B[4 (l / 16) + e][l % 16], e = 0..3).  Sums stay
 // in registers for the wave's whole share and are written once as a partial
 // vector; a fixed-order two-stage sum over waves makes the result
@@ -262,27 +286,46 @@ constexpr int kPartStride = GS_MLP_PARAMS + 1;  // parameters, then the loss
 constexpr int kBwdWavesMax = 2048;
 constexpr int kReduceChunk = 64;                 // waves per first-stage block
 
+// Transposed staging of one group ([unit][sample]); plane 0 holds the BF16
+// value (hi), plane 1 the BF16 rounding of the remainder (lo).
 struct MlpStage {
-  __bf16 x[32][16];
-  __bf16 h1[64][16];
-  __bf16 h2[64][16];
-  __bf16 g1[64][16];
-  __bf16 g2[64][16];
-  __bf16 g3[16][16];
+  __bf16 x[2][32][16];
+  __bf16 h1[2][64][16];
+  __bf16 h2[2][64][16];
+  __bf16 g1[2][64][16];
+  __bf16 g2[2][64][16];
+  __bf16 g3[2][16][16];
 };
 
-__device__ __forceinline__ bf16x4 stage_read(const __bf16 (*rows)[16], int row, int g) {
-  bf16x4 v;
-  __builtin_memcpy(&v, &rows[row][4 * g], sizeof(v));
+__device__ __forceinline__ void stage_put(__bf16 (*plane)[64][16], int u, int r, float v) {
+  const __bf16 h = static_cast<__bf16>(v);
+  plane[0][u][r] = h;
+  plane[1][u][r] = static_cast<__bf16>(v - static_cast<float>(h));
+}
+
+struct Split4 {
+  bf16x4 hi, lo;
+};
+
+template <int ROWS>
+__device__ __forceinline__ Split4 stage_read(const __bf16 (*plane)[ROWS][16], int row, int g) {
+  Split4 v;
+  __builtin_memcpy(&v.hi, &plane[0][row][4 * g], sizeof(v.hi));
+  __builtin_memcpy(&v.lo, &plane[1][row][4 * g], sizeof(v.lo));
   return v;
 }
 
-// D-layout gradients (4 row-blocks) as the two B operands of the next product.
-__device__ __forceinline__ void grad_to_b(const floatx4 h[4], bf16x8& B0, bf16x8& B1) {
+// (a_hi + a_lo)(b_hi + b_lo) without the lo x lo term, small terms first.
+__device__ __forceinline__ floatx4 mfma16x3(const Split4& a, const Split4& b, const floatx4& c) {
+  return mfma16(a.hi, b.hi, mfma16(a.lo, b.hi, mfma16(a.hi, b.lo, c)));
+}
+
+// D-layout gradients (4 row-blocks) as the split B operands of the next product.
+__device__ __forceinline__ void grad_to_b(const floatx4 h[4], Split8& B0, Split8& B1) {
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
-    B0[e] = static_cast<__bf16>(h[e >> 2][e & 3]);
-    B1[e] = static_cast<__bf16>(h[2 + (e >> 2)][e & 3]);
+    split_put(B0, e, h[e >> 2][e & 3]);
+    split_put(B1, e, h[2 + (e >> 2)][e & 3]);
   }
 }
 
@@ -333,32 +376,32 @@ __device__ __forceinline__ void mlp_bwd_group(const MlpShared& sh, MlpStage& sg,
       G.db3[i] += g3[i];
     }
   }
-  bf16x8 Bg3;
+  Split8 Bg3;
 #pragma unroll
-  for (int e = 0; e < 8; ++e) Bg3[e] = static_cast<__bf16>((g == 0 && e < 4) ? g3[e & 3] : 0.0f);
+  for (int e = 0; e < 8; ++e) split_put(Bg3, e, (g == 0 && e < 4) ? g3[e & 3] : 0.0f);
   floatx4 g2[4];
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
-    const floatx4 t = mfma(sh.ops[(kOpW3T + b) * 64 + lane], Bg3, zero);
+    const floatx4 t = mfma2(sh.ops[(kOpW3T + b) * 64 + lane], Bg3, zero);
 #pragma unroll
     for (int i = 0; i < 4; ++i) g2[b][i] = (st.h2[b][i] + sh.bias[64 + 16 * b + 4 * g + i] > 0.0f) ? t[i] : 0.0f;
   }
-  bf16x8 G0, G1;
+  Split8 G0, G1;
   grad_to_b(g2, G0, G1);
   floatx4 g1[4];
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
-    floatx4 t = mfma(sh.ops[(kOpW2T + 2 * b) * 64 + lane], G0, zero);
-    t = mfma(sh.ops[(kOpW2T + 2 * b + 1) * 64 + lane], G1, t);
+    floatx4 t = mfma2(sh.ops[(kOpW2T + 2 * b) * 64 + lane], G0, zero);
+    t = mfma2(sh.ops[(kOpW2T + 2 * b + 1) * 64 + lane], G1, t);
 #pragma unroll
     for (int i = 0; i < 4; ++i) g1[b][i] = (st.h1[b][i] + sh.bias[16 * b + 4 * g + i] > 0.0f) ? t[i] : 0.0f;
   }
-  bf16x8 H0, H1;
+  Split8 H0, H1;
   grad_to_b(g1, H0, H1);
-  dxz = mfma(sh.ops[(kOpW1T + 0) * 64 + lane], H0, zero);
-  dxz = mfma(sh.ops[(kOpW1T + 1) * 64 + lane], H1, dxz);
-  dxe = mfma(sh.ops[(kOpW1T + 2) * 64 + lane], H0, zero);
-  dxe = mfma(sh.ops[(kOpW1T + 3) * 64 + lane], H1, dxe);
+  dxz = mfma2(sh.ops[(kOpW1T + 0) * 64 + lane], H0, zero);
+  dxz = mfma2(sh.ops[(kOpW1T + 1) * 64 + lane], H1, dxz);
+  dxe = mfma2(sh.ops[(kOpW1T + 2) * 64 + lane], H0, zero);
+  dxe = mfma2(sh.ops[(kOpW1T + 3) * 64 + lane], H1, dxe);
 
   // transposed staging for the weight gradients
 #pragma unroll
@@ -366,39 +409,47 @@ __device__ __forceinline__ void mlp_bwd_group(const MlpShared& sh, MlpStage& sg,
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int u = 16 * b + 4 * g + i;
-      sg.h1[u][r] = static_cast<__bf16>(fmaxf(st.h1[b][i] + sh.bias[u], 0.0f));
-      sg.h2[u][r] = static_cast<__bf16>(fmaxf(st.h2[b][i] + sh.bias[64 + u], 0.0f));
-      sg.g1[u][r] = static_cast<__bf16>(g1[b][i]);
-      sg.g2[u][r] = static_cast<__bf16>(g2[b][i]);
+      stage_put(sg.h1, u, r, fmaxf(st.h1[b][i] + sh.bias[u], 0.0f));
+      stage_put(sg.h2, u, r, fmaxf(st.h2[b][i] + sh.bias[64 + u], 0.0f));
+      stage_put(sg.g1, u, r, g1[b][i]);
+      stage_put(sg.g2, u, r, g2[b][i]);
       G.db1[4 * b + i] += g1[b][i];
       G.db2[4 * b + i] += g2[b][i];
     }
 #pragma unroll
-  for (int e = 0; e < 8; ++e) sg.x[8 * g + e][r] = st.X[e];
+  for (int e = 0; e < 8; ++e) {
+    sg.x[0][8 * g + e][r] = st.X.hi[e];
+    sg.x[1][8 * g + e][r] = st.X.lo[e];
+  }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) sg.g3[4 * g + i][r] = static_cast<__bf16>(g == 0 ? g3[i] : 0.0f);
+  for (int i = 0; i < 4; ++i) {
+    const float v = g == 0 ? g3[i] : 0.0f;
+    const __bf16 h = static_cast<__bf16>(v);
+    sg.g3[0][4 * g + i][r] = h;
+    sg.g3[1][4 * g + i][r] = static_cast<__bf16>(v - static_cast<float>(h));
+  }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  bf16x4 aG2[4], aG1[4], bH1[4], bH2[4];
+  Split4 bH1[4], bH2[4];
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
-    aG2[b] = stage_read(sg.g2, 16 * b + r, g);
-    aG1[b] = stage_read(sg.g1, 16 * b + r, g);
-    bH1[b] = stage_read(sg.h1, 16 * b + r, g);
-    bH2[b] = stage_read(sg.h2, 16 * b + r, g);
+    bH1[b] = stage_read<64>(sg.h1, 16 * b + r, g);
+    bH2[b] = stage_read<64>(sg.h2, 16 * b + r, g);
   }
-  const bf16x4 bX0 = stage_read(sg.x, r, g), bX1 = stage_read(sg.x, 16 + r, g);
-  const bf16x4 aG3 = stage_read(sg.g3, r, g);
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
+  const Split4 bX0 = stage_read<32>(sg.x, r, g), bX1 = stage_read<32>(sg.x, 16 + r, g);
+  const Split4 aG3 = stage_read<16>(sg.g3, r, g);
 #pragma unroll
   for (int bo = 0; bo < 4; ++bo) {
+    const Split4 aG2 = stage_read<64>(sg.g2, 16 * bo + r, g);
+    const Split4 aG1 = stage_read<64>(sg.g1, 16 * bo + r, g);
 #pragma unroll
-    for (int bi = 0; bi < 4; ++bi) G.dW2[bo][bi] = mfma16(aG2[bo], bH1[bi], G.dW2[bo][bi]);
-    G.dW1[bo][0] = mfma16(aG1[bo], bX0, G.dW1[bo][0]);
-    G.dW1[bo][1] = mfma16(aG1[bo], bX1, G.dW1[bo][1]);
-    G.dW3[bo] = mfma16(aG3, bH2[bo], G.dW3[bo]);
+    for (int bi = 0; bi < 4; ++bi) G.dW2[bo][bi] = mfma16x3(aG2, bH1[bi], G.dW2[bo][bi]);
+    G.dW1[bo][0] = mfma16x3(aG1, bX0, G.dW1[bo][0]);
+    G.dW1[bo][1] = mfma16x3(aG1, bX1, G.dW1[bo][1]);
+    G.dW3[bo] = mfma16x3(aG3, bH2[bo], G.dW3[bo]);
   }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
 }
 
 // MODE 0: sample s has direction dirs[s] and latent s / per (per a power of

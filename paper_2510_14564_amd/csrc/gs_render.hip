@@ -494,6 +494,21 @@ __device__ __forceinline__ void bwd_terms(const float4& p, const float4& q, floa
   v[8] = G2 * w;                             // dL/db
 }
 
+// Per-Gaussian gradient accumulator row: nine sums padded to one 64-byte line.
+constexpr int kAccStride = 16;
+
+// g2d[k][i] = acc[i][k]: the [9][n] output from the line-per-Gaussian rows.
+__global__ __launch_bounds__(256) void k_acc_to_g2d(int n, const float4* __restrict__ acc, float* __restrict__ g2d) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float4 a = acc[4 * static_cast<int64_t>(i)];
+  const float4 b = acc[4 * static_cast<int64_t>(i) + 1];
+  const float4 c = acc[4 * static_cast<int64_t>(i) + 2];
+  const float v[9] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x};
+#pragma unroll
+  for (int k = 0; k < GS_G2D; ++k) g2d[static_cast<int64_t>(k) * n + i] = v[k];
+}
+
 // Per (pixel, entry) derivative, walked back to front.  Starting from the light
 // S = T_f bg behind the last entry, each blended entry m (going backwards)
 // recovers T_m = T_{m+1} / (1 - alpha_m) and uses the light behind it,
@@ -507,7 +522,10 @@ __device__ __forceinline__ void bwd_terms(const float4& p, const float4& q, floa
 // re-derived from the same alpha evaluation as the forward; entries past
 // n_contrib are never touched; a wave visits only the entries whose
 // alpha-support box meets its quadrant.  The nine per-pair gradients are summed
-// over the wave and added to the Gaussian's g2d entries by nine lanes at once.
+// over the wave and added by nine lanes at once to the Gaussian's row of the
+// accumulator acc[n][kAccStride]: one 64-byte line per Gaussian, so the nine
+// atomics of an instruction meet in one line (the [9][n] output is written
+// from it afterwards).
 __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ranges,
                                                     const uint32_t* __restrict__ point_list,
                                                     const float4* __restrict__ rec, DevCam cam,
@@ -515,7 +533,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
                                                     const uint32_t* __restrict__ n_contrib,
                                                     const float* __restrict__ t_ckpt,
                                                     const float* __restrict__ dL_dimage, int n,
-                                                    float* __restrict__ g2d, const int32_t* __restrict__ plan) {
+                                                    float* __restrict__ acc, const int32_t* __restrict__ plan) {
   __shared__ Stage st;
   __shared__ uint32_t s_max;
   const int tile = tile_of_block(plan, blockIdx.x, gridDim.x);
@@ -533,7 +551,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
   const bool lo8 = (lane & 8) == 0;
   const int out_slot = (lane == 63) ? 8 : kReduceSlot[((lane >> 4) << 1) | ((lane >> 3) & 1)];
   const bool writer = ((lane & 7) == 0) || lane == 63;
-  float* const g_out = g2d + static_cast<int64_t>(out_slot) * n;
+  float* const g_out = acc + out_slot;
 
   float G0 = 0.f, G1 = 0.f, G2 = 0.f, T = 1.0f;
   uint32_t ncon = 0;
@@ -580,7 +598,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
       bwd_terms(p, q, cb, ok, dx, dy, alpha, eg, og, G0, G1, G2, T, GS, v);
       const float red8 = wave_sum8(v, lo8);
       const float red9 = wave_sum_to_lane63(v[8]);  // dL/db
-      if (writer) unsafeAtomicAdd(&g_out[st.gid[j]], lane == 63 ? red9 : red8);
+      if (writer) unsafeAtomicAdd(&g_out[static_cast<int64_t>(st.gid[j]) * kAccStride], lane == 63 ? red9 : red8);
     }
   }
 }
@@ -596,7 +614,7 @@ __global__ __launch_bounds__(256) void k_render_bwd_light(const uint2* __restric
                                                           const float* __restrict__ final_T,
                                                           const uint32_t* __restrict__ n_contrib,
                                                           const float* __restrict__ dL_dimage, int n,
-                                                          float* __restrict__ g2d, const int32_t* __restrict__ plan) {
+                                                          float* __restrict__ acc, const int32_t* __restrict__ plan) {
   __shared__ LightStage stage[4];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int tile = light_tile(plan, blockIdx.x, wave);
@@ -608,7 +626,7 @@ __global__ __launch_bounds__(256) void k_render_bwd_light(const uint2* __restric
   const bool lo8 = (lane & 8) == 0;
   const int out_slot = (lane == 63) ? 8 : kReduceSlot[((lane >> 4) << 1) | ((lane >> 3) & 1)];
   const bool writer = ((lane & 7) == 0) || lane == 63;
-  float* const g_out = g2d + static_cast<int64_t>(out_slot) * n;
+  float* const g_out = acc + out_slot;
   const int64_t HW = static_cast<int64_t>(cam.width) * cam.height;
   float G0[4], G1[4], G2[4], T[4], GS[4], px[4], py[4];
   uint32_t ncon[4];
@@ -659,13 +677,19 @@ __global__ __launch_bounds__(256) void k_render_bwd_light(const uint2* __restric
     if (__ballot(any) == 0) continue;
     const float red8 = wave_sum8(vs, lo8);
     const float red9 = wave_sum_to_lane63(vs[8]);
-    if (writer) unsafeAtomicAdd(&g_out[ls.gid[j]], lane == 63 ? red9 : red8);
+    if (writer) unsafeAtomicAdd(&g_out[static_cast<int64_t>(ls.gid[j]) * kAccStride], lane == 63 ? red9 : red8);
   }
 }
 
+// Workspace: 256 reserved bytes, the backward's tile plan, then the
+// accumulator rows (256-byte aligned).
+static size_t bwd_acc_offset(int ntiles) {
+  return (256 + sizeof(int32_t) * plan_ints(ntiles) + 255) / 256 * 256;
+}
+
 size_t render_bwd_workspace(int64_t n, int64_t k, int ntiles, int deterministic) {
-  (void)n; (void)k; (void)deterministic;
-  return 256 + sizeof(int32_t) * plan_ints(ntiles);
+  (void)k; (void)deterministic;
+  return bwd_acc_offset(ntiles) + sizeof(float) * kAccStride * static_cast<size_t>(n);
 }
 
 gs_status launch_render_bwd(int64_t n, const gs_projected& proj, const uint32_t* point_list, const uint32_t* ranges,
@@ -674,10 +698,11 @@ gs_status launch_render_bwd(int64_t n, const gs_projected& proj, const uint32_t*
                             size_t ws_bytes, int deterministic, int schedule, hipStream_t s) {
   (void)ws_bytes;
   if (deterministic) return fail(GS_ERR_UNSUPPORTED, "gs_render_bwd: deterministic reduction not built yet");
-  gs_status st = check_hip(hipMemsetAsync(g2d, 0, sizeof(float) * GS_G2D * static_cast<size_t>(n), s),
-                           "hipMemsetAsync(g2d)");
-  if (st != GS_OK) return st;
   const int ntiles = cam.tiles_x * cam.tiles_y;
+  float* acc = reinterpret_cast<float*>(static_cast<char*>(ws) + bwd_acc_offset(ntiles));
+  gs_status st = check_hip(hipMemsetAsync(acc, 0, sizeof(float) * kAccStride * static_cast<size_t>(n), s),
+                           "hipMemsetAsync(acc)");
+  if (st != GS_OK) return st;
   int32_t* plan = nullptr;
   if (schedule == 1) {
     // plan from the forward's per-tile work counts (largest n_contrib)
@@ -688,14 +713,18 @@ gs_status launch_render_bwd(int64_t n, const gs_projected& proj, const uint32_t*
     if (st != GS_OK) return st;
     k_render_bwd_light<<<static_cast<unsigned>(ceil_div(ntiles, 4)), 256, 0, s>>>(
         reinterpret_cast<const uint2*>(ranges), point_list, reinterpret_cast<const float4*>(proj.records), cam,
-        final_T, n_contrib, dL_dimage, static_cast<int>(n), g2d, plan);
+        final_T, n_contrib, dL_dimage, static_cast<int>(n), acc, plan);
     st = check_launch("k_render_bwd_light");
     if (st != GS_OK) return st;
   }
   k_render_bwd<<<ntiles, 256, 0, s>>>(reinterpret_cast<const uint2*>(ranges), point_list,
                                       reinterpret_cast<const float4*>(proj.records), cam, final_T, n_contrib,
-                                      t_ckpt, dL_dimage, static_cast<int>(n), g2d, plan);
-  return check_launch("k_render_bwd");
+                                      t_ckpt, dL_dimage, static_cast<int>(n), acc, plan);
+  st = check_launch("k_render_bwd");
+  if (st != GS_OK) return st;
+  k_acc_to_g2d<<<static_cast<unsigned>(ceil_div(n, 256)), 256, 0, s>>>(static_cast<int>(n),
+                                                                       reinterpret_cast<const float4*>(acc), g2d);
+  return check_launch("k_acc_to_g2d");
 }
 
 }  // namespace gs

@@ -1,11 +1,15 @@
 """Parity of the learned colour decoder's matrix-core kernels with the FP64 oracle.
 
 Both sides use the same BF16 latents and weights (widened exactly to FP64 in
-the oracle).  The HIP path also rounds the SH encoding of the direction and
-both hidden activations to BF16 before each product and accumulates in FP32;
-the tolerance is the running error bound of exactly those roundings,
-propagated through |W| in FP64 (ReLU is 1-Lipschitz, the sigmoid 1/4).  The
-observed maximum error is printed.
+the oracle).  In the forward the HIP path carries the SH encoding of the
+direction and both hidden activations as hi + lo BF16 pairs (relative error
+at most 2^-17, bounded here by UA = 2^-16) and accumulates in FP32; the
+backward does the same for the gradients entering each product and for both
+operands of the weight-gradient products (whose dropped lo x lo term is
+below 2^-17 relative).  The tolerance
+is the running error bound of exactly those roundings, propagated through |W|
+in FP64 (ReLU is 1-Lipschitz, the sigmoid 1/4).  The observed maximum error
+is printed.
 """
 import numpy as np
 import pytest
@@ -18,6 +22,7 @@ from gpu_helpers import DEV, say, to_dev
 pytestmark = pytest.mark.gpu
 
 U = 2.0 ** -8      # bf16 relative rounding bound (half an ulp = 2^-9, doubled for safety)
+UA = 2.0 ** -16    # hi + lo pair of bf16 values (2^-17 + FP32 rounding, doubled)
 G32 = 2.0 ** -22   # FP32 accumulation, per term, with margin
 
 
@@ -58,7 +63,7 @@ def fwd_bounds(x, P, ex=None):
     sl = _slices(P)
     ax = np.abs(x)
     if ex is None:
-        ex = np.concatenate([np.zeros_like(ax[:, :16]), U * ax[:, 16:]], axis=1)
+        ex = np.concatenate([np.zeros_like(ax[:, :16]), UA * ax[:, 16:]], axis=1)
     W1, W2, W3 = np.abs(sl["W1"]), np.abs(sl["W2"]), np.abs(sl["W3"])
     a1 = x @ sl["W1"].T + sl["b1"]
     h1 = np.maximum(a1, 0)
@@ -66,11 +71,12 @@ def fwd_bounds(x, P, ex=None):
     h2 = np.maximum(a2, 0)
     a3 = h2 @ sl["W3"].T + sl["b3"]
     c = 1 / (1 + np.exp(-a3))
-    d1 = ex @ W1.T + 32 * G32 * ((ax + ex) @ W1.T + np.abs(sl["b1"]))
-    e1 = d1 + U * (h1 + d1)
-    d2 = e1 @ W2.T + 64 * G32 * ((h1 + e1) @ W2.T + np.abs(sl["b2"]))
-    e2 = d2 + U * (h2 + d2)
-    d3 = e2 @ W3.T + 64 * G32 * ((h2 + e2) @ W3.T + np.abs(sl["b3"]))
+    # 2x the terms: every product is two accumulated MFMAs (hi, lo)
+    d1 = ex @ W1.T + 64 * G32 * ((ax + ex) @ W1.T + np.abs(sl["b1"]))
+    e1 = d1 + UA * (h1 + d1)
+    d2 = e1 @ W2.T + 128 * G32 * ((h1 + e1) @ W2.T + np.abs(sl["b2"]))
+    e2 = d2 + UA * (h2 + d2)
+    d3 = e2 @ W3.T + 128 * G32 * ((h2 + e2) @ W3.T + np.abs(sl["b3"]))
     dc = 0.25 * d3 + 2e-6
     return dict(sl=sl, ax=ax, ex=ex, a1=a1, h1=h1, a2=a2, h2=h2, c=c, d1=d1, e1=e1, d2=d2, e2=e2, dc=dc)
 
@@ -96,20 +102,24 @@ def bwd_bounds(x, P, G, eG=None, ex=None):
     s3 = c * (1 - c)
     g3 = G * s3
     eg3 = np.abs(G) * (dc + dc * dc) + eG * (s3 + dc + dc * dc) + 1e-6 * np.abs(g3)
-    eg3b = eg3 + U * (np.abs(g3) + eg3)
+    eg3b = eg3 + UA * (np.abs(g3) + eg3)
     t2 = g3 @ sl["W3"]
     et2 = eg3b @ W3 + 3 * G32 * (np.abs(g3) + eg3b) @ W3
     g2 = t2 * (f["a2"] > 0)
     eg2 = np.where(np.abs(f["a2"]) <= f["d2"], np.abs(t2) + et2, et2)
-    eg2b = eg2 + U * (np.abs(g2) + eg2)
+    eg2b = eg2 + UA * (np.abs(g2) + eg2)
     t1 = g2 @ sl["W2"]
     et1 = eg2b @ W2 + 64 * G32 * (np.abs(g2) + eg2b) @ W2
     g1 = t1 * (f["a1"] > 0)
     eg1 = np.where(np.abs(f["a1"]) <= f["d1"], np.abs(t1) + et1, et1)
-    eg1b = eg1 + U * (np.abs(g1) + eg1)
+    eg1b = eg1 + UA * (np.abs(g1) + eg1)
     edx = eg1b @ W1 + 64 * G32 * (np.abs(g1) + eg1b) @ W1
     acc = (S / 16 + 256) * F32
-    h1, e1, h2, e2 = f["h1"], f["e1"], f["h2"], f["e2"]
+    h1, h2 = f["h1"], f["h2"]
+    # the weight-gradient products read hi + lo pairs (lo x lo dropped)
+    e1 = f["e1"] + UA * (h1 + f["e1"])
+    e2 = f["e2"] + UA * (h2 + f["e2"])
+    ex = ex + np.concatenate([np.zeros_like(ax[:, :16]), UA * (ax[:, 16:] + ex[:, 16:])], axis=1)
     xs = ax + ex
     eP = np.zeros(oracle.MLP_PARAMS)
 
