@@ -54,6 +54,59 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# kernels of each stage (as named in the rocprofv3 summaries under profiles/)
+STAGE_KERNELS = {
+    "project": ("k_project<", "k_mlp_fwd<1>"),
+    "bin_sort": ("k_depth_keys", "k_rs_hist", "k_rs_scatter", "k_scan_", "k_gather_counts", "k_emit", "k_ranges"),
+    "render_fwd": ("k_render_fwd_light", "k_render_fwd<false>"),
+    "render_bwd": ("k_render_bwd", "k_acc_to_g2d"),
+    "project_bwd": ("k_project_bwd<", "k_mlp_bwd<1>", "k_mlp_reduce"),
+}
+
+
+# sources whose kernels run in each stage
+STAGE_SOURCES = {
+    "project": ("gs_project.hip", "gs_sh.h", "gs_mlp.hip", "gs_internal.h"),
+    "bin_sort": ("gs_binsort.hip", "gs_internal.h"),
+    "render_fwd": ("gs_render.hip", "gs_plan.hip", "gs_internal.h"),
+    "render_bwd": ("gs_render.hip", "gs_plan.hip", "gs_internal.h"),
+    "project_bwd": ("gs_project.hip", "gs_sh.h", "gs_mlp.hip", "gs_internal.h"),
+}
+
+
+def counter_traffic_bytes(stage):
+    """Calibrated HBM bytes (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel
+    factors) per call of a stage, from the committed counter summary; None if
+    it is missing or any kernel source changed since it was taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_main_workload.txt")
+    if not os.path.exists(path):
+        return None
+    csrc = os.path.join(ROOT, "paper_2510_14564_amd", "csrc")
+    total, seen = 0.0, False
+    for line in open(path):
+        m = re.match(r"# source-sha256 (\S+) (\w+)", line)
+        if m:
+            f = os.path.join(csrc, m.group(1))
+            changed = not os.path.exists(f) or hashlib.sha256(open(f, "rb").read()).hexdigest()[:16] != m.group(2)
+            if changed and m.group(1) in STAGE_SOURCES[stage]:
+                return None
+            continue
+        if line.startswith("#") or not line.strip():
+            continue
+        parts = line.split()
+        name = parts[0]
+        if name.startswith(STAGE_KERNELS[stage]) or (name == "k_tile_plan" and stage in ("render_fwd", "render_bwd")):
+            try:
+                mb = float(parts[-1])
+            except ValueError:
+                continue
+            total += mb * 1e6 * (0.5 if name == "k_tile_plan" else 1.0)
+            seen = True
+    return total if seen else None
+
+
 class StageTimer:
     """Records a pair of events on the current stream around each stage."""
 
@@ -257,10 +310,14 @@ def main():
                         "achieved": PROJECT_BWD_BYTES_PER_G[deg] * n / (stage_ms["project_bwd"] * 1e-3) / 1e9,
                         "peak": HBM_PEAK_GBS, "unit": "GB/s"},
     }
-    for r in rooflines.values():
+    for name, r in rooflines.items():
         r["achieved"] = round(r["achieved"], 2)
         r["frac"] = round(r["achieved"] / r["peak"], 4)
-        r["traffic"] = None
+        tb = counter_traffic_bytes(name)
+        # measured HBM traffic of the stage per call, as a rate over its time
+        r["traffic"] = None if tb is None else round(tb / (stage_ms[name] * 1e-3) / 1e9, 1)
+        r["traffic_unit"] = "GB/s"
+        r["traffic_bytes_per_call"] = None if tb is None else round(tb)
     dominant = max(("render_bwd", "render_fwd", "project", "project_bwd"), key=lambda s: stage_ms.get(s, 0))
     roof = dict(rooflines[dominant])
     roof["kernel"] = dominant

@@ -77,27 +77,23 @@ __global__ __launch_bounds__(256) void k_scan_sums(const uint32_t* __restrict__ 
   if (threadIdx.x == 0) sums[blockIdx.x] = red[0];
 }
 
-// One block: exclusive scan of `nb` block sums in place; total (64-bit) out.
-__global__ __launch_bounds__(256) void k_scan_top(uint32_t* __restrict__ sums, int nb,
-                                                  unsigned long long* __restrict__ total) {
-  __shared__ uint32_t lds[256];
-  uint64_t carry = 0;
-  for (int base = 0; base < nb; base += 256) {
-    const int idx = base + threadIdx.x;
-    const uint32_t v = idx < nb ? sums[idx] : 0u;
-    uint32_t tot;
-    const uint32_t ex = block_exclusive_scan(v, lds, tot);
-    if (idx < nb) sums[idx] = static_cast<uint32_t>(carry) + ex;
-    carry += tot;
-  }
-  if (threadIdx.x == 0 && total) *total = carry;
-}
-
+// Per chunk: its offset is the sum of the sums of all earlier chunks, which
+// every block adds up itself (a few thousand values at most, read from L2) --
+// no separate top-level scan launch.  The last block also writes the 64-bit
+// total.  Thread t owns items [16 t, 16 t + 16) of the chunk.
 __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__ in, int64_t n,
-                                                    const uint32_t* __restrict__ sums, uint32_t* __restrict__ out) {
+                                                    const uint32_t* __restrict__ sums, uint32_t* __restrict__ out,
+                                                    unsigned long long* __restrict__ total) {
   __shared__ uint32_t lds[256];
-  const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanChunk;
-  // blocked arrangement: thread t owns items [t*16, t*16+16) of the chunk
+  __shared__ unsigned long long red[4];
+  const int b = blockIdx.x;
+  unsigned long long pre = 0;
+  for (int i = threadIdx.x; i < b; i += 256) pre += sums[i];
+  for (int o = 32; o > 0; o >>= 1) pre += __shfl_xor(pre, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = pre;
+  __syncthreads();
+  const unsigned long long offset = red[0] + red[1] + red[2] + red[3];
+  const int64_t base = static_cast<int64_t>(b) * kScanChunk;
   uint32_t v[kScanItems];
   uint32_t s = 0;
   const int64_t my = base + static_cast<int64_t>(threadIdx.x) * kScanItems;
@@ -107,12 +103,13 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__
     s += v[j];
   }
   uint32_t tot;
-  uint32_t run = block_exclusive_scan(s, lds, tot) + sums[blockIdx.x];
+  uint32_t run = block_exclusive_scan(s, lds, tot) + static_cast<uint32_t>(offset);
   for (int j = 0; j < kScanItems; ++j) {
     const int64_t idx = my + j;
     if (idx < n) out[idx] = run;
     run += v[j];
   }
+  if (total && b == static_cast<int>(gridDim.x) - 1 && threadIdx.x == 0) *total = offset + tot;
 }
 
 struct ScanWs {
@@ -125,8 +122,7 @@ static size_t scan_ws_words(int64_t n) { return static_cast<size_t>(ceil_div(n >
 static gs_status device_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, ScanWs ws, hipStream_t s) {
   const int nb = static_cast<int>(ceil_div(n > 0 ? n : 1, kScanChunk));
   k_scan_sums<<<nb, 256, 0, s>>>(in, n, ws.sums);
-  k_scan_top<<<1, 256, 0, s>>>(ws.sums, nb, ws.total);
-  k_scan_apply<<<nb, 256, 0, s>>>(in, n, ws.sums, out);
+  k_scan_apply<<<nb, 256, 0, s>>>(in, n, ws.sums, out, ws.total);
   return check_launch("device_exclusive_scan");
 }
 
@@ -235,39 +231,10 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* __res
   }
 }
 
-// Exclusive scan of up to kSmallScan values by one 1024-thread block.
-constexpr int kSmallScan = 1 << 17;
-__global__ __launch_bounds__(1024) void k_scan_small(const uint32_t* __restrict__ in, int n,
-                                                     uint32_t* __restrict__ out) {
-  __shared__ uint32_t part[1024];
-  const int per = (n + 1023) / 1024;
-  const int b = threadIdx.x * per;
-  uint32_t s = 0;
-  for (int i = 0; i < per; ++i) s += (b + i < n) ? in[b + i] : 0u;
-  part[threadIdx.x] = s;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    const uint32_t t = (threadIdx.x >= static_cast<unsigned>(off)) ? part[threadIdx.x - off] : 0u;
-    __syncthreads();
-    part[threadIdx.x] += t;
-    __syncthreads();
-  }
-  uint32_t run = part[threadIdx.x] - s;
-  for (int i = 0; i < per; ++i) {
-    if (b + i < n) {
-      const uint32_t x = in[b + i];
-      out[b + i] = run;
-      run += x;
-    }
-  }
-}
-
 static gs_status scan_hist(uint32_t* hist, int64_t nh, ScanWs sws, hipStream_t s) {
-  if (nh <= kSmallScan) {
-    k_scan_small<<<1, 1024, 0, s>>>(hist, static_cast<int>(nh), hist);
-    return check_launch("k_scan_small");
-  }
-  return device_exclusive_scan(hist, hist, nh, sws, s);
+  ScanWs w = sws;
+  w.total = nullptr;
+  return device_exclusive_scan(hist, hist, nh, w, s);
 }
 
 // Sorts `count` pairs over key bits [0, total_bits) in passes of <= 8 bits.

@@ -82,8 +82,13 @@ __device__ __forceinline__ uint32_t uniform(uint32_t x) {
 constexpr int kListStride = kBatch + 4; // per-wave list of staged slots, padded to kUnroll
 
 // Work-split threshold: a tile is heavy when its work count exceeds this
-// multiple of the mean count over all tiles (tuned by measurement).
+// multiple of the mean count over all tiles (tuned by measurement).  The
+// backward's count (largest n_contrib) is its exact walk length; the
+// forward's only count before it runs is the list length, which does not
+// predict where pixels saturate (measured: ordering the forward by it made
+// the launch slower), so the forward uses the plan only to merge light tiles.
 constexpr float kHeavyFactor = 4.0f;
+constexpr float kHeavyFactorFwd = 3.0e38f;
 
 // Tile of workgroup `bid`.  Plain form: XCD-aware spatial map.  With a plan
 // (balanced form): heavy tiles first, largest first, one per workgroup in
@@ -379,7 +384,7 @@ gs_status launch_render_fwd(const gs_projected& proj, const uint32_t* point_list
     plan = reinterpret_cast<int32_t*>(tail);
     tile_work = reinterpret_cast<uint32_t*>(tail + plan_ints(ntiles));
     if (schedule == 1) {
-      gs_status st = launch_tile_plan(ntiles, ranges, nullptr, kHeavyFactor, kLightMax, plan, s);
+      gs_status st = launch_tile_plan(ntiles, ranges, nullptr, kHeavyFactorFwd, kLightMax, plan, s);
       if (st != GS_OK) return st;
       k_render_fwd_light<<<static_cast<unsigned>(ceil_div(ntiles, 4)), 256, 0, s>>>(
           reinterpret_cast<const uint2*>(ranges), point_list, reinterpret_cast<const float4*>(proj.records), cam,

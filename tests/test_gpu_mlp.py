@@ -128,19 +128,36 @@ def bwd_bounds(x, P, G, eG=None, ex=None):
         eP[off:off + int(np.prod(shape))] = v.reshape(-1)
 
     ag1, ag2, ag3 = np.abs(g1), np.abs(g2), np.abs(g3)
+    # mass: the sum over samples of |per-sample terms| of each exact gradient
+    mass = np.zeros(oracle.MLP_PARAMS)
+
+    def put_mass(name, v):
+        off, shape = oracle.MLP_SLICES[name]
+        mass[off:off + int(np.prod(shape))] = v.reshape(-1)
+
+    put_mass("W1", ag1.T @ ax)
+    put_mass("W2", ag2.T @ h1)
+    put_mass("W3", ag3.T @ h2)
+    put_mass("b1", ag1.sum(0))
+    put_mass("b2", ag2.sum(0))
+    put_mass("b3", ag3.sum(0))
     put("W1", eg1b.T @ xs + ag1.T @ ex + acc * (ag1 + eg1b).T @ xs)
     put("W2", eg2b.T @ (h1 + e1) + ag2.T @ e1 + acc * (ag2 + eg2b).T @ (h1 + e1))
     put("W3", eg3b.T @ (h2 + e2) + ag3.T @ e2 + acc * (ag3 + eg3b).T @ (h2 + e2))
     put("b1", eg1.sum(0) + acc * (ag1 + eg1).sum(0))
     put("b2", eg2.sum(0) + acc * (ag2 + eg2).sum(0))
     put("b3", eg3.sum(0) + acc * (ag3 + eg3).sum(0))
-    return eP + 1e-7, edx + 1e-7, c
+    return eP + 1e-7, edx + 1e-7, mass
 
 
-def reading18(got, want, floor=1e-2):
-    """Fraction of entries within floor * max(|g*|, 1e-3 max|g*|)."""
-    tol = floor * np.maximum(np.abs(want), 1e-3 * np.abs(want).max())
-    return float(np.mean(np.abs(got - want) <= tol))
+def reading18(got, want, floor=1e-2, mass=None):
+    """Fraction of entries within floor * max(|g*|, 1e-3 max|g*|), and, when
+    the term mass is given, 1e-2 of it (a sum over samples that cancels by more
+    than 100x is judged against its terms, which its rounding scales with)."""
+    ref = np.maximum(np.abs(want), 1e-3 * np.abs(want).max())
+    if mass is not None:
+        ref = np.maximum(ref, 1e-2 * mass)
+    return float(np.mean(np.abs(got - want) <= floor * ref))
 
 
 def _dirs(n, per, seed):
@@ -230,11 +247,11 @@ def _bwd_workspace(gs, S, per):
     return torch.empty(gs.mlp_bwd_workspace(S, per), dtype=torch.uint8, device=DEV)
 
 
-def _check_grads(label, got_P, want_P, bP, got_z, want_z, bz):
+def _check_grads(label, got_P, want_P, bP, got_z, want_z, bz, massP=None):
     errP, errz = np.abs(got_P - want_P), np.abs(got_z - want_z)
     assert (errP <= bP).all(), f"{label} dP: worst err/bound {(errP / bP).max():.2f}"
     assert (errz <= bz).all(), f"{label} dz: worst err/bound {(errz / bz).max():.2f}"
-    fP, fz = reading18(got_P, want_P), reading18(got_z, want_z)
+    fP, fz = reading18(got_P, want_P, mass=massP), reading18(got_z, want_z)
     say(f"  {label}: max err/bound dP {(errP / bP).max():.3f} dz {(errz / bz).max():.3f}; "
         f"within 1e-2 rel: dP {fP:.4f} dz {fz:.4f}")
     assert fP >= 0.99 and fz >= 0.99
@@ -264,10 +281,10 @@ def test_mlp_backward_matches_oracle_within_bound(gs, n, per):
     P = scenes.bf16_to_f32(Pbits).astype(np.float64)
     x = oracle.mlp_inputs(scenes.bf16_to_f32(z).astype(np.float64), d.astype(np.float64))
     want_P, dx = oracle.mlp_bwd(x, P, G.astype(np.float64))
-    bP, bdx, _ = bwd_bounds(x, P, G.astype(np.float64))
+    bP, bdx, massP = bwd_bounds(x, P, G.astype(np.float64))
     want_z = dx[:, :16].reshape(n, per, 16).sum(1)
     bz = bdx[:, :16].reshape(n, per, 16).sum(1) + per * F32 * np.abs(dx[:, :16]).reshape(n, per, 16).sum(1)
-    _check_grads(f"n={n} per={per}", got_P, want_P, bP, got_z, want_z, bz)
+    _check_grads(f"n={n} per={per}", got_P, want_P, bP, got_z, want_z, bz, massP)
 
 
 def test_mlp_distillation_loss_and_gradient(gs):
@@ -298,11 +315,11 @@ def test_mlp_distillation_loss_and_gradient(gs):
     assert abs(loss.item() - want_loss) <= bl, (loss.item(), want_loss, bl)
     G = 2 * scale * (c - t)
     want_P, dx = oracle.mlp_bwd(x, P, G)
-    bP, bdx, _ = bwd_bounds(x, P, G, eG=2 * scale * dc)
+    bP, bdx, massP = bwd_bounds(x, P, G, eG=2 * scale * dc)
     want_z = dx[:, :16].reshape(n, per, 16).sum(1)
     bz = bdx[:, :16].reshape(n, per, 16).sum(1) + per * F32 * np.abs(dx[:, :16]).reshape(n, per, 16).sum(1)
     _check_grads("distill", dP.cpu().numpy().astype(np.float64), want_P, bP,
-                 dlat.cpu().numpy().astype(np.float64), want_z, bz)
+                 dlat.cpu().numpy().astype(np.float64), want_z, bz, massP)
 
 
 def test_project_bwd_learned_colour(gs):
@@ -334,7 +351,7 @@ def test_project_bwd_learned_colour(gs):
     # geometry: the oracle's SH backward on a degree-0 copy (no direction term)
     s0 = scenes.Scene(n, 0, scene.means, scene.log_scales, scene.quats, scene.logits,
                       np.zeros((1, 3, n), np.float32))
-    geo = oracle.project_bwd(s0, cam, g2d_h.astype(np.float64))
+    geo = oracle.project_bwd(s0, cam, np.ascontiguousarray(g2d_h.T).astype(np.float64))
     o = oracle.project(s0, cam)
     ok = (o["flags"] & 0b1110) == 0
     for kk in ("log_scales", "quats", "logits"):
@@ -354,11 +371,11 @@ def test_project_bwd_learned_colour(gs):
     x = oracle.mlp_inputs(zt.detach().numpy(), dirs[:, None, :])
     # the kernel's direction is FP32: widen the input bound of the SH half
     ex = np.concatenate([np.zeros((len(idx), 16)), (U + 1e-5) * np.abs(x[:, 16:]) + 1e-6], axis=1)
-    bP, bdx, _ = bwd_bounds(x, P, Gc, ex=ex)
+    bP, bdx, massP = bwd_bounds(x, P, Gc, ex=ex)
     got_z = grads["latents"].cpu().numpy().astype(np.float64)
     assert (got_z[~live] == 0).all()
     _check_grads("learned colour", grads["mlp"].cpu().numpy().astype(np.float64), Pt.grad.numpy(), bP,
-                 got_z[idx], zt.grad.numpy(), bdx[:, :16])
+                 got_z[idx], zt.grad.numpy(), bdx[:, :16], massP)
     # means: geometry (1e-3 relative) + the direction share, whose error is at
     # most |grad Y_j| <= 10 on the unit sphere times the dL/dY bound, over |v|
     share = mt.grad.numpy()
