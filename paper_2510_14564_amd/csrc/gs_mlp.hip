@@ -129,12 +129,10 @@ __device__ __forceinline__ void relu_to_b(const floatx4 h[4], const float* bias,
 // Layer-1 B operand of lane (g, sample s): latent values 8g..8g+7 (g < 2,
 // exact BF16, lo = 0) or the SH encoding values 8(g-2)..8(g-2)+7 of the view
 // direction (g >= 2).
-__device__ __forceinline__ Split8 input_operand(int g, bool valid, const uint16_t* __restrict__ zrow,
-                                                const float d[3]) {
+__device__ __forceinline__ Split8 input_operand(int g, bool valid, const uint4& zslice, const float d[3]) {
   Split8 X;
   if (g < 2) {
-    uint4 raw = make_uint4(0, 0, 0, 0);
-    if (valid) raw = *reinterpret_cast<const uint4*>(zrow + 8 * g);
+    const uint4 raw = valid ? zslice : make_uint4(0, 0, 0, 0);
     __builtin_memcpy(&X.hi, &raw, sizeof(X.hi));
 #pragma unroll
     for (int e = 0; e < 8; ++e) X.lo[e] = static_cast<__bf16>(0.0f);
@@ -174,6 +172,62 @@ __device__ __forceinline__ void mlp_forward_group(const MlpShared& sh, int lane,
 
 __device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + __expf(-x)); }
 
+// Inputs of one lane's sample.  The kernels load them one group ahead, so
+// their latency hides behind the current group's arithmetic (a wave runs
+// many groups in turn and few waves share a SIMD).
+struct SampleIn {
+  float a[3];       // unit direction (MODE 0) or the Gaussian's mean (MODE 1)
+  float c[3];       // backward: dL/dc or the distillation target (quarter 0)
+  uint4 z;          // latent values 8 g .. 8 g + 7 (quarters 0, 1)
+  float m[3];       // MODE 1 backward: dL/dmean so far (the geometry's share)
+  bool in;          // s < S (and, MODE 1, the Gaussian is live)
+};
+
+template <int MODE, bool BWD>
+__device__ __forceinline__ SampleIn load_sample(int s, int S, int per, int g, const uint16_t* __restrict__ latents,
+                                                const float* __restrict__ dirs, const float* __restrict__ means,
+                                                const int* __restrict__ radius, const float* __restrict__ dL_dc,
+                                                const float* __restrict__ dmean = nullptr) {
+  SampleIn x;
+  x.a[0] = 0.f; x.a[1] = 0.f; x.a[2] = 1.f;
+  x.c[0] = x.c[1] = x.c[2] = 0.f;
+  x.m[0] = x.m[1] = x.m[2] = 0.f;
+  x.z = make_uint4(0, 0, 0, 0);
+  x.in = s < S;
+  if (!x.in) return x;
+  if (MODE == 0) {
+    x.a[0] = dirs[3 * static_cast<int64_t>(s)];
+    x.a[1] = dirs[3 * static_cast<int64_t>(s) + 1];
+    x.a[2] = dirs[3 * static_cast<int64_t>(s) + 2];
+  } else {
+    x.in = radius[s] > 0;
+    x.a[0] = means[s]; x.a[1] = means[S + s]; x.a[2] = means[2 * S + s];
+  }
+  if (g < 2) x.z = *reinterpret_cast<const uint4*>(latents + static_cast<int64_t>(s / per) * 16 + 8 * g);
+  if (BWD && g == 0) {
+#pragma unroll
+    for (int i = 0; i < kMlpOut; ++i) {
+      if (MODE == 1) x.c[i] = dL_dc[static_cast<int64_t>(6 + i) * S + s];   // g2d rows 6..8
+      else x.c[i] = dL_dc[3 * static_cast<int64_t>(s) + i];                  // [S][3]
+      if (MODE == 1 && dmean && x.in) x.m[i] = dmean[static_cast<int64_t>(i) * S + s];
+    }
+  }
+  return x;
+}
+
+// Unit view direction of a loaded sample (MODE 1: from the mean and camera).
+template <int MODE>
+__device__ __forceinline__ void sample_dir(const SampleIn& x, const DevCam& cam, float d[3], float& len) {
+  len = 1.f;
+  if (MODE == 0) {
+    d[0] = x.a[0]; d[1] = x.a[1]; d[2] = x.a[2];
+  } else if (x.in) {
+    view_dir(x.a, cam, d, len);
+  } else {
+    d[0] = 0.f; d[1] = 0.f; d[2] = 1.f;
+  }
+}
+
 // MODE 0: samples s < S with unit directions dirs[s][3], latent s / per,
 //         colours out[s][3].
 // MODE 1: sample s = Gaussian s of the projection; direction from its centre
@@ -190,23 +244,19 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(int S, int per, const uint16_t*
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
   const int stride = gridDim.x * 4;
-  for (int grp = blockIdx.x * 4 + wave; grp * 16 < S; grp += stride) {
+  int grp = blockIdx.x * 4 + wave;
+  SampleIn cur = load_sample<MODE, false>(grp * 16 + r, S, per, g, latents, dirs, means, radius, nullptr);
+  for (; grp * 16 < S; grp += stride) {
     const int s = grp * 16 + r;
-    bool valid = s < S;
-    float d[3] = {0.f, 0.f, 1.f};
-    if (MODE == 0) {
-      if (valid) { d[0] = dirs[3 * s]; d[1] = dirs[3 * s + 1]; d[2] = dirs[3 * s + 2]; }
-    } else {
-      valid = valid && radius[s] > 0;
-      if (valid) {
-        const float m[3] = {means[s], means[S + s], means[2 * S + s]};
-        float len;
-        view_dir(m, cam, d, len);
-      }
-    }
+    const SampleIn nxt = load_sample<MODE, false>((grp + stride) * 16 + r, S, per, g, latents, dirs, means, radius,
+                                                  nullptr);
+    const bool valid = cur.in;
+    float d[3], len;
+    sample_dir<MODE>(cur, cam, d, len);
     MlpFwdState st;
-    st.X = input_operand(g, valid, latents + static_cast<int64_t>(valid ? s / per : 0) * 16, d);
+    st.X = input_operand(g, valid, cur.z, d);
     mlp_forward_group(sh, lane, st);
+    cur = nxt;
     if (g == 0 && valid) {
 #pragma unroll
       for (int i = 0; i < kMlpOut; ++i) {
@@ -219,8 +269,10 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(int S, int per, const uint16_t*
   }
 }
 
+// At least four groups of 16 per wave; about three workgroups per CU at most
+// (each copies the 31 KB operand image to LDS once).
 static unsigned mlp_grid(int64_t S) {
-  return static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>(ceil_div(S, 64), 4096)));
+  return static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>(ceil_div(S, 256), 768)));
 }
 
 gs_status launch_mlp_pack(const uint16_t* params, void* packed, hipStream_t s) {
@@ -283,21 +335,25 @@ __device__ __forceinline__ floatx4 mfma16(const bf16x4& a, const bf16x4& b, cons
 }
 
 constexpr int kPartStride = GS_MLP_PARAMS + 1;  // parameters, then the loss
-constexpr int kBwdWavesMax = 2048;
+constexpr int kBwdWavesMax = 1024;
 constexpr int kReduceChunk = 64;                 // waves per first-stage block
 
 // Transposed staging of one group ([unit][sample]); plane 0 holds the BF16
-// value (hi), plane 1 the BF16 rounding of the remainder (lo).
+// value (hi), plane 1 the BF16 rounding of the remainder (lo).  Rows are
+// padded to kRow = 20 values (10 banks): the four quarters of a wave, which
+// write rows 4 apart, then land on disjoint LDS banks, and row starts stay
+// 8-byte aligned for the operand reads.
+constexpr int kRow = 20;
 struct MlpStage {
-  __bf16 x[2][32][16];
-  __bf16 h1[2][64][16];
-  __bf16 h2[2][64][16];
-  __bf16 g1[2][64][16];
-  __bf16 g2[2][64][16];
-  __bf16 g3[2][16][16];
+  __bf16 x[2][32][kRow];
+  __bf16 h1[2][64][kRow];
+  __bf16 h2[2][64][kRow];
+  __bf16 g1[2][64][kRow];
+  __bf16 g2[2][64][kRow];
+  __bf16 g3[2][16][kRow];
 };
 
-__device__ __forceinline__ void stage_put(__bf16 (*plane)[64][16], int u, int r, float v) {
+__device__ __forceinline__ void stage_put(__bf16 (*plane)[64][kRow], int u, int r, float v) {
   const __bf16 h = static_cast<__bf16>(v);
   plane[0][u][r] = h;
   plane[1][u][r] = static_cast<__bf16>(v - static_cast<float>(h));
@@ -308,7 +364,7 @@ struct Split4 {
 };
 
 template <int ROWS>
-__device__ __forceinline__ Split4 stage_read(const __bf16 (*plane)[ROWS][16], int row, int g) {
+__device__ __forceinline__ Split4 stage_read(const __bf16 (*plane)[ROWS][kRow], int row, int g) {
   Split4 v;
   __builtin_memcpy(&v.hi, &plane[0][row][4 * g], sizeof(v.hi));
   __builtin_memcpy(&v.lo, &plane[1][row][4 * g], sizeof(v.lo));
@@ -347,15 +403,14 @@ struct MlpGrads {
 // One group: forward, loss gradient, backward, weight-gradient update.
 // Returns dL/dz (dxz) and dL/dY (dxe) of this lane's sample in the D layout.
 template <int MODE>
-__device__ __forceinline__ void mlp_bwd_group(const MlpShared& sh, MlpStage& sg, MlpGrads& G, int lane, int s,
-                                              bool valid, const uint16_t* __restrict__ zrow, const float d[3],
-                                              int S, const float* __restrict__ dL_dc,
-                                              const float* __restrict__ target, float scale, floatx4& dxz,
-                                              floatx4& dxe) {
+__device__ __forceinline__ void mlp_bwd_group(const MlpShared& sh, MlpStage& sg, MlpGrads& G, int lane,
+                                              const SampleIn& x, const float d[3], bool loss_mode, float scale,
+                                              floatx4& dxz, floatx4& dxe) {
   const int g = lane >> 4, r = lane & 15;
+  const bool valid = x.in;
   const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
   MlpFwdState st;
-  st.X = input_operand(g, valid, zrow, d);
+  st.X = input_operand(g, valid, x.z, d);
   mlp_forward_group(sh, lane, st);
   floatx4 g3 = zero;
   if (g == 0 && valid) {
@@ -363,14 +418,12 @@ __device__ __forceinline__ void mlp_bwd_group(const MlpShared& sh, MlpStage& sg,
     for (int i = 0; i < kMlpOut; ++i) {
       const float c = sigmoidf(st.o[i] + sh.bias[128 + i]);
       float gc;
-      if (MODE == 1) {
-        gc = dL_dc[static_cast<int64_t>(6 + i) * S + s];
-      } else if (target) {
-        const float e = c - target[3 * static_cast<int64_t>(s) + i];
+      if (MODE == 0 && loss_mode) {
+        const float e = c - x.c[i];
         G.loss += scale * e * e;
         gc = 2.0f * scale * e;
       } else {
-        gc = dL_dc[3 * static_cast<int64_t>(s) + i];
+        gc = x.c[i];
       }
       g3[i] = gc * c * (1.0f - c);
       G.db3[i] += g3[i];
@@ -491,24 +544,26 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(int S, int per, const uint16_t*
   // per >= 16: a wave owns whole latents (per / 16 consecutive groups each)
   const int gpl = per >= 16 ? per / 16 : 1;
   const int nunits = ngroups / gpl;
+  const bool loss_mode = (MODE == 0) && target != nullptr;
+  const float* cin = (MODE == 0 && loss_mode) ? target : dL_dc;
+  // groups of this wave in order: units wave_id, wave_id + nwaves, ..., each
+  // unit's gpl groups in turn; the next group's inputs are loaded ahead
+  auto group_of = [&](int unit, int q) { return (unit * gpl + q) * 16 + r; };
+  SampleIn cur = load_sample<MODE, true>(group_of(wave_id, 0), wave_id < nunits ? S : 0, per, g, latents, dirs,
+                                         means, radius, cin, dmean);
   for (int unit = wave_id; unit < nunits; unit += nwaves) {
     floatx4 zacc = zero;
     for (int q = 0; q < gpl; ++q) {
-      const int s = (unit * gpl + q) * 16 + r;
-      bool valid = s < S;
-      float d[3] = {0.f, 0.f, 1.f}, len = 1.f;
-      if (MODE == 0) {
-        if (valid) { d[0] = dirs[3 * s]; d[1] = dirs[3 * s + 1]; d[2] = dirs[3 * s + 2]; }
-      } else {
-        valid = valid && radius[s] > 0;
-        if (valid) {
-          const float m[3] = {means[s], means[S + s], means[2 * S + s]};
-          view_dir(m, cam, d, len);
-        }
-      }
+      const int s = group_of(unit, q);
+      const int nunit = (q + 1 < gpl) ? unit : unit + nwaves;
+      const int nq = (q + 1 < gpl) ? q + 1 : 0;
+      const SampleIn nxt = load_sample<MODE, true>(group_of(nunit, nq), nunit < nunits ? S : 0, per, g, latents,
+                                                   dirs, means, radius, cin, dmean);
+      const bool valid = cur.in;
+      float d[3], len;
+      sample_dir<MODE>(cur, cam, d, len);
       floatx4 dxz, dxe;
-      mlp_bwd_group<MODE>(sh, sg, G, lane, s, valid, latents + static_cast<int64_t>(valid ? s / per : 0) * 16, d,
-                          S, dL_dc, target, scale, dxz, dxe);
+      mlp_bwd_group<MODE>(sh, sg, G, lane, cur, d, loss_mode, scale, dxz, dxe);
       if (per >= 16) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) zacc[i] += row_sum16(dxz[i]);
@@ -539,9 +594,10 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(int S, int per, const uint16_t*
           const float dd = d[0] * gd[0] + d[1] * gd[1] + d[2] * gd[2];
           const float il = 1.0f / len;
 #pragma unroll
-          for (int k = 0; k < 3; ++k) dmean[static_cast<int64_t>(k) * S + s] += (gd[k] - d[k] * dd) * il;
+          for (int k = 0; k < 3; ++k) dmean[static_cast<int64_t>(k) * S + s] = cur.m[k] + (gd[k] - d[k] * dd) * il;
         }
       }
+      cur = nxt;
     }
     if (per >= 16 && r == 0) {
 #pragma unroll
