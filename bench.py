@@ -181,7 +181,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-colour timing")
     ap.add_argument("--compare-plain", action="store_true",
-                    help="also time the SH step with the plain (unbalanced) work split")
+                    help="also time the SH step with the plain and the merged work splits")
     ap.add_argument("--hbm-probe", action="store_true",
                     help="also time a 2 GiB device-to-device copy (achievable HBM bandwidth, counter calibration)")
     args = ap.parse_args()
@@ -247,12 +247,15 @@ def main():
         return ms, st_ms
 
     ms_step, stage_ms = run_timed(step, "SH colour")
-    plain = None
+    other_splits = None
     if args.compare_plain:
-        rast.schedule = gs.SCHEDULE_PLAIN
-        p_ms, p_stage = run_timed(step, "SH colour, plain work split")
+        other_splits = {}
+        for name, sched in (("plain", gs.SCHEDULE_PLAIN), ("merged", gs.SCHEDULE_MERGED)):
+            rast.schedule = sched
+            p_ms, p_stage = run_timed(step, f"SH colour, {name} work split")
+            other_splits[name] = {"ms_per_step": round(p_ms, 4),
+                                  "stages_ms": {k: round(v, 4) for k, v in p_stage.items()}}
         rast.schedule = gs.SCHEDULE_BALANCED
-        plain = {"ms_per_step": round(p_ms, 4), "stages_ms": {k: round(v, 4) for k, v in p_stage.items()}}
 
     # learned colour on the same scene, cameras and targets: random-init
     # decoder (the step's cost does not depend on the weight values)
@@ -346,8 +349,8 @@ def main():
         "roofline": roof,
         "rooflines": rooflines,
     }
-    if plain is not None:
-        result["plain_work_split"] = plain
+    if other_splits is not None:
+        result["other_work_splits"] = other_splits
     if mlp_ms is not None:
         result["learned_colour"] = {"ms_per_step": round(mlp_ms, 4),
                                     "stages_ms": {k: round(v, 4) for k, v in mlp_stage_ms.items()},

@@ -158,15 +158,21 @@ gs_status gs_bin_sort(int64_t n, const gs_projected* proj, const gs_camera* cam,
                       gs_stream stream);
 
 /* Work split of the compositing kernels (Sec. IV: workload imbalance between
- * dense and sparse tiles).  PLAIN: one workgroup per tile, tiles mapped so
- * that neighbours share an XCD.  BALANCED: a plan built on the device from
- * each tile's work count (list length for the forward, largest n_contrib for
- * the backward) starts the heavy tiles -- above four times the mean count --
- * first, largest first, and maps the rest as in PLAIN.  Per-tile arithmetic
- * is identical, so both give the same image (bit for bit) and the same
- * gradients up to the order of the atomic sums. */
+ * dense and sparse tiles, adaptive merging of thread blocks).  PLAIN: one
+ * workgroup per tile, tiles mapped so that neighbours share an XCD.
+ * BALANCED: the backward builds a plan on the device from each tile's work
+ * count (the largest n_contrib of its pixels, left by the forward in t_ckpt):
+ * heavy tiles -- above four times the mean count -- start first, largest
+ * first, tiles with nothing to walk are skipped, the rest are mapped as in
+ * PLAIN; the forward, which has no such count before it runs, stays PLAIN.
+ * MERGED: BALANCED plus light tiles (at most 64 entries to walk) merged four
+ * to a workgroup, one wave per tile and four pixels per lane, in both
+ * directions.  Per-tile arithmetic is identical in all three, so they give
+ * the same image (bit for bit) and the same gradients up to the order of the
+ * atomic sums. */
 #define GS_SCHEDULE_PLAIN 0
 #define GS_SCHEDULE_BALANCED 1
+#define GS_SCHEDULE_MERGED 2
 
 /* Forward compositing (Sec. II-A, C = sum_i c_i alpha_i prod_{j<i} (1 - alpha_j)
  * over the tile's depth-ordered list).  Per pixel: power = -1/2 (A dx^2 +

@@ -150,10 +150,10 @@ gs_status gs_render_fwd(int64_t n, const gs_projected* proj, const uint32_t* poi
   if ((st = validate_projected(proj, n, "gs_render_fwd")) != GS_OK) return st;
   if (!ranges || !image || !final_T || !n_contrib || (k > 0 && !point_list))
     return fail(GS_ERR_INVALID_ARG, "gs_render_fwd: NULL array");
-  if (schedule != GS_SCHEDULE_PLAIN && schedule != GS_SCHEDULE_BALANCED)
+  if (schedule < GS_SCHEDULE_PLAIN || schedule > GS_SCHEDULE_MERGED)
     return fail(GS_ERR_INVALID_ARG, "gs_render_fwd: unknown schedule");
-  if (schedule == GS_SCHEDULE_BALANCED && !t_ckpt)
-    return fail(GS_ERR_INVALID_ARG, "gs_render_fwd: the balanced schedule keeps its plan in t_ckpt");
+  if (schedule != GS_SCHEDULE_PLAIN && !t_ckpt)
+    return fail(GS_ERR_INVALID_ARG, "gs_render_fwd: the balanced schedules keep their plan in t_ckpt");
   return launch_render_fwd(*proj, point_list, ranges, k, make_devcam(*cam), image, final_T, n_contrib, t_ckpt,
                            schedule, static_cast<hipStream_t>(stream));
 }
@@ -202,7 +202,7 @@ gs_status gs_render_bwd(int64_t n, const gs_projected* proj, const uint32_t* poi
   if (!ranges || !final_T || !n_contrib || !t_ckpt || !dL_dimage || (n > 0 && !g2d) || (k > 0 && !point_list))
     return fail(GS_ERR_INVALID_ARG, "gs_render_bwd: NULL array");
   const DevCam d = make_devcam(*cam);
-  if (schedule != GS_SCHEDULE_PLAIN && schedule != GS_SCHEDULE_BALANCED)
+  if (schedule < GS_SCHEDULE_PLAIN || schedule > GS_SCHEDULE_MERGED)
     return fail(GS_ERR_INVALID_ARG, "gs_render_bwd: unknown schedule");
   if (ws_bytes < render_bwd_workspace(n, k, d.tiles_x * d.tiles_y, deterministic) || !ws)
     return fail(GS_ERR_INVALID_ARG, "gs_render_bwd: workspace too small");

@@ -145,10 +145,18 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint32_t* __restri
   __syncthreads();
   const uint32_t mask = (1u << nbits) - 1u;
   const int64_t base = static_cast<int64_t>(blockIdx.x) * CHUNK;
+  // all loads first, so that they are in flight together
+  uint32_t kk[ITEMS];
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const int64_t idx = base + j * kRsThreads + threadIdx.x;
+    kk[j] = idx < count ? keys[idx] : 0u;
+  }
+#pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
     const int64_t idx = base + j * kRsThreads + threadIdx.x;
     const bool valid = idx < count;
-    const uint32_t d = valid ? ((keys[idx] >> shift) & mask) : 0u;
+    const uint32_t d = (kk[j] >> shift) & mask;
     const uint64_t peers = match_digit(d, nbits, valid);
     if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&cnt[d], static_cast<uint32_t>(__popcll(peers)));
   }
@@ -333,7 +341,13 @@ __global__ __launch_bounds__(256) void k_emit(int n, const uint32_t* __restrict_
     }
     const uint32_t j = p - s_pre[wave][lo];
     const uint32_t w = static_cast<uint32_t>(s_w[wave][lo]);
-    const uint32_t row = j / w, col = j - row * w;
+    // row = j / w without an integer division: the float quotient is within
+    // one of the exact one for j, w < 2^24 (tiles of a rectangle), corrected
+    // by one integer step
+    uint32_t row = static_cast<uint32_t>(static_cast<float>(j) * __builtin_amdgcn_rcpf(static_cast<float>(w)));
+    if (row * w > j) --row;
+    else if ((row + 1) * w <= j) ++row;
+    const uint32_t col = j - row * w;
     tile_keys[base + p] = static_cast<uint32_t>((s_y0[wave][lo] + static_cast<int>(row)) * tiles_x +
                                                 s_x0[wave][lo] + static_cast<int>(col));
     gids[base + p] = s_gid[wave][lo];

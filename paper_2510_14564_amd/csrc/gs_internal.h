@@ -46,7 +46,8 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // (largest n_contrib of its pixels), which the backward plans from.
 inline size_t ckpt_core_floats(int64_t k, int64_t ntiles) { return static_cast<size_t>(k / 256 + ntiles + 1) * 256; }
 inline size_t ckpt_floats(int64_t k, int64_t ntiles) {
-  return ckpt_core_floats(k, ntiles) + 16 + 4 * static_cast<size_t>(ntiles) + static_cast<size_t>(ntiles);
+  // plan: 16-value header + one entry per tile; work counts: one per tile
+  return ckpt_core_floats(k, ntiles) + 16 + 2 * static_cast<size_t>(ntiles);
 }
 
 // Aligned carve-out of a caller-supplied workspace.

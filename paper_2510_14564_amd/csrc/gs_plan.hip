@@ -25,77 +25,82 @@ constexpr int kPlanThreads = 1024;
 constexpr int kHeavyCap = 1024;    // at most this many heavy tiles are ordered
 
 // Plan workspace in int32 values for ntiles tiles.
-size_t plan_ints(int ntiles) { return kPlanHeader + 4 * static_cast<size_t>(ntiles); }
+size_t plan_ints(int ntiles) { return kPlanHeader + static_cast<size_t>(ntiles); }
 
-// counts == NULL: a tile's count is its list length from ranges.
+// counts == NULL: a tile's count is its list length from ranges.  Thread t
+// owns a contiguous run of tiles, so one block-wide scan of three class
+// counts gives every tile its place (tile order inside each class).
 __global__ __launch_bounds__(kPlanThreads) void k_tile_plan(int ntiles, const uint2* __restrict__ ranges,
                                                             const uint32_t* __restrict__ counts,
                                                             float heavy_factor, int light_max,
                                                             int32_t* __restrict__ plan) {
   __shared__ float s_red[kPlanThreads / 64];
+  __shared__ uint32_t s_scan[3][kPlanThreads / 64];
   __shared__ uint32_t s_hw[kHeavyCap];
   __shared__ int s_ht[kHeavyCap];
-  __shared__ int s_wave_cnt[3][kPlanThreads / 64];
-  __shared__ int s_base[3];
-  __shared__ int s_over;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int32_t* const order = plan + kPlanHeader;
-  int32_t* const med = order + ntiles;           // staging: medium tiles in tile order
-  int32_t* const lig = med + ntiles;             // staging: light tiles in tile order
-  int32_t* const over = lig + ntiles;            // staging: heavy tiles beyond the cap
   auto count_of = [&](int t) -> uint32_t { return counts ? counts[t] : (ranges[t].y - ranges[t].x); };
+  const int per = (ntiles + kPlanThreads - 1) / kPlanThreads;
+  const int t0 = min(ntiles, tid * per), t1 = min(ntiles, t0 + per);
 
   float sum = 0.f;
-  for (int t = tid; t < ntiles; t += kPlanThreads) sum += static_cast<float>(count_of(t));
+  for (int t = t0; t < t1; ++t) sum += static_cast<float>(count_of(t));
   for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
   if (lane == 0) s_red[wave] = sum;
-  if (tid < 3) s_base[tid] = 0;
-  if (tid == 0) s_over = 0;
   __syncthreads();
   float total = 0.f;
   for (int w = 0; w < kPlanThreads / 64; ++w) total += s_red[w];
   const float thresh = fmaxf(heavy_factor * total / static_cast<float>(max(ntiles, 1)),
                              static_cast<float>(light_max));
-  const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-
-  // chunked, order-preserving split into the three classes
-  for (int c0 = 0; c0 < ntiles; c0 += kPlanThreads) {
-    const int t = c0 + tid;
-    int cls = -1;
-    uint32_t w = 0;
-    if (t < ntiles) {
-      w = count_of(t);
-      cls = static_cast<float>(w) > thresh ? 0 : (static_cast<int>(w) <= light_max ? 2 : 1);
-    }
-    int rank = 0;
+  auto cls_of = [&](uint32_t w) -> int {
+    return static_cast<float>(w) > thresh ? 0 : (static_cast<int>(w) <= light_max ? 2 : 1);
+  };
+  // per-thread class counts, then an exclusive scan over threads (wave
+  // shuffles, then the wave totals in LDS)
+  uint32_t c[3] = {0u, 0u, 0u};
+  for (int t = t0; t < t1; ++t) ++c[cls_of(count_of(t))];
+  uint32_t ex[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const uint64_t bal = __ballot(cls == k);
-      if (cls == k) rank = __popcll(bal & below);
-      if (lane == 0) s_wave_cnt[k][wave] = __popcll(bal);
+  for (int k = 0; k < 3; ++k) {
+    uint32_t incl = c[k];
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t v = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += v;
     }
-    __syncthreads();
-    if (cls >= 0) {
-      int pos = s_base[cls] + rank;
-      for (int v = 0; v < wave; ++v) pos += s_wave_cnt[cls][v];
-      if (cls == 0) {
-        if (pos < kHeavyCap) { s_hw[pos] = w; s_ht[pos] = t; }
-        else over[atomicAdd(&s_over, 1)] = t;
-      } else if (cls == 1) {
-        med[pos] = t;
-      } else {
-        lig[pos] = t;
-      }
-    }
-    __syncthreads();
-    if (tid < 3) {
-      int add = 0;
-      for (int v = 0; v < kPlanThreads / 64; ++v) add += s_wave_cnt[tid][v];
-      s_base[tid] += add;
-    }
-    __syncthreads();
+    ex[k] = incl - c[k];
+    if (lane == 63) s_scan[k][wave] = incl;
   }
-  const int H = min(s_base[0], kHeavyCap), O = s_over, M = s_base[1], L = s_base[2];
+  __syncthreads();
+  uint32_t tot[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    uint32_t before = 0, all = 0;
+    for (int w = 0; w < kPlanThreads / 64; ++w) {
+      const uint32_t v = s_scan[k][w];
+      before += (w < wave) ? v : 0u;
+      all += v;
+    }
+    ex[k] += before;
+    tot[k] = all;
+  }
+  const int H = static_cast<int>(min(tot[0], static_cast<uint32_t>(kHeavyCap)));
+  const int O = static_cast<int>(tot[0]) - H;          // heavy beyond the cap: placed after the medium ones
+  const int M = static_cast<int>(tot[1]), L = static_cast<int>(tot[2]);
+  for (int t = t0; t < t1; ++t) {
+    const uint32_t w = count_of(t);
+    const int k = cls_of(w);
+    const int pos = static_cast<int>(ex[k]++);
+    if (k == 0) {
+      if (pos < kHeavyCap) { s_hw[pos] = w; s_ht[pos] = t; }
+      else order[H + M + (pos - kHeavyCap)] = t;
+    } else if (k == 1) {
+      order[H + pos] = t;
+    } else {
+      order[H + M + O + pos] = t;
+    }
+  }
+  __syncthreads();
   // heavy tiles: rank by (count descending, tile ascending)
   for (int i = tid; i < H; i += kPlanThreads) {
     const uint32_t wi = s_hw[i];
@@ -107,9 +112,6 @@ __global__ __launch_bounds__(kPlanThreads) void k_tile_plan(int ntiles, const ui
     }
     order[r] = ti;
   }
-  for (int i = tid; i < M; i += kPlanThreads) order[H + i] = med[i];
-  for (int i = tid; i < O; i += kPlanThreads) order[H + M + i] = over[i];
-  for (int i = tid; i < L; i += kPlanThreads) order[H + M + O + i] = lig[i];
   if (tid == 0) {
     plan[0] = H;
     plan[1] = M + O;

@@ -383,7 +383,7 @@ gs_status launch_render_fwd(const gs_projected& proj, const uint32_t* point_list
     float* tail = t_ckpt + ckpt_core_floats(k, ntiles);
     plan = reinterpret_cast<int32_t*>(tail);
     tile_work = reinterpret_cast<uint32_t*>(tail + plan_ints(ntiles));
-    if (schedule == 1) {
+    if (schedule == 2) {
       gs_status st = launch_tile_plan(ntiles, ranges, nullptr, kHeavyFactorFwd, kLightMax, plan, s);
       if (st != GS_OK) return st;
       k_render_fwd_light<<<static_cast<unsigned>(ceil_div(ntiles, 4)), 256, 0, s>>>(
@@ -709,18 +709,22 @@ gs_status launch_render_bwd(int64_t n, const gs_projected& proj, const uint32_t*
                            "hipMemsetAsync(acc)");
   if (st != GS_OK) return st;
   int32_t* plan = nullptr;
-  if (schedule == 1) {
-    // plan from the forward's per-tile work counts (largest n_contrib)
+  if (schedule >= 1) {
+    // plan from the forward's per-tile work counts (largest n_contrib).  BALANCED
+    // leaves tiles with nothing to walk out (their light class, limit 0);
+    // MERGED hands tiles with at most kLightMax entries to the merged kernel.
     const float* tail = t_ckpt + ckpt_core_floats(k, ntiles);
     const uint32_t* tile_work = reinterpret_cast<const uint32_t*>(tail + plan_ints(ntiles));
     plan = reinterpret_cast<int32_t*>(static_cast<char*>(ws) + 256);
-    st = launch_tile_plan(ntiles, ranges, tile_work, kHeavyFactor, kLightMax, plan, s);
+    st = launch_tile_plan(ntiles, ranges, tile_work, kHeavyFactor, schedule == 2 ? kLightMax : 0, plan, s);
     if (st != GS_OK) return st;
-    k_render_bwd_light<<<static_cast<unsigned>(ceil_div(ntiles, 4)), 256, 0, s>>>(
-        reinterpret_cast<const uint2*>(ranges), point_list, reinterpret_cast<const float4*>(proj.records), cam,
-        final_T, n_contrib, dL_dimage, static_cast<int>(n), acc, plan);
-    st = check_launch("k_render_bwd_light");
-    if (st != GS_OK) return st;
+    if (schedule == 2) {
+      k_render_bwd_light<<<static_cast<unsigned>(ceil_div(ntiles, 4)), 256, 0, s>>>(
+          reinterpret_cast<const uint2*>(ranges), point_list, reinterpret_cast<const float4*>(proj.records), cam,
+          final_T, n_contrib, dL_dimage, static_cast<int>(n), acc, plan);
+      st = check_launch("k_render_bwd_light");
+      if (st != GS_OK) return st;
+    }
   }
   k_render_bwd<<<ntiles, 256, 0, s>>>(reinterpret_cast<const uint2*>(ranges), point_list,
                                       reinterpret_cast<const float4*>(proj.records), cam, final_T, n_contrib,

@@ -28,7 +28,7 @@ L1_PARTIALS = 1024
 MLP_PARAMS = 6467
 MLP_PACKED_BYTES = 31244
 
-SCHEDULE_PLAIN, SCHEDULE_BALANCED = 0, 1
+SCHEDULE_PLAIN, SCHEDULE_BALANCED, SCHEDULE_MERGED = 0, 1, 2
 GS_OK, GS_ERR_INVALID_ARG, GS_ERR_CAPACITY, GS_ERR_HIP, GS_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
 STATUS_NAMES = {0: "GS_OK", -1: "GS_ERR_INVALID_ARG", -2: "GS_ERR_CAPACITY", -3: "GS_ERR_HIP",
                 -4: "GS_ERR_UNSUPPORTED"}

@@ -122,7 +122,7 @@ def test_render_calls_reject_nulls(gs):
     assert st == gs.GS_ERR_INVALID_ARG
     # an unknown schedule, and the balanced schedule without its plan storage
     p = ctypes.c_void_p(0x1000)
-    for sched, ck in ((2, p), (-1, p), (gs.SCHEDULE_BALANCED, NULL)):
+    for sched, ck in ((3, p), (-1, p), (gs.SCHEDULE_BALANCED, NULL), (gs.SCHEDULE_MERGED, NULL)):
         st = gs._lib.gs_render_fwd(10, ctypes.byref(_proj(gs)), p, p, 5, ctypes.byref(c), p, p, p, ck, sched, NULL)
         assert st == gs.GS_ERR_INVALID_ARG, sched
         assert "schedule" in gs.last_error()

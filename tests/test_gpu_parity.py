@@ -122,9 +122,10 @@ def test_staged_parity(gs, name):
     o_img, o_T, o_nc, o_fl = oracle.render_fwd(h["rec"][:, :9], o_pl, o_ranges, cam, margin=1e-4)
     err, nflag = compare_render(image, fT, nc, o_img, o_T, o_nc, o_fl)
     say(f"  render fwd: max err {err:.2e}, flagged pixels {nflag}")
-    # the plain work split gives the same image bit for bit
-    image_p, fT_p, nc_p, ck_p = gpu_render(gs, scene.n, out, pl, ranges, k, cam, schedule=gs.SCHEDULE_PLAIN)
-    assert torch.equal(image, image_p) and torch.equal(fT, fT_p) and torch.equal(nc, nc_p)
+    # the other work splits give the same image bit for bit
+    for sched in (gs.SCHEDULE_PLAIN, gs.SCHEDULE_MERGED):
+        image_p, fT_p, nc_p, _ = gpu_render(gs, scene.n, out, pl, ranges, k, cam, schedule=sched)
+        assert torch.equal(image, image_p) and torch.equal(fT, fT_p) and torch.equal(nc, nc_p), sched
 
     # ---- 4: render backward (flagged pixels carry no upstream gradient)
     G = scenes.upstream_grad(cam, 1001)
@@ -139,11 +140,12 @@ def test_staged_parity(gs, name):
                                       stats=mass_used))
     say(f"  render bwd: worst rel err {worst:.2e}; entries judged against term mass: "
         f"{sum(mass_used.values())} of {g2d_h.size}")
-    # the plain work split: same gradients up to the order of the atomic sums
-    g2d_p = gpu_render_bwd(gs, scene.n, out, pl, ranges, k, cam, fT, nc, ck, to_dev(G),
-                           schedule=gs.SCHEDULE_PLAIN).cpu().numpy().T
-    for j, nm in enumerate("u v Sxx Sxy Syy o r g b".split()):
-        grad_close(g2d_p[:, j], o_g2d[:, j], name=f"plain g2d.{nm}", mass=o_mass[:, j])
+    # the other work splits: same gradients up to the order of the atomic sums
+    for sched in (gs.SCHEDULE_PLAIN, gs.SCHEDULE_MERGED):
+        g2d_p = gpu_render_bwd(gs, scene.n, out, pl, ranges, k, cam, fT, nc, ck, to_dev(G),
+                               schedule=sched).cpu().numpy().T
+        for j, nm in enumerate("u v Sxx Sxy Syy o r g b".split()):
+            grad_close(g2d_p[:, j], o_g2d[:, j], name=f"schedule {sched} g2d.{nm}", mass=o_mass[:, j])
 
     # ---- 5: projection backward from the HIP path's g2d
     grads = {kk: torch.empty_like(v) for kk, v in p.items()}
