@@ -160,16 +160,18 @@ gs_status gs_bin_sort(int64_t n, const gs_projected* proj, const gs_camera* cam,
 /* Work split of the compositing kernels (Sec. IV: workload imbalance between
  * dense and sparse tiles, adaptive merging of thread blocks).  PLAIN: one
  * workgroup per tile, tiles mapped so that neighbours share an XCD.
- * BALANCED: the backward builds a plan on the device from each tile's work
- * count (the largest n_contrib of its pixels, left by the forward in t_ckpt):
- * heavy tiles -- above four times the mean count -- start first, largest
- * first, tiles with nothing to walk are skipped, the rest are mapped as in
- * PLAIN; the forward, which has no such count before it runs, stays PLAIN.
- * MERGED: BALANCED plus light tiles (at most 64 entries to walk) merged four
- * to a workgroup, one wave per tile and four pixels per lane, in both
- * directions.  Per-tile arithmetic is identical in all three, so they give
- * the same image (bit for bit) and the same gradients up to the order of the
- * atomic sums. */
+ * BALANCED: the backward gives every 256-entry batch of a tile's walk its
+ * own workgroup -- (tile, batch) items planned on the device from the
+ * largest n_contrib of each tile, which the forward leaves in t_ckpt -- and
+ * starts each batch's walk from the forward's checkpoints at the batch end
+ * (the transmittance and the per-batch colour sums, so the light behind is
+ * a sum of non-negative terms); tiles with nothing to walk are skipped.  The
+ * forward, which has no work count before it runs, stays PLAIN.  MERGED:
+ * BALANCED plus light tiles (at most 64 entries to walk) merged four to a
+ * workgroup, one wave per tile and four pixels per lane, in both directions.
+ * Per-pixel arithmetic is the same in all three, so they give the same image
+ * (bit for bit) and the same gradients up to rounding (order of the atomic
+ * sums; the light behind from batch sums). */
 #define GS_SCHEDULE_PLAIN 0
 #define GS_SCHEDULE_BALANCED 1
 #define GS_SCHEDULE_MERGED 2

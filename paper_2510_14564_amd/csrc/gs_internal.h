@@ -43,11 +43,13 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Transmittance checkpoint buffer for K entries over `ntiles` tiles: the
 // checkpoints, then the forward's tile plan, then each tile's work count
-// (largest n_contrib of its pixels), which the backward plans from.
+// (largest n_contrib of its pixels), which the backward plans from, then the
+// forward's per-batch colour sums (three planes laid out like the checkpoints).
 inline size_t ckpt_core_floats(int64_t k, int64_t ntiles) { return static_cast<size_t>(k / 256 + ntiles + 1) * 256; }
 inline size_t ckpt_floats(int64_t k, int64_t ntiles) {
-  // plan: 16-value header + one entry per tile; work counts: one per tile
-  return ckpt_core_floats(k, ntiles) + 16 + 2 * static_cast<size_t>(ntiles);
+  // plan: 16-value header + one entry per tile; work counts: one per tile;
+  // then the per-batch colour sums, three planes of the checkpoint layout
+  return 4 * ckpt_core_floats(k, ntiles) + 16 + 2 * static_cast<size_t>(ntiles);
 }
 
 // Aligned carve-out of a caller-supplied workspace.
@@ -112,6 +114,12 @@ constexpr int kPlanHeader = 16;
 size_t plan_ints(int ntiles);
 gs_status launch_tile_plan(int ntiles, const uint32_t* ranges, const uint32_t* counts, float heavy_factor,
                            int light_max, int32_t* plan, hipStream_t s);
+gs_status launch_batch_plan(int ntiles, const uint32_t* ranges, const uint32_t* work, int light_max, int32_t* items,
+                            int32_t* light, hipStream_t s);
+// Backward work items (pairs) for K entries over ntiles tiles, with header.
+inline size_t batch_item_ints(int64_t k, int64_t ntiles) {
+  return 16 + 2 * static_cast<size_t>(k / 256 + ntiles + 1);
+}
 gs_status launch_project_bwd(const gs_gaussians& g, const DevCam& cam, const int* radius, const float* g2d,
                              gs_gaussians_grad& grad, void* ws, hipStream_t s);
 size_t binsort_workspace(int64_t n, int64_t capacity, int ntiles);

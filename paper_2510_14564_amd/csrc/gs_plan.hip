@@ -120,6 +120,76 @@ __global__ __launch_bounds__(kPlanThreads) void k_tile_plan(int ntiles, const ui
   }
 }
 
+// Backward work items: every batch of 256 list entries that some pixel of
+// the tile walks becomes its own workgroup, (tile, batch) in tile order.  A
+// tile's walk length is min(list length, largest n_contrib) -- the count the
+// forward left in `work`.  Tiles with a count of at most light_max go to the
+// light list instead (a plan with H = M = 0), or nowhere when light is NULL
+// (with light_max = 0: the tiles whose pixels blend nothing).
+// items: [0] item count, from kPlanHeader pairs (tile, batch).
+__global__ __launch_bounds__(kPlanThreads) void k_batch_plan(int ntiles, const uint2* __restrict__ ranges,
+                                                             const uint32_t* __restrict__ work, int light_max,
+                                                             int32_t* __restrict__ items,
+                                                             int32_t* __restrict__ light) {
+  __shared__ uint32_t s_scan[2][kPlanThreads / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int per = (ntiles + kPlanThreads - 1) / kPlanThreads;
+  const int t0 = min(ntiles, tid * per), t1 = min(ntiles, t0 + per);
+  auto batches_of = [&](int t) -> uint32_t {
+    const uint32_t len = min(ranges[t].y - ranges[t].x, work[t]);
+    return static_cast<int>(work[t]) <= light_max ? 0u : (len + 255u) / 256u;
+  };
+  auto is_light = [&](int t) -> bool { return work[t] > 0u && static_cast<int>(work[t]) <= light_max; };
+  uint32_t c[2] = {0u, 0u};
+  for (int t = t0; t < t1; ++t) {
+    c[0] += batches_of(t);
+    c[1] += is_light(t) ? 1u : 0u;
+  }
+  uint32_t ex[2], tot[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    uint32_t incl = c[k];
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t v = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += v;
+    }
+    ex[k] = incl - c[k];
+    if (lane == 63) s_scan[k][wave] = incl;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    uint32_t before = 0, all = 0;
+    for (int w = 0; w < kPlanThreads / 64; ++w) {
+      const uint32_t v = s_scan[k][w];
+      before += (w < wave) ? v : 0u;
+      all += v;
+    }
+    ex[k] += before;
+    tot[k] = all;
+  }
+  for (int t = t0; t < t1; ++t) {
+    const uint32_t nb = batches_of(t);
+    for (uint32_t j = 0; j < nb; ++j) {
+      items[kPlanHeader + 2 * (ex[0] + j)] = t;
+      items[kPlanHeader + 2 * (ex[0] + j) + 1] = static_cast<int32_t>(j);
+    }
+    ex[0] += nb;
+    if (light && is_light(t)) light[kPlanHeader + ex[1]++] = t;
+  }
+  if (tid == 0) {
+    items[0] = static_cast<int32_t>(tot[0]);
+    if (light) { light[0] = 0; light[1] = 0; light[2] = static_cast<int32_t>(tot[1]); light[3] = 0; }
+  }
+}
+
+gs_status launch_batch_plan(int ntiles, const uint32_t* ranges, const uint32_t* work, int light_max, int32_t* items,
+                            int32_t* light, hipStream_t s) {
+  k_batch_plan<<<1, kPlanThreads, 0, s>>>(ntiles, reinterpret_cast<const uint2*>(ranges), work, light_max, items,
+                                          light);
+  return check_launch("k_batch_plan");
+}
+
 gs_status launch_tile_plan(int ntiles, const uint32_t* ranges, const uint32_t* counts, float heavy_factor,
                            int light_max, int32_t* plan, hipStream_t s) {
   k_tile_plan<<<1, kPlanThreads, 0, s>>>(ntiles, reinterpret_cast<const uint2*>(ranges), counts, heavy_factor,

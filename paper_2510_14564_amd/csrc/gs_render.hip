@@ -81,13 +81,10 @@ __device__ __forceinline__ uint32_t uniform(uint32_t x) {
 }
 constexpr int kListStride = kBatch + 4; // per-wave list of staged slots, padded to kUnroll
 
-// Work-split threshold: a tile is heavy when its work count exceeds this
-// multiple of the mean count over all tiles (tuned by measurement).  The
-// backward's count (largest n_contrib) is its exact walk length; the
-// forward's only count before it runs is the list length, which does not
-// predict where pixels saturate (measured: ordering the forward by it made
-// the launch slower), so the forward uses the plan only to merge light tiles.
-constexpr float kHeavyFactor = 4.0f;
+// The forward's only work count before it runs is the list length, which does
+// not predict where pixels saturate (measured: ordering the forward by it made
+// the launch slower), so its plan never marks tiles heavy and serves only to
+// merge light tiles.
 constexpr float kHeavyFactorFwd = 3.0e38f;
 
 // Tile of workgroup `bid`.  Plain form: XCD-aware spatial map.  With a plan
@@ -227,7 +224,8 @@ __global__ __launch_bounds__(256) void k_render_fwd(const uint2* __restrict__ ra
                                                     uint32_t* __restrict__ n_contrib, float* __restrict__ t_ckpt,
                                                     unsigned long long* __restrict__ counts,
                                                     const int32_t* __restrict__ plan,
-                                                    uint32_t* __restrict__ tile_work) {
+                                                    uint32_t* __restrict__ tile_work,
+                                                    float* __restrict__ c_ckpt, size_t cplane) {
   __shared__ Stage st;
   __shared__ uint32_t s_work;
   const int tile = tile_of_block(plan, blockIdx.x, gridDim.x);
@@ -252,6 +250,10 @@ __global__ __launch_bounds__(256) void k_render_fwd(const uint2* __restrict__ ra
   uint32_t contrib = 0, n_exam = 0, n_blend = 0;
   bool done = !inside;
   const size_t slot0 = ckpt_slot0(rg.x, tile);
+  // colour is summed per batch and the batch sums are added up; for tiles of
+  // several batches each batch sum is kept (c_ckpt), so that a backward walk
+  // can start at any batch end from the light behind it
+  const bool multi = (rg.y - rg.x) > static_cast<uint32_t>(kBatch);
 
   for (uint32_t base = rg.x, b = 0; base < rg.y; base += kBatch, ++b) {
     if (__syncthreads_count(done) == 256) break;
@@ -263,6 +265,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(const uint2* __restrict__ ra
     __syncthreads();
     const uint32_t m0 = base - rg.x + 1u;
     const int L = st.len[wave];
+    float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
     for (int i0 = 0; i0 < L; i0 += kUnroll) {
       if (__ballot(!done) == 0) break;  // whole wave finished: leave the batch
       const uint4 jj = *reinterpret_cast<const uint4*>(&st.list[wave][i0]);
@@ -271,10 +274,19 @@ __global__ __launch_bounds__(256) void k_render_fwd(const uint2* __restrict__ ra
       for (int u = 0; u < kUnroll; ++u) {
         const uint32_t j = js[u];
         if (COUNT) n_exam += (!done && j != kNull) ? 1u : 0u;
-        const bool blend = fwd_pair(st.p[j], st.q[j], st.c[j].x, px, py, m0 + j, T, acc0, acc1, acc2, contrib, done);
+        const bool blend = fwd_pair(st.p[j], st.q[j], st.c[j].x, px, py, m0 + j, T, s0, s1, s2, contrib, done);
         if (COUNT) n_blend += blend ? 1u : 0u;
       }
     }
+    if (!COUNT && c_ckpt && multi) {
+      const size_t o = (slot0 + b) * kBatch + threadIdx.x;
+      c_ckpt[o] = s0;
+      c_ckpt[cplane + o] = s1;
+      c_ckpt[2 * cplane + o] = s2;
+    }
+    acc0 += s0;
+    acc1 += s1;
+    acc2 += s2;
   }
   if (COUNT) {
     __shared__ unsigned long long s_cnt[2];
@@ -379,10 +391,13 @@ gs_status launch_render_fwd(const gs_projected& proj, const uint32_t* point_list
   const int ntiles = cam.tiles_x * cam.tiles_y;
   int32_t* plan = nullptr;
   uint32_t* tile_work = nullptr;
+  float* c_ckpt = nullptr;
+  const size_t cplane = ckpt_core_floats(k, ntiles);
   if (t_ckpt) {
     float* tail = t_ckpt + ckpt_core_floats(k, ntiles);
     plan = reinterpret_cast<int32_t*>(tail);
     tile_work = reinterpret_cast<uint32_t*>(tail + plan_ints(ntiles));
+    c_ckpt = tail + plan_ints(ntiles) + ntiles;
     if (schedule == 2) {
       gs_status st = launch_tile_plan(ntiles, ranges, nullptr, kHeavyFactorFwd, kLightMax, plan, s);
       if (st != GS_OK) return st;
@@ -397,7 +412,7 @@ gs_status launch_render_fwd(const gs_projected& proj, const uint32_t* point_list
   }
   k_render_fwd<false><<<ntiles, 256, 0, s>>>(reinterpret_cast<const uint2*>(ranges), point_list,
                                              reinterpret_cast<const float4*>(proj.records), cam, image, final_T,
-                                             n_contrib, t_ckpt, nullptr, plan, tile_work);
+                                             n_contrib, t_ckpt, nullptr, plan, tile_work, c_ckpt, cplane);
   return check_launch("k_render_fwd");
 }
 
@@ -408,7 +423,7 @@ gs_status launch_render_count(const gs_projected& proj, const uint32_t* point_li
   if (st != GS_OK) return st;
   k_render_fwd<true><<<ntiles, 256, 0, s>>>(reinterpret_cast<const uint2*>(ranges), point_list,
                                             reinterpret_cast<const float4*>(proj.records), cam, nullptr, nullptr,
-                                            nullptr, nullptr, counts, nullptr, nullptr);
+                                            nullptr, nullptr, counts, nullptr, nullptr, nullptr, 0);
   return check_launch("k_render_count");
 }
 
@@ -538,11 +553,25 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
                                                     const uint32_t* __restrict__ n_contrib,
                                                     const float* __restrict__ t_ckpt,
                                                     const float* __restrict__ dL_dimage, int n,
-                                                    float* __restrict__ acc, const int32_t* __restrict__ plan) {
+                                                    float* __restrict__ acc, const int32_t* __restrict__ plan,
+                                                    const int32_t* __restrict__ items,
+                                                    const uint32_t* __restrict__ tile_work,
+                                                    const float* __restrict__ c_ckpt, size_t cplane) {
   __shared__ Stage st;
   __shared__ uint32_t s_max;
-  const int tile = tile_of_block(plan, blockIdx.x, gridDim.x);
-  if (tile < 0) return;
+  // items: this workgroup walks one batch of one tile (the batch plan);
+  // otherwise the whole tile (plain map, or the plan's order)
+  int tile, b_only = -1;
+  if (items) {
+    const int nitems = items[0];
+    if (static_cast<int>(blockIdx.x) >= nitems) return;
+    const int it = xcd_remap(blockIdx.x, nitems);
+    tile = items[kPlanHeader + 2 * it];
+    b_only = items[kPlanHeader + 2 * it + 1];
+  } else {
+    tile = tile_of_block(plan, blockIdx.x, gridDim.x);
+    if (tile < 0) return;
+  }
   const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
   int lx, ly;
   tile_pixel(threadIdx.x, lx, ly);
@@ -570,14 +599,31 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
   const float T_final = T;
   const size_t slot0 = ckpt_slot0(rg.x, tile);
   float GS = T * (G0 * cam.bg[0] + G1 * cam.bg[1] + G2 * cam.bg[2]);
-  if (threadIdx.x == 0) s_max = 0;
-  __syncthreads();
-  if (ncon) atomicMax(&s_max, ncon);
-  __syncthreads();
-  const uint32_t len = min(rg.y - rg.x, s_max);  // n_contrib never exceeds the list
+  uint32_t smax;
+  if (tile_work) {
+    smax = tile_work[tile];  // the largest n_contrib of the tile, from the forward
+  } else {
+    if (threadIdx.x == 0) s_max = 0;
+    __syncthreads();
+    if (ncon) atomicMax(&s_max, ncon);
+    __syncthreads();
+    smax = s_max;
+  }
+  const uint32_t len = min(rg.y - rg.x, smax);  // n_contrib never exceeds the list
   const int nbatch = static_cast<int>((len + kBatch - 1) / kBatch);
+  int b_hi = nbatch - 1, b_lo = 0;
+  if (b_only >= 0) {
+    b_hi = b_lo = b_only;
+    // light behind the end of this batch: the forward's colour sums of the
+    // pixel's later batches (each a sum of non-negative terms), dotted with G
+    const int last = ncon ? static_cast<int>((ncon - 1) / kBatch) : -1;
+    for (int bb = b_only + 1; bb <= last; ++bb) {
+      const size_t o = (slot0 + bb) * kBatch + threadIdx.x;
+      GS += G0 * c_ckpt[o] + G1 * c_ckpt[cplane + o] + G2 * c_ckpt[2 * cplane + o];
+    }
+  }
 
-  for (int bi = nbatch - 1; bi >= 0; --bi) {
+  for (int bi = b_hi; bi >= b_lo; --bi) {
     const uint32_t m0 = static_cast<uint32_t>(bi) * kBatch;
     const int cnt = static_cast<int>(min(static_cast<uint32_t>(kBatch), len - m0));
     T = (bi + 1 < nbatch) ? t_ckpt[(slot0 + bi + 1) * kBatch + threadIdx.x] : T_final;
@@ -686,15 +732,16 @@ __global__ __launch_bounds__(256) void k_render_bwd_light(const uint2* __restric
   }
 }
 
-// Workspace: 256 reserved bytes, the backward's tile plan, then the
-// accumulator rows (256-byte aligned).
-static size_t bwd_acc_offset(int ntiles) {
-  return (256 + sizeof(int32_t) * plan_ints(ntiles) + 255) / 256 * 256;
+// Workspace: 256 reserved bytes, the light-tile list (plan layout), the batch
+// items, then the accumulator rows (256-byte aligned).
+static size_t bwd_items_offset(int ntiles) { return 256 + sizeof(int32_t) * plan_ints(ntiles); }
+static size_t bwd_acc_offset(int64_t k, int ntiles) {
+  return (bwd_items_offset(ntiles) + sizeof(int32_t) * batch_item_ints(k, ntiles) + 255) / 256 * 256;
 }
 
 size_t render_bwd_workspace(int64_t n, int64_t k, int ntiles, int deterministic) {
-  (void)k; (void)deterministic;
-  return bwd_acc_offset(ntiles) + sizeof(float) * kAccStride * static_cast<size_t>(n);
+  (void)deterministic;
+  return bwd_acc_offset(k, ntiles) + sizeof(float) * kAccStride * static_cast<size_t>(n);
 }
 
 gs_status launch_render_bwd(int64_t n, const gs_projected& proj, const uint32_t* point_list, const uint32_t* ranges,
@@ -704,32 +751,39 @@ gs_status launch_render_bwd(int64_t n, const gs_projected& proj, const uint32_t*
   (void)ws_bytes;
   if (deterministic) return fail(GS_ERR_UNSUPPORTED, "gs_render_bwd: deterministic reduction not built yet");
   const int ntiles = cam.tiles_x * cam.tiles_y;
-  float* acc = reinterpret_cast<float*>(static_cast<char*>(ws) + bwd_acc_offset(ntiles));
+  char* w = static_cast<char*>(ws);
+  float* acc = reinterpret_cast<float*>(w + bwd_acc_offset(k, ntiles));
   gs_status st = check_hip(hipMemsetAsync(acc, 0, sizeof(float) * kAccStride * static_cast<size_t>(n), s),
                            "hipMemsetAsync(acc)");
   if (st != GS_OK) return st;
-  int32_t* plan = nullptr;
-  if (schedule >= 1) {
-    // plan from the forward's per-tile work counts (largest n_contrib).  BALANCED
-    // leaves tiles with nothing to walk out (their light class, limit 0);
-    // MERGED hands tiles with at most kLightMax entries to the merged kernel.
+  const uint2* rg = reinterpret_cast<const uint2*>(ranges);
+  const float4* rec = reinterpret_cast<const float4*>(proj.records);
+  if (schedule == 0) {
+    k_render_bwd<<<ntiles, 256, 0, s>>>(rg, point_list, rec, cam, final_T, n_contrib, t_ckpt, dL_dimage,
+                                        static_cast<int>(n), acc, nullptr, nullptr, nullptr, nullptr, 0);
+    st = check_launch("k_render_bwd");
+  } else {
+    // one workgroup per (tile, batch) walked, from the forward's work counts;
+    // MERGED hands tiles with at most kLightMax entries to the merged kernel
     const float* tail = t_ckpt + ckpt_core_floats(k, ntiles);
     const uint32_t* tile_work = reinterpret_cast<const uint32_t*>(tail + plan_ints(ntiles));
-    plan = reinterpret_cast<int32_t*>(static_cast<char*>(ws) + 256);
-    st = launch_tile_plan(ntiles, ranges, tile_work, kHeavyFactor, schedule == 2 ? kLightMax : 0, plan, s);
+    const float* c_ckpt = tail + plan_ints(ntiles) + ntiles;
+    int32_t* light = schedule == 2 ? reinterpret_cast<int32_t*>(w + 256) : nullptr;
+    int32_t* items = reinterpret_cast<int32_t*>(w + bwd_items_offset(ntiles));
+    st = launch_batch_plan(ntiles, ranges, tile_work, schedule == 2 ? kLightMax : 0, items, light, s);
     if (st != GS_OK) return st;
-    if (schedule == 2) {
+    if (light) {
       k_render_bwd_light<<<static_cast<unsigned>(ceil_div(ntiles, 4)), 256, 0, s>>>(
-          reinterpret_cast<const uint2*>(ranges), point_list, reinterpret_cast<const float4*>(proj.records), cam,
-          final_T, n_contrib, dL_dimage, static_cast<int>(n), acc, plan);
+          rg, point_list, rec, cam, final_T, n_contrib, dL_dimage, static_cast<int>(n), acc, light);
       st = check_launch("k_render_bwd_light");
       if (st != GS_OK) return st;
     }
+    const unsigned grid = static_cast<unsigned>(k / kBatch + ntiles + 1);
+    k_render_bwd<<<grid, 256, 0, s>>>(rg, point_list, rec, cam, final_T, n_contrib, t_ckpt, dL_dimage,
+                                      static_cast<int>(n), acc, nullptr, items, tile_work, c_ckpt,
+                                      ckpt_core_floats(k, ntiles));
+    st = check_launch("k_render_bwd");
   }
-  k_render_bwd<<<ntiles, 256, 0, s>>>(reinterpret_cast<const uint2*>(ranges), point_list,
-                                      reinterpret_cast<const float4*>(proj.records), cam, final_T, n_contrib,
-                                      t_ckpt, dL_dimage, static_cast<int>(n), acc, plan);
-  st = check_launch("k_render_bwd");
   if (st != GS_OK) return st;
   k_acc_to_g2d<<<static_cast<unsigned>(ceil_div(n, 256)), 256, 0, s>>>(static_cast<int>(n),
                                                                        reinterpret_cast<const float4*>(acc), g2d);
