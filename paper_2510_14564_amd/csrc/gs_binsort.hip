@@ -277,20 +277,41 @@ static int sort_passes(int bits) { return (bits + 7) / 8; }
 
 // ------------------------------------------------------------- bin kernels
 
+// Depth keys, and each Gaussian's tile rectangle packed into 8 bytes
+// (x0 | x_end << 16, y0 | y_end << 16, ends exclusive; all zero when empty) so
+// that the later rank-order passes read one small word per Gaussian instead
+// of its record and radius.
 __global__ __launch_bounds__(256) void k_depth_keys(int n, const float* __restrict__ depth,
-                                                    uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+                                                    const float4* __restrict__ records,
+                                                    const int* __restrict__ radius, int tiles_x, int tiles_y,
+                                                    uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                    uint2* __restrict__ rect) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   keys[i] = __float_as_uint(depth[i]);
   vals[i] = static_cast<uint32_t>(i);
+  const float4 r0 = records[3 * static_cast<int64_t>(i)];
+  int x0, x1, y0, y1;
+  const int c = tile_rect(r0.x, r0.y, radius[i], tiles_x, tiles_y, x0, x1, y0, y1);
+  rect[i] = c > 0 ? make_uint2(static_cast<uint32_t>(x0) | (static_cast<uint32_t>(x1 + 1) << 16),
+                               static_cast<uint32_t>(y0) | (static_cast<uint32_t>(y1 + 1) << 16))
+                  : make_uint2(0u, 0u);
 }
 
+__device__ __forceinline__ uint32_t rect_count(uint2 rc) {
+  return ((rc.x >> 16) - (rc.x & 0xFFFFu)) * ((rc.y >> 16) - (rc.y & 0xFFFFu));
+}
+
+// Rank order: each Gaussian's rectangle and tile count (one gather per
+// Gaussian).
 __global__ __launch_bounds__(256) void k_gather_counts(int n, const uint32_t* __restrict__ order,
-                                                       const uint32_t* __restrict__ tiles_touched,
-                                                       uint32_t* __restrict__ out) {
+                                                       const uint2* __restrict__ rect, uint32_t* __restrict__ out,
+                                                       uint2* __restrict__ rect_rank) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
-  out[r] = tiles_touched[order[r]];
+  const uint2 rc = rect[order[r]];
+  out[r] = rect_count(rc);
+  rect_rank[r] = rc;
 }
 
 // Emit: a wave takes 64 consecutive depth ranks and writes all of their
@@ -300,20 +321,21 @@ __global__ __launch_bounds__(256) void k_gather_counts(int n, const uint32_t* __
 // Gaussian's tiles are written row-major over its rectangle.
 __global__ __launch_bounds__(256) void k_emit(int n, const uint32_t* __restrict__ order,
                                               const uint32_t* __restrict__ offsets,
-                                              const float4* __restrict__ records, const int* __restrict__ radius,
-                                              int tiles_x, int tiles_y, uint32_t* __restrict__ tile_keys,
-                                              uint32_t* __restrict__ gids) {
+                                              const uint2* __restrict__ rect_rank, int tiles_x,
+                                              uint32_t* __restrict__ tile_keys, uint32_t* __restrict__ gids) {
   __shared__ uint32_t s_pre[4][65];   // exclusive prefix of entry counts within the wave, plus total
   __shared__ uint32_t s_gid[4][64];
   __shared__ int s_x0[4][64], s_y0[4][64], s_w[4][64];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r = (blockIdx.x * 4 + wave) * 64 + lane;
   uint32_t cnt = 0, gid = 0;
-  int x0 = 0, x1 = -1, y0 = 0, y1 = -1;
+  int x0 = 0, x1 = -1, y0 = 0;
   if (r < n) {
     gid = order[r];
-    const float4 rec = records[3 * gid];
-    cnt = static_cast<uint32_t>(tile_rect(rec.x, rec.y, radius[gid], tiles_x, tiles_y, x0, x1, y0, y1));
+    const uint2 rc = rect_rank[r];
+    cnt = rect_count(rc);
+    x0 = static_cast<int>(rc.x & 0xFFFFu); x1 = static_cast<int>(rc.x >> 16) - 1;
+    y0 = static_cast<int>(rc.y & 0xFFFFu);
   }
   // inclusive scan of cnt over the wave (Hillis-Steele with shuffles)
   uint32_t incl = cnt;
@@ -378,6 +400,7 @@ static int bits_for(int64_t values) {  // bits needed to represent 0..values-1
 
 struct BinWs {
   uint32_t *dk0, *dv0, *dk1, *dv1, *cnt, *offs;
+  uint2 *rect, *rect_rank;
   uint32_t *ek0, *ek1, *ev1;
   uint32_t* hist;
   ScanWs scan;
@@ -390,6 +413,7 @@ static BinWs carve_bin(void* ws, int64_t n, int64_t cap, size_t* used) {
   b.dk0 = c.take<uint32_t>(N); b.dv0 = c.take<uint32_t>(N);
   b.dk1 = c.take<uint32_t>(N); b.dv1 = c.take<uint32_t>(N);
   b.cnt = c.take<uint32_t>(N); b.offs = c.take<uint32_t>(N);
+  b.rect = c.take<uint2>(N); b.rect_rank = c.take<uint2>(N);
   b.ek0 = c.take<uint32_t>(C); b.ek1 = c.take<uint32_t>(C); b.ev1 = c.take<uint32_t>(C);
   const size_t hist_words = 256 * static_cast<size_t>(std::max(ceil_div(std::max<int64_t>(n, 1), kRsThreads * kRsItemsN),
                                                                ceil_div(std::max<int64_t>(cap, 1), kRsThreads * kRsItemsK)));
@@ -419,12 +443,13 @@ gs_status run_bin_sort(int64_t n64, const gs_projected& proj, const DevCam& cam,
   int64_t K = 0;
   if (n > 0) {
     const unsigned g = static_cast<unsigned>(ceil_div(n, 256));
-    k_depth_keys<<<g, 256, 0, s>>>(n, proj.depth, b.dk0, b.dv0);
+    k_depth_keys<<<g, 256, 0, s>>>(n, proj.depth, reinterpret_cast<const float4*>(proj.records), proj.radius,
+                                   cam.tiles_x, cam.tiles_y, b.dk0, b.dv0, b.rect);
     int passes = 0;
     if ((st = radix_sort_pairs<kRsItemsN>(b.dk0, b.dv0, b.dk1, b.dv1, n, 32, b.hist, b.scan, s, &passes)) != GS_OK)
       return st;
     const uint32_t* order = (passes % 2 == 0) ? b.dv0 : b.dv1;
-    k_gather_counts<<<g, 256, 0, s>>>(n, order, proj.tiles_touched, b.cnt);
+    k_gather_counts<<<g, 256, 0, s>>>(n, order, b.rect, b.cnt, b.rect_rank);
     if ((st = device_exclusive_scan(b.cnt, b.offs, n, b.scan, s)) != GS_OK) return st;
     unsigned long long total = 0;
     if ((st = check_hip(hipMemcpyAsync(&total, b.scan.total, sizeof(total), hipMemcpyDeviceToHost, s),
@@ -443,8 +468,7 @@ gs_status run_bin_sort(int64_t n64, const gs_projected& proj, const DevCam& cam,
       uint32_t* kb = b.ek1;
       uint32_t* vb = (tp % 2 == 0) ? b.ev1 : point_list;
       k_emit<<<static_cast<unsigned>(ceil_div(n, 256)), 256, 0, s>>>(
-          n, order, b.offs, reinterpret_cast<const float4*>(proj.records), proj.radius, cam.tiles_x, cam.tiles_y, ka,
-          va);
+          n, order, b.offs, b.rect_rank, cam.tiles_x, ka, va);
       if ((st = check_launch("k_emit")) != GS_OK) return st;
       int p2 = 0;
       if ((st = radix_sort_pairs<kRsItemsK>(ka, va, kb, vb, K, tbits, b.hist, b.scan, s, &p2)) != GS_OK) return st;
