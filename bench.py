@@ -316,7 +316,8 @@ def main():
     for name, r in rooflines.items():
         r["achieved"] = round(r["achieved"], 2)
         r["frac"] = round(r["achieved"] / r["peak"], 4)
-        tb = counter_traffic_bytes(name)
+        # the committed counters were taken on the main workload only
+        tb = counter_traffic_bytes(name) if cfg == 3 else None
         # measured HBM traffic of the stage per call, as a rate over its time
         r["traffic"] = None if tb is None else round(tb / (stage_ms[name] * 1e-3) / 1e9, 1)
         r["traffic_unit"] = "GB/s"
