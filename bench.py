@@ -177,7 +177,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", type=int, default=3, choices=[1, 2, 3, 4])
+    ap.add_argument("--config", type=int, default=3, choices=[1, 2, 3, 4, 5])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-colour timing")
     ap.add_argument("--compare-plain", action="store_true",
@@ -263,7 +263,7 @@ def main():
     if not args.no_mlp:
         from paper_2510_14564_amd.decoder import Decoder
         from paper_2510_14564_amd.raster import rasterize_learned
-        dec = Decoder(scene.n, device=dev, seed=cfg)
+        dec = Decoder(scene.n, device=dev, seed=cfg, latents_bits=scene.latents)
         dec.latents.requires_grad_(True)
         dec.params.requires_grad_(True)
 
@@ -339,7 +339,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": {1: "tiny", 2: "skewed", 3: "main", 4: "heavy"}[cfg] +
+        "config": {"workload": {1: "tiny", 2: "skewed", 3: "main", 4: "heavy", 5: "learned colour"}[cfg] +
                    f": {n} Gaussians, SH degree {deg}, {W}x{H}, 16x16 tiles, "
                    f"{ncam} camera(s), colour SH, L1 loss",
                    "gaussians": n, "width": W, "height": H, "sh_degree": deg, "colour": "sh",

@@ -106,9 +106,24 @@ def project(scene, cam):
     return dict(rec=rec, depth=depth, radius=radius, rect=rect, tiles_touched=tt, flags=flags)
 
 
-def bin_sort(u, v, radius, depth_f32, W: int, H: int):
+def bin_rects(u, v, radius, W: int, H: int):
+    """Each Gaussian's tile rectangle int32[n][4] = (x0, x1, y0, y1), inclusive
+    (x1 < x0: no tile), the per-tile entry counts int64[T] and their total K."""
+    u = _d(u); v = _d(v)
+    radius = np.ascontiguousarray(radius, np.int32)
+    n = u.shape[0]
+    rect = np.zeros((n, 4), np.int32)
+    counts = np.zeros(((W + TILE - 1) // TILE) * ((H + TILE - 1) // TILE), np.int64)
+    K = _load().or_bin_rects(ctypes.c_int64(n), _p(u), _p(v), _p(radius), ctypes.c_int(W), ctypes.c_int(H),
+                             _p(rect), _p(counts))
+    return rect, counts, int(K)
+
+
+def bin_sort(u, v, radius, depth_f32, W: int, H: int, tile_mask=None):
     """Tile binning and (tile, depth bits, index) sort on FP32-valued inputs.
-    Returns (point_list uint32[K], ranges uint32[T][2], tiles_touched int64[n], offsets int64[n])."""
+    Returns (point_list uint32[K], ranges uint32[T][2], tiles_touched int64[n], offsets int64[n]).
+    With tile_mask (uint8[T]) only the selected tiles get lists; the others get
+    empty ranges and K counts the selected tiles' entries."""
     u = _d(u); v = _d(v)
     radius = np.ascontiguousarray(radius, np.int32)
     bits = np.ascontiguousarray(np.asarray(depth_f32, np.float32)).view(np.uint32)
@@ -119,10 +134,16 @@ def bin_sort(u, v, radius, depth_f32, W: int, H: int):
     K = lib.or_bin_count(ctypes.c_int64(n), _p(u), _p(v), _p(radius), ctypes.c_int(W), ctypes.c_int(H),
                          _p(tt), _p(off))
     ntiles = ((W + TILE - 1) // TILE) * ((H + TILE - 1) // TILE)
+    tm = None
+    if tile_mask is not None:
+        tm = np.ascontiguousarray(tile_mask, np.uint8)
+        assert tm.shape == (ntiles,)
+        _, counts, _ = bin_rects(u, v, radius, W, H)
+        K = int(counts[tm != 0].sum())
     pl = np.zeros(max(K, 1), np.uint32)
     ranges = np.zeros((ntiles, 2), np.uint32)
     rc = lib.or_bin_sort(ctypes.c_int64(n), _p(u), _p(v), _p(radius), _p(bits), ctypes.c_int(W),
-                         ctypes.c_int(H), ctypes.c_int64(K), _p(pl), _p(ranges))
+                         ctypes.c_int(H), _p(tm), ctypes.c_int64(K), _p(pl), _p(ranges))
     if rc != 0:
         raise RuntimeError(f"or_bin_sort failed: {rc}")
     return pl[:K], ranges, tt, off

@@ -371,9 +371,29 @@ int64_t or_bin_count(int64_t n, const double* u, const double* v, const int32_t*
     return total;
 }
 
-/* point_list[K], ranges[T][2]; depth_bits are the FP32 bit patterns of depth. */
+/* Every Gaussian's tile rectangle rect[i] = (x0, x1, y0, y1), inclusive
+ * (x1 < x0 when it touches no tile), and the per-tile entry counts
+ * counts[ty * tiles_x + tx] (a Gaussian counts once in every tile of its
+ * rectangle).  Returns K, the total. */
+int64_t or_bin_rects(int64_t n, const double* u, const double* v, const int32_t* radius, int W, int H,
+                     int32_t* rect, int64_t* counts) {
+    int64_t tx = (W + OR_TILE - 1) / OR_TILE, ty = (H + OR_TILE - 1) / OR_TILE;
+    int64_t total = 0;
+    for (int64_t t = 0; t < tx * ty; ++t) counts[t] = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t* r = rect + 4 * i;
+        total += tile_rect(u[i], v[i], radius[i], W, H, r);
+        for (int y = r[2]; y <= r[3]; ++y)
+            for (int x = r[0]; x <= r[1]; ++x) ++counts[y * tx + x];
+    }
+    return total;
+}
+
+/* point_list[K], ranges[T][2]; depth_bits are the FP32 bit patterns of depth.
+ * tile_mask (optional): only the tiles with a non-zero byte get their lists
+ * (the others get empty ranges); K is then the entry count of those tiles. */
 int or_bin_sort(int64_t n, const double* u, const double* v, const int32_t* radius,
-                const uint32_t* depth_bits, int W, int H, int64_t K,
+                const uint32_t* depth_bits, int W, int H, const uint8_t* tile_mask, int64_t K,
                 uint32_t* point_list, uint32_t* ranges) {
     int64_t tx = (W + OR_TILE - 1) / OR_TILE, ty = (H + OR_TILE - 1) / OR_TILE;
     int64_t ntiles = tx * ty;
@@ -386,6 +406,7 @@ int or_bin_sort(int64_t n, const double* u, const double* v, const int32_t* radi
         if (cnt == 0) continue;
         for (int y = rect[2]; y <= rect[3]; ++y)
             for (int x = rect[0]; x <= rect[1]; ++x) {
+                if (tile_mask && !tile_mask[y * tx + x]) continue;
                 if (off >= K) { free(e); return -3; }
                 e[off].tile = (uint32_t)(y * tx + x);
                 e[off].key = depth_bits[i];

@@ -259,6 +259,26 @@ def test_bin_sort_matches_python_sort_with_ties_and_offscreen():
     assert np.array_equal(pl, want_pl)
     assert np.array_equal(ranges, want_ranges)
     assert tt.sum() == len(pl) and off[-1] + tt[-1] == len(pl)
+    # rectangles and per-tile counts against the Python rectangles and sort
+    rect, counts, K = oracle.bin_rects(u, v, r, W, H)
+    assert K == len(want_pl)
+    assert np.array_equal(counts, (want_ranges[:, 1] - want_ranges[:, 0]).astype(np.int64))
+    for i in range(n):
+        rc = brute._rect(float(u[i]), float(v[i]), int(r[i]), W, H)
+        assert (rect[i, 1] < rect[i, 0]) if rc is None else tuple(rect[i]) == rc, i
+    # a tile mask keeps exactly the selected tiles' lists, in the same order
+    mask = np.zeros(len(want_ranges), np.uint8)
+    mask[[0, 3, 4, 11, 34]] = 1
+    mpl, mranges, _, _ = oracle.bin_sort(u, v, r, depth, W, H, tile_mask=mask)
+    m = 0
+    for t in range(len(mask)):
+        s, e = mranges[t]
+        if mask[t]:
+            assert s == m and np.array_equal(mpl[s:e], want_pl[want_ranges[t, 0]:want_ranges[t, 1]]), t
+            m = e
+        else:
+            assert s == e == m, t
+    assert m == len(mpl)
 
 
 def test_tile_rect_integer_form_avoids_fp32_round_up():
