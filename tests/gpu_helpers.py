@@ -71,6 +71,25 @@ def grad_close(got, want, rtol=GRAD_RTOL, name="", mass=None, stats=None):
     return float((err / (ref + 1e-30)).max()) if want.size else 0.0
 
 
+def chain_mass(scene, cam, *weights):
+    """Term mass of the projection backward: for each weights[n][9] >= 0, per
+    parameter sum_j |d param / d record_j| weights[:, j], from one oracle pass
+    per record channel j (a Gaussian's parameter gradient depends on its own
+    record gradient only).  With weights = |g2d| this is the sum of the chain
+    rule's per-channel terms, which the FP32 rounding of a cancelling
+    parameter gradient scales with."""
+    n = scene.n
+    out = [None] * len(weights)
+    for j in range(9):
+        e = np.zeros((n, 9))
+        e[:, j] = 1.0
+        col = oracle.project_bwd(scene, cam, e)
+        for w_i, w in enumerate(weights):
+            acc = {k: np.abs(v) * w[:, j] for k, v in col.items()}
+            out[w_i] = acc if out[w_i] is None else {k: out[w_i][k] + acc[k] for k in acc}
+    return out
+
+
 def gpu_bin_sort(gs, n, out, cam, capacity=None):
     cs = gs.camera_struct(cam)
     cap = capacity if capacity is not None else max(1024, int(out.tiles_touched.sum().item()))
