@@ -181,7 +181,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-colour timing")
     ap.add_argument("--compare-plain", action="store_true",
-                    help="also time the SH step with the plain and the merged work splits")
+                    help="also time the SH step with the plain and the merged work splits, and with the "
+                         "deterministic reduction")
     ap.add_argument("--hbm-probe", action="store_true",
                     help="also time a 2 GiB device-to-device copy (achievable HBM bandwidth, counter calibration)")
     args = ap.parse_args()
@@ -256,6 +257,11 @@ def main():
             other_splits[name] = {"ms_per_step": round(p_ms, 4),
                                   "stages_ms": {k: round(v, 4) for k, v in p_stage.items()}}
         rast.schedule = gs.SCHEDULE_BALANCED
+        rast.deterministic = True
+        p_ms, p_stage = run_timed(step, "SH colour, deterministic reduction")
+        other_splits["balanced, deterministic"] = {"ms_per_step": round(p_ms, 4),
+                                                   "stages_ms": {k: round(v, 4) for k, v in p_stage.items()}}
+        rast.deterministic = False
 
     # learned colour on the same scene, cameras and targets: random-init
     # decoder (the step's cost does not depend on the weight values)

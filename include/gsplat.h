@@ -216,9 +216,11 @@ gs_status gs_render_bwd_workspace(int64_t n, int64_t k, const gs_camera* cam, in
  * [b, c]] is the 2D covariance whose inverse is the record's conic (b counted
  * in both off-diagonal places).  Each pixel's conic gradient is carried to
  * Sigma' before the sum over pixels, which stays well conditioned where the
- * conic is nearly singular (elongated footprints).  deterministic = 1 sums the
- * per-(tile, Gaussian) partials in a fixed order (bit-reproducible); 0 uses
- * device atomics.  ws as sized by gs_render_bwd_workspace (holds the
+ * conic is nearly singular (elongated footprints).  deterministic = 1 writes
+ * one partial per (tile, Gaussian) entry and sums each Gaussian's partials in
+ * the row-major order of its tile rectangle: no atomics, the same bits on
+ * every run for a given schedule (its workspace holds 36 bytes per entry);
+ * 0 adds the partials with device atomics (summation order varies).  ws as sized by gs_render_bwd_workspace (holds the
  * backward's tile plan).  schedule as for gs_render_fwd; BALANCED plans from
  * the work counts the forward left in t_ckpt. */
 gs_status gs_render_bwd(int64_t n, const gs_projected* proj, const uint32_t* point_list, const uint32_t* ranges,

@@ -126,6 +126,13 @@ static gs_status device_exclusive_scan(const uint32_t* in, uint32_t* out, int64_
   return check_launch("device_exclusive_scan");
 }
 
+size_t scan_sums_words(int64_t n) { return scan_ws_words(n); }
+
+gs_status launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* sums,
+                                unsigned long long* total, hipStream_t s) {
+  return device_exclusive_scan(in, out, n, ScanWs{sums, total}, s);
+}
+
 // ---------------------------------------------------------------- radix sort
 // One stable LSD pass on (key, value) pairs over `nbits` bits at `shift`.
 // Block b owns keys [b*CHUNK, (b+1)*CHUNK); wave w of the block owns the

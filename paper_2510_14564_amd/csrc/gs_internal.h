@@ -123,6 +123,11 @@ inline size_t batch_item_ints(int64_t k, int64_t ntiles) {
 gs_status launch_project_bwd(const gs_gaussians& g, const DevCam& cam, const int* radius, const float* g2d,
                              gs_gaussians_grad& grad, void* ws, hipStream_t s);
 size_t binsort_workspace(int64_t n, int64_t capacity, int ntiles);
+// Exclusive prefix sum of n uint32 values (out may alias in); sums holds
+// scan_sums_words(n) words, total (optional) receives the 64-bit sum.
+size_t scan_sums_words(int64_t n);
+gs_status launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* sums,
+                                unsigned long long* total, hipStream_t s);
 gs_status run_bin_sort(int64_t n, const gs_projected& proj, const DevCam& cam, void* ws, size_t ws_bytes,
                        uint32_t* point_list, int64_t capacity, uint32_t* ranges, int64_t* k_out, hipStream_t s);
 gs_status launch_render_fwd(const gs_projected& proj, const uint32_t* point_list, const uint32_t* ranges, int64_t k,

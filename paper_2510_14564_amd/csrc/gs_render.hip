@@ -529,6 +529,71 @@ __global__ __launch_bounds__(256) void k_acc_to_g2d(int n, const float4* __restr
   for (int k = 0; k < GS_G2D; ++k) g2d[static_cast<int64_t>(k) * n + i] = v[k];
 }
 
+// ------------------------------------------------- deterministic reduction
+// Every (tile, Gaussian) entry gets its own row of nine partial sums; the rows
+// of one Gaussian are contiguous, in the row-major order of its tile
+// rectangle:  row = base_g + (ty - y0) w + (tx - x0), with base the exclusive
+// prefix sum of the rectangle areas in Gaussian order (the areas sum to K).
+// The backward writes each entry's row once -- a workgroup adds its four
+// waves' sums in wave order -- and the reduction adds a Gaussian's rows in
+// rectangle order.  No atomics: the result is the same bit for bit on every
+// run (for a given schedule).  Rows of entries no pixel reaches stay zero.
+constexpr int kDetRow = 9;
+
+__global__ __launch_bounds__(256) void k_det_count(int n, const float4* __restrict__ rec,
+                                                   const int* __restrict__ radius, int tiles_x, int tiles_y,
+                                                   uint32_t* __restrict__ cnt) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  int x0, x1, y0, y1;
+  cnt[i] = static_cast<uint32_t>(tile_rect(rec[3 * static_cast<int64_t>(i)].x, rec[3 * static_cast<int64_t>(i)].y,
+                                           radius[i], tiles_x, tiles_y, x0, x1, y0, y1));
+}
+
+// row_of[i] = (base_i - (y0 w + x0), w) in wrap-around uint32 arithmetic, so
+// that the row of tile (tx, ty) is row_of.x + ty w + tx.
+__global__ __launch_bounds__(256) void k_det_rows(int n, const float4* __restrict__ rec,
+                                                  const int* __restrict__ radius, int tiles_x, int tiles_y,
+                                                  const uint32_t* __restrict__ base, uint2* __restrict__ row_of) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  int x0, x1, y0, y1;
+  tile_rect(rec[3 * static_cast<int64_t>(i)].x, rec[3 * static_cast<int64_t>(i)].y, radius[i], tiles_x, tiles_y,
+            x0, x1, y0, y1);
+  const uint32_t w = static_cast<uint32_t>(max(x1 - x0 + 1, 0));
+  row_of[i] = make_uint2(base[i] - (static_cast<uint32_t>(y0) * w + static_cast<uint32_t>(x0)), w);
+}
+
+__device__ __forceinline__ uint32_t det_row(uint2 ro, int tx, int ty) {
+  return ro.x + static_cast<uint32_t>(ty) * ro.y + static_cast<uint32_t>(tx);
+}
+
+__global__ __launch_bounds__(256) void k_zero4(float4* __restrict__ p, int64_t n4) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < n4;
+       i += static_cast<int64_t>(gridDim.x) * 256)
+    p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// g2d[c][i] = sum over the Gaussian's rows, in rectangle order.
+__global__ __launch_bounds__(256) void k_det_reduce(int n, const uint32_t* __restrict__ cnt,
+                                                    const uint32_t* __restrict__ base,
+                                                    const float* __restrict__ part, uint32_t rows,
+                                                    float* __restrict__ g2d) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  float s[kDetRow];
+#pragma unroll
+  for (int c = 0; c < kDetRow; ++c) s[c] = 0.0f;
+  const uint32_t b = base[i], e = min(b + cnt[i], rows);
+  for (uint32_t r = b; r < e; ++r) {
+    const float* row = part + static_cast<size_t>(r) * kDetRow;
+#pragma unroll
+    for (int c = 0; c < kDetRow; ++c) s[c] += row[c];
+  }
+#pragma unroll
+  for (int c = 0; c < GS_G2D; ++c) g2d[static_cast<int64_t>(c) * n + i] = s[c];
+}
+
 // Per (pixel, entry) derivative, walked back to front.  Starting from the light
 // S = T_f bg behind the last entry, each blended entry m (going backwards)
 // recovers T_m = T_{m+1} / (1 - alpha_m) and uses the light behind it,
@@ -545,7 +610,9 @@ __global__ __launch_bounds__(256) void k_acc_to_g2d(int n, const float4* __restr
 // over the wave and added by nine lanes at once to the Gaussian's row of the
 // accumulator acc[n][kAccStride]: one 64-byte line per Gaussian, so the nine
 // atomics of an instruction meet in one line (the [9][n] output is written
-// from it afterwards).
+// from it afterwards).  DET: the sums go to the entry's row of `part` instead
+// (deterministic reduction above).
+template <bool DET>
 __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ranges,
                                                     const uint32_t* __restrict__ point_list,
                                                     const float4* __restrict__ rec, DevCam cam,
@@ -556,9 +623,14 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
                                                     float* __restrict__ acc, const int32_t* __restrict__ plan,
                                                     const int32_t* __restrict__ items,
                                                     const uint32_t* __restrict__ tile_work,
-                                                    const float* __restrict__ c_ckpt, size_t cplane) {
+                                                    const float* __restrict__ c_ckpt, size_t cplane,
+                                                    float* __restrict__ part, const uint2* __restrict__ row_of,
+                                                    uint32_t rows) {
   __shared__ Stage st;
   __shared__ uint32_t s_max;
+  // DET: each wave's nine sums per staged entry, [wave][entry][9]
+  __shared__ float4 s_part4[DET ? 4 * kBatch * kDetRow / 4 : 1];
+  float* const s_part = reinterpret_cast<float*>(s_part4);
   // items: this workgroup walks one batch of one tile (the batch plan);
   // otherwise the whole tile (plain map, or the plan's order)
   int tile, b_only = -1;
@@ -629,6 +701,9 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
     T = (bi + 1 < nbatch) ? t_ckpt[(slot0 + bi + 1) * kBatch + threadIdx.x] : T_final;
     __syncthreads();
     stage_batch(st, rec, point_list, rg.x + m0, cnt, x0, y0);
+    if constexpr (DET) {
+      for (int i = threadIdx.x; i < 4 * kBatch * kDetRow / 4; i += 256) s_part4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
     __syncthreads();
     build_list(st, cnt, false);
     __syncthreads();
@@ -649,7 +724,26 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
       bwd_terms(p, q, cb, ok, dx, dy, alpha, eg, og, G0, G1, G2, T, GS, v);
       const float red8 = wave_sum8(v, lo8);
       const float red9 = wave_sum_to_lane63(v[8]);  // dL/db
-      if (writer) unsafeAtomicAdd(&g_out[static_cast<int64_t>(st.gid[j]) * kAccStride], lane == 63 ? red9 : red8);
+      if constexpr (DET) {
+        if (writer) s_part[(wave * kBatch + static_cast<int>(j)) * kDetRow + out_slot] = lane == 63 ? red9 : red8;
+      } else {
+        if (writer) unsafeAtomicAdd(&g_out[static_cast<int64_t>(st.gid[j]) * kAccStride], lane == 63 ? red9 : red8);
+      }
+    }
+    if constexpr (DET) {
+      // entry t's row: its four waves' sums added in wave order
+      __syncthreads();
+      const int t = threadIdx.x;
+      if (t < cnt) {
+        const uint32_t r = det_row(row_of[st.gid[t]], tx, ty);
+        if (r < rows) {
+          float* const dst = part + static_cast<size_t>(r) * kDetRow;
+#pragma unroll
+          for (int c = 0; c < kDetRow; ++c)
+            dst[c] = ((s_part[t * kDetRow + c] + s_part[(kBatch + t) * kDetRow + c]) +
+                      s_part[(2 * kBatch + t) * kDetRow + c]) + s_part[(3 * kBatch + t) * kDetRow + c];
+        }
+      }
     }
   }
 }
@@ -658,14 +752,17 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
 // Backward of light tiles (the largest n_contrib at most kLightMax): one wave
 // per tile, four pixels per lane as in the forward.  Each lane adds its four
 // pixels' terms before the wave sum, so one reduction and one set of atomics
-// serve 256 pixels.
+// serve 256 pixels.  DET: the wave's sums are the entry's whole row.
+template <bool DET>
 __global__ __launch_bounds__(256) void k_render_bwd_light(const uint2* __restrict__ ranges,
                                                           const uint32_t* __restrict__ point_list,
                                                           const float4* __restrict__ rec, DevCam cam,
                                                           const float* __restrict__ final_T,
                                                           const uint32_t* __restrict__ n_contrib,
                                                           const float* __restrict__ dL_dimage, int n,
-                                                          float* __restrict__ acc, const int32_t* __restrict__ plan) {
+                                                          float* __restrict__ acc, const int32_t* __restrict__ plan,
+                                                          float* __restrict__ part,
+                                                          const uint2* __restrict__ row_of, uint32_t rows) {
   __shared__ LightStage stage[4];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int tile = light_tile(plan, blockIdx.x, wave);
@@ -728,7 +825,12 @@ __global__ __launch_bounds__(256) void k_render_bwd_light(const uint2* __restric
     if (__ballot(any) == 0) continue;
     const float red8 = wave_sum8(vs, lo8);
     const float red9 = wave_sum_to_lane63(vs[8]);
-    if (writer) unsafeAtomicAdd(&g_out[static_cast<int64_t>(ls.gid[j]) * kAccStride], lane == 63 ? red9 : red8);
+    if constexpr (DET) {
+      const uint32_t r = det_row(row_of[ls.gid[j]], tx, ty);
+      if (writer && r < rows) part[static_cast<size_t>(r) * kDetRow + out_slot] = lane == 63 ? red9 : red8;
+    } else {
+      if (writer) unsafeAtomicAdd(&g_out[static_cast<int64_t>(ls.gid[j]) * kAccStride], lane == 63 ? red9 : red8);
+    }
   }
 }
 
@@ -739,8 +841,36 @@ static size_t bwd_acc_offset(int64_t k, int ntiles) {
   return (bwd_items_offset(ntiles) + sizeof(int32_t) * batch_item_ints(k, ntiles) + 255) / 256 * 256;
 }
 
+// Deterministic mode, after the items: per-Gaussian counts, bases and row
+// maps, the scan's block sums, and the rows (9 floats per entry).
+struct DetWs {
+  uint32_t* cnt;
+  uint32_t* base;
+  uint2* row_of;
+  uint32_t* sums;
+  float* part;
+  size_t part_floats;
+};
+
+static DetWs carve_det(void* det, int64_t n, int64_t k, size_t* used) {
+  Carver c(det);
+  DetWs d;
+  d.cnt = c.take<uint32_t>(static_cast<size_t>(n));
+  d.base = c.take<uint32_t>(static_cast<size_t>(n));
+  d.row_of = c.take<uint2>(static_cast<size_t>(n));
+  d.sums = c.take<uint32_t>(scan_sums_words(n));
+  d.part_floats = (static_cast<size_t>(k) * kDetRow + 3) / 4 * 4;
+  d.part = c.take<float>(d.part_floats);
+  if (used) *used = c.off;
+  return d;
+}
+
 size_t render_bwd_workspace(int64_t n, int64_t k, int ntiles, int deterministic) {
-  (void)deterministic;
+  if (deterministic) {
+    size_t used = 0;
+    carve_det(nullptr, n, k, &used);
+    return bwd_acc_offset(k, ntiles) + used;
+  }
   return bwd_acc_offset(k, ntiles) + sizeof(float) * kAccStride * static_cast<size_t>(n);
 }
 
@@ -749,19 +879,49 @@ gs_status launch_render_bwd(int64_t n, const gs_projected& proj, const uint32_t*
                             const uint32_t* n_contrib, const float* t_ckpt, const float* dL_dimage, float* g2d, void* ws,
                             size_t ws_bytes, int deterministic, int schedule, hipStream_t s) {
   (void)ws_bytes;
-  if (deterministic) return fail(GS_ERR_UNSUPPORTED, "gs_render_bwd: deterministic reduction not built yet");
   const int ntiles = cam.tiles_x * cam.tiles_y;
   char* w = static_cast<char*>(ws);
   float* acc = reinterpret_cast<float*>(w + bwd_acc_offset(k, ntiles));
-  gs_status st = check_hip(hipMemsetAsync(acc, 0, sizeof(float) * kAccStride * static_cast<size_t>(n), s),
-                           "hipMemsetAsync(acc)");
-  if (st != GS_OK) return st;
   const uint2* rg = reinterpret_cast<const uint2*>(ranges);
   const float4* rec = reinterpret_cast<const float4*>(proj.records);
+  const unsigned gn = static_cast<unsigned>(ceil_div(n, 256));
+  gs_status st;
+  DetWs det{};
+  const uint32_t rows = static_cast<uint32_t>(k);
+  if (deterministic) {
+    det = carve_det(acc, n, k, nullptr);
+    acc = nullptr;
+    k_det_count<<<gn, 256, 0, s>>>(static_cast<int>(n), rec, proj.radius, cam.tiles_x, cam.tiles_y, det.cnt);
+    if ((st = check_launch("k_det_count")) != GS_OK) return st;
+    if ((st = launch_exclusive_scan(det.cnt, det.base, n, det.sums, nullptr, s)) != GS_OK) return st;
+    k_det_rows<<<gn, 256, 0, s>>>(static_cast<int>(n), rec, proj.radius, cam.tiles_x, cam.tiles_y, det.base,
+                                  det.row_of);
+    if ((st = check_launch("k_det_rows")) != GS_OK) return st;
+    if (det.part_floats) {
+      const int64_t n4 = static_cast<int64_t>(det.part_floats / 4);
+      k_zero4<<<static_cast<unsigned>(std::min<int64_t>(ceil_div(n4, 256), 8192)), 256, 0, s>>>(
+          reinterpret_cast<float4*>(det.part), n4);
+      if ((st = check_launch("k_zero4")) != GS_OK) return st;
+    }
+  } else {
+    st = check_hip(hipMemsetAsync(acc, 0, sizeof(float) * kAccStride * static_cast<size_t>(n), s),
+                   "hipMemsetAsync(acc)");
+    if (st != GS_OK) return st;
+  }
+  auto bwd = [&](unsigned grid, const int32_t* items, const uint32_t* tile_work, const float* c_ckpt,
+                 size_t cplane) {
+    if (deterministic)
+      k_render_bwd<true><<<grid, 256, 0, s>>>(rg, point_list, rec, cam, final_T, n_contrib, t_ckpt, dL_dimage,
+                                              static_cast<int>(n), acc, nullptr, items, tile_work, c_ckpt, cplane,
+                                              det.part, det.row_of, rows);
+    else
+      k_render_bwd<false><<<grid, 256, 0, s>>>(rg, point_list, rec, cam, final_T, n_contrib, t_ckpt, dL_dimage,
+                                               static_cast<int>(n), acc, nullptr, items, tile_work, c_ckpt, cplane,
+                                               nullptr, nullptr, 0);
+    return check_launch("k_render_bwd");
+  };
   if (schedule == 0) {
-    k_render_bwd<<<ntiles, 256, 0, s>>>(rg, point_list, rec, cam, final_T, n_contrib, t_ckpt, dL_dimage,
-                                        static_cast<int>(n), acc, nullptr, nullptr, nullptr, nullptr, 0);
-    st = check_launch("k_render_bwd");
+    st = bwd(static_cast<unsigned>(ntiles), nullptr, nullptr, nullptr, 0);
   } else {
     // one workgroup per (tile, batch) walked, from the forward's work counts;
     // MERGED hands tiles with at most kLightMax entries to the merged kernel
@@ -773,20 +933,24 @@ gs_status launch_render_bwd(int64_t n, const gs_projected& proj, const uint32_t*
     st = launch_batch_plan(ntiles, ranges, tile_work, schedule == 2 ? kLightMax : 0, items, light, s);
     if (st != GS_OK) return st;
     if (light) {
-      k_render_bwd_light<<<static_cast<unsigned>(ceil_div(ntiles, 4)), 256, 0, s>>>(
-          rg, point_list, rec, cam, final_T, n_contrib, dL_dimage, static_cast<int>(n), acc, light);
+      const unsigned lg = static_cast<unsigned>(ceil_div(ntiles, 4));
+      if (deterministic)
+        k_render_bwd_light<true><<<lg, 256, 0, s>>>(rg, point_list, rec, cam, final_T, n_contrib, dL_dimage,
+                                                    static_cast<int>(n), acc, light, det.part, det.row_of, rows);
+      else
+        k_render_bwd_light<false><<<lg, 256, 0, s>>>(rg, point_list, rec, cam, final_T, n_contrib, dL_dimage,
+                                                     static_cast<int>(n), acc, light, nullptr, nullptr, 0);
       st = check_launch("k_render_bwd_light");
       if (st != GS_OK) return st;
     }
-    const unsigned grid = static_cast<unsigned>(k / kBatch + ntiles + 1);
-    k_render_bwd<<<grid, 256, 0, s>>>(rg, point_list, rec, cam, final_T, n_contrib, t_ckpt, dL_dimage,
-                                      static_cast<int>(n), acc, nullptr, items, tile_work, c_ckpt,
-                                      ckpt_core_floats(k, ntiles));
-    st = check_launch("k_render_bwd");
+    st = bwd(static_cast<unsigned>(k / kBatch + ntiles + 1), items, tile_work, c_ckpt, ckpt_core_floats(k, ntiles));
   }
   if (st != GS_OK) return st;
-  k_acc_to_g2d<<<static_cast<unsigned>(ceil_div(n, 256)), 256, 0, s>>>(static_cast<int>(n),
-                                                                       reinterpret_cast<const float4*>(acc), g2d);
+  if (deterministic) {
+    k_det_reduce<<<gn, 256, 0, s>>>(static_cast<int>(n), det.cnt, det.base, det.part, rows, g2d);
+    return check_launch("k_det_reduce");
+  }
+  k_acc_to_g2d<<<gn, 256, 0, s>>>(static_cast<int>(n), reinterpret_cast<const float4*>(acc), g2d);
   return check_launch("k_acc_to_g2d");
 }
 

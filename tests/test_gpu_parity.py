@@ -414,3 +414,44 @@ def test_end_to_end_parity(gs, name):
         mass = np.maximum(carried[kk] / MASS_FLOOR, cm[kk])[..., sel]
         worst = max(worst, grad_close(grads[kk].cpu().numpy()[..., sel], o_gr[kk][..., sel], name=kk, mass=mass))
     say(f"  render bwd + project bwd: worst rel err {worst:.2e}")
+
+
+@pytest.mark.parametrize("name", ["ragged", "skewed", "main"])
+def test_deterministic_backward(gs, name):
+    """deterministic = 1: every (tile, Gaussian) entry's partial is written once
+    and each Gaussian's partials are added in a fixed order (no atomics).  Two
+    runs give the same bits under every work split, and the gradients meet the
+    staged tolerance (the main workload on every 16th tile)."""
+    if name == "main":
+        scene, cam = scenes.config_scene(3), scenes.config_camera(3, 0)
+    else:
+        scene, cam = _case(name)
+    say(f"[deterministic {name}] n={scene.n} {cam.width}x{cam.height}")
+    p, g, out = gpu_project(gs, scene, cam)
+    h = proj_host(out)
+    k, pl, ranges = gpu_bin_sort(gs, scene.n, out, cam)
+    W, H = cam.width, cam.height
+    tiles_x = (W + 15) // 16
+    tmask = np.ones(tiles_x * ((H + 15) // 16), np.uint8)
+    if name == "main":
+        tmask[:] = 0
+        tmask[::16] = 1
+    o_pl, o_ranges, _, _ = oracle.bin_sort(h["u"], h["v"], h["radius"], h["depth"], W, H, tile_mask=tmask)
+    image, fT, nc, ck = gpu_render(gs, scene.n, out, pl, ranges, k, cam)
+    _, _, _, o_fl = oracle.render_fwd(h["rec"][:, :9], o_pl, o_ranges, cam, margin=1e-4, tile_mask=tmask)
+    ys, xs = np.mgrid[0:H, 0:W]
+    G = scenes.upstream_grad(cam, 1001)
+    G[:, ~tmask[(ys // 16) * tiles_x + (xs // 16)].astype(bool)] = 0.0
+    G[:, o_fl != 0] = 0.0
+    o_g2d, o_mass = oracle.render_bwd(h["rec"][:, :9], o_pl, o_ranges, cam, G, tile_mask=tmask, with_mass=True)
+    Gd = to_dev(G)
+    for sched in (gs.SCHEDULE_PLAIN, gs.SCHEDULE_BALANCED, gs.SCHEDULE_MERGED):
+        a = gpu_render_bwd(gs, scene.n, out, pl, ranges, k, cam, fT, nc, ck, Gd, deterministic=True, schedule=sched)
+        b = gpu_render_bwd(gs, scene.n, out, pl, ranges, k, cam, fT, nc, ck, Gd, deterministic=True, schedule=sched)
+        assert torch.equal(a, b), f"schedule {sched}: two deterministic runs differ"
+        ah = a.cpu().numpy().T
+        worst = 0.0
+        for j, nm in enumerate("u v Sxx Sxy Syy o r g b".split()):
+            worst = max(worst, grad_close(ah[:, j], o_g2d[:, j], name=f"schedule {sched} g2d.{nm}",
+                                          mass=o_mass[:, j]))
+        say(f"  schedule {sched}: bit-identical reruns, worst rel err {worst:.2e}")
