@@ -99,6 +99,13 @@ def test_workspace_queries_are_host_only(gs):
     assert b2.value > b.value
     assert gs._lib.gs_bin_sort_workspace(-1, 0, ctypes.byref(c), ctypes.byref(b)) == gs.GS_ERR_INVALID_ARG
     assert gs._lib.gs_render_bwd_workspace(10, 10, ctypes.byref(c), 0, ctypes.byref(b)) == gs.GS_OK
+    # the deterministic reduction holds a 36-byte row per entry
+    d1, d2 = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert gs._lib.gs_render_bwd_workspace(1000, 100000, ctypes.byref(c), 1, ctypes.byref(d1)) == gs.GS_OK
+    assert gs._lib.gs_render_bwd_workspace(1000, 200000, ctypes.byref(c), 1, ctypes.byref(d2)) == gs.GS_OK
+    assert d2.value - d1.value >= 36 * 100000
+    assert gs._lib.gs_render_bwd_workspace(1000, 100000, ctypes.byref(c), 0, ctypes.byref(b)) == gs.GS_OK
+    assert d1.value > b.value
 
 
 def test_bin_sort_rejects_small_workspace_and_bad_alignment(gs):
