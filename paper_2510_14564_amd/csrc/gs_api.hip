@@ -119,7 +119,7 @@ gs_status gs_bin_sort_workspace(int64_t n, int64_t capacity, const gs_camera* ca
   if ((st = validate_camera(cam)) != GS_OK) return st;
   if (n < 0 || capacity < 0 || !bytes) return fail(GS_ERR_INVALID_ARG, "gs_bin_sort_workspace: bad n/capacity/bytes");
   const DevCam d = make_devcam(*cam);
-  *bytes = binsort_workspace(n, capacity, d.tiles_x * d.tiles_y);
+  *bytes = binsort_workspace(n, capacity, d.tiles_x, d.tiles_y);
   return GS_OK;
 }
 
@@ -134,7 +134,7 @@ gs_status gs_bin_sort(int64_t n, const gs_projected* proj, const gs_camera* cam,
     return fail(GS_ERR_INVALID_ARG, "gs_bin_sort: NULL output or negative capacity");
   if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(GS_ERR_INVALID_ARG, "gs_bin_sort: ws not 256-aligned");
   const DevCam d = make_devcam(*cam);
-  if (ws_bytes < binsort_workspace(n, capacity, d.tiles_x * d.tiles_y))
+  if (ws_bytes < binsort_workspace(n, capacity, d.tiles_x, d.tiles_y))
     return fail(GS_ERR_INVALID_ARG, "gs_bin_sort: workspace too small");
   return run_bin_sort(n, *proj, d, ws, ws_bytes, point_list, capacity, ranges, k_out,
                       static_cast<hipStream_t>(stream));

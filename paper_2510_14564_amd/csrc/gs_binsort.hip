@@ -399,6 +399,285 @@ __global__ __launch_bounds__(256) void k_ranges(int ntiles, const uint32_t* __re
   ranges[t] = make_uint2(lb(static_cast<uint32_t>(t)), lb(static_cast<uint32_t>(t + 1)));
 }
 
+// ----------------------------------------------------------- direct emission
+// The tile sort without sorting.  After the depth sort the entries of tile t
+// are, in order, the depth ranks whose rectangle contains t.  The ranks are
+// cut into C chunks of about E entries each (chunk c = ranks [R_c, R_c+1)).
+//  1. k_chunk_count: per chunk, the entry count of every tile, from a 2D
+//     difference array of the chunk's rectangles in LDS (four LDS atomics per
+//     Gaussian, then prefix sums along rows and columns) -- table[c][t].
+//  2. k_chunk_colscan: per tile, the exclusive prefix over chunks (in place)
+//     and the tile's total; k_tile_starts: exclusive prefix of the totals
+//     over tiles, which gives the ranges.
+//  3. k_emit_direct: one workgroup per chunk walks its ranks 256 at a time
+//     (1024 entries placed per round), keeping each tile's next free
+//     position in LDS.  Within a group of 256
+//     ranks, rank i = 64 w + l precedes rank i' on tile (tx, ty) iff both
+//     rectangles contain the tile; with per-wave 64-bit masks col[w][x] (lanes
+//     whose rectangle spans column x) and row[w][y], the number of earlier
+//     ranks on the tile is sum_{w' < w} popc(col[w'][tx] & row[w'][ty]) +
+//     popc(col[w][tx] & row[w][ty] & lanes below l).  So every entry computes
+//     its final position independently; the last entry of a tile in the group
+//     advances the tile's position afterwards.
+// Same result as a stable sort by tile of the rank-ordered emission, i.e. the
+// order (tile, depth bits, index).  Used while the per-chunk tables fit in LDS.
+constexpr int kDirectMaxCells = 9216;   // (tiles_x + 1) (tiles_y + 1)
+constexpr int kDirectMaxEdge = 512;     // tiles_x + tiles_y
+constexpr int kDirectChunks = 512;      // chunks at most
+constexpr int64_t kDirectMinEntries = 4096;
+
+static bool direct_ok(int tiles_x, int tiles_y) {
+  return (tiles_x + 1) * (tiles_y + 1) <= kDirectMaxCells && tiles_x + tiles_y <= kDirectMaxEdge;
+}
+static int64_t direct_max_chunks(int64_t cap) {
+  return std::max<int64_t>(1, std::min<int64_t>(kDirectChunks, ceil_div(std::max<int64_t>(cap, 1), kDirectMinEntries)));
+}
+
+// R_c = first rank whose entry offset is >= c E (c < C); R_C = n.
+__global__ __launch_bounds__(256) void k_chunk_bounds(int n, const uint32_t* __restrict__ offs, uint32_t E, int C,
+                                                      uint32_t* __restrict__ bounds) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c > C) return;
+  if (c == C) { bounds[c] = static_cast<uint32_t>(n); return; }
+  const uint32_t key = static_cast<uint32_t>(c) * E;
+  uint32_t lo = 0, hi = static_cast<uint32_t>(n);
+  while (lo < hi) {
+    const uint32_t mid = lo + ((hi - lo) >> 1);
+    if (offs[mid] < key) lo = mid + 1; else hi = mid;
+  }
+  bounds[c] = lo;
+}
+
+// In-place inclusive prefix sums of `len` ints at p[0], p[stride], ... by one wave.
+__device__ __forceinline__ void wave_prefix_lds(int* p, int len, int stride, int lane) {
+  int carry = 0;
+  for (int b = 0; b < len; b += 64) {
+    const int i = b + lane;
+    int v = i < len ? p[i * stride] : 0;
+    for (int d = 1; d < 64; d <<= 1) {
+      const int t = __shfl_up(v, d, 64);
+      if (lane >= d) v += t;
+    }
+    if (i < len) p[i * stride] = v + carry;
+    carry += __shfl(v, 63, 64);
+  }
+}
+
+constexpr int kDirectThreads = 1024;
+constexpr int kDirectWaves = kDirectThreads / 64;
+
+__global__ __launch_bounds__(kDirectThreads) void k_chunk_count(const uint32_t* __restrict__ bounds,
+                                                                const uint2* __restrict__ rect_rank, int tiles_x,
+                                                                int tiles_y, uint32_t* __restrict__ table) {
+  extern __shared__ int s_diff[];   // (tiles_y + 1) rows of (tiles_x + 1)
+  const int c = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int pitch = tiles_x + 1, cells = pitch * (tiles_y + 1);
+  for (int i = tid; i < cells; i += kDirectThreads) s_diff[i] = 0;
+  __syncthreads();
+  const uint32_t r1 = bounds[c + 1];
+  for (uint32_t r = bounds[c] + tid; r < r1; r += kDirectThreads) {
+    const uint2 rc = rect_rank[r];
+    if (rect_count(rc) == 0) continue;
+    const int x0 = static_cast<int>(rc.x & 0xFFFFu), xe = static_cast<int>(rc.x >> 16);
+    const int y0 = static_cast<int>(rc.y & 0xFFFFu), ye = static_cast<int>(rc.y >> 16);
+    atomicAdd(&s_diff[y0 * pitch + x0], 1);
+    atomicAdd(&s_diff[y0 * pitch + xe], -1);
+    atomicAdd(&s_diff[ye * pitch + x0], -1);
+    atomicAdd(&s_diff[ye * pitch + xe], 1);
+  }
+  __syncthreads();
+  for (int y = wave; y < tiles_y; y += kDirectWaves) wave_prefix_lds(s_diff + y * pitch, tiles_x, 1, lane);
+  __syncthreads();
+  for (int x = wave; x < tiles_x; x += kDirectWaves) wave_prefix_lds(s_diff + x, tiles_y, pitch, lane);
+  __syncthreads();
+  uint32_t* const out = table + static_cast<size_t>(c) * tiles_x * tiles_y;
+  for (int y = wave; y < tiles_y; y += kDirectWaves)
+    for (int x = lane; x < tiles_x; x += 64) out[y * tiles_x + x] = static_cast<uint32_t>(s_diff[y * pitch + x]);
+}
+
+// One workgroup (16 waves) per 64 tiles; wave w owns a contiguous range of
+// chunks.  table[c][t] becomes the entries of tile t in chunks before c.
+__global__ __launch_bounds__(1024) void k_chunk_colscan(int C, int ntiles, uint32_t* __restrict__ table,
+                                                        uint32_t* __restrict__ total) {
+  __shared__ uint32_t s_part[16][64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int t = blockIdx.x * 64 + lane;
+  const int per = (C + 15) / 16;
+  const int c0 = min(C, wave * per), c1 = min(C, c0 + per);
+  uint32_t sum = 0;
+  if (t < ntiles)
+    for (int c = c0; c < c1; ++c) sum += table[static_cast<size_t>(c) * ntiles + t];
+  s_part[wave][lane] = sum;
+  __syncthreads();
+  uint32_t run = 0, all = 0;
+  for (int w = 0; w < 16; ++w) {
+    const uint32_t v = s_part[w][lane];
+    run += (w < wave) ? v : 0u;
+    all += v;
+  }
+  if (t >= ntiles) return;
+  if (wave == 0) total[t] = all;
+  for (int c = c0; c < c1; ++c) {
+    const size_t o = static_cast<size_t>(c) * ntiles + t;
+    const uint32_t v = table[o];
+    table[o] = run;
+    run += v;
+  }
+}
+
+// start[t] = exclusive prefix of total over tiles; ranges[t] = (start, start + total).
+__global__ __launch_bounds__(1024) void k_tile_starts(int ntiles, const uint32_t* __restrict__ total,
+                                                      uint32_t* __restrict__ start, uint2* __restrict__ ranges) {
+  __shared__ uint32_t s_w[16];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int per = (ntiles + 1023) / 1024;
+  const int t0 = min(ntiles, tid * per), t1 = min(ntiles, t0 + per);
+  uint32_t sum = 0;
+  for (int t = t0; t < t1; ++t) sum += total[t];
+  uint32_t incl = sum;
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t v = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += v;
+  }
+  if (lane == 63) s_w[wave] = incl;
+  __syncthreads();
+  uint32_t run = incl - sum;
+  for (int w = 0; w < wave; ++w) run += s_w[w];
+  for (int t = t0; t < t1; ++t) {
+    const uint32_t v = total[t];
+    start[t] = run;
+    ranges[t] = make_uint2(run, run + v);
+    run += v;
+  }
+}
+
+// Groups of 256 ranks: waves 0-3 hold the ranks and their coverage masks,
+// all 16 waves then place 1024 entries per round.
+__global__ __launch_bounds__(kDirectThreads) void k_emit_direct(const uint32_t* __restrict__ bounds,
+                                                                const uint32_t* __restrict__ order,
+                                                                const uint2* __restrict__ rect_rank,
+                                                                const uint32_t* __restrict__ table,
+                                                                const uint32_t* __restrict__ start, int tiles_x,
+                                                                int tiles_y, uint32_t* __restrict__ point_list,
+                                                                uint32_t capacity) {
+  extern __shared__ unsigned long long s_dyn[];
+  __shared__ uint32_t s_pre[257];
+  __shared__ uint32_t s_gid[256];
+  __shared__ uint2 s_rect[256];
+  __shared__ uint32_t s_wsum[4];
+  const int ntiles = tiles_x * tiles_y;
+  const int edge = tiles_x + tiles_y;
+  // masks: col[w][x] at s_dyn[w * edge + x], row[w][y] at s_dyn[w * edge + tiles_x + y]; then run[t]
+  uint32_t* const s_run = reinterpret_cast<uint32_t*>(s_dyn + 4 * edge);
+  const int c = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const uint32_t R0 = bounds[c], R1 = bounds[c + 1];
+  if (R0 >= R1) return;
+  const uint32_t* const tab = table + static_cast<size_t>(c) * ntiles;
+  for (int t = tid; t < ntiles; t += kDirectThreads) s_run[t] = start[t] + tab[t];
+  for (uint32_t r0 = R0; r0 < R1; r0 += 256) {
+    __syncthreads();   // the previous group's readers are done
+    if (wave < 4) {
+      const uint32_t r = r0 + static_cast<uint32_t>(tid);
+      const bool valid = r < R1;
+      const uint2 rc = valid ? rect_rank[r] : make_uint2(0u, 0u);
+      const uint32_t cnt = rect_count(rc);
+      s_rect[tid] = rc;
+      s_gid[tid] = valid ? order[r] : 0u;
+      uint32_t incl = cnt;
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t t = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += t;
+      }
+      s_pre[tid] = incl - cnt;             // within the wave for now
+      if (lane == 63) s_wsum[wave] = incl;
+      // this wave's coverage masks: zero, then set -- per lane over its own
+      // columns and rows, or by ballots over the wave's joint extent,
+      // whichever takes fewer steps
+      unsigned long long* const col = s_dyn + wave * edge;
+      unsigned long long* const row = col + tiles_x;
+      for (int i = lane; i < edge; i += 64) col[i] = 0ull;
+      const int x0 = static_cast<int>(rc.x & 0xFFFFu), xe = static_cast<int>(rc.x >> 16);
+      const int y0 = static_cast<int>(rc.y & 0xFFFFu), ye = static_cast<int>(rc.y >> 16);
+      const bool has = cnt > 0;
+      int own = has ? (xe - x0) + (ye - y0) : 0;
+      int xmin = has ? x0 : tiles_x, xmax = has ? xe : 0, ymin = has ? y0 : tiles_y, ymax = has ? ye : 0;
+      for (int o = 32; o > 0; o >>= 1) {
+        own = max(own, __shfl_xor(own, o, 64));
+        xmin = min(xmin, __shfl_xor(xmin, o, 64));
+        xmax = max(xmax, __shfl_xor(xmax, o, 64));
+        ymin = min(ymin, __shfl_xor(ymin, o, 64));
+        ymax = max(ymax, __shfl_xor(ymax, o, 64));
+      }
+      const unsigned long long bit = 1ull << lane;
+      if (own <= max(xmax - xmin, 0) + max(ymax - ymin, 0)) {
+        if (has) {
+          for (int x = x0; x < xe; ++x) atomicOr(&col[x], bit);
+          for (int y = y0; y < ye; ++y) atomicOr(&row[y], bit);
+        }
+      } else {
+        for (int x = xmin; x < xmax; ++x) {
+          const unsigned long long m = __ballot(has && x0 <= x && x < xe);
+          if (lane == 0) col[x] = m;
+        }
+        for (int y = ymin; y < ymax; ++y) {
+          const unsigned long long m = __ballot(has && y0 <= y && y < ye);
+          if (lane == 0) row[y] = m;
+        }
+      }
+    }
+    __syncthreads();
+    if (wave < 4) {
+      uint32_t before = 0;
+      for (int w = 0; w < wave; ++w) before += s_wsum[w];
+      s_pre[tid] += before;
+      if (tid == 255) s_pre[256] = before + s_wsum[3];
+    }
+    __syncthreads();
+    const uint32_t S = s_pre[256];
+    for (uint32_t e0 = 0; e0 < S; e0 += kDirectThreads) {
+      const uint32_t e = e0 + static_cast<uint32_t>(tid);
+      bool last = false;
+      int t = 0;
+      uint32_t next = 0;
+      if (e < S) {
+        // owner: the last rank i with s_pre[i] <= e
+        int lo = 0, hi = 255;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_pre[mid] <= e) lo = mid; else hi = mid - 1;
+        }
+        const uint2 q = s_rect[lo];
+        const uint32_t j = e - s_pre[lo];
+        const uint32_t qx0 = q.x & 0xFFFFu, w = (q.x >> 16) - qx0;
+        // row = j / w without an integer division (float quotient within one)
+        uint32_t rr = static_cast<uint32_t>(static_cast<float>(j) * __builtin_amdgcn_rcpf(static_cast<float>(w)));
+        if (rr * w > j) --rr;
+        else if ((rr + 1) * w <= j) ++rr;
+        const int tx = static_cast<int>(qx0 + (j - rr * w));
+        const int ty = static_cast<int>((q.y & 0xFFFFu) + rr);
+        t = ty * tiles_x + tx;
+        const int wv = lo >> 6, l = lo & 63;
+        uint32_t within = 0;
+        unsigned long long later = 0ull;
+#pragma unroll
+        for (int w2 = 0; w2 < 4; ++w2) {
+          const unsigned long long m = s_dyn[w2 * edge + tx] & s_dyn[w2 * edge + tiles_x + ty];
+          if (w2 < wv) within += static_cast<uint32_t>(__popcll(m));
+          else if (w2 == wv) { within += static_cast<uint32_t>(__popcll(m & ((1ull << l) - 1ull))); later |= (m >> l) >> 1; }
+          else later |= m;
+        }
+        const uint32_t pos = s_run[t] + within;
+        if (pos < capacity) point_list[pos] = s_gid[lo];
+        last = later == 0ull;
+        next = pos + 1;
+      }
+      __syncthreads();
+      if (last) s_run[t] = next;
+      __syncthreads();
+    }
+  }
+}
+
 static int bits_for(int64_t values) {  // bits needed to represent 0..values-1
   int b = 0;
   while ((int64_t(1) << b) < values) ++b;
@@ -411,9 +690,11 @@ struct BinWs {
   uint32_t *ek0, *ek1, *ev1;
   uint32_t* hist;
   ScanWs scan;
+  // direct emission: chunk bounds, chunk x tile table, tile totals and starts
+  uint32_t *bounds, *table, *total, *start;
 };
 
-static BinWs carve_bin(void* ws, int64_t n, int64_t cap, size_t* used) {
+static BinWs carve_bin(void* ws, int64_t n, int64_t cap, int tiles_x, int tiles_y, size_t* used) {
   Carver c(ws);
   BinWs b;
   const size_t N = static_cast<size_t>(n > 0 ? n : 1), C = static_cast<size_t>(cap > 0 ? cap : 1);
@@ -428,14 +709,22 @@ static BinWs carve_bin(void* ws, int64_t n, int64_t cap, size_t* used) {
   b.hist = c.take<uint32_t>(hist_words);
   b.scan.sums = c.take<uint32_t>(scan_ws_words(std::max<int64_t>(static_cast<int64_t>(hist_words), maxn)));
   b.scan.total = c.take<unsigned long long>(1);
+  b.bounds = b.table = b.total = b.start = nullptr;
+  if (direct_ok(tiles_x, tiles_y)) {
+    const size_t nt = static_cast<size_t>(tiles_x) * tiles_y;
+    const size_t chunks = static_cast<size_t>(direct_max_chunks(cap));
+    b.bounds = c.take<uint32_t>(chunks + 1);
+    b.table = c.take<uint32_t>(chunks * nt);
+    b.total = c.take<uint32_t>(nt);
+    b.start = c.take<uint32_t>(nt);
+  }
   *used = c.off + 256;
   return b;
 }
 
-size_t binsort_workspace(int64_t n, int64_t capacity, int ntiles) {
-  (void)ntiles;
+size_t binsort_workspace(int64_t n, int64_t capacity, int tiles_x, int tiles_y) {
   size_t used = 0;
-  carve_bin(nullptr, n, capacity, &used);
+  carve_bin(nullptr, n, capacity, tiles_x, tiles_y, &used);
   return used;
 }
 
@@ -444,7 +733,7 @@ gs_status run_bin_sort(int64_t n64, const gs_projected& proj, const DevCam& cam,
   const int n = static_cast<int>(n64);
   const int ntiles = cam.tiles_x * cam.tiles_y;
   size_t need = 0;
-  BinWs b = carve_bin(ws, n64, capacity, &need);
+  BinWs b = carve_bin(ws, n64, capacity, cam.tiles_x, cam.tiles_y, &need);
   if (ws_bytes < need) return fail(GS_ERR_INVALID_ARG, "gs_bin_sort: workspace too small");
   gs_status st;
   int64_t K = 0;
@@ -466,6 +755,24 @@ gs_status run_bin_sort(int64_t n64, const gs_projected& proj, const DevCam& cam,
     *k_out = K;
     if (K >= (int64_t(1) << 32)) return fail(GS_ERR_UNSUPPORTED, "gs_bin_sort: more than 2^32 entries");
     if (K > capacity) return fail(GS_ERR_CAPACITY, "gs_bin_sort: capacity too small");
+    if (K > 0 && b.table) {
+      const uint32_t E = static_cast<uint32_t>(std::max<int64_t>(kDirectMinEntries, ceil_div(K, kDirectChunks)));
+      const int C = static_cast<int>(ceil_div(K, E));
+      const int tx = cam.tiles_x, ty = cam.tiles_y;
+      k_chunk_bounds<<<static_cast<unsigned>(ceil_div(C + 1, 256)), 256, 0, s>>>(n, b.offs, E, C, b.bounds);
+      if ((st = check_launch("k_chunk_bounds")) != GS_OK) return st;
+      k_chunk_count<<<C, kDirectThreads, sizeof(int) * (tx + 1) * (ty + 1), s>>>(b.bounds, b.rect_rank, tx, ty,
+                                                                            b.table);
+      if ((st = check_launch("k_chunk_count")) != GS_OK) return st;
+      k_chunk_colscan<<<static_cast<unsigned>(ceil_div(ntiles, 64)), 1024, 0, s>>>(C, ntiles, b.table, b.total);
+      if ((st = check_launch("k_chunk_colscan")) != GS_OK) return st;
+      k_tile_starts<<<1, 1024, 0, s>>>(ntiles, b.total, b.start, reinterpret_cast<uint2*>(ranges));
+      if ((st = check_launch("k_tile_starts")) != GS_OK) return st;
+      const size_t dyn = sizeof(unsigned long long) * 4 * (tx + ty) + sizeof(uint32_t) * ntiles;
+      k_emit_direct<<<C, kDirectThreads, dyn, s>>>(b.bounds, order, b.rect_rank, b.table, b.start, tx, ty, point_list,
+                                        static_cast<uint32_t>(std::min<int64_t>(capacity, UINT32_MAX)));
+      return check_launch("k_emit_direct");
+    }
     if (K > 0) {
       const int tbits = bits_for(ntiles);
       const int tp = sort_passes(tbits);

@@ -122,7 +122,7 @@ inline size_t batch_item_ints(int64_t k, int64_t ntiles) {
 }
 gs_status launch_project_bwd(const gs_gaussians& g, const DevCam& cam, const int* radius, const float* g2d,
                              gs_gaussians_grad& grad, void* ws, hipStream_t s);
-size_t binsort_workspace(int64_t n, int64_t capacity, int ntiles);
+size_t binsort_workspace(int64_t n, int64_t capacity, int tiles_x, int tiles_y);
 // Exclusive prefix sum of n uint32 values (out may alias in); sums holds
 // scan_sums_words(n) words, total (optional) receives the 64-bit sum.
 size_t scan_sums_words(int64_t n);

@@ -455,3 +455,20 @@ def test_deterministic_backward(gs, name):
             worst = max(worst, grad_close(ah[:, j], o_g2d[:, j], name=f"schedule {sched} g2d.{nm}",
                                           mass=o_mass[:, j]))
         say(f"  schedule {sched}: bit-identical reruns, worst rel err {worst:.2e}")
+
+
+def test_bin_sort_wide_frame_fallback(gs):
+    """A frame whose per-chunk tile tables exceed the LDS budget (150 x 63
+    tiles) takes the two-pass radix tile sort instead of the direct emission;
+    both must give the oracle's lists bit for bit."""
+    scene = scenes.skewed_scene(30000, 91, n_clusters=16, log_scale_mean=-3.6, sh_degree=1)
+    cam = scenes.pinhole(2400, 1000, 70.0, np.eye(3), (0.0, 0.0, 3.0))
+    say(f"[bin/sort wide] n={scene.n} {cam.width}x{cam.height}")
+    p, g, out = gpu_project(gs, scene, cam)
+    h = proj_host(out)
+    k, pl, ranges = gpu_bin_sort(gs, scene.n, out, cam)
+    o_pl, o_ranges, _, _ = oracle.bin_sort(h["u"], h["v"], h["radius"], h["depth"], cam.width, cam.height)
+    assert k == len(o_pl) and k > 0
+    assert np.array_equal(pl[:k].cpu().numpy().view(np.uint32), o_pl), "point_list"
+    assert np.array_equal(ranges.cpu().numpy().view(np.uint32), o_ranges), "ranges"
+    say(f"  K={k} bit-exact")
