@@ -409,25 +409,30 @@ __global__ __launch_bounds__(256) void k_ranges(int ntiles, const uint32_t* __re
 //  2. k_chunk_colscan: per tile, the exclusive prefix over chunks (in place)
 //     and the tile's total; k_tile_starts: exclusive prefix of the totals
 //     over tiles, which gives the ranges.
-//  3. k_emit_direct: one workgroup per chunk walks its ranks 256 at a time
-//     (1024 entries placed per round), keeping each tile's next free
-//     position in LDS.  Within a group of 256
-//     ranks, rank i = 64 w + l precedes rank i' on tile (tx, ty) iff both
-//     rectangles contain the tile; with per-wave 64-bit masks col[w][x] (lanes
-//     whose rectangle spans column x) and row[w][y], the number of earlier
-//     ranks on the tile is sum_{w' < w} popc(col[w'][tx] & row[w'][ty]) +
-//     popc(col[w][tx] & row[w][ty] & lanes below l).  So every entry computes
-//     its final position independently; the last entry of a tile in the group
-//     advances the tile's position afterwards.
+//  3. k_emit_direct: one workgroup per chunk walks its ranks 256 at a time.
+//     Rank 64 w + l of a group comes before rank 64 w' + l' on a tile that
+//     both rectangles contain iff (w, l) < (w', l'); with per-wave 64-bit
+//     masks col[w][x] (lanes whose rectangle spans column x) and row[w][y],
+//     the number of the group's ranks before rank 64 w + l on tile (tx, ty)
+//     is sum_{w' < w} popc(col[w'][tx] & row[w'][ty]) + popc(col[w][tx] &
+//     row[w][ty] & lanes below l).  So each entry computes its final
+//     position independently from the tile's position at the group start.
 // Same result as a stable sort by tile of the rank-ordered emission, i.e. the
 // order (tile, depth bits, index).  Used while the per-chunk tables fit in LDS.
-constexpr int kDirectMaxCells = 9216;   // (tiles_x + 1) (tiles_y + 1)
-constexpr int kDirectMaxEdge = 512;     // tiles_x + tiles_y
 constexpr int kDirectChunks = 512;      // chunks at most
 constexpr int64_t kDirectMinEntries = 4096;
+constexpr size_t kLdsBudget = 65536;    // bytes of LDS per workgroup
+constexpr size_t kEmitStaticLds = 4608; // k_emit_direct's fixed arrays, rounded up
 
+// LDS of the direct emission: masks col[4][tiles_x], row[4][tiles_y] (u64),
+// then pos[ntiles] (u32) and delta[ntiles] (u16).
+static size_t emit_dyn_lds(int tiles_x, int tiles_y) {
+  const size_t nt = static_cast<size_t>(tiles_x) * tiles_y;
+  return 32 * static_cast<size_t>(tiles_x + tiles_y) + 4 * nt + 2 * ((nt + 1) / 2 * 2);
+}
 static bool direct_ok(int tiles_x, int tiles_y) {
-  return (tiles_x + 1) * (tiles_y + 1) <= kDirectMaxCells && tiles_x + tiles_y <= kDirectMaxEdge;
+  return 4 * static_cast<size_t>(tiles_x + 1) * (tiles_y + 1) <= kLdsBudget &&
+         emit_dyn_lds(tiles_x, tiles_y) + kEmitStaticLds <= kLdsBudget;
 }
 static int64_t direct_max_chunks(int64_t cap) {
   return std::max<int64_t>(1, std::min<int64_t>(kDirectChunks, ceil_div(std::max<int64_t>(cap, 1), kDirectMinEntries)));
@@ -551,8 +556,15 @@ __global__ __launch_bounds__(1024) void k_tile_starts(int ntiles, const uint32_t
   }
 }
 
-// Groups of 256 ranks: waves 0-3 hold the ranks and their coverage masks,
-// all 16 waves then place 1024 entries per round.
+// Groups of 256 ranks.  Waves 0-3 load the group's ranks (64 each) and build
+// their coverage masks; then wave w places the entries of rank-wave w & 3,
+// taking every fourth run of 64 of them.  An entry finds its rank by a
+// binary search over the 64 entry offsets of its rank-wave, its tile from
+// the rank's rectangle, and its position as the tile's position at the start
+// of the group plus the count of the group's earlier ranks on the tile.  The
+// entry of the tile's last rank in the group also writes the group's count
+// for the tile into delta[t], which one pass over the tiles adds to the
+// positions once every entry of the group is placed.
 __global__ __launch_bounds__(kDirectThreads) void k_emit_direct(const uint32_t* __restrict__ bounds,
                                                                 const uint32_t* __restrict__ order,
                                                                 const uint2* __restrict__ rect_rank,
@@ -560,22 +572,26 @@ __global__ __launch_bounds__(kDirectThreads) void k_emit_direct(const uint32_t* 
                                                                 const uint32_t* __restrict__ start, int tiles_x,
                                                                 int tiles_y, uint32_t* __restrict__ point_list,
                                                                 uint32_t capacity) {
+  // dynamic: col[4][tiles_x] row[4][tiles_y] (u64), then pos[ntiles] (u32), delta[ntiles] (u16)
   extern __shared__ unsigned long long s_dyn[];
-  __shared__ uint32_t s_pre[257];
+  __shared__ uint32_t s_pre[4][65];   // per rank-wave: exclusive entry offsets, then the total
   __shared__ uint32_t s_gid[256];
   __shared__ uint2 s_rect[256];
-  __shared__ uint32_t s_wsum[4];
   const int ntiles = tiles_x * tiles_y;
   const int edge = tiles_x + tiles_y;
-  // masks: col[w][x] at s_dyn[w * edge + x], row[w][y] at s_dyn[w * edge + tiles_x + y]; then run[t]
-  uint32_t* const s_run = reinterpret_cast<uint32_t*>(s_dyn + 4 * edge);
+  uint32_t* const s_pos = reinterpret_cast<uint32_t*>(s_dyn + 4 * edge);
+  uint16_t* const s_delta = reinterpret_cast<uint16_t*>(s_pos + ntiles);
   const int c = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const uint32_t R0 = bounds[c], R1 = bounds[c + 1];
   if (R0 >= R1) return;
   const uint32_t* const tab = table + static_cast<size_t>(c) * ntiles;
-  for (int t = tid; t < ntiles; t += kDirectThreads) s_run[t] = start[t] + tab[t];
+  for (int t = tid; t < ntiles; t += kDirectThreads) {
+    s_pos[t] = start[t] + tab[t];
+    s_delta[t] = 0;
+  }
+  const int rw = wave & 3, helper = wave >> 2;
   for (uint32_t r0 = R0; r0 < R1; r0 += 256) {
-    __syncthreads();   // the previous group's readers are done
+    __syncthreads();   // positions updated, masks of the previous group no longer read
     if (wave < 4) {
       const uint32_t r = r0 + static_cast<uint32_t>(tid);
       const bool valid = r < R1;
@@ -588,8 +604,8 @@ __global__ __launch_bounds__(kDirectThreads) void k_emit_direct(const uint32_t* 
         const uint32_t t = __shfl_up(incl, d, 64);
         if (lane >= d) incl += t;
       }
-      s_pre[tid] = incl - cnt;             // within the wave for now
-      if (lane == 63) s_wsum[wave] = incl;
+      s_pre[wave][lane] = incl - cnt;
+      if (lane == 63) s_pre[wave][64] = incl;
       // this wave's coverage masks: zero, then set -- per lane over its own
       // columns and rows, or by ballots over the wave's joint extent,
       // whichever takes fewer steps
@@ -626,54 +642,48 @@ __global__ __launch_bounds__(kDirectThreads) void k_emit_direct(const uint32_t* 
       }
     }
     __syncthreads();
-    if (wave < 4) {
-      uint32_t before = 0;
-      for (int w = 0; w < wave; ++w) before += s_wsum[w];
-      s_pre[tid] += before;
-      if (tid == 255) s_pre[256] = before + s_wsum[3];
+    // place the entries of rank-wave rw, runs of 64 taken round-robin by its
+    // four helper waves
+    const uint32_t* const pre = s_pre[rw];
+    const uint32_t S = pre[64];
+    for (uint32_t e = static_cast<uint32_t>(helper) * 64 + lane; e - lane < S; e += 256) {
+      if (e >= S) continue;
+      int lo = 0;
+#pragma unroll
+      for (int step = 32; step > 0; step >>= 1)
+        lo += (pre[lo + step] <= e) ? step : 0;   // the last rank with offset <= e
+      const int i = rw * 64 + lo;
+      const uint2 q = s_rect[i];
+      const uint32_t j = e - pre[lo];
+      const uint32_t qx0 = q.x & 0xFFFFu, w = (q.x >> 16) - qx0;
+      // row = j / w without an integer division (float quotient within one)
+      uint32_t rr = static_cast<uint32_t>(static_cast<float>(j) * __builtin_amdgcn_rcpf(static_cast<float>(w)));
+      const uint32_t prod = rr * w;
+      rr = (prod > j) ? rr - 1u : ((prod + w <= j) ? rr + 1u : rr);
+      const int tx = static_cast<int>(qx0 + (j - rr * w));
+      const int ty = static_cast<int>((q.y & 0xFFFFu) + rr);
+      const int t = ty * tiles_x + tx;
+      // earlier ranks of the group on the tile: whole earlier rank-waves, then
+      // the lanes below lo of this one; later ones decide "last"
+      const unsigned long long below = (1ull << lo) - 1ull;
+      uint32_t within = 0;
+      unsigned long long later = 0ull;
+#pragma unroll
+      for (int w2 = 0; w2 < 4; ++w2) {
+        const unsigned long long m = s_dyn[w2 * edge + tx] & s_dyn[w2 * edge + tiles_x + ty];
+        const unsigned long long lo_sel = (w2 < rw) ? ~0ull : ((w2 == rw) ? below : 0ull);
+        const unsigned long long hi_sel = (w2 > rw) ? ~0ull : ((w2 == rw) ? ~(below | (1ull << lo)) : 0ull);
+        within += static_cast<uint32_t>(__popcll(m & lo_sel));
+        later |= m & hi_sel;
+      }
+      const uint32_t p = s_pos[t] + within;
+      if (p < capacity) point_list[p] = s_gid[i];
+      if (later == 0ull) s_delta[t] = static_cast<uint16_t>(within + 1u);   // at most 256
     }
     __syncthreads();
-    const uint32_t S = s_pre[256];
-    for (uint32_t e0 = 0; e0 < S; e0 += kDirectThreads) {
-      const uint32_t e = e0 + static_cast<uint32_t>(tid);
-      bool last = false;
-      int t = 0;
-      uint32_t next = 0;
-      if (e < S) {
-        // owner: the last rank i with s_pre[i] <= e
-        int lo = 0, hi = 255;
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (s_pre[mid] <= e) lo = mid; else hi = mid - 1;
-        }
-        const uint2 q = s_rect[lo];
-        const uint32_t j = e - s_pre[lo];
-        const uint32_t qx0 = q.x & 0xFFFFu, w = (q.x >> 16) - qx0;
-        // row = j / w without an integer division (float quotient within one)
-        uint32_t rr = static_cast<uint32_t>(static_cast<float>(j) * __builtin_amdgcn_rcpf(static_cast<float>(w)));
-        if (rr * w > j) --rr;
-        else if ((rr + 1) * w <= j) ++rr;
-        const int tx = static_cast<int>(qx0 + (j - rr * w));
-        const int ty = static_cast<int>((q.y & 0xFFFFu) + rr);
-        t = ty * tiles_x + tx;
-        const int wv = lo >> 6, l = lo & 63;
-        uint32_t within = 0;
-        unsigned long long later = 0ull;
-#pragma unroll
-        for (int w2 = 0; w2 < 4; ++w2) {
-          const unsigned long long m = s_dyn[w2 * edge + tx] & s_dyn[w2 * edge + tiles_x + ty];
-          if (w2 < wv) within += static_cast<uint32_t>(__popcll(m));
-          else if (w2 == wv) { within += static_cast<uint32_t>(__popcll(m & ((1ull << l) - 1ull))); later |= (m >> l) >> 1; }
-          else later |= m;
-        }
-        const uint32_t pos = s_run[t] + within;
-        if (pos < capacity) point_list[pos] = s_gid[lo];
-        last = later == 0ull;
-        next = pos + 1;
-      }
-      __syncthreads();
-      if (last) s_run[t] = next;
-      __syncthreads();
+    for (int t = tid; t < ntiles; t += kDirectThreads) {
+      const uint32_t d = s_delta[t];
+      if (d) { s_pos[t] += d; s_delta[t] = 0; }
     }
   }
 }
@@ -768,7 +778,7 @@ gs_status run_bin_sort(int64_t n64, const gs_projected& proj, const DevCam& cam,
       if ((st = check_launch("k_chunk_colscan")) != GS_OK) return st;
       k_tile_starts<<<1, 1024, 0, s>>>(ntiles, b.total, b.start, reinterpret_cast<uint2*>(ranges));
       if ((st = check_launch("k_tile_starts")) != GS_OK) return st;
-      const size_t dyn = sizeof(unsigned long long) * 4 * (tx + ty) + sizeof(uint32_t) * ntiles;
+      const size_t dyn = emit_dyn_lds(tx, ty);
       k_emit_direct<<<C, kDirectThreads, dyn, s>>>(b.bounds, order, b.rect_rank, b.table, b.start, tx, ty, point_list,
                                         static_cast<uint32_t>(std::min<int64_t>(capacity, UINT32_MAX)));
       return check_launch("k_emit_direct");
