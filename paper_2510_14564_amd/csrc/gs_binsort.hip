@@ -17,7 +17,7 @@
 namespace gs {
 
 constexpr int kRsThreads = 256;
-constexpr int kRsItemsN = 4;    // depth sort of N keys: 1024 keys per block (more blocks)
+constexpr int kOsItemsN = 16;   // depth sort of N keys (onesweep): 4096 keys per workgroup
 constexpr int kRsItemsK = 16;   // tile sort of K entries: 4096 keys per block
 constexpr int kScanItems = 16;
 constexpr int kScanChunk = 256 * kScanItems;
@@ -280,6 +280,235 @@ static gs_status radix_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, uint
   return GS_OK;
 }
 
+// ------------------------------------------------------------ onesweep sort
+// Stable LSD radix sort of (key, value) pairs in passes of up to 8 bits, one
+// sweep per pass:
+//   k_os_hist     one read of the keys: the global digit counts of every
+//                 pass at once (workgroup counts in LDS, then one atomic per
+//                 digit per workgroup); it also clears the pass state below.
+//   k_os_scatter  per pass: workgroup v (in the order workgroups start, from
+//                 an atomic counter) ranks chunk v of the keys stably, then
+//                 learns how many keys of each digit the chunks before it
+//                 hold by decoupled look-back: it publishes its own digit
+//                 counts, walks back over its predecessors' published words
+//                 (a count, or an inclusive prefix that ends the walk) and
+//                 publishes its inclusive prefix.  A workgroup waits only on
+//                 workgroups that started before it and publish their counts
+//                 without waiting, so every wait ends; each spin is bounded
+//                 all the same, and a bound that runs out sets an error flag.
+// Published words pack a 2-bit state with a 30-bit count and are read and
+// written with device-scope atomics, which keep them coherent across XCDs.
+
+constexpr uint32_t kOsEmpty = 0u, kOsAgg = 1u, kOsIncl = 2u;
+constexpr uint32_t kOsCountMask = (1u << 30) - 1u;
+constexpr int kOsHistBlocks = 1024;
+constexpr int kOsMaxPasses = 4;
+constexpr uint32_t kOsSpinLimit = 1u << 22;
+constexpr int kOsWindow = 8;
+
+__device__ __forceinline__ uint32_t os_load(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void os_store(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ghist[pass][256] must be zero on entry.  Clears state[] (state_words) and
+// the per-pass start counters.
+__global__ __launch_bounds__(256) void k_os_hist(const uint32_t* __restrict__ keys, int64_t count, int total_bits,
+                                                 uint32_t* __restrict__ ghist, uint32_t* __restrict__ state,
+                                                 int64_t state_words, uint32_t* __restrict__ counters) {
+  __shared__ uint32_t h[kOsMaxPasses][256];
+  const int passes = (total_bits + 7) / 8;
+  for (int p = 0; p < kOsMaxPasses; ++p) h[p][threadIdx.x] = 0;
+  const int64_t gtid = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  const int64_t gstride = static_cast<int64_t>(gridDim.x) * 256;
+  for (int64_t i = gtid; i < state_words; i += gstride) state[i] = 0u;
+  if (gtid < kOsMaxPasses) counters[gtid] = 0u;
+  __syncthreads();
+  constexpr int U = 8;
+  for (int64_t base = static_cast<int64_t>(blockIdx.x) * 256 * U; base < count; base += gstride * U) {
+    uint32_t k[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t idx = base + u * 256 + threadIdx.x;
+      k[u] = idx < count ? keys[idx] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (base + u * 256 + threadIdx.x >= count) continue;
+      for (int p = 0; p < passes; ++p) {
+        const int nbits = min(8, total_bits - 8 * p);
+        atomicAdd(&h[p][(k[u] >> (8 * p)) & ((1u << nbits) - 1u)], 1u);
+      }
+    }
+  }
+  __syncthreads();
+  for (int p = 0; p < passes; ++p)
+    if (h[p][threadIdx.x]) atomicAdd(&ghist[p * 256 + threadIdx.x], h[p][threadIdx.x]);
+}
+
+template <int ITEMS>
+__global__ __launch_bounds__(kRsThreads) void k_os_scatter(const uint32_t* __restrict__ keys_in,
+                                                           const uint32_t* __restrict__ vals_in,
+                                                           uint32_t* __restrict__ keys_out,
+                                                           uint32_t* __restrict__ vals_out, int64_t count,
+                                                           int shift, int nbits,
+                                                           const uint32_t* __restrict__ ghist_pass,
+                                                           uint32_t* __restrict__ state_pass,
+                                                           uint32_t* __restrict__ counter, uint32_t* __restrict__ err) {
+  constexpr int CHUNK = kRsThreads * ITEMS;
+  constexpr int PER_WAVE = CHUNK / 4;
+  __shared__ uint32_t sk[CHUNK];
+  __shared__ uint32_t sv[CHUNK];
+  __shared__ uint32_t wrun[4][256];   // per-wave running digit counts
+  __shared__ uint32_t dstart[256];    // block-local start of each digit
+  __shared__ uint32_t gbase[256];     // global start of each digit for this block
+  __shared__ uint32_t scan_tmp[256];
+  __shared__ uint32_t s_vid;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const uint32_t mask = (1u << nbits) - 1u;
+  if (tid == 0) s_vid = atomicAdd(counter, 1u);
+  wrun[0][tid] = 0; wrun[1][tid] = 0; wrun[2][tid] = 0; wrun[3][tid] = 0;
+  __syncthreads();
+  const uint32_t vid = s_vid;
+  const int64_t base = static_cast<int64_t>(vid) * CHUNK + static_cast<int64_t>(wave) * PER_WAVE;
+  const uint64_t below = lanemask_lt();
+  uint32_t k[ITEMS], v[ITEMS], lr[ITEMS];
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const int64_t idx = base + j * 64 + lane;
+    const bool valid = idx < count;
+    k[j] = valid ? keys_in[idx] : 0u;
+    v[j] = valid ? vals_in[idx] : 0u;
+  }
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const int64_t idx = base + j * 64 + lane;
+    const bool valid = idx < count;
+    const uint32_t d = (k[j] >> shift) & mask;
+    const uint64_t peers = match_digit(d, nbits, valid);
+    const uint32_t before = valid ? wrun[wave][d] : 0u;
+    lr[j] = before + static_cast<uint32_t>(__popcll(peers & below));
+    if (valid && (peers & below) == 0) wrun[wave][d] = before + static_cast<uint32_t>(__popcll(peers));
+  }
+  __syncthreads();
+  // per digit: wave offsets and the block's count, then block-local starts
+  const uint32_t c0 = wrun[0][tid], c1 = wrun[1][tid], c2 = wrun[2][tid], c3 = wrun[3][tid];
+  const uint32_t cnt = c0 + c1 + c2 + c3;
+  uint32_t tot;
+  const uint32_t ds = block_exclusive_scan(cnt, scan_tmp, tot);
+  // global digit starts of this pass: exclusive scan of the global counts
+  const uint32_t gd = block_exclusive_scan(static_cast<uint32_t>(tid) <= mask ? ghist_pass[tid] : 0u, scan_tmp, tot);
+  // decoupled look-back, one digit per thread
+  uint32_t prefix = 0;
+  if (static_cast<uint32_t>(tid) <= mask) {
+    uint32_t* mine = state_pass + static_cast<int64_t>(vid) * 256 + tid;
+    if (vid == 0) {
+      os_store(mine, (kOsIncl << 30) | cnt);
+    } else {
+      os_store(mine, (kOsAgg << 30) | cnt);
+      // walk back kOsWindow predecessors at a time (their loads in flight
+      // together): add counts until an inclusive prefix; at a predecessor
+      // that has not published yet, wait for it and reload from there
+      int64_t j = static_cast<int64_t>(vid) - 1;
+      uint32_t spins = 0;
+      bool found = false;
+      while (j >= 0 && !found) {
+        uint32_t w[kOsWindow];
+#pragma unroll
+        for (int u = 0; u < kOsWindow; ++u) w[u] = (j - u >= 0) ? os_load(state_pass + (j - u) * 256 + tid) : 0u;
+        int used = 0;
+        bool blocked = false;
+#pragma unroll
+        for (int u = 0; u < kOsWindow; ++u) {
+          if (found || blocked || j - u < 0) continue;
+          const uint32_t f = w[u] >> 30;
+          if (f == kOsEmpty) { blocked = true; continue; }
+          prefix += w[u] & kOsCountMask;
+          ++used;
+          if (f == kOsIncl) found = true;
+        }
+        j -= used;
+        if (blocked && !found) {
+          if (++spins > kOsSpinLimit) { atomicOr(err, 1u); break; }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+      os_store(mine, (kOsIncl << 30) | ((prefix + cnt) & kOsCountMask));
+    }
+  }
+  wrun[0][tid] = ds;
+  wrun[1][tid] = ds + c0;
+  wrun[2][tid] = ds + c0 + c1;
+  wrun[3][tid] = ds + c0 + c1 + c2;
+  dstart[tid] = ds;
+  gbase[tid] = gd + prefix;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const int64_t idx = base + j * 64 + lane;
+    if (idx < count) {
+      const uint32_t d = (k[j] >> shift) & mask;
+      const uint32_t pos = wrun[wave][d] + lr[j];
+      sk[pos] = k[j];
+      sv[pos] = v[j];
+    }
+  }
+  __syncthreads();
+  const int64_t bbase = static_cast<int64_t>(vid) * CHUNK;
+  const int64_t nvalid = min(static_cast<int64_t>(CHUNK), count - bbase);
+  for (int p = tid; p < nvalid; p += kRsThreads) {
+    const uint32_t key = sk[p];
+    const uint32_t d = (key >> shift) & mask;
+    const uint32_t g = gbase[d] + (static_cast<uint32_t>(p) - dstart[d]);
+    keys_out[g] = key;
+    vals_out[g] = sv[p];
+  }
+}
+
+struct OsWs {
+  uint32_t* ghist;     // [kOsMaxPasses][256]
+  uint32_t* state;     // [passes][chunks][256]
+  uint32_t* counters;  // [kOsMaxPasses]
+  uint32_t* err;       // [1]
+};
+
+static size_t os_state_words(int64_t count, int items, int passes) {
+  return static_cast<size_t>(passes) * 256 * static_cast<size_t>(ceil_div(std::max<int64_t>(count, 1),
+                                                                          kRsThreads * items));
+}
+
+// Sorts `count` pairs over key bits [0, total_bits).  Input in (ka, va); the
+// result ends in (ka, va) if the pass count is even, else in (kb, vb).
+// w.ghist must be zero on entry (k_depth_keys clears both sorts' counts).
+template <int ITEMS>
+static gs_status onesweep_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int64_t count,
+                                     int total_bits, OsWs w, hipStream_t s, int* passes_out) {
+  constexpr int CHUNK = kRsThreads * ITEMS;
+  const int passes = (total_bits + 7) / 8;
+  *passes_out = 0;
+  if (count <= 0) return GS_OK;
+  const int nblocks = static_cast<int>(ceil_div(count, CHUNK));
+  gs_status st;
+  const int hb = static_cast<int>(std::min<int64_t>(kOsHistBlocks, ceil_div(count, 256 * 8)));
+  k_os_hist<<<std::max(hb, 1), 256, 0, s>>>(ka, count, total_bits, w.ghist, w.state,
+                                            static_cast<int64_t>(os_state_words(count, ITEMS, passes)), w.counters);
+  if ((st = check_launch("k_os_hist")) != GS_OK) return st;
+  for (int p = 0; p < passes; ++p) {
+    const int nbits = std::min(8, total_bits - 8 * p);
+    k_os_scatter<ITEMS><<<nblocks, kRsThreads, 0, s>>>(ka, va, kb, vb, count, 8 * p, nbits, w.ghist + p * 256,
+                                                       w.state + static_cast<size_t>(p) * nblocks * 256,
+                                                       w.counters + p, w.err);
+    if ((st = check_launch("k_os_scatter")) != GS_OK) return st;
+    uint32_t* t = ka; ka = kb; kb = t;
+    t = va; va = vb; vb = t;
+  }
+  *passes_out = passes;
+  return GS_OK;
+}
+
 static int sort_passes(int bits) { return (bits + 7) / 8; }
 
 // ------------------------------------------------------------- bin kernels
@@ -287,13 +516,16 @@ static int sort_passes(int bits) { return (bits + 7) / 8; }
 // Depth keys, and each Gaussian's tile rectangle packed into 8 bytes
 // (x0 | x_end << 16, y0 | y_end << 16, ends exclusive; all zero when empty) so
 // that the later rank-order passes read one small word per Gaussian instead
-// of its record and radius.
+// of its record and radius.  Also clears `zero_words` words at `zero` (the
+// depth sort's digit counts, K and the look-back error flag).
 __global__ __launch_bounds__(256) void k_depth_keys(int n, const float* __restrict__ depth,
                                                     const float4* __restrict__ records,
                                                     const int* __restrict__ radius, int tiles_x, int tiles_y,
                                                     uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                                                    uint2* __restrict__ rect) {
+                                                    uint2* __restrict__ rect, uint32_t* __restrict__ zero,
+                                                    int zero_words) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  for (int z = i; z < zero_words; z += gridDim.x * blockDim.x) zero[z] = 0u;
   if (i >= n) return;
   keys[i] = __float_as_uint(depth[i]);
   vals[i] = static_cast<uint32_t>(i);
@@ -700,6 +932,9 @@ struct BinWs {
   uint32_t *ek0, *ek1, *ev1;
   uint32_t* hist;
   ScanWs scan;
+  OsWs os;                        // depth sort state
+  uint32_t* zero;                 // its digit counts and the error flag, cleared by k_depth_keys
+  unsigned long long* readback;   // [0] K, [1] the error flag
   // direct emission: chunk bounds, chunk x tile table, tile totals and starts
   uint32_t *bounds, *table, *total, *start;
 };
@@ -713,12 +948,18 @@ static BinWs carve_bin(void* ws, int64_t n, int64_t cap, int tiles_x, int tiles_
   b.cnt = c.take<uint32_t>(N); b.offs = c.take<uint32_t>(N);
   b.rect = c.take<uint2>(N); b.rect_rank = c.take<uint2>(N);
   b.ek0 = c.take<uint32_t>(C); b.ek1 = c.take<uint32_t>(C); b.ev1 = c.take<uint32_t>(C);
-  const size_t hist_words = 256 * static_cast<size_t>(std::max(ceil_div(std::max<int64_t>(n, 1), kRsThreads * kRsItemsN),
-                                                               ceil_div(std::max<int64_t>(cap, 1), kRsThreads * kRsItemsK)));
+  const size_t hist_words = 256 * static_cast<size_t>(ceil_div(std::max<int64_t>(cap, 1), kRsThreads * kRsItemsK));
   const int64_t maxn = std::max<int64_t>(std::max<int64_t>(n, cap), 1);
   b.hist = c.take<uint32_t>(hist_words);
   b.scan.sums = c.take<uint32_t>(scan_ws_words(std::max<int64_t>(static_cast<int64_t>(hist_words), maxn)));
-  b.scan.total = c.take<unsigned long long>(1);
+  // cleared by k_depth_keys: the onesweep digit counts, then K and the error flag
+  b.zero = c.take<uint32_t>(kOsMaxPasses * 256 + 4);
+  b.readback = reinterpret_cast<unsigned long long*>(b.zero + kOsMaxPasses * 256);
+  b.scan.total = b.readback;
+  b.os.ghist = b.zero;
+  b.os.err = reinterpret_cast<uint32_t*>(b.readback + 1);
+  b.os.state = c.take<uint32_t>(os_state_words(n, kOsItemsN, kOsMaxPasses));
+  b.os.counters = c.take<uint32_t>(kOsMaxPasses);
   b.bounds = b.table = b.total = b.start = nullptr;
   if (direct_ok(tiles_x, tiles_y)) {
     const size_t nt = static_cast<size_t>(tiles_x) * tiles_y;
@@ -750,17 +991,21 @@ gs_status run_bin_sort(int64_t n64, const gs_projected& proj, const DevCam& cam,
   if (n > 0) {
     const unsigned g = static_cast<unsigned>(ceil_div(n, 256));
     k_depth_keys<<<g, 256, 0, s>>>(n, proj.depth, reinterpret_cast<const float4*>(proj.records), proj.radius,
-                                   cam.tiles_x, cam.tiles_y, b.dk0, b.dv0, b.rect);
+                                   cam.tiles_x, cam.tiles_y, b.dk0, b.dv0, b.rect, b.zero, kOsMaxPasses * 256 + 4);
+    if ((st = check_launch("k_depth_keys")) != GS_OK) return st;
     int passes = 0;
-    if ((st = radix_sort_pairs<kRsItemsN>(b.dk0, b.dv0, b.dk1, b.dv1, n, 32, b.hist, b.scan, s, &passes)) != GS_OK)
+    if ((st = onesweep_sort_pairs<kOsItemsN>(b.dk0, b.dv0, b.dk1, b.dv1, n, 32, b.os, s, &passes)) != GS_OK)
       return st;
     const uint32_t* order = (passes % 2 == 0) ? b.dv0 : b.dv1;
     k_gather_counts<<<g, 256, 0, s>>>(n, order, b.rect, b.cnt, b.rect_rank);
     if ((st = device_exclusive_scan(b.cnt, b.offs, n, b.scan, s)) != GS_OK) return st;
-    unsigned long long total = 0;
-    if ((st = check_hip(hipMemcpyAsync(&total, b.scan.total, sizeof(total), hipMemcpyDeviceToHost, s),
+    unsigned long long rb[2] = {0ull, 0ull};
+    if ((st = check_hip(hipMemcpyAsync(rb, b.readback, sizeof(rb), hipMemcpyDeviceToHost, s),
                         "hipMemcpyAsync(K)")) != GS_OK) return st;
     if ((st = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize")) != GS_OK) return st;
+    if (static_cast<uint32_t>(rb[1]) != 0u)
+      return fail(GS_ERR_HIP, "gs_bin_sort: depth sort look-back did not complete (spin limit)");
+    const unsigned long long total = rb[0];
     K = static_cast<int64_t>(total);
     *k_out = K;
     if (K >= (int64_t(1) << 32)) return fail(GS_ERR_UNSUPPORTED, "gs_bin_sort: more than 2^32 entries");
