@@ -57,9 +57,10 @@ def log(*a):
 # kernels of each stage (as named in the rocprofv3 summaries under profiles/)
 STAGE_KERNELS = {
     "project": ("k_project<", "k_mlp_fwd<1>"),
-    "bin_sort": ("k_depth_keys", "k_rs_hist", "k_rs_scatter", "k_scan_", "k_gather_counts", "k_emit", "k_ranges"),
+    "bin_sort": ("k_depth_keys", "k_os_", "k_rs_hist", "k_rs_scatter", "k_scan_", "k_gather_counts", "k_chunk_",
+                 "k_tile_starts", "k_emit", "k_ranges"),
     "render_fwd": ("k_render_fwd_light", "k_render_fwd<false>"),
-    "render_bwd": ("k_render_bwd", "k_acc_to_g2d"),
+    "render_bwd": ("k_render_bwd", "k_acc_to_g2d", "k_det_", "k_zero4"),
     "project_bwd": ("k_project_bwd<", "k_mlp_bwd<1>", "k_mlp_reduce"),
 }
 
