@@ -120,6 +120,13 @@ class Distiller:
             dec.adam_latents(self.dlat[lo:hi], lr_z, self.epoch, lo, hi)
         self.losses = torch.cat([self.losses, row])
 
+    def train(self, epochs: int, lr_w: float = 1e-3, lr_z: float = 1e-2, final_factor: float = 0.01):
+        """`epochs` epochs with both learning rates decayed on a cosine from
+        their base value to `final_factor` times it."""
+        for e in range(epochs):
+            f = final_factor + (1.0 - final_factor) * 0.5 * (1.0 + np.cos(np.pi * e / max(epochs - 1, 1)))
+            self.run_epoch(lr_w * f, lr_z * f)
+
     def loss_history(self) -> np.ndarray:
         """Per-epoch mean squared colour error (weighted by batch size)."""
         L = self.losses.cpu().numpy().astype(np.float64)

@@ -220,6 +220,22 @@ def config_scene(cfg: int, n: int | None = None) -> Scene:
     raise ValueError(f"unknown workload {cfg}")
 
 
+def low_rank_colour(scene: Scene, rank: int, seed: int) -> Scene:
+    """The same scene with view-dependent colour of low rank: the SH
+    coefficients of degree >= 1 are a_i B for per-Gaussian factors a_i ~
+    N(0, I_rank) and one scene-wide basis B (rank x 3 ((D+1)^2 - 1)) with
+    N(0, 0.05^2 / rank) entries, so each coefficient keeps the std 0.05 of the
+    independent draw while the whole view dependence spans `rank` dimensions
+    (as correlated highlights do).  DC coefficients are kept."""
+    rng = np.random.default_rng(seed)
+    nb = (scene.sh_degree + 1) ** 2
+    basis = rng.normal(0.0, 0.05 / np.sqrt(rank), (rank, 3 * (nb - 1)))
+    a = rng.standard_normal((scene.n, rank))
+    sh = scene.sh.astype(np.float64).copy()
+    sh[1:] = (a @ basis).T.reshape(nb - 1, 3, scene.n)
+    return dataclasses.replace(scene, sh=_f32(sh))
+
+
 def config_camera(cfg: int, k: int = 0, bg=(0.0, 0.0, 0.0)) -> Camera:
     if cfg == 1:
         return front_camera(128, 128, 3.0, 60.0, bg)
