@@ -109,20 +109,39 @@ struct Split8 {
   bf16x8 hi, lo;
 };
 
-__device__ __forceinline__ void split_put(Split8& s, int e, float v) {
-  const __bf16 h = static_cast<__bf16>(v);
-  s.hi[e] = h;
-  s.lo[e] = static_cast<__bf16>(v - static_cast<float>(h));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+
+// Two values split at once: one packed conversion for both hi parts, one for
+// both lo parts (round to nearest even, as a single conversion would).
+struct Split2 {
+  bf16x2 hi, lo;
+};
+__device__ __forceinline__ Split2 split2(float a, float b) {
+  const floatx2 v = {a, b};
+  Split2 p;
+  p.hi = __builtin_convertvector(v, bf16x2);
+  p.lo = __builtin_convertvector(v - __builtin_convertvector(p.hi, floatx2), bf16x2);
+  return p;
+}
+
+// slots e, e + 1 (e even) of s
+__device__ __forceinline__ void split_put2(Split8& s, int e, float a, float b) {
+  const Split2 p = split2(a, b);
+  s.hi[e] = p.hi[0]; s.hi[e + 1] = p.hi[1];
+  s.lo[e] = p.lo[0]; s.lo[e + 1] = p.lo[1];
 }
 
 // Read a D-layout result (4 row-blocks) back as the split B operands of the
 // next layer, after bias + ReLU.
 __device__ __forceinline__ void relu_to_b(const floatx4 h[4], const float* bias, int g, Split8& B0, Split8& B1) {
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
+  for (int e = 0; e < 8; e += 2) {
     const int b0 = e >> 2, i = e & 3;
-    split_put(B0, e, fmaxf(h[b0][i] + bias[16 * b0 + 4 * g + i], 0.0f));
-    split_put(B1, e, fmaxf(h[2 + b0][i] + bias[16 * (2 + b0) + 4 * g + i], 0.0f));
+    split_put2(B0, e, fmaxf(h[b0][i] + bias[16 * b0 + 4 * g + i], 0.0f),
+               fmaxf(h[b0][i + 1] + bias[16 * b0 + 4 * g + i + 1], 0.0f));
+    split_put2(B1, e, fmaxf(h[2 + b0][i] + bias[16 * (2 + b0) + 4 * g + i], 0.0f),
+               fmaxf(h[2 + b0][i + 1] + bias[16 * (2 + b0) + 4 * g + i + 1], 0.0f));
   }
 }
 
@@ -139,8 +158,11 @@ __device__ __forceinline__ Split8 input_operand(int g, bool valid, const uint4& 
   } else {
     float Y[16];
     sh_basis(3, d[0], d[1], d[2], Y);
+    // static indices (a lane-dependent index into Y would become a select chain)
+    const bool upper = g == 3;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) split_put(X, e, valid ? Y[8 * (g - 2) + e] : 0.0f);
+    for (int e = 0; e < 8; e += 2)
+      split_put2(X, e, valid ? (upper ? Y[8 + e] : Y[e]) : 0.0f, valid ? (upper ? Y[9 + e] : Y[e + 1]) : 0.0f);
   }
   return X;
 }
@@ -353,10 +375,11 @@ struct MlpStage {
   __bf16 g3[2][16][kRow];
 };
 
-__device__ __forceinline__ void stage_put(__bf16 (*plane)[64][kRow], int u, int r, float v) {
-  const __bf16 h = static_cast<__bf16>(v);
-  plane[0][u][r] = h;
-  plane[1][u][r] = static_cast<__bf16>(v - static_cast<float>(h));
+// units u and u + 1 of sample r
+__device__ __forceinline__ void stage_put2(__bf16 (*plane)[64][kRow], int u, int r, float a, float b) {
+  const Split2 p = split2(a, b);
+  plane[0][u][r] = p.hi[0]; plane[0][u + 1][r] = p.hi[1];
+  plane[1][u][r] = p.lo[0]; plane[1][u + 1][r] = p.lo[1];
 }
 
 struct Split4 {
@@ -379,9 +402,9 @@ __device__ __forceinline__ floatx4 mfma16x3(const Split4& a, const Split4& b, co
 // D-layout gradients (4 row-blocks) as the split B operands of the next product.
 __device__ __forceinline__ void grad_to_b(const floatx4 h[4], Split8& B0, Split8& B1) {
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    split_put(B0, e, h[e >> 2][e & 3]);
-    split_put(B1, e, h[2 + (e >> 2)][e & 3]);
+  for (int e = 0; e < 8; e += 2) {
+    split_put2(B0, e, h[e >> 2][e & 3], h[e >> 2][(e & 3) + 1]);
+    split_put2(B1, e, h[2 + (e >> 2)][e & 3], h[2 + (e >> 2)][(e & 3) + 1]);
   }
 }
 
@@ -431,7 +454,8 @@ __device__ __forceinline__ void mlp_bwd_group(const MlpShared& sh, MlpStage& sg,
   }
   Split8 Bg3;
 #pragma unroll
-  for (int e = 0; e < 8; ++e) split_put(Bg3, e, (g == 0 && e < 4) ? g3[e & 3] : 0.0f);
+  for (int e = 0; e < 8; e += 2)
+    split_put2(Bg3, e, (g == 0 && e < 4) ? g3[e & 3] : 0.0f, (g == 0 && e < 4) ? g3[(e & 3) + 1] : 0.0f);
   floatx4 g2[4];
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
@@ -460,12 +484,18 @@ __device__ __forceinline__ void mlp_bwd_group(const MlpShared& sh, MlpStage& sg,
 #pragma unroll
   for (int b = 0; b < 4; ++b)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < 4; i += 2) {
       const int u = 16 * b + 4 * g + i;
-      stage_put(sg.h1, u, r, fmaxf(st.h1[b][i] + sh.bias[u], 0.0f));
-      stage_put(sg.h2, u, r, fmaxf(st.h2[b][i] + sh.bias[64 + u], 0.0f));
-      stage_put(sg.g1, u, r, g1[b][i]);
-      stage_put(sg.g2, u, r, g2[b][i]);
+      stage_put2(sg.h1, u, r, fmaxf(st.h1[b][i] + sh.bias[u], 0.0f), fmaxf(st.h1[b][i + 1] + sh.bias[u + 1], 0.0f));
+      stage_put2(sg.h2, u, r, fmaxf(st.h2[b][i] + sh.bias[64 + u], 0.0f),
+                 fmaxf(st.h2[b][i + 1] + sh.bias[64 + u + 1], 0.0f));
+      stage_put2(sg.g1, u, r, g1[b][i], g1[b][i + 1]);
+      stage_put2(sg.g2, u, r, g2[b][i], g2[b][i + 1]);
+    }
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
       G.db1[4 * b + i] += g1[b][i];
       G.db2[4 * b + i] += g2[b][i];
     }
@@ -579,9 +609,7 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(int S, int per, const uint16_t*
         // dL/dd = sum_j dL/dY_j grad Y_j(d); this lane holds j = 4g + i
         float w16[16];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) w16[j] = 0.f;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) w16[4 * g + i] = dxe[i];
+        for (int j = 0; j < 16; ++j) w16[j] = ((j >> 2) == g) ? dxe[j & 3] : 0.0f;
         float gd[3];
         sh_basis_vjp(3, d[0], d[1], d[2], w16, gd[0], gd[1], gd[2]);
 #pragma unroll
