@@ -34,19 +34,22 @@ __device__ __forceinline__ size_t ckpt_slot0(uint32_t start, int tile) {
   return static_cast<size_t>(start / kBatch) + static_cast<size_t>(tile);
 }
 
-// Records are staged in LDS with the conic pre-scaled by -log2(e)/2 (and
-// -log2(e) off-diagonal) so that the base-2 exponent is
-//   p2 = a dx^2 + b dx dy + c dy^2 = power * log2(e),
-// and alpha's Gaussian factor is a single v_exp_f32: p = (u, v, a, b),
-// q = (c, opacity, r, g).  Slots past the end of a batch hold a null record
-// (opacity 0), which every pixel skips.
-// p2 (base-2 power), 2^p2 and the unclamped o 2^p2 for one (pixel, entry) pair.
+// Records are staged in LDS with the conic (A, B, C) pre-scaled by
+// -log2(e)/2: a = -log2(e) A / 2, b = -log2(e) B / 2, c = -log2(e) C / 2, so
+// that with n = (a dx + b dy, b dx + c dy) the base-2 exponent is
+//   p2 = dx n.x + dy n.y = power * log2(e),
+// alpha's Gaussian factor is a single v_exp_f32, and n (= -log2(e)/2 times
+// the conic applied to d) is what the backward's covariance gradient needs:
+// p = (u, v, a, b), q = (c, opacity, r, g).  Slots past the end of a batch
+// hold a null record (opacity 0), which every pixel skips.
+// p2 (base-2 power), 2^p2, the unclamped o 2^p2 and n for one (pixel, entry) pair.
 __device__ __forceinline__ void eval_pair(const float4& p, const float4& q, float px, float py, float& dx,
-                                          float& dy, float& p2, float& eg, float& og) {
+                                          float& dy, float& p2, float& eg, float& og, float& nx, float& ny) {
   dx = p.x - px;
   dy = p.y - py;
-  const float dxx = dx * dx, dyy = dy * dy, dxy = dx * dy;
-  p2 = fmaf(p.z, dxx, fmaf(q.x, dyy, p.w * dxy));
+  nx = fmaf(p.z, dx, p.w * dy);
+  ny = fmaf(q.x, dy, p.w * dx);
+  p2 = fmaf(dx, nx, dy * ny);
   eg = __builtin_amdgcn_exp2f(p2);
   og = q.y * eg;
 }
@@ -126,7 +129,7 @@ __device__ __forceinline__ void stage_light(LightStage& ls, const float4* __rest
     const float4 r0 = rec[3 * gid];
     const float4 r1 = rec[3 * gid + 1];
     const float4 r2 = rec[3 * gid + 2];
-    ls.p[lane] = make_float4(r0.x, r0.y, -0.5f * kLog2e * r0.z, -kLog2e * r0.w);
+    ls.p[lane] = make_float4(r0.x, r0.y, -0.5f * kLog2e * r0.z, -0.5f * kLog2e * r0.w);
     ls.q[lane] = make_float4(-0.5f * kLog2e * r1.x, r1.y, r1.z, r1.w);
     ls.c[lane] = make_float2(r2.x, __uint_as_float(quad_mask(r0, r2, x0, y0)));
     ls.gid[lane] = gid;
@@ -157,7 +160,7 @@ __device__ __forceinline__ void stage_batch(Stage& st, const float4* __restrict_
     const float4 r0 = rec[3 * gid];
     const float4 r1 = rec[3 * gid + 1];
     const float4 r2 = rec[3 * gid + 2];
-    st.p[t] = make_float4(r0.x, r0.y, -0.5f * kLog2e * r0.z, -kLog2e * r0.w);
+    st.p[t] = make_float4(r0.x, r0.y, -0.5f * kLog2e * r0.z, -0.5f * kLog2e * r0.w);
     st.q[t] = make_float4(-0.5f * kLog2e * r1.x, r1.y, r1.z, r1.w);
     st.c[t] = make_float2(r2.x, __uint_as_float(quad_mask(r0, r2, x0, y0)));
     st.gid[t] = gid;
@@ -196,8 +199,8 @@ __device__ __forceinline__ void build_list(Stage& st, int cnt, bool all) {
 __device__ __forceinline__ bool fwd_pair(const float4& p, const float4& q, float cb, float px, float py, uint32_t m1,
                                          float& T, float& acc0, float& acc1, float& acc2, uint32_t& contrib,
                                          bool& done) {
-  float dx, dy, p2, eg, og;
-  eval_pair(p, q, px, py, dx, dy, p2, eg, og);
+  float dx, dy, p2, eg, og, nx, ny;
+  eval_pair(p, q, px, py, dx, dy, p2, eg, og, nx, ny);
   const float alpha = fminf(kAlphaMax, og);
   const bool ok = !done && (p2 <= 0.0f) && (alpha >= kAlphaMin);
   const float Tn = T * (1.0f - alpha);
@@ -479,9 +482,9 @@ __device__ __forceinline__ float wave_sum8(const float v[8], bool lo8) {
 // Gradient terms of one (pixel, entry) pair of the back-to-front walk, after
 // the alpha evaluation: recovers T before the entry, updates the light behind
 // (as G.S) and writes the nine per-pair terms (all zero when !ok).
-__device__ __forceinline__ void bwd_terms(const float4& p, const float4& q, float cb, bool ok, float dx, float dy,
-                                          float alpha, float eg, float og, float G0, float G1, float G2, float& T,
-                                          float& GS, float v[9]) {
+__device__ __forceinline__ void bwd_terms(const float4& q, float cb, bool ok, float nx, float ny, float alpha,
+                                          float eg, float og, float G0, float G1, float G2, float& T, float& GS,
+                                          float v[9]) {
   // hardware reciprocal (1 ulp): T is re-anchored every 256 entries, so its
   // rounding stays far below the tolerance of the recovered transmittance
   const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
@@ -495,23 +498,28 @@ __device__ __forceinline__ void bwd_terms(const float4& p, const float4& q, floa
   // dL/dpower (natural-log power) and dL/do = e^power dL/dalpha
   const float dpow = (ok && unclamped) ? alpha * dalpha : 0.0f;
   const float dop = (ok && unclamped) ? eg * dalpha : 0.0f;
-  // (nkx, nky) = log2(e) * (-K d) with K the conic and d = (dx, dy).  The
+  // n = (nx, ny) = -log2(e)/2 K d with K the conic and d = (dx, dy).  The
   // pair's conic gradient -1/2 dpow d d^T is carried to Sigma' = K^-1 right
   // here, -K (.) K = 1/2 dpow (K d)(K d)^T, before any summation: converting
-  // the summed conic gradient cancels badly for elongated footprints.
-  const float nkx = fmaf(p.z + p.z, dx, p.w * dy);
-  const float nky = fmaf(q.x + q.x, dy, p.w * dx);
-  const float dq = dpow * kLn2;              // undoes the log2(e) scale once
-  const float hx = (0.5f * kLn2) * dq * nkx; // ... and twice for the products
-  v[0] = dq * nkx;                           // dL/du
-  v[1] = dq * nky;                           // dL/dv
-  v[2] = hx * nkx;                           // dL/dSigma'_xx
-  v[3] = (hx + hx) * nky;                    // dL/dSigma'_xy (both entries)
-  v[4] = (0.5f * kLn2) * dq * nky * nky;     // dL/dSigma'_yy
+  // the summed conic gradient cancels badly for elongated footprints.  The
+  // constant factors (powers of ln 2 and 2) are applied once per Gaussian
+  // after the sums (kGradScale).
+  const float ux = dpow * nx, uy = dpow * ny;
+  v[0] = ux;                                 // dL/du            / (2 ln2)
+  v[1] = uy;                                 // dL/dv            / (2 ln2)
+  v[2] = ux * nx;                            // dL/dSigma'_xx    / (2 ln2^2)
+  v[3] = ux * ny;                            // dL/dSigma'_xy    / (4 ln2^2), both entries
+  v[4] = uy * ny;                            // dL/dSigma'_yy    / (2 ln2^2)
   v[5] = dop;                                // dL/dopacity
   v[6] = G0 * w;                             // dL/dr
   v[7] = G1 * w;                             // dL/dg
   v[8] = G2 * w;                             // dL/db
+}
+
+// Factors that turn the summed terms of bwd_terms into the gradients.
+__device__ __forceinline__ float grad_scale(int c) {
+  constexpr float l1 = 2.0f * kLn2, l2 = 2.0f * kLn2 * kLn2;
+  return c < 2 ? l1 : (c == 3 ? l2 + l2 : (c < 5 ? l2 : 1.0f));
 }
 
 // Per-Gaussian gradient accumulator row: nine sums padded to one 64-byte line.
@@ -526,7 +534,7 @@ __global__ __launch_bounds__(256) void k_acc_to_g2d(int n, const float4* __restr
   const float4 c = acc[4 * static_cast<int64_t>(i) + 2];
   const float v[9] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x};
 #pragma unroll
-  for (int k = 0; k < GS_G2D; ++k) g2d[static_cast<int64_t>(k) * n + i] = v[k];
+  for (int k = 0; k < GS_G2D; ++k) g2d[static_cast<int64_t>(k) * n + i] = v[k] * grad_scale(k);
 }
 
 // ------------------------------------------------- deterministic reduction
@@ -591,7 +599,7 @@ __global__ __launch_bounds__(256) void k_det_reduce(int n, const uint32_t* __res
     for (int c = 0; c < kDetRow; ++c) s[c] += row[c];
   }
 #pragma unroll
-  for (int c = 0; c < GS_G2D; ++c) g2d[static_cast<int64_t>(c) * n + i] = s[c];
+  for (int c = 0; c < GS_G2D; ++c) g2d[static_cast<int64_t>(c) * n + i] = s[c] * grad_scale(c);
 }
 
 // Per (pixel, entry) derivative, walked back to front.  Starting from the light
@@ -715,13 +723,13 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
       const float4 p = st.p[j];
       const float4 q = st.q[j];
       const float cb = st.c[j].x;
-      float dx, dy, p2, eg, og;
-      eval_pair(p, q, px, py, dx, dy, p2, eg, og);
+      float dx, dy, p2, eg, og, nx, ny;
+      eval_pair(p, q, px, py, dx, dy, p2, eg, og, nx, ny);
       const float alpha = fminf(kAlphaMax, og);
       const bool ok = (m < ncon) && (p2 <= 0.0f) && (alpha >= kAlphaMin);
       if (__ballot(ok) == 0) continue;
       float v[9];
-      bwd_terms(p, q, cb, ok, dx, dy, alpha, eg, og, G0, G1, G2, T, GS, v);
+      bwd_terms(q, cb, ok, nx, ny, alpha, eg, og, G0, G1, G2, T, GS, v);
       const float red8 = wave_sum8(v, lo8);
       const float red9 = wave_sum_to_lane63(v[8]);  // dL/db
       if constexpr (DET) {
@@ -812,12 +820,12 @@ __global__ __launch_bounds__(256) void k_render_bwd_light(const uint2* __restric
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       if (!((mask >> k) & 1u)) continue;
-      float dx, dy, p2, eg, og;
-      eval_pair(p, q, px[k], py[k], dx, dy, p2, eg, og);
+      float dx, dy, p2, eg, og, nx, ny;
+      eval_pair(p, q, px[k], py[k], dx, dy, p2, eg, og, nx, ny);
       const float alpha = fminf(kAlphaMax, og);
       const bool ok = (m < ncon[k]) && (p2 <= 0.0f) && (alpha >= kAlphaMin);
       float v[9];
-      bwd_terms(p, q, cb, ok, dx, dy, alpha, eg, og, G0[k], G1[k], G2[k], T[k], GS[k], v);
+      bwd_terms(q, cb, ok, nx, ny, alpha, eg, og, G0[k], G1[k], G2[k], T[k], GS[k], v);
 #pragma unroll
       for (int t = 0; t < 9; ++t) vs[t] += v[t];
       any = any || ok;
