@@ -62,17 +62,59 @@ __device__ __forceinline__ void tile_pixel(int tid, int& lx, int& ly) {
   ly = ((w >> 1) << 3) + (l >> 3);
 }
 
-// Quadrants of the tile whose pixel centres meet the record's alpha-support box
-// (bit w = quadrant of wave w).  Outside the box alpha < 1/255, so a wave whose
-// bit is clear would skip the entry at every pixel anyway.
-__device__ __forceinline__ uint32_t quad_mask(const float4& r0, const float4& r2, float x0, float y0) {
+// Smallest q(d) = A dx^2 + 2 B dx dy + C dy^2 over the rectangle
+// dx in [xa, xb], dy in [ya, yb] (A, C > 0, A C > B^2): zero if it holds
+// the origin, else the least of the four edge minima (on an edge q is a
+// parabola in the free coordinate, minimised at -B X / C or -B Y / A and
+// clamped to the edge).
+__device__ __forceinline__ float conic_min_rect(float A, float B, float C, float iA, float iC, float xa, float xb,
+                                                float ya, float yb) {
+  if (xa <= 0.0f && xb >= 0.0f && ya <= 0.0f && yb >= 0.0f) return 0.0f;
+  float best = 3.0e38f;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const float X = k ? xb : xa;
+    const float y = fminf(fmaxf(-B * X * iC, ya), yb);
+    best = fminf(best, fmaf(fmaf(A, X, 2.0f * B * y), X, C * y * y));
+    const float Y = k ? yb : ya;
+    const float x = fminf(fmaxf(-B * Y * iA, xa), xb);
+    best = fminf(best, fmaf(fmaf(C, Y, 2.0f * B * x), Y, A * x * x));
+  }
+  return best;
+}
+
+// Quadrants of the tile whose pixel centres can reach alpha >= 1/255 (bit w =
+// quadrant of wave w): first the record's alpha-support box, then the exact
+// support ellipse q(d) <= rho^2 = 2 ln(255 o) against each remaining
+// quadrant's rectangle of pixel centres.  A wave whose bit is clear would skip
+// the entry at every pixel anyway.  The ellipse test takes twice the box's
+// slack (rho^2 x 1.04 + 4e-4, the rectangle widened by the box's 1e-3 px +
+// 1e-6 |u|), covering the FP32 error of both its own evaluation and the
+// per-pixel one for footprints with condition number up to 1e5 (larger ones
+// have an unbounded box and keep their box mask).
+__device__ __forceinline__ uint32_t quad_mask(const float4& r0, const float4& r1, const float4& r2, float x0,
+                                              float y0) {
   const float u = r0.x, v = r0.y, ex = r2.z, ey = r2.w;
   if (!(ex >= 0.0f)) return 0u;
   const bool xl = (u - ex <= x0 + 7.5f) && (u + ex >= x0 + 0.5f);
   const bool xr = (u - ex <= x0 + 15.5f) && (u + ex >= x0 + 8.5f);
   const bool yt = (v - ey <= y0 + 7.5f) && (v + ey >= y0 + 0.5f);
   const bool yb = (v - ey <= y0 + 15.5f) && (v + ey >= y0 + 8.5f);
-  return (xl && yt ? 1u : 0u) | (xr && yt ? 2u : 0u) | (xl && yb ? 4u : 0u) | (xr && yb ? 8u : 0u);
+  const uint32_t box = (xl && yt ? 1u : 0u) | (xr && yt ? 2u : 0u) | (xl && yb ? 4u : 0u) | (xr && yb ? 8u : 0u);
+  if (box == 0u || !(ex < 1.0e30f)) return box;
+  const float A = r0.z, B = r0.w, C = r1.x;
+  const float iA = 1.0f / A, iC = 1.0f / C;
+  const float rho2 = (2.0f * 1.04f) * logf(255.0f * r1.y) + 4e-4f;
+  const float dl = 1e-3f + 1e-6f * fmaxf(fabsf(u), fabsf(v));
+  uint32_t m = 0u;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (!((box >> k) & 1u)) continue;
+    const float xa = x0 + ((k & 1) ? 8.5f : 0.5f) - dl - u;
+    const float ya = y0 + ((k & 2) ? 8.5f : 0.5f) - dl - v;
+    if (conic_min_rect(A, B, C, iA, iC, xa, xa + 7.0f + 2.0f * dl, ya, ya + 7.0f + 2.0f * dl) <= rho2) m |= 1u << k;
+  }
+  return m;
 }
 
 constexpr int kNull = kBatch;           // LDS slot of a null record (opacity 0)
@@ -131,7 +173,7 @@ __device__ __forceinline__ void stage_light(LightStage& ls, const float4* __rest
     const float4 r2 = rec[3 * gid + 2];
     ls.p[lane] = make_float4(r0.x, r0.y, -0.5f * kLog2e * r0.z, -0.5f * kLog2e * r0.w);
     ls.q[lane] = make_float4(-0.5f * kLog2e * r1.x, r1.y, r1.z, r1.w);
-    ls.c[lane] = make_float2(r2.x, __uint_as_float(quad_mask(r0, r2, x0, y0)));
+    ls.c[lane] = make_float2(r2.x, __uint_as_float(quad_mask(r0, r1, r2, x0, y0)));
     ls.gid[lane] = gid;
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -162,7 +204,7 @@ __device__ __forceinline__ void stage_batch(Stage& st, const float4* __restrict_
     const float4 r2 = rec[3 * gid + 2];
     st.p[t] = make_float4(r0.x, r0.y, -0.5f * kLog2e * r0.z, -0.5f * kLog2e * r0.w);
     st.q[t] = make_float4(-0.5f * kLog2e * r1.x, r1.y, r1.z, r1.w);
-    st.c[t] = make_float2(r2.x, __uint_as_float(quad_mask(r0, r2, x0, y0)));
+    st.c[t] = make_float2(r2.x, __uint_as_float(quad_mask(r0, r1, r2, x0, y0)));
     st.gid[t] = gid;
   } else {
     st.p[t] = make_float4(0.f, 0.f, 0.f, 0.f);
