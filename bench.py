@@ -228,8 +228,9 @@ def main():
         for i in range(args.warmup):
             step_fn(i)
         torch.cuda.synchronize()
-        timer.reset()
-        timer.enabled = True
+        # the step time is taken without the per-stage events (their host calls
+        # fall where the GPU waits for the host after the bin/sort readback);
+        # the same steps then run again with them for the stage breakdown
         log(f"[bench] {label}: timing {args.steps} steps")
         t0 = torch.cuda.Event(enable_timing=True)
         t1 = torch.cuda.Event(enable_timing=True)
@@ -241,6 +242,11 @@ def main():
         t1.record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - wall0
+        timer.reset()
+        timer.enabled = True
+        for i in range(args.steps):
+            step_fn(args.warmup + i)
+        torch.cuda.synchronize()
         timer.enabled = False
         ms = t0.elapsed_time(t1) / args.steps
         st_ms = {k: float(np.mean(v)) for k, v in timer.ms().items()}

@@ -280,6 +280,11 @@ static gs_status radix_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, uint
   return GS_OK;
 }
 
+// Tile count of a packed rectangle (x0 | x_end << 16, y0 | y_end << 16).
+__device__ __forceinline__ uint32_t rect_count(uint2 rc) {
+  return ((rc.x >> 16) - (rc.x & 0xFFFFu)) * ((rc.y >> 16) - (rc.y & 0xFFFFu));
+}
+
 // ------------------------------------------------------------ onesweep sort
 // Stable LSD radix sort of (key, value) pairs in passes of up to 8 bits, one
 // sweep per pass:
@@ -356,9 +361,31 @@ __global__ __launch_bounds__(kRsThreads) void k_os_scatter(const uint32_t* __res
                                                            int shift, int nbits,
                                                            const uint32_t* __restrict__ ghist_pass,
                                                            uint32_t* __restrict__ state_pass,
-                                                           uint32_t* __restrict__ counter, uint32_t* __restrict__ err) {
+                                                           uint32_t* __restrict__ counter, uint32_t* __restrict__ err,
+                                                           const uint2* __restrict__ rect,
+                                                           uint2* __restrict__ rect_out,
+                                                           uint32_t* __restrict__ cnt_out) {
   constexpr int CHUNK = kRsThreads * ITEMS;
   constexpr int PER_WAVE = CHUNK / 4;
+  // rect != NULL (last pass): also gather each value's rectangle and tile
+  // count into the output order
+  auto emit = [&](int64_t g, uint32_t key, uint32_t val) {
+    keys_out[g] = key;
+    vals_out[g] = val;
+    if (rect) {
+      const uint2 rc = rect[val];
+      rect_out[g] = rc;
+      cnt_out[g] = rect_count(rc);
+    }
+  };
+  // every key has the same digit: the pass keeps the order (a copy)
+  if (__syncthreads_or(static_cast<uint32_t>(threadIdx.x) <= ((1u << nbits) - 1u) &&
+                       static_cast<int64_t>(ghist_pass[threadIdx.x]) == count)) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * CHUNK + threadIdx.x;
+         i < min(count, static_cast<int64_t>(blockIdx.x + 1) * CHUNK); i += kRsThreads)
+      emit(i, keys_in[i], vals_in[i]);
+    return;
+  }
   __shared__ uint32_t sk[CHUNK];
   __shared__ uint32_t sv[CHUNK];
   __shared__ uint32_t wrun[4][256];   // per-wave running digit counts
@@ -463,8 +490,7 @@ __global__ __launch_bounds__(kRsThreads) void k_os_scatter(const uint32_t* __res
     const uint32_t key = sk[p];
     const uint32_t d = (key >> shift) & mask;
     const uint32_t g = gbase[d] + (static_cast<uint32_t>(p) - dstart[d]);
-    keys_out[g] = key;
-    vals_out[g] = sv[p];
+    emit(g, key, sv[p]);
   }
 }
 
@@ -485,7 +511,9 @@ static size_t os_state_words(int64_t count, int items, int passes) {
 // w.ghist must be zero on entry (k_depth_keys clears both sorts' counts).
 template <int ITEMS>
 static gs_status onesweep_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int64_t count,
-                                     int total_bits, OsWs w, hipStream_t s, int* passes_out) {
+                                     int total_bits, OsWs w, hipStream_t s, int* passes_out,
+                                     const uint2* rect = nullptr, uint2* rect_out = nullptr,
+                                     uint32_t* cnt_out = nullptr) {
   constexpr int CHUNK = kRsThreads * ITEMS;
   const int passes = (total_bits + 7) / 8;
   *passes_out = 0;
@@ -498,9 +526,11 @@ static gs_status onesweep_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, u
   if ((st = check_launch("k_os_hist")) != GS_OK) return st;
   for (int p = 0; p < passes; ++p) {
     const int nbits = std::min(8, total_bits - 8 * p);
+    const bool last = p + 1 == passes;
     k_os_scatter<ITEMS><<<nblocks, kRsThreads, 0, s>>>(ka, va, kb, vb, count, 8 * p, nbits, w.ghist + p * 256,
                                                        w.state + static_cast<size_t>(p) * nblocks * 256,
-                                                       w.counters + p, w.err);
+                                                       w.counters + p, w.err, last ? rect : nullptr,
+                                                       last ? rect_out : nullptr, last ? cnt_out : nullptr);
     if ((st = check_launch("k_os_scatter")) != GS_OK) return st;
     uint32_t* t = ka; ka = kb; kb = t;
     t = va; va = vb; vb = t;
@@ -535,22 +565,6 @@ __global__ __launch_bounds__(256) void k_depth_keys(int n, const float* __restri
   rect[i] = c > 0 ? make_uint2(static_cast<uint32_t>(x0) | (static_cast<uint32_t>(x1 + 1) << 16),
                                static_cast<uint32_t>(y0) | (static_cast<uint32_t>(y1 + 1) << 16))
                   : make_uint2(0u, 0u);
-}
-
-__device__ __forceinline__ uint32_t rect_count(uint2 rc) {
-  return ((rc.x >> 16) - (rc.x & 0xFFFFu)) * ((rc.y >> 16) - (rc.y & 0xFFFFu));
-}
-
-// Rank order: each Gaussian's rectangle and tile count (one gather per
-// Gaussian).
-__global__ __launch_bounds__(256) void k_gather_counts(int n, const uint32_t* __restrict__ order,
-                                                       const uint2* __restrict__ rect, uint32_t* __restrict__ out,
-                                                       uint2* __restrict__ rect_rank) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  const uint2 rc = rect[order[r]];
-  out[r] = rect_count(rc);
-  rect_rank[r] = rc;
 }
 
 // Emit: a wave takes 64 consecutive depth ranks and writes all of their
@@ -670,13 +684,20 @@ static int64_t direct_max_chunks(int64_t cap) {
   return std::max<int64_t>(1, std::min<int64_t>(kDirectChunks, ceil_div(std::max<int64_t>(cap, 1), kDirectMinEntries)));
 }
 
-// R_c = first rank whose entry offset is >= c E (c < C); R_C = n.
-__global__ __launch_bounds__(256) void k_chunk_bounds(int n, const uint32_t* __restrict__ offs, uint32_t E, int C,
+// Chunk size E = max(4096, ceil(K / 512)) and count C = min(ceil(K / E), cmax)
+// from the entry total K on the device; R_c = first rank whose entry offset
+// is >= c E for c < C, R_c = n for C <= c <= cmax (empty chunks).
+__global__ __launch_bounds__(256) void k_chunk_bounds(int n, const uint32_t* __restrict__ offs,
+                                                      const unsigned long long* __restrict__ ktotal, int cmax,
                                                       uint32_t* __restrict__ bounds) {
   const int c = blockIdx.x * 256 + threadIdx.x;
-  if (c > C) return;
-  if (c == C) { bounds[c] = static_cast<uint32_t>(n); return; }
-  const uint32_t key = static_cast<uint32_t>(c) * E;
+  if (c > cmax) return;
+  const unsigned long long K = *ktotal;
+  const unsigned long long E = max(static_cast<unsigned long long>(kDirectMinEntries),
+                                   (K + kDirectChunks - 1) / kDirectChunks);
+  const unsigned long long C = min((K + E - 1) / E, static_cast<unsigned long long>(cmax));
+  if (static_cast<unsigned long long>(c) >= C) { bounds[c] = static_cast<uint32_t>(n); return; }
+  const unsigned long long key = static_cast<unsigned long long>(c) * E;
   uint32_t lo = 0, hi = static_cast<uint32_t>(n);
   while (lo < hi) {
     const uint32_t mid = lo + ((hi - lo) >> 1);
@@ -994,40 +1015,44 @@ gs_status run_bin_sort(int64_t n64, const gs_projected& proj, const DevCam& cam,
                                    cam.tiles_x, cam.tiles_y, b.dk0, b.dv0, b.rect, b.zero, kOsMaxPasses * 256 + 4);
     if ((st = check_launch("k_depth_keys")) != GS_OK) return st;
     int passes = 0;
-    if ((st = onesweep_sort_pairs<kOsItemsN>(b.dk0, b.dv0, b.dk1, b.dv1, n, 32, b.os, s, &passes)) != GS_OK)
+    // the last pass also gathers each rank's rectangle and tile count
+    if ((st = onesweep_sort_pairs<kOsItemsN>(b.dk0, b.dv0, b.dk1, b.dv1, n, 32, b.os, s, &passes, b.rect,
+                                             b.rect_rank, b.cnt)) != GS_OK)
       return st;
     const uint32_t* order = (passes % 2 == 0) ? b.dv0 : b.dv1;
-    k_gather_counts<<<g, 256, 0, s>>>(n, order, b.rect, b.cnt, b.rect_rank);
     if ((st = device_exclusive_scan(b.cnt, b.offs, n, b.scan, s)) != GS_OK) return st;
     unsigned long long rb[2] = {0ull, 0ull};
+    if (b.table) {
+      // direct emission, sized on the device from the scanned total: no host
+      // wait between the depth sort and the placement; K (and the look-back
+      // flag) are read once at the end
+      const int tx = cam.tiles_x, ty = cam.tiles_y;
+      const int cmax = static_cast<int>(direct_max_chunks(capacity));
+      k_chunk_bounds<<<static_cast<unsigned>(ceil_div(cmax + 1, 256)), 256, 0, s>>>(n, b.offs, b.readback, cmax,
+                                                                                   b.bounds);
+      if ((st = check_launch("k_chunk_bounds")) != GS_OK) return st;
+      k_chunk_count<<<cmax, kDirectThreads, sizeof(int) * (tx + 1) * (ty + 1), s>>>(b.bounds, b.rect_rank, tx, ty,
+                                                                                   b.table);
+      if ((st = check_launch("k_chunk_count")) != GS_OK) return st;
+      k_chunk_colscan<<<static_cast<unsigned>(ceil_div(ntiles, 64)), 1024, 0, s>>>(cmax, ntiles, b.table, b.total);
+      if ((st = check_launch("k_chunk_colscan")) != GS_OK) return st;
+      k_tile_starts<<<1, 1024, 0, s>>>(ntiles, b.total, b.start, reinterpret_cast<uint2*>(ranges));
+      if ((st = check_launch("k_tile_starts")) != GS_OK) return st;
+      k_emit_direct<<<cmax, kDirectThreads, emit_dyn_lds(tx, ty), s>>>(
+          b.bounds, order, b.rect_rank, b.table, b.start, tx, ty, point_list,
+          static_cast<uint32_t>(std::min<int64_t>(capacity, UINT32_MAX)));
+      if ((st = check_launch("k_emit_direct")) != GS_OK) return st;
+    }
     if ((st = check_hip(hipMemcpyAsync(rb, b.readback, sizeof(rb), hipMemcpyDeviceToHost, s),
                         "hipMemcpyAsync(K)")) != GS_OK) return st;
     if ((st = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize")) != GS_OK) return st;
     if (static_cast<uint32_t>(rb[1]) != 0u)
       return fail(GS_ERR_HIP, "gs_bin_sort: depth sort look-back did not complete (spin limit)");
-    const unsigned long long total = rb[0];
-    K = static_cast<int64_t>(total);
+    K = static_cast<int64_t>(rb[0]);
     *k_out = K;
     if (K >= (int64_t(1) << 32)) return fail(GS_ERR_UNSUPPORTED, "gs_bin_sort: more than 2^32 entries");
     if (K > capacity) return fail(GS_ERR_CAPACITY, "gs_bin_sort: capacity too small");
-    if (K > 0 && b.table) {
-      const uint32_t E = static_cast<uint32_t>(std::max<int64_t>(kDirectMinEntries, ceil_div(K, kDirectChunks)));
-      const int C = static_cast<int>(ceil_div(K, E));
-      const int tx = cam.tiles_x, ty = cam.tiles_y;
-      k_chunk_bounds<<<static_cast<unsigned>(ceil_div(C + 1, 256)), 256, 0, s>>>(n, b.offs, E, C, b.bounds);
-      if ((st = check_launch("k_chunk_bounds")) != GS_OK) return st;
-      k_chunk_count<<<C, kDirectThreads, sizeof(int) * (tx + 1) * (ty + 1), s>>>(b.bounds, b.rect_rank, tx, ty,
-                                                                            b.table);
-      if ((st = check_launch("k_chunk_count")) != GS_OK) return st;
-      k_chunk_colscan<<<static_cast<unsigned>(ceil_div(ntiles, 64)), 1024, 0, s>>>(C, ntiles, b.table, b.total);
-      if ((st = check_launch("k_chunk_colscan")) != GS_OK) return st;
-      k_tile_starts<<<1, 1024, 0, s>>>(ntiles, b.total, b.start, reinterpret_cast<uint2*>(ranges));
-      if ((st = check_launch("k_tile_starts")) != GS_OK) return st;
-      const size_t dyn = emit_dyn_lds(tx, ty);
-      k_emit_direct<<<C, kDirectThreads, dyn, s>>>(b.bounds, order, b.rect_rank, b.table, b.start, tx, ty, point_list,
-                                        static_cast<uint32_t>(std::min<int64_t>(capacity, UINT32_MAX)));
-      return check_launch("k_emit_direct");
-    }
+    if (b.table) return GS_OK;
     if (K > 0) {
       const int tbits = bits_for(ntiles);
       const int tp = sort_passes(tbits);
