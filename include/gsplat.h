@@ -157,6 +157,23 @@ gs_status gs_bin_sort(int64_t n, const gs_projected* proj, const gs_camera* cam,
                       uint32_t* point_list, int64_t capacity, uint32_t* ranges, int64_t* k_out,
                       gs_stream stream);
 
+/* gs_bin_sort without the wait: the same lists, with K written to device
+ * memory k_dev[0] and the depth sort's look-back error flag to k_dev[1]
+ * (uint64 each, both in stream order), so a caller can queue the rest of the
+ * frame at once and check them later.  The lists are valid only if
+ * k_dev[0] <= capacity and k_dev[1] == 0 (then they equal gs_bin_sort's);
+ * otherwise they are undefined, no out-of-bounds access happens, and the
+ * caller grows the buffers and redoes the frame.  Until it knows K the caller
+ * passes `capacity` as k to gs_render_ckpt_floats, gs_render_fwd,
+ * gs_render_bwd_workspace and gs_render_bwd (an upper bound serves every
+ * layout and launch there).  Only for frames whose per-chunk tables fit in
+ * LDS (tiles_x + 1)(tiles_y + 1) * 4 <= 64 KiB and the emission's tables
+ * too; larger frames return GS_ERR_UNSUPPORTED before any device work.
+ * Other errors as gs_bin_sort. */
+gs_status gs_bin_sort_async(int64_t n, const gs_projected* proj, const gs_camera* cam, void* ws, size_t ws_bytes,
+                            uint32_t* point_list, int64_t capacity, uint32_t* ranges, uint64_t* k_dev,
+                            gs_stream stream);
+
 /* Work split of the compositing kernels (Sec. IV: workload imbalance between
  * dense and sparse tiles, adaptive merging of thread blocks).  PLAIN: one
  * workgroup per tile, tiles mapped so that neighbours share an XCD.

@@ -136,8 +136,29 @@ gs_status gs_bin_sort(int64_t n, const gs_projected* proj, const gs_camera* cam,
   const DevCam d = make_devcam(*cam);
   if (ws_bytes < binsort_workspace(n, capacity, d.tiles_x, d.tiles_y))
     return fail(GS_ERR_INVALID_ARG, "gs_bin_sort: workspace too small");
-  return run_bin_sort(n, *proj, d, ws, ws_bytes, point_list, capacity, ranges, k_out,
+  return run_bin_sort(n, *proj, d, ws, ws_bytes, point_list, capacity, ranges, k_out, nullptr,
                       static_cast<hipStream_t>(stream));
+}
+
+gs_status gs_bin_sort_async(int64_t n, const gs_projected* proj, const gs_camera* cam, void* ws, size_t ws_bytes,
+                            uint32_t* point_list, int64_t capacity, uint32_t* ranges, uint64_t* k_dev,
+                            gs_stream stream) {
+  set_error("");
+  gs_status st;
+  if (n < 0 || n > (int64_t(1) << 30)) return fail(GS_ERR_INVALID_ARG, "gs_bin_sort_async: bad n");
+  if ((st = validate_camera(cam)) != GS_OK) return st;
+  if ((st = validate_projected(proj, n, "gs_bin_sort_async")) != GS_OK) return st;
+  if (!k_dev || !ranges || capacity < 0 || (capacity > 0 && !point_list) || (!ws && ws_bytes > 0))
+    return fail(GS_ERR_INVALID_ARG, "gs_bin_sort_async: NULL output or negative capacity");
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+    return fail(GS_ERR_INVALID_ARG, "gs_bin_sort_async: ws not 256-aligned");
+  const DevCam d = make_devcam(*cam);
+  if (!binsort_direct(d.tiles_x, d.tiles_y))
+    return fail(GS_ERR_UNSUPPORTED, "gs_bin_sort_async: frame too large for the direct emission; use gs_bin_sort");
+  if (ws_bytes < binsort_workspace(n, capacity, d.tiles_x, d.tiles_y))
+    return fail(GS_ERR_INVALID_ARG, "gs_bin_sort_async: workspace too small");
+  return run_bin_sort(n, *proj, d, ws, ws_bytes, point_list, capacity, ranges, nullptr,
+                      reinterpret_cast<unsigned long long*>(k_dev), static_cast<hipStream_t>(stream));
 }
 
 gs_status gs_render_fwd(int64_t n, const gs_projected* proj, const uint32_t* point_list, const uint32_t* ranges,

@@ -687,12 +687,16 @@ static int64_t direct_max_chunks(int64_t cap) {
 // Chunk size E = max(4096, ceil(K / 512)) and count C = min(ceil(K / E), cmax)
 // from the entry total K on the device; R_c = first rank whose entry offset
 // is >= c E for c < C, R_c = n for C <= c <= cmax (empty chunks).
+// With k_dev != NULL (no host wait) thread 0 also copies K and the depth
+// sort's look-back flag to k_dev[0], k_dev[1].
 __global__ __launch_bounds__(256) void k_chunk_bounds(int n, const uint32_t* __restrict__ offs,
                                                       const unsigned long long* __restrict__ ktotal, int cmax,
-                                                      uint32_t* __restrict__ bounds) {
+                                                      uint32_t* __restrict__ bounds,
+                                                      unsigned long long* __restrict__ k_dev) {
   const int c = blockIdx.x * 256 + threadIdx.x;
   if (c > cmax) return;
   const unsigned long long K = *ktotal;
+  if (k_dev && c == 0) { k_dev[0] = K; k_dev[1] = ktotal[1]; }
   const unsigned long long E = max(static_cast<unsigned long long>(kDirectMinEntries),
                                    (K + kDirectChunks - 1) / kDirectChunks);
   const unsigned long long C = min((K + E - 1) / E, static_cast<unsigned long long>(cmax));
@@ -784,27 +788,36 @@ __global__ __launch_bounds__(1024) void k_chunk_colscan(int C, int ntiles, uint3
 }
 
 // start[t] = exclusive prefix of total over tiles; ranges[t] = (start, start + total).
+// If the entries do not fit in `capacity`, every range is written empty
+// instead, so that work queued on these lists before the caller learns of
+// the overflow (the no-wait call) reads nothing past the buffers.
 __global__ __launch_bounds__(1024) void k_tile_starts(int ntiles, const uint32_t* __restrict__ total,
-                                                      uint32_t* __restrict__ start, uint2* __restrict__ ranges) {
-  __shared__ uint32_t s_w[16];
+                                                      uint32_t* __restrict__ start, uint2* __restrict__ ranges,
+                                                      unsigned long long capacity) {
+  __shared__ unsigned long long s_w[16];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int per = (ntiles + 1023) / 1024;
   const int t0 = min(ntiles, tid * per), t1 = min(ntiles, t0 + per);
-  uint32_t sum = 0;
+  unsigned long long sum = 0;
   for (int t = t0; t < t1; ++t) sum += total[t];
-  uint32_t incl = sum;
+  unsigned long long incl = sum;
   for (int d = 1; d < 64; d <<= 1) {
-    const uint32_t v = __shfl_up(incl, d, 64);
+    const unsigned long long v = __shfl_up(incl, d, 64);
     if (lane >= d) incl += v;
   }
   if (lane == 63) s_w[wave] = incl;
   __syncthreads();
-  uint32_t run = incl - sum;
-  for (int w = 0; w < wave; ++w) run += s_w[w];
+  unsigned long long run = incl - sum, all = 0;
+  for (int w = 0; w < 16; ++w) {
+    all += s_w[w];
+    run += (w < wave) ? s_w[w] : 0ull;
+  }
+  // positions are 32-bit: a total beyond that does not fit either
+  const bool fits = all <= min(capacity, 0xFFFFFFFFull);
   for (int t = t0; t < t1; ++t) {
     const uint32_t v = total[t];
-    start[t] = run;
-    ranges[t] = make_uint2(run, run + v);
+    start[t] = static_cast<uint32_t>(run);
+    ranges[t] = fits ? make_uint2(static_cast<uint32_t>(run), static_cast<uint32_t>(run + v)) : make_uint2(0u, 0u);
     run += v;
   }
 }
@@ -1000,8 +1013,15 @@ size_t binsort_workspace(int64_t n, int64_t capacity, int tiles_x, int tiles_y) 
   return used;
 }
 
+bool binsort_direct(int tiles_x, int tiles_y) { return direct_ok(tiles_x, tiles_y); }
+
+__global__ void k_put_zero_k(unsigned long long* __restrict__ k_dev) {
+  if (threadIdx.x < 2) k_dev[threadIdx.x] = 0ull;
+}
+
 gs_status run_bin_sort(int64_t n64, const gs_projected& proj, const DevCam& cam, void* ws, size_t ws_bytes,
-                       uint32_t* point_list, int64_t capacity, uint32_t* ranges, int64_t* k_out, hipStream_t s) {
+                       uint32_t* point_list, int64_t capacity, uint32_t* ranges, int64_t* k_out,
+                       unsigned long long* k_dev, hipStream_t s) {
   const int n = static_cast<int>(n64);
   const int ntiles = cam.tiles_x * cam.tiles_y;
   size_t need = 0;
@@ -1029,19 +1049,21 @@ gs_status run_bin_sort(int64_t n64, const gs_projected& proj, const DevCam& cam,
       const int tx = cam.tiles_x, ty = cam.tiles_y;
       const int cmax = static_cast<int>(direct_max_chunks(capacity));
       k_chunk_bounds<<<static_cast<unsigned>(ceil_div(cmax + 1, 256)), 256, 0, s>>>(n, b.offs, b.readback, cmax,
-                                                                                   b.bounds);
+                                                                                   b.bounds, k_dev);
       if ((st = check_launch("k_chunk_bounds")) != GS_OK) return st;
       k_chunk_count<<<cmax, kDirectThreads, sizeof(int) * (tx + 1) * (ty + 1), s>>>(b.bounds, b.rect_rank, tx, ty,
                                                                                    b.table);
       if ((st = check_launch("k_chunk_count")) != GS_OK) return st;
       k_chunk_colscan<<<static_cast<unsigned>(ceil_div(ntiles, 64)), 1024, 0, s>>>(cmax, ntiles, b.table, b.total);
       if ((st = check_launch("k_chunk_colscan")) != GS_OK) return st;
-      k_tile_starts<<<1, 1024, 0, s>>>(ntiles, b.total, b.start, reinterpret_cast<uint2*>(ranges));
+      k_tile_starts<<<1, 1024, 0, s>>>(ntiles, b.total, b.start, reinterpret_cast<uint2*>(ranges),
+                                       static_cast<unsigned long long>(capacity));
       if ((st = check_launch("k_tile_starts")) != GS_OK) return st;
       k_emit_direct<<<cmax, kDirectThreads, emit_dyn_lds(tx, ty), s>>>(
           b.bounds, order, b.rect_rank, b.table, b.start, tx, ty, point_list,
           static_cast<uint32_t>(std::min<int64_t>(capacity, UINT32_MAX)));
       if ((st = check_launch("k_emit_direct")) != GS_OK) return st;
+      if (k_dev) return GS_OK;   // the caller checks K and the flag later
     }
     if ((st = check_hip(hipMemcpyAsync(rb, b.readback, sizeof(rb), hipMemcpyDeviceToHost, s),
                         "hipMemcpyAsync(K)")) != GS_OK) return st;
@@ -1072,7 +1094,11 @@ gs_status run_bin_sort(int64_t n64, const gs_projected& proj, const DevCam& cam,
       return check_launch("k_ranges");
     }
   } else {
-    *k_out = 0;
+    if (k_out) *k_out = 0;
+    if (k_dev) {
+      k_put_zero_k<<<1, 64, 0, s>>>(k_dev);
+      if ((st = check_launch("k_put_zero_k")) != GS_OK) return st;
+    }
   }
   // K == 0: every tile is empty
   if ((st = check_hip(hipMemsetAsync(ranges, 0, sizeof(uint32_t) * 2 * static_cast<size_t>(ntiles), s),

@@ -128,8 +128,12 @@ size_t binsort_workspace(int64_t n, int64_t capacity, int tiles_x, int tiles_y);
 size_t scan_sums_words(int64_t n);
 gs_status launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* sums,
                                 unsigned long long* total, hipStream_t s);
+// k_dev == NULL: waits for K (*k_out); else no wait, K and the look-back
+// flag go to k_dev[0], k_dev[1] (direct emission only, see binsort_direct).
 gs_status run_bin_sort(int64_t n, const gs_projected& proj, const DevCam& cam, void* ws, size_t ws_bytes,
-                       uint32_t* point_list, int64_t capacity, uint32_t* ranges, int64_t* k_out, hipStream_t s);
+                       uint32_t* point_list, int64_t capacity, uint32_t* ranges, int64_t* k_out,
+                       unsigned long long* k_dev, hipStream_t s);
+bool binsort_direct(int tiles_x, int tiles_y);
 gs_status launch_render_fwd(const gs_projected& proj, const uint32_t* point_list, const uint32_t* ranges, int64_t k,
                             const DevCam& cam, float* image, float* final_T, uint32_t* n_contrib, float* t_ckpt,
                             int schedule, hipStream_t s);

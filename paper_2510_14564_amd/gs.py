@@ -34,7 +34,7 @@ STATUS_NAMES = {0: "GS_OK", -1: "GS_ERR_INVALID_ARG", -2: "GS_ERR_CAPACITY", -3:
                 -4: "GS_ERR_UNSUPPORTED"}
 
 # every symbol declared in include/gsplat.h
-EXPORTS = ("gs_last_error", "gs_version", "gs_project", "gs_bin_sort_workspace", "gs_bin_sort",
+EXPORTS = ("gs_last_error", "gs_version", "gs_project", "gs_bin_sort_workspace", "gs_bin_sort", "gs_bin_sort_async",
            "gs_render_fwd", "gs_render_count", "gs_render_ckpt_floats", "gs_render_bwd_workspace", "gs_render_bwd", "gs_project_bwd",
            "gs_project_bwd_workspace", "gs_l1_loss", "gs_mlp_pack", "gs_mlp_fwd", "gs_mlp_bwd_workspace",
            "gs_mlp_bwd", "gs_sh_colour", "gs_adam_step")
@@ -79,6 +79,7 @@ _sigs = {
     "gs_project": ([_P(Gaussians), _P(Camera), _P(Projected), _vp], ctypes.c_int),
     "gs_bin_sort_workspace": ([_i64, _i64, _P(Camera), _P(_sz)], ctypes.c_int),
     "gs_bin_sort": ([_i64, _P(Projected), _P(Camera), _vp, _sz, _vp, _i64, _vp, _P(_i64), _vp], ctypes.c_int),
+    "gs_bin_sort_async": ([_i64, _P(Projected), _P(Camera), _vp, _sz, _vp, _i64, _vp, _vp, _vp], ctypes.c_int),
     "gs_render_fwd": ([_i64, _P(Projected), _vp, _vp, _i64, _P(Camera), _vp, _vp, _vp, _vp, _i32, _vp],
                       ctypes.c_int),
     "gs_render_ckpt_floats": ([_i64, _P(Camera), _P(_sz)], ctypes.c_int),
@@ -210,6 +211,16 @@ def bin_sort(n: int, proj: ProjectedBuffers, cam: Camera, ws, point_list, ranges
         raise e
     _check(st, "gs_bin_sort")
     return int(k.value)
+
+
+def bin_sort_async(n: int, proj: ProjectedBuffers, cam: Camera, ws, point_list, ranges, k_dev, stream=None):
+    """bin_sort without the host wait: K and the look-back flag go to the
+    device tensor k_dev (int64[2]); the lists are valid only if
+    k_dev[0] <= point_list.numel() and k_dev[1] == 0."""
+    assert k_dev.dtype == torch.int64 and k_dev.numel() >= 2 and k_dev.is_cuda
+    _check(_lib.gs_bin_sort_async(n, ctypes.byref(proj.struct()), ctypes.byref(cam), _ptr(ws),
+                                  ws.numel() * ws.element_size(), _ptr(point_list), point_list.numel(), _ptr(ranges),
+                                  _ptr(k_dev), _stream(stream)), "gs_bin_sort_async")
 
 
 def render_fwd(n: int, proj: ProjectedBuffers, point_list, ranges, k: int, cam: Camera, image, final_T, n_contrib,

@@ -38,8 +38,18 @@ class Rasterizer:
     """Holds device buffers for one camera resolution and one Gaussian count."""
 
     def __init__(self, cam, sh_degree: int, device="cuda", deterministic: bool = False, capacity: int | None = None,
-                 schedule: int = gs.SCHEDULE_BALANCED):
+                 schedule: int = gs.SCHEDULE_BALANCED, async_k: bool = False):
         self.cam = cam
+        # async_k: bin with gs_bin_sort_async (no host wait inside a frame) once
+        # a frame's K is known; each frame's K is checked at the next forward
+        # (or by check_async), which raises GsError if that frame's lists did
+        # not fit -- its outputs are then invalid and the capacity has grown
+        self.async_k = async_k
+        self.k_dev = None       # int64[2] on the device, K and the look-back flag
+        self.k_host = None      # its pinned host copy
+        self._k_event = None
+        self._k_cap = 0
+        self.last_k = None
         self.schedule = schedule
         self.cs = gs.camera_struct(cam)
         self.sh_degree = sh_degree
@@ -59,7 +69,6 @@ class Rasterizer:
         self.image = torch.empty((3, H, W), dtype=torch.float32, device=self.device)
         self.final_T = torch.empty((H, W), dtype=torch.float32, device=self.device)
         self.n_contrib = torch.empty((H, W), dtype=torch.int32, device=self.device)
-        self.last_k = 0
         self.timer = None          # optional callable(stage_name) -> context manager
 
     def _stage(self, name):
@@ -95,16 +104,33 @@ class Rasterizer:
         g = self._gauss(means, log_scales, quats, logits, colour)
         with self._stage("project"):
             gs.project(g, self.cs, self.proj)
-        while True:
+        k = None
+        if self.async_k and self.last_k is not None:
+            self.check_async()
+            if self.k_dev is None:
+                self.k_dev = torch.zeros(2, dtype=torch.int64, device=self.device)
+                self.k_host = torch.zeros(2, dtype=torch.int64, pin_memory=True)
+            try:
+                with self._stage("bin_sort"):
+                    gs.bin_sort_async(n, self.proj, self.cs, self.bin_ws, self.point_list, self.ranges, self.k_dev)
+                self.k_host.copy_(self.k_dev, non_blocking=True)
+                self._k_event = torch.cuda.Event()
+                self._k_event.record()
+                k = self._k_cap = self._cap   # an upper bound serves every later layout
+            except gs.GsError as e:
+                if e.status != gs.GS_ERR_UNSUPPORTED:
+                    raise
+                self.async_k = False           # frame too large for the direct emission
+        while k is None:
             try:
                 with self._stage("bin_sort"):
                     k = gs.bin_sort(n, self.proj, self.cs, self.bin_ws, self.point_list, self.ranges)
-                break
             except gs.GsError as e:
                 if e.status != gs.GS_ERR_CAPACITY:
                     raise
                 self._alloc_lists(int(e.required * 1.25) + 1024)
-        self.last_k = k
+            else:
+                self.last_k = k
         need = gs.render_ckpt_floats(k, self.cs)
         if self.t_ckpt is None or self.t_ckpt.numel() < need:
             self.t_ckpt = torch.empty(int(need * 1.25), dtype=torch.float32, device=self.device)
@@ -113,6 +139,26 @@ class Rasterizer:
                           self.n_contrib, self.t_ckpt, schedule=self.schedule)
         return FrameState(n, k, self.proj, self.point_list, self.ranges, self.image, self.final_T, self.n_contrib,
                           self.t_ckpt)
+
+    def check_async(self) -> int | None:
+        """Check the last frame binned without a host wait: returns its K, or
+        raises GsError (GS_ERR_CAPACITY with .required = K, after growing the
+        capacity; GS_ERR_HIP if its depth sort did not complete)."""
+        if self._k_event is None:
+            return self.last_k
+        self._k_event.synchronize()
+        self._k_event = None
+        K, flag = int(self.k_host[0]), int(self.k_host[1])
+        if flag:
+            raise gs.GsError(gs.GS_ERR_HIP, "gs_bin_sort_async", "depth sort look-back did not complete")
+        if K > self._k_cap:
+            self._alloc_lists(int(K * 1.25) + 1024)
+            e = gs.GsError(gs.GS_ERR_CAPACITY, "gs_bin_sort_async",
+                           f"a frame needed {K} entries, the capacity was {self._k_cap}")
+            e.required = K
+            raise e
+        self.last_k = K
+        return K
 
     def backward(self, st: FrameState, means, log_scales, quats, logits, colour, dL_dimage, g2d=None):
         n = st.n

@@ -140,3 +140,22 @@ def test_camera_struct_layout_matches_header(gs):
     # int32 x2 + float x7 + R[9] + t[3] + bg[3] = 2*4 + 22*4 bytes
     assert ctypes.sizeof(gs.Camera) == 8 + 22 * 4
     assert ctypes.sizeof(gs.Gaussians) == 8 + 4 + 4 + 7 * 8
+
+
+def test_bin_sort_async_argument_checks(gs):
+    """Host-side rejections of the no-wait bin/sort: a NULL K buffer, a small
+    workspace, and a frame whose per-chunk tables exceed LDS (2400 x 1000 px,
+    150 x 63 tiles), which must use gs_bin_sort -- all before device work."""
+    c = _cam(gs)
+    fake = ctypes.c_void_p(0x1000)
+    st = gs._lib.gs_bin_sort_async(10, ctypes.byref(_proj(gs)), ctypes.byref(c), fake, 1 << 30, fake, 100, fake,
+                                   NULL, NULL)
+    assert st == gs.GS_ERR_INVALID_ARG
+    st = gs._lib.gs_bin_sort_async(10, ctypes.byref(_proj(gs)), ctypes.byref(c), fake, 16, fake, 100, fake, fake,
+                                   NULL)
+    assert st == gs.GS_ERR_INVALID_ARG
+    wide = gs.camera_struct(scenes.pinhole(2400, 1000, 70.0, np.eye(3), (0.0, 0.0, 3.0)))
+    st = gs._lib.gs_bin_sort_async(10, ctypes.byref(_proj(gs)), ctypes.byref(wide), fake, 1 << 40, fake, 100, fake,
+                                   fake, NULL)
+    assert st == gs.GS_ERR_UNSUPPORTED
+    assert "gs_bin_sort" in gs.last_error()

@@ -29,7 +29,7 @@ import torch
 import oracle
 from paper_2510_14564_amd import scenes
 from gpu_helpers import (DEV, MASS_FLOOR, PROJ_RTOL, chain_mass, compare_render, gpu_bin_sort, gpu_project,
-                         gpu_render, gpu_render_bwd, grad_close, proj_host, say, to_dev)
+                         gpu_render, gpu_render_bwd, grad_close, proj_host, say, to_dev, upload)
 
 pytestmark = pytest.mark.gpu
 
@@ -472,3 +472,42 @@ def test_bin_sort_wide_frame_fallback(gs):
     assert np.array_equal(pl[:k].cpu().numpy().view(np.uint32), o_pl), "point_list"
     assert np.array_equal(ranges.cpu().numpy().view(np.uint32), o_ranges), "ranges"
     say(f"  K={k} bit-exact")
+
+
+def test_bin_sort_async_matches_sync(gs):
+    """Frames binned without the host wait (gs_bin_sort_async, K checked one
+    frame later) give the same images and, with the deterministic reduction,
+    the same gradients bit for bit as the waiting call; a frame whose lists do
+    not fit is reported at the check with the size it needed."""
+    from paper_2510_14564_amd.raster import Rasterizer
+    scene = scenes.config_scene(2)
+    cams = [scenes.orbit_camera(k, 32, 800, 800) for k in (0, 3, 9, 17)]
+    p = upload(scene)
+    G = to_dev(scenes.upstream_grad(cams[0], 2001))
+    args = (p["means"], p["log_scales"], p["quats"], p["logits"], p["sh"])
+    outs = {}
+    for mode in (False, True):
+        rast = Rasterizer(cams[0], 3, device=DEV, deterministic=True, async_k=mode, capacity=8_000_000)
+        frames = []
+        for cam in cams:
+            rast.set_camera(cam)
+            st = rast.forward(*args)
+            g, _ = rast.backward(st, *args, G)
+            frames.append((st.image.clone(), st.n_contrib.clone(), {kk: v.clone() for kk, v in g.items()}))
+        assert rast.check_async() is not None
+        outs[mode] = frames
+    for (i0, n0, g0), (i1, n1, g1) in zip(outs[False], outs[True]):
+        assert torch.equal(i0, i1) and torch.equal(n0, n1)
+        for kk in g0:
+            assert torch.equal(g0[kk], g1[kk]), kk
+    say("  async bin/sort: 4 frames bit-identical to the waiting call")
+    rast = Rasterizer(cams[0], 3, device=DEV, async_k=True)
+    rast.forward(*args)                    # first frame waits and learns K
+    k0 = rast.last_k
+    rast._alloc_lists(k0 // 2)             # the next frame's lists cannot fit
+    rast.forward(*args)
+    with pytest.raises(gs.GsError) as ei:
+        rast.check_async()
+    assert ei.value.status == gs.GS_ERR_CAPACITY and ei.value.required == k0
+    rast.forward(*args)                    # capacity grown by the check
+    assert rast.check_async() == k0
