@@ -184,6 +184,8 @@ def main():
     ap.add_argument("--compare-plain", action="store_true",
                     help="also time the SH step with the plain and the merged work splits, and with the "
                          "deterministic reduction")
+    ap.add_argument("--wait-k", action="store_true",
+                    help="bin/sort waits for the entry count every frame (no gs_bin_sort_async)")
     ap.add_argument("--hbm-probe", action="store_true",
                     help="also time a 2 GiB device-to-device copy (achievable HBM bandwidth, counter calibration)")
     args = ap.parse_args()
@@ -208,6 +210,20 @@ def main():
     targets = [torch.from_numpy(scenes.target_image(cams[k], 3000 + k)).to(dev) for k in range(ncam)]
     partials = torch.empty(gs.L1_PARTIALS, dtype=torch.float32, device=dev)
     rast = Rasterizer(cams[0], scene.sh_degree, device=dev)
+    # list capacity for the whole orbit (one waiting bin/sort per camera), so
+    # that the timed steps can bin without the host wait: each frame's K is
+    # then checked at the next frame and at the end, and an overflow would
+    # raise instead of passing unnoticed
+    if not args.wait_k:
+        with torch.no_grad():
+            kmax = 0
+            for cam in cams:
+                rast.set_camera(cam)
+                st = rast.forward(params["means"], params["log_scales"], params["quats"], params["logits"],
+                                  params["sh"])
+                kmax = max(kmax, st.k)
+        rast._alloc_lists(int(kmax * 1.1) + 1024)
+        rast.async_k = True
     timer = StageTimer(torch)
     rast.timer = timer
 
@@ -294,6 +310,9 @@ def main():
 
         mlp_ms, mlp_stage_ms = run_timed(step_mlp, "learned colour")
 
+    # every frame binned without the wait fitted its lists (else this raises)
+    rast.check_async()
+    rast.async_k = False
     # algorithmic work of the timed steps (recounted untimed, same cameras)
     walked, examined, blended, ks = [], [], [], []
     counts = torch.zeros(2, dtype=torch.int64, device=dev)
@@ -356,6 +375,7 @@ def main():
                    f": {n} Gaussians, SH degree {deg}, {W}x{H}, 16x16 tiles, "
                    f"{ncam} camera(s), colour SH, L1 loss",
                    "gaussians": n, "width": W, "height": H, "sh_degree": deg, "colour": "sh",
+                   "bin_sort": "waits for K" if args.wait_k else "no host wait (K checked a frame later)",
                    "parallelism": "single GPU"},
         "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "pairs_per_step": {"examined_fwd": round(p_exam), "walked_bwd": round(p_walk), "blended": round(p_blend)},
