@@ -822,16 +822,76 @@ __global__ __launch_bounds__(1024) void k_tile_starts(int ntiles, const uint32_t
   }
 }
 
-// Groups of 256 ranks.  Waves 0-3 load the group's ranks (64 each) and build
-// their coverage masks; then wave w places the entries of rank-wave w & 3,
-// taking every fourth run of 64 of them.  An entry finds its rank by a
-// binary search over the 64 entry offsets of its rank-wave, its tile from
-// the rank's rectangle, and its position as the tile's position at the start
-// of the group plus the count of the group's earlier ranks on the tile.  The
-// entry of the tile's last rank in the group also writes the group's count
-// for the tile into delta[t], which one pass over the tiles adds to the
-// positions once every entry of the group is placed.
-__global__ __launch_bounds__(kDirectThreads) void k_emit_direct(const uint32_t* __restrict__ bounds,
+// Placement of entry e of rank-wave rw (uniform over the wave) of the
+// current group (offsets pre[0..64], total pre[64]): the entry goes to its
+// tile's position at the group start plus the group's earlier ranks on that
+// tile; the group's last entry on a tile stores the group's count there.
+__device__ __forceinline__ void place_entry(int rw, uint32_t e, const uint32_t* __restrict__ pre,
+                                            const uint2* __restrict__ s_rect, const uint32_t* __restrict__ s_gid,
+                                            const unsigned long long* __restrict__ s_dyn,
+                                            const uint32_t* __restrict__ s_pos, uint16_t* __restrict__ s_delta,
+                                            int edge, int tiles_x, uint32_t* __restrict__ point_list,
+                                            uint32_t capacity) {
+  if (e >= pre[64]) return;
+  int lo = 0;
+#pragma unroll
+  for (int step = 32; step > 0; step >>= 1)
+    lo += (pre[lo + step] <= e) ? step : 0;   // the last rank with offset <= e
+  const int i = rw * 64 + lo;
+  const uint2 q = s_rect[i];
+  const uint32_t j = e - pre[lo];
+  const uint32_t qx0 = q.x & 0xFFFFu, w = (q.x >> 16) - qx0;
+  // row = j / w without an integer division (float quotient within one)
+  uint32_t rr = static_cast<uint32_t>(static_cast<float>(j) * __builtin_amdgcn_rcpf(static_cast<float>(w)));
+  const uint32_t prod = rr * w;
+  rr = rr + static_cast<uint32_t>(prod + w <= j) - static_cast<uint32_t>(prod > j);
+  const int tx = static_cast<int>(qx0 + (j - rr * w));
+  const int ty = static_cast<int>((q.y & 0xFFFFu) + rr);
+  const int t = ty * tiles_x + tx;
+  // the group's ranks on the tile, per rank-wave; earlier ones: whole earlier
+  // rank-waves, then the lanes below lo of this one; later ones decide "last"
+  unsigned long long m[4];
+#pragma unroll
+  for (int w2 = 0; w2 < 4; ++w2) m[w2] = s_dyn[w2 * edge + tx] & s_dyn[w2 * edge + tiles_x + ty];
+  const unsigned long long below = (1ull << lo) - 1ull, above = ~(below | (1ull << lo));
+  uint32_t within;
+  unsigned long long later;
+  switch (rw) {
+    case 0:
+      within = __popcll(m[0] & below);
+      later = (m[0] & above) | m[1] | m[2] | m[3];
+      break;
+    case 1:
+      within = __popcll(m[0]) + __popcll(m[1] & below);
+      later = (m[1] & above) | m[2] | m[3];
+      break;
+    case 2:
+      within = __popcll(m[0]) + __popcll(m[1]) + __popcll(m[2] & below);
+      later = (m[2] & above) | m[3];
+      break;
+    default:
+      within = __popcll(m[0]) + __popcll(m[1]) + __popcll(m[2]) + __popcll(m[3] & below);
+      later = m[3] & above;
+      break;
+  }
+  const uint32_t p = s_pos[t] + within;
+  if (p < capacity) point_list[p] = s_gid[i];
+  if (later == 0ull) s_delta[t] = static_cast<uint16_t>(within + 1u);   // at most 256
+}
+
+// Groups of 256 ranks.  Waves 0-3 load the group's ranks (64 each, a
+// rank-wave) and build their coverage masks; then the group's runs of 64
+// entries (rank-wave 0's, then 1's, ...) are dealt to the 16 waves in turn,
+// so that a rank-wave with many entries does not hold up the group.  An entry
+// finds its rank by a binary search over the 64 entry offsets of its
+// rank-wave, its tile from the rank's rectangle, and its position as the
+// tile's position at the start of the group plus the count of the group's
+// earlier ranks on the tile.  The entry of the tile's last rank in the group
+// also writes the group's count for the tile into delta[t], which one pass
+// over the tiles adds to the positions once every entry of the group is
+// placed.
+// two workgroups per CU (8 waves per SIMD): at most 64 VGPRs
+__global__ __launch_bounds__(kDirectThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_emit_direct(const uint32_t* __restrict__ bounds,
                                                                 const uint32_t* __restrict__ order,
                                                                 const uint2* __restrict__ rect_rank,
                                                                 const uint32_t* __restrict__ table,
@@ -848,6 +908,7 @@ __global__ __launch_bounds__(kDirectThreads) void k_emit_direct(const uint32_t* 
   uint32_t* const s_pos = reinterpret_cast<uint32_t*>(s_dyn + 4 * edge);
   uint16_t* const s_delta = reinterpret_cast<uint16_t*>(s_pos + ntiles);
   const int c = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wave_u = __builtin_amdgcn_readfirstlane(wave);
   const uint32_t R0 = bounds[c], R1 = bounds[c + 1];
   if (R0 >= R1) return;
   const uint32_t* const tab = table + static_cast<size_t>(c) * ntiles;
@@ -855,7 +916,6 @@ __global__ __launch_bounds__(kDirectThreads) void k_emit_direct(const uint32_t* 
     s_pos[t] = start[t] + tab[t];
     s_delta[t] = 0;
   }
-  const int rw = wave & 3, helper = wave >> 2;
   for (uint32_t r0 = R0; r0 < R1; r0 += 256) {
     __syncthreads();   // positions updated, masks of the previous group no longer read
     if (wave < 4) {
@@ -908,43 +968,20 @@ __global__ __launch_bounds__(kDirectThreads) void k_emit_direct(const uint32_t* 
       }
     }
     __syncthreads();
-    // place the entries of rank-wave rw, runs of 64 taken round-robin by its
-    // four helper waves
-    const uint32_t* const pre = s_pre[rw];
-    const uint32_t S = pre[64];
-    for (uint32_t e = static_cast<uint32_t>(helper) * 64 + lane; e - lane < S; e += 256) {
-      if (e >= S) continue;
-      int lo = 0;
-#pragma unroll
-      for (int step = 32; step > 0; step >>= 1)
-        lo += (pre[lo + step] <= e) ? step : 0;   // the last rank with offset <= e
-      const int i = rw * 64 + lo;
-      const uint2 q = s_rect[i];
-      const uint32_t j = e - pre[lo];
-      const uint32_t qx0 = q.x & 0xFFFFu, w = (q.x >> 16) - qx0;
-      // row = j / w without an integer division (float quotient within one)
-      uint32_t rr = static_cast<uint32_t>(static_cast<float>(j) * __builtin_amdgcn_rcpf(static_cast<float>(w)));
-      const uint32_t prod = rr * w;
-      rr = (prod > j) ? rr - 1u : ((prod + w <= j) ? rr + 1u : rr);
-      const int tx = static_cast<int>(qx0 + (j - rr * w));
-      const int ty = static_cast<int>((q.y & 0xFFFFu) + rr);
-      const int t = ty * tiles_x + tx;
-      // earlier ranks of the group on the tile: whole earlier rank-waves, then
-      // the lanes below lo of this one; later ones decide "last"
-      const unsigned long long below = (1ull << lo) - 1ull;
-      uint32_t within = 0;
-      unsigned long long later = 0ull;
-#pragma unroll
-      for (int w2 = 0; w2 < 4; ++w2) {
-        const unsigned long long m = s_dyn[w2 * edge + tx] & s_dyn[w2 * edge + tiles_x + ty];
-        const unsigned long long lo_sel = (w2 < rw) ? ~0ull : ((w2 == rw) ? below : 0ull);
-        const unsigned long long hi_sel = (w2 > rw) ? ~0ull : ((w2 == rw) ? ~(below | (1ull << lo)) : 0ull);
-        within += static_cast<uint32_t>(__popcll(m & lo_sel));
-        later |= m & hi_sel;
+    // place the group's entries: the runs of 64 entries of rank-waves 0..3 in
+    // turn, dealt to the 16 waves round-robin (a run's rank-wave is uniform
+    // over the wave)
+    {
+      const uint32_t c1 = __builtin_amdgcn_readfirstlane((s_pre[0][64] + 63u) >> 6);
+      const uint32_t c2 = c1 + __builtin_amdgcn_readfirstlane((s_pre[1][64] + 63u) >> 6);
+      const uint32_t c3 = c2 + __builtin_amdgcn_readfirstlane((s_pre[2][64] + 63u) >> 6);
+      const uint32_t nrun = c3 + __builtin_amdgcn_readfirstlane((s_pre[3][64] + 63u) >> 6);
+      for (uint32_t run = static_cast<uint32_t>(wave_u); run < nrun; run += kDirectWaves) {
+        const int rw = run < c1 ? 0 : (run < c2 ? 1 : (run < c3 ? 2 : 3));
+        const uint32_t first = run < c1 ? 0u : (run < c2 ? c1 : (run < c3 ? c2 : c3));
+        place_entry(rw, (run - first) * 64u + lane, s_pre[rw], s_rect, s_gid, s_dyn, s_pos, s_delta, edge,
+                    tiles_x, point_list, capacity);
       }
-      const uint32_t p = s_pos[t] + within;
-      if (p < capacity) point_list[p] = s_gid[i];
-      if (later == 0ull) s_delta[t] = static_cast<uint16_t>(within + 1u);   // at most 256
     }
     __syncthreads();
     for (int t = tid; t < ntiles; t += kDirectThreads) {

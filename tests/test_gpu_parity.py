@@ -474,6 +474,47 @@ def test_bin_sort_wide_frame_fallback(gs):
     say(f"  K={k} bit-exact")
 
 
+def _slab_scene(n_small=20000, n_big=700, seed=93):
+    """Small Gaussians everywhere plus large ones in a thin depth slab: rank
+    groups inside the slab touch thousands of tiles, the others a few hundred."""
+    a = scenes.uniform_scene(n_small, seed, log_scale_mean=-4.5, log_scale_std=0.3, sh_degree=1)
+    b = scenes.uniform_scene(n_big, seed + 1, log_scale_mean=-1.8, log_scale_std=0.2, sh_degree=1)
+    means = b.means.copy()
+    means[2] = np.float32(0.5) + np.float32(0.05) * (means[2] + 1) / 2
+    cat = lambda x, y: np.concatenate([x, y], axis=-1)
+    return scenes.Scene(n_small + n_big, 1, cat(a.means, means), cat(a.log_scales, b.log_scales),
+                        cat(a.quats, b.quats), cat(a.logits, b.logits), cat(a.sh, b.sh))
+
+
+def test_bin_sort_many_tiles_per_group(gs):
+    """Direct emission where some groups of 256 consecutive depth ranks cover
+    thousands of tiles (their rank-waves hold very different entry counts) and
+    the others a few hundred: the lists must still be the oracle's bit for bit."""
+    scene = _slab_scene()
+    cam = scenes.front_camera(1600, 1064, 3.0, 60.0)
+    say(f"[bin/sort many tiles] n={scene.n} {cam.width}x{cam.height}")
+    p, g, out = gpu_project(gs, scene, cam)
+    h = proj_host(out)
+    rect, _, _ = oracle.bin_rects(h["u"], h["v"], h["radius"], cam.width, cam.height)
+    order = np.lexsort((np.arange(scene.n), h["depth"].astype(np.float32).view(np.uint32)))
+    tx = cam.tiles_x
+    wide = []
+    for g0 in range(0, scene.n, 256):
+        tiles = set()
+        for k in order[g0:g0 + 256]:
+            x0, x1, y0, y1 = rect[k]
+            for y in range(y0, y1 + 1):
+                tiles.update(range(y * tx + x0, y * tx + x1 + 1))
+        wide.append(len(tiles) > 2048)
+    assert any(wide) and not all(wide), "the scene must mix wide and narrow rank groups"
+    k, pl, ranges = gpu_bin_sort(gs, scene.n, out, cam)
+    o_pl, o_ranges, _, _ = oracle.bin_sort(h["u"], h["v"], h["radius"], h["depth"], cam.width, cam.height)
+    assert k == len(o_pl) and k > 0
+    assert np.array_equal(pl[:k].cpu().numpy().view(np.uint32), o_pl), "point_list"
+    assert np.array_equal(ranges.cpu().numpy().view(np.uint32), o_ranges), "ranges"
+    say(f"  K={k}, {sum(wide)} of {len(wide)} aligned rank groups wide, bit-exact")
+
+
 def test_bin_sort_async_matches_sync(gs):
     """Frames binned without the host wait (gs_bin_sort_async, K checked one
     frame later) give the same images and, with the deterministic reduction,
