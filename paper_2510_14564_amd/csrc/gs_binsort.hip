@@ -306,7 +306,7 @@ __device__ __forceinline__ uint32_t rect_count(uint2 rc) {
 
 constexpr uint32_t kOsEmpty = 0u, kOsAgg = 1u, kOsIncl = 2u;
 constexpr uint32_t kOsCountMask = (1u << 30) - 1u;
-constexpr int kOsHistBlocks = 1024;
+constexpr int kOsHistBlocks = 256;   // more workgroups queue on the digit counts' atomics
 constexpr int kOsMaxPasses = 4;
 constexpr uint32_t kOsSpinLimit = 1u << 22;
 constexpr int kOsWindow = 8;
@@ -758,32 +758,38 @@ __global__ __launch_bounds__(kDirectThreads) void k_chunk_count(const uint32_t* 
 }
 
 // One workgroup (16 waves) per 64 tiles; wave w owns a contiguous range of
-// chunks.  table[c][t] becomes the entries of tile t in chunks before c.
+// at most kDirectChunks / 16 chunks, whose counts it holds in registers (one
+// read of the table, all loads in flight at once).  table[c][t] becomes the
+// entries of tile t in chunks before c; total[t] is the tile's count.
+constexpr int kColPer = kDirectChunks / 16;
 __global__ __launch_bounds__(1024) void k_chunk_colscan(int C, int ntiles, uint32_t* __restrict__ table,
                                                         uint32_t* __restrict__ total) {
   __shared__ uint32_t s_part[16][64];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int t = blockIdx.x * 64 + lane;
-  const int per = (C + 15) / 16;
+  const int per = (C + 15) / 16;   // at most kColPer (C <= kDirectChunks)
   const int c0 = min(C, wave * per), c1 = min(C, c0 + per);
+  uint32_t v[kColPer];
   uint32_t sum = 0;
-  if (t < ntiles)
-    for (int c = c0; c < c1; ++c) sum += table[static_cast<size_t>(c) * ntiles + t];
+#pragma unroll
+  for (int k = 0; k < kColPer; ++k) {
+    v[k] = (t < ntiles && c0 + k < c1) ? table[static_cast<size_t>(c0 + k) * ntiles + t] : 0u;
+    sum += v[k];
+  }
   s_part[wave][lane] = sum;
   __syncthreads();
   uint32_t run = 0, all = 0;
   for (int w = 0; w < 16; ++w) {
-    const uint32_t v = s_part[w][lane];
-    run += (w < wave) ? v : 0u;
-    all += v;
+    const uint32_t x = s_part[w][lane];
+    run += (w < wave) ? x : 0u;
+    all += x;
   }
   if (t >= ntiles) return;
   if (wave == 0) total[t] = all;
-  for (int c = c0; c < c1; ++c) {
-    const size_t o = static_cast<size_t>(c) * ntiles + t;
-    const uint32_t v = table[o];
-    table[o] = run;
-    run += v;
+#pragma unroll
+  for (int k = 0; k < kColPer; ++k) {
+    if (c0 + k < c1) table[static_cast<size_t>(c0 + k) * ntiles + t] = run;
+    run += v[k];
   }
 }
 
