@@ -97,17 +97,37 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__
   uint32_t v[kScanItems];
   uint32_t s = 0;
   const int64_t my = base + static_cast<int64_t>(threadIdx.x) * kScanItems;
-  for (int j = 0; j < kScanItems; ++j) {
-    const int64_t idx = my + j;
-    v[j] = idx < n ? in[idx] : 0u;
-    s += v[j];
+  // whole, 16-byte aligned runs move as four 16-byte accesses
+  const bool vec = my + kScanItems <= n && ((reinterpret_cast<uintptr_t>(in + my) |
+                                              reinterpret_cast<uintptr_t>(out + my)) & 15u) == 0;
+  if (vec) {
+#pragma unroll
+    for (int q = 0; q < kScanItems / 4; ++q) {
+      const uint4 w = reinterpret_cast<const uint4*>(in + my)[q];
+      v[4 * q] = w.x; v[4 * q + 1] = w.y; v[4 * q + 2] = w.z; v[4 * q + 3] = w.w;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) v[j] = my + j < n ? in[my + j] : 0u;
   }
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) s += v[j];
   uint32_t tot;
   uint32_t run = block_exclusive_scan(s, lds, tot) + static_cast<uint32_t>(offset);
+  uint32_t o[kScanItems];
+#pragma unroll
   for (int j = 0; j < kScanItems; ++j) {
-    const int64_t idx = my + j;
-    if (idx < n) out[idx] = run;
+    o[j] = run;
     run += v[j];
+  }
+  if (vec) {
+#pragma unroll
+    for (int q = 0; q < kScanItems / 4; ++q)
+      reinterpret_cast<uint4*>(out + my)[q] = make_uint4(o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]);
+  } else {
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j)
+      if (my + j < n) out[my + j] = o[j];
   }
   if (total && b == static_cast<int>(gridDim.x) - 1 && threadIdx.x == 0) *total = offset + tot;
 }
