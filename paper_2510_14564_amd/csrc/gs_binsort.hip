@@ -77,29 +77,58 @@ __global__ __launch_bounds__(256) void k_scan_sums(const uint32_t* __restrict__ 
   if (threadIdx.x == 0) sums[blockIdx.x] = red[0];
 }
 
+// Chunk bounds of the direct emission, derived from the scanned counts (see
+// k_scan_apply<true>): with K the total, chunk size E = max(min_entries,
+// ceil(K / target)) and count C = min(ceil(K / E), cmax), bounds[c] is the
+// first rank whose exclusive offset is >= c E for c < C, and n for
+// C <= c <= cmax.  k_dev != NULL: K and the depth sort's look-back flag
+// (total[1]) are also copied to k_dev[0], k_dev[1].
+struct ChunkArgs {
+  uint32_t* bounds;
+  int cmax;
+  unsigned long long min_entries, target;
+  unsigned long long* k_dev;
+};
+
 // Per chunk: its offset is the sum of the sums of all earlier chunks, which
 // every block adds up itself (a few thousand values at most, read from L2) --
 // no separate top-level scan launch.  The last block also writes the 64-bit
-// total.  Thread t owns items [16 t, 16 t + 16) of the chunk.
+// total.  Thread t owns items [16 t, 16 t + 16) of the chunk; whole, 16-byte
+// aligned runs move as four 16-byte accesses.
+// BOUNDS: instead of the offsets, write the chunk bounds of ChunkArgs.  Every
+// block also sums all chunk sums (K); item i, whose offsets span (offs[i],
+// offs[i] + cnt[i]], holds the bound of every chunk c >= 1 with c E in that
+// span: bounds[c] = i + 1 (the lower bound of c E among the offsets).
+template <bool BOUNDS>
 __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__ in, int64_t n,
                                                     const uint32_t* __restrict__ sums, uint32_t* __restrict__ out,
-                                                    unsigned long long* __restrict__ total) {
+                                                    unsigned long long* __restrict__ total, ChunkArgs ca) {
   __shared__ uint32_t lds[256];
-  __shared__ unsigned long long red[4];
+  __shared__ unsigned long long red[2][4];
   const int b = blockIdx.x;
-  unsigned long long pre = 0;
-  for (int i = threadIdx.x; i < b; i += 256) pre += sums[i];
-  for (int o = 32; o > 0; o >>= 1) pre += __shfl_xor(pre, o, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = pre;
+  unsigned long long pre = 0, all = 0;
+  const int upto = BOUNDS ? static_cast<int>(gridDim.x) : b;
+  for (int i = threadIdx.x; i < upto; i += 256) {
+    const uint32_t x = sums[i];
+    if (i < b) pre += x;
+    all += x;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    pre += __shfl_xor(pre, o, 64);
+    if (BOUNDS) all += __shfl_xor(all, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = pre;
+    red[1][threadIdx.x >> 6] = all;
+  }
   __syncthreads();
-  const unsigned long long offset = red[0] + red[1] + red[2] + red[3];
+  const unsigned long long offset = red[0][0] + red[0][1] + red[0][2] + red[0][3];
   const int64_t base = static_cast<int64_t>(b) * kScanChunk;
   uint32_t v[kScanItems];
   uint32_t s = 0;
   const int64_t my = base + static_cast<int64_t>(threadIdx.x) * kScanItems;
-  // whole, 16-byte aligned runs move as four 16-byte accesses
   const bool vec = my + kScanItems <= n && ((reinterpret_cast<uintptr_t>(in + my) |
-                                              reinterpret_cast<uintptr_t>(out + my)) & 15u) == 0;
+                                              (BOUNDS ? 0u : reinterpret_cast<uintptr_t>(out + my))) & 15u) == 0;
   if (vec) {
 #pragma unroll
     for (int q = 0; q < kScanItems / 4; ++q) {
@@ -113,21 +142,41 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__
 #pragma unroll
   for (int j = 0; j < kScanItems; ++j) s += v[j];
   uint32_t tot;
-  uint32_t run = block_exclusive_scan(s, lds, tot) + static_cast<uint32_t>(offset);
-  uint32_t o[kScanItems];
+  const uint32_t local = block_exclusive_scan(s, lds, tot);
+  if constexpr (BOUNDS) {
+    const unsigned long long K = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    const unsigned long long E = max(ca.min_entries, (K + ca.target - 1) / ca.target);
+    const unsigned long long C = min((K + E - 1) / E, static_cast<unsigned long long>(ca.cmax));
+    unsigned long long o = offset + local;
 #pragma unroll
-  for (int j = 0; j < kScanItems; ++j) {
-    o[j] = run;
-    run += v[j];
-  }
-  if (vec) {
-#pragma unroll
-    for (int q = 0; q < kScanItems / 4; ++q)
-      reinterpret_cast<uint4*>(out + my)[q] = make_uint4(o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]);
+    for (int j = 0; j < kScanItems; ++j) {
+      const unsigned long long hi = o + v[j];
+      for (unsigned long long c = o / E + 1; c < C && c * E <= hi; ++c) ca.bounds[c] = static_cast<uint32_t>(my + j + 1);
+      o = hi;
+    }
+    if (b == 0) {
+      for (int c = threadIdx.x; c <= ca.cmax; c += 256)
+        if (static_cast<unsigned long long>(c) >= C) ca.bounds[c] = static_cast<uint32_t>(n);
+        else if (c == 0) ca.bounds[0] = 0u;
+      if (ca.k_dev && threadIdx.x == 0) { ca.k_dev[0] = K; ca.k_dev[1] = total[1]; }
+    }
   } else {
+    uint32_t o[kScanItems];
+    uint32_t run = local + static_cast<uint32_t>(offset);
 #pragma unroll
-    for (int j = 0; j < kScanItems; ++j)
-      if (my + j < n) out[my + j] = o[j];
+    for (int j = 0; j < kScanItems; ++j) {
+      o[j] = run;
+      run += v[j];
+    }
+    if (vec) {
+#pragma unroll
+      for (int q = 0; q < kScanItems / 4; ++q)
+        reinterpret_cast<uint4*>(out + my)[q] = make_uint4(o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < kScanItems; ++j)
+        if (my + j < n) out[my + j] = o[j];
+    }
   }
   if (total && b == static_cast<int>(gridDim.x) - 1 && threadIdx.x == 0) *total = offset + tot;
 }
@@ -142,8 +191,16 @@ static size_t scan_ws_words(int64_t n) { return static_cast<size_t>(ceil_div(n >
 static gs_status device_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, ScanWs ws, hipStream_t s) {
   const int nb = static_cast<int>(ceil_div(n > 0 ? n : 1, kScanChunk));
   k_scan_sums<<<nb, 256, 0, s>>>(in, n, ws.sums);
-  k_scan_apply<<<nb, 256, 0, s>>>(in, n, ws.sums, out, ws.total);
+  k_scan_apply<false><<<nb, 256, 0, s>>>(in, n, ws.sums, out, ws.total, ChunkArgs{});
   return check_launch("device_exclusive_scan");
+}
+
+// The scan's total and the direct emission's chunk bounds (no offsets).
+static gs_status device_chunk_bounds(const uint32_t* in, int64_t n, ScanWs ws, ChunkArgs ca, hipStream_t s) {
+  const int nb = static_cast<int>(ceil_div(n > 0 ? n : 1, kScanChunk));
+  k_scan_sums<<<nb, 256, 0, s>>>(in, n, ws.sums);
+  k_scan_apply<true><<<nb, 256, 0, s>>>(in, n, ws.sums, nullptr, ws.total, ca);
+  return check_launch("device_chunk_bounds");
 }
 
 size_t scan_sums_words(int64_t n) { return scan_ws_words(n); }
@@ -704,32 +761,6 @@ static int64_t direct_max_chunks(int64_t cap) {
   return std::max<int64_t>(1, std::min<int64_t>(kDirectChunks, ceil_div(std::max<int64_t>(cap, 1), kDirectMinEntries)));
 }
 
-// Chunk size E = max(4096, ceil(K / 512)) and count C = min(ceil(K / E), cmax)
-// from the entry total K on the device; R_c = first rank whose entry offset
-// is >= c E for c < C, R_c = n for C <= c <= cmax (empty chunks).
-// With k_dev != NULL (no host wait) thread 0 also copies K and the depth
-// sort's look-back flag to k_dev[0], k_dev[1].
-__global__ __launch_bounds__(256) void k_chunk_bounds(int n, const uint32_t* __restrict__ offs,
-                                                      const unsigned long long* __restrict__ ktotal, int cmax,
-                                                      uint32_t* __restrict__ bounds,
-                                                      unsigned long long* __restrict__ k_dev) {
-  const int c = blockIdx.x * 256 + threadIdx.x;
-  if (c > cmax) return;
-  const unsigned long long K = *ktotal;
-  if (k_dev && c == 0) { k_dev[0] = K; k_dev[1] = ktotal[1]; }
-  const unsigned long long E = max(static_cast<unsigned long long>(kDirectMinEntries),
-                                   (K + kDirectChunks - 1) / kDirectChunks);
-  const unsigned long long C = min((K + E - 1) / E, static_cast<unsigned long long>(cmax));
-  if (static_cast<unsigned long long>(c) >= C) { bounds[c] = static_cast<uint32_t>(n); return; }
-  const unsigned long long key = static_cast<unsigned long long>(c) * E;
-  uint32_t lo = 0, hi = static_cast<uint32_t>(n);
-  while (lo < hi) {
-    const uint32_t mid = lo + ((hi - lo) >> 1);
-    if (offs[mid] < key) lo = mid + 1; else hi = mid;
-  }
-  bounds[c] = lo;
-}
-
 // In-place inclusive prefix sums of `len` ints at p[0], p[stride], ... by one wave.
 __device__ __forceinline__ void wave_prefix_lds(int* p, int len, int stride, int lane) {
   int carry = 0;
@@ -1103,7 +1134,6 @@ gs_status run_bin_sort(int64_t n64, const gs_projected& proj, const DevCam& cam,
                                              b.rect_rank, b.cnt)) != GS_OK)
       return st;
     const uint32_t* order = (passes % 2 == 0) ? b.dv0 : b.dv1;
-    if ((st = device_exclusive_scan(b.cnt, b.offs, n, b.scan, s)) != GS_OK) return st;
     unsigned long long rb[2] = {0ull, 0ull};
     if (b.table) {
       // direct emission, sized on the device from the scanned total: no host
@@ -1111,9 +1141,11 @@ gs_status run_bin_sort(int64_t n64, const gs_projected& proj, const DevCam& cam,
       // flag) are read once at the end
       const int tx = cam.tiles_x, ty = cam.tiles_y;
       const int cmax = static_cast<int>(direct_max_chunks(capacity));
-      k_chunk_bounds<<<static_cast<unsigned>(ceil_div(cmax + 1, 256)), 256, 0, s>>>(n, b.offs, b.readback, cmax,
-                                                                                   b.bounds, k_dev);
-      if ((st = check_launch("k_chunk_bounds")) != GS_OK) return st;
+      if ((st = device_chunk_bounds(b.cnt, n, b.scan,
+                                    ChunkArgs{b.bounds, cmax, static_cast<unsigned long long>(kDirectMinEntries),
+                                              static_cast<unsigned long long>(kDirectChunks), k_dev},
+                                    s)) != GS_OK)
+        return st;
       k_chunk_count<<<cmax, kDirectThreads, sizeof(int) * (tx + 1) * (ty + 1), s>>>(b.bounds, b.rect_rank, tx, ty,
                                                                                    b.table);
       if ((st = check_launch("k_chunk_count")) != GS_OK) return st;
@@ -1127,6 +1159,8 @@ gs_status run_bin_sort(int64_t n64, const gs_projected& proj, const DevCam& cam,
           static_cast<uint32_t>(std::min<int64_t>(capacity, UINT32_MAX)));
       if ((st = check_launch("k_emit_direct")) != GS_OK) return st;
       if (k_dev) return GS_OK;   // the caller checks K and the flag later
+    } else if ((st = device_exclusive_scan(b.cnt, b.offs, n, b.scan, s)) != GS_OK) {
+      return st;
     }
     if ((st = check_hip(hipMemcpyAsync(rb, b.readback, sizeof(rb), hipMemcpyDeviceToHost, s),
                         "hipMemcpyAsync(K)")) != GS_OK) return st;
