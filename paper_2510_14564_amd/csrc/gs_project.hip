@@ -141,6 +141,12 @@ __global__ __launch_bounds__(256) void k_project(int n, const float* __restrict_
 #pragma unroll
   for (int k = 0; k < 4; ++k) q[k] = quats[k * n + i];
   const float logit = logits[i];
+  // the colour coefficients (most of the bytes read) are loaded with the
+  // geometry, before it is known whether the Gaussian is live, so that their
+  // latency overlaps the projection arithmetic
+  float shv[3 * (NC > 0 ? NC : 1)];
+#pragma unroll
+  for (int j = 0; j < 3 * NC; ++j) shv[j] = sh[j * n + i];
   Geo g;
   bool live = project_geometry(m, s, q, logit, cam, g);
   float rgb[3] = {0.0f, 0.0f, 0.0f};
@@ -153,7 +159,7 @@ __global__ __launch_bounds__(256) void k_project(int n, const float* __restrict_
     for (int ch = 0; ch < 3; ++ch) {
       float acc = 0.0f;
 #pragma unroll
-      for (int j = 0; j < NC; ++j) acc += Y[j] * sh[(3 * j + ch) * n + i];
+      for (int j = 0; j < NC; ++j) acc += Y[j] * shv[3 * j + ch];
       rgb[ch] = fmaxf(acc + 0.5f, 0.0f);
     }
     live = isfinite(rgb[0]) && isfinite(rgb[1]) && isfinite(rgb[2]);
