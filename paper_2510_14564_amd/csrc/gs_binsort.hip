@@ -430,34 +430,56 @@ __global__ __launch_bounds__(256) void k_os_hist(const uint32_t* __restrict__ ke
     if (h[p][threadIdx.x]) atomicAdd(&ghist[p * 256 + threadIdx.x], h[p][threadIdx.x]);
 }
 
+// Pass `pass` of the sort over key bits [0, total_bits).  A pass whose digit
+// is the same for every key keeps the order.  The last pass that changes it
+// (from the digit counts of every pass, ghist) is the terminal one: it writes
+// the values in their final order to vals_final, with each value's rectangle
+// and tile count when rect != NULL, and no keys; the passes after it return
+// at once.  (All passes trivial: pass 0 is terminal and copies.)
 template <int ITEMS>
 __global__ __launch_bounds__(kRsThreads) void k_os_scatter(const uint32_t* __restrict__ keys_in,
                                                            const uint32_t* __restrict__ vals_in,
                                                            uint32_t* __restrict__ keys_out,
                                                            uint32_t* __restrict__ vals_out, int64_t count,
-                                                           int shift, int nbits,
-                                                           const uint32_t* __restrict__ ghist_pass,
+                                                           int pass, int total_bits,
+                                                           const uint32_t* __restrict__ ghist,
                                                            uint32_t* __restrict__ state_pass,
                                                            uint32_t* __restrict__ counter, uint32_t* __restrict__ err,
+                                                           uint32_t* __restrict__ vals_final,
                                                            const uint2* __restrict__ rect,
                                                            uint2* __restrict__ rect_out,
                                                            uint32_t* __restrict__ cnt_out) {
   constexpr int CHUNK = kRsThreads * ITEMS;
   constexpr int PER_WAVE = CHUNK / 4;
-  // rect != NULL (last pass): also gather each value's rectangle and tile
-  // count into the output order
+  const int passes = (total_bits + 7) / 8;
+  const int shift = 8 * pass, nbits = min(8, total_bits - 8 * pass);
+  const uint32_t* const ghist_pass = ghist + pass * 256;
+  int last_changing = 0;
+  bool trivial = false;
+  for (int q = 0; q < passes; ++q) {
+    const int qb = min(8, total_bits - 8 * q);
+    const bool t = __syncthreads_or(static_cast<uint32_t>(threadIdx.x) <= ((1u << qb) - 1u) &&
+                                    static_cast<int64_t>(ghist[q * 256 + threadIdx.x]) == count);
+    if (!t) last_changing = q;
+    if (q == pass) trivial = t;
+  }
+  if (pass > last_changing) return;   // the order is final already
+  const bool terminal = pass == last_changing;
   auto emit = [&](int64_t g, uint32_t key, uint32_t val) {
-    keys_out[g] = key;
-    vals_out[g] = val;
-    if (rect) {
-      const uint2 rc = rect[val];
-      rect_out[g] = rc;
-      cnt_out[g] = rect_count(rc);
+    if (terminal) {
+      vals_final[g] = val;
+      if (rect) {
+        const uint2 rc = rect[val];
+        rect_out[g] = rc;
+        cnt_out[g] = rect_count(rc);
+      }
+    } else {
+      keys_out[g] = key;
+      vals_out[g] = val;
     }
   };
   // every key has the same digit: the pass keeps the order (a copy)
-  if (__syncthreads_or(static_cast<uint32_t>(threadIdx.x) <= ((1u << nbits) - 1u) &&
-                       static_cast<int64_t>(ghist_pass[threadIdx.x]) == count)) {
+  if (trivial) {
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * CHUNK + threadIdx.x;
          i < min(count, static_cast<int64_t>(blockIdx.x + 1) * CHUNK); i += kRsThreads)
       emit(i, keys_in[i], vals_in[i]);
@@ -583,17 +605,18 @@ static size_t os_state_words(int64_t count, int items, int passes) {
                                                                           kRsThreads * items));
 }
 
-// Sorts `count` pairs over key bits [0, total_bits).  Input in (ka, va); the
-// result ends in (ka, va) if the pass count is even, else in (kb, vb).
+// Sorts `count` pairs over key bits [0, total_bits).  Input in (ka, va),
+// which the passes use as ping-pong buffers with (kb, vb); the values in
+// sorted order end in vals_final (with rect: each value's rectangle and tile
+// count in rect_out, cnt_out).
 // w.ghist must be zero on entry (k_depth_keys clears both sorts' counts).
 template <int ITEMS>
 static gs_status onesweep_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int64_t count,
-                                     int total_bits, OsWs w, hipStream_t s, int* passes_out,
+                                     int total_bits, OsWs w, hipStream_t s, uint32_t* vals_final,
                                      const uint2* rect = nullptr, uint2* rect_out = nullptr,
                                      uint32_t* cnt_out = nullptr) {
   constexpr int CHUNK = kRsThreads * ITEMS;
   const int passes = (total_bits + 7) / 8;
-  *passes_out = 0;
   if (count <= 0) return GS_OK;
   const int nblocks = static_cast<int>(ceil_div(count, CHUNK));
   gs_status st;
@@ -602,17 +625,13 @@ static gs_status onesweep_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, u
                                             static_cast<int64_t>(os_state_words(count, ITEMS, passes)), w.counters);
   if ((st = check_launch("k_os_hist")) != GS_OK) return st;
   for (int p = 0; p < passes; ++p) {
-    const int nbits = std::min(8, total_bits - 8 * p);
-    const bool last = p + 1 == passes;
-    k_os_scatter<ITEMS><<<nblocks, kRsThreads, 0, s>>>(ka, va, kb, vb, count, 8 * p, nbits, w.ghist + p * 256,
+    k_os_scatter<ITEMS><<<nblocks, kRsThreads, 0, s>>>(ka, va, kb, vb, count, p, total_bits, w.ghist,
                                                        w.state + static_cast<size_t>(p) * nblocks * 256,
-                                                       w.counters + p, w.err, last ? rect : nullptr,
-                                                       last ? rect_out : nullptr, last ? cnt_out : nullptr);
+                                                       w.counters + p, w.err, vals_final, rect, rect_out, cnt_out);
     if ((st = check_launch("k_os_scatter")) != GS_OK) return st;
     uint32_t* t = ka; ka = kb; kb = t;
     t = va; va = vb; vb = t;
   }
-  *passes_out = passes;
   return GS_OK;
 }
 
@@ -1055,7 +1074,7 @@ static int bits_for(int64_t values) {  // bits needed to represent 0..values-1
 }
 
 struct BinWs {
-  uint32_t *dk0, *dv0, *dk1, *dv1, *cnt, *offs;
+  uint32_t *dk0, *dv0, *dk1, *dv1, *order, *cnt, *offs;
   uint2 *rect, *rect_rank;
   uint32_t *ek0, *ek1, *ev1;
   uint32_t* hist;
@@ -1073,6 +1092,7 @@ static BinWs carve_bin(void* ws, int64_t n, int64_t cap, int tiles_x, int tiles_
   const size_t N = static_cast<size_t>(n > 0 ? n : 1), C = static_cast<size_t>(cap > 0 ? cap : 1);
   b.dk0 = c.take<uint32_t>(N); b.dv0 = c.take<uint32_t>(N);
   b.dk1 = c.take<uint32_t>(N); b.dv1 = c.take<uint32_t>(N);
+  b.order = c.take<uint32_t>(N);
   b.cnt = c.take<uint32_t>(N); b.offs = c.take<uint32_t>(N);
   b.rect = c.take<uint2>(N); b.rect_rank = c.take<uint2>(N);
   b.ek0 = c.take<uint32_t>(C); b.ek1 = c.take<uint32_t>(C); b.ev1 = c.take<uint32_t>(C);
@@ -1128,12 +1148,11 @@ gs_status run_bin_sort(int64_t n64, const gs_projected& proj, const DevCam& cam,
     k_depth_keys<<<g, 256, 0, s>>>(n, proj.depth, reinterpret_cast<const float4*>(proj.records), proj.radius,
                                    cam.tiles_x, cam.tiles_y, b.dk0, b.dv0, b.rect, b.zero, kOsMaxPasses * 256 + 4);
     if ((st = check_launch("k_depth_keys")) != GS_OK) return st;
-    int passes = 0;
-    // the last pass also gathers each rank's rectangle and tile count
-    if ((st = onesweep_sort_pairs<kOsItemsN>(b.dk0, b.dv0, b.dk1, b.dv1, n, 32, b.os, s, &passes, b.rect,
+    // the terminal pass also gathers each rank's rectangle and tile count
+    if ((st = onesweep_sort_pairs<kOsItemsN>(b.dk0, b.dv0, b.dk1, b.dv1, n, 32, b.os, s, b.order, b.rect,
                                              b.rect_rank, b.cnt)) != GS_OK)
       return st;
-    const uint32_t* order = (passes % 2 == 0) ? b.dv0 : b.dv1;
+    const uint32_t* order = b.order;
     unsigned long long rb[2] = {0ull, 0ull};
     if (b.table) {
       // direct emission, sized on the device from the scanned total: no host

@@ -22,6 +22,8 @@ differently are located, flagged and counted rather than hidden:
                   the oracle); tiles whose lists differ are validated and left
                   out, the rest meet the tolerances above
 """
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -513,6 +515,44 @@ def test_bin_sort_many_tiles_per_group(gs):
     assert np.array_equal(pl[:k].cpu().numpy().view(np.uint32), o_pl), "point_list"
     assert np.array_equal(ranges.cpu().numpy().view(np.uint32), o_ranges), "ranges"
     say(f"  K={k}, {sum(wide)} of {len(wide)} aligned rank groups wide, bit-exact")
+
+
+def _depth_case_scene(kind, n=20000, seed=95):
+    """Scenes whose depth keys exercise the depth sort's digit structure
+    (camera at distance 3 on the z axis: depth = z + 3)."""
+    sc = scenes.uniform_scene(n, seed, log_scale_mean=-4.0, log_scale_std=0.3, sh_degree=1)
+    means = sc.means.copy()
+    if kind == "quantised":    # depths 2, 2.5, 3, 3.5: bytes 0-1 and 3 shared
+        means[2] = np.float32(-1.0) + np.float32(0.5) * (np.arange(n) % 4).astype(np.float32)
+    elif kind == "equal":      # one depth: every digit shared
+        means[2] = np.float32(0.0)
+    return dataclasses.replace(sc, means=means)
+
+
+@pytest.mark.parametrize("kind", ["straddle", "quantised", "equal"])
+def test_bin_sort_depth_digit_cases(gs, kind):
+    """The depth sort skips passes whose digit every key shares and finishes
+    in the last pass that reorders: top byte varying (straddle: depths across
+    2.0, all four passes), only byte 2 varying (quantised: two copies, then the
+    last reordering pass), no byte varying (equal: one copy).  The lists must
+    be the oracle's bit for bit."""
+    scene = _depth_case_scene(kind)
+    cam = scenes.front_camera(800, 800, 2.5 if kind == "straddle" else 3.0, 60.0)
+    say(f"[bin/sort depth digits] {kind} n={scene.n}")
+    p, g, out = gpu_project(gs, scene, cam)
+    h = proj_host(out)
+    live = h["radius"] > 0
+    bits = h["depth"].astype(np.float32).view(np.uint32)[live]
+    varying = [len(np.unique((bits >> (8 * q)) & 255)) > 1 for q in range(4)]
+    expect = {"straddle": varying[3], "quantised": varying == [False, False, True, False],
+              "equal": not any(varying)}[kind]
+    assert expect, (kind, varying)
+    k, pl, ranges = gpu_bin_sort(gs, scene.n, out, cam)
+    o_pl, o_ranges, _, _ = oracle.bin_sort(h["u"], h["v"], h["radius"], h["depth"], cam.width, cam.height)
+    assert k == len(o_pl) and k > 0
+    assert np.array_equal(pl[:k].cpu().numpy().view(np.uint32), o_pl), "point_list"
+    assert np.array_equal(ranges.cpu().numpy().view(np.uint32), o_ranges), "ranges"
+    say(f"  K={k}, varying digits {varying}, bit-exact")
 
 
 def test_bin_sort_async_matches_sync(gs):
