@@ -772,8 +772,10 @@ static size_t emit_dyn_lds(int tiles_x, int tiles_y) {
   const size_t nt = static_cast<size_t>(tiles_x) * tiles_y;
   return 32 * static_cast<size_t>(tiles_x + tiles_y) + 4 * nt + 2 * ((nt + 1) / 2 * 2);
 }
+constexpr int kStartRegs = 16;   // tiles per thread of k_tile_starts (1024 threads)
 static bool direct_ok(int tiles_x, int tiles_y) {
   return 4 * static_cast<size_t>(tiles_x + 1) * (tiles_y + 1) <= kLdsBudget &&
+         static_cast<size_t>(tiles_x) * tiles_y <= static_cast<size_t>(kStartRegs) * 1024 &&
          emit_dyn_lds(tiles_x, tiles_y) + kEmitStaticLds <= kLdsBudget;
 }
 static int64_t direct_max_chunks(int64_t cap) {
@@ -872,10 +874,16 @@ __global__ __launch_bounds__(1024) void k_tile_starts(int ntiles, const uint32_t
                                                       unsigned long long capacity) {
   __shared__ unsigned long long s_w[16];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int per = (ntiles + 1023) / 1024;
+  const int per = (ntiles + 1023) / 1024;   // at most kStartRegs: direct_ok keeps ntiles below 16384
   const int t0 = min(ntiles, tid * per), t1 = min(ntiles, t0 + per);
+  // the thread's totals, read once with all loads in flight
+  uint32_t v[kStartRegs];
   unsigned long long sum = 0;
-  for (int t = t0; t < t1; ++t) sum += total[t];
+#pragma unroll
+  for (int k = 0; k < kStartRegs; ++k) {
+    v[k] = t0 + k < t1 ? total[t0 + k] : 0u;
+    sum += v[k];
+  }
   unsigned long long incl = sum;
   for (int d = 1; d < 64; d <<= 1) {
     const unsigned long long v = __shfl_up(incl, d, 64);
@@ -890,11 +898,15 @@ __global__ __launch_bounds__(1024) void k_tile_starts(int ntiles, const uint32_t
   }
   // positions are 32-bit: a total beyond that does not fit either
   const bool fits = all <= min(capacity, 0xFFFFFFFFull);
-  for (int t = t0; t < t1; ++t) {
-    const uint32_t v = total[t];
-    start[t] = static_cast<uint32_t>(run);
-    ranges[t] = fits ? make_uint2(static_cast<uint32_t>(run), static_cast<uint32_t>(run + v)) : make_uint2(0u, 0u);
-    run += v;
+#pragma unroll
+  for (int k = 0; k < kStartRegs; ++k) {
+    const int t = t0 + k;
+    if (t < t1) {
+      start[t] = static_cast<uint32_t>(run);
+      ranges[t] = fits ? make_uint2(static_cast<uint32_t>(run), static_cast<uint32_t>(run + v[k]))
+                       : make_uint2(0u, 0u);
+    }
+    run += v[k];
   }
 }
 

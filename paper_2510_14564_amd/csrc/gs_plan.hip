@@ -22,6 +22,7 @@
 namespace gs {
 
 constexpr int kPlanThreads = 1024;
+constexpr int kPlanRegs = 16;   // tiles per thread held in registers by k_batch_plan
 constexpr int kHeavyCap = 1024;    // at most this many heavy tiles are ordered
 
 // Plan workspace in int32 values for ntiles tiles.
@@ -135,15 +136,37 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(int ntiles, const u
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int per = (ntiles + kPlanThreads - 1) / kPlanThreads;
   const int t0 = min(ntiles, tid * per), t1 = min(ntiles, t0 + per);
-  auto batches_of = [&](int t) -> uint32_t {
-    const uint32_t len = min(ranges[t].y - ranges[t].x, work[t]);
-    return static_cast<int>(work[t]) <= light_max ? 0u : (len + 255u) / 256u;
+  auto batches_of = [&](uint2 rg, uint32_t wk) -> uint32_t {
+    const uint32_t len = min(rg.y - rg.x, wk);
+    return static_cast<int>(wk) <= light_max ? 0u : (len + 255u) / 256u;
   };
-  auto is_light = [&](int t) -> bool { return work[t] > 0u && static_cast<int>(work[t]) <= light_max; };
+  auto is_light = [&](uint32_t wk) -> bool { return wk > 0u && static_cast<int>(wk) <= light_max; };
+  // up to kPlanRegs tiles per thread are read once, all loads in flight
+  // together; larger grids read them in the loops
+  const bool regs = per <= kPlanRegs;
+  uint32_t nbr[kPlanRegs];
+  bool lgt[kPlanRegs];
   uint32_t c[2] = {0u, 0u};
-  for (int t = t0; t < t1; ++t) {
-    c[0] += batches_of(t);
-    c[1] += is_light(t) ? 1u : 0u;
+  if (regs) {
+    uint2 rg[kPlanRegs];
+    uint32_t wk[kPlanRegs];
+#pragma unroll
+    for (int k = 0; k < kPlanRegs; ++k) {
+      rg[k] = t0 + k < t1 ? ranges[t0 + k] : make_uint2(0u, 0u);
+      wk[k] = t0 + k < t1 ? work[t0 + k] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < kPlanRegs; ++k) {
+      nbr[k] = t0 + k < t1 ? batches_of(rg[k], wk[k]) : 0u;
+      lgt[k] = t0 + k < t1 && is_light(wk[k]);
+      c[0] += nbr[k];
+      c[1] += lgt[k] ? 1u : 0u;
+    }
+  } else {
+    for (int t = t0; t < t1; ++t) {
+      c[0] += batches_of(ranges[t], work[t]);
+      c[1] += is_light(work[t]) ? 1u : 0u;
+    }
   }
   uint32_t ex[2], tot[2];
 #pragma unroll
@@ -168,14 +191,20 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(int ntiles, const u
     ex[k] += before;
     tot[k] = all;
   }
-  for (int t = t0; t < t1; ++t) {
-    const uint32_t nb = batches_of(t);
+  auto put = [&](int t, uint32_t nb, bool lt) {
     for (uint32_t j = 0; j < nb; ++j) {
       items[kPlanHeader + 2 * (ex[0] + j)] = t;
       items[kPlanHeader + 2 * (ex[0] + j) + 1] = static_cast<int32_t>(j);
     }
     ex[0] += nb;
-    if (light && is_light(t)) light[kPlanHeader + ex[1]++] = t;
+    if (light && lt) light[kPlanHeader + ex[1]++] = t;
+  };
+  if (regs) {
+#pragma unroll
+    for (int k = 0; k < kPlanRegs; ++k)
+      if (t0 + k < t1) put(t0 + k, nbr[k], lgt[k]);
+  } else {
+    for (int t = t0; t < t1; ++t) put(t, batches_of(ranges[t], work[t]), is_light(work[t]));
   }
   if (tid == 0) {
     items[0] = static_cast<int32_t>(tot[0]);
