@@ -11,12 +11,33 @@ __global__ __launch_bounds__(256) void k_l1_partial(const float* __restrict__ im
                                                     int64_t count, float inv_count, float* __restrict__ grad,
                                                     float* __restrict__ partial) {
   __shared__ float red[256];
+  auto sgn = [&](float d) { return d > 0.0f ? inv_count : (d < 0.0f ? -inv_count : 0.0f); };
   float s = 0.0f;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < count;
-       i += static_cast<int64_t>(gridDim.x) * 256) {
+  const int64_t t0 = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * 256;
+  // 16-byte accesses when all three arrays allow them (four values per step),
+  // then the remaining count % 4 values
+  const bool vec = ((reinterpret_cast<uintptr_t>(img) | reinterpret_cast<uintptr_t>(tgt) |
+                     reinterpret_cast<uintptr_t>(grad)) & 15u) == 0;
+  int64_t done = 0;
+  if (vec) {
+    const int64_t n4 = count / 4;
+    for (int64_t i = t0; i < n4; i += stride) {
+      const float4 a = reinterpret_cast<const float4*>(img)[i];
+      const float4 b = reinterpret_cast<const float4*>(tgt)[i];
+      const float d0 = a.x - b.x, d1 = a.y - b.y, d2 = a.z - b.z, d3 = a.w - b.w;
+      s += fabsf(d0);
+      s += fabsf(d1);
+      s += fabsf(d2);
+      s += fabsf(d3);
+      if (grad) reinterpret_cast<float4*>(grad)[i] = make_float4(sgn(d0), sgn(d1), sgn(d2), sgn(d3));
+    }
+    done = 4 * n4;
+  }
+  for (int64_t i = done + t0; i < count; i += stride) {
     const float d = img[i] - tgt[i];
     s += fabsf(d);
-    if (grad) grad[i] = d > 0.0f ? inv_count : (d < 0.0f ? -inv_count : 0.0f);
+    if (grad) grad[i] = sgn(d);
   }
   red[threadIdx.x] = s;
   __syncthreads();
