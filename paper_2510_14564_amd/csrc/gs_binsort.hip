@@ -782,18 +782,30 @@ static int64_t direct_max_chunks(int64_t cap) {
   return std::max<int64_t>(1, std::min<int64_t>(kDirectChunks, ceil_div(std::max<int64_t>(cap, 1), kDirectMinEntries)));
 }
 
+// Inclusive prefix sum over the 64 lanes on DPP (row shifts, then the row
+// broadcasts of lanes 15 and 31): no LDS round trips.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int dpp_i32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROW_MASK, 0xF, true);
+}
+__device__ __forceinline__ int wave_incl_scan(int x) {
+  x += dpp_i32<0x111, 0xF>(x);   // row_shr:1
+  x += dpp_i32<0x112, 0xF>(x);   // row_shr:2
+  x += dpp_i32<0x114, 0xF>(x);   // row_shr:4
+  x += dpp_i32<0x118, 0xF>(x);   // row_shr:8
+  x += dpp_i32<0x142, 0xA>(x);   // row_bcast:15 into rows 1, 3
+  x += dpp_i32<0x143, 0xC>(x);   // row_bcast:31 into rows 2, 3
+  return x;
+}
+
 // In-place inclusive prefix sums of `len` ints at p[0], p[stride], ... by one wave.
 __device__ __forceinline__ void wave_prefix_lds(int* p, int len, int stride, int lane) {
   int carry = 0;
   for (int b = 0; b < len; b += 64) {
     const int i = b + lane;
-    int v = i < len ? p[i * stride] : 0;
-    for (int d = 1; d < 64; d <<= 1) {
-      const int t = __shfl_up(v, d, 64);
-      if (lane >= d) v += t;
-    }
+    const int v = wave_incl_scan(i < len ? p[i * stride] : 0);
     if (i < len) p[i * stride] = v + carry;
-    carry += __shfl(v, 63, 64);
+    carry += __builtin_amdgcn_readlane(v, 63);
   }
 }
 
