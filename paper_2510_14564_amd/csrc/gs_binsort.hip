@@ -42,21 +42,34 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t digit, int nbits, bool 
 // Exclusive prefix sum of uint32 values: per-block sums, one-block scan of the
 // sums (which also yields the 64-bit total), then per-block scan + offset.
 
+// Inclusive prefix sum over the 64 lanes on DPP (row shifts, then the row
+// broadcasts of lanes 15 and 31): no LDS round trips.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int dpp_i32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROW_MASK, 0xF, true);
+}
+__device__ __forceinline__ int wave_incl_scan(int x) {
+  x += dpp_i32<0x111, 0xF>(x);   // row_shr:1
+  x += dpp_i32<0x112, 0xF>(x);   // row_shr:2
+  x += dpp_i32<0x114, 0xF>(x);   // row_shr:4
+  x += dpp_i32<0x118, 0xF>(x);   // row_shr:8
+  x += dpp_i32<0x142, 0xA>(x);   // row_bcast:15 into rows 1, 3
+  x += dpp_i32<0x143, 0xC>(x);   // row_bcast:31 into rows 2, 3
+  return x;
+}
+
+// Exclusive prefix over a 256-thread workgroup: wave scans on DPP, then the
+// four wave totals through LDS (lds >= 4 words; free again on return).
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* lds, uint32_t& total) {
-  // 256 threads, lds >= 256 words
-  const int tid = threadIdx.x;
-  lds[tid] = v;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t incl = static_cast<uint32_t>(wave_incl_scan(static_cast<int>(v)));
+  if (lane == 63) lds[wave] = incl;
   __syncthreads();
-  for (int off = 1; off < 256; off <<= 1) {
-    const uint32_t t = (tid >= off) ? lds[tid - off] : 0u;
-    __syncthreads();
-    lds[tid] += t;
-    __syncthreads();
-  }
-  total = lds[255];
-  const uint32_t incl = lds[tid];
+  const uint32_t w0 = lds[0], w1 = lds[1], w2 = lds[2], w3 = lds[3];
+  const uint32_t before = (wave > 0 ? w0 : 0u) + (wave > 1 ? w1 : 0u) + (wave > 2 ? w2 : 0u);
+  total = ((w0 + w1) + w2) + w3;
   __syncthreads();
-  return incl - v;
+  return before + incl - v;
 }
 
 __global__ __launch_bounds__(256) void k_scan_sums(const uint32_t* __restrict__ in, int64_t n,
@@ -780,22 +793,6 @@ static bool direct_ok(int tiles_x, int tiles_y) {
 }
 static int64_t direct_max_chunks(int64_t cap) {
   return std::max<int64_t>(1, std::min<int64_t>(kDirectChunks, ceil_div(std::max<int64_t>(cap, 1), kDirectMinEntries)));
-}
-
-// Inclusive prefix sum over the 64 lanes on DPP (row shifts, then the row
-// broadcasts of lanes 15 and 31): no LDS round trips.
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ int dpp_i32(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROW_MASK, 0xF, true);
-}
-__device__ __forceinline__ int wave_incl_scan(int x) {
-  x += dpp_i32<0x111, 0xF>(x);   // row_shr:1
-  x += dpp_i32<0x112, 0xF>(x);   // row_shr:2
-  x += dpp_i32<0x114, 0xF>(x);   // row_shr:4
-  x += dpp_i32<0x118, 0xF>(x);   // row_shr:8
-  x += dpp_i32<0x142, 0xA>(x);   // row_bcast:15 into rows 1, 3
-  x += dpp_i32<0x143, 0xC>(x);   // row_bcast:31 into rows 2, 3
-  return x;
 }
 
 // In-place inclusive prefix sums of `len` ints at p[0], p[stride], ... by one wave.
