@@ -81,13 +81,11 @@ __global__ __launch_bounds__(256) void k_scan_sums(const uint32_t* __restrict__ 
     const int64_t idx = base + j * 256 + threadIdx.x;
     if (idx < n) s += in[idx];
   }
-  red[threadIdx.x] = s;
+  // wave totals (lane 63 of the DPP scan), then the four in a fixed order
+  const uint32_t w = static_cast<uint32_t>(__builtin_amdgcn_readlane(wave_incl_scan(static_cast<int>(s)), 63));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = w;
   __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) sums[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) sums[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
 // Chunk bounds of the direct emission, derived from the scanned counts (see

@@ -7,10 +7,31 @@ namespace gs {
 
 constexpr int kL1Blocks = GS_L1_PARTIALS;
 
+// Sum over a 256-thread workgroup in a fixed order: DPP within each 16-lane
+// row, the rows of a wave through readlane, then the four waves via LDS
+// (red >= 4 floats).  The result is valid in thread 0.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float block_sum256(float v, float* red) {
+  v += dpp_f32<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_f32<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp_f32<0x124>(v);   // row_ror:4
+  v += dpp_f32<0x128>(v);   // row_ror:8
+  // readlane moves 32-bit words: the float's bits, not its value
+  auto lane_f = [&](int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); };
+  const float w = (lane_f(0) + lane_f(16)) + (lane_f(32) + lane_f(48));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = w;
+  __syncthreads();
+  return ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+
 __global__ __launch_bounds__(256) void k_l1_partial(const float* __restrict__ img, const float* __restrict__ tgt,
                                                     int64_t count, float inv_count, float* __restrict__ grad,
                                                     float* __restrict__ partial) {
-  __shared__ float red[256];
+  __shared__ float red[4];
   auto sgn = [&](float d) { return d > 0.0f ? inv_count : (d < 0.0f ? -inv_count : 0.0f); };
   float s = 0.0f;
   const int64_t t0 = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
@@ -39,27 +60,17 @@ __global__ __launch_bounds__(256) void k_l1_partial(const float* __restrict__ im
     s += fabsf(d);
     if (grad) grad[i] = sgn(d);
   }
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+  const float total = block_sum256(s, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = total;
 }
 
 __global__ __launch_bounds__(256) void k_l1_final(const float* __restrict__ partial, int nb, float inv_count,
                                                   float* __restrict__ loss) {
-  __shared__ float red[256];
+  __shared__ float red[4];
   float s = 0.0f;
   for (int i = threadIdx.x; i < nb; i += 256) s += partial[i];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) *loss = red[0] * inv_count;
+  const float total = block_sum256(s, red);
+  if (threadIdx.x == 0) *loss = total * inv_count;
 }
 
 gs_status launch_l1(const float* img, const float* target, int64_t count, float* loss, float* grad,
