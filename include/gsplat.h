@@ -42,7 +42,7 @@ typedef enum {
 
 #define GS_TILE 16        /* tile edge in pixels: 16x16 pixel blocks share one list (Sec. IV-C.1) */
 #define GS_REC_FLOATS 12  /* floats per projected record (48 bytes, 16-byte aligned) */
-#define GS_G2D 9          /* per-Gaussian 2D gradients: u v Sxx Sxy Syy o r g b (see gs_render_bwd) */
+#define GS_G2D 9          /* per-Gaussian 2D gradients: u v Sxx Sxy Syy o r g b (see gs_render_bwd_2d) */
 #define GS_MLP_LATENT 16  /* learned-colour latent width */
 #define GS_MLP_HIDDEN 64
 #define GS_MLP_PARAMS 6467 /* 64*32 + 64 + 64*64 + 64 + 3*64 + 3 */
@@ -95,7 +95,7 @@ typedef struct {
  *     Sec. V).  (ex, ey) are the half-extents of a box around (u, v) outside
  *     which alpha < 1/255 everywhere (with a small safety margin); the
  *     compositing kernels use it to skip whole waves of pixels.
- *   depth[n]: camera-space t_z (the sort key, Sec. II-A "sorted by depth").
+ *   depth[n]: camera-space t_z (the sort key: Sec. II-A blends in depth order).
  *   radius[n]: ceil(3 sqrt(lambda_max(Sigma'))) pixels, 0 when culled.
  *   tiles_touched[n]: number of 16x16 tiles met by the square of half-width
  *     radius around (u, v), 0 when culled or off-screen. */
@@ -141,8 +141,8 @@ gs_status gs_project(const gs_gaussians* g, const gs_camera* cam, gs_projected* 
  * (tile, Gaussian) pairs.  Host-only; never touches the device. */
 gs_status gs_bin_sort_workspace(int64_t n, int64_t capacity, const gs_camera* cam, size_t* bytes);
 
-/* Tile binning and depth sort (Sec. II-A "sorted by depth", Sec. IV-C.1 16x16
- * tiles).  Every Gaussian emits one entry per tile its square meets; entries
+/* Tile binning and depth sort (Sec. II-A, front-to-back blending order;
+ * Sec. IV-C.1, 16x16 tiles).  Every Gaussian emits one entry per tile its square meets; entries
  * are ordered by (tile, FP32 bit pattern of depth, Gaussian index), a total
  * order, so the result is unique and bit-reproducible.
  *   point_list[capacity]: Gaussian index of each entry, in that order.
@@ -165,7 +165,7 @@ gs_status gs_bin_sort(int64_t n, const gs_projected* proj, const gs_camera* cam,
  * otherwise they are undefined, no out-of-bounds access happens, and the
  * caller grows the buffers and redoes the frame.  Until it knows K the caller
  * passes `capacity` as k to gs_render_ckpt_floats, gs_render_fwd,
- * gs_render_bwd_workspace and gs_render_bwd (an upper bound serves every
+ * gs_render_bwd_workspace, gs_render_bwd and their _2d forms (an upper bound serves every
  * layout and launch there).  Only for frames whose per-chunk tables fit in
  * LDS (tiles_x + 1)(tiles_y + 1) * 4 <= 64 KiB and the emission's tables
  * too; larger frames return GS_ERR_UNSUPPORTED before any device work.
@@ -219,37 +219,75 @@ gs_status gs_render_count(int64_t n, const gs_projected* proj, const uint32_t* p
 /* Floats of the transmittance checkpoint buffer for K entries. Host-only. */
 gs_status gs_render_ckpt_floats(int64_t k, const gs_camera* cam, size_t* floats);
 
-/* Workspace bytes for gs_render_bwd (depends on n and K). Host-only. */
-gs_status gs_render_bwd_workspace(int64_t n, int64_t k, const gs_camera* cam, int32_t deterministic, size_t* bytes);
+/* Per-Gaussian statistics that densification reads (the adaptive density
+ * control of 3DGS that Sec. III builds on), accumulated by gs_render_bwd over
+ * the views of an interval: grad_norm_sum[i] += |(dL/du, dL/dv)| of the view
+ * (pixel units) and visible_count[i] += 1 for every view in which Gaussian i
+ * meets at least one tile.  Device arrays [n], added to (never cleared by the
+ * library). */
+typedef struct {
+  float* grad_norm_sum;
+  uint32_t* visible_count;
+} gs_densify_stats;
 
-/* Backward of the compositing: exact derivative of the forward above with its
- * skip/stop decisions held fixed.  Each pixel's list is walked back to front
- * from its n_contrib: the transmittance before each entry is recovered by
- * division from the forward's value at the end of the entry's 256-entry batch
- * (t_ckpt, or final_T for the last batch) -- never stored per pair -- and the
- * light behind it is accumulated on the way.  Inputs: the forward's final_T,
- * n_contrib and t_ckpt, and dL_dimage[3][H][W].  Output g2d[9][n] per Gaussian,
- * overwritten: dL/d(u, v, a, b, c, opacity, r, g, b) where Sigma' = [[a, b],
- * [b, c]] is the 2D covariance whose inverse is the record's conic (b counted
- * in both off-diagonal places).  Each pixel's conic gradient is carried to
- * Sigma' before the sum over pixels, which stays well conditioned where the
- * conic is nearly singular (elongated footprints).  deterministic = 1 writes
- * one partial per (tile, Gaussian) entry and sums each Gaussian's partials in
- * the row-major order of its tile rectangle: no atomics, the same bits on
- * every run for a given schedule (its workspace holds 36 bytes per entry);
- * 0 adds the partials with device atomics (summation order varies).  ws as sized by gs_render_bwd_workspace (holds the
- * backward's tile plan).  schedule as for gs_render_fwd; BALANCED plans from
- * the work counts the forward left in t_ckpt. */
-gs_status gs_render_bwd(int64_t n, const gs_projected* proj, const uint32_t* point_list, const uint32_t* ranges,
-                        int64_t k, const gs_camera* cam, const float* final_T, const uint32_t* n_contrib,
-                        const float* t_ckpt, const float* dL_dimage, float* g2d, void* ws, size_t ws_bytes,
+/* Workspace bytes for gs_render_bwd (depends on the Gaussian set's n and
+ * colour mode, K and the camera). Host-only. */
+gs_status gs_render_bwd_workspace(const gs_gaussians* g, int64_t k, const gs_camera* cam, int32_t deterministic,
+                                  size_t* bytes);
+
+/* Backward of the whole splatting step (Sec. II-A, the blending sum and the
+ * EWA projection differentiated): dL/dimage -> gradients of the raw
+ * parameters, the compositing backward followed by the projection backward in
+ * one call.  The compositing part is the exact derivative of gs_render_fwd
+ * with its skip/stop decisions held fixed: each pixel's list is walked back to
+ * front from its n_contrib, the transmittance before each entry is recovered
+ * by division from the forward's value at the end of the entry's 256-entry
+ * batch (t_ckpt, or final_T for the last batch) -- never stored per pair --
+ * and the light behind it is accumulated on the way.  The projection part
+ * applies the chain rule through gs_project, recomputing its forward
+ * quantities from the parameters.
+ *   g, cam: the Gaussian set and camera of the forward; proj, point_list,
+ *     ranges, k, final_T, n_contrib, t_ckpt: that forward's outputs (k as
+ *     passed to gs_render_fwd); dL_dimage[3][H][W].
+ *   grad: every array overwritten, same layouts as g (colour_mode 0: means,
+ *     log_scales, quats, logits, sh; colour_mode 1: means, log_scales, quats,
+ *     logits, latents [n][16] FP32 and mlp [GS_MLP_PARAMS] FP32 summed over
+ *     Gaussians in a fixed order, plus the view direction's share of means).
+ *     Culled Gaussians get zero gradients.
+ *   stats: densification statistics to accumulate into, or NULL.
+ *   deterministic = 1: no atomics, one partial per (tile, Gaussian) entry
+ *     summed per Gaussian in the row-major order of its tile rectangle: the
+ *     same bits on every run for a given schedule; 0: device atomics.
+ *   schedule: as for gs_render_fwd (BALANCED plans from the work counts the
+ *     forward left in t_ckpt).
+ *   ws: gs_render_bwd_workspace bytes, 256-byte aligned, caller-owned.
+ * Errors: INVALID_ARG for NULL arrays, bad sizes, an unknown schedule or a
+ * small workspace (before any device work); HIP for launch failures. */
+gs_status gs_render_bwd(const gs_gaussians* g, const gs_camera* cam, const gs_projected* proj,
+                        const uint32_t* point_list, const uint32_t* ranges, int64_t k, const float* final_T,
+                        const uint32_t* n_contrib, const float* t_ckpt, const float* dL_dimage,
+                        gs_gaussians_grad* grad, gs_densify_stats* stats, void* ws, size_t ws_bytes,
                         int32_t deterministic, int32_t schedule, gs_stream stream);
 
-/* Backward of the projection: chain rule from g2d[9][n] to the raw parameters
- * (means, log_scales, quats, logits, sh) through the steps of gs_project
- * (Sec. II-A, the EWA projection and the SH colour).  The forward quantities
- * are recomputed from the parameters.  Culled Gaussians get zero gradients.
- * Every gradient array is overwritten.
+/* The compositing half of gs_render_bwd on its own, stopping at the
+ * per-Gaussian record gradients: g2d[9][n] (overwritten) =
+ * dL/d(u, v, a, b, c, opacity, r, g, b), where Sigma' = [[a, b], [b, c]] is
+ * the 2D covariance whose inverse is the record's conic (b counted in both
+ * off-diagonal places).  Each pixel's conic gradient is carried to Sigma'
+ * before the sum over pixels, which stays well conditioned where the conic is
+ * nearly singular (elongated footprints).  Same decisions, arguments and
+ * determinism as gs_render_bwd; ws as sized by gs_render_bwd_2d_workspace. */
+gs_status gs_render_bwd_2d_workspace(int64_t n, int64_t k, const gs_camera* cam, int32_t deterministic,
+                                     size_t* bytes);
+gs_status gs_render_bwd_2d(int64_t n, const gs_projected* proj, const uint32_t* point_list, const uint32_t* ranges,
+                           int64_t k, const gs_camera* cam, const float* final_T, const uint32_t* n_contrib,
+                           const float* t_ckpt, const float* dL_dimage, float* g2d, void* ws, size_t ws_bytes,
+                           int32_t deterministic, int32_t schedule, gs_stream stream);
+
+/* The projection half of gs_render_bwd on its own: chain rule from g2d[9][n]
+ * (the layout gs_render_bwd_2d writes) to the raw parameters through the
+ * steps of gs_project (Sec. II-A, the EWA projection and the SH colour).
+ * Every gradient array is overwritten; culled Gaussians get zero gradients.
  * colour_mode 1 (learned colour) instead fills grad->latents [n][16] FP32,
  * grad->mlp [GS_MLP_PARAMS] FP32 (summed over Gaussians in a fixed order) and
  * adds the view direction's share to grad->means; grad->sh may be NULL.  It
@@ -259,6 +297,38 @@ gs_status gs_render_bwd(int64_t n, const gs_projected* proj, const uint32_t* poi
 gs_status gs_project_bwd_workspace(const gs_gaussians* g, size_t* bytes);
 gs_status gs_project_bwd(const gs_gaussians* g, const gs_camera* cam, const gs_projected* proj, const float* g2d,
                          gs_gaussians_grad* grad, void* ws, size_t ws_bytes, gs_stream stream);
+
+/* ------------------------------------------------------- optimiser step
+ * Writable parameter arrays of a Gaussian set (same layouts as gs_gaussians);
+ * also used for the Adam moments, which have the parameters' shapes. */
+typedef struct {
+  float* means;
+  float* log_scales;
+  float* quats;
+  float* logits;
+  float* sh;
+} gs_param_arrays;
+
+/* Adam hyper-parameters of a Gaussian set: one learning rate per parameter
+ * group (the SH coefficients split into the degree-0 term and the rest),
+ * shared moments decay rates, epsilon, and the step number (from 1). */
+typedef struct {
+  float lr_means, lr_log_scales, lr_quats, lr_logits, lr_sh_dc, lr_sh_rest;
+  float beta1, beta2, eps;
+  int32_t step;
+} gs_adam_config;
+
+/* One Adam step (bias-corrected) over every parameter array of a Gaussian set
+ * in one launch -- the optimiser step that follows gs_render_bwd in training:
+ *   m = b1 m + (1 - b1) g,  v = b2 v + (1 - b2) g^2,
+ *   p -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps)
+ * with the group's lr.  params, m and v are updated in place; grad as written
+ * by gs_render_bwd (colour_mode 0 fields).  n Gaussians, SH degree in 0..3.
+ * Errors: INVALID_ARG for NULL arrays, step < 1, betas outside [0, 1),
+ * eps <= 0 or a non-finite learning rate. */
+gs_status gs_adam_gaussians(int64_t n, int32_t sh_degree, const gs_param_arrays* params, const gs_gaussians_grad* grad,
+                            const gs_param_arrays* m, const gs_param_arrays* v, const gs_adam_config* cfg,
+                            gs_stream stream);
 
 /* ---------------------------------------------------------- learned colour
  * Optional decoder that replaces the SH colour read (not part of the paper):
@@ -322,6 +392,19 @@ gs_status gs_adam_step(int64_t n, float* param, const float* grad, float* m, flo
 #define GS_L1_PARTIALS 1024
 gs_status gs_l1_loss(const float* img, const float* target, int64_t count, float* loss, float* grad,
                      float* partials, gs_stream stream);
+
+/* ------------------------------------------------------------ measurement
+ * Kernel timer (for benchmarks; not needed by the path).  After
+ * gs_kernel_timer_start, every kernel the library launches from the calling
+ * thread is bracketed by two HIP events recorded on its launch stream, until
+ * gs_kernel_timer_stop, which waits for those events and writes one line per
+ * kernel name, "name launches total_ms", in first-launch order, into buf
+ * (size bytes, truncated and NUL-terminated; *needed = the full length + 1;
+ * buf may be NULL to query the length).  One timer per thread; the events add
+ * a few microseconds per launch.  Errors: INVALID_ARG when no timer (start:
+ * another timer) is running on the thread; HIP if an event failed. */
+gs_status gs_kernel_timer_start(void);
+gs_status gs_kernel_timer_stop(char* buf, size_t size, size_t* needed);
 
 #ifdef __cplusplus
 }

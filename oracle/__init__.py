@@ -149,29 +149,80 @@ def bin_sort(u, v, radius, depth_f32, W: int, H: int, tile_mask=None):
     return pl[:K], ranges, tt, off
 
 
-def render_fwd(rec, point_list, ranges, cam, margin: float = 1e-4, tile_mask=None):
+# near-threshold margins of the per-pixel walk: alpha vs 1/255 (relative),
+# T' vs 1e-4 (relative, base value; grows along the walk), o e^power vs 0.99
+MARGINS = (1e-5, 1e-4, 1e-5)
+
+
+def _margins(m):
+    m = np.asarray(m if m is not None else MARGINS, np.float64).reshape(-1)
+    if m.size == 1:
+        m = np.repeat(m, 3)
+    return np.ascontiguousarray(m[:3])
+
+
+def render_fwd(rec, point_list, ranges, cam, margins=None, tile_mask=None, flips=None, with_near=False):
     """Front-to-back compositing per pixel.  Returns image[3][H][W], final_T[H][W],
-    n_contrib[H][W] (int32) and per-pixel decision flags."""
+    n_contrib[H][W] (int32) and per-pixel decision flags (bit0 alpha near 1/255,
+    bit1 T' near 1e-4, bit2 o e^power near 0.99); with_near=True also the number
+    of near decisions per pixel.  flips[H][W] (uint8) takes the other branch of
+    the pixel's near decisions whose bits are set (walk order)."""
     W, H = cam.width, cam.height
     rec = _d(rec)
     pl = np.ascontiguousarray(point_list, np.uint32)
     rg = np.ascontiguousarray(ranges, np.uint32)
     bg = np.asarray(cam.bg, np.float32).astype(np.float64)
+    mg = _margins(margins)
     image = np.zeros((3, H, W))
     fT = np.zeros((H, W))
     nc = np.zeros((H, W), np.int32)
     fl = np.zeros((H, W), np.uint8)
+    nn = np.zeros((H, W), np.uint8)
     tm = None if tile_mask is None else np.ascontiguousarray(tile_mask, np.uint8)
+    fp = None if flips is None else np.ascontiguousarray(flips, np.uint8)
+    assert fp is None or fp.shape == (H, W)
     if not pl.size:
         pl = np.zeros(1, np.uint32)
-    _load().or_render_fwd(ctypes.c_int(W), ctypes.c_int(H), _p(rec), _p(pl),
-                          _p(rg), _p(bg), ctypes.c_double(margin), _p(tm), _p(image), _p(fT), _p(nc), _p(fl))
-    return image, fT, nc, fl
+    _load().or_render_fwd(ctypes.c_int(W), ctypes.c_int(H), _p(rec), _p(pl), _p(rg), _p(bg), _p(mg), _p(tm),
+                          _p(fp), _p(image), _p(fT), _p(nc), _p(fl), _p(nn))
+    return (image, fT, nc, fl, nn) if with_near else (image, fT, nc, fl)
 
 
-def render_bwd(rec, point_list, ranges, cam, dL_dimage, tile_mask=None, with_mass=False):
-    """Gradient of sum(dL_dimage * image) w.r.t. the records: g2d[n][9].
-    with_mass=True also returns the per-entry sum of |per-pair terms|."""
+def render_pixels(rec, point_list, ranges, cam, pix, flips, margins=None):
+    """The per-pixel walk for (pixel, flips) pairs: pix int64[m] = y W + x,
+    flips uint8[m].  Returns colour[m][3] (with background), final_T[m],
+    n_contrib[m], flags[m] and near counts[m]."""
+    W, H = cam.width, cam.height
+    rec = _d(rec)
+    pl = np.ascontiguousarray(point_list, np.uint32)
+    rg = np.ascontiguousarray(ranges, np.uint32)
+    bg = np.asarray(cam.bg, np.float32).astype(np.float64)
+    mg = _margins(margins)
+    pix = np.ascontiguousarray(pix, np.int64)
+    fp = np.ascontiguousarray(flips, np.uint8)
+    m = pix.shape[0]
+    assert fp.shape == (m,)
+    out = np.zeros((m, 3))
+    fT = np.zeros(m)
+    nc = np.zeros(m, np.int32)
+    fl = np.zeros(m, np.uint8)
+    nn = np.zeros(m, np.uint8)
+    if not pl.size:
+        pl = np.zeros(1, np.uint32)
+    rc = _load().or_render_pixels(ctypes.c_int(W), ctypes.c_int(H), _p(rec), _p(pl), _p(rg), _p(bg), _p(mg),
+                                  ctypes.c_int64(m), _p(pix), _p(fp), _p(out), _p(fT), _p(nc), _p(fl), _p(nn))
+    if rc != 0:
+        raise ValueError(f"or_render_pixels failed: {rc}")
+    return out, fT, nc, fl, nn
+
+
+def render_bwd(rec, point_list, ranges, cam, dL_dimage, tile_mask=None, with_mass=False, margins=None, flips=None):
+    """Gradient of sum(dL_dimage * image) w.r.t. the records: g2d[n][9] in
+    record order (u, v, A, B, C, o, r, g, b), the conic entries as they enter
+    the power (B once).  with_mass=True also returns the per-entry sum of
+    |per-pixel terms| (mass[n][9]) and the same sum for the per-pixel conic
+    gradient carried to the 2D covariance (cov_mass[n][3], (a, b, c)).
+    flips as for render_fwd."""
     W, H = cam.width, cam.height
     rec = _d(rec)
     n = rec.shape[0]
@@ -179,18 +230,23 @@ def render_bwd(rec, point_list, ranges, cam, dL_dimage, tile_mask=None, with_mas
     rg = np.ascontiguousarray(ranges, np.uint32)
     bg = np.asarray(cam.bg, np.float32).astype(np.float64)
     G = _d(dL_dimage)
+    mg = _margins(margins)
     g2d = np.zeros((n, 9))
     mass = np.zeros((n, 9)) if with_mass else None
+    cmass = np.zeros((n, 3)) if with_mass else None
     tm = None if tile_mask is None else np.ascontiguousarray(tile_mask, np.uint8)
+    fp = None if flips is None else np.ascontiguousarray(flips, np.uint8)
+    assert fp is None or fp.shape == (H, W)
     if not pl.size:
         pl = np.zeros(1, np.uint32)
     _load().or_render_bwd(ctypes.c_int(W), ctypes.c_int(H), ctypes.c_int64(n), _p(rec),
-                          _p(pl), _p(rg), _p(bg), _p(G), _p(tm), _p(g2d), _p(mass))
-    return (g2d, mass) if with_mass else g2d
+                          _p(pl), _p(rg), _p(bg), _p(G), _p(tm), _p(mg), _p(fp), _p(g2d), _p(mass), _p(cmass))
+    return (g2d, mass, cmass) if with_mass else g2d
 
 
 def project_bwd(scene, cam, g2d):
-    """Chain rule from record gradients g2d[n][9] to the raw parameters."""
+    """Chain rule from record gradients g2d[n][9] (record order, conic entries as
+    returned by render_bwd) to the raw parameters."""
     n = scene.n
     means, ls, q, lg, sh = (_d(scene.means), _d(scene.log_scales), _d(scene.quats),
                             _d(scene.logits), _d(scene.sh))
@@ -208,14 +264,14 @@ def project_bwd(scene, cam, g2d):
     return g
 
 
-def forward(scene, cam, margin: float = 1e-4):
+def forward(scene, cam, margins=None):
     """Whole forward in FP64: project -> bin/sort on the FP64 projection -> render.
     The sort key is the FP64 depth rounded to FP32 bits (the binning reading)."""
     pr = project(scene, cam)
     rec = pr["rec"]
     pl, ranges, tt, off = bin_sort(rec[:, 0], rec[:, 1], pr["radius"], pr["depth"].astype(np.float32),
                                    cam.width, cam.height)
-    image, fT, nc, fl = render_fwd(rec, pl, ranges, cam, margin)
+    image, fT, nc, fl = render_fwd(rec, pl, ranges, cam, margins)
     return dict(proj=pr, point_list=pl, ranges=ranges, image=image, final_T=fT, n_contrib=nc, pix_flags=fl)
 
 
@@ -277,3 +333,35 @@ def sh_colour(sh, deg, dirs):
     out = np.zeros((n, per, 3))
     _load().or_sh_colour(ctypes.c_int64(n), ctypes.c_int(deg), _p(sh), _p(dirs), ctypes.c_int(per), _p(out))
     return out
+
+
+# ------------------------------------------------------------ optimiser step
+
+def adam_step(p, g, m, v, lr, step: int, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-15):
+    """One bias-corrected Adam step in FP64 (Kingma & Ba, Algorithm 1), the
+    optimiser of 3DGS training: returns the new (p, m, v).
+      m = b1 m + (1 - b1) g;  v = b2 v + (1 - b2) g^2
+      p = p - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)
+    lr may be an array broadcast against p (one rate per parameter group)."""
+    p, g, m, v = (np.asarray(a, np.float64) for a in (p, g, m, v))
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    mh = m / (1.0 - beta1 ** step)
+    vh = v / (1.0 - beta2 ** step)
+    return p - np.asarray(lr, np.float64) * mh / (np.sqrt(vh) + eps), m, v
+
+
+def densify_stats(g2d_views, visible_views):
+    """Densification statistics over views: per Gaussian, the sum of
+    |(dL/du, dL/dv)| over the views that see it and the number of those
+    views.  g2d_views: record gradients [n][9] per view (u, v first);
+    visible_views: bool [n] per view."""
+    gsum = None
+    cnt = None
+    for g, vis in zip(g2d_views, visible_views):
+        g = np.asarray(g, np.float64)
+        vis = np.asarray(vis, bool)
+        term = np.where(vis, np.hypot(g[:, 0], g[:, 1]), 0.0)
+        gsum = term if gsum is None else gsum + term
+        cnt = vis.astype(np.int64) if cnt is None else cnt + vis
+    return gsum, cnt

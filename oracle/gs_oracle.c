@@ -436,13 +436,117 @@ int or_bin_sort(int64_t n, const double* u, const double* v, const int32_t* radi
  *   skipped; if T (1 - alpha) < 1e-4 the walk stops before blending (reading);
  *   otherwise C += c alpha T, T *= (1 - alpha), n_contrib = position + 1.
  *   out = C + T bg.
- * Pixel flags: bit0 alpha within rel. `margin` of 1/255, bit1 T' within rel.
- * `margin` of 1e-4, bit2 o e^power within rel. `margin` of 0.99.
- * tile_mask (optional): only tiles with a non-zero byte are rendered.
+ *
+ * Near-threshold decisions.  An FP32 evaluation of the same walk may take a
+ * decision the other way when the FP64 value lies close to its threshold.  The
+ * walk counts such "near" decisions in the order it meets them (k = 0, 1, ...)
+ * and sets a pixel flag for each kind:
+ *   bit0  alpha within a relative margins[0] of 1/255   (skip or blend),
+ *   bit1  T' within a relative mT of 1e-4               (stop or blend),
+ *   bit2  o e^power within a relative margins[2] of 0.99 (clamp or not).
+ * mT starts at margins[1] and grows by alpha/(1 - alpha) margins[0] + 2^-22
+ * for every blended entry (margins[0]: clamped entries add 1e-6 instead):
+ * the relative error that a product of (1 - alpha) factors carries when each
+ * alpha is known to margins[0] relative and each product is rounded once.
+ * Bit k of `flips` (a per-pixel mask; 0 = none) makes the walk take the other
+ * branch of near decision k; with flips = 0 this is the plain definition.
+ * The walk stops counting at 8 near decisions (flips has 8 bits).
  */
+typedef struct {
+    uint32_t* idx;
+    double *alpha, *T, *eg, *dx, *dy;
+    uint8_t* clamped;
+    int cap;
+} or_blend_buf;
+
+static void blend_buf_grow(or_blend_buf* b, int need) {
+    if (need <= b->cap) return;
+    int cap = b->cap ? b->cap : 256;
+    while (cap < need) cap *= 2;
+    b->idx = (uint32_t*)realloc(b->idx, sizeof(uint32_t) * cap);
+    b->alpha = (double*)realloc(b->alpha, sizeof(double) * cap);
+    b->T = (double*)realloc(b->T, sizeof(double) * cap);
+    b->eg = (double*)realloc(b->eg, sizeof(double) * cap);
+    b->dx = (double*)realloc(b->dx, sizeof(double) * cap);
+    b->dy = (double*)realloc(b->dy, sizeof(double) * cap);
+    b->clamped = (uint8_t*)realloc(b->clamped, cap);
+    b->cap = cap;
+}
+
+static void blend_buf_free(or_blend_buf* b) {
+    free(b->idx); free(b->alpha); free(b->T); free(b->eg); free(b->dx); free(b->dy); free(b->clamped);
+}
+
+typedef struct {
+    double acc[3], T;
+    int32_t nc;
+    uint8_t flags, n_near;
+    int nb; /* blended entries recorded in the buffer */
+} or_pixel;
+
+/* One pixel's front-to-back walk over list entries [s, e).  If bl is not NULL
+ * the blended entries are recorded in walk order (for the backward). */
+static void walk_pixel(const double* rec, const uint32_t* point_list, uint32_t s, uint32_t e, double cxp,
+                       double cyp, const double* margins, uint32_t flips, or_blend_buf* bl, or_pixel* out) {
+    double T = 1.0, acc[3] = {0, 0, 0};
+    double mT = margins[1];
+    int32_t nc = 0;
+    uint8_t fl = 0;
+    int k = 0, nb = 0;
+    for (uint32_t m = s; m < e; ++m) {
+        const double* g = rec + 9 * (int64_t)point_list[m];
+        double dx = g[0] - cxp, dy = g[1] - cyp;
+        double power = -0.5 * (g[2] * dx * dx + g[4] * dy * dy) - g[3] * dx * dy;
+        if (power > 0.0) continue; /* only an FP guard: Sigma' is positive definite */
+        double eg = exp(power);
+        double og = g[5] * eg;
+        int clamp = !(og < OR_ALPHA_MAX);
+        if (fabs(og - OR_ALPHA_MAX) <= margins[2] * OR_ALPHA_MAX && k < 8) {
+            fl |= 4;
+            if ((flips >> k) & 1u) clamp = !clamp;
+            ++k;
+        }
+        double alpha = clamp ? OR_ALPHA_MAX : og;
+        int skip = alpha < OR_ALPHA_MIN;
+        if (fabs(alpha - OR_ALPHA_MIN) <= margins[0] * OR_ALPHA_MIN && k < 8) {
+            fl |= 1;
+            if ((flips >> k) & 1u) skip = !skip;
+            ++k;
+        }
+        if (skip) continue;
+        double Tn = T * (1.0 - alpha);
+        int stop = Tn < OR_T_MIN;
+        if (fabs(Tn - OR_T_MIN) <= mT * OR_T_MIN && k < 8) {
+            fl |= 2;
+            if ((flips >> k) & 1u) stop = !stop;
+            ++k;
+        }
+        if (stop) break;
+        if (bl) {
+            blend_buf_grow(bl, nb + 1);
+            bl->idx[nb] = point_list[m]; bl->alpha[nb] = alpha; bl->T[nb] = T; bl->eg[nb] = eg;
+            bl->dx[nb] = dx; bl->dy[nb] = dy; bl->clamped[nb] = (uint8_t)clamp;
+        }
+        ++nb;
+        for (int ch = 0; ch < 3; ++ch) acc[ch] += g[6 + ch] * alpha * T;
+        T = Tn;
+        nc = (int32_t)(m - s + 1);
+        mT += (clamp ? 1e-6 : alpha / (1.0 - alpha) * margins[0]) + 0x1p-22;
+    }
+    for (int ch = 0; ch < 3; ++ch) out->acc[ch] = acc[ch];
+    out->T = T;
+    out->nc = nc;
+    out->flags = fl;
+    out->n_near = (uint8_t)k;
+    out->nb = nb;
+}
+
+/* Forward render of every pixel (of the tiles selected by tile_mask, if not
+ * NULL).  flips: per-pixel near-decision masks (NULL = none).  pix_flags and
+ * n_near (per pixel, may be NULL) receive the walk's flags and near count. */
 int or_render_fwd(int W, int H, const double* rec, const uint32_t* point_list, const uint32_t* ranges,
-                  const double* bg, double margin, const uint8_t* tile_mask,
-                  double* image, double* final_T, int32_t* n_contrib, uint8_t* pix_flags) {
+                  const double* bg, const double* margins, const uint8_t* tile_mask, const uint8_t* flips,
+                  double* image, double* final_T, int32_t* n_contrib, uint8_t* pix_flags, uint8_t* n_near) {
     int64_t tx = (W + OR_TILE - 1) / OR_TILE, ty = (H + OR_TILE - 1) / OR_TILE;
     int64_t HW = (int64_t)W * H;
 #pragma omp parallel for schedule(dynamic, 1)
@@ -452,161 +556,150 @@ int or_render_fwd(int W, int H, const double* rec, const uint32_t* point_list, c
         uint32_t s = ranges[2 * t], e = ranges[2 * t + 1];
         for (int64_t py = y0; py < y0 + OR_TILE && py < H; ++py)
             for (int64_t px = x0; px < x0 + OR_TILE && px < W; ++px) {
-                double T = 1.0, acc[3] = {0, 0, 0};
-                int32_t nc = 0;
-                uint8_t fl = 0;
-                double cxp = px + 0.5, cyp = py + 0.5;
-                for (uint32_t m = s; m < e; ++m) {
-                    const double* g = rec + 9 * (int64_t)point_list[m];
-                    double dx = g[0] - cxp, dy = g[1] - cyp;
-                    double power = -0.5 * (g[2] * dx * dx + g[4] * dy * dy) - g[3] * dx * dy;
-                    if (power > 0.0) continue;
-                    double og = g[5] * exp(power);
-                    if (fabs(og - OR_ALPHA_MAX) <= margin * OR_ALPHA_MAX) fl |= 4;
-                    double alpha = og < OR_ALPHA_MAX ? og : OR_ALPHA_MAX;
-                    if (fabs(alpha - OR_ALPHA_MIN) <= margin * OR_ALPHA_MIN) fl |= 1;
-                    if (alpha < OR_ALPHA_MIN) continue;
-                    double Tn = T * (1.0 - alpha);
-                    if (fabs(Tn - OR_T_MIN) <= margin * OR_T_MIN) fl |= 2;
-                    if (Tn < OR_T_MIN) break;
-                    for (int ch = 0; ch < 3; ++ch) acc[ch] += g[6 + ch] * alpha * T;
-                    T = Tn;
-                    nc = (int32_t)(m - s + 1);
-                }
                 int64_t p = py * W + px;
-                for (int ch = 0; ch < 3; ++ch) image[ch * HW + p] = acc[ch] + T * bg[ch];
-                final_T[p] = T;
-                n_contrib[p] = nc;
-                if (pix_flags) pix_flags[p] = fl;
+                or_pixel o;
+                walk_pixel(rec, point_list, s, e, px + 0.5, py + 0.5, margins, flips ? flips[p] : 0u, NULL, &o);
+                for (int ch = 0; ch < 3; ++ch) image[ch * HW + p] = o.acc[ch] + o.T * bg[ch];
+                final_T[p] = o.T;
+                n_contrib[p] = o.nc;
+                if (pix_flags) pix_flags[p] = o.flags;
+                if (n_near) n_near[p] = o.n_near;
             }
+    }
+    return 0;
+}
+
+/* The same walk for a list of (pixel, flips) pairs: pixel index pix[j] =
+ * y W + x with mask flips[j].  Outputs per pair: colour out[j][3] (with bg),
+ * final_T, n_contrib, flags and near count.  Used to enumerate the outcomes a
+ * flagged pixel may legitimately have. */
+int or_render_pixels(int W, int H, const double* rec, const uint32_t* point_list, const uint32_t* ranges,
+                     const double* bg, const double* margins, int64_t npairs, const int64_t* pix,
+                     const uint8_t* flips, double* out, double* final_T, int32_t* n_contrib, uint8_t* pix_flags,
+                     uint8_t* n_near) {
+    int64_t tx = (W + OR_TILE - 1) / OR_TILE;
+    for (int64_t j = 0; j < npairs; ++j)
+        if (pix[j] < 0 || pix[j] >= (int64_t)W * H) return -1;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t j = 0; j < npairs; ++j) {
+        int64_t px = pix[j] % W, py = pix[j] / W;
+        int64_t t = (py / OR_TILE) * tx + px / OR_TILE;
+        or_pixel o;
+        walk_pixel(rec, point_list, ranges[2 * t], ranges[2 * t + 1], px + 0.5, py + 0.5, margins, flips[j], NULL,
+                   &o);
+        for (int ch = 0; ch < 3; ++ch) out[3 * j + ch] = o.acc[ch] + o.T * bg[ch];
+        final_T[j] = o.T;
+        n_contrib[j] = o.nc;
+        pix_flags[j] = o.flags;
+        n_near[j] = o.n_near;
     }
     return 0;
 }
 
 /* ------------------------------------------------------ backward render ---
  * Exact derivative of the blending above with the set of blended entries held
- * fixed (skips and the stop are piecewise-constant decisions).  For blended
- * entry m of a pixel with upstream gradient G:
+ * fixed (skips and the stop are piecewise-constant decisions; `flips` selects
+ * the branches exactly as in the forward).  For blended entry m of a pixel
+ * with upstream gradient G:
  *   dL/dc_m   = alpha_m T_m G
  *   dL/dalpha = sum_k G_k (c_mk T_m - S_mk/(1 - alpha_m)),
  *               S_m = sum_{j>m, blended} c_j alpha_j T_j + T_final bg
  *   alpha = o e^power (unclamped branch): dL/do = e^power dL/dalpha,
  *   dL/dpower = alpha dL/dalpha; on the clamped branch both are 0.
  *   dL/du = dL/dpower (-A dx - B dy), dL/dv = dL/dpower (-B dx - C dy)
- *   the conic K = [[A, B], [B, C]] takes dL/dK = -1/2 d d^T dL/dpower per pair,
- *   which is carried to the 2D covariance Sigma' = K^-1 pair by pair:
- *   dL/dSigma' = -K (dL/dK) K.  g2d slots 2..4 hold dL/d(a, b, c) for
- *   Sigma' = [[a, b], [b, c]] (b counted in both off-diagonal places).
+ *   dL/dA = -1/2 dx^2 dL/dpower, dL/dB = -dx dy dL/dpower,
+ *   dL/dC = -1/2 dy^2 dL/dpower  (B enters the power once, as -B dx dy).
  * The oracle recomputes the forward per pixel itself, keeps the blended list,
  * and forms S_m as an explicit suffix sum.  g2d is [n][9] in record order
- * (u, v, A, B, C, o, r, g, b) and is overwritten.  If g2d_mass is not NULL it
- * receives the sum of |per-pair term| for each entry of g2d -- the scale that
- * rounding errors of any summation order are proportional to.
+ * (u, v, A, B, C, o, r, g, b), summed over pixels, and is overwritten.
+ * Optional outputs, scales for judging any other summation order (its
+ * rounding error is proportional to them, not to the sum):
+ *   g2d_mass[n][9]  sum over pixels of |per-pixel term| of each g2d entry;
+ *   cov_mass[n][3]  the same for the per-pixel conic gradient carried to the
+ *                   2D covariance Sigma' = K^-1 = [[a, b], [b, c]] before the
+ *                   sum, dL/dSigma' = -K (dL/dK) K, as (a, b, c) with b
+ *                   counted in both off-diagonal places.
  */
 int or_render_bwd(int W, int H, int64_t n, const double* rec, const uint32_t* point_list,
                   const uint32_t* ranges, const double* bg, const double* dL_dimage,
-                  const uint8_t* tile_mask, double* g2d, double* g2d_mass) {
+                  const uint8_t* tile_mask, const double* margins, const uint8_t* flips, double* g2d,
+                  double* g2d_mass, double* cov_mass) {
     int64_t tx = (W + OR_TILE - 1) / OR_TILE, ty = (H + OR_TILE - 1) / OR_TILE;
     int64_t HW = (int64_t)W * H;
     memset(g2d, 0, sizeof(double) * 9 * (size_t)n);
     if (g2d_mass) memset(g2d_mass, 0, sizeof(double) * 9 * (size_t)n);
+    if (cov_mass) memset(cov_mass, 0, sizeof(double) * 3 * (size_t)n);
 #pragma omp parallel
     {
-        int cap = 1024;
-        uint32_t* lst = (uint32_t*)malloc(sizeof(uint32_t) * cap);
-        double* al = (double*)malloc(sizeof(double) * cap);
-        double* Ts = (double*)malloc(sizeof(double) * cap);
-        double* ex = (double*)malloc(sizeof(double) * cap);
-        double* dxs = (double*)malloc(sizeof(double) * cap);
-        double* dys = (double*)malloc(sizeof(double) * cap);
-        uint8_t* clamped = (uint8_t*)malloc(cap);
+        or_blend_buf bl;
+        memset(&bl, 0, sizeof bl);
 #pragma omp for schedule(dynamic, 1)
         for (int64_t t = 0; t < tx * ty; ++t) {
             if (tile_mask && !tile_mask[t]) continue;
             int64_t x0 = (t % tx) * OR_TILE, y0 = (t / tx) * OR_TILE;
             uint32_t s = ranges[2 * t], e = ranges[2 * t + 1];
-            if ((int64_t)(e - s) > cap) {
-                cap = (int)(e - s);
-                lst = (uint32_t*)realloc(lst, sizeof(uint32_t) * cap);
-                al = (double*)realloc(al, sizeof(double) * cap);
-                Ts = (double*)realloc(Ts, sizeof(double) * cap);
-                ex = (double*)realloc(ex, sizeof(double) * cap);
-                dxs = (double*)realloc(dxs, sizeof(double) * cap);
-                dys = (double*)realloc(dys, sizeof(double) * cap);
-                clamped = (uint8_t*)realloc(clamped, cap);
-            }
             for (int64_t py = y0; py < y0 + OR_TILE && py < H; ++py)
                 for (int64_t px = x0; px < x0 + OR_TILE && px < W; ++px) {
                     int64_t p = py * W + px;
                     double G[3] = {dL_dimage[p], dL_dimage[HW + p], dL_dimage[2 * HW + p]};
-                    double cxp = px + 0.5, cyp = py + 0.5;
                     /* forward walk, remembering the blended entries */
-                    int nb = 0;
-                    double T = 1.0;
-                    for (uint32_t m = s; m < e; ++m) {
-                        const double* g = rec + 9 * (int64_t)point_list[m];
-                        double dx = g[0] - cxp, dy = g[1] - cyp;
-                        double power = -0.5 * (g[2] * dx * dx + g[4] * dy * dy) - g[3] * dx * dy;
-                        if (power > 0.0) continue;
-                        double eg = exp(power);
-                        double og = g[5] * eg;
-                        double alpha = og < OR_ALPHA_MAX ? og : OR_ALPHA_MAX;
-                        if (alpha < OR_ALPHA_MIN) continue;
-                        double Tn = T * (1.0 - alpha);
-                        if (Tn < OR_T_MIN) break;
-                        lst[nb] = point_list[m]; al[nb] = alpha; Ts[nb] = T; ex[nb] = eg;
-                        dxs[nb] = dx; dys[nb] = dy; clamped[nb] = !(og < OR_ALPHA_MAX);
-                        ++nb;
-                        T = Tn;
-                    }
+                    or_pixel o;
+                    walk_pixel(rec, point_list, s, e, px + 0.5, py + 0.5, margins, flips ? flips[p] : 0u, &bl, &o);
                     /* suffix sums S_m, walking back */
-                    double S[3] = {T * bg[0], T * bg[1], T * bg[2]};
-                    for (int k = nb - 1; k >= 0; --k) {
-                        const double* g = rec + 9 * (int64_t)lst[k];
-                        double a = al[k], Tm = Ts[k];
+                    double S[3] = {o.T * bg[0], o.T * bg[1], o.T * bg[2]};
+                    for (int k = o.nb - 1; k >= 0; --k) {
+                        const double* g = rec + 9 * (int64_t)bl.idx[k];
+                        double a = bl.alpha[k], Tm = bl.T[k];
                         double dc[3], dalpha = 0.0;
                         for (int ch = 0; ch < 3; ++ch) {
                             dc[ch] = a * Tm * G[ch];
                             dalpha += G[ch] * (g[6 + ch] * Tm - S[ch] / (1.0 - a));
                         }
                         double dpow = 0.0, dop = 0.0;
-                        if (!clamped[k]) { dop = ex[k] * dalpha; dpow = a * dalpha; }
-                        double dx = dxs[k], dy = dys[k];
+                        if (!bl.clamped[k]) { dop = bl.eg[k] * dalpha; dpow = a * dalpha; }
+                        double dx = bl.dx[k], dy = bl.dy[k];
                         double gr[9];
                         gr[0] = dpow * (-g[2] * dx - g[3] * dy);
                         gr[1] = dpow * (-g[3] * dx - g[4] * dy);
-                        /* dL/dK (symmetric), then -K dL/dK K */
-                        double K[4] = {g[2], g[3], g[3], g[4]};
-                        double GK[4] = {-0.5 * dx * dx * dpow, -0.5 * dx * dy * dpow,
-                                        -0.5 * dx * dy * dpow, -0.5 * dy * dy * dpow};
-                        double KG[4], GS[4];
-                        for (int a = 0; a < 2; ++a)
-                            for (int b = 0; b < 2; ++b) KG[2 * a + b] = K[2 * a] * GK[b] + K[2 * a + 1] * GK[2 + b];
-                        for (int a = 0; a < 2; ++a)
-                            for (int b = 0; b < 2; ++b)
-                                GS[2 * a + b] = -(KG[2 * a] * K[b] + KG[2 * a + 1] * K[2 + b]);
-                        gr[2] = GS[0];
-                        gr[3] = GS[1] + GS[2];
-                        gr[4] = GS[3];
+                        gr[2] = -0.5 * dx * dx * dpow;
+                        gr[3] = -dx * dy * dpow;
+                        gr[4] = -0.5 * dy * dy * dpow;
                         gr[5] = dop;
                         gr[6] = dc[0]; gr[7] = dc[1]; gr[8] = dc[2];
-                        double* out = g2d + 9 * (int64_t)lst[k];
+                        double* out = g2d + 9 * (int64_t)bl.idx[k];
                         for (int q = 0; q < 9; ++q) {
 #pragma omp atomic
                             out[q] += gr[q];
                         }
                         if (g2d_mass) {
-                            double* mo = g2d_mass + 9 * (int64_t)lst[k];
+                            double* mo = g2d_mass + 9 * (int64_t)bl.idx[k];
                             for (int q = 0; q < 9; ++q) {
 #pragma omp atomic
                                 mo[q] += fabs(gr[q]);
+                            }
+                        }
+                        if (cov_mass) {
+                            /* -K Gc K with Gc = [[gA, gB/2], [gB/2, gC]] */
+                            double K[4] = {g[2], g[3], g[3], g[4]};
+                            double Gc[4] = {gr[2], 0.5 * gr[3], 0.5 * gr[3], gr[4]};
+                            double KG[4], GS[4];
+                            for (int i = 0; i < 2; ++i)
+                                for (int j = 0; j < 2; ++j) KG[2 * i + j] = K[2 * i] * Gc[j] + K[2 * i + 1] * Gc[2 + j];
+                            for (int i = 0; i < 2; ++i)
+                                for (int j = 0; j < 2; ++j)
+                                    GS[2 * i + j] = -(KG[2 * i] * K[j] + KG[2 * i + 1] * K[2 + j]);
+                            double cm[3] = {fabs(GS[0]), fabs(GS[1] + GS[2]), fabs(GS[3])};
+                            double* co = cov_mass + 3 * (int64_t)bl.idx[k];
+                            for (int q = 0; q < 3; ++q) {
+#pragma omp atomic
+                                co[q] += cm[q];
                             }
                         }
                         for (int ch = 0; ch < 3; ++ch) S[ch] += g[6 + ch] * a * Tm;
                     }
                 }
         }
-        free(lst); free(al); free(Ts); free(ex); free(dxs); free(dys); free(clamped);
+        blend_buf_free(&bl);
     }
     return 0;
 }
@@ -617,9 +710,8 @@ int or_render_bwd(int W, int H, int64_t n, const double* rec, const uint32_t* po
  *   colour: clamp mask, dL/df_jk = Y_j(d) dL/dc_k, dL/dd = sum f_jk grad Y_j,
  *           then mu via (I - d d^T)/|mu - c|;
  *   opacity: dL/dlogit = dL/do o (1 - o);
- *   g2d slots 2..4 already hold dL/d(a, b, c) of Sigma' = [[a, b], [b, c]]
- *          (the render backward converts from the conic pair by pair), so
- *          the symmetric covariance gradient is [[ga, gb/2], [gb/2, gc]];
+ *   conic: K = Sigma'^-1, d(K) = -K d(Sigma') K, so the symmetric conic
+ *          gradient Gc = [[gA, gB/2], [gB/2, gC]] gives dL/dSigma' = -K Gc K;
  *   Sigma' = T Sigma T^T (T = J W): dL/dSigma = T^T G T, dL/dT = 2 G T Sigma;
  *   dL/dJ = dL/dT W^T; J(t) with the clamp mask on the slopes; u, v -> t;
  *   t = W mu + t_cw -> dL/dmu += W^T dL/dt;
@@ -662,8 +754,14 @@ int or_project_bwd(int64_t n, int deg, const double* means, const double* log_sc
             for (int k = 0; k < 3; ++k) gm[k] += (gd[k] - st.d[k] * dd) / st.dirlen;
             /* opacity */
             gl = g[5] * st.o * (1.0 - st.o);
-            /* symmetric gradient of Sigma' */
-            double GS[4] = {g[2], 0.5 * g[3], 0.5 * g[3], g[4]};
+            /* conic -> Sigma': dL/dSigma' = -K Gc K */
+            double K[4] = {rec[2], rec[3], rec[3], rec[4]};
+            double Gc[4] = {g[2], 0.5 * g[3], 0.5 * g[3], g[4]};
+            double KG[4], GS[4];
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) KG[2 * a + b] = K[2 * a] * Gc[b] + K[2 * a + 1] * Gc[2 + b];
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) GS[2 * a + b] = -(KG[2 * a] * K[b] + KG[2 * a + 1] * K[2 + b]);
             /* dL/dSigma = T^T GS T ; dL/dT = 2 GS T Sigma */
             double gSig[9], gT[6];
             for (int a = 0; a < 3; ++a)

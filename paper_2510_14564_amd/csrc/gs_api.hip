@@ -3,8 +3,12 @@
 #include <math.h>
 
 #include <cmath>
+#include <cstdio>
+#include <cstring>
 
+#include <map>
 #include <string>
+#include <vector>
 
 #include "gs_internal.h"
 
@@ -92,6 +96,58 @@ static gs_status validate_projected(const gs_projected* p, int64_t n, const char
   if (reinterpret_cast<uintptr_t>(p->records) % 16 != 0)
     return fail(GS_ERR_INVALID_ARG, f + ": records must be 16-byte aligned");
   return GS_OK;
+}
+
+// ------------------------------------------------------------ kernel timer
+namespace {
+struct TimerRec {
+  const char* name;
+  hipEvent_t a, b;
+};
+thread_local bool t_timing = false;
+thread_local std::vector<TimerRec> t_recs;
+thread_local std::vector<hipEvent_t> t_pool;
+thread_local hipError_t t_timer_err = hipSuccess;
+
+hipEvent_t pool_get() {
+  if (!t_pool.empty()) {
+    hipEvent_t e = t_pool.back();
+    t_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  const hipError_t r = hipEventCreate(&e);
+  if (r != hipSuccess) {
+    t_timer_err = r;
+    return nullptr;
+  }
+  return e;
+}
+}  // namespace
+
+TimedLaunch::TimedLaunch(const char* name, hipStream_t s) : slot_(-1), s_(s) {
+  if (!t_timing) return;
+  hipEvent_t a = pool_get();
+  hipEvent_t b = a ? pool_get() : nullptr;
+  if (!b) {
+    if (a) t_pool.push_back(a);
+    return;
+  }
+  const hipError_t r = hipEventRecord(a, s);
+  if (r != hipSuccess) {
+    t_timer_err = r;
+    t_pool.push_back(a);
+    t_pool.push_back(b);
+    return;
+  }
+  t_recs.push_back({name, a, b});
+  slot_ = static_cast<int>(t_recs.size()) - 1;
+}
+
+TimedLaunch::~TimedLaunch() {
+  if (slot_ < 0) return;
+  const hipError_t r = hipEventRecord(t_recs[slot_].b, s_);
+  if (r != hipSuccess) t_timer_err = r;
 }
 
 }  // namespace gs
@@ -201,35 +257,111 @@ gs_status gs_render_ckpt_floats(int64_t k, const gs_camera* cam, size_t* floats)
   return GS_OK;
 }
 
-gs_status gs_render_bwd_workspace(int64_t n, int64_t k, const gs_camera* cam, int32_t deterministic, size_t* bytes) {
+gs_status gs_render_bwd_2d_workspace(int64_t n, int64_t k, const gs_camera* cam, int32_t deterministic,
+                                     size_t* bytes) {
   set_error("");
   gs_status st;
   if ((st = validate_camera(cam)) != GS_OK) return st;
-  if (n < 0 || k < 0 || !bytes) return fail(GS_ERR_INVALID_ARG, "gs_render_bwd_workspace: bad arguments");
+  if (n < 0 || k < 0 || !bytes) return fail(GS_ERR_INVALID_ARG, "gs_render_bwd_2d_workspace: bad arguments");
   const DevCam d = make_devcam(*cam);
   *bytes = render_bwd_workspace(n, k, d.tiles_x * d.tiles_y, deterministic);
   return GS_OK;
 }
 
-gs_status gs_render_bwd(int64_t n, const gs_projected* proj, const uint32_t* point_list, const uint32_t* ranges,
-                        int64_t k, const gs_camera* cam, const float* final_T, const uint32_t* n_contrib,
-                        const float* t_ckpt, const float* dL_dimage, float* g2d, void* ws, size_t ws_bytes,
+gs_status gs_render_bwd_2d(int64_t n, const gs_projected* proj, const uint32_t* point_list, const uint32_t* ranges,
+                           int64_t k, const gs_camera* cam, const float* final_T, const uint32_t* n_contrib,
+                           const float* t_ckpt, const float* dL_dimage, float* g2d, void* ws, size_t ws_bytes,
+                           int32_t deterministic, int32_t schedule, gs_stream stream) {
+  set_error("");
+  gs_status st;
+  if (n < 0 || k < 0) return fail(GS_ERR_INVALID_ARG, "gs_render_bwd_2d: negative n or k");
+  if ((st = validate_camera(cam)) != GS_OK) return st;
+  if ((st = validate_projected(proj, n, "gs_render_bwd_2d")) != GS_OK) return st;
+  if (!ranges || !final_T || !n_contrib || !t_ckpt || !dL_dimage || (n > 0 && !g2d) || (k > 0 && !point_list))
+    return fail(GS_ERR_INVALID_ARG, "gs_render_bwd_2d: NULL array");
+  const DevCam d = make_devcam(*cam);
+  if (schedule < GS_SCHEDULE_PLAIN || schedule > GS_SCHEDULE_MERGED)
+    return fail(GS_ERR_INVALID_ARG, "gs_render_bwd_2d: unknown schedule");
+  if (ws_bytes < render_bwd_workspace(n, k, d.tiles_x * d.tiles_y, deterministic) || !ws)
+    return fail(GS_ERR_INVALID_ARG, "gs_render_bwd_2d: workspace too small");
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(GS_ERR_INVALID_ARG, "gs_render_bwd_2d: ws not 256-aligned");
+  if (n == 0) return GS_OK;
+  return launch_render_bwd(n, *proj, point_list, ranges, k, d, final_T, n_contrib, t_ckpt, dL_dimage, g2d, ws,
+                           ws_bytes, deterministic, schedule, nullptr, static_cast<hipStream_t>(stream));
+}
+
+// Workspace of the full backward: the record gradients g2d[9][n] (unless the
+// projection reads the compositing's accumulator rows directly: atomic mode,
+// SH colour), the compositing backward's workspace, the decoder backward's.
+namespace {
+struct FullBwdWs {
+  float* g2d;
+  void* ws2d;
+  void* wspb;
+  size_t bytes;
+  bool rows;
+};
+FullBwdWs carve_full_bwd(void* base, const gs_gaussians& g, int64_t k, int ntiles, int deterministic) {
+  FullBwdWs f;
+  f.rows = !deterministic && g.colour_mode == 0;
+  Carver c(base);
+  f.g2d = c.take<float>(f.rows ? 0 : static_cast<size_t>(GS_G2D) * static_cast<size_t>(g.n));
+  f.ws2d = c.take<char>(render_bwd_workspace(g.n, k, ntiles, deterministic));
+  f.wspb = c.take<char>(g.colour_mode == 1 ? mlp_bwd_workspace(g.n, 1) : 0);
+  f.bytes = c.off;
+  return f;
+}
+}  // namespace
+
+gs_status gs_render_bwd_workspace(const gs_gaussians* g, int64_t k, const gs_camera* cam, int32_t deterministic,
+                                  size_t* bytes) {
+  set_error("");
+  gs_status st;
+  if ((st = validate_gaussians(g, "gs_render_bwd_workspace")) != GS_OK) return st;
+  if ((st = validate_camera(cam)) != GS_OK) return st;
+  if (k < 0 || !bytes) return fail(GS_ERR_INVALID_ARG, "gs_render_bwd_workspace: bad arguments");
+  const DevCam d = make_devcam(*cam);
+  *bytes = carve_full_bwd(nullptr, *g, k, d.tiles_x * d.tiles_y, deterministic).bytes;
+  return GS_OK;
+}
+
+gs_status gs_render_bwd(const gs_gaussians* g, const gs_camera* cam, const gs_projected* proj,
+                        const uint32_t* point_list, const uint32_t* ranges, int64_t k, const float* final_T,
+                        const uint32_t* n_contrib, const float* t_ckpt, const float* dL_dimage,
+                        gs_gaussians_grad* grad, gs_densify_stats* stats, void* ws, size_t ws_bytes,
                         int32_t deterministic, int32_t schedule, gs_stream stream) {
   set_error("");
   gs_status st;
-  if (n < 0 || k < 0) return fail(GS_ERR_INVALID_ARG, "gs_render_bwd: negative n or k");
+  if ((st = validate_gaussians(g, "gs_render_bwd")) != GS_OK) return st;
   if ((st = validate_camera(cam)) != GS_OK) return st;
+  const int64_t n = g->n;
+  if (k < 0) return fail(GS_ERR_INVALID_ARG, "gs_render_bwd: negative k");
   if ((st = validate_projected(proj, n, "gs_render_bwd")) != GS_OK) return st;
-  if (!ranges || !final_T || !n_contrib || !t_ckpt || !dL_dimage || (n > 0 && !g2d) || (k > 0 && !point_list))
+  if (!ranges || !final_T || !n_contrib || !t_ckpt || !dL_dimage || (k > 0 && !point_list))
     return fail(GS_ERR_INVALID_ARG, "gs_render_bwd: NULL array");
-  const DevCam d = make_devcam(*cam);
+  if (!grad) return fail(GS_ERR_INVALID_ARG, "gs_render_bwd: grad is NULL");
+  const bool mlp = g->colour_mode == 1;
+  if (n > 0 && (!grad->means || !grad->log_scales || !grad->quats || !grad->logits || (!mlp && !grad->sh) ||
+                (mlp && (!grad->latents || !grad->mlp))))
+    return fail(GS_ERR_INVALID_ARG, "gs_render_bwd: NULL gradient array");
+  if (stats && n > 0 && (!stats->grad_norm_sum || !stats->visible_count))
+    return fail(GS_ERR_INVALID_ARG, "gs_render_bwd: NULL densification statistics array");
   if (schedule < GS_SCHEDULE_PLAIN || schedule > GS_SCHEDULE_MERGED)
     return fail(GS_ERR_INVALID_ARG, "gs_render_bwd: unknown schedule");
-  if (ws_bytes < render_bwd_workspace(n, k, d.tiles_x * d.tiles_y, deterministic) || !ws)
-    return fail(GS_ERR_INVALID_ARG, "gs_render_bwd: workspace too small");
+  const DevCam d = make_devcam(*cam);
+  const FullBwdWs layout = carve_full_bwd(nullptr, *g, k, d.tiles_x * d.tiles_y, deterministic);
+  if (!ws || ws_bytes < layout.bytes) return fail(GS_ERR_INVALID_ARG, "gs_render_bwd: workspace too small");
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(GS_ERR_INVALID_ARG, "gs_render_bwd: ws not 256-aligned");
   if (n == 0) return GS_OK;
-  return launch_render_bwd(n, *proj, point_list, ranges, k, d, final_T, n_contrib, t_ckpt, dL_dimage, g2d, ws,
-                           ws_bytes, deterministic, schedule, static_cast<hipStream_t>(stream));
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const FullBwdWs f = carve_full_bwd(ws, *g, k, d.tiles_x * d.tiles_y, deterministic);
+  const float* rows = nullptr;
+  st = launch_render_bwd(n, *proj, point_list, ranges, k, d, final_T, n_contrib, t_ckpt, dL_dimage,
+                         f.rows ? nullptr : f.g2d, f.ws2d, ws_bytes - (static_cast<char*>(f.ws2d) - static_cast<char*>(ws)),
+                         deterministic, schedule, &rows, s);
+  if (st != GS_OK) return st;
+  return launch_project_bwd(*g, d, proj->radius, f.rows ? rows : f.g2d, f.rows, proj->tiles_touched, stats, *grad,
+                            f.wspb, s);
 }
 
 gs_status gs_project_bwd_workspace(const gs_gaussians* g, size_t* bytes) {
@@ -257,8 +389,8 @@ gs_status gs_project_bwd(const gs_gaussians* g, const gs_camera* cam, const gs_p
       return fail(GS_ERR_INVALID_ARG, "gs_project_bwd: workspace too small");
   }
   if (g->n == 0) return GS_OK;
-  return launch_project_bwd(*g, make_devcam(*cam), mlp ? proj->radius : nullptr, g2d, *grad, ws,
-                            static_cast<hipStream_t>(stream));
+  return launch_project_bwd(*g, make_devcam(*cam), mlp ? proj->radius : nullptr, g2d, false, nullptr, nullptr, *grad,
+                            ws, static_cast<hipStream_t>(stream));
 }
 
 gs_status gs_mlp_pack(const uint16_t* params, void* packed, gs_stream stream) {
@@ -325,6 +457,78 @@ gs_status gs_adam_step(int64_t n, float* param, const float* grad, float* m, flo
   const double bc2 = 1.0 - std::pow(static_cast<double>(beta2), step);
   return launch_adam(n, param, grad, m, v, param_bf16, lr, beta1, beta2, eps, static_cast<float>(bc1),
                      static_cast<float>(bc2), static_cast<hipStream_t>(stream));
+}
+
+gs_status gs_adam_gaussians(int64_t n, int32_t sh_degree, const gs_param_arrays* params, const gs_gaussians_grad* grad,
+                            const gs_param_arrays* m, const gs_param_arrays* v, const gs_adam_config* cfg,
+                            gs_stream stream) {
+  set_error("");
+  if (n < 0 || n > (int64_t(1) << 30) || sh_degree < 0 || sh_degree > 3 || !params || !grad || !m || !v || !cfg)
+    return fail(GS_ERR_INVALID_ARG, "gs_adam_gaussians: bad arguments");
+  const float lrs[] = {cfg->lr_means, cfg->lr_log_scales, cfg->lr_quats, cfg->lr_logits, cfg->lr_sh_dc,
+                       cfg->lr_sh_rest};
+  for (float lr : lrs)
+    if (!std::isfinite(lr)) return fail(GS_ERR_INVALID_ARG, "gs_adam_gaussians: non-finite learning rate");
+  if (cfg->step < 1 || !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) || !(cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f) ||
+      !(cfg->eps > 0.0f))
+    return fail(GS_ERR_INVALID_ARG, "gs_adam_gaussians: bad step, betas or eps");
+  if (n > 0) {
+    const gs_param_arrays* sets[] = {params, m, v};
+    for (const gs_param_arrays* a : sets)
+      if (!a->means || !a->log_scales || !a->quats || !a->logits || !a->sh)
+        return fail(GS_ERR_INVALID_ARG, "gs_adam_gaussians: NULL parameter or moment array");
+    if (!grad->means || !grad->log_scales || !grad->quats || !grad->logits || !grad->sh)
+      return fail(GS_ERR_INVALID_ARG, "gs_adam_gaussians: NULL gradient array");
+  }
+  if (n == 0) return GS_OK;
+  return launch_adam_gaussians(n, sh_degree, *params, *grad, *m, *v, *cfg, static_cast<hipStream_t>(stream));
+}
+
+gs_status gs_kernel_timer_start(void) {
+  set_error("");
+  if (t_timing) return fail(GS_ERR_INVALID_ARG, "gs_kernel_timer_start: a timer is already running on this thread");
+  t_recs.clear();
+  t_timer_err = hipSuccess;
+  t_timing = true;
+  return GS_OK;
+}
+
+gs_status gs_kernel_timer_stop(char* buf, size_t size, size_t* needed) {
+  set_error("");
+  if (!t_timing) return fail(GS_ERR_INVALID_ARG, "gs_kernel_timer_stop: no timer is running on this thread");
+  t_timing = false;
+  std::vector<std::string> order;
+  std::map<std::string, std::pair<long long, double>> acc;
+  gs_status st = GS_OK;
+  for (const TimerRec& r : t_recs) {
+    float ms = 0.0f;
+    if (st == GS_OK) st = check_hip(hipEventSynchronize(r.b), "hipEventSynchronize");
+    if (st == GS_OK) st = check_hip(hipEventElapsedTime(&ms, r.a, r.b), "hipEventElapsedTime");
+    auto it = acc.find(r.name);
+    if (it == acc.end()) {
+      order.push_back(r.name);
+      it = acc.emplace(r.name, std::make_pair(0LL, 0.0)).first;
+    }
+    it->second.first += 1;
+    it->second.second += ms;
+    t_pool.push_back(r.a);
+    t_pool.push_back(r.b);
+  }
+  t_recs.clear();
+  if (st == GS_OK && t_timer_err != hipSuccess) st = check_hip(t_timer_err, "kernel timer event");
+  std::string out;
+  for (const std::string& name : order) {
+    char line[256];
+    snprintf(line, sizeof line, "%s %lld %.6f\n", name.c_str(), acc[name].first, acc[name].second);
+    out += line;
+  }
+  if (needed) *needed = out.size() + 1;
+  if (buf && size > 0) {
+    const size_t m = std::min(size - 1, out.size());
+    memcpy(buf, out.data(), m);
+    buf[m] = '\0';
+  }
+  return st;
 }
 
 gs_status gs_l1_loss(const float* img, const float* target, int64_t count, float* loss, float* grad,

@@ -201,16 +201,16 @@ static size_t scan_ws_words(int64_t n) { return static_cast<size_t>(ceil_div(n >
 
 static gs_status device_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, ScanWs ws, hipStream_t s) {
   const int nb = static_cast<int>(ceil_div(n > 0 ? n : 1, kScanChunk));
-  k_scan_sums<<<nb, 256, 0, s>>>(in, n, ws.sums);
-  k_scan_apply<false><<<nb, 256, 0, s>>>(in, n, ws.sums, out, ws.total, ChunkArgs{});
+  { TimedLaunch gs_tl("k_scan_sums", s); k_scan_sums<<<nb, 256, 0, s>>>(in, n, ws.sums); }
+  { TimedLaunch gs_tl("k_scan_apply<false>", s); k_scan_apply<false><<<nb, 256, 0, s>>>(in, n, ws.sums, out, ws.total, ChunkArgs{}); }
   return check_launch("device_exclusive_scan");
 }
 
 // The scan's total and the direct emission's chunk bounds (no offsets).
 static gs_status device_chunk_bounds(const uint32_t* in, int64_t n, ScanWs ws, ChunkArgs ca, hipStream_t s) {
   const int nb = static_cast<int>(ceil_div(n > 0 ? n : 1, kScanChunk));
-  k_scan_sums<<<nb, 256, 0, s>>>(in, n, ws.sums);
-  k_scan_apply<true><<<nb, 256, 0, s>>>(in, n, ws.sums, nullptr, ws.total, ca);
+  { TimedLaunch gs_tl("k_scan_sums", s); k_scan_sums<<<nb, 256, 0, s>>>(in, n, ws.sums); }
+  { TimedLaunch gs_tl("k_scan_apply<true>", s); k_scan_apply<true><<<nb, 256, 0, s>>>(in, n, ws.sums, nullptr, ws.total, ca); }
   return check_launch("device_chunk_bounds");
 }
 
@@ -353,10 +353,10 @@ static gs_status radix_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, uint
     for (int shift = 0; shift < total_bits; shift += 8) {
       const int nbits = min(8, total_bits - shift);
       const int64_t nh = static_cast<int64_t>(1 << nbits) * nblocks;
-      k_rs_hist<ITEMS><<<nblocks, kRsThreads, 0, s>>>(ka, count, shift, nbits, hist, nblocks);
+      { TimedLaunch gs_tl("k_rs_hist", s); k_rs_hist<ITEMS><<<nblocks, kRsThreads, 0, s>>>(ka, count, shift, nbits, hist, nblocks); }
       gs_status st = scan_hist(hist, nh, sws, s);
       if (st != GS_OK) return st;
-      k_rs_scatter<ITEMS><<<nblocks, kRsThreads, 0, s>>>(ka, va, kb, vb, count, shift, nbits, hist, nblocks);
+      { TimedLaunch gs_tl("k_rs_scatter", s); k_rs_scatter<ITEMS><<<nblocks, kRsThreads, 0, s>>>(ka, va, kb, vb, count, shift, nbits, hist, nblocks); }
       st = check_launch("k_rs_scatter");
       if (st != GS_OK) return st;
       uint32_t* t = ka; ka = kb; kb = t;
@@ -632,13 +632,13 @@ static gs_status onesweep_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, u
   const int nblocks = static_cast<int>(ceil_div(count, CHUNK));
   gs_status st;
   const int hb = static_cast<int>(std::min<int64_t>(kOsHistBlocks, ceil_div(count, 256 * 8)));
-  k_os_hist<<<std::max(hb, 1), 256, 0, s>>>(ka, count, total_bits, w.ghist, w.state,
-                                            static_cast<int64_t>(os_state_words(count, ITEMS, passes)), w.counters);
+  { TimedLaunch gs_tl("k_os_hist", s); k_os_hist<<<std::max(hb, 1), 256, 0, s>>>(ka, count, total_bits, w.ghist, w.state,
+                                            static_cast<int64_t>(os_state_words(count, ITEMS, passes)), w.counters); }
   if ((st = check_launch("k_os_hist")) != GS_OK) return st;
   for (int p = 0; p < passes; ++p) {
-    k_os_scatter<ITEMS><<<nblocks, kRsThreads, 0, s>>>(ka, va, kb, vb, count, p, total_bits, w.ghist,
+    { TimedLaunch gs_tl("k_os_scatter", s); k_os_scatter<ITEMS><<<nblocks, kRsThreads, 0, s>>>(ka, va, kb, vb, count, p, total_bits, w.ghist,
                                                        w.state + static_cast<size_t>(p) * nblocks * 256,
-                                                       w.counters + p, w.err, vals_final, rect, rect_out, cnt_out);
+                                                       w.counters + p, w.err, vals_final, rect, rect_out, cnt_out); }
     if ((st = check_launch("k_os_scatter")) != GS_OK) return st;
     uint32_t* t = ka; ka = kb; kb = t;
     t = va; va = vb; vb = t;
@@ -1164,8 +1164,8 @@ gs_status run_bin_sort(int64_t n64, const gs_projected& proj, const DevCam& cam,
   int64_t K = 0;
   if (n > 0) {
     const unsigned g = static_cast<unsigned>(ceil_div(n, 256));
-    k_depth_keys<<<g, 256, 0, s>>>(n, proj.depth, reinterpret_cast<const float4*>(proj.records), proj.radius,
-                                   cam.tiles_x, cam.tiles_y, b.dk0, b.dv0, b.rect, b.zero, kOsMaxPasses * 256 + 4);
+    { TimedLaunch gs_tl("k_depth_keys", s); k_depth_keys<<<g, 256, 0, s>>>(n, proj.depth, reinterpret_cast<const float4*>(proj.records), proj.radius,
+                                   cam.tiles_x, cam.tiles_y, b.dk0, b.dv0, b.rect, b.zero, kOsMaxPasses * 256 + 4); }
     if ((st = check_launch("k_depth_keys")) != GS_OK) return st;
     // the terminal pass also gathers each rank's rectangle and tile count
     if ((st = onesweep_sort_pairs<kOsItemsN>(b.dk0, b.dv0, b.dk1, b.dv1, n, 32, b.os, s, b.order, b.rect,
@@ -1184,17 +1184,17 @@ gs_status run_bin_sort(int64_t n64, const gs_projected& proj, const DevCam& cam,
                                               static_cast<unsigned long long>(kDirectChunks), k_dev},
                                     s)) != GS_OK)
         return st;
-      k_chunk_count<<<cmax, kDirectThreads, sizeof(int) * (tx + 1) * (ty + 1), s>>>(b.bounds, b.rect_rank, tx, ty,
-                                                                                   b.table);
+      { TimedLaunch gs_tl("k_chunk_count", s); k_chunk_count<<<cmax, kDirectThreads, sizeof(int) * (tx + 1) * (ty + 1), s>>>(b.bounds, b.rect_rank, tx, ty,
+                                                                                   b.table); }
       if ((st = check_launch("k_chunk_count")) != GS_OK) return st;
-      k_chunk_colscan<<<static_cast<unsigned>(ceil_div(ntiles, 64)), 1024, 0, s>>>(cmax, ntiles, b.table, b.total);
+      { TimedLaunch gs_tl("k_chunk_colscan", s); k_chunk_colscan<<<static_cast<unsigned>(ceil_div(ntiles, 64)), 1024, 0, s>>>(cmax, ntiles, b.table, b.total); }
       if ((st = check_launch("k_chunk_colscan")) != GS_OK) return st;
-      k_tile_starts<<<1, 1024, 0, s>>>(ntiles, b.total, b.start, reinterpret_cast<uint2*>(ranges),
-                                       static_cast<unsigned long long>(capacity));
+      { TimedLaunch gs_tl("k_tile_starts", s); k_tile_starts<<<1, 1024, 0, s>>>(ntiles, b.total, b.start, reinterpret_cast<uint2*>(ranges),
+                                       static_cast<unsigned long long>(capacity)); }
       if ((st = check_launch("k_tile_starts")) != GS_OK) return st;
-      k_emit_direct<<<cmax, kDirectThreads, emit_dyn_lds(tx, ty), s>>>(
+      { TimedLaunch gs_tl("k_emit_direct", s); k_emit_direct<<<cmax, kDirectThreads, emit_dyn_lds(tx, ty), s>>>(
           b.bounds, order, b.rect_rank, b.table, b.start, tx, ty, point_list,
-          static_cast<uint32_t>(std::min<int64_t>(capacity, UINT32_MAX)));
+          static_cast<uint32_t>(std::min<int64_t>(capacity, UINT32_MAX))); }
       if ((st = check_launch("k_emit_direct")) != GS_OK) return st;
       if (k_dev) return GS_OK;   // the caller checks K and the flag later
     } else if ((st = device_exclusive_scan(b.cnt, b.offs, n, b.scan, s)) != GS_OK) {
@@ -1218,20 +1218,20 @@ gs_status run_bin_sort(int64_t n64, const gs_projected& proj, const DevCam& cam,
       uint32_t* va = (tp % 2 == 0) ? point_list : b.ev1;
       uint32_t* kb = b.ek1;
       uint32_t* vb = (tp % 2 == 0) ? b.ev1 : point_list;
-      k_emit<<<static_cast<unsigned>(ceil_div(n, 256)), 256, 0, s>>>(
-          n, order, b.offs, b.rect_rank, cam.tiles_x, ka, va);
+      { TimedLaunch gs_tl("k_emit", s); k_emit<<<static_cast<unsigned>(ceil_div(n, 256)), 256, 0, s>>>(
+          n, order, b.offs, b.rect_rank, cam.tiles_x, ka, va); }
       if ((st = check_launch("k_emit")) != GS_OK) return st;
       int p2 = 0;
       if ((st = radix_sort_pairs<kRsItemsK>(ka, va, kb, vb, K, tbits, b.hist, b.scan, s, &p2)) != GS_OK) return st;
       const uint32_t* sorted_tiles = (p2 % 2 == 0) ? ka : kb;
-      k_ranges<<<static_cast<unsigned>(ceil_div(ntiles, 256)), 256, 0, s>>>(
-          ntiles, sorted_tiles, static_cast<uint32_t>(K), reinterpret_cast<uint2*>(ranges));
+      { TimedLaunch gs_tl("k_ranges", s); k_ranges<<<static_cast<unsigned>(ceil_div(ntiles, 256)), 256, 0, s>>>(
+          ntiles, sorted_tiles, static_cast<uint32_t>(K), reinterpret_cast<uint2*>(ranges)); }
       return check_launch("k_ranges");
     }
   } else {
     if (k_out) *k_out = 0;
     if (k_dev) {
-      k_put_zero_k<<<1, 64, 0, s>>>(k_dev);
+      { TimedLaunch gs_tl("k_put_zero_k", s); k_put_zero_k<<<1, 64, 0, s>>>(k_dev); }
       if ((st = check_launch("k_put_zero_k")) != GS_OK) return st;
     }
   }

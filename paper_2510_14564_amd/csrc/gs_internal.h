@@ -105,10 +105,36 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
   return start + local;
 }
 
+// Per-Gaussian gradient accumulator rows of the compositing backward (atomic
+// mode): nine sums padded to one 64-byte line.  The sums hold the record
+// gradients up to constant factors (powers of 2 ln 2) that grad_scale applies
+// once per Gaussian: u, v, Sigma'_xx, Sigma'_xy (both entries), Sigma'_yy,
+// opacity, r, g, b.
+constexpr int kAccStride = 16;
+constexpr float kLn2 = 0.6931471805599453f;
+__device__ __forceinline__ float grad_scale(int c) {
+  constexpr float l1 = 2.0f * kLn2, l2 = 2.0f * kLn2 * kLn2;
+  return c < 2 ? l1 : (c == 3 ? l2 + l2 : (c < 5 ? l2 : 1.0f));
+}
+
 }  // namespace gs
 
 // Launchers implemented in the kernel translation units.
 namespace gs {
+// Measurement: while gs_kernel_timer_start is in effect on the calling
+// thread, a TimedLaunch in scope around a kernel launch records a HIP event on
+// the launch stream before and after it (a no-op otherwise).
+struct TimedLaunch {
+  TimedLaunch(const char* name, hipStream_t s);
+  ~TimedLaunch();
+  TimedLaunch(const TimedLaunch&) = delete;
+  TimedLaunch& operator=(const TimedLaunch&) = delete;
+
+ private:
+  int slot_;
+  hipStream_t s_;
+};
+
 gs_status launch_project(const gs_gaussians& g, const DevCam& cam, gs_projected& out, hipStream_t s);
 constexpr int kPlanHeader = 16;
 size_t plan_ints(int ntiles);
@@ -120,8 +146,13 @@ gs_status launch_batch_plan(int ntiles, const uint32_t* ranges, const uint32_t* 
 inline size_t batch_item_ints(int64_t k, int64_t ntiles) {
   return 16 + 2 * static_cast<size_t>(k / 256 + ntiles + 1);
 }
-gs_status launch_project_bwd(const gs_gaussians& g, const DevCam& cam, const int* radius, const float* g2d,
-                             gs_gaussians_grad& grad, void* ws, hipStream_t s);
+// Record gradients handed to the projection backward: g2d[9][n] (rows ==
+// false) or the compositing backward's accumulator rows acc[n][kAccStride]
+// before grad_scale (rows == true, SH colour only).  stats (optional) gets
+// |dL/d(u, v)| added per Gaussian and count += 1 where tiles_touched > 0.
+gs_status launch_project_bwd(const gs_gaussians& g, const DevCam& cam, const int* radius, const float* g2d, bool rows,
+                             const uint32_t* tiles_touched, gs_densify_stats* stats, gs_gaussians_grad& grad,
+                             void* ws, hipStream_t s);
 size_t binsort_workspace(int64_t n, int64_t capacity, int tiles_x, int tiles_y);
 // Exclusive prefix sum of n uint32 values (out may alias in); sums holds
 // scan_sums_words(n) words, total (optional) receives the 64-bit sum.
@@ -140,10 +171,12 @@ gs_status launch_render_fwd(const gs_projected& proj, const uint32_t* point_list
 gs_status launch_render_count(const gs_projected& proj, const uint32_t* point_list, const uint32_t* ranges,
                               const DevCam& cam, unsigned long long* counts, hipStream_t s);
 size_t render_bwd_workspace(int64_t n, int64_t k, int ntiles, int deterministic);
+// g2d == NULL (atomic mode only): the sums stay in the accumulator rows,
+// returned in *rows_out (acc[n][kAccStride], before grad_scale).
 gs_status launch_render_bwd(int64_t n, const gs_projected& proj, const uint32_t* point_list, const uint32_t* ranges,
                             int64_t k, const DevCam& cam, const float* final_T,
                             const uint32_t* n_contrib, const float* t_ckpt, const float* dL_dimage, float* g2d, void* ws,
-                            size_t ws_bytes, int deterministic, int schedule, hipStream_t s);
+                            size_t ws_bytes, int deterministic, int schedule, const float** rows_out, hipStream_t s);
 gs_status launch_mlp_pack(const uint16_t* params, void* packed, hipStream_t s);
 gs_status launch_mlp_fwd(int64_t S, int per, const uint16_t* latents, const float* dirs, const void* packed,
                          float* rgb, hipStream_t s);
@@ -163,4 +196,7 @@ gs_status launch_adam(int64_t n, float* p, const float* g, float* m, float* v, u
                       float b2, float eps, float bc1, float bc2, hipStream_t s);
 gs_status launch_l1(const float* img, const float* target, int64_t count, float* loss, float* grad, float* partials,
                     hipStream_t s);
+gs_status launch_adam_gaussians(int64_t n, int sh_degree, const gs_param_arrays& p, const gs_gaussians_grad& g,
+                                const gs_param_arrays& m, const gs_param_arrays& v, const gs_adam_config& cfg,
+                                hipStream_t s);
 }  // namespace gs

@@ -77,8 +77,8 @@ gs_status launch_l1(const float* img, const float* target, int64_t count, float*
                     float* partials, hipStream_t s) {
   const int nb = static_cast<int>(std::min<int64_t>(kL1Blocks, ceil_div(count, 256)));
   const float inv = 1.0f / static_cast<float>(count);
-  k_l1_partial<<<nb, 256, 0, s>>>(img, target, count, inv, grad, partials);
-  k_l1_final<<<1, 256, 0, s>>>(partials, nb, inv, loss);
+  { TimedLaunch gs_tl("k_l1_partial", s); k_l1_partial<<<nb, 256, 0, s>>>(img, target, count, inv, grad, partials); }
+  { TimedLaunch gs_tl("k_l1_final", s); k_l1_final<<<1, 256, 0, s>>>(partials, nb, inv, loss); }
   return check_launch("k_l1");
 }
 

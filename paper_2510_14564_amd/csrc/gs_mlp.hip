@@ -300,7 +300,7 @@ static unsigned mlp_grid(int64_t S) {
 gs_status launch_mlp_pack(const uint16_t* params, void* packed, hipStream_t s) {
   uint4* ops = static_cast<uint4*>(packed);
   float* bias = reinterpret_cast<float*>(ops + kOps * 64);
-  k_mlp_pack<<<kOps, 64, 0, s>>>(params, ops, bias);
+  { TimedLaunch gs_tl("k_mlp_pack", s); k_mlp_pack<<<kOps, 64, 0, s>>>(params, ops, bias); }
   return check_launch("k_mlp_pack");
 }
 
@@ -313,16 +313,16 @@ gs_status launch_mlp_fwd(int64_t S, int per, const uint16_t* latents, const floa
                          float* rgb, hipStream_t s) {
   if (S == 0) return GS_OK;
   DevCam dummy{};
-  k_mlp_fwd<0><<<mlp_grid(S), 256, 0, s>>>(static_cast<int>(S), per, latents, dirs, nullptr, nullptr, dummy,
-                                           packed_ops(packed), packed_bias(packed), rgb, nullptr);
+  { TimedLaunch gs_tl("k_mlp_fwd<0>", s); k_mlp_fwd<0><<<mlp_grid(S), 256, 0, s>>>(static_cast<int>(S), per, latents, dirs, nullptr, nullptr, dummy,
+                                           packed_ops(packed), packed_bias(packed), rgb, nullptr); }
   return check_launch("k_mlp_fwd");
 }
 
 gs_status launch_mlp_render(int64_t n, const uint16_t* latents, const float* means, const int* radius,
                             const DevCam& cam, const void* packed, float* records, hipStream_t s) {
   if (n == 0) return GS_OK;
-  k_mlp_fwd<1><<<mlp_grid(n), 256, 0, s>>>(static_cast<int>(n), 1, latents, nullptr, means, radius, cam,
-                                           packed_ops(packed), packed_bias(packed), nullptr, records);
+  { TimedLaunch gs_tl("k_mlp_fwd<1>", s); k_mlp_fwd<1><<<mlp_grid(n), 256, 0, s>>>(static_cast<int>(n), 1, latents, nullptr, means, radius, cam,
+                                           packed_ops(packed), packed_bias(packed), nullptr, records); }
   return check_launch("k_mlp_render");
 }
 
@@ -719,8 +719,8 @@ size_t mlp_bwd_workspace(int64_t S, int per) {
 static gs_status reduce_partials(float* ws, int nwaves, float* dparams, float* loss, hipStream_t s) {
   const int chunks = static_cast<int>(ceil_div(nwaves, kReduceChunk));
   float* stage2 = ws + static_cast<size_t>(nwaves) * kPartStride;
-  k_mlp_reduce1<<<dim3(static_cast<unsigned>(ceil_div(kPartStride, 64)), chunks), 256, 0, s>>>(ws, nwaves, stage2);
-  k_mlp_reduce2<<<static_cast<unsigned>(ceil_div(kPartStride, 256)), 256, 0, s>>>(stage2, chunks, dparams, loss);
+  { TimedLaunch gs_tl("k_mlp_reduce1", s); k_mlp_reduce1<<<dim3(static_cast<unsigned>(ceil_div(kPartStride, 64)), chunks), 256, 0, s>>>(ws, nwaves, stage2); }
+  { TimedLaunch gs_tl("k_mlp_reduce2", s); k_mlp_reduce2<<<static_cast<unsigned>(ceil_div(kPartStride, 256)), 256, 0, s>>>(stage2, chunks, dparams, loss); }
   return check_launch("k_mlp_reduce");
 }
 
@@ -729,9 +729,9 @@ gs_status launch_mlp_bwd(int64_t S, int per, const uint16_t* latents, const floa
                          float* loss, void* ws, hipStream_t s) {
   const int waves = mlp_bwd_waves(S, per);
   DevCam dummy{};
-  k_mlp_bwd<0><<<waves / 4, 256, 0, s>>>(static_cast<int>(S), per, latents, dirs, nullptr, nullptr, dummy,
+  { TimedLaunch gs_tl("k_mlp_bwd<0>", s); k_mlp_bwd<0><<<waves / 4, 256, 0, s>>>(static_cast<int>(S), per, latents, dirs, nullptr, nullptr, dummy,
                                          packed_ops(packed), packed_bias(packed), dL_drgb, target, scale, dlat,
-                                         nullptr, static_cast<float*>(ws));
+                                         nullptr, static_cast<float*>(ws)); }
   gs_status st = check_launch("k_mlp_bwd");
   if (st != GS_OK) return st;
   return reduce_partials(static_cast<float*>(ws), waves, dparams, loss, s);
@@ -741,9 +741,9 @@ gs_status launch_mlp_render_bwd(int64_t n, const uint16_t* latents, const float*
                                 const DevCam& cam, const void* packed, const float* g2d, float* dlat,
                                 float* dmeans, float* dparams, void* ws, hipStream_t s) {
   const int waves = mlp_bwd_waves(n, 1);
-  k_mlp_bwd<1><<<waves / 4, 256, 0, s>>>(static_cast<int>(n), 1, latents, nullptr, means, radius, cam,
+  { TimedLaunch gs_tl("k_mlp_bwd<1>", s); k_mlp_bwd<1><<<waves / 4, 256, 0, s>>>(static_cast<int>(n), 1, latents, nullptr, means, radius, cam,
                                          packed_ops(packed), packed_bias(packed), g2d, nullptr, 0.0f, dlat, dmeans,
-                                         static_cast<float*>(ws));
+                                         static_cast<float*>(ws)); }
   gs_status st = check_launch("k_mlp_render_bwd");
   if (st != GS_OK) return st;
   return reduce_partials(static_cast<float*>(ws), waves, dparams, nullptr, s);
@@ -774,8 +774,8 @@ __global__ __launch_bounds__(256) void k_sh_colour(int S, int per, int n, int de
 gs_status launch_sh_colour(int64_t S, int per, int64_t n, int deg, const float* sh, const float* dirs, int clamp01,
                            float* out, hipStream_t s) {
   if (S == 0) return GS_OK;
-  k_sh_colour<<<static_cast<unsigned>(ceil_div(S, 256)), 256, 0, s>>>(static_cast<int>(S), per, static_cast<int>(n),
-                                                                      deg, sh, dirs, clamp01, out);
+  { TimedLaunch gs_tl("k_sh_colour", s); k_sh_colour<<<static_cast<unsigned>(ceil_div(S, 256)), 256, 0, s>>>(static_cast<int>(S), per, static_cast<int>(n),
+                                                                      deg, sh, dirs, clamp01, out); }
   return check_launch("k_sh_colour");
 }
 
@@ -805,7 +805,7 @@ __global__ __launch_bounds__(256) void k_adam(int64_t n, float* __restrict__ p, 
 gs_status launch_adam(int64_t n, float* p, const float* g, float* m, float* v, uint16_t* pb, float lr, float b1,
                       float b2, float eps, float bc1, float bc2, hipStream_t s) {
   if (n == 0) return GS_OK;
-  k_adam<<<static_cast<unsigned>(ceil_div(n, 256)), 256, 0, s>>>(n, p, g, m, v, pb, lr, b1, b2, eps, bc1, bc2);
+  { TimedLaunch gs_tl("k_adam", s); k_adam<<<static_cast<unsigned>(ceil_div(n, 256)), 256, 0, s>>>(n, p, g, m, v, pb, lr, b1, b2, eps, bc1, bc2); }
   return check_launch("k_adam");
 }
 

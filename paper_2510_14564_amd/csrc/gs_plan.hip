@@ -214,15 +214,15 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(int ntiles, const u
 
 gs_status launch_batch_plan(int ntiles, const uint32_t* ranges, const uint32_t* work, int light_max, int32_t* items,
                             int32_t* light, hipStream_t s) {
-  k_batch_plan<<<1, kPlanThreads, 0, s>>>(ntiles, reinterpret_cast<const uint2*>(ranges), work, light_max, items,
-                                          light);
+  { TimedLaunch gs_tl("k_batch_plan", s); k_batch_plan<<<1, kPlanThreads, 0, s>>>(ntiles, reinterpret_cast<const uint2*>(ranges), work, light_max, items,
+                                          light); }
   return check_launch("k_batch_plan");
 }
 
 gs_status launch_tile_plan(int ntiles, const uint32_t* ranges, const uint32_t* counts, float heavy_factor,
                            int light_max, int32_t* plan, hipStream_t s) {
-  k_tile_plan<<<1, kPlanThreads, 0, s>>>(ntiles, reinterpret_cast<const uint2*>(ranges), counts, heavy_factor,
-                                         light_max, plan);
+  { TimedLaunch gs_tl("k_tile_plan", s); k_tile_plan<<<1, kPlanThreads, 0, s>>>(ntiles, reinterpret_cast<const uint2*>(ranges), counts, heavy_factor,
+                                         light_max, plan); }
   return check_launch("k_tile_plan");
 }
 

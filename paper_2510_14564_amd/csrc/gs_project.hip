@@ -193,21 +193,21 @@ gs_status launch_project(const gs_gaussians& g, const DevCam& cam, gs_projected&
   const dim3 block(256), grid(static_cast<unsigned>(ceil_div(n, 256)));
   float4* rec = reinterpret_cast<float4*>(out.records);
   if (g.colour_mode == 1) {
-    k_project<-1><<<grid, block, 0, s>>>(n, g.means, g.log_scales, g.quats, g.logits, nullptr, cam, rec, out.depth,
-                                         out.radius, out.tiles_touched);
+    { TimedLaunch gs_tl("k_project<-1>", s); k_project<-1><<<grid, block, 0, s>>>(n, g.means, g.log_scales, g.quats, g.logits, nullptr, cam, rec, out.depth,
+                                         out.radius, out.tiles_touched); }
     gs_status st = check_launch("k_project");
     if (st != GS_OK) return st;
     return launch_mlp_render(n, g.latents, g.means, out.radius, cam, g.mlp, out.records, s);
   }
   switch (g.sh_degree) {
-    case 0: k_project<0><<<grid, block, 0, s>>>(n, g.means, g.log_scales, g.quats, g.logits, g.sh, cam, rec,
-                                                 out.depth, out.radius, out.tiles_touched); break;
-    case 1: k_project<1><<<grid, block, 0, s>>>(n, g.means, g.log_scales, g.quats, g.logits, g.sh, cam, rec,
-                                                 out.depth, out.radius, out.tiles_touched); break;
-    case 2: k_project<2><<<grid, block, 0, s>>>(n, g.means, g.log_scales, g.quats, g.logits, g.sh, cam, rec,
-                                                 out.depth, out.radius, out.tiles_touched); break;
-    default: k_project<3><<<grid, block, 0, s>>>(n, g.means, g.log_scales, g.quats, g.logits, g.sh, cam, rec,
-                                                  out.depth, out.radius, out.tiles_touched); break;
+    case 0: { TimedLaunch gs_tl("k_project<0>", s); k_project<0><<<grid, block, 0, s>>>(n, g.means, g.log_scales, g.quats, g.logits, g.sh, cam, rec,
+                                                 out.depth, out.radius, out.tiles_touched); } break;
+    case 1: { TimedLaunch gs_tl("k_project<1>", s); k_project<1><<<grid, block, 0, s>>>(n, g.means, g.log_scales, g.quats, g.logits, g.sh, cam, rec,
+                                                 out.depth, out.radius, out.tiles_touched); } break;
+    case 2: { TimedLaunch gs_tl("k_project<2>", s); k_project<2><<<grid, block, 0, s>>>(n, g.means, g.log_scales, g.quats, g.logits, g.sh, cam, rec,
+                                                 out.depth, out.radius, out.tiles_touched); } break;
+    default: { TimedLaunch gs_tl("k_project<3>", s); k_project<3><<<grid, block, 0, s>>>(n, g.means, g.log_scales, g.quats, g.logits, g.sh, cam, rec,
+                                                  out.depth, out.radius, out.tiles_touched); } break;
   }
   return check_launch("k_project");
 }
@@ -222,7 +222,14 @@ gs_status launch_project(const gs_gaussians& g, const DevCam& cam, gs_projected&
 //   Sigma = M M^T, M = R S:  dL/dM = 2 dL/dSigma M,
 //                     dL/ds_k = S_k (R^T dL/dM)_kk,  dL/dR = dL/dM S;
 //   R(q^) -> q^ -> q through the normalisation.
-template <int DEG>
+//
+// The record gradients come as g2d[9][n] (ROWS == false) or, straight from
+// the compositing backward, as its accumulator rows acc[n][kAccStride]
+// before the per-channel factors grad_scale (ROWS == true).  With stat_grad
+// non-NULL, the densification statistics of the view are accumulated:
+// stat_grad[i] += |(dL/du, dL/dv)| (pixel units) and stat_count[i] += 1 for
+// every Gaussian whose footprint meets a tile.
+template <int DEG, bool ROWS>
 __global__ __launch_bounds__(256) void k_project_bwd(int n, const float* __restrict__ means,
                                                      const float* __restrict__ log_scales,
                                                      const float* __restrict__ quats,
@@ -230,7 +237,10 @@ __global__ __launch_bounds__(256) void k_project_bwd(int n, const float* __restr
                                                      const float* __restrict__ sh, DevCam cam,
                                                      const float* __restrict__ g2d, float* __restrict__ g_means,
                                                      float* __restrict__ g_scales, float* __restrict__ g_quats,
-                                                     float* __restrict__ g_logits, float* __restrict__ g_sh) {
+                                                     float* __restrict__ g_logits, float* __restrict__ g_sh,
+                                                     const uint32_t* __restrict__ tiles_touched,
+                                                     float* __restrict__ stat_grad,
+                                                     uint32_t* __restrict__ stat_count) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   // DEG < 0: colour comes from the learned decoder, whose backward adds its
@@ -276,8 +286,20 @@ __global__ __launch_bounds__(256) void k_project_bwd(int n, const float* __restr
     return;
   }
   float G[GS_G2D];
+  if constexpr (ROWS) {
+    const float4* row = reinterpret_cast<const float4*>(g2d + static_cast<int64_t>(i) * kAccStride);
+    const float4 a = row[0], b = row[1], c = row[2];
+    const float v[GS_G2D] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x};
 #pragma unroll
-  for (int k = 0; k < GS_G2D; ++k) G[k] = g2d[k * n + i];
+    for (int k = 0; k < GS_G2D; ++k) G[k] = v[k] * grad_scale(k);
+  } else {
+#pragma unroll
+    for (int k = 0; k < GS_G2D; ++k) G[k] = g2d[k * n + i];
+  }
+  if (stat_grad && tiles_touched[i] > 0) {
+    stat_grad[i] += sqrtf(G[0] * G[0] + G[1] * G[1]);
+    stat_count[i] += 1u;
+  }
   float gm[3] = {0.0f, 0.0f, 0.0f};
 
   // ---- colour
@@ -390,22 +412,37 @@ __global__ __launch_bounds__(256) void k_project_bwd(int n, const float* __restr
   for (int k = 0; k < 3; ++k) g_means[k * n + i] = gm[k];
 }
 
-gs_status launch_project_bwd(const gs_gaussians& g, const DevCam& cam, const int* radius, const float* g2d,
-                             gs_gaussians_grad& gr, void* ws, hipStream_t s) {
+gs_status launch_project_bwd(const gs_gaussians& g, const DevCam& cam, const int* radius, const float* g2d, bool rows,
+                             const uint32_t* tiles_touched, gs_densify_stats* stats, gs_gaussians_grad& gr, void* ws,
+                             hipStream_t s) {
   const int n = static_cast<int>(g.n);
   if (n == 0) return GS_OK;
+  if (rows && g.colour_mode == 1) return fail(GS_ERR_INVALID_ARG, "projection backward: rows need SH colour");
   const dim3 block(256), grid(static_cast<unsigned>(ceil_div(n, 256)));
-#define GS_PB(D)                                                                                                \
-  k_project_bwd<D><<<grid, block, 0, s>>>(n, g.means, g.log_scales, g.quats, g.logits, g.sh, cam, g2d, gr.means, \
-                                          gr.log_scales, gr.quats, gr.logits, gr.sh)
-  if (g.colour_mode == 1) {
-    GS_PB(-1);
-  } else {
-    switch (g.sh_degree) {
-      case 0: GS_PB(0); break;
-      case 1: GS_PB(1); break;
-      case 2: GS_PB(2); break;
-      default: GS_PB(3); break;
+  float* sg = stats ? stats->grad_norm_sum : nullptr;
+  uint32_t* sc = stats ? stats->visible_count : nullptr;
+#define GS_PB(D, R)                                                                                               \
+  k_project_bwd<D, R><<<grid, block, 0, s>>>(n, g.means, g.log_scales, g.quats, g.logits, g.sh, cam, g2d,          \
+                                             gr.means, gr.log_scales, gr.quats, gr.logits, gr.sh, tiles_touched, \
+                                             sg, sc)
+  {
+    TimedLaunch gs_tl(g.colour_mode == 1 ? "k_project_bwd<-1>" : (rows ? "k_project_bwd<rows>" : "k_project_bwd"), s);
+    if (g.colour_mode == 1) {
+      GS_PB(-1, false);
+    } else if (rows) {
+      switch (g.sh_degree) {
+        case 0: GS_PB(0, true); break;
+        case 1: GS_PB(1, true); break;
+        case 2: GS_PB(2, true); break;
+        default: GS_PB(3, true); break;
+      }
+    } else {
+      switch (g.sh_degree) {
+        case 0: GS_PB(0, false); break;
+        case 1: GS_PB(1, false); break;
+        case 2: GS_PB(2, false); break;
+        default: GS_PB(3, false); break;
+      }
     }
   }
 #undef GS_PB

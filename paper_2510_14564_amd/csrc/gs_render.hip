@@ -24,7 +24,6 @@ namespace gs {
 constexpr int kBatch = 256;
 constexpr int kUnroll = 4;
 constexpr float kLog2e = 1.4426950408889634f;
-constexpr float kLn2 = 0.6931471805599453f;
 
 // Transmittance checkpoints: the forward stores every pixel's T at the start of
 // each 256-entry batch b >= 1 of its tile, in slot floor(S_t / 256) + t + b
@@ -446,18 +445,18 @@ gs_status launch_render_fwd(const gs_projected& proj, const uint32_t* point_list
     if (schedule == 2) {
       gs_status st = launch_tile_plan(ntiles, ranges, nullptr, kHeavyFactorFwd, kLightMax, plan, s);
       if (st != GS_OK) return st;
-      k_render_fwd_light<<<static_cast<unsigned>(ceil_div(ntiles, 4)), 256, 0, s>>>(
+      { TimedLaunch gs_tl("k_render_fwd_light", s); k_render_fwd_light<<<static_cast<unsigned>(ceil_div(ntiles, 4)), 256, 0, s>>>(
           reinterpret_cast<const uint2*>(ranges), point_list, reinterpret_cast<const float4*>(proj.records), cam,
-          image, final_T, n_contrib, plan, tile_work);
+          image, final_T, n_contrib, plan, tile_work); }
       st = check_launch("k_render_fwd_light");
       if (st != GS_OK) return st;
     } else {
       plan = nullptr;
     }
   }
-  k_render_fwd<false><<<ntiles, 256, 0, s>>>(reinterpret_cast<const uint2*>(ranges), point_list,
+  { TimedLaunch gs_tl("k_render_fwd<false>", s); k_render_fwd<false><<<ntiles, 256, 0, s>>>(reinterpret_cast<const uint2*>(ranges), point_list,
                                              reinterpret_cast<const float4*>(proj.records), cam, image, final_T,
-                                             n_contrib, t_ckpt, nullptr, plan, tile_work, c_ckpt, cplane);
+                                             n_contrib, t_ckpt, nullptr, plan, tile_work, c_ckpt, cplane); }
   return check_launch("k_render_fwd");
 }
 
@@ -466,9 +465,9 @@ gs_status launch_render_count(const gs_projected& proj, const uint32_t* point_li
   const int ntiles = cam.tiles_x * cam.tiles_y;
   gs_status st = check_hip(hipMemsetAsync(counts, 0, 2 * sizeof(unsigned long long), s), "hipMemsetAsync(counts)");
   if (st != GS_OK) return st;
-  k_render_fwd<true><<<ntiles, 256, 0, s>>>(reinterpret_cast<const uint2*>(ranges), point_list,
+  { TimedLaunch gs_tl("k_render_fwd<true>", s); k_render_fwd<true><<<ntiles, 256, 0, s>>>(reinterpret_cast<const uint2*>(ranges), point_list,
                                             reinterpret_cast<const float4*>(proj.records), cam, nullptr, nullptr,
-                                            nullptr, nullptr, counts, nullptr, nullptr, nullptr, 0);
+                                            nullptr, nullptr, counts, nullptr, nullptr, nullptr, 0); }
   return check_launch("k_render_count");
 }
 
@@ -557,15 +556,6 @@ __device__ __forceinline__ void bwd_terms(const float4& q, float cb, bool ok, fl
   v[7] = G1 * w;                             // dL/dg
   v[8] = G2 * w;                             // dL/db
 }
-
-// Factors that turn the summed terms of bwd_terms into the gradients.
-__device__ __forceinline__ float grad_scale(int c) {
-  constexpr float l1 = 2.0f * kLn2, l2 = 2.0f * kLn2 * kLn2;
-  return c < 2 ? l1 : (c == 3 ? l2 + l2 : (c < 5 ? l2 : 1.0f));
-}
-
-// Per-Gaussian gradient accumulator row: nine sums padded to one 64-byte line.
-constexpr int kAccStride = 16;
 
 // g2d[k][i] = acc[i][k]: the [9][n] output from the line-per-Gaussian rows.
 __global__ __launch_bounds__(256) void k_acc_to_g2d(int n, const float4* __restrict__ acc, float* __restrict__ g2d) {
@@ -927,8 +917,9 @@ size_t render_bwd_workspace(int64_t n, int64_t k, int ntiles, int deterministic)
 gs_status launch_render_bwd(int64_t n, const gs_projected& proj, const uint32_t* point_list, const uint32_t* ranges,
                             int64_t k, const DevCam& cam, const float* final_T,
                             const uint32_t* n_contrib, const float* t_ckpt, const float* dL_dimage, float* g2d, void* ws,
-                            size_t ws_bytes, int deterministic, int schedule, hipStream_t s) {
+                            size_t ws_bytes, int deterministic, int schedule, const float** rows_out, hipStream_t s) {
   (void)ws_bytes;
+  if (!g2d && (deterministic || !rows_out)) return fail(GS_ERR_INVALID_ARG, "render backward: no output");
   const int ntiles = cam.tiles_x * cam.tiles_y;
   char* w = static_cast<char*>(ws);
   float* acc = reinterpret_cast<float*>(w + bwd_acc_offset(k, ntiles));
@@ -941,33 +932,35 @@ gs_status launch_render_bwd(int64_t n, const gs_projected& proj, const uint32_t*
   if (deterministic) {
     det = carve_det(acc, n, k, nullptr);
     acc = nullptr;
-    k_det_count<<<gn, 256, 0, s>>>(static_cast<int>(n), rec, proj.radius, cam.tiles_x, cam.tiles_y, det.cnt);
+    { TimedLaunch gs_tl("k_det_count", s); k_det_count<<<gn, 256, 0, s>>>(static_cast<int>(n), rec, proj.radius, cam.tiles_x, cam.tiles_y, det.cnt); }
     if ((st = check_launch("k_det_count")) != GS_OK) return st;
     if ((st = launch_exclusive_scan(det.cnt, det.base, n, det.sums, nullptr, s)) != GS_OK) return st;
-    k_det_rows<<<gn, 256, 0, s>>>(static_cast<int>(n), rec, proj.radius, cam.tiles_x, cam.tiles_y, det.base,
-                                  det.row_of);
+    { TimedLaunch gs_tl("k_det_rows", s); k_det_rows<<<gn, 256, 0, s>>>(static_cast<int>(n), rec, proj.radius, cam.tiles_x, cam.tiles_y, det.base,
+                                  det.row_of); }
     if ((st = check_launch("k_det_rows")) != GS_OK) return st;
     if (det.part_floats) {
       const int64_t n4 = static_cast<int64_t>(det.part_floats / 4);
-      k_zero4<<<static_cast<unsigned>(std::min<int64_t>(ceil_div(n4, 256), 8192)), 256, 0, s>>>(
-          reinterpret_cast<float4*>(det.part), n4);
+      { TimedLaunch gs_tl("k_zero4", s); k_zero4<<<static_cast<unsigned>(std::min<int64_t>(ceil_div(n4, 256), 8192)), 256, 0, s>>>(
+          reinterpret_cast<float4*>(det.part), n4); }
       if ((st = check_launch("k_zero4")) != GS_OK) return st;
     }
   } else {
-    st = check_hip(hipMemsetAsync(acc, 0, sizeof(float) * kAccStride * static_cast<size_t>(n), s),
-                   "hipMemsetAsync(acc)");
-    if (st != GS_OK) return st;
+    // a fill kernel rather than a memset node, so that the call can be captured in a graph
+    const int64_t n4 = static_cast<int64_t>(kAccStride / 4) * n;
+    { TimedLaunch gs_tl("k_zero4", s); k_zero4<<<static_cast<unsigned>(std::min<int64_t>(ceil_div(n4, 256), 8192)), 256, 0, s>>>(
+        reinterpret_cast<float4*>(acc), n4); }
+    if ((st = check_launch("k_zero4")) != GS_OK) return st;
   }
   auto bwd = [&](unsigned grid, const int32_t* items, const uint32_t* tile_work, const float* c_ckpt,
                  size_t cplane) {
     if (deterministic)
-      k_render_bwd<true><<<grid, 256, 0, s>>>(rg, point_list, rec, cam, final_T, n_contrib, t_ckpt, dL_dimage,
+      { TimedLaunch gs_tl("k_render_bwd<true>", s); k_render_bwd<true><<<grid, 256, 0, s>>>(rg, point_list, rec, cam, final_T, n_contrib, t_ckpt, dL_dimage,
                                               static_cast<int>(n), acc, nullptr, items, tile_work, c_ckpt, cplane,
-                                              det.part, det.row_of, rows);
+                                              det.part, det.row_of, rows); }
     else
-      k_render_bwd<false><<<grid, 256, 0, s>>>(rg, point_list, rec, cam, final_T, n_contrib, t_ckpt, dL_dimage,
+      { TimedLaunch gs_tl("k_render_bwd<false>", s); k_render_bwd<false><<<grid, 256, 0, s>>>(rg, point_list, rec, cam, final_T, n_contrib, t_ckpt, dL_dimage,
                                                static_cast<int>(n), acc, nullptr, items, tile_work, c_ckpt, cplane,
-                                               nullptr, nullptr, 0);
+                                               nullptr, nullptr, 0); }
     return check_launch("k_render_bwd");
   };
   if (schedule == 0) {
@@ -985,11 +978,11 @@ gs_status launch_render_bwd(int64_t n, const gs_projected& proj, const uint32_t*
     if (light) {
       const unsigned lg = static_cast<unsigned>(ceil_div(ntiles, 4));
       if (deterministic)
-        k_render_bwd_light<true><<<lg, 256, 0, s>>>(rg, point_list, rec, cam, final_T, n_contrib, dL_dimage,
-                                                    static_cast<int>(n), acc, light, det.part, det.row_of, rows);
+        { TimedLaunch gs_tl("k_render_bwd_light<true>", s); k_render_bwd_light<true><<<lg, 256, 0, s>>>(rg, point_list, rec, cam, final_T, n_contrib, dL_dimage,
+                                                    static_cast<int>(n), acc, light, det.part, det.row_of, rows); }
       else
-        k_render_bwd_light<false><<<lg, 256, 0, s>>>(rg, point_list, rec, cam, final_T, n_contrib, dL_dimage,
-                                                     static_cast<int>(n), acc, light, nullptr, nullptr, 0);
+        { TimedLaunch gs_tl("k_render_bwd_light<false>", s); k_render_bwd_light<false><<<lg, 256, 0, s>>>(rg, point_list, rec, cam, final_T, n_contrib, dL_dimage,
+                                                     static_cast<int>(n), acc, light, nullptr, nullptr, 0); }
       st = check_launch("k_render_bwd_light");
       if (st != GS_OK) return st;
     }
@@ -997,10 +990,14 @@ gs_status launch_render_bwd(int64_t n, const gs_projected& proj, const uint32_t*
   }
   if (st != GS_OK) return st;
   if (deterministic) {
-    k_det_reduce<<<gn, 256, 0, s>>>(static_cast<int>(n), det.cnt, det.base, det.part, rows, g2d);
+    { TimedLaunch gs_tl("k_det_reduce", s); k_det_reduce<<<gn, 256, 0, s>>>(static_cast<int>(n), det.cnt, det.base, det.part, rows, g2d); }
     return check_launch("k_det_reduce");
   }
-  k_acc_to_g2d<<<gn, 256, 0, s>>>(static_cast<int>(n), reinterpret_cast<const float4*>(acc), g2d);
+  if (!g2d) {
+    *rows_out = acc;
+    return GS_OK;
+  }
+  { TimedLaunch gs_tl("k_acc_to_g2d", s); k_acc_to_g2d<<<gn, 256, 0, s>>>(static_cast<int>(n), reinterpret_cast<const float4*>(acc), g2d); }
   return check_launch("k_acc_to_g2d");
 }
 

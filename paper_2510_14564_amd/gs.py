@@ -35,9 +35,10 @@ STATUS_NAMES = {0: "GS_OK", -1: "GS_ERR_INVALID_ARG", -2: "GS_ERR_CAPACITY", -3:
 
 # every symbol declared in include/gsplat.h
 EXPORTS = ("gs_last_error", "gs_version", "gs_project", "gs_bin_sort_workspace", "gs_bin_sort", "gs_bin_sort_async",
-           "gs_render_fwd", "gs_render_count", "gs_render_ckpt_floats", "gs_render_bwd_workspace", "gs_render_bwd", "gs_project_bwd",
-           "gs_project_bwd_workspace", "gs_l1_loss", "gs_mlp_pack", "gs_mlp_fwd", "gs_mlp_bwd_workspace",
-           "gs_mlp_bwd", "gs_sh_colour", "gs_adam_step")
+           "gs_render_fwd", "gs_render_count", "gs_render_ckpt_floats", "gs_render_bwd_workspace", "gs_render_bwd",
+           "gs_render_bwd_2d_workspace", "gs_render_bwd_2d", "gs_project_bwd", "gs_project_bwd_workspace",
+           "gs_adam_gaussians", "gs_l1_loss", "gs_mlp_pack", "gs_mlp_fwd", "gs_mlp_bwd_workspace", "gs_mlp_bwd",
+           "gs_sh_colour", "gs_adam_step", "gs_kernel_timer_start", "gs_kernel_timer_stop")
 
 
 class GsError(RuntimeError):
@@ -71,6 +72,22 @@ class GaussiansGrad(ctypes.Structure):
                 ("mlp", ctypes.c_void_p)]
 
 
+class DensifyStats(ctypes.Structure):
+    _fields_ = [("grad_norm_sum", ctypes.c_void_p), ("visible_count", ctypes.c_void_p)]
+
+
+class ParamArrays(ctypes.Structure):
+    _fields_ = [("means", ctypes.c_void_p), ("log_scales", ctypes.c_void_p), ("quats", ctypes.c_void_p),
+                ("logits", ctypes.c_void_p), ("sh", ctypes.c_void_p)]
+
+
+class AdamConfig(ctypes.Structure):
+    _fields_ = [("lr_means", ctypes.c_float), ("lr_log_scales", ctypes.c_float), ("lr_quats", ctypes.c_float),
+                ("lr_logits", ctypes.c_float), ("lr_sh_dc", ctypes.c_float), ("lr_sh_rest", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("step", ctypes.c_int32)]
+
+
 _vp, _i64, _i32, _sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
 _P = ctypes.POINTER
 _sigs = {
@@ -84,9 +101,16 @@ _sigs = {
                       ctypes.c_int),
     "gs_render_ckpt_floats": ([_i64, _P(Camera), _P(_sz)], ctypes.c_int),
     "gs_render_count": ([_i64, _P(Projected), _vp, _vp, _i64, _P(Camera), _vp, _vp], ctypes.c_int),
-    "gs_render_bwd_workspace": ([_i64, _i64, _P(Camera), _i32, _P(_sz)], ctypes.c_int),
-    "gs_render_bwd": ([_i64, _P(Projected), _vp, _vp, _i64, _P(Camera), _vp, _vp, _vp, _vp, _vp, _vp, _sz, _i32,
-                       _i32, _vp], ctypes.c_int),
+    "gs_render_bwd_workspace": ([_P(Gaussians), _i64, _P(Camera), _i32, _P(_sz)], ctypes.c_int),
+    "gs_render_bwd": ([_P(Gaussians), _P(Camera), _P(Projected), _vp, _vp, _i64, _vp, _vp, _vp, _vp,
+                       _P(GaussiansGrad), _P(DensifyStats), _vp, _sz, _i32, _i32, _vp], ctypes.c_int),
+    "gs_render_bwd_2d_workspace": ([_i64, _i64, _P(Camera), _i32, _P(_sz)], ctypes.c_int),
+    "gs_render_bwd_2d": ([_i64, _P(Projected), _vp, _vp, _i64, _P(Camera), _vp, _vp, _vp, _vp, _vp, _vp, _sz, _i32,
+                          _i32, _vp], ctypes.c_int),
+    "gs_kernel_timer_start": ([], ctypes.c_int),
+    "gs_kernel_timer_stop": ([ctypes.c_char_p, _sz, _P(_sz)], ctypes.c_int),
+    "gs_adam_gaussians": ([_i64, _i32, _P(ParamArrays), _P(GaussiansGrad), _P(ParamArrays), _P(ParamArrays),
+                           _P(AdamConfig), _vp], ctypes.c_int),
     "gs_project_bwd_workspace": ([_P(Gaussians), _P(_sz)], ctypes.c_int),
     "gs_project_bwd": ([_P(Gaussians), _P(Camera), _P(Projected), _vp, _P(GaussiansGrad), _vp, _sz, _vp],
                        ctypes.c_int),
@@ -245,19 +269,73 @@ def render_ckpt_floats(k: int, cam: Camera) -> int:
     return int(f.value)
 
 
-def render_bwd_workspace(n: int, k: int, cam: Camera, deterministic: bool) -> int:
+def render_bwd_2d_workspace(n: int, k: int, cam: Camera, deterministic: bool) -> int:
     b = ctypes.c_size_t(0)
-    _check(_lib.gs_render_bwd_workspace(n, k, ctypes.byref(cam), int(deterministic), ctypes.byref(b)),
-           "gs_render_bwd_workspace")
+    _check(_lib.gs_render_bwd_2d_workspace(n, k, ctypes.byref(cam), int(deterministic), ctypes.byref(b)),
+           "gs_render_bwd_2d_workspace")
     return int(b.value)
 
 
-def render_bwd(n: int, proj: ProjectedBuffers, point_list, ranges, k: int, cam: Camera, final_T, n_contrib, t_ckpt,
-               dL_dimage, g2d, ws, deterministic: bool = False, schedule=SCHEDULE_BALANCED, stream=None):
-    _check(_lib.gs_render_bwd(n, ctypes.byref(proj.struct()), _ptr(point_list), _ptr(ranges), k, ctypes.byref(cam),
-                              _ptr(final_T), _ptr(n_contrib), _ptr(t_ckpt), _ptr(dL_dimage), _ptr(g2d), _ptr(ws),
-                              ws.numel() * ws.element_size(), int(deterministic), int(schedule), _stream(stream)),
+def render_bwd_2d(n: int, proj: ProjectedBuffers, point_list, ranges, k: int, cam: Camera, final_T, n_contrib, t_ckpt,
+                  dL_dimage, g2d, ws, deterministic: bool = False, schedule=SCHEDULE_BALANCED, stream=None):
+    """Compositing backward only: record gradients g2d[9][n] (Sigma' form)."""
+    _check(_lib.gs_render_bwd_2d(n, ctypes.byref(proj.struct()), _ptr(point_list), _ptr(ranges), k,
+                                 ctypes.byref(cam), _ptr(final_T), _ptr(n_contrib), _ptr(t_ckpt), _ptr(dL_dimage),
+                                 _ptr(g2d), _ptr(ws), ws.numel() * ws.element_size(), int(deterministic),
+                                 int(schedule), _stream(stream)), "gs_render_bwd_2d")
+
+
+def render_bwd_workspace(gauss: Gaussians, k: int, cam: Camera, deterministic: bool) -> int:
+    b = ctypes.c_size_t(0)
+    _check(_lib.gs_render_bwd_workspace(ctypes.byref(gauss), k, ctypes.byref(cam), int(deterministic),
+                                        ctypes.byref(b)), "gs_render_bwd_workspace")
+    return int(b.value)
+
+
+def _grad_struct(grads: dict) -> GaussiansGrad:
+    gg = GaussiansGrad()
+    gg.means, gg.log_scales, gg.quats, gg.logits = (_ptr(grads["means"]), _ptr(grads["log_scales"]),
+                                                    _ptr(grads["quats"]), _ptr(grads["logits"]))
+    gg.sh, gg.latents, gg.mlp = _ptr(grads.get("sh")), _ptr(grads.get("latents")), _ptr(grads.get("mlp"))
+    return gg
+
+
+def render_bwd(gauss: Gaussians, cam: Camera, proj: ProjectedBuffers, point_list, ranges, k: int, final_T, n_contrib,
+               t_ckpt, dL_dimage, grads: dict, ws, stats=None, deterministic: bool = False,
+               schedule=SCHEDULE_BALANCED, stream=None):
+    """Full backward, dL/dimage -> parameter gradients (grads keyed like
+    project_bwd's).  stats: optional (grad_norm_sum float32[n],
+    visible_count int32[n]) accumulated in place."""
+    st = None
+    if stats is not None:
+        st = DensifyStats()
+        st.grad_norm_sum, st.visible_count = _ptr(stats[0]), _ptr(stats[1])
+    _check(_lib.gs_render_bwd(ctypes.byref(gauss), ctypes.byref(cam), ctypes.byref(proj.struct()), _ptr(point_list),
+                              _ptr(ranges), k, _ptr(final_T), _ptr(n_contrib), _ptr(t_ckpt), _ptr(dL_dimage),
+                              ctypes.byref(_grad_struct(grads)), ctypes.byref(st) if st is not None else None,
+                              _ptr(ws), _nbytes(ws), int(deterministic), int(schedule), _stream(stream)),
            "gs_render_bwd")
+
+
+def _param_struct(d: dict) -> ParamArrays:
+    pa = ParamArrays()
+    pa.means, pa.log_scales, pa.quats, pa.logits, pa.sh = (_ptr(d["means"]), _ptr(d["log_scales"]),
+                                                           _ptr(d["quats"]), _ptr(d["logits"]), _ptr(d["sh"]))
+    return pa
+
+
+def adam_gaussians(n: int, sh_degree: int, params: dict, grads: dict, m: dict, v: dict, lrs: dict, step: int,
+                   beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-15, stream=None):
+    """One fused Adam step over every parameter array (updated in place).
+    lrs: learning rates keyed means, log_scales, quats, logits, sh_dc, sh_rest."""
+    cfg = AdamConfig()
+    cfg.lr_means, cfg.lr_log_scales, cfg.lr_quats = lrs["means"], lrs["log_scales"], lrs["quats"]
+    cfg.lr_logits, cfg.lr_sh_dc, cfg.lr_sh_rest = lrs["logits"], lrs["sh_dc"], lrs["sh_rest"]
+    cfg.beta1, cfg.beta2, cfg.eps, cfg.step = beta1, beta2, eps, int(step)
+    _check(_lib.gs_adam_gaussians(n, sh_degree, ctypes.byref(_param_struct(params)),
+                                  ctypes.byref(_grad_struct(grads)), ctypes.byref(_param_struct(m)),
+                                  ctypes.byref(_param_struct(v)), ctypes.byref(cfg), _stream(stream)),
+           "gs_adam_gaussians")
 
 
 def project_bwd_workspace(gauss: Gaussians) -> int:
@@ -274,13 +352,10 @@ def project_bwd(gauss: Gaussians, cam: Camera, g2d, grads: dict, proj: Projected
                 stream=None):
     """grads: device tensors keyed like the parameters ("sh" for SH colour,
     "latents" [n][16] and "mlp" [MLP_PARAMS] FP32 for the learned colour)."""
-    gg = GaussiansGrad()
-    gg.means, gg.log_scales, gg.quats, gg.logits = (_ptr(grads["means"]), _ptr(grads["log_scales"]),
-                                                    _ptr(grads["quats"]), _ptr(grads["logits"]))
-    gg.sh, gg.latents, gg.mlp = _ptr(grads.get("sh")), _ptr(grads.get("latents")), _ptr(grads.get("mlp"))
     ps = ctypes.byref(proj.struct()) if proj is not None else None
-    _check(_lib.gs_project_bwd(ctypes.byref(gauss), ctypes.byref(cam), ps, _ptr(g2d), ctypes.byref(gg), _ptr(ws),
-                               _nbytes(ws), _stream(stream)), "gs_project_bwd")
+    _check(_lib.gs_project_bwd(ctypes.byref(gauss), ctypes.byref(cam), ps, _ptr(g2d),
+                               ctypes.byref(_grad_struct(grads)), _ptr(ws), _nbytes(ws), _stream(stream)),
+           "gs_project_bwd")
 
 
 def l1_loss(img, target, loss, grad, partials, stream=None):
@@ -340,3 +415,28 @@ def adam_step(param, grad, m, v, lr: float, step: int, beta1: float = 0.9, beta2
               param_bf16=None, stream=None):
     _check(_lib.gs_adam_step(param.numel(), _ptr(param), _ptr(grad), _ptr(m), _ptr(v), _ptr(param_bf16), float(lr),
                              float(beta1), float(beta2), float(eps), int(step), _stream(stream)), "gs_adam_step")
+
+
+# ------------------------------------------------------------ measurement
+
+def kernel_timer_start():
+    """Time every kernel the library launches from this thread (HIP events
+    on the launch stream) until kernel_timer_stop."""
+    _check(_lib.gs_kernel_timer_start(), "gs_kernel_timer_start")
+
+
+def kernel_timer_stop() -> dict:
+    """Stop the timer: {kernel name: (launches, total ms)} in first-launch order."""
+    size = 1 << 20
+    buf = ctypes.create_string_buffer(size)
+    need = ctypes.c_size_t(0)
+    _check(_lib.gs_kernel_timer_stop(buf, size, ctypes.byref(need)), "gs_kernel_timer_stop")
+    if need.value > size:
+        raise RuntimeError("kernel timer report truncated")
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, count, ms = line.rsplit(" ", 2)
+        out[name] = (int(count), float(ms))
+    return out
+
+

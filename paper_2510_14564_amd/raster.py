@@ -1,12 +1,15 @@
 """Differentiable tile rasterisation as a torch.autograd.Function over the C ABI.
 
 forward : gs_project -> gs_bin_sort -> gs_render_fwd
-backward: gs_render_bwd -> gs_project_bwd
+backward: gs_render_bwd (compositing backward + projection backward)
 The saved state per call is the projection, the sorted list, the tile ranges,
-the final transmittance and per-pixel contributor counts; nothing per
-(pixel, Gaussian) pair is stored -- the backward recomputes transmittance.
-Buffers are kept in a Rasterizer and reused across iterations; the (tile,
-Gaussian) capacity grows on demand (the library reports the size it needs).
+the final transmittance, per-pixel contributor counts and the batch-boundary
+transmittance checkpoints; nothing per (pixel, Gaussian) pair is stored --
+the backward recomputes transmittance.  Each forward gets its own output
+buffers (from PyTorch's caching allocator, so no device allocation once warm)
+and its camera; the Rasterizer keeps the scratch workspaces and the (tile,
+Gaussian) capacity, which grows on demand (the library reports the size it
+needs).
 The colour comes from SH coefficients (a tensor) or from the learned decoder
 (a decoder.LearnedColour: BF16 latents + packed weights, colour_mode 1).
 """
@@ -23,8 +26,13 @@ from .decoder import LearnedColour
 
 @dataclasses.dataclass
 class FrameState:
+    """One forward's outputs, kept for its backward.  Every frame owns its
+    buffers and its camera, so several frames can be alive at once (views
+    summed into one loss); the rasterizer only shares scratch workspaces,
+    which each call uses on the stream and leaves."""
     n: int
     k: int
+    cs: gs.Camera
     proj: gs.ProjectedBuffers
     point_list: torch.Tensor
     ranges: torch.Tensor
@@ -35,7 +43,7 @@ class FrameState:
 
 
 class Rasterizer:
-    """Holds device buffers for one camera resolution and one Gaussian count."""
+    """Buffers and settings for one camera resolution and one Gaussian count."""
 
     def __init__(self, cam, sh_degree: int, device="cuda", deterministic: bool = False, capacity: int | None = None,
                  schedule: int = gs.SCHEDULE_BALANCED, async_k: bool = False):
@@ -58,18 +66,12 @@ class Rasterizer:
         self.ntiles = gs.n_tiles(cam)
         self._cap = capacity
         self._n = None
-        self.proj = None
-        self.point_list = None
+        self._ckpt_floats = 0
         self.bin_ws = None
         self.bwd_ws = None
-        self.pbwd_ws = None
-        self.t_ckpt = None
-        H, W = cam.height, cam.width
-        self.ranges = torch.empty((self.ntiles, 2), dtype=torch.int32, device=self.device)
-        self.image = torch.empty((3, H, W), dtype=torch.float32, device=self.device)
-        self.final_T = torch.empty((H, W), dtype=torch.float32, device=self.device)
-        self.n_contrib = torch.empty((H, W), dtype=torch.int32, device=self.device)
+        self.stats = None          # optional (grad_norm_sum, visible_count), see enable_densify_stats
         self.timer = None          # optional callable(stage_name) -> context manager
+        self.last_frame = None     # the latest forward's FrameState (for inspection)
 
     def _stage(self, name):
         return self.timer(name) if self.timer is not None else contextlib.nullcontext()
@@ -77,14 +79,12 @@ class Rasterizer:
     def _ensure(self, n: int):
         if self._n != n:
             self._n = n
-            self.proj = gs.ProjectedBuffers(n, self.device)
             if self._cap is None:
                 self._cap = max(1024, 8 * n)
             self._alloc_lists(self._cap)
 
     def _alloc_lists(self, cap: int):
         self._cap = cap
-        self.point_list = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
         ws = gs.bin_sort_workspace(self._n, cap, self.cs)
         self.bin_ws = torch.empty(ws, dtype=torch.uint8, device=self.device)
 
@@ -92,6 +92,14 @@ class Rasterizer:
         assert cam.width == self.cam.width and cam.height == self.cam.height
         self.cam = cam
         self.cs = gs.camera_struct(cam)
+
+    def enable_densify_stats(self, n: int):
+        """Accumulate densification statistics over the following backwards:
+        (sum over views of |dL/d(u, v)|, number of views that see the
+        Gaussian).  Returns the two tensors (zeroed)."""
+        self.stats = (torch.zeros(n, dtype=torch.float32, device=self.device),
+                      torch.zeros(n, dtype=torch.int32, device=self.device))
+        return self.stats
 
     def _gauss(self, means, log_scales, quats, logits, colour) -> gs.Gaussians:
         if isinstance(colour, LearnedColour):
@@ -101,18 +109,24 @@ class Rasterizer:
     def forward(self, means, log_scales, quats, logits, colour) -> FrameState:
         n = means.shape[1]
         self._ensure(n)
+        dev = self.device
+        cs = self.cs
         g = self._gauss(means, log_scales, quats, logits, colour)
+        proj = gs.ProjectedBuffers(n, dev)
         with self._stage("project"):
-            gs.project(g, self.cs, self.proj)
+            gs.project(g, cs, proj)
+        ranges = torch.empty((self.ntiles, 2), dtype=torch.int32, device=dev)
         k = None
+        point_list = None
         if self.async_k and self.last_k is not None:
             self.check_async()
             if self.k_dev is None:
-                self.k_dev = torch.zeros(2, dtype=torch.int64, device=self.device)
+                self.k_dev = torch.zeros(2, dtype=torch.int64, device=dev)
                 self.k_host = torch.zeros(2, dtype=torch.int64, pin_memory=True)
+            point_list = torch.empty(max(self._cap, 1), dtype=torch.int32, device=dev)
             try:
                 with self._stage("bin_sort"):
-                    gs.bin_sort_async(n, self.proj, self.cs, self.bin_ws, self.point_list, self.ranges, self.k_dev)
+                    gs.bin_sort_async(n, proj, cs, self.bin_ws, point_list, ranges, self.k_dev)
                 self.k_host.copy_(self.k_dev, non_blocking=True)
                 self._k_event = torch.cuda.Event()
                 self._k_event.record()
@@ -122,23 +136,30 @@ class Rasterizer:
                     raise
                 self.async_k = False           # frame too large for the direct emission
         while k is None:
+            if point_list is None or point_list.numel() < self._cap:
+                point_list = torch.empty(max(self._cap, 1), dtype=torch.int32, device=dev)
             try:
                 with self._stage("bin_sort"):
-                    k = gs.bin_sort(n, self.proj, self.cs, self.bin_ws, self.point_list, self.ranges)
+                    k = gs.bin_sort(n, proj, cs, self.bin_ws, point_list, ranges)
             except gs.GsError as e:
                 if e.status != gs.GS_ERR_CAPACITY:
                     raise
                 self._alloc_lists(int(e.required * 1.25) + 1024)
             else:
                 self.last_k = k
-        need = gs.render_ckpt_floats(k, self.cs)
-        if self.t_ckpt is None or self.t_ckpt.numel() < need:
-            self.t_ckpt = torch.empty(int(need * 1.25), dtype=torch.float32, device=self.device)
+        need = gs.render_ckpt_floats(k, cs)
+        if need > self._ckpt_floats:
+            self._ckpt_floats = int(need * 1.25)
+        H, W = self.cam.height, self.cam.width
+        image = torch.empty((3, H, W), dtype=torch.float32, device=dev)
+        final_T = torch.empty((H, W), dtype=torch.float32, device=dev)
+        n_contrib = torch.empty((H, W), dtype=torch.int32, device=dev)
+        t_ckpt = torch.empty(self._ckpt_floats, dtype=torch.float32, device=dev)
         with self._stage("render_fwd"):
-            gs.render_fwd(n, self.proj, self.point_list, self.ranges, k, self.cs, self.image, self.final_T,
-                          self.n_contrib, self.t_ckpt, schedule=self.schedule)
-        return FrameState(n, k, self.proj, self.point_list, self.ranges, self.image, self.final_T, self.n_contrib,
-                          self.t_ckpt)
+            gs.render_fwd(n, proj, point_list, ranges, k, cs, image, final_T, n_contrib, t_ckpt,
+                          schedule=self.schedule)
+        self.last_frame = FrameState(n, k, cs, proj, point_list, ranges, image, final_T, n_contrib, t_ckpt)
+        return self.last_frame
 
     def check_async(self) -> int | None:
         """Check the last frame binned without a host wait: returns its K, or
@@ -160,33 +181,27 @@ class Rasterizer:
         self.last_k = K
         return K
 
-    def backward(self, st: FrameState, means, log_scales, quats, logits, colour, dL_dimage, g2d=None):
+    def backward(self, st: FrameState, means, log_scales, quats, logits, colour, dL_dimage) -> dict:
+        """Parameter gradients of sum(dL_dimage * image) for frame st."""
         n = st.n
         dL_dimage = dL_dimage.contiguous()
-        need = gs.render_bwd_workspace(n, st.k, self.cs, self.deterministic)
+        g = self._gauss(means, log_scales, quats, logits, colour)
+        need = gs.render_bwd_workspace(g, st.k, st.cs, self.deterministic)
         if self.bwd_ws is None or self.bwd_ws.numel() < need:
             self.bwd_ws = torch.empty(need, dtype=torch.uint8, device=self.device)
-        if g2d is None:
-            g2d = torch.empty((gs.G2D, n), dtype=torch.float32, device=self.device)
-        with self._stage("render_bwd"):
-            gs.render_bwd(n, st.proj, st.point_list, st.ranges, st.k, self.cs, st.final_T, st.n_contrib, st.t_ckpt,
-                          dL_dimage, g2d, self.bwd_ws, self.deterministic, schedule=self.schedule)
         grads = {k: torch.empty_like(v) for k, v in
                  (("means", means), ("log_scales", log_scales), ("quats", quats), ("logits", logits))}
-        g = self._gauss(means, log_scales, quats, logits, colour)
-        ws = None
         if isinstance(colour, LearnedColour):
             grads["latents"] = torch.empty((n, 16), dtype=torch.float32, device=self.device)
             grads["mlp"] = torch.empty(gs.MLP_PARAMS, dtype=torch.float32, device=self.device)
-            need = gs.project_bwd_workspace(g)
-            if self.pbwd_ws is None or self.pbwd_ws.numel() < need:
-                self.pbwd_ws = torch.empty(need, dtype=torch.uint8, device=self.device)
-            ws = self.pbwd_ws
         else:
             grads["sh"] = torch.empty_like(colour)
-        with self._stage("project_bwd"):
-            gs.project_bwd(g, self.cs, g2d, grads, proj=st.proj, ws=ws)
-        return grads, g2d
+        stats = self.stats if (self.stats is not None and self.stats[0].numel() == n) else None
+        with self._stage("render_bwd"):
+            gs.render_bwd(g, st.cs, st.proj, st.point_list, st.ranges, st.k, st.final_T, st.n_contrib, st.t_ckpt,
+                          dL_dimage, grads, self.bwd_ws, stats=stats, deterministic=self.deterministic,
+                          schedule=self.schedule)
+        return grads
 
 
 class _RasterizeFn(torch.autograd.Function):
@@ -200,13 +215,12 @@ class _RasterizeFn(torch.autograd.Function):
         st = rast.forward(means, log_scales, quats, logits, colour)
         ctx.rast, ctx.st, ctx.colour = rast, st, colour
         ctx.save_for_backward(means, log_scales, quats, logits)
-        # the rasterizer reuses its image buffer next call: hand autograd a copy
-        return st.image.clone()
+        return st.image
 
     @staticmethod
     def backward(ctx, dL_dimage):
         means, log_scales, quats, logits = ctx.saved_tensors
-        grads, _ = ctx.rast.backward(ctx.st, means, log_scales, quats, logits, ctx.colour, dL_dimage)
+        grads = ctx.rast.backward(ctx.st, means, log_scales, quats, logits, ctx.colour, dL_dimage)
         if isinstance(ctx.colour, LearnedColour):
             gc0, gc1 = grads["latents"], grads["mlp"]
         else:

@@ -98,14 +98,28 @@ def test_workspace_queries_are_host_only(gs):
     assert gs._lib.gs_bin_sort_workspace(4096, 40000, ctypes.byref(c), ctypes.byref(b2)) == gs.GS_OK
     assert b2.value > b.value
     assert gs._lib.gs_bin_sort_workspace(-1, 0, ctypes.byref(c), ctypes.byref(b)) == gs.GS_ERR_INVALID_ARG
-    assert gs._lib.gs_render_bwd_workspace(10, 10, ctypes.byref(c), 0, ctypes.byref(b)) == gs.GS_OK
+    assert gs._lib.gs_render_bwd_2d_workspace(10, 10, ctypes.byref(c), 0, ctypes.byref(b)) == gs.GS_OK
     # the deterministic reduction holds a 36-byte row per entry
     d1, d2 = ctypes.c_size_t(0), ctypes.c_size_t(0)
-    assert gs._lib.gs_render_bwd_workspace(1000, 100000, ctypes.byref(c), 1, ctypes.byref(d1)) == gs.GS_OK
-    assert gs._lib.gs_render_bwd_workspace(1000, 200000, ctypes.byref(c), 1, ctypes.byref(d2)) == gs.GS_OK
+    assert gs._lib.gs_render_bwd_2d_workspace(1000, 100000, ctypes.byref(c), 1, ctypes.byref(d1)) == gs.GS_OK
+    assert gs._lib.gs_render_bwd_2d_workspace(1000, 200000, ctypes.byref(c), 1, ctypes.byref(d2)) == gs.GS_OK
     assert d2.value - d1.value >= 36 * 100000
-    assert gs._lib.gs_render_bwd_workspace(1000, 100000, ctypes.byref(c), 0, ctypes.byref(b)) == gs.GS_OK
+    assert gs._lib.gs_render_bwd_2d_workspace(1000, 100000, ctypes.byref(c), 0, ctypes.byref(b)) == gs.GS_OK
     assert d1.value > b.value
+    # the full backward: the 2D workspace, plus the record gradients g2d[9][n]
+    # where the projection cannot read the accumulator rows (deterministic
+    # mode, learned colour), plus the decoder backward's workspace
+    for det, mode in ((0, 0), (1, 0), (0, 1)):
+        f = ctypes.c_size_t(0)
+        g = _gauss(gs, n=1000, deg=3, mode=mode)
+        g.latents = g.mlp = ctypes.c_void_p(0x1000)
+        assert gs._lib.gs_render_bwd_workspace(ctypes.byref(g), 100000, ctypes.byref(c), det, ctypes.byref(f)) == \
+            gs.GS_OK
+        two_d = d1.value if det else b.value
+        assert f.value >= two_d + (0 if (det, mode) == (0, 0) else 36 * 1000), (det, mode)
+    bad = _gauss(gs, n=1000, deg=5)
+    assert gs._lib.gs_render_bwd_workspace(ctypes.byref(bad), 10, ctypes.byref(c), 0, ctypes.byref(b)) == \
+        gs.GS_ERR_INVALID_ARG
 
 
 def test_bin_sort_rejects_small_workspace_and_bad_alignment(gs):
@@ -124,9 +138,28 @@ def test_render_calls_reject_nulls(gs):
     st = gs._lib.gs_render_fwd(10, ctypes.byref(_proj(gs)), NULL, NULL, 5, ctypes.byref(c), NULL, NULL, NULL, NULL,
                                0, NULL)
     assert st == gs.GS_ERR_INVALID_ARG
-    st = gs._lib.gs_render_bwd(10, ctypes.byref(_proj(gs)), NULL, NULL, 5, ctypes.byref(c), NULL, NULL, NULL,
-                               NULL, NULL, NULL, 0, 0, 0, NULL)
+    st = gs._lib.gs_render_bwd_2d(10, ctypes.byref(_proj(gs)), NULL, NULL, 5, ctypes.byref(c), NULL, NULL, NULL,
+                                  NULL, NULL, NULL, 0, 0, 0, NULL)
     assert st == gs.GS_ERR_INVALID_ARG
+    p = ctypes.c_void_p(0x1000)
+    gr = gs.GaussiansGrad()
+    gr.means = gr.log_scales = gr.quats = gr.logits = gr.sh = p
+    g = _gauss(gs)
+    ws = ctypes.c_void_p(0x100000)
+
+    def full(grad, stats=None, ws_bytes=1 << 40, sched=1, ranges=p, wsp=ws):
+        return gs._lib.gs_render_bwd(ctypes.byref(g), ctypes.byref(c), ctypes.byref(_proj(gs)), p, ranges, 5, p, p,
+                                     p, p, ctypes.byref(grad), stats, wsp, ws_bytes, 0, sched, NULL)
+    assert full(gr, ranges=NULL) == gs.GS_ERR_INVALID_ARG
+    nog = gs.GaussiansGrad()
+    nog.means = nog.log_scales = nog.quats = nog.logits = p
+    assert full(nog) == gs.GS_ERR_INVALID_ARG and "gradient" in gs.last_error()       # sh gradient missing
+    half = gs.DensifyStats()
+    half.grad_norm_sum = p
+    assert full(gr, stats=ctypes.byref(half)) == gs.GS_ERR_INVALID_ARG and "statistics" in gs.last_error()
+    assert full(gr, ws_bytes=16) == gs.GS_ERR_INVALID_ARG and "workspace" in gs.last_error()
+    assert full(gr, wsp=ctypes.c_void_p(0x100010)) == gs.GS_ERR_INVALID_ARG and "aligned" in gs.last_error()
+    assert full(gr, sched=5) == gs.GS_ERR_INVALID_ARG and "schedule" in gs.last_error()
     # an unknown schedule, and the balanced schedule without its plan storage
     p = ctypes.c_void_p(0x1000)
     for sched, ck in ((3, p), (-1, p), (gs.SCHEDULE_BALANCED, NULL), (gs.SCHEDULE_MERGED, NULL)):
@@ -134,6 +167,36 @@ def test_render_calls_reject_nulls(gs):
         assert st == gs.GS_ERR_INVALID_ARG, sched
         assert "schedule" in gs.last_error()
     assert gs._lib.gs_l1_loss(NULL, NULL, 0, NULL, NULL, NULL, NULL) == gs.GS_ERR_INVALID_ARG
+
+
+def test_adam_gaussians_argument_checks(gs):
+    """The fused Gaussian Adam step rejects bad hyper-parameters and missing
+    arrays before any device work."""
+    p = ctypes.c_void_p(0x1000)
+    arr = gs.ParamArrays()
+    arr.means = arr.log_scales = arr.quats = arr.logits = arr.sh = p
+    gr = gs.GaussiansGrad()
+    gr.means = gr.log_scales = gr.quats = gr.logits = gr.sh = p
+
+    def call(cfg, n=10, deg=3, params=arr, grad=gr):
+        return gs._lib.gs_adam_gaussians(n, deg, ctypes.byref(params), ctypes.byref(grad), ctypes.byref(arr),
+                                         ctypes.byref(arr), ctypes.byref(cfg), NULL)
+
+    def cfg(**over):
+        c = gs.AdamConfig()
+        c.lr_means = c.lr_log_scales = c.lr_quats = c.lr_logits = c.lr_sh_dc = c.lr_sh_rest = 1e-3
+        c.beta1, c.beta2, c.eps, c.step = 0.9, 0.999, 1e-15, 1
+        for k, v in over.items():
+            setattr(c, k, v)
+        return c
+    for bad in (dict(step=0), dict(beta1=1.0), dict(beta2=-0.1), dict(eps=0.0), dict(lr_quats=float("inf"))):
+        assert call(cfg(**bad)) == gs.GS_ERR_INVALID_ARG, bad
+    assert call(cfg(), deg=4) == gs.GS_ERR_INVALID_ARG
+    assert call(cfg(), n=-1) == gs.GS_ERR_INVALID_ARG
+    holey = gs.ParamArrays()
+    holey.means = holey.log_scales = holey.quats = holey.logits = p
+    assert call(cfg(), params=holey) == gs.GS_ERR_INVALID_ARG
+    assert call(cfg(), n=0) == gs.GS_OK            # nothing to do, no device work
 
 
 def test_camera_struct_layout_matches_header(gs):

@@ -224,6 +224,104 @@ def test_skip_below_alpha_min_and_clamp_at_099():
     assert g2d[0, 5] == 0.0 and g2d[0, 0] == 0.0
 
 
+def _walk_at(rec, cam, px, py, flips=0, margins=None, G=None):
+    """Render records stacked on one pixel (depth = order) with a near-decision
+    mask at that pixel; returns the pixel's colour, T, n_contrib, flags, near
+    count and, with an upstream gradient G at the pixel, the record gradients."""
+    n = len(rec)
+    depth = np.arange(1, n + 1, dtype=np.float32)
+    radius = np.full(n, 3, np.int32)
+    pl, ranges, _, _ = oracle.bin_sort(rec[:, 0], rec[:, 1], radius, depth, cam.width, cam.height)
+    fl = np.zeros((cam.height, cam.width), np.uint8)
+    fl[py, px] = flips
+    img, fT, nc, flags, nn = oracle.render_fwd(rec, pl, ranges, cam, margins=margins, flips=fl, with_near=True)
+    g2d = None
+    if G is not None:
+        Gi = np.zeros((3, cam.height, cam.width))
+        Gi[:, py, px] = G
+        g2d = oracle.render_bwd(rec, pl, ranges, cam, Gi, margins=margins, flips=fl)
+    return img[:, py, px], fT[py, px], int(nc[py, px]), int(flags[py, px]), int(nn[py, px]), g2d
+
+
+def test_near_decision_flips_match_nudged_inputs():
+    """Taking the other branch of a near-threshold decision (the masks that
+    locate FP32/FP64 splits) gives the plain walk of an input nudged across the
+    threshold, forward and backward; bits follow the walk order."""
+    cam = scenes.front_camera(32, 32, 3.0, 60.0, bg=(0.2, 0.5, 0.8))
+    px, py = 5, 7
+    G = np.array([0.7, -0.4, 1.1])
+    bg = np.asarray(cam.bg, np.float32).astype(np.float64)
+    # alpha vs 1/255: a single entry at the pixel centre (power 0, alpha = o)
+    up = _records_at_pixel(1, (1 + 1e-7) / 255, px, py)
+    dn = _records_at_pixel(1, (1 - 1e-7) / 255, px, py)
+    c0, T0, n0, f0, k0, _ = _walk_at(up, cam, px, py)
+    assert (n0, f0, k0) == (1, 1, 1)
+    c1, T1, n1, _, _, _ = _walk_at(up, cam, px, py, flips=1)
+    cd, Td, nd, fd, _, _ = _walk_at(dn, cam, px, py)
+    assert (n1, nd, fd) == (0, 0, 1) and T1 == Td == 1.0
+    np.testing.assert_allclose(c1, bg, atol=0) and np.testing.assert_allclose(cd, bg, atol=0)
+    assert _walk_at(up, cam, px, py, margins=(0.0, 0.0, 0.0))[3] == 0
+    # two near entries: bit k flips the k-th near decision met by the walk
+    two = np.concatenate([up, dn])
+    assert _walk_at(two, cam, px, py)[2:5] == (1, 1, 2)
+    for mask, want_nc, want_T in ((1, 0, 1.0), (2, 2, (1 - up[0, 5]) * (1 - dn[0, 5])), (3, 2, 1 - dn[0, 5])):
+        _, T, nc, _, _, _ = _walk_at(two, cam, px, py, flips=mask)
+        assert nc == want_nc and abs(T - want_T) < 1e-15, mask
+    # T' vs 1e-4: identical entries whose 14th blend lands just below / above 1e-4
+    a_lo = 1 - (1e-4 * (1 - 1e-9)) ** (1 / 14)
+    a_hi = 1 - (1e-4 * (1 + 1e-9)) ** (1 / 14)
+    lo = _records_at_pixel(20, a_lo, px, py)
+    hi = _records_at_pixel(20, a_hi, px, py)
+    c0, T0, n0, f0, k0, g0 = _walk_at(lo, cam, px, py, G=G)
+    assert n0 == 13 and f0 & 2 and k0 == 1
+    c1, T1, n1, _, _, g1 = _walk_at(lo, cam, px, py, flips=1, G=G)
+    ch, Th, nh, _, _, gh = _walk_at(hi, cam, px, py, G=G)
+    assert n1 == nh == 14
+    np.testing.assert_allclose(c1, ch, rtol=1e-7)
+    np.testing.assert_allclose(T1, Th, rtol=1e-7)
+    np.testing.assert_allclose(g1, gh, rtol=1e-6, atol=1e-12)
+    assert not g0[13].any() and np.abs(g1[13]).max() > 0   # the 14th entry's gradient exists only when blended
+    # o e^power vs 0.99: clamped (dL/do = 0) or not
+    cl = _records_at_pixel(1, 0.99 * (1 + 1e-7), px, py)
+    un = _records_at_pixel(1, 0.99 * (1 - 1e-7), px, py)
+    _, _, _, f0, k0, g0 = _walk_at(cl, cam, px, py, G=G)
+    assert f0 == 4 and k0 == 1 and g0[0, 5] == 0.0
+    _, _, _, _, _, g1 = _walk_at(cl, cam, px, py, flips=1, G=G)
+    _, _, _, _, _, gu = _walk_at(un, cam, px, py, G=G)
+    assert gu[0, 5] != 0.0
+    np.testing.assert_allclose(g1, gu, rtol=1e-6, atol=1e-15)
+
+
+def test_record_gradients_match_finite_differences():
+    """Every record channel of the render backward -- centre (u, v), the conic
+    entries A, B, C as they enter the power (B once), opacity and colour --
+    against central differences of the FP64 render in that record entry, at
+    entries where no pixel's decisions move."""
+    s = _tiny_scene(24)
+    cam = scenes.pinhole(40, 36, 60.0, np.eye(3), (0.05, 0.0, 3.0), bg=(0.2, 0.5, 0.8))
+    f = oracle.forward(s, cam)
+    rec, pl, ranges = f["proj"]["rec"], f["point_list"], f["ranges"]
+    G = scenes.upstream_grad(cam, 8)
+    g2d = oracle.render_bwd(rec, pl, ranges, cam, G)
+    checked = 0
+    for i in np.argsort(-np.abs(g2d[:, 5]))[:8]:
+        for ch in range(9):
+            h = 1e-5 * max(abs(rec[i, ch]), 1e-3)
+            vals = []
+            for sgn in (1, -1):
+                r2 = rec.copy()
+                r2[i, ch] += sgn * h
+                img, _, nc, _ = oracle.render_fwd(r2, pl, ranges, cam)
+                vals.append((float(np.sum(G * img)), nc))
+            if not (np.array_equal(vals[0][1], f["n_contrib"]) and np.array_equal(vals[1][1], f["n_contrib"])):
+                continue
+            fd = (vals[0][0] - vals[1][0]) / (2 * h)
+            scale = np.abs(g2d[:, ch]).max()
+            assert abs(fd - g2d[i, ch]) <= 1e-5 * max(abs(g2d[i, ch]), 1e-3 * scale), (i, ch, fd, g2d[i, ch])
+            checked += 1
+    assert checked >= 60
+
+
 # ------------------------------------------------------------------ binning
 
 def _py_bin_sort(u, v, r, depth, W, H):
@@ -380,7 +478,7 @@ def test_oracle_backward_matches_central_finite_differences():
     s = _tiny_scene(23)
     cam = scenes.pinhole(32, 32, 60.0, np.eye(3), (0.0, 0.0, 3.0))
     G = scenes.upstream_grad(cam, 6)
-    f = oracle.forward(s, cam, margin=1e-3)
+    f = oracle.forward(s, cam, margins=1e-3)
     g = oracle.backward(s, cam, f, G)
 
     def loss(sc):
