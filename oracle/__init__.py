@@ -23,10 +23,11 @@ TILE = 16
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (IEEE FP64, no fast-math, OpenMP)."""
+    """Compile the oracle with gcc (IEEE FP64, no fast-math, no contraction of
+    products and sums into fused multiply-adds, OpenMP)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + f".tmp{os.getpid()}"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall",
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall", "-ffp-contract=off",
                                "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -365,3 +366,82 @@ def densify_stats(g2d_views, visible_views):
         gsum = term if gsum is None else gsum + term
         cnt = vis.astype(np.int64) if cnt is None else cnt + vis
     return gsum, cnt
+
+
+# ------------------------------------------------- colour-hash sampling
+
+CHS_BUCKETS = 4096
+
+
+def colour_hash(rgb):
+    """Bucket (Sec. IV-C.1) of each FP32 colour rgb[n][3]: 4-bit levels of the
+    channels' 8-bit values, hashed as R_q 256 + G_q 16 + B_q.  uint16[n]."""
+    rgb = np.ascontiguousarray(np.asarray(rgb, np.float32).reshape(-1, 3))
+    n = rgb.shape[0]
+    h = np.zeros(max(n, 1), np.uint16)
+    _load().or_colour_hash(ctypes.c_int64(n), _p(rgb), _p(h))
+    return h[:n]
+
+
+def chs_aggregate(rec, point_list, ranges, hashes, window):
+    """Per-entry records of the colour-hash sampling mode: dict with rec_e[K][9],
+    rep[K] (list position of each entry's representative), size[K] (its
+    group's size), tab_count[4096] and tab_sum[4096][4] (r, g, b, opacity)."""
+    rec = _d(rec)
+    pl = np.ascontiguousarray(point_list, np.uint32)
+    rg = np.ascontiguousarray(ranges, np.uint32)
+    hs = np.ascontiguousarray(hashes, np.uint16)
+    K = pl.shape[0]
+    rec_e = np.zeros((max(K, 1), 9))
+    rep = np.zeros(max(K, 1), np.int64)
+    size = np.zeros(max(K, 1), np.int32)
+    tc = np.zeros(CHS_BUCKETS, np.uint32)
+    ts = np.zeros((CHS_BUCKETS, 4))
+    if not pl.size:
+        pl = np.zeros(1, np.uint32)
+    rc = _load().or_chs_aggregate(ctypes.c_int64(rg.shape[0]), _p(rg), _p(pl), _p(rec), _p(hs), ctypes.c_int(window),
+                                  _p(rec_e), _p(rep), _p(size), _p(tc), _p(ts))
+    if rc != 0:
+        raise ValueError(f"or_chs_aggregate failed: {rc}")
+    return dict(rec_e=rec_e[:K], rep=rep[:K], size=size[:K], tab_count=tc, tab_sum=ts)
+
+
+def chs_render_fwd(rec, point_list, ranges, cam, hashes, window, margins=None, tile_mask=None, agg=None):
+    """Forward compositing in the colour-hash sampling mode: the plain walk over
+    the per-entry records of chs_aggregate (point list 0..K-1, same ranges).
+    Returns (image, final_T, n_contrib, flags, agg); n_contrib counts list
+    positions, as in the exact mode."""
+    if agg is None:
+        agg = chs_aggregate(rec, point_list, ranges, hashes, window)
+    K = agg["rec_e"].shape[0]
+    ident = np.arange(K, dtype=np.uint32)
+    image, fT, nc, fl = render_fwd(agg["rec_e"], ident, ranges, cam, margins, tile_mask=tile_mask)
+    return image, fT, nc, fl, agg
+
+
+def chs_render_bwd(rec, point_list, ranges, cam, hashes, window, dL_dimage, tile_mask=None, agg=None,
+                   margins=None):
+    """Record gradients g2d[n][9] of sum(dL_dimage * image) in the colour-hash
+    sampling mode: the backward of the walk over the per-entry records, then
+    the chain rule of the aggregation (or_chs_route)."""
+    rec = _d(rec)
+    if agg is None:
+        agg = chs_aggregate(rec, point_list, ranges, hashes, window)
+    K = agg["rec_e"].shape[0]
+    ident = np.arange(K, dtype=np.uint32)
+    g_e = render_bwd(agg["rec_e"], ident, ranges, cam, dL_dimage, tile_mask=tile_mask, margins=margins)
+    n = rec.shape[0]
+    g2d = np.zeros((n, 9))
+    pl = np.ascontiguousarray(point_list, np.uint32)
+    rg = np.ascontiguousarray(ranges, np.uint32)
+    if not pl.size:
+        pl = np.zeros(1, np.uint32)
+        g_e = np.zeros((1, 9))
+    g_e = np.ascontiguousarray(g_e)
+    rep = np.ascontiguousarray(agg["rep"]) if K else np.zeros(1, np.int64)
+    size = np.ascontiguousarray(agg["size"]) if K else np.zeros(1, np.int32)
+    rc = _load().or_chs_route(ctypes.c_int64(n), ctypes.c_int64(rg.shape[0]), _p(rg), _p(pl), _p(rec),
+                              ctypes.c_int(window), _p(rep), _p(size), _p(g_e), _p(g2d))
+    if rc != 0:
+        raise ValueError(f"or_chs_route failed: {rc}")
+    return g2d

@@ -988,3 +988,154 @@ int or_mlp_inputs(int64_t n, int per, const double* z, const double* dirs, doubl
         }
     return 0;
 }
+
+/* ------------------------------------------------- colour-hash sampling ---
+ * Similarity-based sampling with colour hashing (Sec. IV-C.1), an optional
+ * approximate mode of the forward and backward compositing.  Readings (the
+ * paper gives the quantisation and hash formulas and the aggregation rule,
+ * not where the aggregation happens or what a merged Gaussian looks like):
+ *   - Colour quantisation: each channel's 8-bit value is
+ *     v8 = floor(255 clamp(c, 0, 1) + 1/2), evaluated in FP32 (two rounded
+ *     operations, product then sum; a NaN channel counts as 0), and its level
+ *     is c_q = floor(v8 / 256 * 16) = v8 >> 4 (16 levels per channel).
+ *   - Hash: h = R_q * 256 + G_q * 16 + B_q, one of 4096 buckets.
+ *   - Grouping: the 16x16 tile is the block that shares one Gaussian list;
+ *     the list is taken in windows of `window` consecutive entries starting
+ *     at the tile's first entry.  Inside a window, the entries whose Gaussians
+ *     fall into the same bucket form one group.
+ *   - Aggregation: a group of two or more is composited as one entry, its
+ *     front-most member (the representative), whose colour becomes the mean
+ *     of the members' colours and whose opacity becomes the accumulated
+ *     opacity 1 - prod_j (1 - o_j) (what members with one footprint and one
+ *     colour would composite to at the footprint's centre).  The other
+ *     members are not composited.  A group of one keeps its record as it is,
+ *     so window = 1 is the exact method.
+ *   - Bucket table: over all list entries of the frame, per bucket, the
+ *     entry count and the sums of colour and opacity (the representative
+ *     colour of a bucket is its colour sum over its count).
+ * The compositing itself is the plain walk above, run over per-entry records.
+ */
+
+/* 4-bit level of one colour channel (FP32, as stated above). */
+static uint32_t chs_level(float c) {
+    float cc = c > 0.0f ? (c < 1.0f ? c : 1.0f) : 0.0f; /* NaN -> 0 */
+    float t = cc * 255.0f;
+    t = t + 0.5f;
+    uint32_t v8 = (uint32_t)floorf(t);
+    return v8 >> 4;
+}
+
+/* Bucket of each of n FP32 colours rgb[n][3]. */
+int or_colour_hash(int64_t n, const float* rgb, uint16_t* hash) {
+    for (int64_t i = 0; i < n; ++i)
+        hash[i] = (uint16_t)(chs_level(rgb[3 * i]) * 256u + chs_level(rgb[3 * i + 1]) * 16u +
+                             chs_level(rgb[3 * i + 2]));
+    return 0;
+}
+
+/* Per-entry records of the approximate mode.  For list position m (tile t,
+ * window w) with Gaussian i = point_list[m]:
+ *   rep[m]    = list position of the group's representative (m itself for a
+ *               representative),
+ *   size[m]   = number of members of m's group,
+ *   rec_e[m]  = rec[i] with, for a representative, colour = the members'
+ *               mean colour and opacity = 1 - prod (1 - o_j), and for every
+ *               other member opacity 0 (never composited: alpha = 0 < 1/255).
+ * Compositing rec_e with point list 0, 1, ..., K-1 and the same ranges is the
+ * approximate render.  tab_count[4096] and tab_sum[4096][4] (r, g, b,
+ * opacity) receive the bucket table (may be NULL).  Returns 0, or -1 for a
+ * window outside [1, 2^20]. */
+int or_chs_aggregate(int64_t ntiles, const uint32_t* ranges, const uint32_t* point_list, const double* rec,
+                     const uint16_t* hash, int window, double* rec_e, int64_t* rep, int32_t* size,
+                     uint32_t* tab_count, double* tab_sum) {
+    if (window < 1 || window > (1 << 20)) return -1;
+    if (tab_count) memset(tab_count, 0, sizeof(uint32_t) * 4096);
+    if (tab_sum) memset(tab_sum, 0, sizeof(double) * 4096 * 4);
+    int64_t first[4096];
+    for (int b = 0; b < 4096; ++b) first[b] = -1;
+    for (int64_t t = 0; t < ntiles; ++t) {
+        int64_t s = ranges[2 * t], e = ranges[2 * t + 1];
+        for (int64_t w0 = s; w0 < e; w0 += window) {
+            int64_t w1 = w0 + window < e ? w0 + window : e;
+            /* members: each entry joins the group of its bucket's first entry */
+            for (int64_t m = w0; m < w1; ++m) {
+                uint32_t h = hash[point_list[m]];
+                if (first[h] < 0) first[h] = m;
+                rep[m] = first[h];
+            }
+            /* group sizes, then each representative's mean colour and
+             * accumulated opacity (members in list order) */
+            for (int64_t m = w0; m < w1; ++m) {
+                const double* g = rec + 9 * (int64_t)point_list[m];
+                memcpy(rec_e + 9 * m, g, 9 * sizeof(double));
+                size[m] = 0;
+            }
+            for (int64_t m = w0; m < w1; ++m) size[rep[m]] += 1;
+            for (int64_t m = w0; m < w1; ++m) {
+                if (rep[m] != m || size[m] == 1) continue; /* a group of one is its Gaussian */
+                double csum[3] = {0, 0, 0}, keep = 1.0;
+                for (int64_t j = m; j < w1; ++j) {
+                    if (rep[j] != m) continue;
+                    const double* g = rec + 9 * (int64_t)point_list[j];
+                    for (int ch = 0; ch < 3; ++ch) csum[ch] += g[6 + ch];
+                    keep *= 1.0 - g[5];
+                }
+                for (int ch = 0; ch < 3; ++ch) rec_e[9 * m + 6 + ch] = csum[ch] / size[m];
+                rec_e[9 * m + 5] = 1.0 - keep;
+            }
+            for (int64_t m = w0; m < w1; ++m) {
+                if (rep[m] != m) {
+                    rec_e[9 * m + 5] = 0.0;
+                    size[m] = size[rep[m]];
+                }
+                first[hash[point_list[m]]] = -1;
+            }
+        }
+    }
+    if (tab_count || tab_sum) {
+        for (int64_t t = 0; t < ntiles; ++t)
+            for (int64_t m = ranges[2 * t]; m < (int64_t)ranges[2 * t + 1]; ++m) {
+                uint32_t i = point_list[m], h = hash[i];
+                if (tab_count) tab_count[h] += 1;
+                if (tab_sum)
+                    for (int q = 0; q < 4; ++q) tab_sum[4 * h + q] += rec[9 * (int64_t)i + (q < 3 ? 6 + q : 5)];
+            }
+    }
+    return 0;
+}
+
+/* Chain rule of the aggregation: from the gradients g_e[K][9] of the per-entry
+ * records (the backward render of rec_e over point list 0..K-1) to the
+ * Gaussians' record gradients g2d[n][9] (overwritten).  Per group with
+ * representative m and members j (list positions):
+ *   geometry (u, v, A, B, C): all of g_e[m] goes to the representative;
+ *   colour: c_m = mean_j c_j, so each member gets g_e[m][colour] / size;
+ *   opacity: o_m = 1 - prod_j (1 - o_j), so member j gets
+ *            g_e[m][o] prod_{i != j} (1 - o_i).
+ * Members other than the representative carry no geometry gradient of their
+ * own (they are not composited). */
+int or_chs_route(int64_t n, int64_t ntiles, const uint32_t* ranges, const uint32_t* point_list, const double* rec,
+                 int window, const int64_t* rep, const int32_t* size, const double* g_e, double* g2d) {
+    if (window < 1 || window > (1 << 20)) return -1;
+    memset(g2d, 0, sizeof(double) * 9 * (size_t)n);
+    for (int64_t t = 0; t < ntiles; ++t) {
+        int64_t s = ranges[2 * t], e = ranges[2 * t + 1];
+        for (int64_t w0 = s; w0 < e; w0 += window) {
+            int64_t w1 = w0 + window < e ? w0 + window : e;
+            for (int64_t m = w0; m < w1; ++m) {
+                int64_t r = rep[m];
+                if (r < w0 || r > m) return -2;
+                const double* ge = g_e + 9 * r;
+                double* out = g2d + 9 * (int64_t)point_list[m];
+                if (r == m)
+                    for (int q = 0; q < 5; ++q) out[q] += ge[q];
+                for (int ch = 0; ch < 3; ++ch) out[6 + ch] += ge[6 + ch] / size[m];
+                double others = 1.0;
+                for (int64_t j = r; j < w1; ++j)
+                    if (rep[j] == r && j != m) others *= 1.0 - rec[9 * (int64_t)point_list[j] + 5];
+                out[5] += ge[5] * others;
+            }
+        }
+    }
+    return 0;
+}

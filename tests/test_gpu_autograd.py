@@ -207,11 +207,13 @@ def test_autograd_matches_finite_differences(gs):
     """Central differences of the GPU step itself at the tiny workload (4,096
     Gaussians, 128x128): L = sum(G * image) with G the L1 gradient at the
     start point, for the Gaussians with the largest gradients.  A point is
-    used only if the perturbed renders keep every list and every pixel's
-    n_contrib and the two one-sided differences agree within 5 %, i.e. no
-    decision moves within the step (a skip flip at alpha = 1/255 moves L by
-    well under 1 % of the step's change); the FP32 difference quotient is then
-    accurate to about 1e-4 and must agree with the autograd gradient to 1e-2."""
+    used only if no decision moves within the step: the perturbed renders keep
+    every list, every pixel's n_contrib (the stop) and the number of blended
+    pairs (a skip flip at alpha = 1/255 changes it by one; it moves one
+    pixel by about c/255, which is a sizeable part of L's change over a step
+    of 2e-4 in a mean), and the two one-sided differences agree within 5 %.
+    The FP32 difference quotient is then accurate to about 1e-4 and must
+    agree with the autograd gradient to 1e-2."""
     from paper_2510_14564_amd.raster import Rasterizer, l1_loss, rasterize
     scene, cam = scenes.config_scene(1), scenes.config_camera(1, bg=(0.2, 0.5, 0.8))
     say(f"[autograd FD] n={scene.n}")
@@ -227,6 +229,13 @@ def test_autograd_matches_finite_differences(gs):
     L0 = float((Gh * base).sum())
     nc0 = rast.last_frame.n_contrib.cpu().numpy()
     pl0 = _lists(rast.last_frame)
+    counts = torch.zeros(2, dtype=torch.int64, device=DEV)
+
+    def blended(st):
+        gs.render_count(st.n, st.proj, st.point_list, st.ranges, st.k, st.cs, counts)
+        return int(counts[1].item())
+
+    bl0 = blended(rast.last_frame)
 
     def loss_at(key, idx, value):
         q = {k: v.detach().clone() for k, v in p.items()}
@@ -235,7 +244,8 @@ def test_autograd_matches_finite_differences(gs):
             st = rast.forward(q["means"], q["log_scales"], q["quats"], q["logits"], q["sh"])
             torch.cuda.synchronize()
             im = st.image.cpu().numpy().astype(np.float64)
-            same = np.array_equal(st.n_contrib.cpu().numpy(), nc0) and _lists(st) == pl0
+            same = (np.array_equal(st.n_contrib.cpu().numpy(), nc0) and _lists(st) == pl0 and
+                    blended(st) == bl0)
         return float((Gh * im).sum()), same
 
     steps = {"means": 2e-4, "log_scales": 2e-3, "quats": 2e-3, "logits": 2e-3, "sh": 2e-3}
