@@ -151,15 +151,21 @@ def bin_sort(u, v, radius, depth_f32, W: int, H: int, tile_mask=None):
 
 
 # near-threshold margins of the per-pixel walk: alpha vs 1/255 (relative),
-# T' vs 1e-4 (relative, base value; grows along the walk), o e^power vs 0.99
-MARGINS = (1e-5, 1e-4, 1e-5)
+# T' vs 1e-4 (relative, base value; grows along the walk), o e^power vs 0.99,
+# and the coefficient of the pair's power-term magnitude added to the two
+# alpha margins (8 units of 2^-24: the FP32 evaluation error of the power)
+POWER_ERR = 8.0 * 2.0 ** -24
+MARGINS = (1e-5, 1e-4, 1e-5, POWER_ERR)
 
 
 def _margins(m):
+    """Four margins; a scalar or three values get no power-term margin."""
     m = np.asarray(m if m is not None else MARGINS, np.float64).reshape(-1)
     if m.size == 1:
         m = np.repeat(m, 3)
-    return np.ascontiguousarray(m[:3])
+    if m.size == 3:
+        m = np.append(m, 0.0)
+    return np.ascontiguousarray(m[:4])
 
 
 def render_fwd(rec, point_list, ranges, cam, margins=None, tile_mask=None, flips=None, with_near=False):
@@ -430,14 +436,22 @@ def chs_render_bwd(rec, point_list, ranges, cam, hashes, window, dL_dimage, tile
     K = agg["rec_e"].shape[0]
     ident = np.arange(K, dtype=np.uint32)
     g_e = render_bwd(agg["rec_e"], ident, ranges, cam, dL_dimage, tile_mask=tile_mask, margins=margins)
+    return chs_route(rec, point_list, ranges, window, agg, g_e)
+
+
+def chs_route(rec, point_list, ranges, window, agg, g_e):
+    """The aggregation's chain rule (or_chs_route): per-entry record gradients
+    g_e[K][9] of the sampling mode's records -> per-Gaussian g2d[n][9]."""
+    rec = _d(rec)
+    K = agg["rec_e"].shape[0]
     n = rec.shape[0]
     g2d = np.zeros((n, 9))
     pl = np.ascontiguousarray(point_list, np.uint32)
     rg = np.ascontiguousarray(ranges, np.uint32)
+    g_e = np.ascontiguousarray(_d(g_e))
     if not pl.size:
         pl = np.zeros(1, np.uint32)
         g_e = np.zeros((1, 9))
-    g_e = np.ascontiguousarray(g_e)
     rep = np.ascontiguousarray(agg["rep"]) if K else np.zeros(1, np.int64)
     size = np.ascontiguousarray(agg["size"]) if K else np.zeros(1, np.int32)
     rc = _load().or_chs_route(ctypes.c_int64(n), ctypes.c_int64(rg.shape[0]), _p(rg), _p(pl), _p(rec),

@@ -441,13 +441,18 @@ int or_bin_sort(int64_t n, const double* u, const double* v, const int32_t* radi
  * decision the other way when the FP64 value lies close to its threshold.  The
  * walk counts such "near" decisions in the order it meets them (k = 0, 1, ...)
  * and sets a pixel flag for each kind:
- *   bit0  alpha within a relative margins[0] of 1/255   (skip or blend),
- *   bit1  T' within a relative mT of 1e-4               (stop or blend),
- *   bit2  o e^power within a relative margins[2] of 0.99 (clamp or not).
- * mT starts at margins[1] and grows by alpha/(1 - alpha) margins[0] + 2^-22
- * for every blended entry (margins[0]: clamped entries add 1e-6 instead):
- * the relative error that a product of (1 - alpha) factors carries when each
- * alpha is known to margins[0] relative and each product is rounded once.
+ *   bit0  alpha within a relative ma of 1/255            (skip or blend),
+ *   bit1  T' within a relative mT of 1e-4                (stop or blend),
+ *   bit2  o e^power within a relative mc of 0.99          (clamp or not).
+ * The pair's alpha margins are ma = margins[0] + margins[3] Q and
+ * mc = margins[2] + margins[3] Q with Q = (|A| dx^2 + 2 |B dx dy| + |C| dy^2)/2,
+ * the magnitude of the power's terms: a power evaluated in FP32 errs by a few
+ * units of 2^-24 of Q, which exceeds the fixed margin for elongated footprints
+ * whose terms cancel (margins[3] = 0: fixed margins only).
+ * mT starts at margins[1] and grows by alpha/(1 - alpha) ma + 2^-22 for
+ * every blended entry (clamped entries add 1e-6 instead): the relative error
+ * that a product of (1 - alpha) factors carries when each alpha is known to
+ * ma relative and each product is rounded once.
  * Bit k of `flips` (a per-pixel mask; 0 = none) makes the walk take the other
  * branch of near decision k; with flips = 0 this is the plain definition.
  * The walk stops counting at 8 near decisions (flips has 8 bits).
@@ -500,15 +505,19 @@ static void walk_pixel(const double* rec, const uint32_t* point_list, uint32_t s
         if (power > 0.0) continue; /* only an FP guard: Sigma' is positive definite */
         double eg = exp(power);
         double og = g[5] * eg;
+        double qm = margins[3] > 0.0
+                        ? margins[3] * 0.5 * (fabs(g[2]) * dx * dx + 2.0 * fabs(g[3] * dx * dy) + fabs(g[4]) * dy * dy)
+                        : 0.0;
+        double ma = margins[0] + qm;
         int clamp = !(og < OR_ALPHA_MAX);
-        if (fabs(og - OR_ALPHA_MAX) <= margins[2] * OR_ALPHA_MAX && k < 8) {
+        if (fabs(og - OR_ALPHA_MAX) <= (margins[2] + qm) * OR_ALPHA_MAX && k < 8) {
             fl |= 4;
             if ((flips >> k) & 1u) clamp = !clamp;
             ++k;
         }
         double alpha = clamp ? OR_ALPHA_MAX : og;
         int skip = alpha < OR_ALPHA_MIN;
-        if (fabs(alpha - OR_ALPHA_MIN) <= margins[0] * OR_ALPHA_MIN && k < 8) {
+        if (fabs(alpha - OR_ALPHA_MIN) <= ma * OR_ALPHA_MIN && k < 8) {
             fl |= 1;
             if ((flips >> k) & 1u) skip = !skip;
             ++k;
@@ -531,7 +540,7 @@ static void walk_pixel(const double* rec, const uint32_t* point_list, uint32_t s
         for (int ch = 0; ch < 3; ++ch) acc[ch] += g[6 + ch] * alpha * T;
         T = Tn;
         nc = (int32_t)(m - s + 1);
-        mT += (clamp ? 1e-6 : alpha / (1.0 - alpha) * margins[0]) + 0x1p-22;
+        mT += (clamp ? 1e-6 : alpha / (1.0 - alpha) * ma) + 0x1p-22;
     }
     for (int ch = 0; ch < 3; ++ch) out->acc[ch] = acc[ch];
     out->T = T;

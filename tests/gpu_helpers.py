@@ -21,11 +21,13 @@ MASS_FLOOR = 1e-2
 PROJ_RTOL = 2e-5         # projected quantities, relative to the field's scale
 # near-threshold margins of the oracle's walk when it composites the HIP
 # path's own FP32 records (staged): alpha vs 1/255 and o e^power vs 0.99 at
-# 1e-5 relative, T' vs 1e-4 from 1e-4 relative plus the error a product of
+# 1e-5 relative plus 8 units of 2^-24 of the pair's power-term magnitude (the
+# FP32 evaluation error of the power, large for elongated footprints whose
+# terms cancel), T' vs 1e-4 from 1e-4 relative plus the error a product of
 # (1 - alpha) factors accumulates; from raw parameters (end to end) the
-# records themselves differ by FP32 rounding, so every margin is 1e-3
-STAGED_MARGINS = (1e-5, 1e-4, 1e-5)
-E2E_MARGINS = (1e-3, 1e-3, 1e-3)
+# records themselves differ by FP32 rounding, so the fixed margins are 1e-3
+STAGED_MARGINS = (1e-5, 1e-4, 1e-5, oracle.POWER_ERR)
+E2E_MARGINS = (1e-3, 1e-3, 1e-3, oracle.POWER_ERR)
 
 
 def say(*a):
@@ -56,17 +58,21 @@ def proj_host(out):
                 radius=out.radius.cpu().numpy(), tiles_touched=out.tiles_touched.cpu().numpy())
 
 
-def grad_close(got, want, rtol=GRAD_RTOL, name="", mass=None, stats=None):
+def grad_close(got, want, rtol=GRAD_RTOL, name="", mass=None, stats=None, extra=None):
     """Relative error 1e-3 against max(|g*|, 1e-3 max|g*|) and, when the oracle's
     term mass is given, 1e-2 of it: a sum that cancels by more than 100x is
     judged against its terms, which is what its rounding error scales with.
-    Returns the worst ratio to the plain (mass-free) relative bound."""
+    extra (absolute, per entry) is added to the bound: the response of g* to
+    a known error of its inputs.  Returns the worst ratio to the plain
+    (mass-free) relative bound."""
     got = np.asarray(got, np.float64)
     want = np.asarray(want, np.float64)
     scale = np.abs(want).max() if want.size else 0.0
     ref = np.maximum(np.abs(want), 1e-3 * scale)
     plain = rtol * ref
     bound = plain if mass is None else rtol * np.maximum(ref, MASS_FLOOR * np.asarray(mass, np.float64))
+    if extra is not None:
+        bound = bound + np.asarray(extra, np.float64)
     err = np.abs(got - want)
     bad = err > bound + 1e-30
     if bad.any():
@@ -169,6 +175,27 @@ def sigma_to_conic_grad(rec, g):
     out = g.copy()
     out[:, 2], out[:, 3], out[:, 4] = Gc[:, 0, 0], 2.0 * Gc[:, 0, 1], Gc[:, 1, 1]
     out[~live, 2:5] = 0.0
+    return out
+
+
+def record_sensitivity(rec, pl, ranges, cam, G, deltas, tile_mask=None, flips=None, margins=STAGED_MARGINS):
+    """How far the oracle's record gradients (Sigma' form) move when the
+    records move by their FP32 error: sum over record fields f of
+    |g(rec + deltas[:, f] e_f) - g(rec)|, one oracle pass per field (every
+    Gaussian's field f moved at once).  From raw parameters the two sides'
+    records differ by FP32 rounding of the projection, so a gradient compared
+    end to end may differ by this much on top of the staged tolerance (large
+    only for sums that cancel: a small footprint's dL/du is a difference of
+    its left and right pixels)."""
+    g0 = oracle.render_bwd(rec, pl, ranges, cam, G, tile_mask=tile_mask, margins=margins, flips=flips)
+    out = np.zeros_like(g0)
+    for f in range(9):
+        if not np.any(deltas[:, f]):
+            continue
+        r2 = rec.copy()
+        r2[:, f] += deltas[:, f]
+        g1 = oracle.render_bwd(r2, pl, ranges, cam, G, tile_mask=tile_mask, margins=margins, flips=flips)
+        out += np.abs(conic_to_sigma_grad(rec, g1 - g0))
     return out
 
 

@@ -17,7 +17,7 @@ import torch
 
 import oracle
 from paper_2510_14564_amd import scenes
-from gpu_helpers import DEV, say, to_dev
+from gpu_helpers import DEV, say, sigma_to_conic_grad, to_dev
 from mlp_bounds import F32, U, UA, _check_grads, bwd_bounds, error_bound, fwd_bounds, kaiming_params, reading18  # noqa: F401
 
 pytestmark = pytest.mark.gpu
@@ -211,8 +211,10 @@ def test_project_bwd_learned_colour(gs):
     # geometry: the oracle's SH backward on a degree-0 copy (no direction term)
     s0 = scenes.Scene(n, 0, scene.means, scene.log_scales, scene.quats, scene.logits,
                       np.zeros((1, 3, n), np.float32))
-    geo = oracle.project_bwd(s0, cam, np.ascontiguousarray(g2d_h.T).astype(np.float64))
+    # g2d carries dL/dSigma' (the library's record-gradient form); the oracle's
+    # projection backward takes the conic form: converted on the oracle's records
     o = oracle.project(s0, cam)
+    geo = oracle.project_bwd(s0, cam, sigma_to_conic_grad(o["rec"], g2d_h.T))
     ok = (o["flags"] & 0b1110) == 0
     for kk in ("log_scales", "quats", "logits"):
         grad_close(grads[kk].cpu().numpy()[..., ok], geo[kk][..., ok], name=kk)

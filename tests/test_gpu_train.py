@@ -31,7 +31,9 @@ def test_densify_stats_accumulate_over_views(gs):
     from paper_2510_14564_amd.raster import Rasterizer
     scene = scenes.config_scene(2, n=50000)
     n = scene.n
-    cams = [scenes.orbit_camera(k, 32, 400, 300) for k in (0, 3, 7)]
+    # a 25-degree field of view sees 70-74 % of the scene from each of these
+    # orbit positions, so visibility differs between Gaussians and views
+    cams = [scenes.orbit_camera(k, 32, 400, 300, fov_x_deg=25.0) for k in (0, 3, 7)]
     say(f"[densify stats] n={n}, {len(cams)} views")
     p = {k: to_dev(v) for k, v in scene.arrays().items() if k in PARAMS}
     rast = Rasterizer(cams[0], scene.sh_degree, device=DEV, deterministic=True)
@@ -83,8 +85,11 @@ def test_adam_gaussians_matches_oracle(gs, deg, n):
     f32 = lambda x: float(np.float32(x))  # noqa: E731
     lrs = {k: f32(v) for k, v in LRS.items()}
     b1, b2, eps = f32(0.9), f32(0.999), f32(1e-15)
+    Mabs = {k: np.zeros(s) for k, s in shapes.items()}
     for step, scale in enumerate((1.0, 1e-3, 30.0), start=1):
         g = {k: (rng.normal(size=s) * scale).astype(np.float32) for k, s in shapes.items()}
+        for k in PARAMS:
+            Mabs[k] = b1 * Mabs[k] + (1.0 - b1) * np.abs(g[k].astype(np.float64))
         gs.adam_gaussians(n, deg, dp, {k: to_dev(v) for k, v in g.items()}, dm, dv, LRS, step, beta1=0.9,
                           beta2=0.999, eps=1e-15)
         for k in PARAMS:
@@ -93,11 +98,15 @@ def test_adam_gaussians_matches_oracle(gs, deg, n):
     torch.cuda.synchronize()
     for k in PARAMS:
         lr = LRS[k] if k != "sh" else max(LRS["sh_dc"], LRS["sh_rest"])
-        for name, got, want, tol in (("p", dp[k], Po[k], 1e-4 * lr), ("m", dm[k], Mo[k], 0.0),
-                                     ("v", dv[k], Vo[k], 0.0)):
+        # the first moment is a signed sum b1^2 (1-b1) g1 + b1 (1-b1) g2 + (1-b1) g3:
+        # its FP32 rounding is relative to the sum of its terms' magnitudes
+        # (Mabs), not to the sum itself, which may cancel; the second moment's
+        # terms are all non-negative
+        for name, got, want, scale, tol in (("p", dp[k], Po[k], np.abs(Po[k]), 1e-4 * lr),
+                                            ("m", dm[k], Mo[k], Mabs[k], 0.0), ("v", dv[k], Vo[k], np.abs(Vo[k]), 0.0)):
             got = got.cpu().numpy().astype(np.float64)
             err = np.abs(got - want)
-            bound = 4e-7 * np.abs(want) + tol + 1e-30
+            bound = 4e-7 * scale + tol + 1e-30
             assert (err <= bound).all(), (k, name, float((err / bound).max()))
 
 
