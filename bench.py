@@ -379,6 +379,30 @@ def learned_quality(torch, gs, scenes, dev, epochs=400):
             "distill_epochs": epochs, "distill_s": round(t_dist, 3)}
 
 
+def sampling_quality(torch, gs, scenes, dev, cfg, coherent=False):
+    """The colour-hash sampling mode against the exact method on camera 0 of
+    a workload: PSNR of the sampled render against the exact render, and the
+    fraction of list entries merged into a group representative."""
+    from paper_2510_14564_amd.raster import Rasterizer
+    scene = scenes.config_scene(cfg)
+    if coherent:
+        scene = scenes.coherent_colour(scene, 1000 * cfg + 77)
+    cam = scenes.config_camera(cfg, 0)
+    p = {k: torch.from_numpy(v).to(dev) for k, v in scene.arrays().items() if k != "latents"}
+    imgs = []
+    for sched in (gs.SCHEDULE_BALANCED, gs.SCHEDULE_BALANCED | gs.RENDER_COLOUR_HASH):
+        rast = Rasterizer(cam, scene.sh_degree, device=dev, schedule=sched)
+        with torch.no_grad():
+            st = rast.forward(p["means"], p["log_scales"], p["quats"], p["logits"], p["sh"])
+        imgs.append(st.image.clamp(0.0, 1.0))
+    rep = torch.empty(max(st.k, 1), dtype=torch.int32, device=dev)
+    gs.colour_hash_table(st.n, st.proj, st.point_list, st.ranges, st.k, st.cs, None, None, None, rep)
+    merged = (rep[:st.k].to(torch.int64) != torch.arange(st.k, device=dev)).double().mean().item()
+    mse = torch.mean((imgs[0] - imgs[1]) ** 2).item()
+    return {"scene": f"{scenes.CONFIG_NAMES[cfg]}{', coherent colour' if coherent else ''}", "k": st.k,
+            "merged_fraction": round(merged, 4), "psnr_vs_exact_db": round(10 * math.log10(1.0 / max(mse, 1e-30)), 3)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -394,6 +418,7 @@ def main():
                          "deterministic reduction")
     ap.add_argument("--wait-k", action="store_true",
                     help="bin/sort waits for the entry count every frame (no gs_bin_sort_async)")
+    ap.add_argument("--no-sampling", action="store_true", help="skip the colour-hash sampling timing and quality")
     ap.add_argument("--hbm-probe", action="store_true",
                     help="also time a 2 GiB device-to-device copy (achievable HBM bandwidth, counter calibration)")
     args = ap.parse_args()
@@ -429,6 +454,13 @@ def main():
         other_splits["balanced, deterministic"] = {"ms_per_step": round(r["ms"], 4),
                                                    "stages_ms": {k: round(v, 4) for k, v in r["stages_ms"].items()}}
         hw.rast.deterministic = False
+
+    # the approximate colour-hash sampling mode (Sec. IV-C.1) on the same steps
+    sampled = None
+    if not args.no_sampling:
+        hw.rast.schedule = gs.SCHEDULE_BALANCED | gs.RENDER_COLOUR_HASH
+        sampled = hw.run(hw.step, "SH colour, colour-hash sampling", args.steps, args.warmup)
+        hw.rast.schedule = gs.SCHEDULE_BALANCED
 
     # learned colour on the same scene, cameras and targets: random-init
     # decoder (the step's cost does not depend on the weight values)
@@ -500,6 +532,12 @@ def main():
         result["other_work_splits"] = other_splits
     if mlp is not None:
         result["learned_colour"] = dict(summary(mlp), speedup_vs_sh=round(sh["ms"] / mlp["ms"], 4))
+    if sampled is not None:
+        log("[bench] colour-hash sampling quality ...")
+        result["colour_hash_sampling"] = dict(
+            summary(sampled), speedup_vs_exact=round(sh["ms"] / sampled["ms"], 4),
+            approximate=True,
+            quality=[sampling_quality(torch, gs, scenes, dev, c, coh) for c in (2, 3) for coh in (False, True)])
     if not args.no_extras and cfg == 3:
         extras = {}
         del hw

@@ -193,6 +193,25 @@ gs_status gs_bin_sort_async(int64_t n, const gs_projected* proj, const gs_camera
 #define GS_SCHEDULE_BALANCED 1
 #define GS_SCHEDULE_MERGED 2
 
+/* Colour-hash sampling (Sec. IV-C.1, similarity-based sampling with colour
+ * hashing): an APPROXIMATE mode of the compositing, selected by or-ing this
+ * flag into the schedule argument of gs_render_fwd, gs_render_bwd and
+ * gs_render_bwd_2d (the forward and its backward must both carry it).  Each
+ * Gaussian's colour is quantised per channel to its 8-bit value
+ * v8 = floor(255 clamp(c, 0, 1) + 1/2) (FP32) and then to 4 bits,
+ * c_q = floor(v8 / 256 * 16); the bucket is R_q 256 + G_q 16 + B_q (4096
+ * buckets).  In every 256-entry window of a tile's list (windows start at the
+ * tile's first entry) the entries whose buckets agree form a group; a group of
+ * two or more is composited as its front-most member with the members' mean
+ * colour and the accumulated opacity 1 - prod (1 - o_j), and its other
+ * members are not composited (groups of one are unchanged).  The backward
+ * hands the gradient of a group's opacity and colour to its members by the
+ * chain rule and the footprint's gradient to the representative.  Results
+ * differ from the exact method; the image is still deterministic.  Needs
+ * schedule PLAIN or BALANCED and, in the backward, deterministic = 0
+ * (GS_ERR_UNSUPPORTED otherwise). */
+#define GS_RENDER_COLOUR_HASH 0x100
+
 /* Forward compositing (Sec. II-A, C = sum_i c_i alpha_i prod_{j<i} (1 - alpha_j)
  * over the tile's depth-ordered list).  Per pixel: power = -1/2 (A dx^2 +
  * C dy^2) - B dx dy, alpha = min(0.99, o exp(power)); entries with power > 0 or
@@ -215,6 +234,23 @@ gs_status gs_render_fwd(int64_t n, const gs_projected* proj, const uint32_t* poi
  * pairs the backward walks. */
 gs_status gs_render_count(int64_t n, const gs_projected* proj, const uint32_t* point_list, const uint32_t* ranges,
                           int64_t k, const gs_camera* cam, uint64_t* counts, gs_stream stream);
+
+/* The colour-hash sampling mode's bucket table for a binned frame (the
+ * bucket-wise aggregation of Sec. IV-C.1, two-stage: each window's groups are
+ * summed in LDS, then each group is added to the frame's table in device
+ * memory), over every list entry:
+ *   count[4096] (uint32, overwritten): list entries per bucket;
+ *   sums[4096][4] (float, overwritten): sums of their colour (r, g, b) and
+ *     opacity, so count and sums give each bucket's representative colour;
+ *   bucket[k] (uint16): each list entry's bucket;
+ *   rep[k] (uint32): list position of each entry's group representative (its
+ *     own position for groups of one).
+ * Any output may be NULL.  proj, point_list, ranges and k as for
+ * gs_render_fwd.  count and bucket/rep are exact; the float sums depend on
+ * the order of the device atomics. */
+gs_status gs_colour_hash_table(int64_t n, const gs_projected* proj, const uint32_t* point_list,
+                               const uint32_t* ranges, int64_t k, const gs_camera* cam, uint32_t* count,
+                               float* sums, uint16_t* bucket, uint32_t* rep, gs_stream stream);
 
 /* Floats of the transmittance checkpoint buffer for K entries. Host-only. */
 gs_status gs_render_ckpt_floats(int64_t k, const gs_camera* cam, size_t* floats);
@@ -395,14 +431,15 @@ gs_status gs_l1_loss(const float* img, const float* target, int64_t count, float
 
 /* ------------------------------------------------------------ measurement
  * Kernel timer (for benchmarks; not needed by the path).  After
- * gs_kernel_timer_start, every kernel the library launches from the calling
- * thread is bracketed by two HIP events recorded on its launch stream, until
- * gs_kernel_timer_stop, which waits for those events and writes one line per
+ * gs_kernel_timer_start, every kernel the library launches is bracketed by
+ * two HIP events recorded on its launch stream, until gs_kernel_timer_stop, which waits for those events and writes one line per
  * kernel name, "name launches total_ms", in first-launch order, into buf
  * (size bytes, truncated and NUL-terminated; *needed = the full length + 1;
- * buf may be NULL to query the length).  One timer per thread; the events add
- * a few microseconds per launch.  Errors: INVALID_ARG when no timer (start:
- * another timer) is running on the thread; HIP if an event failed. */
+ * buf may be NULL to query the length).  One timer per process: launches
+ * from every host thread are timed (an autograd backward runs on a thread of
+ * its own); the events add a few microseconds per launch.  Errors:
+ * INVALID_ARG when no timer (start: a timer) is running; HIP if an event
+ * failed. */
 gs_status gs_kernel_timer_start(void);
 gs_status gs_kernel_timer_stop(char* buf, size_t size, size_t* needed);
 

@@ -12,6 +12,9 @@
 
 #include "gs_internal.h"
 
+#include <atomic>
+#include <mutex>
+
 namespace gs {
 
 static thread_local std::string t_error;
@@ -99,26 +102,30 @@ static gs_status validate_projected(const gs_projected* p, int64_t n, const char
 }
 
 // ------------------------------------------------------------ kernel timer
+// One timer per process: the backward of an autograd step runs on another
+// host thread than its forward, and both must be seen.
 namespace {
 struct TimerRec {
   const char* name;
   hipEvent_t a, b;
 };
-thread_local bool t_timing = false;
-thread_local std::vector<TimerRec> t_recs;
-thread_local std::vector<hipEvent_t> t_pool;
-thread_local hipError_t t_timer_err = hipSuccess;
+std::atomic<bool> g_timing{false};
+std::mutex g_timer_mu;
+std::vector<TimerRec> g_recs;
+std::vector<hipEvent_t> g_pool;
+hipError_t g_timer_err = hipSuccess;
 
+// caller holds g_timer_mu
 hipEvent_t pool_get() {
-  if (!t_pool.empty()) {
-    hipEvent_t e = t_pool.back();
-    t_pool.pop_back();
+  if (!g_pool.empty()) {
+    hipEvent_t e = g_pool.back();
+    g_pool.pop_back();
     return e;
   }
   hipEvent_t e = nullptr;
   const hipError_t r = hipEventCreate(&e);
   if (r != hipSuccess) {
-    t_timer_err = r;
+    g_timer_err = r;
     return nullptr;
   }
   return e;
@@ -126,28 +133,31 @@ hipEvent_t pool_get() {
 }  // namespace
 
 TimedLaunch::TimedLaunch(const char* name, hipStream_t s) : slot_(-1), s_(s) {
-  if (!t_timing) return;
+  if (!g_timing.load(std::memory_order_acquire)) return;
+  std::lock_guard<std::mutex> lock(g_timer_mu);
   hipEvent_t a = pool_get();
   hipEvent_t b = a ? pool_get() : nullptr;
   if (!b) {
-    if (a) t_pool.push_back(a);
+    if (a) g_pool.push_back(a);
     return;
   }
   const hipError_t r = hipEventRecord(a, s);
   if (r != hipSuccess) {
-    t_timer_err = r;
-    t_pool.push_back(a);
-    t_pool.push_back(b);
+    g_timer_err = r;
+    g_pool.push_back(a);
+    g_pool.push_back(b);
     return;
   }
-  t_recs.push_back({name, a, b});
-  slot_ = static_cast<int>(t_recs.size()) - 1;
+  g_recs.push_back({name, a, b});
+  slot_ = static_cast<int>(g_recs.size()) - 1;
 }
 
 TimedLaunch::~TimedLaunch() {
   if (slot_ < 0) return;
-  const hipError_t r = hipEventRecord(t_recs[slot_].b, s_);
-  if (r != hipSuccess) t_timer_err = r;
+  std::lock_guard<std::mutex> lock(g_timer_mu);
+  if (slot_ >= static_cast<int>(g_recs.size())) return;  // the timer was stopped meanwhile
+  const hipError_t r = hipEventRecord(g_recs[slot_].b, s_);
+  if (r != hipSuccess) g_timer_err = r;
 }
 
 }  // namespace gs
@@ -217,6 +227,21 @@ gs_status gs_bin_sort_async(int64_t n, const gs_projected* proj, const gs_camera
                       reinterpret_cast<unsigned long long*>(k_dev), static_cast<hipStream_t>(stream));
 }
 
+namespace {
+// The schedule argument of the compositing calls: a work split in the low
+// byte, optionally or-ed with GS_RENDER_COLOUR_HASH.
+gs_status validate_schedule(int32_t schedule, int32_t deterministic, bool backward, const char* fn) {
+  const int32_t split = schedule & 0xFF, flags = schedule & ~0xFF;
+  if (split < GS_SCHEDULE_PLAIN || split > GS_SCHEDULE_MERGED || (flags & ~GS_RENDER_COLOUR_HASH) != 0)
+    return fail(GS_ERR_INVALID_ARG, std::string(fn) + ": unknown schedule");
+  if (flags && split == GS_SCHEDULE_MERGED)
+    return fail(GS_ERR_UNSUPPORTED, std::string(fn) + ": colour-hash sampling needs schedule PLAIN or BALANCED");
+  if (flags && backward && deterministic)
+    return fail(GS_ERR_UNSUPPORTED, std::string(fn) + ": colour-hash sampling has no deterministic backward");
+  return GS_OK;
+}
+}  // namespace
+
 gs_status gs_render_fwd(int64_t n, const gs_projected* proj, const uint32_t* point_list, const uint32_t* ranges,
                         int64_t k, const gs_camera* cam, float* image, float* final_T, uint32_t* n_contrib,
                         float* t_ckpt, int32_t schedule, gs_stream stream) {
@@ -227,9 +252,8 @@ gs_status gs_render_fwd(int64_t n, const gs_projected* proj, const uint32_t* poi
   if ((st = validate_projected(proj, n, "gs_render_fwd")) != GS_OK) return st;
   if (!ranges || !image || !final_T || !n_contrib || (k > 0 && !point_list))
     return fail(GS_ERR_INVALID_ARG, "gs_render_fwd: NULL array");
-  if (schedule < GS_SCHEDULE_PLAIN || schedule > GS_SCHEDULE_MERGED)
-    return fail(GS_ERR_INVALID_ARG, "gs_render_fwd: unknown schedule");
-  if (schedule != GS_SCHEDULE_PLAIN && !t_ckpt)
+  if ((st = validate_schedule(schedule, 0, false, "gs_render_fwd")) != GS_OK) return st;
+  if ((schedule & 0xFF) != GS_SCHEDULE_PLAIN && !t_ckpt)
     return fail(GS_ERR_INVALID_ARG, "gs_render_fwd: the balanced schedules keep their plan in t_ckpt");
   return launch_render_fwd(*proj, point_list, ranges, k, make_devcam(*cam), image, final_T, n_contrib, t_ckpt,
                            schedule, static_cast<hipStream_t>(stream));
@@ -245,6 +269,19 @@ gs_status gs_render_count(int64_t n, const gs_projected* proj, const uint32_t* p
   if (!ranges || !counts || (k > 0 && !point_list)) return fail(GS_ERR_INVALID_ARG, "gs_render_count: NULL array");
   return launch_render_count(*proj, point_list, ranges, make_devcam(*cam),
                              reinterpret_cast<unsigned long long*>(counts), static_cast<hipStream_t>(stream));
+}
+
+gs_status gs_colour_hash_table(int64_t n, const gs_projected* proj, const uint32_t* point_list,
+                               const uint32_t* ranges, int64_t k, const gs_camera* cam, uint32_t* count,
+                               float* sums, uint16_t* bucket, uint32_t* rep, gs_stream stream) {
+  set_error("");
+  gs_status st;
+  if (n < 0 || k < 0) return fail(GS_ERR_INVALID_ARG, "gs_colour_hash_table: negative n or k");
+  if ((st = validate_camera(cam)) != GS_OK) return st;
+  if ((st = validate_projected(proj, n, "gs_colour_hash_table")) != GS_OK) return st;
+  if (!ranges || (k > 0 && !point_list)) return fail(GS_ERR_INVALID_ARG, "gs_colour_hash_table: NULL array");
+  return launch_chs_table(*proj, point_list, ranges, make_devcam(*cam), count, sums, bucket, rep,
+                          static_cast<hipStream_t>(stream));
 }
 
 gs_status gs_render_ckpt_floats(int64_t k, const gs_camera* cam, size_t* floats) {
@@ -280,8 +317,7 @@ gs_status gs_render_bwd_2d(int64_t n, const gs_projected* proj, const uint32_t* 
   if (!ranges || !final_T || !n_contrib || !t_ckpt || !dL_dimage || (n > 0 && !g2d) || (k > 0 && !point_list))
     return fail(GS_ERR_INVALID_ARG, "gs_render_bwd_2d: NULL array");
   const DevCam d = make_devcam(*cam);
-  if (schedule < GS_SCHEDULE_PLAIN || schedule > GS_SCHEDULE_MERGED)
-    return fail(GS_ERR_INVALID_ARG, "gs_render_bwd_2d: unknown schedule");
+  if ((st = validate_schedule(schedule, deterministic, true, "gs_render_bwd_2d")) != GS_OK) return st;
   if (ws_bytes < render_bwd_workspace(n, k, d.tiles_x * d.tiles_y, deterministic) || !ws)
     return fail(GS_ERR_INVALID_ARG, "gs_render_bwd_2d: workspace too small");
   if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(GS_ERR_INVALID_ARG, "gs_render_bwd_2d: ws not 256-aligned");
@@ -346,8 +382,7 @@ gs_status gs_render_bwd(const gs_gaussians* g, const gs_camera* cam, const gs_pr
     return fail(GS_ERR_INVALID_ARG, "gs_render_bwd: NULL gradient array");
   if (stats && n > 0 && (!stats->grad_norm_sum || !stats->visible_count))
     return fail(GS_ERR_INVALID_ARG, "gs_render_bwd: NULL densification statistics array");
-  if (schedule < GS_SCHEDULE_PLAIN || schedule > GS_SCHEDULE_MERGED)
-    return fail(GS_ERR_INVALID_ARG, "gs_render_bwd: unknown schedule");
+  if ((st = validate_schedule(schedule, deterministic, true, "gs_render_bwd")) != GS_OK) return st;
   const DevCam d = make_devcam(*cam);
   const FullBwdWs layout = carve_full_bwd(nullptr, *g, k, d.tiles_x * d.tiles_y, deterministic);
   if (!ws || ws_bytes < layout.bytes) return fail(GS_ERR_INVALID_ARG, "gs_render_bwd: workspace too small");
@@ -486,21 +521,29 @@ gs_status gs_adam_gaussians(int64_t n, int32_t sh_degree, const gs_param_arrays*
 
 gs_status gs_kernel_timer_start(void) {
   set_error("");
-  if (t_timing) return fail(GS_ERR_INVALID_ARG, "gs_kernel_timer_start: a timer is already running on this thread");
-  t_recs.clear();
-  t_timer_err = hipSuccess;
-  t_timing = true;
+  std::lock_guard<std::mutex> lock(g_timer_mu);
+  if (g_timing.load()) return fail(GS_ERR_INVALID_ARG, "gs_kernel_timer_start: the timer is already running");
+  g_recs.clear();
+  g_timer_err = hipSuccess;
+  g_timing.store(true, std::memory_order_release);
   return GS_OK;
 }
 
 gs_status gs_kernel_timer_stop(char* buf, size_t size, size_t* needed) {
   set_error("");
-  if (!t_timing) return fail(GS_ERR_INVALID_ARG, "gs_kernel_timer_stop: no timer is running on this thread");
-  t_timing = false;
+  std::vector<TimerRec> recs;
+  hipError_t terr;
+  {
+    std::lock_guard<std::mutex> lock(g_timer_mu);
+    if (!g_timing.load()) return fail(GS_ERR_INVALID_ARG, "gs_kernel_timer_stop: the timer is not running");
+    g_timing.store(false, std::memory_order_release);
+    recs.swap(g_recs);
+    terr = g_timer_err;
+  }
   std::vector<std::string> order;
   std::map<std::string, std::pair<long long, double>> acc;
   gs_status st = GS_OK;
-  for (const TimerRec& r : t_recs) {
+  for (const TimerRec& r : recs) {
     float ms = 0.0f;
     if (st == GS_OK) st = check_hip(hipEventSynchronize(r.b), "hipEventSynchronize");
     if (st == GS_OK) st = check_hip(hipEventElapsedTime(&ms, r.a, r.b), "hipEventElapsedTime");
@@ -511,11 +554,15 @@ gs_status gs_kernel_timer_stop(char* buf, size_t size, size_t* needed) {
     }
     it->second.first += 1;
     it->second.second += ms;
-    t_pool.push_back(r.a);
-    t_pool.push_back(r.b);
   }
-  t_recs.clear();
-  if (st == GS_OK && t_timer_err != hipSuccess) st = check_hip(t_timer_err, "kernel timer event");
+  {
+    std::lock_guard<std::mutex> lock(g_timer_mu);
+    for (const TimerRec& r : recs) {
+      g_pool.push_back(r.a);
+      g_pool.push_back(r.b);
+    }
+  }
+  if (st == GS_OK && terr != hipSuccess) st = check_hip(terr, "kernel timer event");
   std::string out;
   for (const std::string& name : order) {
     char line[256];

@@ -19,6 +19,8 @@
 // backward re-derives exactly the forward's skip decisions and transmittances.
 #include "gs_internal.h"
 
+#include <type_traits>
+
 namespace gs {
 
 constexpr int kBatch = 256;
@@ -232,6 +234,174 @@ __device__ __forceinline__ void build_list(Stage& st, int cnt, bool all) {
   if (lane == 0) st.len[wave] = Lp;
 }
 
+// ------------------------------------------------------ colour-hash sampling
+// Sec. IV-C.1 (similarity-based sampling with colour hashing), an optional
+// approximate mode of both compositing directions.  Each channel's 8-bit value
+// v8 = floor(255 clamp(c, 0, 1) + 1/2) (FP32, product then sum; NaN counts as
+// 0) gives the level v8 >> 4 = floor(v8 / 256 * 16), and the bucket is
+// R_q 256 + G_q 16 + B_q (4096 buckets).  Inside each 256-entry batch of a
+// tile's list (the LDS staging window), the entries whose colours share a
+// bucket form a group; a group of two or more is composited as its front-most
+// member with the members' mean colour and the accumulated opacity
+// 1 - prod (1 - o_j), and its other members are not composited.  The grouping
+// is done in LDS with a 4096-bucket table: per bucket one byte per wave, the
+// lane (+1) of the wave's first member, and per wave-first member the ballot
+// mask of its wave's members, so a representative walks its members in list
+// order (wave by wave, lanes ascending) and the result does not depend on
+// timing.  The backward regroups each batch identically, so the aggregated
+// opacity and colour -- and every skip and stop decision -- are the forward's
+// bit for bit; the gradient that reaches a group's aggregated opacity and
+// colour is handed to its members by the chain rule (opacity: times the
+// product of the other members' (1 - o); colour: over the group size), the
+// footprint's gradient to the representative alone.
+constexpr int kChsBuckets = 4096;
+constexpr uint32_t kChsNone = 0xFFFFFFFFu;
+
+__device__ __forceinline__ uint32_t chs_level(float c) {
+  const float cc = c > 0.0f ? fminf(c, 1.0f) : 0.0f;
+  const float t = __fadd_rn(__fmul_rn(cc, 255.0f), 0.5f);
+  return static_cast<uint32_t>(floorf(t)) >> 4;
+}
+
+__device__ __forceinline__ uint32_t chs_bucket(float r, float g, float b) {
+  return chs_level(r) * 256u + chs_level(g) * 16u + chs_level(b);
+}
+
+struct ChsStage {
+  uint32_t table[kChsBuckets];  // byte w: 1 + lane of wave w's first member of the bucket (0: none)
+  uint64_t wmask[kBatch];       // at a wave's first member of a bucket: the wave's members of it
+  uint32_t rep[kBatch];         // slot of the group's representative (groups of >= 2), else kChsNone
+  float share_o[kBatch];        // product over the group's other members of (1 - o)
+  float inv_n[kBatch];          // 1 / group size
+};
+
+// Thread t's bucket and whether it is its wave's first member of the bucket
+// (it then resets the bucket's table word once nobody reads it any more).
+struct ChsSlot {
+  uint32_t bucket;
+  bool wave_first;
+};
+
+__device__ __forceinline__ void chs_clear(ChsStage& cs) {
+  for (int i = threadIdx.x; i < kChsBuckets; i += 256) cs.table[i] = 0u;
+}
+
+// Alpha-support box of a representative whose opacity rose from o to o_hat:
+// the half-extents grow with rho = sqrt(2 ln(255 o) 1.02 + 2e-4) (the slack
+// the projection gives rho^2), so the pixel-independent part of each extent
+// scales by rho_hat / rho (times 1 + 1e-5 for the rounding of the rescale).
+__device__ __forceinline__ void chs_support(float o, float o_hat, float u, float v, float& ex, float& ey) {
+  if (!(ex < 1.0e30f)) return;                 // unbounded box stays unbounded
+  const float lo_new = logf(255.0f * o_hat);
+  if (!(lo_new > 0.0f)) { ex = -1.0f; ey = -1.0f; return; }
+  const float lo_old = logf(255.0f * o);
+  if (!(lo_old > 0.0f) || !(ex >= 0.0f)) { ex = 3.0e38f; ey = 3.0e38f; return; }
+  const float scale = sqrtf((2.0f * lo_new * 1.02f + 2e-4f) / (2.0f * lo_old * 1.02f + 2e-4f)) * (1.0f + 1e-5f);
+  const float mx = 1e-3f + 1e-6f * fabsf(u), my = 1e-3f + 1e-6f * fabsf(v);
+  ex = fmaxf(ex - mx, 0.0f) * scale + mx;
+  ey = fmaxf(ey - my, 0.0f) * scale + my;
+}
+
+// Groups the staged batch (slots 0..cnt-1 in list order) by colour bucket and
+// rewrites it in place: a representative of a group of two or more gets the
+// mean colour, the accumulated opacity and the quadrant mask of that opacity;
+// the other members get an empty quadrant mask.  SHARES also fills rep,
+// share_o and inv_n for the backward.  cs.table must be zero on entry; call
+// chs_release after the next workgroup barrier.  One barrier inside.
+template <bool SHARES>
+__device__ ChsSlot chs_group(Stage& st, ChsStage& cs, const float4* __restrict__ rec, int cnt, float x0, float y0) {
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const bool valid = t < cnt;
+  const uint32_t h = valid ? chs_bucket(st.q[t].z, st.q[t].w, st.c[t].x) : 0u;
+  // lanes of this wave whose bucket equals this lane's (12 ballots)
+  uint64_t same = __ballot(valid);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    const bool bit = (h >> k) & 1u;
+    const uint64_t b = __ballot(bit);
+    same &= bit ? b : ~b;
+  }
+  const bool wfirst = valid && static_cast<int>(__builtin_ctzll(same)) == lane;
+  if (wfirst) {
+    cs.wmask[t] = same;
+    atomicOr(&cs.table[h], static_cast<uint32_t>(lane + 1) << (8 * wave));
+  }
+  if (SHARES) cs.rep[t] = kChsNone;
+  __syncthreads();
+  if (valid) {
+    const uint32_t word = cs.table[h];
+    const int w0 = static_cast<int>(__builtin_ctz(word)) >> 3;
+    const int r = 64 * w0 + static_cast<int>((word >> (8 * w0)) & 0xFFu) - 1;
+    int n = 0;
+    for (int w = w0; w < 4; ++w) {
+      const uint32_t b = (word >> (8 * w)) & 0xFFu;
+      if (b) n += __popcll(cs.wmask[64 * w + static_cast<int>(b) - 1]);
+    }
+    if (n > 1) {
+      if (SHARES) {
+        cs.rep[t] = static_cast<uint32_t>(r);
+        cs.inv_n[t] = 1.0f / static_cast<float>(n);
+      }
+      if (t == r) {
+        // members in list order: waves ascending, lanes ascending
+        float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, keep = 1.0f;
+        for (int w = w0; w < 4; ++w) {
+          const uint32_t b = (word >> (8 * w)) & 0xFFu;
+          if (!b) continue;
+          uint64_t m = cs.wmask[64 * w + static_cast<int>(b) - 1];
+          while (m) {
+            const int j = 64 * w + static_cast<int>(__builtin_ctzll(m));
+            m &= m - 1;
+            const float4 q = st.q[j];
+            s0 += q.z;
+            s1 += q.w;
+            s2 += st.c[j].x;
+            if (SHARES) cs.share_o[j] = keep;   // product over the members before j
+            keep *= 1.0f - q.y;
+          }
+        }
+        if (SHARES) {
+          // times the product over the members after j
+          float suf = 1.0f;
+          for (int w = 3; w >= w0; --w) {
+            const uint32_t b = (word >> (8 * w)) & 0xFFu;
+            if (!b) continue;
+            uint64_t m = cs.wmask[64 * w + static_cast<int>(b) - 1];
+            while (m) {
+              const int bit = 63 - static_cast<int>(__builtin_clzll(m));
+              m &= ~(1ull << bit);
+              const int j = 64 * w + bit;
+              cs.share_o[j] *= suf;
+              suf *= 1.0f - st.q[j].y;
+            }
+          }
+        }
+        const float inv = 1.0f / static_cast<float>(n);
+        const float o_hat = 1.0f - keep;
+        const uint32_t gid = st.gid[t];
+        const float4 r0 = rec[3 * gid];
+        float4 r1 = rec[3 * gid + 1];
+        float4 r2 = rec[3 * gid + 2];
+        chs_support(r1.y, o_hat, r0.x, r0.y, r2.z, r2.w);
+        r1.y = o_hat;
+        float4 q = st.q[t];
+        q.y = o_hat;
+        q.z = s0 * inv;
+        q.w = s1 * inv;
+        st.q[t] = q;
+        st.c[t] = make_float2(s2 * inv, __uint_as_float(quad_mask(r0, r1, r2, x0, y0)));
+      } else {
+        st.c[t].y = __uint_as_float(0u);  // not composited: no wave visits it
+      }
+    }
+  }
+  return ChsSlot{h, wfirst};
+}
+
+__device__ __forceinline__ void chs_release(ChsStage& cs, const ChsSlot& sl) {
+  if (sl.wave_first) cs.table[sl.bucket] = 0u;
+}
+
 // ------------------------------------------------------------------- forward
 
 // One (pixel, entry) step of the front-to-back walk; m1 = 1 + the entry's
@@ -260,7 +430,7 @@ __device__ __forceinline__ bool fwd_pair(const float4& p, const float4& q, float
 // COUNT = true runs the same decisions on every entry (no culling) but only
 // counts, per pixel, the pairs examined (alpha evaluated before the walk ends)
 // and the pairs blended, and adds them to counts[0], counts[1].
-template <bool COUNT>
+template <bool COUNT, bool CHS = false>
 __global__ __launch_bounds__(256) void k_render_fwd(const uint2* __restrict__ ranges,
                                                     const uint32_t* __restrict__ point_list,
                                                     const float4* __restrict__ rec, DevCam cam,
@@ -272,8 +442,10 @@ __global__ __launch_bounds__(256) void k_render_fwd(const uint2* __restrict__ ra
                                                     float* __restrict__ c_ckpt, size_t cplane) {
   __shared__ Stage st;
   __shared__ uint32_t s_work;
+  __shared__ typename std::conditional<CHS, ChsStage, char>::type cs;
   const int tile = tile_of_block(plan, blockIdx.x, gridDim.x);
   if (tile < 0) return;
+  if constexpr (CHS) chs_clear(cs);
   const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
   int lx, ly;
   tile_pixel(threadIdx.x, lx, ly);
@@ -305,8 +477,14 @@ __global__ __launch_bounds__(256) void k_render_fwd(const uint2* __restrict__ ra
     const int cnt = static_cast<int>(min(static_cast<uint32_t>(kBatch), rg.y - base));
     stage_batch(st, rec, point_list, base, cnt, x0, y0);
     __syncthreads();
+    ChsSlot sl{0u, false};
+    if constexpr (CHS) {
+      sl = chs_group<false>(st, cs, rec, cnt, x0, y0);
+      __syncthreads();
+    }
     build_list(st, cnt, COUNT);
     __syncthreads();
+    if constexpr (CHS) chs_release(cs, sl);
     const uint32_t m0 = base - rg.x + 1u;
     const int L = st.len[wave];
     float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
@@ -429,10 +607,98 @@ __global__ __launch_bounds__(256) void k_render_fwd_light(const uint2* __restric
   if (lane == 0) tile_work[tile] = mx;
 }
 
+// Bucket table of the colour-hash sampling mode over every list entry of the
+// frame (every 256-entry window, whether or not compositing reaches it), and
+// optionally each entry's bucket and representative.  Two stages, as the
+// paper describes the aggregation: within the workgroup each window's groups
+// are summed at their representative in LDS; then each group adds its count
+// and sums to the frame's 4096-bucket table with device atomics.  One
+// workgroup per tile, windows in list order.
+__global__ __launch_bounds__(256) void k_chs_table(const uint2* __restrict__ ranges,
+                                                   const uint32_t* __restrict__ point_list,
+                                                   const float4* __restrict__ rec, DevCam cam,
+                                                   uint32_t* __restrict__ tab_count, float* __restrict__ tab_sum,
+                                                   uint16_t* __restrict__ bucket_out, uint32_t* __restrict__ rep_out) {
+  __shared__ Stage st;
+  __shared__ ChsStage cs;
+  __shared__ float4 s_sum[kBatch];    // colour and opacity sums of a group, at its representative
+  __shared__ uint32_t s_n[kBatch];
+  const int tile = blockIdx.x;
+  const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
+  const float x0 = static_cast<float>(tx * kTile), y0 = static_cast<float>(ty * kTile);
+  const uint2 rg = ranges[tile];
+  const int t = threadIdx.x;
+  chs_clear(cs);
+  for (uint32_t base = rg.x; base < rg.y; base += kBatch) {
+    const int cnt = static_cast<int>(min(static_cast<uint32_t>(kBatch), rg.y - base));
+    __syncthreads();
+    stage_batch(st, rec, point_list, base, cnt, x0, y0);
+    s_sum[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+    s_n[t] = 0u;
+    __syncthreads();
+    const bool valid = t < cnt;
+    // the entry's own colour and opacity, before the grouping rewrites the batch
+    const float4 own = valid ? make_float4(st.q[t].z, st.q[t].w, st.c[t].x, st.q[t].y) : make_float4(0.f, 0.f, 0.f, 0.f);
+    const ChsSlot sl = chs_group<true>(st, cs, rec, cnt, x0, y0);
+    __syncthreads();
+    chs_release(cs, sl);
+    const int r = valid && cs.rep[t] != kChsNone ? static_cast<int>(cs.rep[t]) : t;
+    if (valid) {
+      if (bucket_out) bucket_out[base + t] = static_cast<uint16_t>(sl.bucket);
+      if (rep_out) rep_out[base + t] = base + static_cast<uint32_t>(r);
+      if (tab_count || tab_sum) {
+        // stage 1: the group's sums at its representative (LDS)
+        atomicAdd(&s_n[r], 1u);
+        atomicAdd(&s_sum[r].x, own.x);
+        atomicAdd(&s_sum[r].y, own.y);
+        atomicAdd(&s_sum[r].z, own.z);
+        atomicAdd(&s_sum[r].w, own.w);
+      }
+    }
+    __syncthreads();
+    // stage 2: one set of device atomics per group
+    if (valid && r == t && (tab_count || tab_sum)) {
+      const uint32_t h = sl.bucket;
+      if (tab_count) atomicAdd(&tab_count[h], s_n[t]);
+      if (tab_sum) {
+        const float4 v = s_sum[t];
+        unsafeAtomicAdd(&tab_sum[4 * h], v.x);
+        unsafeAtomicAdd(&tab_sum[4 * h + 1], v.y);
+        unsafeAtomicAdd(&tab_sum[4 * h + 2], v.z);
+        unsafeAtomicAdd(&tab_sum[4 * h + 3], v.w);
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_chs_table_clear(uint32_t* __restrict__ tab_count, float* __restrict__ tab_sum) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= kChsBuckets) return;
+  if (tab_count) tab_count[i] = 0u;
+  if (tab_sum) reinterpret_cast<float4*>(tab_sum)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+gs_status launch_chs_table(const gs_projected& proj, const uint32_t* point_list, const uint32_t* ranges,
+                           const DevCam& cam, uint32_t* tab_count, float* tab_sum, uint16_t* bucket_out,
+                           uint32_t* rep_out, hipStream_t s) {
+  const int ntiles = cam.tiles_x * cam.tiles_y;
+  if (tab_count || tab_sum) {
+    { TimedLaunch gs_tl("k_chs_table_clear", s); k_chs_table_clear<<<kChsBuckets / 256, 256, 0, s>>>(tab_count, tab_sum); }
+    gs_status st = check_launch("k_chs_table_clear");
+    if (st != GS_OK) return st;
+  }
+  { TimedLaunch gs_tl("k_chs_table", s); k_chs_table<<<ntiles, 256, 0, s>>>(reinterpret_cast<const uint2*>(ranges), point_list,
+                                                   reinterpret_cast<const float4*>(proj.records), cam, tab_count,
+                                                   tab_sum, bucket_out, rep_out); }
+  return check_launch("k_chs_table");
+}
+
 gs_status launch_render_fwd(const gs_projected& proj, const uint32_t* point_list, const uint32_t* ranges, int64_t k,
                             const DevCam& cam, float* image, float* final_T, uint32_t* n_contrib, float* t_ckpt,
-                            int schedule, hipStream_t s) {
+                            int schedule_flags, hipStream_t s) {
   const int ntiles = cam.tiles_x * cam.tiles_y;
+  const bool chs = (schedule_flags & GS_RENDER_COLOUR_HASH) != 0;
+  const int schedule = schedule_flags & 0xFF;
   int32_t* plan = nullptr;
   uint32_t* tile_work = nullptr;
   float* c_ckpt = nullptr;
@@ -454,9 +720,18 @@ gs_status launch_render_fwd(const gs_projected& proj, const uint32_t* point_list
       plan = nullptr;
     }
   }
-  { TimedLaunch gs_tl("k_render_fwd<false>", s); k_render_fwd<false><<<ntiles, 256, 0, s>>>(reinterpret_cast<const uint2*>(ranges), point_list,
-                                             reinterpret_cast<const float4*>(proj.records), cam, image, final_T,
-                                             n_contrib, t_ckpt, nullptr, plan, tile_work, c_ckpt, cplane); }
+  if (chs) {
+    TimedLaunch gs_tl("k_render_fwd<false, true>", s);
+    k_render_fwd<false, true><<<ntiles, 256, 0, s>>>(reinterpret_cast<const uint2*>(ranges), point_list,
+                                                      reinterpret_cast<const float4*>(proj.records), cam, image,
+                                                      final_T, n_contrib, t_ckpt, nullptr, plan, tile_work, c_ckpt,
+                                                      cplane);
+  } else {
+    TimedLaunch gs_tl("k_render_fwd<false>", s);
+    k_render_fwd<false><<<ntiles, 256, 0, s>>>(reinterpret_cast<const uint2*>(ranges), point_list,
+                                               reinterpret_cast<const float4*>(proj.records), cam, image, final_T,
+                                               n_contrib, t_ckpt, nullptr, plan, tile_work, c_ckpt, cplane);
+  }
   return check_launch("k_render_fwd");
 }
 
@@ -652,7 +927,7 @@ __global__ __launch_bounds__(256) void k_det_reduce(int n, const uint32_t* __res
 // atomics of an instruction meet in one line (the [9][n] output is written
 // from it afterwards).  DET: the sums go to the entry's row of `part` instead
 // (deterministic reduction above).
-template <bool DET>
+template <bool DET, bool CHS = false>
 __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ranges,
                                                     const uint32_t* __restrict__ point_list,
                                                     const float4* __restrict__ rec, DevCam cam,
@@ -671,6 +946,11 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
   // DET: each wave's nine sums per staged entry, [wave][entry][9]
   __shared__ float4 s_part4[DET ? 4 * kBatch * kDetRow / 4 : 1];
   float* const s_part = reinterpret_cast<float*>(s_part4);
+  // CHS: the grouping, and per staged entry the sums of the gradient reaching
+  // its group's aggregated opacity and colour (representatives only)
+  __shared__ typename std::conditional<CHS, ChsStage, char>::type cs;
+  __shared__ float4 s_chs4[CHS ? kBatch : 1];
+  float* const s_chs = reinterpret_cast<float*>(s_chs4);
   // items: this workgroup walks one batch of one tile (the batch plan);
   // otherwise the whole tile (plain map, or the plan's order)
   int tile, b_only = -1;
@@ -684,6 +964,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
     tile = tile_of_block(plan, blockIdx.x, gridDim.x);
     if (tile < 0) return;
   }
+  if constexpr (CHS) chs_clear(cs);
   const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
   int lx, ly;
   tile_pixel(threadIdx.x, lx, ly);
@@ -739,14 +1020,23 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
     const uint32_t m0 = static_cast<uint32_t>(bi) * kBatch;
     const int cnt = static_cast<int>(min(static_cast<uint32_t>(kBatch), len - m0));
     T = (bi + 1 < nbatch) ? t_ckpt[(slot0 + bi + 1) * kBatch + threadIdx.x] : T_final;
+    // CHS groups the whole 256-entry window, walked or not, as the forward did
+    const int cnt_all = CHS ? static_cast<int>(min(static_cast<uint32_t>(kBatch), rg.y - rg.x - m0)) : cnt;
     __syncthreads();
-    stage_batch(st, rec, point_list, rg.x + m0, cnt, x0, y0);
+    stage_batch(st, rec, point_list, rg.x + m0, cnt_all, x0, y0);
     if constexpr (DET) {
       for (int i = threadIdx.x; i < 4 * kBatch * kDetRow / 4; i += 256) s_part4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
+    if constexpr (CHS) s_chs4[threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
+    ChsSlot sl{0u, false};
+    if constexpr (CHS) {
+      sl = chs_group<true>(st, cs, rec, cnt_all, x0, y0);
+      __syncthreads();
+    }
     build_list(st, cnt, false);
     __syncthreads();
+    if constexpr (CHS) chs_release(cs, sl);
     for (int i = st.len[wave] - 1; i >= 0; --i) {
       const uint32_t j = uniform(st.list[wave][i]);
       if (j == kNull) continue;
@@ -767,7 +1057,35 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
       if constexpr (DET) {
         if (writer) s_part[(wave * kBatch + static_cast<int>(j)) * kDetRow + out_slot] = lane == 63 ? red9 : red8;
       } else {
-        if (writer) unsafeAtomicAdd(&g_out[static_cast<int64_t>(st.gid[j]) * kAccStride], lane == 63 ? red9 : red8);
+        // CHS: a group's opacity and colour sums wait in LDS for the member pass below
+        bool to_lds = false;
+        if constexpr (CHS) to_lds = out_slot >= 5 && cs.rep[j] != kChsNone;
+        if (writer) {
+          if (to_lds)
+            atomicAdd(&s_chs[4 * static_cast<int>(j) + out_slot - 5], lane == 63 ? red9 : red8);
+          else
+            unsafeAtomicAdd(&g_out[static_cast<int64_t>(st.gid[j]) * kAccStride], lane == 63 ? red9 : red8);
+        }
+      }
+    }
+    if constexpr (CHS) {
+      // every member of a group of two or more (representative included) gets
+      // its share of the gradient of the group's opacity and colour
+      __syncthreads();
+      const int t = threadIdx.x;
+      if (t < cnt_all) {
+        const uint32_t r = cs.rep[t];
+        if (r != kChsNone) {
+          const float4 tot = s_chs4[r];
+          if (tot.x != 0.0f || tot.y != 0.0f || tot.z != 0.0f || tot.w != 0.0f) {
+            float* const row = acc + static_cast<int64_t>(st.gid[t]) * kAccStride;
+            const float so = cs.share_o[t], sn = cs.inv_n[t];
+            unsafeAtomicAdd(row + 5, tot.x * so);
+            unsafeAtomicAdd(row + 6, tot.y * sn);
+            unsafeAtomicAdd(row + 7, tot.z * sn);
+            unsafeAtomicAdd(row + 8, tot.w * sn);
+          }
+        }
       }
     }
     if constexpr (DET) {
@@ -917,8 +1235,12 @@ size_t render_bwd_workspace(int64_t n, int64_t k, int ntiles, int deterministic)
 gs_status launch_render_bwd(int64_t n, const gs_projected& proj, const uint32_t* point_list, const uint32_t* ranges,
                             int64_t k, const DevCam& cam, const float* final_T,
                             const uint32_t* n_contrib, const float* t_ckpt, const float* dL_dimage, float* g2d, void* ws,
-                            size_t ws_bytes, int deterministic, int schedule, const float** rows_out, hipStream_t s) {
+                            size_t ws_bytes, int deterministic, int schedule_flags, const float** rows_out, hipStream_t s) {
   (void)ws_bytes;
+  const bool chs = (schedule_flags & GS_RENDER_COLOUR_HASH) != 0;
+  const int schedule = schedule_flags & 0xFF;
+  if (chs && (deterministic || schedule == GS_SCHEDULE_MERGED))
+    return fail(GS_ERR_UNSUPPORTED, "render backward: colour-hash sampling needs atomic mode and PLAIN or BALANCED");
   if (!g2d && (deterministic || !rows_out)) return fail(GS_ERR_INVALID_ARG, "render backward: no output");
   const int ntiles = cam.tiles_x * cam.tiles_y;
   char* w = static_cast<char*>(ws);
@@ -957,6 +1279,10 @@ gs_status launch_render_bwd(int64_t n, const gs_projected& proj, const uint32_t*
       { TimedLaunch gs_tl("k_render_bwd<true>", s); k_render_bwd<true><<<grid, 256, 0, s>>>(rg, point_list, rec, cam, final_T, n_contrib, t_ckpt, dL_dimage,
                                               static_cast<int>(n), acc, nullptr, items, tile_work, c_ckpt, cplane,
                                               det.part, det.row_of, rows); }
+    else if (chs)
+      { TimedLaunch gs_tl("k_render_bwd<false, true>", s); k_render_bwd<false, true><<<grid, 256, 0, s>>>(rg, point_list, rec, cam, final_T, n_contrib, t_ckpt, dL_dimage,
+                                                     static_cast<int>(n), acc, nullptr, items, tile_work, c_ckpt, cplane,
+                                                     nullptr, nullptr, 0); }
     else
       { TimedLaunch gs_tl("k_render_bwd<false>", s); k_render_bwd<false><<<grid, 256, 0, s>>>(rg, point_list, rec, cam, final_T, n_contrib, t_ckpt, dL_dimage,
                                                static_cast<int>(n), acc, nullptr, items, tile_work, c_ckpt, cplane,

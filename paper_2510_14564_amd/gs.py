@@ -29,13 +29,16 @@ MLP_PARAMS = 6467
 MLP_PACKED_BYTES = 31244
 
 SCHEDULE_PLAIN, SCHEDULE_BALANCED, SCHEDULE_MERGED = 0, 1, 2
+# or-ed into a compositing call's schedule: the approximate colour-hash sampling mode
+RENDER_COLOUR_HASH = 0x100
+COLOUR_BUCKETS = 4096
 GS_OK, GS_ERR_INVALID_ARG, GS_ERR_CAPACITY, GS_ERR_HIP, GS_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
 STATUS_NAMES = {0: "GS_OK", -1: "GS_ERR_INVALID_ARG", -2: "GS_ERR_CAPACITY", -3: "GS_ERR_HIP",
                 -4: "GS_ERR_UNSUPPORTED"}
 
 # every symbol declared in include/gsplat.h
 EXPORTS = ("gs_last_error", "gs_version", "gs_project", "gs_bin_sort_workspace", "gs_bin_sort", "gs_bin_sort_async",
-           "gs_render_fwd", "gs_render_count", "gs_render_ckpt_floats", "gs_render_bwd_workspace", "gs_render_bwd",
+           "gs_render_fwd", "gs_render_count", "gs_colour_hash_table", "gs_render_ckpt_floats", "gs_render_bwd_workspace", "gs_render_bwd",
            "gs_render_bwd_2d_workspace", "gs_render_bwd_2d", "gs_project_bwd", "gs_project_bwd_workspace",
            "gs_adam_gaussians", "gs_l1_loss", "gs_mlp_pack", "gs_mlp_fwd", "gs_mlp_bwd_workspace", "gs_mlp_bwd",
            "gs_sh_colour", "gs_adam_step", "gs_kernel_timer_start", "gs_kernel_timer_stop")
@@ -101,6 +104,8 @@ _sigs = {
                       ctypes.c_int),
     "gs_render_ckpt_floats": ([_i64, _P(Camera), _P(_sz)], ctypes.c_int),
     "gs_render_count": ([_i64, _P(Projected), _vp, _vp, _i64, _P(Camera), _vp, _vp], ctypes.c_int),
+    "gs_colour_hash_table": ([_i64, _P(Projected), _vp, _vp, _i64, _P(Camera), _vp, _vp, _vp, _vp, _vp],
+                             ctypes.c_int),
     "gs_render_bwd_workspace": ([_P(Gaussians), _i64, _P(Camera), _i32, _P(_sz)], ctypes.c_int),
     "gs_render_bwd": ([_P(Gaussians), _P(Camera), _P(Projected), _vp, _vp, _i64, _vp, _vp, _vp, _vp,
                        _P(GaussiansGrad), _P(DensifyStats), _vp, _sz, _i32, _i32, _vp], ctypes.c_int),
@@ -263,6 +268,16 @@ def render_count(n: int, proj: ProjectedBuffers, point_list, ranges, k: int, cam
                                 _ptr(counts), _stream(stream)), "gs_render_count")
 
 
+def colour_hash_table(n: int, proj: ProjectedBuffers, point_list, ranges, k: int, cam: Camera, count=None, sums=None,
+                      bucket=None, rep=None, stream=None):
+    """Colour-hash sampling statistics of a binned frame: count uint32[4096],
+    sums float[4096][4] (r, g, b, opacity), bucket uint16[k] and rep uint32[k]
+    (device tensors, each optional, overwritten)."""
+    _check(_lib.gs_colour_hash_table(n, ctypes.byref(proj.struct()), _ptr(point_list), _ptr(ranges), k,
+                                     ctypes.byref(cam), _ptr(count), _ptr(sums), _ptr(bucket), _ptr(rep),
+                                     _stream(stream)), "gs_colour_hash_table")
+
+
 def render_ckpt_floats(k: int, cam: Camera) -> int:
     f = ctypes.c_size_t(0)
     _check(_lib.gs_render_ckpt_floats(k, ctypes.byref(cam), ctypes.byref(f)), "gs_render_ckpt_floats")
@@ -361,6 +376,7 @@ def project_bwd(gauss: Gaussians, cam: Camera, g2d, grads: dict, proj: Projected
 def l1_loss(img, target, loss, grad, partials, stream=None):
     _check(_lib.gs_l1_loss(_ptr(img), _ptr(target), img.numel(), _ptr(loss), _ptr(grad), _ptr(partials),
                            _stream(stream)), "gs_l1_loss")
+
 
 
 # ------------------------------------------------------------ learned colour

@@ -40,6 +40,7 @@ class FrameState:
     final_T: torch.Tensor
     n_contrib: torch.Tensor
     t_ckpt: torch.Tensor
+    schedule: int = gs.SCHEDULE_BALANCED   # work split (and sampling flag) of the forward; the backward uses it
 
 
 class Rasterizer:
@@ -47,6 +48,8 @@ class Rasterizer:
 
     def __init__(self, cam, sh_degree: int, device="cuda", deterministic: bool = False, capacity: int | None = None,
                  schedule: int = gs.SCHEDULE_BALANCED, async_k: bool = False):
+        """schedule: a work split, optionally or-ed with gs.RENDER_COLOUR_HASH
+        (the approximate colour-hash sampling mode, forward and backward)."""
         self.cam = cam
         # async_k: bin with gs_bin_sort_async (no host wait inside a frame) once
         # a frame's K is known; each frame's K is checked at the next forward
@@ -158,7 +161,8 @@ class Rasterizer:
         with self._stage("render_fwd"):
             gs.render_fwd(n, proj, point_list, ranges, k, cs, image, final_T, n_contrib, t_ckpt,
                           schedule=self.schedule)
-        self.last_frame = FrameState(n, k, cs, proj, point_list, ranges, image, final_T, n_contrib, t_ckpt)
+        self.last_frame = FrameState(n, k, cs, proj, point_list, ranges, image, final_T, n_contrib, t_ckpt,
+                                     self.schedule)
         return self.last_frame
 
     def check_async(self) -> int | None:
@@ -200,7 +204,7 @@ class Rasterizer:
         with self._stage("render_bwd"):
             gs.render_bwd(g, st.cs, st.proj, st.point_list, st.ranges, st.k, st.final_T, st.n_contrib, st.t_ckpt,
                           dL_dimage, grads, self.bwd_ws, stats=stats, deterministic=self.deterministic,
-                          schedule=self.schedule)
+                          schedule=st.schedule)
         return grads
 
 

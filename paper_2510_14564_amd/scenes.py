@@ -236,6 +236,22 @@ def low_rank_colour(scene: Scene, rank: int, seed: int) -> Scene:
     return dataclasses.replace(scene, sh=_f32(sh))
 
 
+def coherent_colour(scene: Scene, seed: int, noise: float = 0.03) -> Scene:
+    """The same scene with spatially coherent base colour, as in captured
+    scenes where neighbouring Gaussians of a dense region share a colour: the
+    degree-0 coefficient of channel k is 1.2 sin(2.5 <w_k, mu> + phi_k) +
+    N(0, noise^2), a smooth field over space (w_k unit directions, phi_k
+    phases, both seeded).  Higher-degree coefficients are kept."""
+    rng = np.random.default_rng(seed)
+    w = rng.standard_normal((3, 3))
+    w /= np.linalg.norm(w, axis=1, keepdims=True)
+    phi = rng.uniform(0.0, 2.0 * np.pi, 3)
+    mu = scene.means.astype(np.float64)
+    sh = scene.sh.astype(np.float64).copy()
+    sh[0] = 1.2 * np.sin(2.5 * (w @ mu) + phi[:, None]) + rng.normal(0.0, noise, (3, scene.n))
+    return dataclasses.replace(scene, sh=_f32(sh))
+
+
 def config_camera(cfg: int, k: int = 0, bg=(0.0, 0.0, 0.0)) -> Camera:
     if cfg == 1:
         return front_camera(128, 128, 3.0, 60.0, bg)
