@@ -212,6 +212,9 @@ def oracle_render_bwd_sigma(rec, pl, ranges, cam, G, tile_mask=None, flips=None,
 
 # ------------------------------------------------- forward comparison
 
+_POPCOUNT8 = np.array([bin(i).count("1") for i in range(256)], np.int64)
+
+
 def check_render(image, fT, nc, rec, pl, ranges, cam, margins=STAGED_MARGINS, tile_mask=None, pix_mask=None,
                  t_rtol=5e-4, max_ambiguous=1e-4):
     """Compare the HIP forward with the oracle's on every pixel of pix_mask.
@@ -221,9 +224,11 @@ def check_render(image, fT, nc, rec, pl, ranges, cam, margins=STAGED_MARGINS, ti
     is not skipped: the oracle walks it once per combination of branches of its
     near decisions, and the HIP pixel must be one of those outcomes -- equal
     n_contrib, colour within PIX_ATOL and final_T within t_rtol relative.  The
-    branches of an alpha or stop decision differ by at least 1/255 in T or by
-    n_contrib, so the closest outcome identifies the branch the HIP path took;
-    the oracle then uses that branch (flips) for this pixel.  A pixel whose
+    branches of one alpha or stop decision differ by at least 1/255 in T or by
+    n_contrib, but two flips can compensate each other, so the matching
+    outcome with the fewest flips, then the closest transmittance, identifies
+    the branch the HIP path took; the oracle then uses that branch (flips) for
+    this pixel.  A pixel whose
     outcomes cannot be told apart (a clamp at 0.99 changes T by about 1e-5) is
     ambiguous: its colour is checked, and its upstream gradient must be zeroed.
     Afterwards every pixel must match the oracle with the resolved branches:
@@ -259,8 +264,13 @@ def check_render(image, fT, nc, rec, pl, ranges, cam, margins=STAGED_MARGINS, ti
             cand = np.flatnonzero(okp)
             assert cand.size, (f"pixel {divmod(int(p), W)[::-1]} matches no branch of its near decisions: "
                                f"HIP n_contrib {n.flat[p]}, T {T.flat[p]!r}")
-            best = cand[np.argmin(ep[cand])]
-            rest = cand[cand != best]
+            # fewest flipped decisions first (FP32 takes a decision the other
+            # way only when it lies very close to its threshold; two flips can
+            # compensate in T and colour), then the closest transmittance
+            nflip = _POPCOUNT8[cand]
+            fewest = cand[nflip == nflip.min()]
+            best = fewest[np.argmin(ep[fewest])]
+            rest = fewest[fewest != best]
             flips.flat[p] = best
             if rest.size and ep[rest].min() <= 4 * ep[best] + 1e-6:
                 amb.flat[p] = True
