@@ -429,6 +429,22 @@ gs_status gs_adam_step(int64_t n, float* param, const float* grad, float* m, flo
 gs_status gs_l1_loss(const float* img, const float* target, int64_t count, float* loss, float* grad,
                      float* partials, gs_stream stream);
 
+/* gs_l1_loss without caller scratch and without any allocation, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  The partial sums live in
+ * a file-scope device array of GS_L1_STATIC_PARTIALS floats (4 KiB), one copy
+ * per GPU, held until the process ends; its address is looked up on the first
+ * call on each device (with that device current).  Every partial-sum slot is
+ * written before it is read, so nothing needs clearing between calls.  The
+ * partial sums number min(GS_L1_PARTIALS, ceil(count / 256)), which never
+ * exceeds the array (GS_ERR_CAPACITY otherwise), so any count > 0 is taken.
+ * Calls that overlap on one GPU (other streams, other threads) share the array
+ * and race: serialise them.  Same arguments, result and errors as gs_l1_loss
+ * otherwise; GS_ERR_UNSUPPORTED for a device index above 63. */
+#define GS_L1_STATIC_PARTIALS 1024
+gs_status gs_l1_loss_static(const float* img, const float* target, int64_t count, float* loss, float* grad,
+                            gs_stream stream);
+
 /* ------------------------------------------------------------ measurement
  * Kernel timer (for benchmarks; not needed by the path).  After
  * gs_kernel_timer_start, every kernel the library launches is bracketed by

@@ -586,4 +586,18 @@ gs_status gs_l1_loss(const float* img, const float* target, int64_t count, float
   return launch_l1(img, target, count, loss, grad, partials, static_cast<hipStream_t>(stream));
 }
 
+gs_status gs_l1_loss_static(const float* img, const float* target, int64_t count, float* loss, float* grad,
+                            gs_stream stream) {
+  set_error("");
+  if (count <= 0 || !img || !target || !loss)
+    return fail(GS_ERR_INVALID_ARG, "gs_l1_loss_static: bad arguments");
+  // one partial sum per partial-sum workgroup, at most GS_L1_PARTIALS of them
+  if (std::min<int64_t>(GS_L1_PARTIALS, ceil_div(count, 256)) > GS_L1_STATIC_PARTIALS)
+    return fail(GS_ERR_CAPACITY, "gs_l1_loss_static: more partial sums than the static scratch holds");
+  float* partials = nullptr;
+  gs_status st = static_scratch(&partials);
+  if (st != GS_OK) return st;
+  return launch_l1(img, target, count, loss, grad, partials, static_cast<hipStream_t>(stream));
+}
+
 }  // extern "C"

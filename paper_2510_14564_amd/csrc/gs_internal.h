@@ -199,6 +199,9 @@ gs_status launch_adam(int64_t n, float* p, const float* g, float* m, float* v, u
                       float b2, float eps, float bc1, float bc2, hipStream_t s);
 gs_status launch_l1(const float* img, const float* target, int64_t count, float* loss, float* grad, float* partials,
                     hipStream_t s);
+// Device address of the current GPU's copy of the no-allocation L1 scratch
+// array (GS_L1_STATIC_PARTIALS floats), looked up once per device.
+gs_status static_scratch(float** out);
 gs_status launch_adam_gaussians(int64_t n, int sh_degree, const gs_param_arrays& p, const gs_gaussians_grad& g,
                                 const gs_param_arrays& m, const gs_param_arrays& v, const gs_adam_config& cfg,
                                 hipStream_t s);

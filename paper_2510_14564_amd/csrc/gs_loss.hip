@@ -3,6 +3,8 @@
 // partials in a fixed order (deterministic).
 #include "gs_internal.h"
 
+#include <mutex>
+
 namespace gs {
 
 constexpr int kL1Blocks = GS_L1_PARTIALS;
@@ -80,6 +82,38 @@ gs_status launch_l1(const float* img, const float* target, int64_t count, float*
   { TimedLaunch gs_tl("k_l1_partial", s); k_l1_partial<<<nb, 256, 0, s>>>(img, target, count, inv, grad, partials); }
   { TimedLaunch gs_tl("k_l1_final", s); k_l1_final<<<1, 256, 0, s>>>(partials, nb, inv, loss); }
   return check_launch("k_l1");
+}
+
+
+// ------------------------------------------------- no-allocation variant
+// Partial sums of gs_l1_loss_static live in this file-scope device array
+// (one copy per GPU, alive until the process ends).  Host code never passes
+// the array's name to a kernel: the name is a host-side stand-in, and the
+// device address of each GPU's copy is looked up once per device.
+static __device__ __align__(256) float scratch[GS_L1_STATIC_PARTIALS];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Device address of the current device's scratch array (looked up on the
+// first call on each device, with that device current).
+gs_status static_scratch(float** out) {
+  int dev = -1;
+  gs_status st = check_hip(hipGetDevice(&dev), "hipGetDevice");
+  if (st != GS_OK) return st;
+  if (dev < 0 || dev >= kMaxDevices) return fail(GS_ERR_UNSUPPORTED, "gs_l1_loss_static: device index above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    st = check_hip(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (st != GS_OK) return st;
+    g_scratch_ptr[dev] = static_cast<float*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return GS_OK;
 }
 
 }  // namespace gs

@@ -40,7 +40,7 @@ STATUS_NAMES = {0: "GS_OK", -1: "GS_ERR_INVALID_ARG", -2: "GS_ERR_CAPACITY", -3:
 EXPORTS = ("gs_last_error", "gs_version", "gs_project", "gs_bin_sort_workspace", "gs_bin_sort", "gs_bin_sort_async",
            "gs_render_fwd", "gs_render_count", "gs_colour_hash_table", "gs_render_ckpt_floats", "gs_render_bwd_workspace", "gs_render_bwd",
            "gs_render_bwd_2d_workspace", "gs_render_bwd_2d", "gs_project_bwd", "gs_project_bwd_workspace",
-           "gs_adam_gaussians", "gs_l1_loss", "gs_mlp_pack", "gs_mlp_fwd", "gs_mlp_bwd_workspace", "gs_mlp_bwd",
+           "gs_adam_gaussians", "gs_l1_loss", "gs_l1_loss_static", "gs_mlp_pack", "gs_mlp_fwd", "gs_mlp_bwd_workspace", "gs_mlp_bwd",
            "gs_sh_colour", "gs_adam_step", "gs_kernel_timer_start", "gs_kernel_timer_stop")
 
 
@@ -120,6 +120,7 @@ _sigs = {
     "gs_project_bwd": ([_P(Gaussians), _P(Camera), _P(Projected), _vp, _P(GaussiansGrad), _vp, _sz, _vp],
                        ctypes.c_int),
     "gs_l1_loss": ([_vp, _vp, _i64, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "gs_l1_loss_static": ([_vp, _vp, _i64, _vp, _vp, _vp], ctypes.c_int),
     "gs_mlp_pack": ([_vp, _vp, _vp], ctypes.c_int),
     "gs_mlp_fwd": ([_i64, _i32, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
     "gs_mlp_bwd_workspace": ([_i64, _i32, _P(_sz)], ctypes.c_int),
@@ -377,6 +378,11 @@ def l1_loss(img, target, loss, grad, partials, stream=None):
     _check(_lib.gs_l1_loss(_ptr(img), _ptr(target), img.numel(), _ptr(loss), _ptr(grad), _ptr(partials),
                            _stream(stream)), "gs_l1_loss")
 
+
+def l1_loss_static(img, target, loss, grad, stream=None):
+    """gs_l1_loss with the library's static scratch (allocates nothing)."""
+    _check(_lib.gs_l1_loss_static(_ptr(img), _ptr(target), img.numel(), _ptr(loss), _ptr(grad), _stream(stream)),
+           "gs_l1_loss_static")
 
 
 # ------------------------------------------------------------ learned colour
