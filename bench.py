@@ -130,7 +130,7 @@ def counter_traffic_bytes(kernel):
         if line.startswith("#") or not line.strip():
             continue
         parts = line.split()
-        if parts[0] == kernel:
+        if parts[0] == kernel.replace(" ", ""):
             try:
                 return float(parts[-1]) * 1e6
             except ValueError:

@@ -426,7 +426,12 @@ gs_status launch_project_bwd(const gs_gaussians& g, const DevCam& cam, const int
                                              gr.means, gr.log_scales, gr.quats, gr.logits, gr.sh, tiles_touched, \
                                              sg, sc)
   {
-    TimedLaunch gs_tl(g.colour_mode == 1 ? "k_project_bwd<-1>" : (rows ? "k_project_bwd<rows>" : "k_project_bwd"), s);
+    // the kernel's own template name, as profilers report it
+    static const char* const kNames[2][4] = {
+        {"k_project_bwd<0, false>", "k_project_bwd<1, false>", "k_project_bwd<2, false>", "k_project_bwd<3, false>"},
+        {"k_project_bwd<0, true>", "k_project_bwd<1, true>", "k_project_bwd<2, true>", "k_project_bwd<3, true>"}};
+    TimedLaunch gs_tl(g.colour_mode == 1 ? "k_project_bwd<-1, false>"
+                                         : kNames[rows ? 1 : 0][std::min(std::max(g.sh_degree, 0), 3)], s);
     if (g.colour_mode == 1) {
       GS_PB(-1, false);
     } else if (rows) {

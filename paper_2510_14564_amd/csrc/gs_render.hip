@@ -727,7 +727,7 @@ gs_status launch_render_fwd(const gs_projected& proj, const uint32_t* point_list
                                                       final_T, n_contrib, t_ckpt, nullptr, plan, tile_work, c_ckpt,
                                                       cplane);
   } else {
-    TimedLaunch gs_tl("k_render_fwd<false>", s);
+    TimedLaunch gs_tl("k_render_fwd<false, false>", s);
     k_render_fwd<false><<<ntiles, 256, 0, s>>>(reinterpret_cast<const uint2*>(ranges), point_list,
                                                reinterpret_cast<const float4*>(proj.records), cam, image, final_T,
                                                n_contrib, t_ckpt, nullptr, plan, tile_work, c_ckpt, cplane);
@@ -740,7 +740,7 @@ gs_status launch_render_count(const gs_projected& proj, const uint32_t* point_li
   const int ntiles = cam.tiles_x * cam.tiles_y;
   gs_status st = check_hip(hipMemsetAsync(counts, 0, 2 * sizeof(unsigned long long), s), "hipMemsetAsync(counts)");
   if (st != GS_OK) return st;
-  { TimedLaunch gs_tl("k_render_fwd<true>", s); k_render_fwd<true><<<ntiles, 256, 0, s>>>(reinterpret_cast<const uint2*>(ranges), point_list,
+  { TimedLaunch gs_tl("k_render_fwd<true, false>", s); k_render_fwd<true><<<ntiles, 256, 0, s>>>(reinterpret_cast<const uint2*>(ranges), point_list,
                                             reinterpret_cast<const float4*>(proj.records), cam, nullptr, nullptr,
                                             nullptr, nullptr, counts, nullptr, nullptr, nullptr, 0); }
   return check_launch("k_render_count");
@@ -1276,7 +1276,7 @@ gs_status launch_render_bwd(int64_t n, const gs_projected& proj, const uint32_t*
   auto bwd = [&](unsigned grid, const int32_t* items, const uint32_t* tile_work, const float* c_ckpt,
                  size_t cplane) {
     if (deterministic)
-      { TimedLaunch gs_tl("k_render_bwd<true>", s); k_render_bwd<true><<<grid, 256, 0, s>>>(rg, point_list, rec, cam, final_T, n_contrib, t_ckpt, dL_dimage,
+      { TimedLaunch gs_tl("k_render_bwd<true, false>", s); k_render_bwd<true><<<grid, 256, 0, s>>>(rg, point_list, rec, cam, final_T, n_contrib, t_ckpt, dL_dimage,
                                               static_cast<int>(n), acc, nullptr, items, tile_work, c_ckpt, cplane,
                                               det.part, det.row_of, rows); }
     else if (chs)
@@ -1284,7 +1284,7 @@ gs_status launch_render_bwd(int64_t n, const gs_projected& proj, const uint32_t*
                                                      static_cast<int>(n), acc, nullptr, items, tile_work, c_ckpt, cplane,
                                                      nullptr, nullptr, 0); }
     else
-      { TimedLaunch gs_tl("k_render_bwd<false>", s); k_render_bwd<false><<<grid, 256, 0, s>>>(rg, point_list, rec, cam, final_T, n_contrib, t_ckpt, dL_dimage,
+      { TimedLaunch gs_tl("k_render_bwd<false, false>", s); k_render_bwd<false><<<grid, 256, 0, s>>>(rg, point_list, rec, cam, final_T, n_contrib, t_ckpt, dL_dimage,
                                                static_cast<int>(n), acc, nullptr, items, tile_work, c_ckpt, cplane,
                                                nullptr, nullptr, 0); }
     return check_launch("k_render_bwd");
