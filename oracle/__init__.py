@@ -459,3 +459,73 @@ def chs_route(rec, point_list, ranges, window, agg, g_e):
     if rc != 0:
         raise ValueError(f"or_chs_route failed: {rc}")
     return g2d
+
+
+# ---------------------------------------------------- density control (T1)
+
+# (r, alpha, beta, k, a, delta, gamma): neighbour radius, threshold factors,
+# k of the mean neighbour distance, spread factor (> 1), perturbation
+# half-width, merge-radius factor
+DENSITY_DEFAULTS = dict(alpha=1.0, beta=1.0, k=3, spread=1.5, jitter_frac=0.1, gamma=1.0)
+
+
+def density_params(r, alpha=1.0, beta=1.0, k=3, spread=1.5, jitter=None, gamma=1.0):
+    """Parameter vector of or_density_control (jitter defaults to r / 10)."""
+    return np.array([r, alpha, beta, k, spread, 0.1 * r if jitter is None else jitter, gamma], np.float64)
+
+
+def _f32(a):
+    return np.ascontiguousarray(np.asarray(a, np.float32))
+
+
+def density(means, r, query=None):
+    """rho of the queried points (all if None): other points within r (FP32 distance decision)."""
+    m = _f32(means).reshape(3, -1)
+    n = m.shape[1]
+    q = np.arange(n, dtype=np.int64) if query is None else np.ascontiguousarray(query, np.int64)
+    rho = np.zeros(max(len(q), 1), np.int32)
+    _load().or_density(ctypes.c_int64(n), _p(m), ctypes.c_float(r), ctypes.c_int64(len(q)), _p(q), _p(rho))
+    return rho[:len(q)]
+
+
+def knn(means, k, query=None):
+    """(idx[nq][k], d2[nq][k]): the k nearest other points by (FP32 d2, index)."""
+    m = _f32(means).reshape(3, -1)
+    n = m.shape[1]
+    q = np.arange(n, dtype=np.int64) if query is None else np.ascontiguousarray(query, np.int64)
+    idx = np.zeros((max(len(q), 1), k), np.int64)
+    d2 = np.zeros((max(len(q), 1), k), np.float32)
+    rc = _load().or_knn(ctypes.c_int64(n), _p(m), ctypes.c_int(k), ctypes.c_int64(len(q)), _p(q), _p(idx), _p(d2))
+    if rc != 0:
+        raise ValueError(f"or_knn failed: {rc}")
+    return idx[:len(q)], d2[:len(q)]
+
+
+def density_control(scene, prm, noise):
+    """One round of density control (Sec. III-C) in the oracle.  prm from
+    density_params, noise[6][n] (z rows then e rows).  Returns a dict with the
+    new parameter arrays (FP64, n_out columns), per-point rho, cls (1 low,
+    2 high), nn, dbar, fate (-1 removed, else output index) and the
+    statistics."""
+    n, deg = scene.n, scene.sh_degree
+    nc = (deg + 1) ** 2
+    cap = max(2 * n, 1)
+    arrs = [_f32(a) for a in (scene.means, scene.log_scales, scene.quats, scene.logits, scene.sh)]
+    nz = _f32(noise).reshape(6, n)
+    out = dict(means=np.zeros((3, cap)), log_scales=np.zeros((3, cap)), quats=np.zeros((4, cap)),
+               logits=np.zeros(cap), sh=np.zeros((nc, 3, cap)))
+    rho = np.zeros(max(n, 1), np.int32)
+    cls = np.zeros(max(n, 1), np.int8)
+    nn = np.zeros(max(n, 1), np.int64)
+    dbar = np.zeros(max(n, 1), np.float32)
+    fate = np.zeros(max(n, 1), np.int64)
+    stats = np.zeros(8)
+    prm = np.ascontiguousarray(prm, np.float64)
+    _load().or_density_control(ctypes.c_int64(n), ctypes.c_int(deg), *(_p(a) for a in arrs), _p(prm), _p(nz),
+                               _p(out["means"]), _p(out["log_scales"]), _p(out["quats"]), _p(out["logits"]),
+                               _p(out["sh"]), _p(rho), _p(cls), _p(nn), _p(dbar), _p(fate), _p(stats))
+    n_out = int(stats[7])
+    res = {k: v[..., :n_out] for k, v in out.items()}
+    res.update(rho=rho[:n], cls=cls[:n], nn=nn[:n], dbar=dbar[:n], fate=fate[:n], n_out=n_out,
+               stats=dict(zip(("mu", "sigma", "rho_low", "rho_high", "mu_d", "sigma_d", "d_merge"), stats[:7])))
+    return res

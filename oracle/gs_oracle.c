@@ -1148,3 +1148,197 @@ int or_chs_route(int64_t n, int64_t ntiles, const uint32_t* ranges, const uint32
     }
     return 0;
 }
+
+/* --------------------------------------------------- density control (T1) ---
+ * Workload-sensitive density control (Sec. III-C): statistical thresholds on
+ * the local density, densification of sparse points next to themselves with
+ * Gaussian spread and a uniform perturbation, and merging of dense points.
+ * Readings (the paper names the quantities, not every detail):
+ *   - local density rho_i = number of other points within the radius r
+ *     (Sec. III-C.1); the distance decision is taken in FP32, as the kernels
+ *     take it: dx = x_i - x_j per axis, d2 = (dx^2 + dy^2) + dz^2, each
+ *     operation rounded, compared with r2 = r r rounded (d2 <= r2);
+ *   - thresholds rho_low = mu - alpha sigma, rho_high = mu + beta sigma over
+ *     all points (Sec. III-C.1; population standard deviation), in FP64 from
+ *     the exact integer sums S1 = sum rho, S2 = sum rho^2:
+ *     mu = S1/n, sigma = sqrt(max(S2/n - mu^2, 0)); low: rho < rho_low,
+ *     high: rho > rho_high;
+ *   - the mean distance to the k nearest other points (Sec. III-C.2), nearest
+ *     by (FP32 d2, index), sqrt and sum in FP32 in that order, over k;
+ *   - densification: each low point spawns one new point
+ *     p_new = p + (a d_bar) z + delta e with z ~ N(0, I3) and e ~ U(-1, 1)^3
+ *     given per point as inputs (Sec. III-C.2: sigma_p = a d_bar, a > 1, and
+ *     the uniform perturbation); the rest of its parameters are the
+ *     parent's; one round per call (the caller repeats rounds);
+ *   - merging (Sec. III-C.3): d_merge = mu_d + gamma sigma_d over every
+ *     point's nearest-neighbour distance (FP64 statistics); a high point whose
+ *     nearest neighbour is high, has it as its own nearest neighbour (mutual),
+ *     and lies within d_merge merges with it into the lower index:
+ *     position and SH colour opacity-weighted means, scale the mean scale
+ *     (log of the mean of exp(log-scale) per axis), opacity accumulated
+ *     1 - (1 - o_i)(1 - o_j), rotation of the more opaque (lower index on a
+ *     tie); the higher index is removed;
+ *   - output: the kept points in index order, then the new points in the
+ *     order of their parents.
+ */
+
+/* FP32 squared distance between points i and j of means[3][n] (rounded as stated). */
+static float dc_d2(const float* m, int64_t n, int64_t i, int64_t j) {
+    float dx = m[i] - m[j];
+    float dy = m[n + i] - m[n + j];
+    float dz = m[2 * n + i] - m[2 * n + j];
+    float s = dx * dx;
+    s = s + dy * dy;
+    s = s + dz * dz;
+    return s;
+}
+
+/* rho of the queried points q[0..nq) (brute force over all n points). */
+int or_density(int64_t n, const float* means, float r, int64_t nq, const int64_t* q, int32_t* rho) {
+    float r2 = r * r;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t a = 0; a < nq; ++a) {
+        int64_t i = q[a];
+        int32_t c = 0;
+        for (int64_t j = 0; j < n; ++j)
+            if (j != i && dc_d2(means, n, i, j) <= r2) ++c;
+        rho[a] = c;
+    }
+    return 0;
+}
+
+/* The k nearest other points of each queried point, by (FP32 d2, index):
+ * idx[nq][k] (-1 past n - 1 points) and d2[nq][k]. */
+int or_knn(int64_t n, const float* means, int k, int64_t nq, const int64_t* q, int64_t* idx, float* d2) {
+    if (k < 1 || k > 64) return -1;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t a = 0; a < nq; ++a) {
+        int64_t i = q[a];
+        int64_t* bi = idx + a * k;
+        float* bd = d2 + a * k;
+        int cnt = 0;
+        for (int m = 0; m < k; ++m) { bi[m] = -1; bd[m] = INFINITY; }
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            float d = dc_d2(means, n, i, j);
+            /* insert (d, j) if it precedes the current k-th */
+            if (cnt == k && !(d < bd[k - 1] || (d == bd[k - 1] && j < bi[k - 1]))) continue;
+            int pos = cnt < k ? cnt : k - 1;
+            while (pos > 0 && (d < bd[pos - 1] || (d == bd[pos - 1] && j < bi[pos - 1]))) {
+                bd[pos] = bd[pos - 1];
+                bi[pos] = bi[pos - 1];
+                --pos;
+            }
+            bd[pos] = d;
+            bi[pos] = j;
+            if (cnt < k) ++cnt;
+        }
+    }
+    return 0;
+}
+
+static double dc_sigmoid(double x) { return 1.0 / (1.0 + exp(-x)); }
+static double dc_softplus(double x) { return x > 0 ? x + log1p(exp(-x)) : log1p(exp(x)); }
+
+/* One round of density control over n points (brute force, for small n).
+ * prm[7] = r, alpha, beta, k, a, delta, gamma.  noise[6][n] = z (3 rows), e (3 rows).
+ * Outputs (capacity 2n each, SoA with stride 2n): out_means[3], out_ls[3],
+ * out_q[4], out_logit, out_sh[nc*3]; per input point: rho, cls (1 low, 2 high,
+ * 0 neither), nn (nearest other point), dbar (mean k-NN distance, FP32), fate
+ * (-1 removed, else output index); stats[8] = mu, sigma, rho_low, rho_high,
+ * mu_d, sigma_d, d_merge, n_out.  Returns 0. */
+int or_density_control(int64_t n, int deg, const float* means, const float* ls, const float* quats,
+                       const float* logits, const float* sh, const double* prm, const float* noise,
+                       double* out_means, double* out_ls, double* out_q, double* out_logit, double* out_sh,
+                       int32_t* rho, int8_t* cls, int64_t* nn, float* dbar, int64_t* fate, double* stats) {
+    const int nc = (deg + 1) * (deg + 1);
+    const float r = (float)prm[0];
+    const double alpha = prm[1], beta = prm[2];
+    const int k = (int)prm[3];
+    const float a = (float)prm[4], delta = (float)prm[5];
+    const double gamma = prm[6];
+    const int64_t cap = 2 * n;
+    int64_t* q = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    q[0] = 0;
+    for (int64_t i = 0; i < n; ++i) q[i] = i;
+    or_density(n, means, r, n, q, rho);
+    int64_t S1 = 0, S2 = 0;
+    for (int64_t i = 0; i < n; ++i) { S1 += rho[i]; S2 += (int64_t)rho[i] * rho[i]; }
+    double mu = n > 0 ? (double)S1 / (double)n : 0.0;
+    double var = n > 0 ? (double)S2 / (double)n - mu * mu : 0.0;
+    double sigma = sqrt(var > 0.0 ? var : 0.0);
+    double lo = mu - alpha * sigma, hi = mu + beta * sigma;
+    for (int64_t i = 0; i < n; ++i) cls[i] = rho[i] < lo ? 1 : (rho[i] > hi ? 2 : 0);
+    /* k nearest neighbours of every point */
+    int kk = k < 1 ? 1 : k;
+    int64_t* ki = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1) * kk);
+    float* kd = (float*)malloc(sizeof(float) * (size_t)(n > 0 ? n : 1) * kk);
+    or_knn(n, means, kk, n, q, ki, kd);
+    double sd = 0.0, sd2 = 0.0;
+    int64_t nd = 0;
+    float* dnn = (float*)malloc(sizeof(float) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) {
+        nn[i] = ki[i * kk];
+        float s = 0.0f;
+        int cnt = 0;
+        for (int m = 0; m < kk; ++m)
+            if (ki[i * kk + m] >= 0) { s = s + sqrtf(kd[i * kk + m]); ++cnt; }
+        dbar[i] = cnt ? s / (float)cnt : 0.0f;
+        dnn[i] = nn[i] >= 0 ? sqrtf(kd[i * kk]) : 0.0f;
+        if (nn[i] >= 0) { sd += dnn[i]; sd2 += (double)dnn[i] * dnn[i]; ++nd; }
+    }
+    double mu_d = nd ? sd / (double)nd : 0.0;
+    double var_d = nd ? sd2 / (double)nd - mu_d * mu_d : 0.0;
+    double sigma_d = sqrt(var_d > 0.0 ? var_d : 0.0);
+    double dmerge = mu_d + gamma * sigma_d;
+    /* mutual nearest-neighbour merges among high points */
+    int64_t* partner = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t j = nn[i];
+        partner[i] = (cls[i] == 2 && j >= 0 && cls[j] == 2 && nn[j] == i && (double)dnn[i] <= dmerge) ? j : -1;
+    }
+    int64_t o = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t j = partner[i];
+        if (j >= 0 && j < i) { fate[i] = -1; continue; }
+        fate[i] = o;
+        if (j < 0) {
+            for (int c = 0; c < 3; ++c) { out_means[c * cap + o] = means[c * n + i]; out_ls[c * cap + o] = ls[c * n + i]; }
+            for (int c = 0; c < 4; ++c) out_q[c * cap + o] = quats[c * n + i];
+            out_logit[o] = logits[i];
+            for (int c = 0; c < 3 * nc; ++c) out_sh[(int64_t)c * cap + o] = sh[(int64_t)c * n + i];
+        } else {
+            double oi = dc_sigmoid(logits[i]), oj = dc_sigmoid(logits[j]);
+            double w = oi + oj;
+            for (int c = 0; c < 3; ++c) {
+                out_means[c * cap + o] = (oi * means[c * n + i] + oj * means[c * n + j]) / w;
+                out_ls[c * cap + o] = log(0.5 * (exp((double)ls[c * n + i]) + exp((double)ls[c * n + j])));
+            }
+            int64_t qsrc = oj > oi ? j : i;
+            for (int c = 0; c < 4; ++c) out_q[c * cap + o] = quats[c * n + qsrc];
+            double om = oi + oj - oi * oj;
+            out_logit[o] = log(om) + dc_softplus(logits[i]) + dc_softplus(logits[j]);
+            for (int c = 0; c < 3 * nc; ++c)
+                out_sh[(int64_t)c * cap + o] = (oi * sh[(int64_t)c * n + i] + oj * sh[(int64_t)c * n + j]) / w;
+        }
+        ++o;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        if (cls[i] != 1) continue;
+        float t = a * dbar[i];
+        for (int c = 0; c < 3; ++c) {
+            float p = means[c * n + i] + t * noise[c * n + i];
+            p = p + delta * noise[(3 + c) * n + i];
+            out_means[c * cap + o] = p;
+            out_ls[c * cap + o] = ls[c * n + i];
+        }
+        for (int c = 0; c < 4; ++c) out_q[c * cap + o] = quats[c * n + i];
+        out_logit[o] = logits[i];
+        for (int c = 0; c < 3 * nc; ++c) out_sh[(int64_t)c * cap + o] = sh[(int64_t)c * n + i];
+        ++o;
+    }
+    stats[0] = mu; stats[1] = sigma; stats[2] = lo; stats[3] = hi;
+    stats[4] = mu_d; stats[5] = sigma_d; stats[6] = dmerge; stats[7] = (double)o;
+    free(q); free(ki); free(kd); free(dnn); free(partner);
+    return 0;
+}
