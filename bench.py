@@ -405,6 +405,41 @@ def sampling_quality(torch, gs, scenes, dev, cfg, coherent=False):
             "merged_fraction": round(merged, 4), "psnr_vs_exact_db": round(10 * math.log10(1.0 / max(mse, 1e-30)), 3)}
 
 
+def density_timing(torch, gs, scenes, dev, cfg, rounds=3):
+    """One round of density control (Sec. III-C) on a workload's Gaussians:
+    ms per round (the call waits once for the output size) and its kernels."""
+    scene = scenes.config_scene(cfg)
+    n, deg = scene.n, scene.sh_degree
+    r = scenes.DENSITY_RADIUS[cfg]
+    p = {k: torch.from_numpy(v).to(dev) for k, v in scene.arrays().items() if k != "latents"}
+    g = gs.gaussians_struct(p["means"], p["log_scales"], p["quats"], p["logits"], p["sh"], deg)
+    cap = 2 * n
+    nc = (deg + 1) ** 2
+    out = {"means": torch.empty((3, cap), device=dev), "log_scales": torch.empty((3, cap), device=dev),
+           "quats": torch.empty((4, cap), device=dev), "logits": torch.empty(cap, device=dev),
+           "sh": torch.empty((nc, 3, cap), device=dev)}
+    noise = torch.from_numpy(scenes.density_noise(n, 1000 * cfg + 78)).to(dev)
+    ws = torch.empty(gs.density_control_workspace(n), dtype=torch.uint8, device=dev)
+    prm = {"radius": r}
+    rep = gs.density_control(g, prm, noise, out, cap, ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(rounds):
+        gs.density_control(g, prm, noise, out, cap, ws)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / rounds
+    gs.kernel_timer_start()
+    try:
+        gs.density_control(g, prm, noise, out, cap, ws)
+        torch.cuda.synchronize()
+    finally:
+        kt = gs.kernel_timer_stop()
+    return {"workload": f"{scenes.CONFIG_NAMES[cfg]}: {n} Gaussians, r = {r}, k = 3, alpha = beta = gamma = 1",
+            "ms_per_round": round(ms, 4), "kernels_us": {k: round(1e3 * t / c, 2) for k, (c, t) in kt.items()},
+            "rho_mean": round(rep["rho_mean"], 3), "rho_std": round(rep["rho_std"], 3), "n_new": rep["n_new"],
+            "n_merged": rep["n_merged"], "n_out": rep["n_out"]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -564,6 +599,8 @@ def main():
             "sh": summary(r5), "decoder": summary(r5m), "speedup_vs_sh": round(r5["ms"] / r5m["ms"], 4)}
         del h5
         torch.cuda.empty_cache()
+        log("[bench] density control ...")
+        extras["density_control"] = [density_timing(torch, gs, scenes, dev, c) for c in (2, 3)]
         log("[bench] decoder quality (400 distillation epochs, 32 views) ...")
         extras["decoder_quality"] = learned_quality(torch, gs, scenes, dev)
         result["extra_workloads"] = extras

@@ -366,6 +366,68 @@ gs_status gs_adam_gaussians(int64_t n, int32_t sh_degree, const gs_param_arrays*
                             const gs_param_arrays* m, const gs_param_arrays* v, const gs_adam_config* cfg,
                             gs_stream stream);
 
+/* ------------------------------------------------------- density control
+ * Workload-sensitive density control (Sec. III-C), one round per call: each
+ * Gaussian's local density rho = number of other centres within `radius`
+ * (the decision d^2 <= r^2 taken in FP32, each operation rounded), the
+ * thresholds rho_low = mu - alpha sigma and rho_high = mu + beta sigma over all
+ * densities (population statistics in FP64 from the exact integer sums), the
+ * mean distance d_bar to the `knn` nearest other centres (nearest by FP32
+ * squared distance, then index), then
+ *   - densification: every Gaussian with rho < rho_low gets a new neighbour at
+ *     p + (spread d_bar) z + jitter e, with z and e the Gaussian's rows of
+ *     noise[6][n] (z ~ N(0, I3) in rows 0-2, e ~ U(-1, 1)^3 in rows 3-5, drawn
+ *     by the caller), its other parameters copied from it;
+ *   - merging: two Gaussians with rho > rho_high that are each other's nearest
+ *     neighbour within d_merge = mu_d + gamma sigma_d (statistics of every
+ *     Gaussian's nearest-neighbour distance) become one at the lower index:
+ *     opacity-weighted mean position and SH coefficients, scales the mean of
+ *     the two scales (log of the mean of exp(log_scale) per axis), opacity
+ *     1 - (1 - o_i)(1 - o_j), the more opaque one's rotation.
+ * The output holds the surviving Gaussians in index order, then the new ones
+ * in the order of the Gaussians that spawned them. */
+typedef struct {
+  float radius;           /* r > 0 */
+  float alpha, beta;      /* threshold factors >= 0 (the paper's example: 1, 1) */
+  int32_t knn;            /* k in 1..8 */
+  float spread;           /* a > 1: sigma_p = a d_bar */
+  float jitter;           /* half-width of the uniform perturbation, >= 0 */
+  float gamma;            /* merge-radius factor (the paper's example: 1) */
+} gs_density_params;
+
+/* Filled on return (also on GS_ERR_CAPACITY). */
+typedef struct {
+  int64_t n_in, n_merged, n_new, n_out;        /* n_out = n_in - n_merged + n_new */
+  double rho_mean, rho_std, rho_low, rho_high;
+  double d_mean, d_std, d_merge;
+} gs_density_report;
+
+/* Optional per-Gaussian outputs of a round (any pointer may be NULL):
+ * rho[n], cls[n] (0 neither, 1 below rho_low, 2 above rho_high), nn[n]
+ * (nearest other Gaussian, -1 if none), dbar[n], fate[n] (output index, -1
+ * if merged away). */
+typedef struct {
+  int32_t* rho;
+  uint8_t* cls;
+  int32_t* nn;
+  float* dbar;
+  int32_t* fate;
+} gs_density_points;
+
+/* Workspace bytes for n Gaussians. Host-only. */
+gs_status gs_density_control_workspace(int64_t n, size_t* bytes);
+
+/* One round on g (colour_mode 0; n <= 2^30) into out (same layouts as
+ * gs_gaussians with `capacity` in place of n: means[3][capacity], ...).
+ * Synchronises the stream once to read the counts.  Errors: INVALID_ARG for
+ * bad parameters or NULL arrays; CAPACITY when n_out > capacity (report->n_out
+ * holds the size needed; outputs past the capacity are not written);
+ * UNSUPPORTED when a coordinate is not finite or lies 2^18 cells (of 1.07 r)
+ * or more from the origin (the grid's FP32 cell guarantees need less). */
+gs_status gs_density_control(const gs_gaussians* g, const gs_density_params* prm, const float* noise,
+                             gs_param_arrays* out, int64_t capacity, void* ws, size_t ws_bytes,
+                             gs_density_report* report, gs_density_points* points, gs_stream stream);
+
 /* ---------------------------------------------------------- learned colour
  * Optional decoder that replaces the SH colour read (not part of the paper):
  * per sample, x = [z (16 BF16 latent values); Y_0..15(d)] with Y the real SH

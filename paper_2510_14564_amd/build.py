@@ -7,7 +7,8 @@ linked into one shared library next to this file.  Flags common to all HIP code:
   -Xclang -target-feature -Xclang -packed-fp32-ops   (no packed FP32 VALU ops)
   -munsafe-fp-atomics         hardware FP32 atomics on device memory
 The compositing kernels additionally use -ffp-contract=off so that the
-forward and backward evaluate every expression in the same order.
+forward and backward evaluate every expression in the same order, and the
+density control so that its FP32 distance decisions are the definition's.
 """
 from __future__ import annotations
 
@@ -29,6 +30,7 @@ COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
           "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function", f"-I{INCLUDE}", f"-I{CSRC}"]
 PER_FILE = {
     "gs_render.hip": ["-ffp-contract=off"],
+    "gs_density.hip": ["-ffp-contract=off"],
 }
 
 

@@ -519,6 +519,33 @@ gs_status gs_adam_gaussians(int64_t n, int32_t sh_degree, const gs_param_arrays*
   return launch_adam_gaussians(n, sh_degree, *params, *grad, *m, *v, *cfg, static_cast<hipStream_t>(stream));
 }
 
+gs_status gs_density_control_workspace(int64_t n, size_t* bytes) {
+  set_error("");
+  if (n < 0 || n > (int64_t(1) << 30) || !bytes) return fail(GS_ERR_INVALID_ARG, "gs_density_control_workspace: bad arguments");
+  *bytes = density_workspace(n);
+  return GS_OK;
+}
+
+gs_status gs_density_control(const gs_gaussians* g, const gs_density_params* prm, const float* noise,
+                             gs_param_arrays* out, int64_t capacity, void* ws, size_t ws_bytes,
+                             gs_density_report* report, gs_density_points* points, gs_stream stream) {
+  set_error("");
+  gs_status st;
+  if ((st = validate_gaussians(g, "gs_density_control")) != GS_OK) return st;
+  if (g->colour_mode != 0) return fail(GS_ERR_INVALID_ARG, "gs_density_control: SH colour (colour_mode 0) only");
+  if (!prm || !out || capacity < 0) return fail(GS_ERR_INVALID_ARG, "gs_density_control: bad arguments");
+  const gs_density_params& p = *prm;
+  if (!(p.radius > 0.0f) || !std::isfinite(p.radius) || !(p.alpha >= 0.0f) || !std::isfinite(p.alpha) ||
+      !(p.beta >= 0.0f) || !std::isfinite(p.beta) || p.knn < 1 || p.knn > 8 || !std::isfinite(p.spread) ||
+      !(p.jitter >= 0.0f) || !std::isfinite(p.jitter) || !std::isfinite(p.gamma))
+    return fail(GS_ERR_INVALID_ARG, "gs_density_control: parameter out of range");
+  if (g->n > 0 && (!noise || !out->means || !out->log_scales || !out->quats || !out->logits || !out->sh))
+    return fail(GS_ERR_INVALID_ARG, "gs_density_control: NULL array");
+  if (!ws || ws_bytes < density_workspace(g->n)) return fail(GS_ERR_INVALID_ARG, "gs_density_control: workspace too small");
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(GS_ERR_INVALID_ARG, "gs_density_control: ws not 256-aligned");
+  return launch_density_control(*g, p, noise, *out, capacity, ws, report, points, static_cast<hipStream_t>(stream));
+}
+
 gs_status gs_kernel_timer_start(void) {
   set_error("");
   std::lock_guard<std::mutex> lock(g_timer_mu);

@@ -165,6 +165,10 @@ gs_status run_bin_sort(int64_t n, const gs_projected& proj, const DevCam& cam, v
                        uint32_t* point_list, int64_t capacity, uint32_t* ranges, int64_t* k_out,
                        unsigned long long* k_dev, hipStream_t s);
 bool binsort_direct(int tiles_x, int tiles_y);
+size_t density_workspace(int64_t n);
+gs_status launch_density_control(const gs_gaussians& g, const gs_density_params& prm, const float* noise,
+                                 gs_param_arrays& out, int64_t cap, void* ws, gs_density_report* rep,
+                                 gs_density_points* pts_out, hipStream_t s);
 gs_status launch_chs_table(const gs_projected& proj, const uint32_t* point_list, const uint32_t* ranges,
                            const DevCam& cam, uint32_t* tab_count, float* tab_sum, uint16_t* bucket_out,
                            uint32_t* rep_out, hipStream_t s);

@@ -40,8 +40,26 @@ STATUS_NAMES = {0: "GS_OK", -1: "GS_ERR_INVALID_ARG", -2: "GS_ERR_CAPACITY", -3:
 EXPORTS = ("gs_last_error", "gs_version", "gs_project", "gs_bin_sort_workspace", "gs_bin_sort", "gs_bin_sort_async",
            "gs_render_fwd", "gs_render_count", "gs_colour_hash_table", "gs_render_ckpt_floats", "gs_render_bwd_workspace", "gs_render_bwd",
            "gs_render_bwd_2d_workspace", "gs_render_bwd_2d", "gs_project_bwd", "gs_project_bwd_workspace",
-           "gs_adam_gaussians", "gs_l1_loss", "gs_l1_loss_static", "gs_mlp_pack", "gs_mlp_fwd", "gs_mlp_bwd_workspace", "gs_mlp_bwd",
+           "gs_adam_gaussians", "gs_density_control_workspace", "gs_density_control", "gs_l1_loss", "gs_l1_loss_static", "gs_mlp_pack", "gs_mlp_fwd", "gs_mlp_bwd_workspace", "gs_mlp_bwd",
            "gs_sh_colour", "gs_adam_step", "gs_kernel_timer_start", "gs_kernel_timer_stop")
+
+
+class DensityParams(ctypes.Structure):
+    _fields_ = [("radius", ctypes.c_float), ("alpha", ctypes.c_float), ("beta", ctypes.c_float),
+                ("knn", ctypes.c_int32), ("spread", ctypes.c_float), ("jitter", ctypes.c_float),
+                ("gamma", ctypes.c_float)]
+
+
+class DensityReport(ctypes.Structure):
+    _fields_ = [("n_in", ctypes.c_int64), ("n_merged", ctypes.c_int64), ("n_new", ctypes.c_int64),
+                ("n_out", ctypes.c_int64), ("rho_mean", ctypes.c_double), ("rho_std", ctypes.c_double),
+                ("rho_low", ctypes.c_double), ("rho_high", ctypes.c_double), ("d_mean", ctypes.c_double),
+                ("d_std", ctypes.c_double), ("d_merge", ctypes.c_double)]
+
+
+class DensityPoints(ctypes.Structure):
+    _fields_ = [("rho", ctypes.c_void_p), ("cls", ctypes.c_void_p), ("nn", ctypes.c_void_p),
+                ("dbar", ctypes.c_void_p), ("fate", ctypes.c_void_p)]
 
 
 class GsError(RuntimeError):
@@ -117,6 +135,9 @@ _sigs = {
     "gs_adam_gaussians": ([_i64, _i32, _P(ParamArrays), _P(GaussiansGrad), _P(ParamArrays), _P(ParamArrays),
                            _P(AdamConfig), _vp], ctypes.c_int),
     "gs_project_bwd_workspace": ([_P(Gaussians), _P(_sz)], ctypes.c_int),
+    "gs_density_control_workspace": ([_i64, _P(_sz)], ctypes.c_int),
+    "gs_density_control": ([_P(Gaussians), _P(DensityParams), _vp, _P(ParamArrays), _i64, _vp, _sz,
+                            _P(DensityReport), _P(DensityPoints), _vp], ctypes.c_int),
     "gs_project_bwd": ([_P(Gaussians), _P(Camera), _P(Projected), _vp, _P(GaussiansGrad), _vp, _sz, _vp],
                        ctypes.c_int),
     "gs_l1_loss": ([_vp, _vp, _i64, _vp, _vp, _vp, _vp], ctypes.c_int),
@@ -352,6 +373,37 @@ def adam_gaussians(n: int, sh_degree: int, params: dict, grads: dict, m: dict, v
                                   ctypes.byref(_grad_struct(grads)), ctypes.byref(_param_struct(m)),
                                   ctypes.byref(_param_struct(v)), ctypes.byref(cfg), _stream(stream)),
            "gs_adam_gaussians")
+
+
+def density_control_workspace(n: int) -> int:
+    b = ctypes.c_size_t(0)
+    _check(_lib.gs_density_control_workspace(n, ctypes.byref(b)), "gs_density_control_workspace")
+    return int(b.value)
+
+
+def density_control(gauss: Gaussians, params: dict, noise, out: dict, capacity: int, ws, points: dict = None,
+                    stream=None) -> dict:
+    """One round of density control (gs_density_control).  params: radius,
+    alpha, beta, knn, spread, jitter, gamma; out: parameter arrays with
+    `capacity` columns; points: optional per-Gaussian outputs (rho, cls, nn,
+    dbar, fate).  Returns the report as a dict; raises GsError (with .report)
+    on failure, e.g. GS_ERR_CAPACITY when the output needs more columns."""
+    prm = DensityParams(params["radius"], params.get("alpha", 1.0), params.get("beta", 1.0),
+                        int(params.get("knn", 3)), params.get("spread", 1.5),
+                        params.get("jitter", 0.1 * params["radius"]), params.get("gamma", 1.0))
+    rep = DensityReport()
+    pts = None
+    if points:
+        pts = DensityPoints(*(_ptr(points.get(k)) for k in ("rho", "cls", "nn", "dbar", "fate")))
+    st = _lib.gs_density_control(ctypes.byref(gauss), ctypes.byref(prm), _ptr(noise),
+                                 ctypes.byref(_param_struct(out)), capacity, _ptr(ws), _nbytes(ws), ctypes.byref(rep),
+                                 ctypes.byref(pts) if pts is not None else None, _stream(stream))
+    report = {f: getattr(rep, f) for f, _ in DensityReport._fields_}
+    if st != GS_OK:
+        e = GsError(st, "gs_density_control", _lib.gs_last_error().decode())
+        e.report = report
+        raise e
+    return report
 
 
 def project_bwd_workspace(gauss: Gaussians) -> int:

@@ -252,6 +252,20 @@ def coherent_colour(scene: Scene, seed: int, noise: float = 0.03) -> Scene:
     return dataclasses.replace(scene, sh=_f32(sh))
 
 
+def density_noise(n: int, seed: int) -> np.ndarray:
+    """Random draws of one density-control round, float32[6][n]: rows 0-2
+    N(0, 1) (the Gaussian spread), rows 3-5 U(-1, 1) (the perturbation)."""
+    rng = np.random.default_rng(seed)
+    z = rng.standard_normal((3, n))
+    e = rng.uniform(-1.0, 1.0, (3, n))
+    return _f32(np.concatenate([z, e]))
+
+
+# neighbour radius of the density control per workload: about 20 other
+# centres within it on average (skewed 200k: 0.03; main 1M: 0.0175)
+DENSITY_RADIUS = {1: 0.08, 2: 0.03, 3: 0.0175, 4: 0.012, 5: 0.03}
+
+
 def config_camera(cfg: int, k: int = 0, bg=(0.0, 0.0, 0.0)) -> Camera:
     if cfg == 1:
         return front_camera(128, 128, 3.0, 60.0, bg)

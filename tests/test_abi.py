@@ -222,3 +222,46 @@ def test_bin_sort_async_argument_checks(gs):
                                    fake, NULL)
     assert st == gs.GS_ERR_UNSUPPORTED
     assert "gs_bin_sort" in gs.last_error()
+
+
+@pytest.mark.parametrize("case", ["r0", "r_nan", "k0", "k9", "alpha_neg", "jitter_neg", "null_noise", "null_out",
+                                  "small_ws", "mode1"])
+def test_density_control_rejects_bad_arguments(gs, case):
+    g = _gauss(gs, n=100, deg=1)
+    prm = gs.DensityParams(0.05, 1.0, 1.0, 3, 1.5, 0.005, 1.0)
+    out = gs.ParamArrays()
+    out.means = out.log_scales = out.quats = out.logits = out.sh = ctypes.c_void_p(0x1000)
+    noise = ctypes.c_void_p(0x1000)
+    need = gs.density_control_workspace(100)
+    ws, nbytes = ctypes.c_void_p(0x100000), need
+    if case == "r0":
+        prm.radius = 0.0
+    elif case == "r_nan":
+        prm.radius = float("nan")
+    elif case == "k0":
+        prm.knn = 0
+    elif case == "k9":
+        prm.knn = 9
+    elif case == "alpha_neg":
+        prm.alpha = -1.0
+    elif case == "jitter_neg":
+        prm.jitter = -0.1
+    elif case == "null_noise":
+        noise = None
+    elif case == "null_out":
+        out.sh = None
+    elif case == "small_ws":
+        nbytes = need - 1
+    elif case == "mode1":
+        g.colour_mode = 1
+        g.latents = g.mlp = ctypes.c_void_p(0x1000)
+    rep = gs.DensityReport()
+    st = gs._lib.gs_density_control(ctypes.byref(g), ctypes.byref(prm), noise, ctypes.byref(out), 200, ws, nbytes,
+                                    ctypes.byref(rep), None, NULL)
+    assert st == gs.GS_ERR_INVALID_ARG, case
+    assert gs.last_error() != ""
+
+
+def test_density_control_workspace_grows_with_n(gs):
+    a, b = gs.density_control_workspace(1000), gs.density_control_workspace(100000)
+    assert b > a > 0 and b - a >= 60 * 99000
