@@ -79,10 +79,11 @@ STAGE_KERNELS = {
     "project": ("k_project<", "k_mlp_fwd<1>"),
     "bin_sort": ("k_depth_keys", "k_os_", "k_rs_hist", "k_rs_scatter", "k_scan_", "k_chunk_",
                  "k_tile_starts", "k_emit", "k_ranges", "k_put_zero_k"),
-    "render_fwd": ("k_render_fwd_light", "k_render_fwd<false>", "k_render_fwd<false, true>", "k_tile_plan"),
+    "render_fwd": ("k_render_fwd_light", "k_render_fwd<false", "k_tile_plan"),
     "l1_loss": ("k_l1_",),
     "render_bwd": ("k_render_bwd", "k_acc_to_g2d", "k_det_", "k_zero4", "k_batch_plan"),
     "colour_hash_table": ("k_chs_table",),
+    "density_control": ("k_dc_",),
     "project_bwd": ("k_project_bwd", "k_mlp_bwd<1>", "k_mlp_reduce"),
     "adam": ("k_adam_gaussians",),
 }
@@ -95,6 +96,7 @@ STAGE_SOURCES = {
     "l1_loss": ("gs_loss.hip", "gs_internal.h"),
     "render_bwd": ("gs_render.hip", "gs_plan.hip", "gs_internal.h"),
     "colour_hash_table": ("gs_render.hip", "gs_internal.h"),
+    "density_control": ("gs_density.hip", "gs_binsort.hip", "gs_internal.h"),
     "project_bwd": ("gs_project.hip", "gs_sh.h", "gs_mlp.hip", "gs_internal.h"),
     "adam": ("gs_optim.hip", "gs_internal.h"),
 }

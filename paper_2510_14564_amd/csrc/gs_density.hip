@@ -14,7 +14,11 @@
 // the same or an adjacent cell (27 cells cover the radius search), and after
 // the cells up to Chebyshev offset R have been scanned every point closer
 // than (R - 1/16) h has been seen (the k-nearest search stops on that
-// guarantee, and scans all points once a query has gone eight rings out).
+// guarantee).  One thread per query scans rings 0-2; a query whose k-th
+// nearest lies farther (isolated points, a few per cent) goes on to a wave
+// of its own that scans rings 0-7 with the 64 lanes sharing each ring's cells,
+// and the few left after that to a whole workgroup that scans every point;
+// partial top-k lists are merged in LDS.
 // Several cells can share a bucket; a scan visits only the points whose own
 // cell is the one it wants, so nothing is counted twice.
 //
@@ -32,7 +36,8 @@
 
 namespace gs {
 
-constexpr int kDcRings = 8;          // rings scanned before a query scans every point
+constexpr int kDcRingsThread = 3;    // rings a thread scans alone (0-2)
+constexpr int kDcRingsWave = 8;      // rings a wave scans for a query (0-7) before every point is scanned
 constexpr float kDcCellScale = 1.07f;
 
 struct DcPoint {   // a point in bucket order: position and its own cell
@@ -77,6 +82,10 @@ struct DcWs {
   double* stat;         // [8] mu, sigma, rho_low, rho_high, mu_d, sigma_d, d_merge, unused
   unsigned long long* total;  // [2] kept, low counts (from the scans)
   uint32_t* range;      // [1] set if a coordinate is out of the cells' range
+  uint32_t* far;        // [n] queries the thread kernel left, [1] their count (far_n)
+  uint32_t* far_n;
+  uint32_t* far2;       // [n] queries the wave kernel left, [1] their count
+  uint32_t* far2_n;
   size_t bytes;
 };
 
@@ -108,6 +117,10 @@ static DcWs carve_dc(void* base, int64_t n) {
   w.stat = c.take<double>(8);
   w.total = c.take<unsigned long long>(2);
   w.range = c.take<uint32_t>(1);
+  w.far = c.take<uint32_t>(nn);
+  w.far_n = c.take<uint32_t>(1);
+  w.far2 = c.take<uint32_t>(nn);
+  w.far2_n = c.take<uint32_t>(1);
   w.bytes = c.off;
   return w;
 }
@@ -116,12 +129,13 @@ size_t density_workspace(int64_t n) { return carve_dc(nullptr, n).bytes; }
 
 __global__ __launch_bounds__(256) void k_dc_clear(uint32_t* __restrict__ a, uint32_t* __restrict__ b, uint32_t T,
                                                   unsigned long long* __restrict__ isum, double* __restrict__ dsum,
-                                                  unsigned long long* __restrict__ total, uint32_t* __restrict__ range) {
+                                                  unsigned long long* __restrict__ total, uint32_t* __restrict__ range,
+                                                  uint32_t* __restrict__ far_n, uint32_t* __restrict__ far2_n) {
   const uint32_t i = blockIdx.x * 256 + threadIdx.x;
   if (i < T) { a[i] = 0u; b[i] = 0u; }
   if (i == 0) {
     isum[0] = 0ull; isum[1] = 0ull; dsum[0] = 0.0; dsum[1] = 0.0;
-    total[0] = 0ull; total[1] = 0ull; range[0] = 0u;
+    total[0] = 0ull; total[1] = 0ull; range[0] = 0u; far_n[0] = 0u; far2_n[0] = 0u;
   }
 }
 
@@ -233,6 +247,38 @@ __device__ __forceinline__ void dc_insert(float (&bd)[K], int (&bi)[K], float d,
   }
 }
 
+// A query's results from its K best: nearest point, its distance and the
+// mean distance of the keff nearest; a1, a2 += the nearest distance and its square.
+template <int K>
+__device__ __forceinline__ void dc_finish(const float (&bd)[K], const int (&bi)[K], int keff, int qi,
+                                          int32_t* __restrict__ nn, float* __restrict__ dnn,
+                                          float* __restrict__ dbar, double& a1, double& a2) {
+  float sum = 0.0f;
+#pragma unroll
+  for (int m = 0; m < K; ++m)
+    if (m < keff) sum = __fadd_rn(sum, sqrtf(bd[m]));
+  const float d0 = keff > 0 ? sqrtf(bd[0]) : 0.0f;
+  nn[qi] = keff > 0 ? bi[0] : -1;
+  dnn[qi] = d0;
+  dbar[qi] = keff > 0 ? sum / static_cast<float>(keff) : 0.0f;
+  if (keff > 0) {
+    a1 += static_cast<double>(d0);
+    a2 += static_cast<double>(d0) * static_cast<double>(d0);
+  }
+}
+
+// Wave sums of the nearest-distance statistics, one atomic per wave.
+__device__ __forceinline__ void dc_dsum(double a1, double a2, double* __restrict__ dsum) {
+  for (int o = 32; o > 0; o >>= 1) {
+    a1 += __shfl_xor(a1, o, 64);
+    a2 += __shfl_xor(a2, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0 && (a1 != 0.0 || a2 != 0.0)) {
+    unsafeAtomicAdd(&dsum[0], a1);
+    unsafeAtomicAdd(&dsum[1], a2);
+  }
+}
+
 // The k nearest other points of every point, by (FP32 d2, index): nearest
 // point, its distance and the mean distance of the k (FP32: square roots
 // summed in order, over k); sums of the nearest distances for d_merge.
@@ -240,7 +286,8 @@ template <int K>
 __global__ __launch_bounds__(256) void k_dc_knn(int n, const DcPoint* __restrict__ pts,
                                                 const uint32_t* __restrict__ start, uint32_t T, float h,
                                                 int32_t* __restrict__ nn, float* __restrict__ dnn,
-                                                float* __restrict__ dbar, double* __restrict__ dsum) {
+                                                float* __restrict__ dbar, double* __restrict__ dsum,
+                                                uint32_t* __restrict__ far, uint32_t* __restrict__ far_n) {
   const int s = blockIdx.x * 256 + threadIdx.x;
   double a1 = 0.0, a2 = 0.0;
   if (s < n) {
@@ -253,7 +300,7 @@ __global__ __launch_bounds__(256) void k_dc_knn(int n, const DcPoint* __restrict
     for (int m = 0; m < K; ++m) { bd[m] = 3.0e38f; bi[m] = 0x7fffffff; }
     // fewer than K other points: no rings, straight to the scan of every point
     bool done = false;
-    for (int R = 0; R < kDcRings && !done && keff == K; ++R) {
+    for (int R = 0; R < kDcRingsThread && !done && keff == K; ++R) {
       for (int dz = -R; dz <= R; ++dz)
         for (int dy = -R; dy <= R; ++dy)
           for (int dx = -R; dx <= R; ++dx) {
@@ -274,35 +321,155 @@ __global__ __launch_bounds__(256) void k_dc_knn(int n, const DcPoint* __restrict
       if (g > 0.0f && bd[K - 1] <= g * g * 0.9999f) done = true;
     }
     if (!done) {
-      // far neighbours (or fewer than K points): every point, once
+      // far neighbours (or fewer than K points): the wave kernel goes on with this query
+      far[atomicAdd(far_n, 1u)] = static_cast<uint32_t>(s);
+    } else {
+      dc_finish<K>(bd, bi, keff, qi, nn, dnn, dbar, a1, a2);
+    }
+  }
+  dc_dsum(a1, a2, dsum);
+}
+
+// Cell t of the shell of ring R (Chebyshev offset exactly R), t < shell(R):
+// the two faces z = -R and z = +R ((2R+1)^2 cells each), then the ring of
+// the 2R-1 layers between them (8R cells each).
+__device__ __forceinline__ int3 dc_shell_cell(int R, int t) {
+  const int side = 2 * R + 1, face = side * side;
+  if (t < 2 * face) {
+    const int z = t < face ? -R : R;
+    const int u = t % face;
+    return make_int3(u % side - R, u / side - R, z);
+  }
+  t -= 2 * face;
+  const int per = 8 * R;
+  const int z = t / per - (R - 1);
+  int u = t % per;
+  // walk the square's boundary: bottom row, right column, top row, left column
+  if (u < side) return make_int3(u - R, -R, z);
+  u -= side;
+  if (u < side - 2) return make_int3(R, u - R + 1, z);
+  u -= side - 2;
+  if (u < side) return make_int3(R - u, R, z);
+  u -= side;
+  return make_int3(-R, R - 1 - u, z);
+}
+
+__device__ __forceinline__ int dc_shell_size(int R) { return R == 0 ? 1 : (2 * R + 1) * (2 * R + 1) * 2 + 8 * R * (2 * R - 1); }
+
+// Queries the thread kernel left, one wave per query: rings 0-7, each ring's
+// cells dealt to the 64 lanes, each lane its own top-k; the wave stops once
+// K of the points its lanes hold lie inside the ring's guarantee.  Queries
+// still open go on to the all-points kernel.
+template <int K>
+__global__ __launch_bounds__(256) void k_dc_knn_wave(int n, const DcPoint* __restrict__ pts,
+                                                     const uint32_t* __restrict__ start, uint32_t T, float h,
+                                                     const uint32_t* __restrict__ far, const uint32_t* __restrict__ far_n,
+                                                     uint32_t* __restrict__ far2, uint32_t* __restrict__ far2_n,
+                                                     int32_t* __restrict__ nn, float* __restrict__ dnn,
+                                                     float* __restrict__ dbar, double* __restrict__ dsum) {
+  __shared__ float s_d[4][64 * K];
+  __shared__ int s_i[4][64 * K];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint32_t count = *far_n;
+  for (uint32_t f = blockIdx.x * 4 + wave; f < count; f += gridDim.x * 4) {
+    const uint32_t slot = far[f];
+    const DcPoint q = pts[slot];
+    const int qi = __float_as_int(q.p.w);
+    float bd[K];
+    int bi[K];
 #pragma unroll
-      for (int m = 0; m < K; ++m) { bd[m] = 3.0e38f; bi[m] = 0x7fffffff; }
-      for (int p = 0; p < n; ++p) {
-        const DcPoint o = pts[p];
-        const int oi = __float_as_int(o.p.w);
-        if (oi != qi) dc_insert<K>(bd, bi, dc_d2(q.p, o.p), oi);
+    for (int m = 0; m < K; ++m) { bd[m] = 3.0e38f; bi[m] = 0x7fffffff; }
+    bool done = false;
+    const bool enough = n - 1 >= K;
+    for (int R = 0; R < kDcRingsWave && !done && enough; ++R) {
+      const int cells = dc_shell_size(R);
+      for (int t = lane; t < cells; t += 64) {
+        const int3 d = dc_shell_cell(R, t);
+        const int cx = q.c.x + d.x, cy = q.c.y + d.y, cz = q.c.z + d.z;
+        const uint32_t b = dc_hash(cx, cy, cz, T - 1u);
+        const uint32_t e = b + 1u < T ? start[b + 1u] : static_cast<uint32_t>(n);
+        for (uint32_t p = start[b]; p < e; ++p) {
+          const DcPoint o = pts[p];
+          const int oi = __float_as_int(o.p.w);
+          if (o.c.x != cx || o.c.y != cy || o.c.z != cz || oi == qi) continue;
+          dc_insert<K>(bd, bi, dc_d2(q.p, o.p), oi);
+        }
+      }
+      const float g = (static_cast<float>(R) - 0.0625f) * h;
+      if (g > 0.0f) {
+        const float g2 = g * g * 0.9999f;
+        int inside = 0;
+#pragma unroll
+        for (int m = 0; m < K; ++m) inside += __popcll(__ballot(bd[m] <= g2));
+        done = inside >= K;
       }
     }
-    float sum = 0.0f;
-#pragma unroll
-    for (int m = 0; m < K; ++m)
-      if (m < keff) sum = __fadd_rn(sum, sqrtf(bd[m]));
-    const float d0 = keff > 0 ? sqrtf(bd[0]) : 0.0f;
-    nn[qi] = keff > 0 ? bi[0] : -1;
-    dnn[qi] = d0;
-    dbar[qi] = keff > 0 ? sum / static_cast<float>(keff) : 0.0f;
-    if (keff > 0) {
-      a1 = static_cast<double>(d0);
-      a2 = a1 * a1;
+    if (!done) {
+      if (lane == 0) far2[atomicAdd(far2_n, 1u)] = slot;
+      continue;
     }
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+      s_d[wave][lane * K + m] = bd[m];
+      s_i[wave][lane * K + m] = bi[m];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane == 0) {
+      for (int l = 1; l < 64; ++l)
+        for (int m = 0; m < K; ++m) dc_insert<K>(bd, bi, s_d[wave][l * K + m], s_i[wave][l * K + m]);
+      double a1 = 0.0, a2 = 0.0;
+      dc_finish<K>(bd, bi, K, qi, nn, dnn, dbar, a1, a2);
+      unsafeAtomicAdd(&dsum[0], a1);
+      unsafeAtomicAdd(&dsum[1], a2);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  for (int o = 32; o > 0; o >>= 1) {
-    a1 += __shfl_xor(a1, o, 64);
-    a2 += __shfl_xor(a2, o, 64);
-  }
-  if ((threadIdx.x & 63) == 0 && (a1 != 0.0 || a2 != 0.0)) {
-    unsafeAtomicAdd(&dsum[0], a1);
-    unsafeAtomicAdd(&dsum[1], a2);
+}
+
+// The queries the ring search left: one workgroup per query at a time scans
+// every point (each thread a strided share, its own top-k), then the 256
+// lists are merged by thread 0 in LDS.
+template <int K>
+__global__ __launch_bounds__(256) void k_dc_knn_far(int n, const DcPoint* __restrict__ pts,
+                                                    const uint32_t* __restrict__ far, const uint32_t* __restrict__ far_n,
+                                                    int32_t* __restrict__ nn, float* __restrict__ dnn,
+                                                    float* __restrict__ dbar, double* __restrict__ dsum) {
+  __shared__ float s_d[256 * K];
+  __shared__ int s_i[256 * K];
+  const uint32_t count = *far_n;
+  for (uint32_t f = blockIdx.x; f < count; f += gridDim.x) {
+    const DcPoint q = pts[far[f]];
+    const int qi = __float_as_int(q.p.w);
+    float bd[K];
+    int bi[K];
+#pragma unroll
+    for (int m = 0; m < K; ++m) { bd[m] = 3.0e38f; bi[m] = 0x7fffffff; }
+    for (int p = threadIdx.x; p < n; p += 256) {
+      const DcPoint o = pts[p];
+      const int oi = __float_as_int(o.p.w);
+      if (oi != qi) dc_insert<K>(bd, bi, dc_d2(q.p, o.p), oi);
+    }
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+      s_d[threadIdx.x * K + m] = bd[m];
+      s_i[threadIdx.x * K + m] = bi[m];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int t = 1; t < 256; ++t)
+        for (int m = 0; m < K; ++m) dc_insert<K>(bd, bi, s_d[t * K + m], s_i[t * K + m]);
+      double a1 = 0.0, a2 = 0.0;
+      dc_finish<K>(bd, bi, min(K, n - 1), qi, nn, dnn, dbar, a1, a2);
+      if (a1 != 0.0 || a2 != 0.0) {
+        unsafeAtomicAdd(&dsum[0], a1);
+        unsafeAtomicAdd(&dsum[1], a2);
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -429,7 +596,7 @@ gs_status launch_density_control(const gs_gaussians& g, const gs_density_params&
   const unsigned gn = static_cast<unsigned>(std::max<int64_t>(ceil_div(n, 256), 1));
   gs_status st;
   { TimedLaunch t("k_dc_clear", s); k_dc_clear<<<static_cast<unsigned>(ceil_div(T, 256)), 256, 0, s>>>(w.count, w.fill, T, w.isum, w.dsum,
-                                                                                               w.total, w.range); }
+                                                                                               w.total, w.range, w.far_n, w.far2_n); }
   if ((st = check_launch("k_dc_clear")) != GS_OK) return st;
   if (n > 0) {
     { TimedLaunch t("k_dc_cells", s); k_dc_cells<<<gn, 256, 0, s>>>(n, g.means, inv_h, T - 1u, w.cell, w.count, w.range); }
@@ -445,7 +612,15 @@ gs_status launch_density_control(const gs_gaussians& g, const gs_density_params&
   if ((st = check_launch("k_dc_thresholds")) != GS_OK) return st;
   if (n > 0) {
 #define GS_DC_KNN(K)                                                                                             \
-  { TimedLaunch t("k_dc_knn<" #K ">", s); k_dc_knn<K><<<gn, 256, 0, s>>>(n, w.pts, w.count, T, h, w.nn, w.dnn, w.dbar, w.dsum); }
+  {                                                                                                              \
+    { TimedLaunch t("k_dc_knn<" #K ">", s);                                                                     \
+      k_dc_knn<K><<<gn, 256, 0, s>>>(n, w.pts, w.count, T, h, w.nn, w.dnn, w.dbar, w.dsum, w.far, w.far_n); }   \
+    { TimedLaunch t("k_dc_knn_wave<" #K ">", s);                                                                \
+      k_dc_knn_wave<K><<<2048, 256, 0, s>>>(n, w.pts, w.count, T, h, w.far, w.far_n, w.far2, w.far2_n, w.nn,      \
+                                            w.dnn, w.dbar, w.dsum); }                                             \
+    { TimedLaunch t("k_dc_knn_far<" #K ">", s);                                                                 \
+      k_dc_knn_far<K><<<1024, 256, 0, s>>>(n, w.pts, w.far2, w.far2_n, w.nn, w.dnn, w.dbar, w.dsum); }           \
+  }
     switch (prm.knn) {
       case 1: GS_DC_KNN(1); break;
       case 2: GS_DC_KNN(2); break;
