@@ -206,7 +206,7 @@ struct SampleIn {
 };
 
 template <int MODE, bool BWD>
-__device__ __forceinline__ SampleIn load_sample(int s, int S, int per, int g, const uint16_t* __restrict__ latents,
+__device__ __forceinline__ SampleIn load_sample(int64_t s64, int S, int per, int g, const uint16_t* __restrict__ latents,
                                                 const float* __restrict__ dirs, const float* __restrict__ means,
                                                 const int* __restrict__ radius, const float* __restrict__ dL_dc,
                                                 const float* __restrict__ dmean = nullptr) {
@@ -215,8 +215,10 @@ __device__ __forceinline__ SampleIn load_sample(int s, int S, int per, int g, co
   x.c[0] = x.c[1] = x.c[2] = 0.f;
   x.m[0] = x.m[1] = x.m[2] = 0.f;
   x.z = make_uint4(0, 0, 0, 0);
-  x.in = s < S;
+  // look-ahead indices run past S (in 64-bit, so they cannot wrap)
+  x.in = s64 >= 0 && s64 < S;
   if (!x.in) return x;
+  const int s = static_cast<int>(s64);
   if (MODE == 0) {
     x.a[0] = dirs[3 * static_cast<int64_t>(s)];
     x.a[1] = dirs[3 * static_cast<int64_t>(s) + 1];
@@ -267,11 +269,12 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(int S, int per, const uint16_t*
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
   const int stride = gridDim.x * 4;
   int grp = blockIdx.x * 4 + wave;
-  SampleIn cur = load_sample<MODE, false>(grp * 16 + r, S, per, g, latents, dirs, means, radius, nullptr);
-  for (; grp * 16 < S; grp += stride) {
+  SampleIn cur = load_sample<MODE, false>(static_cast<int64_t>(grp) * 16 + r, S, per, g, latents, dirs, means, radius,
+                                          nullptr);
+  for (; static_cast<int64_t>(grp) * 16 < S; grp += stride) {
     const int s = grp * 16 + r;
-    const SampleIn nxt = load_sample<MODE, false>((grp + stride) * 16 + r, S, per, g, latents, dirs, means, radius,
-                                                  nullptr);
+    const SampleIn nxt = load_sample<MODE, false>((static_cast<int64_t>(grp) + stride) * 16 + r, S, per, g, latents,
+                                                  dirs, means, radius, nullptr);
     const bool valid = cur.in;
     float d[3], len;
     sample_dir<MODE>(cur, cam, d, len);
@@ -578,13 +581,13 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(int S, int per, const uint16_t*
   const float* cin = (MODE == 0 && loss_mode) ? target : dL_dc;
   // groups of this wave in order: units wave_id, wave_id + nwaves, ..., each
   // unit's gpl groups in turn; the next group's inputs are loaded ahead
-  auto group_of = [&](int unit, int q) { return (unit * gpl + q) * 16 + r; };
+  auto group_of = [&](int unit, int q) { return (static_cast<int64_t>(unit) * gpl + q) * 16 + r; };
   SampleIn cur = load_sample<MODE, true>(group_of(wave_id, 0), wave_id < nunits ? S : 0, per, g, latents, dirs,
                                          means, radius, cin, dmean);
   for (int unit = wave_id; unit < nunits; unit += nwaves) {
     floatx4 zacc = zero;
     for (int q = 0; q < gpl; ++q) {
-      const int s = group_of(unit, q);
+      const int s = static_cast<int>(group_of(unit, q));
       const int nunit = (q + 1 < gpl) ? unit : unit + nwaves;
       const int nq = (q + 1 < gpl) ? q + 1 : 0;
       const SampleIn nxt = load_sample<MODE, true>(group_of(nunit, nq), nunit < nunits ? S : 0, per, g, latents,

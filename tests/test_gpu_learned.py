@@ -4,8 +4,9 @@ Adam, distillation, and the image-quality gain test.
 The decoder is not part of the paper; its quality has no paper value to pin
 against.  The gain test checks what training must achieve whatever the bar:
 the trained decoder renders closer to the SH images than the untrained one
-and than the DC-only SH colour (no view dependence), and its loss reaches the
-scene's capacity bound for a 16-value latent.  The PSNR delta against a
+and than the DC-only SH colour (no view dependence), and its loss is at most
+the least loss any decoder affine in a 16-value latent can reach on the scene
+(a reference level, not a bound on what the non-linear decoder can do).  The PSNR delta against a
 noisy target at the paper's 3DGS PSNR level (noise sigma 0.03569, about
 28.95 dB) is reported, and held to 0.1 dB on a scene whose view dependence
 fits the latent.
@@ -89,7 +90,7 @@ def _psnr(a, b):
     return 10 * math.log10(1.0 / mse) if mse > 0 else float("inf")
 
 
-def _affine_capacity_loss(scene, rank=16):
+def _affine_reference_loss(scene, rank=16):
     """Smallest mean squared colour error (summed over channels, averaged over
     the sphere, no clamp) of any decoder that is affine in a `rank`-value
     latent: the coefficient-space PCA residual, since the real SH basis is
@@ -140,13 +141,14 @@ def _distill_and_compare(gs, scene, epochs=400):
 def test_distillation_gain(gs):
     """Learned-colour scene (200k Gaussians, independent SH coefficients): the
     trained decoder beats the untrained one and DC-only SH, and its training
-    loss reaches the scene's rank-16 affine capacity (the best any decoder
-    affine in a 16-value latent can do: 3 DC values plus 13 of the 45
-    independent view-dependent coefficients)."""
+    loss is at most the rank-16 affine reference (the least loss of any decoder
+    affine in a 16-value latent: 3 DC values plus 13 of the 45 independent
+    view-dependent coefficients).  The ReLU decoder may go below it, and does
+    slightly; the reference is a level training must reach, not a limit."""
     scene = scenes.config_scene(5)
-    bound = _affine_capacity_loss(scene)
+    bound = _affine_reference_loss(scene)
     losses, p_tr, p_un, p_dc, delta = _distill_and_compare(gs, scene)
-    say(f"  rank-16 affine capacity loss {bound:.3e}; trained loss {losses[-1]:.3e}")
+    say(f"  rank-16 affine reference loss {bound:.3e}; trained loss {losses[-1]:.3e}")
     assert p_tr > p_un and p_tr > p_dc
     assert losses[-1] <= bound
 
@@ -156,7 +158,7 @@ def test_distillation_low_rank_colour(gs):
     16-value latent): the trained decoder renders within 0.1 dB of SH under the
     noisy-target reading."""
     scene = scenes.low_rank_colour(scenes.config_scene(5), 8, 5003)
-    assert _affine_capacity_loss(scene) < 1e-12
+    assert _affine_reference_loss(scene) < 1e-12
     losses, p_tr, p_un, p_dc, delta = _distill_and_compare(gs, scene)
     assert p_tr > p_un and p_tr > p_dc
     assert delta <= 0.1, delta

@@ -41,7 +41,8 @@ def _packed(gs, Pbits):
     return packed
 
 
-@pytest.mark.parametrize("n,per", [(1, 1), (37, 3), (4096, 4), (20000, 1)])
+# (16384, 64): a distillation minibatch, 1,048,576 samples, as the distiller runs it
+@pytest.mark.parametrize("n,per", [(1, 1), (37, 3), (4096, 4), (20000, 1), (16384, 64)])
 def test_mlp_forward_matches_oracle_within_bf16_bound(gs, n, per):
     say(f"[mlp fwd] n={n} per={per}")
     Pbits = kaiming_params(10 + n)
@@ -76,10 +77,12 @@ def test_mlp_zero_weights_give_sigmoid_bias(gs):
     assert np.abs(rgb.cpu().numpy() - want).max() < 1e-6
 
 
-def test_project_with_learned_colour(gs):
+@pytest.mark.parametrize("n", [20000, 200000])
+def test_project_with_learned_colour(gs, n):
     """colour_mode 1: geometry identical to the SH projection, colour = decoder of
-    (latent, SH encoding of the camera-to-Gaussian direction) for live Gaussians."""
-    scene = scenes.config_scene(5, n=20000)
+    (latent, SH encoding of the camera-to-Gaussian direction) for live Gaussians;
+    200,000 is the learned-colour workload in full."""
+    scene = scenes.config_scene(5, n=n)
     cam = scenes.config_camera(5)
     say(f"[project learned colour] n={scene.n}")
     Pbits = kaiming_params(5)
@@ -117,7 +120,7 @@ def _bwd_workspace(gs, S, per):
     return torch.empty(gs.mlp_bwd_workspace(S, per), dtype=torch.uint8, device=DEV)
 
 
-@pytest.mark.parametrize("n,per", [(1, 1), (37, 4), (300, 64), (5000, 1), (2000, 16)])
+@pytest.mark.parametrize("n,per", [(1, 1), (37, 4), (300, 64), (5000, 1), (2000, 16), (16384, 64)])
 def test_mlp_backward_matches_oracle_within_bound(gs, n, per):
     say(f"[mlp bwd] n={n} per={per}")
     Pbits = kaiming_params(30 + n)
@@ -182,13 +185,16 @@ def test_mlp_distillation_loss_and_gradient(gs):
                  dlat.cpu().numpy().astype(np.float64), want_z, bz, massP)
 
 
-def test_project_bwd_learned_colour(gs):
+@pytest.mark.parametrize("n", [6000, 200000])
+def test_project_bwd_learned_colour(gs, n):
     """colour_mode 1 backward: geometry gradients as the SH path's (degree 0
     carries no direction term), plus the decoder's latent, weight and
-    view-direction gradients, against the FP64 oracle / torch autograd."""
+    view-direction gradients, against the FP64 oracle / torch autograd;
+    200,000 is the learned-colour workload in full (its weight gradient sums
+    over all of them)."""
     from oracle import brute
     from gpu_helpers import grad_close
-    scene = scenes.config_scene(5, n=6000)
+    scene = scenes.config_scene(5, n=n)
     cam = scenes.config_camera(5)
     n = scene.n
     say(f"[project bwd learned colour] n={n}")
