@@ -462,18 +462,55 @@ __global__ __launch_bounds__(kRsThreads) void k_os_scatter(const uint32_t* __res
                                                            uint32_t* __restrict__ cnt_out) {
   constexpr int CHUNK = kRsThreads * ITEMS;
   constexpr int PER_WAVE = CHUNK / 4;
+  __shared__ uint32_t s_vid, s_whole;
   const int passes = (total_bits + 7) / 8;
   const int shift = 8 * pass, nbits = min(8, total_bits - 8 * pass);
-  const uint32_t* const ghist_pass = ghist + pass * 256;
-  int last_changing = 0;
-  bool trivial = false;
-  for (int q = 0; q < passes; ++q) {
-    const int qb = min(8, total_bits - 8 * q);
-    const bool t = __syncthreads_or(static_cast<uint32_t>(threadIdx.x) <= ((1u << qb) - 1u) &&
-                                    static_cast<int64_t>(ghist[q * 256 + threadIdx.x]) == count);
-    if (!t) last_changing = q;
-    if (q == pass) trivial = t;
+  // every pass's digit counts are read at once (one HBM round trip, not one
+  // per pass behind a barrier), and the chunk's virtual id is drawn alongside
+  uint32_t gh[kOsMaxPasses];
+#pragma unroll
+  for (int q = 0; q < kOsMaxPasses; ++q) gh[q] = q < passes ? ghist[q * 256 + threadIdx.x] : 0u;
+  if (threadIdx.x == 0) {
+    s_whole = 0u;
+    s_vid = atomicAdd(counter, 1u);
   }
+  __syncthreads();
+  // the chunk's keys (whatever the pass turns out to be: a returning or
+  // copying workgroup has read a few KB for nothing)
+  const uint32_t vid = s_vid;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int64_t base = static_cast<int64_t>(vid) * CHUNK + static_cast<int64_t>(wave) * PER_WAVE;
+  uint32_t k[ITEMS], v[ITEMS], lr[ITEMS];
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const int64_t idx = base + j * 64 + lane;
+    const bool valid = idx < count;
+    k[j] = valid ? keys_in[idx] : 0u;
+    v[j] = valid ? vals_in[idx] : 0u;
+  }
+  // bit q of s_whole: some digit of pass q holds every key (the pass keeps the order)
+  uint32_t mine = 0u;
+#pragma unroll
+  for (int q = 0; q < kOsMaxPasses; ++q) {
+    const int qb = min(8, total_bits - 8 * q);
+    if (q < passes && static_cast<uint32_t>(threadIdx.x) <= ((1u << qb) - 1u) && static_cast<int64_t>(gh[q]) == count)
+      mine |= 1u << q;
+  }
+  if (mine) atomicOr(&s_whole, mine);
+  __shared__ uint32_t sk[CHUNK];
+  __shared__ uint32_t sv[CHUNK];
+  __shared__ uint32_t wrun[4][256];   // per-wave running digit counts
+  __shared__ uint32_t dstart[256];    // block-local start of each digit
+  __shared__ uint32_t gbase[256];     // global start of each digit for this block
+  __shared__ uint32_t scan_tmp[256];
+  wrun[0][tid] = 0; wrun[1][tid] = 0; wrun[2][tid] = 0; wrun[3][tid] = 0;
+  __syncthreads();
+  const uint32_t whole = s_whole;
+  int last_changing = 0;
+  for (int q = 0; q < passes; ++q)
+    if (!((whole >> q) & 1u)) last_changing = q;
+  const bool trivial = (whole >> pass) & 1u;
   if (pass > last_changing) return;   // the order is final already
   const bool terminal = pass == last_changing;
   auto emit = [&](int64_t g, uint32_t key, uint32_t val) {
@@ -496,30 +533,8 @@ __global__ __launch_bounds__(kRsThreads) void k_os_scatter(const uint32_t* __res
       emit(i, keys_in[i], vals_in[i]);
     return;
   }
-  __shared__ uint32_t sk[CHUNK];
-  __shared__ uint32_t sv[CHUNK];
-  __shared__ uint32_t wrun[4][256];   // per-wave running digit counts
-  __shared__ uint32_t dstart[256];    // block-local start of each digit
-  __shared__ uint32_t gbase[256];     // global start of each digit for this block
-  __shared__ uint32_t scan_tmp[256];
-  __shared__ uint32_t s_vid;
-  const int tid = threadIdx.x;
-  const int wave = tid >> 6, lane = tid & 63;
   const uint32_t mask = (1u << nbits) - 1u;
-  if (tid == 0) s_vid = atomicAdd(counter, 1u);
-  wrun[0][tid] = 0; wrun[1][tid] = 0; wrun[2][tid] = 0; wrun[3][tid] = 0;
-  __syncthreads();
-  const uint32_t vid = s_vid;
-  const int64_t base = static_cast<int64_t>(vid) * CHUNK + static_cast<int64_t>(wave) * PER_WAVE;
   const uint64_t below = lanemask_lt();
-  uint32_t k[ITEMS], v[ITEMS], lr[ITEMS];
-#pragma unroll
-  for (int j = 0; j < ITEMS; ++j) {
-    const int64_t idx = base + j * 64 + lane;
-    const bool valid = idx < count;
-    k[j] = valid ? keys_in[idx] : 0u;
-    v[j] = valid ? vals_in[idx] : 0u;
-  }
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
     const int64_t idx = base + j * 64 + lane;
@@ -537,7 +552,10 @@ __global__ __launch_bounds__(kRsThreads) void k_os_scatter(const uint32_t* __res
   uint32_t tot;
   const uint32_t ds = block_exclusive_scan(cnt, scan_tmp, tot);
   // global digit starts of this pass: exclusive scan of the global counts
-  const uint32_t gd = block_exclusive_scan(static_cast<uint32_t>(tid) <= mask ? ghist_pass[tid] : 0u, scan_tmp, tot);
+  uint32_t ghp = 0u;
+#pragma unroll
+  for (int q = 0; q < kOsMaxPasses; ++q) ghp = q == pass ? gh[q] : ghp;
+  const uint32_t gd = block_exclusive_scan(static_cast<uint32_t>(tid) <= mask ? ghp : 0u, scan_tmp, tot);
   // decoupled look-back, one digit per thread
   uint32_t prefix = 0;
   if (static_cast<uint32_t>(tid) <= mask) {
@@ -595,7 +613,32 @@ __global__ __launch_bounds__(kRsThreads) void k_os_scatter(const uint32_t* __res
   }
   __syncthreads();
   const int64_t bbase = static_cast<int64_t>(vid) * CHUNK;
-  const int64_t nvalid = min(static_cast<int64_t>(CHUNK), count - bbase);
+  const int nvalid = static_cast<int>(min(static_cast<int64_t>(CHUNK), count - bbase));
+  if (terminal && rect) {
+    // the final order with each value's rectangle: all of the thread's
+    // gathers in flight together
+    uint32_t g[ITEMS], val[ITEMS];
+    uint2 rc[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const int p = tid + j * kRsThreads;
+      if (p < nvalid) {
+        const uint32_t d = (sk[p] >> shift) & mask;
+        g[j] = gbase[d] + (static_cast<uint32_t>(p) - dstart[d]);
+        val[j] = sv[p];
+        rc[j] = rect[val[j]];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      if (tid + j * kRsThreads < nvalid) {
+        vals_final[g[j]] = val[j];
+        rect_out[g[j]] = rc[j];
+        cnt_out[g[j]] = rect_count(rc[j]);
+      }
+    }
+    return;
+  }
   for (int p = tid; p < nvalid; p += kRsThreads) {
     const uint32_t key = sk[p];
     const uint32_t d = (key >> shift) & mask;
@@ -984,7 +1027,10 @@ __device__ __forceinline__ void place_entry(int rw, uint32_t e, const uint32_t* 
 // earlier ranks on the tile.  The entry of the tile's last rank in the group
 // also writes the group's count for the tile into delta[t], which one pass
 // over the tiles adds to the positions once every entry of the group is
-// placed.
+// placed.  Chunks go to workgroups through the XCD-aware map, so each XCD
+// takes consecutive chunks: the short runs that neighbouring chunks write into
+// one tile's list then meet in one L2 instead of being written back to HBM in
+// pieces from several.
 // two workgroups per CU (8 waves per SIMD): at most 64 VGPRs
 __global__ __launch_bounds__(kDirectThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_emit_direct(const uint32_t* __restrict__ bounds,
                                                                 const uint32_t* __restrict__ order,
@@ -1002,7 +1048,7 @@ __global__ __launch_bounds__(kDirectThreads) __attribute__((amdgpu_waves_per_eu(
   const int edge = tiles_x + tiles_y;
   uint32_t* const s_pos = reinterpret_cast<uint32_t*>(s_dyn + 4 * edge);
   uint16_t* const s_delta = reinterpret_cast<uint16_t*>(s_pos + ntiles);
-  const int c = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int c = xcd_remap(blockIdx.x, gridDim.x), tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wave_u = __builtin_amdgcn_readfirstlane(wave);
   const uint32_t R0 = bounds[c], R1 = bounds[c + 1];
   if (R0 >= R1) return;

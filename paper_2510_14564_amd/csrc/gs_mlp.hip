@@ -132,17 +132,22 @@ __device__ __forceinline__ void split_put2(Split8& s, int e, float a, float b) {
   s.lo[e] = p.lo[0]; s.lo[e + 1] = p.lo[1];
 }
 
-// Read a D-layout result (4 row-blocks) back as the split B operands of the
-// next layer, after bias + ReLU.
-__device__ __forceinline__ void relu_to_b(const floatx4 h[4], const float* bias, int g, Split8& B0, Split8& B1) {
+// Read a D-layout pre-activation (4 row-blocks, bias included) back as the
+// split B operands of the next layer, after the ReLU.
+__device__ __forceinline__ void relu_to_b(const floatx4 h[4], Split8& B0, Split8& B1) {
 #pragma unroll
   for (int e = 0; e < 8; e += 2) {
     const int b0 = e >> 2, i = e & 3;
-    split_put2(B0, e, fmaxf(h[b0][i] + bias[16 * b0 + 4 * g + i], 0.0f),
-               fmaxf(h[b0][i + 1] + bias[16 * b0 + 4 * g + i + 1], 0.0f));
-    split_put2(B1, e, fmaxf(h[2 + b0][i] + bias[16 * (2 + b0) + 4 * g + i], 0.0f),
-               fmaxf(h[2 + b0][i + 1] + bias[16 * (2 + b0) + 4 * g + i + 1], 0.0f));
+    split_put2(B0, e, fmaxf(h[b0][i], 0.0f), fmaxf(h[b0][i + 1], 0.0f));
+    split_put2(B1, e, fmaxf(h[2 + b0][i], 0.0f), fmaxf(h[2 + b0][i + 1], 0.0f));
   }
+}
+
+// The biases of a hidden layer in the D layout of row-block b: lane (g, r)
+// holds rows 4 g .. 4 g + 3, i.e. units 16 b + 4 g + i -- the accumulator a
+// layer's products start from, so the pre-activation needs no separate add.
+__device__ __forceinline__ floatx4 bias_d(const float* bias, int b, int g) {
+  return *reinterpret_cast<const floatx4*>(bias + 16 * b + 4 * g);
 }
 
 // Layer-1 B operand of lane (g, sample s): latent values 8g..8g+7 (g < 2,
@@ -176,18 +181,19 @@ __device__ __forceinline__ floatx4 mfma2(const uint4& a, const Split8& b, const 
   return mfma(a, b.lo, mfma(a, b.hi, c));
 }
 
+// h1, h2: pre-activations (biases included); B, C: the split ReLU outputs.
 __device__ __forceinline__ void mlp_forward_group(const MlpShared& sh, int lane, MlpFwdState& st) {
   const int g = lane >> 4;
   const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int b = 0; b < 4; ++b) st.h1[b] = mfma2(sh.ops[(kOpW1 + b) * 64 + lane], st.X, zero);
-  relu_to_b(st.h1, sh.bias, g, st.B0, st.B1);
+  for (int b = 0; b < 4; ++b) st.h1[b] = mfma2(sh.ops[(kOpW1 + b) * 64 + lane], st.X, bias_d(sh.bias, b, g));
+  relu_to_b(st.h1, st.B0, st.B1);
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
-    floatx4 acc = mfma2(sh.ops[(kOpW2 + 2 * b) * 64 + lane], st.B0, zero);
+    floatx4 acc = mfma2(sh.ops[(kOpW2 + 2 * b) * 64 + lane], st.B0, bias_d(sh.bias + 64, b, g));
     st.h2[b] = mfma2(sh.ops[(kOpW2 + 2 * b + 1) * 64 + lane], st.B1, acc);
   }
-  relu_to_b(st.h2, sh.bias + 64, g, st.C0, st.C1);
+  relu_to_b(st.h2, st.C0, st.C1);
   floatx4 acc = mfma2(sh.ops[kOpW3 * 64 + lane], st.C0, zero);
   st.o = mfma2(sh.ops[(kOpW3 + 1) * 64 + lane], st.C1, acc);
 }
@@ -378,11 +384,10 @@ struct MlpStage {
   __bf16 g3[2][16][kRow];
 };
 
-// units u and u + 1 of sample r
-__device__ __forceinline__ void stage_put2(__bf16 (*plane)[64][kRow], int u, int r, float a, float b) {
-  const Split2 p = split2(a, b);
-  plane[0][u][r] = p.hi[0]; plane[0][u + 1][r] = p.hi[1];
-  plane[1][u][r] = p.lo[0]; plane[1][u + 1][r] = p.lo[1];
+// unit u of sample r: slot e of a split operand
+__device__ __forceinline__ void stage_put(__bf16 (*plane)[64][kRow], int u, int r, const Split8& v, int e) {
+  plane[0][u][r] = v.hi[e];
+  plane[1][u][r] = v.lo[e];
 }
 
 struct Split4 {
@@ -464,7 +469,7 @@ __device__ __forceinline__ void mlp_bwd_group(const MlpShared& sh, MlpStage& sg,
   for (int b = 0; b < 4; ++b) {
     const floatx4 t = mfma2(sh.ops[(kOpW3T + b) * 64 + lane], Bg3, zero);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) g2[b][i] = (st.h2[b][i] + sh.bias[64 + 16 * b + 4 * g + i] > 0.0f) ? t[i] : 0.0f;
+    for (int i = 0; i < 4; ++i) g2[b][i] = (st.h2[b][i] > 0.0f) ? t[i] : 0.0f;
   }
   Split8 G0, G1;
   grad_to_b(g2, G0, G1);
@@ -474,7 +479,7 @@ __device__ __forceinline__ void mlp_bwd_group(const MlpShared& sh, MlpStage& sg,
     floatx4 t = mfma2(sh.ops[(kOpW2T + 2 * b) * 64 + lane], G0, zero);
     t = mfma2(sh.ops[(kOpW2T + 2 * b + 1) * 64 + lane], G1, t);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) g1[b][i] = (st.h1[b][i] + sh.bias[16 * b + 4 * g + i] > 0.0f) ? t[i] : 0.0f;
+    for (int i = 0; i < 4; ++i) g1[b][i] = (st.h1[b][i] > 0.0f) ? t[i] : 0.0f;
   }
   Split8 H0, H1;
   grad_to_b(g1, H0, H1);
@@ -483,17 +488,17 @@ __device__ __forceinline__ void mlp_bwd_group(const MlpShared& sh, MlpStage& sg,
   dxe = mfma2(sh.ops[(kOpW1T + 2) * 64 + lane], H0, zero);
   dxe = mfma2(sh.ops[(kOpW1T + 3) * 64 + lane], H1, dxe);
 
-  // transposed staging for the weight gradients
+  // transposed staging for the weight gradients: the split operands the
+  // products above used (slot e of B_c carries unit hid(c, g, e))
 #pragma unroll
-  for (int b = 0; b < 4; ++b)
+  for (int c = 0; c < 2; ++c)
 #pragma unroll
-    for (int i = 0; i < 4; i += 2) {
-      const int u = 16 * b + 4 * g + i;
-      stage_put2(sg.h1, u, r, fmaxf(st.h1[b][i] + sh.bias[u], 0.0f), fmaxf(st.h1[b][i + 1] + sh.bias[u + 1], 0.0f));
-      stage_put2(sg.h2, u, r, fmaxf(st.h2[b][i] + sh.bias[64 + u], 0.0f),
-                 fmaxf(st.h2[b][i + 1] + sh.bias[64 + u + 1], 0.0f));
-      stage_put2(sg.g1, u, r, g1[b][i], g1[b][i + 1]);
-      stage_put2(sg.g2, u, r, g2[b][i], g2[b][i + 1]);
+    for (int e = 0; e < 8; ++e) {
+      const int u = hid(c, g, e);
+      stage_put(sg.h1, u, r, c ? st.B1 : st.B0, e);
+      stage_put(sg.h2, u, r, c ? st.C1 : st.C0, e);
+      stage_put(sg.g1, u, r, c ? H1 : H0, e);
+      stage_put(sg.g2, u, r, c ? G1 : G0, e);
     }
 #pragma unroll
   for (int b = 0; b < 4; ++b)
