@@ -198,7 +198,9 @@ __device__ __forceinline__ void mlp_forward_group(const MlpShared& sh, int lane,
   st.o = mfma2(sh.ops[(kOpW3 + 1) * 64 + lane], st.C1, acc);
 }
 
-__device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + __expf(-x)); }
+// The hardware reciprocal (1 ulp) instead of a correctly rounded division:
+// the colour's error budget is set by the BF16 products, far above it.
+__device__ __forceinline__ float sigmoidf(float x) { return __builtin_amdgcn_rcpf(1.0f + __expf(-x)); }
 
 // Inputs of one lane's sample.  The kernels load them one group ahead, so
 // their latency hides behind the current group's arithmetic (a wave runs
@@ -352,18 +354,13 @@ size_t mlp_packed_bytes() { return kOps * 64 * sizeof(uint4) + kBiasFloats * siz
 // activations and gradients go to LDS transposed ([unit][sample], hi and lo
 // planes) and
 //   dW1 += g1 x^T,  dW2 += g2 h1^T,  dW3 += g3 h2^T
-// run on v_mfma_f32_16x16x16_bf16 as hi.hi + lo.hi + hi.lo (the lo.lo term,
-// about 2^-18 relative, is dropped) with K = the group's 16 samples (lane l holds
-// A[l % 16][4 (l / 16) + e] and B[4 (l / 16) + e][l % 16], e = 0..3).  Sums stay
+// run as hi.hi + lo.hi + hi.lo (the lo.lo term, about 2^-18 relative, is
+// dropped) on two 16x16x32 products whose K runs over the group's 16 samples
+// twice: [g_hi | g_lo] x [h_hi | h_hi], then [g_hi | g_lo] x [h_lo | 0] (for the
+// latent inputs, whose lo part is zero, the first alone).  Sums stay
 // in registers for the wave's whole share and are written once as a partial
 // vector; a fixed-order two-stage sum over waves makes the result
 // deterministic for a given sample count.
-
-typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ floatx4 mfma16(const bf16x4& a, const bf16x4& b, const floatx4& c) {
-  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
-}
 
 constexpr int kPartStride = GS_MLP_PARAMS + 1;  // parameters, then the loss
 constexpr int kBwdWavesMax = 1024;
@@ -375,7 +372,7 @@ constexpr int kReduceChunk = 64;                 // waves per first-stage block
 // write rows 4 apart, then land on disjoint LDS banks, and row starts stay
 // 8-byte aligned for the operand reads.
 constexpr int kRow = 20;
-struct MlpStage {
+struct alignas(16) MlpStage {
   __bf16 x[2][32][kRow];
   __bf16 h1[2][64][kRow];
   __bf16 h2[2][64][kRow];
@@ -390,21 +387,28 @@ __device__ __forceinline__ void stage_put(__bf16 (*plane)[64][kRow], int u, int 
   plane[1][u][r] = v.lo[e];
 }
 
-struct Split4 {
-  bf16x4 hi, lo;
-};
-
+// A 16x16x32 operand over a group's staged samples: lane (g, r) takes row
+// `row`, samples 8 (g & 1) .. 8 (g & 1) + 7 of plane p (K slots 8 g .. 8 g + 7:
+// samples 0..15, then 0..15 again).
 template <int ROWS>
-__device__ __forceinline__ Split4 stage_read(const __bf16 (*plane)[ROWS][kRow], int row, int g) {
-  Split4 v;
-  __builtin_memcpy(&v.hi, &plane[0][row][4 * g], sizeof(v.hi));
-  __builtin_memcpy(&v.lo, &plane[1][row][4 * g], sizeof(v.lo));
+__device__ __forceinline__ bf16x8 stage_read8(const __bf16 (*plane)[ROWS][kRow], int p, int row, int g) {
+  bf16x8 v;
+  __builtin_memcpy(&v, &plane[p][row][8 * (g & 1)], sizeof(v));
   return v;
 }
+// [hi | lo] along K (the gradient side), [hi | hi], and [lo | 0]
+template <int ROWS>
+__device__ __forceinline__ bf16x8 stage_hilo(const __bf16 (*plane)[ROWS][kRow], int row, int g) {
+  return stage_read8<ROWS>(plane, g >> 1, row, g);
+}
+template <int ROWS>
+__device__ __forceinline__ bf16x8 stage_lo0(const __bf16 (*plane)[ROWS][kRow], int row, int g) {
+  bf16x8 v = stage_read8<ROWS>(plane, 1, row, g);
+  return g < 2 ? v : bf16x8{};
+}
 
-// (a_hi + a_lo)(b_hi + b_lo) without the lo x lo term, small terms first.
-__device__ __forceinline__ floatx4 mfma16x3(const Split4& a, const Split4& b, const floatx4& c) {
-  return mfma16(a.hi, b.hi, mfma16(a.lo, b.hi, mfma16(a.hi, b.lo, c)));
+__device__ __forceinline__ floatx4 mfma32(const bf16x8& a, const bf16x8& b, const floatx4& c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
 // D-layout gradients (4 row-blocks) as the split B operands of the next product.
@@ -521,23 +525,26 @@ __device__ __forceinline__ void mlp_bwd_group(const MlpShared& sh, MlpStage& sg,
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  Split4 bH1[4], bH2[4];
+  bf16x8 bH1[4], bH1l[4], bH2[4], bH2l[4];
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
-    bH1[b] = stage_read<64>(sg.h1, 16 * b + r, g);
-    bH2[b] = stage_read<64>(sg.h2, 16 * b + r, g);
+    bH1[b] = stage_read8<64>(sg.h1, 0, 16 * b + r, g);
+    bH1l[b] = stage_lo0<64>(sg.h1, 16 * b + r, g);
+    bH2[b] = stage_read8<64>(sg.h2, 0, 16 * b + r, g);
+    bH2l[b] = stage_lo0<64>(sg.h2, 16 * b + r, g);
   }
-  const Split4 bX0 = stage_read<32>(sg.x, r, g), bX1 = stage_read<32>(sg.x, 16 + r, g);
-  const Split4 aG3 = stage_read<16>(sg.g3, r, g);
+  const bf16x8 bX0 = stage_read8<32>(sg.x, 0, r, g);
+  const bf16x8 bX1 = stage_read8<32>(sg.x, 0, 16 + r, g), bX1l = stage_lo0<32>(sg.x, 16 + r, g);
+  const bf16x8 aG3 = stage_hilo<16>(sg.g3, r, g);
 #pragma unroll
   for (int bo = 0; bo < 4; ++bo) {
-    const Split4 aG2 = stage_read<64>(sg.g2, 16 * bo + r, g);
-    const Split4 aG1 = stage_read<64>(sg.g1, 16 * bo + r, g);
+    const bf16x8 aG2 = stage_hilo<64>(sg.g2, 16 * bo + r, g);
+    const bf16x8 aG1 = stage_hilo<64>(sg.g1, 16 * bo + r, g);
 #pragma unroll
-    for (int bi = 0; bi < 4; ++bi) G.dW2[bo][bi] = mfma16x3(aG2, bH1[bi], G.dW2[bo][bi]);
-    G.dW1[bo][0] = mfma16x3(aG1, bX0, G.dW1[bo][0]);
-    G.dW1[bo][1] = mfma16x3(aG1, bX1, G.dW1[bo][1]);
-    G.dW3[bo] = mfma16x3(aG3, bH2[bo], G.dW3[bo]);
+    for (int bi = 0; bi < 4; ++bi) G.dW2[bo][bi] = mfma32(aG2, bH1l[bi], mfma32(aG2, bH1[bi], G.dW2[bo][bi]));
+    G.dW1[bo][0] = mfma32(aG1, bX0, G.dW1[bo][0]);
+    G.dW1[bo][1] = mfma32(aG1, bX1l, mfma32(aG1, bX1, G.dW1[bo][1]));
+    G.dW3[bo] = mfma32(aG3, bH2l[bo], mfma32(aG3, bH2[bo], G.dW3[bo]));
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -628,7 +635,7 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(int S, int per, const uint16_t*
         if (g == 0 && valid) {
           // d = v / |v| with v = mean - centre:  dL/dv = (dL/dd - d (d . dL/dd)) / |v|
           const float dd = d[0] * gd[0] + d[1] * gd[1] + d[2] * gd[2];
-          const float il = 1.0f / len;
+          const float il = __builtin_amdgcn_rcpf(len);
 #pragma unroll
           for (int k = 0; k < 3; ++k) dmean[static_cast<int64_t>(k) * S + s] = cur.m[k] + (gd[k] - d[k] * dd) * il;
         }
