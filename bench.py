@@ -452,6 +452,9 @@ def main():
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-colour timing")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the heavy-workload and learned-colour-workload timings and the decoder quality")
+    ap.add_argument("--extras", default="",
+                    help="comma-separated subset of the extra timings to run: heavy, learned, density, decoder "
+                         "(default: all)")
     ap.add_argument("--compare-plain", action="store_true",
                     help="also time the SH step with the plain and the merged work splits, and with the "
                          "deterministic reduction")
@@ -577,16 +580,19 @@ def main():
             summary(sampled), speedup_vs_exact=round(sh["ms"] / sampled["ms"], 4),
             approximate=True,
             quality=[sampling_quality(torch, gs, scenes, dev, c, coh) for c in (2, 3) for coh in (False, True)])
+    want = set(args.extras.split(",")) if args.extras else {"heavy", "learned", "density", "decoder"}
     if not args.no_extras and cfg == 3:
         extras = {}
         del hw
         torch.cuda.empty_cache()
+    if not args.no_extras and cfg == 3 and "heavy" in want:
         h4 = Harness(torch, gs, scenes, 4, dev, wait_k=args.wait_k)
         r4 = h4.run(h4.step, "heavy workload", 5, 2)
         extras["heavy"] = dict(summary(r4), workload=f"heavy: {h4.scene.n} Gaussians, anisotropic, SH degree 3, "
                                                     "1920x1080, orbit camera 0, L1 loss")
         del h4
         torch.cuda.empty_cache()
+    if not args.no_extras and cfg == 3 and "learned" in want:
         h5 = Harness(torch, gs, scenes, 5, dev, wait_k=args.wait_k)
         r5 = h5.run(h5.step, "learned-colour workload, SH", args.steps, args.warmup)
         from paper_2510_14564_amd.decoder import Decoder
@@ -601,10 +607,13 @@ def main():
             "sh": summary(r5), "decoder": summary(r5m), "speedup_vs_sh": round(r5["ms"] / r5m["ms"], 4)}
         del h5
         torch.cuda.empty_cache()
+    if not args.no_extras and cfg == 3 and "density" in want:
         log("[bench] density control ...")
         extras["density_control"] = [density_timing(torch, gs, scenes, dev, c) for c in (2, 3)]
+    if not args.no_extras and cfg == 3 and "decoder" in want:
         log("[bench] decoder quality (400 distillation epochs, 32 views) ...")
         extras["decoder_quality"] = learned_quality(torch, gs, scenes, dev)
+    if not args.no_extras and cfg == 3:
         result["extra_workloads"] = extras
     if args.hbm_probe:
         nbytes = 2 << 30
