@@ -1027,10 +1027,7 @@ __device__ __forceinline__ void place_entry(int rw, uint32_t e, const uint32_t* 
 // earlier ranks on the tile.  The entry of the tile's last rank in the group
 // also writes the group's count for the tile into delta[t], which one pass
 // over the tiles adds to the positions once every entry of the group is
-// placed.  Chunks go to workgroups through the XCD-aware map, so each XCD
-// takes consecutive chunks: the short runs that neighbouring chunks write into
-// one tile's list then meet in one L2 instead of being written back to HBM in
-// pieces from several.
+// placed.
 // two workgroups per CU (8 waves per SIMD): at most 64 VGPRs
 __global__ __launch_bounds__(kDirectThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_emit_direct(const uint32_t* __restrict__ bounds,
                                                                 const uint32_t* __restrict__ order,
@@ -1048,7 +1045,7 @@ __global__ __launch_bounds__(kDirectThreads) __attribute__((amdgpu_waves_per_eu(
   const int edge = tiles_x + tiles_y;
   uint32_t* const s_pos = reinterpret_cast<uint32_t*>(s_dyn + 4 * edge);
   uint16_t* const s_delta = reinterpret_cast<uint16_t*>(s_pos + ntiles);
-  const int c = xcd_remap(blockIdx.x, gridDim.x), tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int c = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wave_u = __builtin_amdgcn_readfirstlane(wave);
   const uint32_t R0 = bounds[c], R1 = bounds[c + 1];
   if (R0 >= R1) return;
