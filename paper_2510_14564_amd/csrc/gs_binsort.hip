@@ -27,15 +27,26 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
   return (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
 }
 
-// Lanes of this wave whose `digit` (nbits wide) equals ours, among `active`.
+// Lanes of this wave whose `digit` (nbits wide) equals ours, among `active`:
+// per bit, the ballot xor this lane's bit spread over 64 bits marks the lanes
+// that differ in that bit; the peers are the valid lanes marked by none.
+// Unrolled for the full 8-bit digit (every pass of a 32-bit key).
+__device__ __forceinline__ void match_bit(uint32_t digit, int b, uint32_t& lo, uint32_t& hi) {
+  // bit b of the digit spread over 32 bits (0 or all ones)
+  const uint32_t sb = static_cast<uint32_t>(static_cast<int32_t>(digit << (31 - b)) >> 31);
+  const uint64_t m = __ballot(sb != 0u);
+  lo |= static_cast<uint32_t>(m) ^ sb;
+  hi |= static_cast<uint32_t>(m >> 32) ^ sb;
+}
 __device__ __forceinline__ uint64_t match_digit(uint32_t digit, int nbits, bool valid) {
-  uint64_t peers = __ballot(valid);
-  for (int b = 0; b < nbits; ++b) {
-    const bool bit = (digit >> b) & 1u;
-    const uint64_t m = __ballot(bit);
-    peers &= bit ? m : ~m;
+  uint32_t lo = 0u, hi = 0u;
+  if (nbits == 8) {
+#pragma unroll
+    for (int b = 0; b < 8; ++b) match_bit(digit, b, lo, hi);
+  } else {
+    for (int b = 0; b < nbits; ++b) match_bit(digit, b, lo, hi);
   }
-  return peers;
+  return __ballot(valid) & ~((static_cast<uint64_t>(hi) << 32) | lo);
 }
 
 // --------------------------------------------------------------- device scan
