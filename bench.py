@@ -573,11 +573,13 @@ def main():
     if other_splits is not None:
         result["other_work_splits"] = other_splits
     if mlp is not None:
-        result["learned_colour"] = dict(summary(mlp), speedup_vs_sh=round(sh["ms"] / mlp["ms"], 4))
+        result["learned_colour"] = dict(summary(mlp), speedup_vs_sh=round(sh["ms"] / mlp["ms"], 4),
+                                        speedup_vs_sh_p50=round(sh["p50"] / mlp["p50"], 4))
     if sampled is not None:
         log("[bench] colour-hash sampling quality ...")
         result["colour_hash_sampling"] = dict(
             summary(sampled), speedup_vs_exact=round(sh["ms"] / sampled["ms"], 4),
+            speedup_vs_exact_p50=round(sh["p50"] / sampled["p50"], 4),
             approximate=True,
             quality=[sampling_quality(torch, gs, scenes, dev, c, coh) for c in (2, 3) for coh in (False, True)])
     want = set(args.extras.split(",")) if args.extras else {"heavy", "learned", "density", "decoder"}
@@ -604,7 +606,8 @@ def main():
         extras["learned_colour_workload"] = {
             "workload": f"learned colour: {h5.scene.n} Gaussians, 800x800, SH degree 3 vs 16-value BF16 latent + "
                         "32-64-64-3 decoder",
-            "sh": summary(r5), "decoder": summary(r5m), "speedup_vs_sh": round(r5["ms"] / r5m["ms"], 4)}
+            "sh": summary(r5), "decoder": summary(r5m), "speedup_vs_sh": round(r5["ms"] / r5m["ms"], 4),
+            "speedup_vs_sh_p50": round(r5["p50"] / r5m["p50"], 4)}
         del h5
         torch.cuda.empty_cache()
     if not args.no_extras and cfg == 3 and "density" in want:
