@@ -339,7 +339,7 @@ struct FullBwdWs {
 };
 FullBwdWs carve_full_bwd(void* base, const gs_gaussians& g, int64_t k, int ntiles, int deterministic) {
   FullBwdWs f;
-  f.rows = !deterministic && g.colour_mode == 0;
+  f.rows = !deterministic;
   Carver c(base);
   f.g2d = c.take<float>(f.rows ? 0 : static_cast<size_t>(GS_G2D) * static_cast<size_t>(g.n));
   f.ws2d = c.take<char>(render_bwd_workspace(g.n, k, ntiles, deterministic));

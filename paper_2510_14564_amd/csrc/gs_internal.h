@@ -148,7 +148,8 @@ inline size_t batch_item_ints(int64_t k, int64_t ntiles) {
 }
 // Record gradients handed to the projection backward: g2d[9][n] (rows ==
 // false) or the compositing backward's accumulator rows acc[n][kAccStride]
-// before grad_scale (rows == true, SH colour only).  stats (optional) gets
+// before grad_scale (rows == true; with the learned colour the decoder's
+// backward reads its colour gradient from them too).  stats (optional) gets
 // |dL/d(u, v)| added per Gaussian and count += 1 where tiles_touched > 0.
 gs_status launch_project_bwd(const gs_gaussians& g, const DevCam& cam, const int* radius, const float* g2d, bool rows,
                              const uint32_t* tiles_touched, gs_densify_stats* stats, gs_gaussians_grad& grad,
@@ -194,8 +195,11 @@ size_t mlp_bwd_workspace(int64_t S, int per);
 gs_status launch_mlp_bwd(int64_t S, int per, const uint16_t* latents, const float* dirs, const void* packed,
                          const float* dL_drgb, const float* target, float scale, float* dlat, float* dparams,
                          float* loss, void* ws, hipStream_t s);
+// dL/dc from g2d rows 6..8 (g2d[9][n], rows == false) or from entries 6..8
+// of the accumulator rows acc[n][kAccStride] (rows == true; grad_scale is 1
+// for the colour channels).
 gs_status launch_mlp_render_bwd(int64_t n, const uint16_t* latents, const float* means, const int* radius,
-                                const DevCam& cam, const void* packed, const float* g2d, float* dlat,
+                                const DevCam& cam, const void* packed, const float* g2d, bool rows, float* dlat,
                                 float* dmeans, float* dparams, void* ws, hipStream_t s);
 gs_status launch_sh_colour(int64_t S, int per, int64_t n, int deg, const float* sh, const float* dirs, int clamp01,
                            float* out, hipStream_t s);

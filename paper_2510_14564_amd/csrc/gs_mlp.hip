@@ -213,11 +213,15 @@ struct SampleIn {
   bool in;          // s < S (and, MODE 1, the Gaussian is live)
 };
 
+// dL_dc: channel i of sample s at dL_dc[(c0 + i) cs + s ss] -- MODE 0 [S][3]
+// (c0 0, cs 1, ss 3); MODE 1 g2d[9][S] (c0 6, cs S, ss 1) or accumulator rows
+// [S][kAccStride] (c0 6, cs 1, ss kAccStride).
 template <int MODE, bool BWD>
 __device__ __forceinline__ SampleIn load_sample(int64_t s64, int S, int per, int g, const uint16_t* __restrict__ latents,
                                                 const float* __restrict__ dirs, const float* __restrict__ means,
                                                 const int* __restrict__ radius, const float* __restrict__ dL_dc,
-                                                const float* __restrict__ dmean = nullptr) {
+                                                const float* __restrict__ dmean = nullptr, int64_t cs = 1,
+                                                int64_t ss = 3) {
   SampleIn x;
   x.a[0] = 0.f; x.a[1] = 0.f; x.a[2] = 1.f;
   x.c[0] = x.c[1] = x.c[2] = 0.f;
@@ -239,8 +243,7 @@ __device__ __forceinline__ SampleIn load_sample(int64_t s64, int S, int per, int
   if (BWD && g == 0) {
 #pragma unroll
     for (int i = 0; i < kMlpOut; ++i) {
-      if (MODE == 1) x.c[i] = dL_dc[static_cast<int64_t>(6 + i) * S + s];   // g2d rows 6..8
-      else x.c[i] = dL_dc[3 * static_cast<int64_t>(s) + i];                  // [S][3]
+      x.c[i] = dL_dc[(MODE == 1 ? 6 + i : i) * cs + s * ss];
       if (MODE == 1 && dmean && x.in) x.m[i] = dmean[static_cast<int64_t>(i) * S + s];
     }
   }
@@ -555,7 +558,8 @@ __device__ __forceinline__ void mlp_bwd_group(const MlpShared& sh, MlpStage& sg,
 //         distillation loss scale * |c - target|^2 (accumulated into the
 //         partial's last slot).  dlat[S / per][16] is overwritten.
 // MODE 1: sample s = Gaussian s of the projection (per = 1), dL/dc from rows
-//         6..8 of g2d[9][S]; dlat[s] and the direction's share of dL/dmean are
+//         6..8 of g2d[9][S] or entries 6..8 of the accumulator rows (cs, ss:
+//         see load_sample); dlat[s] and the direction's share of dL/dmean are
 //         written for live Gaussians (dmean is added to), zeros elsewhere.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_mlp_bwd(int S, int per, const uint16_t* __restrict__ latents,
@@ -564,7 +568,7 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(int S, int per, const uint16_t*
                                                  const uint4* __restrict__ ops, const float* __restrict__ bias,
                                                  const float* __restrict__ dL_dc, const float* __restrict__ target,
                                                  float scale, float* __restrict__ dlat, float* __restrict__ dmean,
-                                                 float* __restrict__ partial) {
+                                                 float* __restrict__ partial, int64_t cs, int64_t ss) {
   __shared__ MlpShared sh;
   __shared__ MlpStage stage[4];
   load_packed(sh, ops, bias);
@@ -595,7 +599,7 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(int S, int per, const uint16_t*
   // unit's gpl groups in turn; the next group's inputs are loaded ahead
   auto group_of = [&](int unit, int q) { return (static_cast<int64_t>(unit) * gpl + q) * 16 + r; };
   SampleIn cur = load_sample<MODE, true>(group_of(wave_id, 0), wave_id < nunits ? S : 0, per, g, latents, dirs,
-                                         means, radius, cin, dmean);
+                                         means, radius, cin, dmean, cs, ss);
   for (int unit = wave_id; unit < nunits; unit += nwaves) {
     floatx4 zacc = zero;
     for (int q = 0; q < gpl; ++q) {
@@ -603,7 +607,7 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(int S, int per, const uint16_t*
       const int nunit = (q + 1 < gpl) ? unit : unit + nwaves;
       const int nq = (q + 1 < gpl) ? q + 1 : 0;
       const SampleIn nxt = load_sample<MODE, true>(group_of(nunit, nq), nunit < nunits ? S : 0, per, g, latents,
-                                                   dirs, means, radius, cin, dmean);
+                                                   dirs, means, radius, cin, dmean, cs, ss);
       const bool valid = cur.in;
       float d[3], len;
       sample_dir<MODE>(cur, cam, d, len);
@@ -746,19 +750,20 @@ gs_status launch_mlp_bwd(int64_t S, int per, const uint16_t* latents, const floa
   DevCam dummy{};
   { TimedLaunch gs_tl("k_mlp_bwd<0>", s); k_mlp_bwd<0><<<waves / 4, 256, 0, s>>>(static_cast<int>(S), per, latents, dirs, nullptr, nullptr, dummy,
                                          packed_ops(packed), packed_bias(packed), dL_drgb, target, scale, dlat,
-                                         nullptr, static_cast<float*>(ws)); }
+                                         nullptr, static_cast<float*>(ws), 1, 3); }
   gs_status st = check_launch("k_mlp_bwd");
   if (st != GS_OK) return st;
   return reduce_partials(static_cast<float*>(ws), waves, dparams, loss, s);
 }
 
 gs_status launch_mlp_render_bwd(int64_t n, const uint16_t* latents, const float* means, const int* radius,
-                                const DevCam& cam, const void* packed, const float* g2d, float* dlat,
+                                const DevCam& cam, const void* packed, const float* g2d, bool rows, float* dlat,
                                 float* dmeans, float* dparams, void* ws, hipStream_t s) {
   const int waves = mlp_bwd_waves(n, 1);
+  const int64_t cs = rows ? 1 : n, ss = rows ? kAccStride : 1;
   { TimedLaunch gs_tl("k_mlp_bwd<1>", s); k_mlp_bwd<1><<<waves / 4, 256, 0, s>>>(static_cast<int>(n), 1, latents, nullptr, means, radius, cam,
                                          packed_ops(packed), packed_bias(packed), g2d, nullptr, 0.0f, dlat, dmeans,
-                                         static_cast<float*>(ws)); }
+                                         static_cast<float*>(ws), cs, ss); }
   gs_status st = check_launch("k_mlp_render_bwd");
   if (st != GS_OK) return st;
   return reduce_partials(static_cast<float*>(ws), waves, dparams, nullptr, s);

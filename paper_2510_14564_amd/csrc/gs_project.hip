@@ -417,7 +417,6 @@ gs_status launch_project_bwd(const gs_gaussians& g, const DevCam& cam, const int
                              hipStream_t s) {
   const int n = static_cast<int>(g.n);
   if (n == 0) return GS_OK;
-  if (rows && g.colour_mode == 1) return fail(GS_ERR_INVALID_ARG, "projection backward: rows need SH colour");
   const dim3 block(256), grid(static_cast<unsigned>(ceil_div(n, 256)));
   float* sg = stats ? stats->grad_norm_sum : nullptr;
   uint32_t* sc = stats ? stats->visible_count : nullptr;
@@ -430,10 +429,11 @@ gs_status launch_project_bwd(const gs_gaussians& g, const DevCam& cam, const int
     static const char* const kNames[2][4] = {
         {"k_project_bwd<0, false>", "k_project_bwd<1, false>", "k_project_bwd<2, false>", "k_project_bwd<3, false>"},
         {"k_project_bwd<0, true>", "k_project_bwd<1, true>", "k_project_bwd<2, true>", "k_project_bwd<3, true>"}};
-    TimedLaunch gs_tl(g.colour_mode == 1 ? "k_project_bwd<-1, false>"
+    TimedLaunch gs_tl(g.colour_mode == 1 ? (rows ? "k_project_bwd<-1, true>" : "k_project_bwd<-1, false>")
                                          : kNames[rows ? 1 : 0][std::min(std::max(g.sh_degree, 0), 3)], s);
     if (g.colour_mode == 1) {
-      GS_PB(-1, false);
+      if (rows) GS_PB(-1, true);
+      else GS_PB(-1, false);
     } else if (rows) {
       switch (g.sh_degree) {
         case 0: GS_PB(0, true); break;
@@ -453,7 +453,8 @@ gs_status launch_project_bwd(const gs_gaussians& g, const DevCam& cam, const int
 #undef GS_PB
   gs_status st = check_launch("k_project_bwd");
   if (st != GS_OK || g.colour_mode != 1) return st;
-  return launch_mlp_render_bwd(n, g.latents, g.means, radius, cam, g.mlp, g2d, gr.latents, gr.means, gr.mlp, ws, s);
+  return launch_mlp_render_bwd(n, g.latents, g.means, radius, cam, g.mlp, g2d, rows, gr.latents, gr.means, gr.mlp, ws,
+                               s);
 }
 
 }  // namespace gs
