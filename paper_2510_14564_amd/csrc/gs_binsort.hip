@@ -829,7 +829,7 @@ __global__ __launch_bounds__(256) void k_ranges(int ntiles, const uint32_t* __re
 constexpr int kDirectChunks = 512;      // chunks at most
 constexpr int64_t kDirectMinEntries = 4096;
 constexpr size_t kLdsBudget = 65536;    // bytes of LDS per workgroup
-constexpr size_t kEmitStaticLds = 4608; // k_emit_direct's fixed arrays, rounded up
+constexpr size_t kEmitStaticLds = 9728; // k_emit_direct's fixed arrays, rounded up
 
 // LDS of the direct emission: masks col[4][tiles_x], row[4][tiles_y] (u64),
 // then pos[ntiles] (u32) and delta[ntiles] (u16).
@@ -971,29 +971,63 @@ __global__ __launch_bounds__(1024) void k_tile_starts(int ntiles, const uint32_t
   }
 }
 
+// Inclusive max over the 64 lanes on DPP (row shifts, then the row broadcasts
+// of lanes 15 and 31); lanes shifted in from outside a row read 0.
+__device__ __forceinline__ uint32_t wave_incl_max(uint32_t x) {
+  x = max(x, static_cast<uint32_t>(dpp_i32<0x111, 0xF>(static_cast<int>(x))));   // row_shr:1
+  x = max(x, static_cast<uint32_t>(dpp_i32<0x112, 0xF>(static_cast<int>(x))));   // row_shr:2
+  x = max(x, static_cast<uint32_t>(dpp_i32<0x114, 0xF>(static_cast<int>(x))));   // row_shr:4
+  x = max(x, static_cast<uint32_t>(dpp_i32<0x118, 0xF>(static_cast<int>(x))));   // row_shr:8
+  x = max(x, static_cast<uint32_t>(dpp_i32<0x142, 0xA>(static_cast<int>(x))));   // row_bcast:15 into rows 1, 3
+  x = max(x, static_cast<uint32_t>(dpp_i32<0x143, 0xC>(static_cast<int>(x))));   // row_bcast:31 into rows 2, 3
+  return x;
+}
+
+// Owner of entry e0 + lane among the ranks of one rank-wave (offsets
+// pre[0..64]): the last rank with a nonzero count whose offset is <= the
+// entry.  Lane k looks at rank k: the run's first entry belongs to the
+// highest such rank at or before e0 (a ballot), and each rank starting inside
+// the run marks its first entry's lane in the wave's 64-word scratch; an
+// inclusive max over the lanes then hands every entry its rank -- three LDS
+// accesses and a DPP scan instead of a six-step dependent binary search.
+__device__ __forceinline__ int run_owner(const uint32_t* __restrict__ pre, uint32_t e0, uint32_t* __restrict__ mark,
+                                         int lane) {
+  const uint32_t pk = pre[lane], pk1 = pre[lane + 1];
+  const bool nz = pk1 > pk;
+  const uint64_t before = __ballot(nz && pk <= e0);   // nonzero: entry e0 exists
+  const uint32_t k0 = 63u - static_cast<uint32_t>(__clzll(before));
+  mark[lane] = 0u;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  if (nz && pk > e0 && pk < e0 + 64u) mark[pk - e0] = static_cast<uint32_t>(lane) + 1u;
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  uint32_t v = mark[lane];
+  if (lane == 0) v = k0 + 1u;
+  return static_cast<int>(wave_incl_max(v)) - 1;
+}
+
 // Placement of entry e of rank-wave rw (uniform over the wave) of the
-// current group (offsets pre[0..64], total pre[64]): the entry goes to its
-// tile's position at the group start plus the group's earlier ranks on that
-// tile; the group's last entry on a tile stores the group's count there.
-__device__ __forceinline__ void place_entry(int rw, uint32_t e, const uint32_t* __restrict__ pre,
-                                            const uint2* __restrict__ s_rect, const uint32_t* __restrict__ s_gid,
+// current group (offsets pre[0..64], total pre[64]), owned by rank lo of the
+// rank-wave: the entry goes to its tile's position at the group start plus
+// the group's earlier ranks on that tile; the group's last entry on a tile
+// stores the group's count there.
+__device__ __forceinline__ void place_entry(int rw, uint32_t e, int lo, const uint32_t* __restrict__ pre,
+                                            const uint2* __restrict__ s_rect, const uint32_t* __restrict__ s_magic,
+                                            const uint32_t* __restrict__ s_gid,
                                             const unsigned long long* __restrict__ s_dyn,
                                             const uint32_t* __restrict__ s_pos, uint16_t* __restrict__ s_delta,
                                             int edge, int tiles_x, uint32_t* __restrict__ point_list,
                                             uint32_t capacity) {
   if (e >= pre[64]) return;
-  int lo = 0;
-#pragma unroll
-  for (int step = 32; step > 0; step >>= 1)
-    lo += (pre[lo + step] <= e) ? step : 0;   // the last rank with offset <= e
   const int i = rw * 64 + lo;
   const uint2 q = s_rect[i];
   const uint32_t j = e - pre[lo];
   const uint32_t qx0 = q.x & 0xFFFFu, w = (q.x >> 16) - qx0;
-  // row = j / w without an integer division (float quotient within one)
-  uint32_t rr = static_cast<uint32_t>(static_cast<float>(j) * __builtin_amdgcn_rcpf(static_cast<float>(w)));
-  const uint32_t prod = rr * w;
-  rr = rr + static_cast<uint32_t>(prod + w <= j) - static_cast<uint32_t>(prod > j);
+  // row = j / w as a multiply-high by the rank's magic ceil(2^32 / w) (0 for
+  // w = 1): exact for j, w < 2^16, which the tables' LDS bound guarantees
+  const uint32_t mg = s_magic[i];
+  const uint32_t rr = __umulhi(j, mg) + (mg == 0u ? j : 0u);
   const int tx = static_cast<int>(qx0 + (j - rr * w));
   const int ty = static_cast<int>((q.y & 0xFFFFu) + rr);
   const int t = ty * tiles_x + tx;
@@ -1052,6 +1086,8 @@ __global__ __launch_bounds__(kDirectThreads) __attribute__((amdgpu_waves_per_eu(
   __shared__ uint32_t s_pre[4][65];   // per rank-wave: exclusive entry offsets, then the total
   __shared__ uint32_t s_gid[256];
   __shared__ uint2 s_rect[256];
+  __shared__ uint32_t s_magic[256];   // ceil(2^32 / rectangle width), 0 for width 1
+  __shared__ uint32_t s_mark[kDirectWaves][64];   // per wave: run_owner's scratch
   const int ntiles = tiles_x * tiles_y;
   const int edge = tiles_x + tiles_y;
   uint32_t* const s_pos = reinterpret_cast<uint32_t*>(s_dyn + 4 * edge);
@@ -1074,6 +1110,8 @@ __global__ __launch_bounds__(kDirectThreads) __attribute__((amdgpu_waves_per_eu(
       const uint32_t cnt = rect_count(rc);
       s_rect[tid] = rc;
       s_gid[tid] = valid ? order[r] : 0u;
+      const uint32_t wd = (rc.x >> 16) - (rc.x & 0xFFFFu);
+      s_magic[tid] = wd >= 2u ? 0xFFFFFFFFu / wd + 1u : 0u;
       uint32_t incl = cnt;
       for (int d = 1; d < 64; d <<= 1) {
         const uint32_t t = __shfl_up(incl, d, 64);
@@ -1128,8 +1166,10 @@ __global__ __launch_bounds__(kDirectThreads) __attribute__((amdgpu_waves_per_eu(
       for (uint32_t run = static_cast<uint32_t>(wave_u); run < nrun; run += kDirectWaves) {
         const int rw = run < c1 ? 0 : (run < c2 ? 1 : (run < c3 ? 2 : 3));
         const uint32_t first = run < c1 ? 0u : (run < c2 ? c1 : (run < c3 ? c2 : c3));
-        place_entry(rw, (run - first) * 64u + lane, s_pre[rw], s_rect, s_gid, s_dyn, s_pos, s_delta, edge,
-                    tiles_x, point_list, capacity);
+        const uint32_t e0 = (run - first) * 64u;
+        const int lo = run_owner(s_pre[rw], e0, s_mark[wave_u], lane);
+        place_entry(rw, e0 + lane, lo, s_pre[rw], s_rect, s_magic, s_gid, s_dyn, s_pos, s_delta, edge, tiles_x,
+                    point_list, capacity);
       }
     }
     __syncthreads();
