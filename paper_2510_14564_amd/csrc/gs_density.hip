@@ -64,6 +64,16 @@ __device__ __forceinline__ float dc_d2(const float4& q, const float4& p) {
   return __fadd_rn(s, __fmul_rn(dz, dz));
 }
 
+// The far search splits each remaining query's scan over every point into S
+// ranges, one workgroup each, while count * S fits kFarSlots partial lists
+// (S = min(64, kFarSlots / count)); beyond that, one workgroup per query
+// scans all points and writes the result itself.
+constexpr uint32_t kFarSlots = 16384;
+constexpr uint32_t kFarSplitMax = 64;
+__host__ __device__ __forceinline__ uint32_t far_splits(uint32_t count) {
+  return count == 0 || count > kFarSlots ? 1u : (kFarSlots / count < kFarSplitMax ? kFarSlots / count : kFarSplitMax);
+}
+
 struct DcWs {
   uint32_t* count;      // [T] points per bucket, then their exclusive prefix (bucket starts)
   uint32_t* fill;       // [T]
@@ -86,6 +96,8 @@ struct DcWs {
   uint32_t* far_n;
   uint32_t* far2;       // [n] queries the wave kernel left, [1] their count
   uint32_t* far2_n;
+  float* cand_d;        // [kFarSlots][8] partial k-nearest lists of the split far search
+  int32_t* cand_i;
   size_t bytes;
 };
 
@@ -121,6 +133,8 @@ static DcWs carve_dc(void* base, int64_t n) {
   w.far_n = c.take<uint32_t>(1);
   w.far2 = c.take<uint32_t>(nn);
   w.far2_n = c.take<uint32_t>(1);
+  w.cand_d = c.take<float>(static_cast<size_t>(kFarSlots) * 8);
+  w.cand_i = c.take<int32_t>(static_cast<size_t>(kFarSlots) * 8);
   w.bytes = c.off;
   return w;
 }
@@ -430,25 +444,34 @@ __global__ __launch_bounds__(256) void k_dc_knn_wave(int n, const DcPoint* __res
   }
 }
 
-// The queries the ring search left: one workgroup per query at a time scans
-// every point (each thread a strided share, its own top-k), then the 256
-// lists are merged by thread 0 in LDS.
+// The queries the ring search left: a workgroup per (query, range of points)
+// scans its range (each thread a strided share, its own top-k) and thread 0
+// merges the 256 lists in LDS; with S > 1 ranges the lists go to cand_d /
+// cand_i for k_dc_knn_far_merge, with one range the result is written here.
+// Splitting keeps a few isolated queries from each holding one workgroup
+// over every point (at 1M Gaussians, 44 queries took 1.7 ms that way).
 template <int K>
 __global__ __launch_bounds__(256) void k_dc_knn_far(int n, const DcPoint* __restrict__ pts,
                                                     const uint32_t* __restrict__ far, const uint32_t* __restrict__ far_n,
                                                     int32_t* __restrict__ nn, float* __restrict__ dnn,
-                                                    float* __restrict__ dbar, double* __restrict__ dsum) {
+                                                    float* __restrict__ dbar, double* __restrict__ dsum,
+                                                    float* __restrict__ cand_d, int32_t* __restrict__ cand_i) {
   __shared__ float s_d[256 * K];
   __shared__ int s_i[256 * K];
   const uint32_t count = *far_n;
-  for (uint32_t f = blockIdx.x; f < count; f += gridDim.x) {
+  const uint32_t S = far_splits(count);
+  const uint32_t span = (static_cast<uint32_t>(n) + S - 1u) / S;
+  // items (query f, range r): points [r span, (r + 1) span)
+  for (uint32_t it = blockIdx.x; it < count * S; it += gridDim.x) {
+    const uint32_t f = it / S, r = it - f * S;
     const DcPoint q = pts[far[f]];
     const int qi = __float_as_int(q.p.w);
     float bd[K];
     int bi[K];
 #pragma unroll
     for (int m = 0; m < K; ++m) { bd[m] = 3.0e38f; bi[m] = 0x7fffffff; }
-    for (int p = threadIdx.x; p < n; p += 256) {
+    const int p0 = static_cast<int>(r * span), p1 = min(n, static_cast<int>((r + 1u) * span));
+    for (int p = p0 + threadIdx.x; p < p1; p += 256) {
       const DcPoint o = pts[p];
       const int oi = __float_as_int(o.p.w);
       if (oi != qi) dc_insert<K>(bd, bi, dc_d2(q.p, o.p), oi);
@@ -462,6 +485,63 @@ __global__ __launch_bounds__(256) void k_dc_knn_far(int n, const DcPoint* __rest
     if (threadIdx.x == 0) {
       for (int t = 1; t < 256; ++t)
         for (int m = 0; m < K; ++m) dc_insert<K>(bd, bi, s_d[t * K + m], s_i[t * K + m]);
+      if (S == 1) {
+        double a1 = 0.0, a2 = 0.0;
+        dc_finish<K>(bd, bi, min(K, n - 1), qi, nn, dnn, dbar, a1, a2);
+        if (a1 != 0.0 || a2 != 0.0) {
+          unsafeAtomicAdd(&dsum[0], a1);
+          unsafeAtomicAdd(&dsum[1], a2);
+        }
+      } else {
+#pragma unroll
+        for (int m = 0; m < K; ++m) {
+          cand_d[static_cast<size_t>(it) * 8 + m] = bd[m];
+          cand_i[static_cast<size_t>(it) * 8 + m] = bi[m];
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Merge of the split far search: query f's K nearest among its S ranges'
+// lists, in (distance, index) order as every search keeps them.  One wave per
+// query: lane r takes range r's list (r < S <= 64), then a butterfly over the
+// lanes merges the lists pairwise (exact: the order is total).
+template <int K>
+__global__ __launch_bounds__(64) void k_dc_knn_far_merge(int n, const DcPoint* __restrict__ pts,
+                                                         const uint32_t* __restrict__ far,
+                                                         const uint32_t* __restrict__ far_n, int32_t* __restrict__ nn,
+                                                         float* __restrict__ dnn, float* __restrict__ dbar,
+                                                         double* __restrict__ dsum, const float* __restrict__ cand_d,
+                                                         const int32_t* __restrict__ cand_i) {
+  const uint32_t count = *far_n;
+  const uint32_t S = far_splits(count);
+  if (S == 1u) return;
+  const uint32_t lane = threadIdx.x;
+  for (uint32_t f = blockIdx.x; f < count; f += gridDim.x) {
+    float bd[K];
+    int bi[K];
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+      const size_t o = (static_cast<size_t>(f) * S + lane) * 8 + m;
+      bd[m] = lane < S ? cand_d[o] : 3.0e38f;
+      bi[m] = lane < S ? cand_i[o] : 0x7fffffff;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      float od[K];
+      int oi[K];
+#pragma unroll
+      for (int m = 0; m < K; ++m) {
+        od[m] = __shfl_xor(bd[m], off, 64);
+        oi[m] = __shfl_xor(bi[m], off, 64);
+      }
+#pragma unroll
+      for (int m = 0; m < K; ++m) dc_insert<K>(bd, bi, od[m], oi[m]);
+    }
+    if (lane == 0) {
+      const int qi = __float_as_int(pts[far[f]].p.w);
       double a1 = 0.0, a2 = 0.0;
       dc_finish<K>(bd, bi, min(K, n - 1), qi, nn, dnn, dbar, a1, a2);
       if (a1 != 0.0 || a2 != 0.0) {
@@ -469,7 +549,6 @@ __global__ __launch_bounds__(256) void k_dc_knn_far(int n, const DcPoint* __rest
         unsafeAtomicAdd(&dsum[1], a2);
       }
     }
-    __syncthreads();
   }
 }
 
@@ -619,7 +698,11 @@ gs_status launch_density_control(const gs_gaussians& g, const gs_density_params&
       k_dc_knn_wave<K><<<2048, 256, 0, s>>>(n, w.pts, w.count, T, h, w.far, w.far_n, w.far2, w.far2_n, w.nn,      \
                                             w.dnn, w.dbar, w.dsum); }                                             \
     { TimedLaunch t("k_dc_knn_far<" #K ">", s);                                                                 \
-      k_dc_knn_far<K><<<1024, 256, 0, s>>>(n, w.pts, w.far2, w.far2_n, w.nn, w.dnn, w.dbar, w.dsum); }           \
+      k_dc_knn_far<K><<<1024, 256, 0, s>>>(n, w.pts, w.far2, w.far2_n, w.nn, w.dnn, w.dbar, w.dsum, w.cand_d,     \
+                                           w.cand_i); }                                                          \
+    { TimedLaunch t("k_dc_knn_far_merge<" #K ">", s);                                                           \
+      k_dc_knn_far_merge<K><<<256, 64, 0, s>>>(n, w.pts, w.far2, w.far2_n, w.nn, w.dnn, w.dbar, w.dsum, w.cand_d,  \
+                                              w.cand_i); }                                                       \
   }
     switch (prm.knn) {
       case 1: GS_DC_KNN(1); break;

@@ -34,6 +34,9 @@ def test_every_declared_symbol_is_exported(gs):
 
 def test_version_and_empty_error(gs):
     assert "gfx950" in gs.version()
+    # every entry point clears the error message first (an earlier test in
+    # the same process may have left one)
+    assert gs.mlp_bwd_workspace(16, 1) > 0
     assert gs.last_error() == ""
 
 
