@@ -58,10 +58,17 @@ def _oracle_prm(d):
                      f(d["gamma"])])
 
 
-@pytest.mark.parametrize("case", ["skewed20k", "tiny", "skewed20k_k5"])
+@pytest.mark.parametrize("case", ["skewed20k", "tiny", "skewed20k_k5", "far_split", "far_whole"])
 def test_density_control_matches_oracle(gs, case):
     if case == "tiny":
         scene, r, kw = scenes.config_scene(1), scenes.DENSITY_RADIUS[1], {}
+    elif case.startswith("far"):
+        # a radius far below the spacing of uniform points: every query is
+        # still open after eight rings of cells and goes to the far search --
+        # split over point ranges (3,000 queries) or one workgroup per query
+        # over every point (20,000 queries, more than the split's 16,384 slots)
+        n = 3000 if case == "far_split" else 20000
+        scene, r, kw = scenes.uniform_scene(n, 91, sh_degree=1), 0.002, {}
     else:
         scene = scenes.skewed_scene(20000, 2077, n_clusters=16, log_scale_mean=-4.0, sh_degree=2)
         r, kw = 0.04, ({"knn": 5, "alpha": 0.5, "gamma": 0.5} if case.endswith("k5") else {})
