@@ -166,9 +166,9 @@ gs_status gs_bin_sort(int64_t n, const gs_projected* proj, const gs_camera* cam,
  * caller grows the buffers and redoes the frame.  Until it knows K the caller
  * passes `capacity` as k to gs_render_ckpt_floats, gs_render_fwd,
  * gs_render_bwd_workspace, gs_render_bwd and their _2d forms (an upper bound serves every
- * layout and launch there).  Only for frames whose per-chunk tables fit in
- * LDS (tiles_x + 1)(tiles_y + 1) * 4 <= 64 KiB and the emission's tables
- * too; larger frames return GS_ERR_UNSUPPORTED before any device work.
+ * layout and launch there).  Only for frames of at most 16384 tiles (the
+ * direct emission; gs_bin_sort takes a radix tile sort beyond); larger frames
+ * return GS_ERR_UNSUPPORTED before any device work.
  * Other errors as gs_bin_sort. */
 gs_status gs_bin_sort_async(int64_t n, const gs_projected* proj, const gs_camera* cam, void* ws, size_t ws_bytes,
                             uint32_t* point_list, int64_t capacity, uint32_t* ranges, uint64_t* k_dev,

@@ -7,11 +7,15 @@
 // K entries), the path
 //   1. sorts the N Gaussians by depth bits with a stable LSD radix sort that
 //      starts from index order, which yields (depth bits, index) order;
-//   2. emits every Gaussian's tiles in that rank order at the exclusive prefix
-//      sum of its tile counts;
-//   3. stably sorts the K entries by tile id (ceil(log2 T) bits, 1-2 passes).
-// Stability makes step 3 keep the (depth, index) order inside each tile, so
-// the result equals the full sort bit for bit.
+//   2. places every (tile, Gaussian) entry directly at its final position,
+//      counting for each tile the earlier depth ranks that cover it (the
+//      direct emission below, in two levels: 8 x 8-tile super tiles, then
+//      tiles); or, for frames of more tiles than that handles,
+//   2'. emits every Gaussian's tiles in rank order at the exclusive prefix
+//      sum of its tile counts and stably sorts the K entries by tile id
+//      (ceil(log2 T) bits, 1-2 passes).
+// Both keep the (depth, index) order inside each tile, so the result equals
+// the full sort bit for bit.
 #include "gs_internal.h"
 
 namespace gs {
@@ -384,6 +388,15 @@ __device__ __forceinline__ uint32_t rect_count(uint2 rc) {
   return ((rc.x >> 16) - (rc.x & 0xFFFFu)) * ((rc.y >> 16) - (rc.y & 0xFFFFu));
 }
 
+// The rectangle, in the same packing, of the blocks of 2^shift x 2^shift
+// tiles that a tile rectangle touches (empty stays empty; shift 0: itself).
+__device__ __forceinline__ uint2 rect_at(uint2 rc, int shift) {
+  const uint32_t add = (1u << shift) - 1u;
+  const uint32_t x0 = (rc.x & 0xFFFFu) >> shift, xe = ((rc.x >> 16) + add) >> shift;
+  const uint32_t y0 = (rc.y & 0xFFFFu) >> shift, ye = ((rc.y >> 16) + add) >> shift;
+  return make_uint2(x0 | (xe << 16), y0 | (ye << 16));
+}
+
 // ------------------------------------------------------------ onesweep sort
 // Stable LSD radix sort of (key, value) pairs in passes of up to 8 bits, one
 // sweep per pass:
@@ -470,7 +483,7 @@ __global__ __launch_bounds__(kRsThreads) void k_os_scatter(const uint32_t* __res
                                                            uint32_t* __restrict__ vals_final,
                                                            const uint2* __restrict__ rect,
                                                            uint2* __restrict__ rect_out,
-                                                           uint32_t* __restrict__ cnt_out) {
+                                                           uint32_t* __restrict__ cnt_out, int cshift) {
   constexpr int CHUNK = kRsThreads * ITEMS;
   constexpr int PER_WAVE = CHUNK / 4;
   __shared__ uint32_t s_vid, s_whole;
@@ -530,7 +543,7 @@ __global__ __launch_bounds__(kRsThreads) void k_os_scatter(const uint32_t* __res
       if (rect) {
         const uint2 rc = rect[val];
         rect_out[g] = rc;
-        cnt_out[g] = rect_count(rc);
+        cnt_out[g] = rect_count(rect_at(rc, cshift));
       }
     } else {
       keys_out[g] = key;
@@ -645,7 +658,7 @@ __global__ __launch_bounds__(kRsThreads) void k_os_scatter(const uint32_t* __res
       if (tid + j * kRsThreads < nvalid) {
         vals_final[g[j]] = val[j];
         rect_out[g[j]] = rc[j];
-        cnt_out[g[j]] = rect_count(rc[j]);
+        cnt_out[g[j]] = rect_count(rect_at(rc[j], cshift));
       }
     }
     return;
@@ -672,14 +685,15 @@ static size_t os_state_words(int64_t count, int items, int passes) {
 
 // Sorts `count` pairs over key bits [0, total_bits).  Input in (ka, va),
 // which the passes use as ping-pong buffers with (kb, vb); the values in
-// sorted order end in vals_final (with rect: each value's rectangle and tile
-// count in rect_out, cnt_out).
+// sorted order end in vals_final (with rect: each value's rectangle in
+// rect_out and in cnt_out the count of the blocks of 2^cshift x 2^cshift
+// tiles it touches -- its tile count for cshift 0).
 // w.ghist must be zero on entry (k_depth_keys clears both sorts' counts).
 template <int ITEMS>
 static gs_status onesweep_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int64_t count,
                                      int total_bits, OsWs w, hipStream_t s, uint32_t* vals_final,
                                      const uint2* rect = nullptr, uint2* rect_out = nullptr,
-                                     uint32_t* cnt_out = nullptr) {
+                                     uint32_t* cnt_out = nullptr, int cshift = 0) {
   constexpr int CHUNK = kRsThreads * ITEMS;
   const int passes = (total_bits + 7) / 8;
   if (count <= 0) return GS_OK;
@@ -692,7 +706,8 @@ static gs_status onesweep_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, u
   for (int p = 0; p < passes; ++p) {
     { TimedLaunch gs_tl("k_os_scatter", s); k_os_scatter<ITEMS><<<nblocks, kRsThreads, 0, s>>>(ka, va, kb, vb, count, p, total_bits, w.ghist,
                                                        w.state + static_cast<size_t>(p) * nblocks * 256,
-                                                       w.counters + p, w.err, vals_final, rect, rect_out, cnt_out); }
+                                                       w.counters + p, w.err, vals_final, rect, rect_out, cnt_out,
+                                                       cshift); }
     if ((st = check_launch("k_os_scatter")) != GS_OK) return st;
     uint32_t* t = ka; ka = kb; kb = t;
     t = va; va = vb; vb = t;
@@ -808,44 +823,77 @@ __global__ __launch_bounds__(256) void k_ranges(int ntiles, const uint32_t* __re
 
 // ----------------------------------------------------------- direct emission
 // The tile sort without sorting.  After the depth sort the entries of tile t
-// are, in order, the depth ranks whose rectangle contains t.  The ranks are
-// cut into C chunks of about E entries each (chunk c = ranks [R_c, R_c+1)).
-//  1. k_chunk_count: per chunk, the entry count of every tile, from a 2D
-//     difference array of the chunk's rectangles in LDS (four LDS atomics per
-//     Gaussian, then prefix sums along rows and columns) -- table[c][t].
-//  2. k_chunk_colscan: per tile, the exclusive prefix over chunks (in place)
-//     and the tile's total; k_tile_starts: exclusive prefix of the totals
-//     over tiles, which gives the ranges.
-//  3. k_emit_direct: one workgroup per chunk walks its ranks 256 at a time.
-//     Rank 64 w + l of a group comes before rank 64 w' + l' on a tile that
-//     both rectangles contain iff (w, l) < (w', l'); with per-wave 64-bit
+// are, in order, the depth ranks whose rectangle contains t.  Two levels,
+// with super tiles of 8 x 8 tiles.
+// Coarse: the ranks are cut into C chunks of about E coarse entries each
+// (chunk c = ranks [R_c, R_c+1); a rank has one coarse entry per super tile
+// its rectangle touches).
+//  1. k_chunk_count: per chunk, the coarse entries of every super tile, from
+//     a 2D difference array of the chunk's super-tile rectangles in LDS (four
+//     LDS atomics per Gaussian, then prefix sums along rows and columns) --
+//     table[c][s]; it also adds up the tile counts (K).
+//  2. k_chunk_colscan: per super tile, the exclusive prefix over chunks (in
+//     place) and the total; k_coarse_parts: the super tiles' starts in the
+//     coarse list and the cut of each super tile's run into parts of at most
+//     kPart entries (numbered over the super tiles in turn).
+//  3. k_emit_coarse: one workgroup per chunk walks its ranks 256 at a time.
+//     Rank 64 w + l of a group comes before rank 64 w' + l' on a super tile
+//     that both rectangles contain iff (w, l) < (w', l'); with per-wave 64-bit
 //     masks col[w][x] (lanes whose rectangle spans column x) and row[w][y],
-//     the number of the group's ranks before rank 64 w + l on tile (tx, ty)
-//     is sum_{w' < w} popc(col[w'][tx] & row[w'][ty]) + popc(col[w][tx] &
-//     row[w][ty] & lanes below l).  So each entry computes its final
-//     position independently from the tile's position at the group start.
+//     the number of the group's ranks before rank 64 w + l on (x, y) is
+//     sum_{w' < w} popc(col[w'][x] & row[w'][y]) + popc(col[w][x] & row[w][y]
+//     & lanes below l).  So each entry computes its final position from the
+//     super tile's position at the group start.  A coarse entry holds the
+//     Gaussian and its rectangle within the super tile.
+// Fine: per part (a run of one super tile's coarse entries, in rank order),
+//  4. k_fine_count: the entries of each of the super tile's 64 tiles;
+//     k_fine_scan: per super tile, their exclusive prefix over its parts and
+//     the tile totals; k_tile_starts: the tiles' starts (the ranges).
+//  5. k_fine_emit: a wave takes 64 coarse entries, one per lane.  The entries
+//     covering one of the 64 tiles are the 64-bit mask col[x] & row[y] of the
+//     wave, so the tile's entries go out in one store: lane l at the tile's
+//     position plus the count of the mask's lanes below l.  The waves of a
+//     workgroup take consecutive runs of 64 and offset each tile by the
+//     earlier waves' counts.
+// A tile's stores are consecutive addresses from one workgroup, so a line
+// fills in L2 before it leaves; entries written straight from the chunks to
+// the tiles land as four-byte pieces scattered over the whole list, and lines
+// leave L2 partly written, several times over.
 // Same result as a stable sort by tile of the rank-ordered emission, i.e. the
-// order (tile, depth bits, index).  Used while the per-chunk tables fit in LDS.
-constexpr int kDirectChunks = 512;      // chunks at most
+// order (tile, depth bits, index).  Used for frames of at most
+// kDirectMaxTiles tiles.
+constexpr int kSuperShift = 3;            // super tiles of 8 x 8 tiles
+constexpr int kSuper = 1 << kSuperShift;
+constexpr int kDirectChunks = 512;        // chunks at most
 constexpr int64_t kDirectMinEntries = 4096;
-constexpr size_t kLdsBudget = 65536;    // bytes of LDS per workgroup
-constexpr size_t kEmitStaticLds = 9728; // k_emit_direct's fixed arrays, rounded up
+constexpr size_t kLdsBudget = 65536;      // bytes of LDS per workgroup
+constexpr size_t kEmitStaticLds = 11776;  // k_emit_coarse's fixed arrays, rounded up
+constexpr int kPart = 1024;               // coarse entries per part of the fine passes
+constexpr int kFineThreads = 256;
+constexpr int kFineWaves = kFineThreads / 64;
+constexpr int kPartSteps = kPart / kFineThreads;
+constexpr int kFineGrid = 2048;           // workgroups of the fine passes at most (each loops over parts)
+constexpr int kDirectMaxTiles = 16384;    // tiles at most (one workgroup writes the tile starts)
 
-// LDS of the direct emission: masks col[4][tiles_x], row[4][tiles_y] (u64),
-// then pos[ntiles] (u32) and delta[ntiles] (u16).
-static size_t emit_dyn_lds(int tiles_x, int tiles_y) {
-  const size_t nt = static_cast<size_t>(tiles_x) * tiles_y;
-  return 32 * static_cast<size_t>(tiles_x + tiles_y) + 4 * nt + 2 * ((nt + 1) / 2 * 2);
+static int super_dim(int tiles) { return (tiles + kSuper - 1) >> kSuperShift; }
+
+// LDS of the coarse emission over an sx x sy grid of super tiles: masks
+// col[4][sx], row[4][sy] (u64), then pos[sx sy] (u32) and delta[sx sy] (u16).
+static size_t emit_dyn_lds(int sx, int sy) {
+  const size_t nt = static_cast<size_t>(sx) * sy;
+  return 32 * static_cast<size_t>(sx + sy) + 4 * nt + 2 * ((nt + 1) / 2 * 2);
 }
-constexpr int kStartRegs = 16;   // tiles per thread of k_tile_starts (1024 threads)
 static bool direct_ok(int tiles_x, int tiles_y) {
-  return 4 * static_cast<size_t>(tiles_x + 1) * (tiles_y + 1) <= kLdsBudget &&
-         static_cast<size_t>(tiles_x) * tiles_y <= static_cast<size_t>(kStartRegs) * 1024 &&
-         emit_dyn_lds(tiles_x, tiles_y) + kEmitStaticLds <= kLdsBudget;
+  const int sx = super_dim(tiles_x), sy = super_dim(tiles_y);
+  return static_cast<size_t>(tiles_x) * tiles_y <= static_cast<size_t>(kDirectMaxTiles) &&
+         4 * static_cast<size_t>(sx + 1) * (sy + 1) <= kLdsBudget &&
+         emit_dyn_lds(sx, sy) + kEmitStaticLds <= kLdsBudget;
 }
 static int64_t direct_max_chunks(int64_t cap) {
   return std::max<int64_t>(1, std::min<int64_t>(kDirectChunks, ceil_div(std::max<int64_t>(cap, 1), kDirectMinEntries)));
 }
+// parts at most: every super tile's run of at most `cap` coarse entries in total
+static int64_t direct_max_parts(int64_t cap, int ns) { return ceil_div(std::max<int64_t>(cap, 1), kPart) + ns; }
 
 // In-place inclusive prefix sums of `len` ints at p[0], p[stride], ... by one wave.
 __device__ __forceinline__ void wave_prefix_lds(int* p, int len, int stride, int lane) {
@@ -861,39 +909,54 @@ __device__ __forceinline__ void wave_prefix_lds(int* p, int len, int stride, int
 constexpr int kDirectThreads = 1024;
 constexpr int kDirectWaves = kDirectThreads / 64;
 
+// Per chunk: table[c][s] over the sx x sy super tiles, and the chunk's tile
+// counts added to *kfine.
 __global__ __launch_bounds__(kDirectThreads) void k_chunk_count(const uint32_t* __restrict__ bounds,
-                                                                const uint2* __restrict__ rect_rank, int tiles_x,
-                                                                int tiles_y, uint32_t* __restrict__ table) {
-  extern __shared__ int s_diff[];   // (tiles_y + 1) rows of (tiles_x + 1)
+                                                                const uint2* __restrict__ rect_rank, int sx, int sy,
+                                                                uint32_t* __restrict__ table,
+                                                                unsigned long long* __restrict__ kfine) {
+  extern __shared__ int s_diff[];   // (sy + 1) rows of (sx + 1)
+  __shared__ unsigned long long s_k[kDirectWaves];
   const int c = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int pitch = tiles_x + 1, cells = pitch * (tiles_y + 1);
+  const int pitch = sx + 1, cells = pitch * (sy + 1);
   for (int i = tid; i < cells; i += kDirectThreads) s_diff[i] = 0;
   __syncthreads();
   const uint32_t r1 = bounds[c + 1];
+  unsigned long long fine = 0;
   for (uint32_t r = bounds[c] + tid; r < r1; r += kDirectThreads) {
     const uint2 rc = rect_rank[r];
-    if (rect_count(rc) == 0) continue;
-    const int x0 = static_cast<int>(rc.x & 0xFFFFu), xe = static_cast<int>(rc.x >> 16);
-    const int y0 = static_cast<int>(rc.y & 0xFFFFu), ye = static_cast<int>(rc.y >> 16);
+    fine += rect_count(rc);
+    const uint2 sr = rect_at(rc, kSuperShift);
+    if (rect_count(sr) == 0) continue;
+    const int x0 = static_cast<int>(sr.x & 0xFFFFu), xe = static_cast<int>(sr.x >> 16);
+    const int y0 = static_cast<int>(sr.y & 0xFFFFu), ye = static_cast<int>(sr.y >> 16);
     atomicAdd(&s_diff[y0 * pitch + x0], 1);
     atomicAdd(&s_diff[y0 * pitch + xe], -1);
     atomicAdd(&s_diff[ye * pitch + x0], -1);
     atomicAdd(&s_diff[ye * pitch + xe], 1);
   }
+  for (int o = 32; o > 0; o >>= 1) fine += __shfl_xor(fine, o, 64);
+  if (lane == 0) s_k[wave] = fine;
   __syncthreads();
-  for (int y = wave; y < tiles_y; y += kDirectWaves) wave_prefix_lds(s_diff + y * pitch, tiles_x, 1, lane);
+  if (tid == 0) {
+    unsigned long long k = 0;
+    for (int w = 0; w < kDirectWaves; ++w) k += s_k[w];
+    if (k) atomicAdd(kfine, k);
+  }
+  for (int y = wave; y < sy; y += kDirectWaves) wave_prefix_lds(s_diff + y * pitch, sx, 1, lane);
   __syncthreads();
-  for (int x = wave; x < tiles_x; x += kDirectWaves) wave_prefix_lds(s_diff + x, tiles_y, pitch, lane);
+  for (int x = wave; x < sx; x += kDirectWaves) wave_prefix_lds(s_diff + x, sy, pitch, lane);
   __syncthreads();
-  uint32_t* const out = table + static_cast<size_t>(c) * tiles_x * tiles_y;
-  for (int y = wave; y < tiles_y; y += kDirectWaves)
-    for (int x = lane; x < tiles_x; x += 64) out[y * tiles_x + x] = static_cast<uint32_t>(s_diff[y * pitch + x]);
+  uint32_t* const out = table + static_cast<size_t>(c) * sx * sy;
+  for (int y = wave; y < sy; y += kDirectWaves)
+    for (int x = lane; x < sx; x += 64) out[y * sx + x] = static_cast<uint32_t>(s_diff[y * pitch + x]);
 }
 
-// One workgroup (16 waves) per 64 tiles; wave w owns a contiguous range of
-// at most kDirectChunks / 16 chunks, whose counts it holds in registers (one
-// read of the table, all loads in flight at once).  table[c][t] becomes the
-// entries of tile t in chunks before c; total[t] is the tile's count.
+// One workgroup (16 waves) per 64 columns (tiles or super tiles); wave w owns
+// a contiguous range of at most kDirectChunks / 16 chunks, whose counts it
+// holds in registers (one read of the table, all loads in flight at once).
+// table[c][t] becomes the entries of t in chunks before c; total[t] is t's
+// count.
 constexpr int kColPer = kDirectChunks / 16;
 __global__ __launch_bounds__(1024) void k_chunk_colscan(int C, int ntiles, uint32_t* __restrict__ table,
                                                         uint32_t* __restrict__ total) {
@@ -926,18 +989,54 @@ __global__ __launch_bounds__(1024) void k_chunk_colscan(int C, int ntiles, uint3
   }
 }
 
-// start[t] = exclusive prefix of total over tiles; ranges[t] = (start, start + total).
-// If the entries do not fit in `capacity`, every range is written empty
-// instead, so that work queued on these lists before the caller learns of
-// the overflow (the no-wait call) reads nothing past the buffers.
-__global__ __launch_bounds__(1024) void k_tile_starts(int ntiles, const uint32_t* __restrict__ total,
-                                                      uint32_t* __restrict__ start, uint2* __restrict__ ranges,
-                                                      unsigned long long capacity) {
-  __shared__ unsigned long long s_w[16];
+// Exclusive prefix of one 64-bit value per thread over a workgroup of
+// THREADS threads (s_w: THREADS / 64 words of LDS, free again on return);
+// `all` is the sum.
+template <int THREADS>
+__device__ __forceinline__ unsigned long long block_exclusive_u64(unsigned long long v, unsigned long long* s_w,
+                                                                  unsigned long long& all) {
+  constexpr int W = THREADS / 64;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int per = (ntiles + 1023) / 1024;   // at most kStartRegs: direct_ok keeps ntiles below 16384
-  const int t0 = min(ntiles, tid * per), t1 = min(ntiles, t0 + per);
-  // the thread's totals, read once with all loads in flight
+  unsigned long long incl = v;
+  for (int d = 1; d < 64; d <<= 1) {
+    const unsigned long long u = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += u;
+  }
+  if (lane == 63) s_w[wave] = incl;
+  __syncthreads();
+  unsigned long long before = incl - v;
+  all = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    all += s_w[w];
+    before += (w < wave) ? s_w[w] : 0ull;
+  }
+  __syncthreads();
+  return before;
+}
+
+// start[t] = exclusive prefix of total over the tiles, ranges[t] = (start,
+// start + total), by one workgroup.  K = *kfine (the sum of the tile counts)
+// goes to rb[0] and, if given, k_dev[0]; *fits = whether the entries fit.  If
+// they do not fit in `capacity`, every range is written empty instead, so
+// that work queued on these lists before the caller learns of the overflow
+// (the no-wait call) reads nothing past the buffers.
+struct StartArgs {
+  int ntiles;
+  uint32_t* start;
+  uint2* ranges;
+  unsigned long long capacity;
+  const unsigned long long* kfine;
+  unsigned long long* rb;
+  unsigned long long* k_dev;
+  uint32_t* fits;
+};
+constexpr int kStartRegs = kDirectMaxTiles / 1024;   // a thread's totals, all loads in flight at once
+__global__ __launch_bounds__(1024) void k_tile_starts(const uint32_t* __restrict__ total, StartArgs a) {
+  __shared__ unsigned long long s_w[16];
+  const int tid = threadIdx.x;
+  const int per = (a.ntiles + 1023) / 1024;   // at most kStartRegs: direct_ok bounds the tiles
+  const int t0 = min(a.ntiles, tid * per), t1 = min(a.ntiles, t0 + per);
   uint32_t v[kStartRegs];
   unsigned long long sum = 0;
 #pragma unroll
@@ -945,30 +1044,58 @@ __global__ __launch_bounds__(1024) void k_tile_starts(int ntiles, const uint32_t
     v[k] = t0 + k < t1 ? total[t0 + k] : 0u;
     sum += v[k];
   }
-  unsigned long long incl = sum;
-  for (int d = 1; d < 64; d <<= 1) {
-    const unsigned long long v = __shfl_up(incl, d, 64);
-    if (lane >= d) incl += v;
-  }
-  if (lane == 63) s_w[wave] = incl;
-  __syncthreads();
-  unsigned long long run = incl - sum, all = 0;
-  for (int w = 0; w < 16; ++w) {
-    all += s_w[w];
-    run += (w < wave) ? s_w[w] : 0ull;
-  }
+  unsigned long long all;
+  unsigned long long run = block_exclusive_u64<1024>(sum, s_w, all);
+  const unsigned long long K = *a.kfine;
   // positions are 32-bit: a total beyond that does not fit either
-  const bool fits = all <= min(capacity, 0xFFFFFFFFull);
+  const bool fits = K <= min(a.capacity, 0xFFFFFFFFull);
+  if (tid == 0) {
+    a.rb[0] = K;
+    if (a.k_dev) a.k_dev[0] = K;
+    *a.fits = fits ? 1u : 0u;
+  }
 #pragma unroll
   for (int k = 0; k < kStartRegs; ++k) {
     const int t = t0 + k;
     if (t < t1) {
-      start[t] = static_cast<uint32_t>(run);
-      ranges[t] = fits ? make_uint2(static_cast<uint32_t>(run), static_cast<uint32_t>(run + v[k]))
-                       : make_uint2(0u, 0u);
+      a.start[t] = static_cast<uint32_t>(run);
+      a.ranges[t] = fits ? make_uint2(static_cast<uint32_t>(run), static_cast<uint32_t>(run + v[k]))
+                         : make_uint2(0u, 0u);
     }
     run += v[k];
   }
+}
+
+// Super tile s's run of the coarse list starts at start[s] (exclusive prefix
+// of the totals) and is cut into parts of kPart entries, numbered over the
+// super tiles in turn: parts pbase[s] .. pbase[s+1]-1 (pbase[ns]: all parts).
+// A coarse list longer than its buffer (capacity) gives no parts: K is at
+// least as large, so the frame is reported as not fitting.
+__global__ __launch_bounds__(1024) void k_coarse_parts(int ns, const uint32_t* __restrict__ ctotal,
+                                                       uint32_t* __restrict__ cstart, unsigned long long capacity,
+                                                       uint32_t* __restrict__ pbase) {
+  __shared__ unsigned long long s_w[16];
+  const int tid = threadIdx.x;
+  const int per = (ns + 1023) / 1024;
+  const int t0 = min(ns, tid * per), t1 = min(ns, t0 + per);
+  unsigned long long sum = 0, psum = 0;
+  for (int t = t0; t < t1; ++t) {
+    const uint32_t v = ctotal[t];
+    sum += v;
+    psum += (v + kPart - 1) / kPart;
+  }
+  unsigned long long all, pall;
+  unsigned long long run = block_exclusive_u64<1024>(sum, s_w, all);
+  unsigned long long prun = block_exclusive_u64<1024>(psum, s_w, pall);
+  const bool fits = all <= min(capacity, 0xFFFFFFFFull);
+  for (int t = t0; t < t1; ++t) {
+    const uint32_t v = ctotal[t];
+    cstart[t] = static_cast<uint32_t>(run);
+    pbase[t] = fits ? static_cast<uint32_t>(prun) : 0u;
+    run += v;
+    prun += (v + kPart - 1) / kPart;
+  }
+  if (tid == 0) pbase[ns] = fits ? static_cast<uint32_t>(pall) : 0u;
 }
 
 // Inclusive max over the 64 lanes on DPP (row shifts, then the row broadcasts
@@ -1007,17 +1134,19 @@ __device__ __forceinline__ int run_owner(const uint32_t* __restrict__ pre, uint3
   return static_cast<int>(wave_incl_max(v)) - 1;
 }
 
-// Placement of entry e of rank-wave rw (uniform over the wave) of the
+// Placement of coarse entry e of rank-wave rw (uniform over the wave) of the
 // current group (offsets pre[0..64], total pre[64]), owned by rank lo of the
-// rank-wave: the entry goes to its tile's position at the group start plus
-// the group's earlier ranks on that tile; the group's last entry on a tile
-// stores the group's count there.
+// rank-wave: the entry goes to its super tile's position at the group start
+// plus the group's earlier ranks on that super tile; the group's last entry
+// on a super tile stores the group's count there.  s_rect holds the ranks'
+// super-tile rectangles, s_frect their tile rectangles.
 __device__ __forceinline__ void place_entry(int rw, uint32_t e, int lo, const uint32_t* __restrict__ pre,
-                                            const uint2* __restrict__ s_rect, const uint32_t* __restrict__ s_magic,
+                                            const uint2* __restrict__ s_rect, const uint2* __restrict__ s_frect,
+                                            const uint32_t* __restrict__ s_magic,
                                             const uint32_t* __restrict__ s_gid,
                                             const unsigned long long* __restrict__ s_dyn,
                                             const uint32_t* __restrict__ s_pos, uint16_t* __restrict__ s_delta,
-                                            int edge, int tiles_x, uint32_t* __restrict__ point_list,
+                                            int edge, int tiles_x, unsigned long long* __restrict__ coarse,
                                             uint32_t capacity) {
   if (e >= pre[64]) return;
   const int i = rw * 64 + lo;
@@ -1058,34 +1187,53 @@ __device__ __forceinline__ void place_entry(int rw, uint32_t e, int lo, const ui
       break;
   }
   const uint32_t p = s_pos[t] + within;
-  if (p < capacity) point_list[p] = s_gid[i];
+  if (p < capacity) {
+    // the rank's tile rectangle clipped to super tile (tx, ty), in its frame
+    const uint2 f = s_frect[i];
+    const uint32_t bx = static_cast<uint32_t>(tx) << kSuperShift, by = static_cast<uint32_t>(ty) << kSuperShift;
+    const uint32_t lx0 = max(f.x & 0xFFFFu, bx) - bx, lxe = min(f.x >> 16, bx + kSuper) - bx;
+    const uint32_t ly0 = max(f.y & 0xFFFFu, by) - by, lye = min(f.y >> 16, by + kSuper) - by;
+    const uint32_t lr = lx0 | (lxe << 4) | (ly0 << 8) | (lye << 12);
+    coarse[p] = static_cast<unsigned long long>(s_gid[i]) | (static_cast<unsigned long long>(lr) << 32);
+  }
   if (later == 0ull) s_delta[t] = static_cast<uint16_t>(within + 1u);   // at most 256
 }
 
-// Groups of 256 ranks.  Waves 0-3 load the group's ranks (64 each, a
-// rank-wave) and build their coverage masks; then the group's runs of 64
-// entries (rank-wave 0's, then 1's, ...) are dealt to the 16 waves in turn,
-// so that a rank-wave with many entries does not hold up the group.  An entry
-// finds its rank by a binary search over the 64 entry offsets of its
-// rank-wave, its tile from the rank's rectangle, and its position as the
-// tile's position at the start of the group plus the count of the group's
-// earlier ranks on the tile.  The entry of the tile's last rank in the group
-// also writes the group's count for the tile into delta[t], which one pass
-// over the tiles adds to the positions once every entry of the group is
-// placed.
+// A workgroup barrier that orders LDS only: the waves' outstanding global
+// stores need not drain before it (nothing in the workgroup reads them).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Coarse emission over the sx x sy super tiles (tiles_x, tiles_y below).
+// Groups of 256 ranks.  Waves 0-3 hold the group's ranks (64 each, a
+// rank-wave), loaded while the group before was placed, and build their
+// coverage masks; then the group's runs of 64 entries (rank-wave 0's, then
+// 1's, ...) are dealt to waves 4-15 in turn, so that a rank-wave with many
+// entries does not hold up the group, while waves 0-3 load the next group
+// (they store nothing to global memory, so their loads wait for no stores).  An entry
+// finds its rank from the 64 entry offsets of its rank-wave (run_owner), its
+// super tile from the rank's rectangle, and its position as the super tile's
+// position at the start of the group plus the count of the group's earlier
+// ranks on it.  The entry of the super tile's last rank in the group also
+// writes the group's count into delta[t], which one pass over the super
+// tiles adds to the positions once every entry of the group is placed.
 // two workgroups per CU (8 waves per SIMD): at most 64 VGPRs
-__global__ __launch_bounds__(kDirectThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_emit_direct(const uint32_t* __restrict__ bounds,
+__global__ __launch_bounds__(kDirectThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_emit_coarse(const uint32_t* __restrict__ bounds,
                                                                 const uint32_t* __restrict__ order,
                                                                 const uint2* __restrict__ rect_rank,
                                                                 const uint32_t* __restrict__ table,
                                                                 const uint32_t* __restrict__ start, int tiles_x,
-                                                                int tiles_y, uint32_t* __restrict__ point_list,
+                                                                int tiles_y, unsigned long long* __restrict__ coarse,
                                                                 uint32_t capacity) {
   // dynamic: col[4][tiles_x] row[4][tiles_y] (u64), then pos[ntiles] (u32), delta[ntiles] (u16)
   extern __shared__ unsigned long long s_dyn[];
   __shared__ uint32_t s_pre[4][65];   // per rank-wave: exclusive entry offsets, then the total
   __shared__ uint32_t s_gid[256];
   __shared__ uint2 s_rect[256];
+  __shared__ uint2 s_frect[256];
   __shared__ uint32_t s_magic[256];   // ceil(2^32 / rectangle width), 0 for width 1
   __shared__ uint32_t s_mark[kDirectWaves][64];   // per wave: run_owner's scratch
   const int ntiles = tiles_x * tiles_y;
@@ -1101,15 +1249,30 @@ __global__ __launch_bounds__(kDirectThreads) __attribute__((amdgpu_waves_per_eu(
     s_pos[t] = start[t] + tab[t];
     s_delta[t] = 0;
   }
+  // the next group's ranks, loaded at a clamped index with no condition (so
+  // that no branch hides the count of loads in flight: the first use waits
+  // for these only) and masked at that use
+  uint2 nfr = make_uint2(0u, 0u);
+  uint32_t ngid = 0u;
+  if (wave < 4) {
+    const uint32_t rl = min(R0 + static_cast<uint32_t>(tid), R1 - 1u);
+    nfr = rect_rank[rl];
+    ngid = order[rl];
+  }
   for (uint32_t r0 = R0; r0 < R1; r0 += 256) {
-    __syncthreads();   // positions updated, masks of the previous group no longer read
+    lds_barrier();   // positions updated, masks of the previous group no longer read
     if (wave < 4) {
-      const uint32_t r = r0 + static_cast<uint32_t>(tid);
-      const bool valid = r < R1;
-      const uint2 rc = valid ? rect_rank[r] : make_uint2(0u, 0u);
+      const bool valid = r0 + static_cast<uint32_t>(tid) < R1;
+      const uint2 fr = valid ? nfr : make_uint2(0u, 0u);   // (0, 0) past the chunk: no entries
+      const uint32_t gid = valid ? ngid : 0u;
+      const uint32_t rl = min(r0 + 256u + static_cast<uint32_t>(tid), R1 - 1u);
+      nfr = rect_rank[rl];
+      ngid = order[rl];
+      const uint2 rc = rect_at(fr, kSuperShift);
       const uint32_t cnt = rect_count(rc);
       s_rect[tid] = rc;
-      s_gid[tid] = valid ? order[r] : 0u;
+      s_frect[tid] = fr;
+      s_gid[tid] = gid;
       const uint32_t wd = (rc.x >> 16) - (rc.x & 0xFFFFu);
       s_magic[tid] = wd >= 2u ? 0xFFFFFFFFu / wd + 1u : 0u;
       uint32_t incl = cnt;
@@ -1154,28 +1317,231 @@ __global__ __launch_bounds__(kDirectThreads) __attribute__((amdgpu_waves_per_eu(
         }
       }
     }
-    __syncthreads();
+    lds_barrier();
     // place the group's entries: the runs of 64 entries of rank-waves 0..3 in
-    // turn, dealt to the 16 waves round-robin (a run's rank-wave is uniform
+    // turn, dealt to waves 4-15 round-robin (a run's rank-wave is uniform
     // over the wave)
-    {
+    if (wave_u >= 4) {
       const uint32_t c1 = __builtin_amdgcn_readfirstlane((s_pre[0][64] + 63u) >> 6);
       const uint32_t c2 = c1 + __builtin_amdgcn_readfirstlane((s_pre[1][64] + 63u) >> 6);
       const uint32_t c3 = c2 + __builtin_amdgcn_readfirstlane((s_pre[2][64] + 63u) >> 6);
       const uint32_t nrun = c3 + __builtin_amdgcn_readfirstlane((s_pre[3][64] + 63u) >> 6);
-      for (uint32_t run = static_cast<uint32_t>(wave_u); run < nrun; run += kDirectWaves) {
+      for (uint32_t run = static_cast<uint32_t>(wave_u - 4); run < nrun; run += kDirectWaves - 4) {
         const int rw = run < c1 ? 0 : (run < c2 ? 1 : (run < c3 ? 2 : 3));
         const uint32_t first = run < c1 ? 0u : (run < c2 ? c1 : (run < c3 ? c2 : c3));
         const uint32_t e0 = (run - first) * 64u;
         const int lo = run_owner(s_pre[rw], e0, s_mark[wave_u], lane);
-        place_entry(rw, e0 + lane, lo, s_pre[rw], s_rect, s_magic, s_gid, s_dyn, s_pos, s_delta, edge, tiles_x,
-                    point_list, capacity);
+        place_entry(rw, e0 + lane, lo, s_pre[rw], s_rect, s_frect, s_magic, s_gid, s_dyn, s_pos, s_delta, edge,
+                    tiles_x, coarse, capacity);
       }
     }
-    __syncthreads();
+    lds_barrier();
     for (int t = tid; t < ntiles; t += kDirectThreads) {
       const uint32_t d = s_delta[t];
       if (d) { s_pos[t] += d; s_delta[t] = 0; }
+    }
+  }
+}
+
+// Fine passes.  A coarse entry packs the Gaussian (low word) and its
+// rectangle within the super tile (high word: x0 | x_end << 4 | y0 << 8 |
+// y_end << 12, ends exclusive, all in 0..8).  For a wave's 64 entries (lane e
+// holds entry e, 0 for none) col[x] is the mask of entries spanning column x
+// of the super tile and row[y] of those spanning row y: the entries on tile
+// (x, y) are col[x] & row[y].
+struct FineMasks {
+  uint64_t col[kSuper], row[kSuper];
+};
+__device__ __forceinline__ void fine_masks(uint32_t lr, FineMasks& m) {
+  const uint32_t x0 = lr & 15u, xe = (lr >> 4) & 15u, y0 = (lr >> 8) & 15u, ye = (lr >> 12) & 15u;
+#pragma unroll
+  for (int k = 0; k < kSuper; ++k) {
+    const uint32_t u = static_cast<uint32_t>(k);
+    m.col[k] = __ballot(x0 <= u && u < xe);
+    m.row[k] = __ballot(y0 <= u && u < ye);
+  }
+}
+// Lane t's tile (t & 7, t >> 3): the mask of the wave's entries covering it.
+__device__ __forceinline__ uint64_t fine_tile_mask(const FineMasks& m, int lane) {
+  uint64_t c = m.col[0], r = m.row[0];
+#pragma unroll
+  for (int k = 1; k < kSuper; ++k) {
+    c = (lane & (kSuper - 1)) == k ? m.col[k] : c;
+    r = (lane >> kSuperShift) == k ? m.row[k] : r;
+  }
+  return c & r;
+}
+
+// The fine passes' part p: its super tile (the last s with pbase[s] <= p,
+// from the part bases in LDS) and its coarse entries [lo, hi).
+struct Part {
+  uint32_t s, lo, hi;
+};
+__device__ __forceinline__ Part find_part(const uint32_t* __restrict__ s_pb, int ns, uint32_t p,
+                                          const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ ctotal) {
+  int a = 0, b = ns - 1;
+  while (a < b) {
+    const int mid = (a + b + 1) >> 1;
+    if (s_pb[mid] <= p) a = mid; else b = mid - 1;
+  }
+  const uint32_t s = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(a));
+  const uint32_t base = cstart[s], lo = base + (p - s_pb[s]) * static_cast<uint32_t>(kPart);
+  return Part{s, lo, min(lo + static_cast<uint32_t>(kPart), base + ctotal[s])};
+}
+
+// A part's coarse entries, kPartSteps per thread: step j of wave w holds
+// entries lo + 256 j + 64 w + lane (0 past hi), all loads in flight at once.
+__device__ __forceinline__ void load_part(const unsigned long long* __restrict__ coarse, const Part& pt, int wave,
+                                          int lane, unsigned long long (&v)[kPartSteps]) {
+#pragma unroll
+  for (int j = 0; j < kPartSteps; ++j) {
+    const uint32_t e = pt.lo + static_cast<uint32_t>(j * kFineThreads + wave * 64 + lane);
+    v[j] = e < pt.hi ? coarse[e] : 0ull;
+  }
+}
+
+// Per part p: ftab[p][t] = the entries of its super tile's tile t in the
+// part.  The workgroups loop over the parts.
+__global__ __launch_bounds__(kFineThreads) void k_fine_count(const uint32_t* __restrict__ pbase, int ns,
+                                                             const uint32_t* __restrict__ cstart,
+                                                             const uint32_t* __restrict__ ctotal,
+                                                             const unsigned long long* __restrict__ coarse,
+                                                             uint32_t* __restrict__ ftab) {
+  extern __shared__ uint32_t s_pb[];   // pbase[0..ns]
+  __shared__ uint32_t s_sum[kFineWaves][64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int i = threadIdx.x; i <= ns; i += kFineThreads) s_pb[i] = pbase[i];
+  __syncthreads();
+  const uint32_t np = s_pb[ns];
+  for (uint32_t p = blockIdx.x; p < np; p += gridDim.x) {
+    const Part pt = find_part(s_pb, ns, p, cstart, ctotal);
+    unsigned long long v[kPartSteps];
+    load_part(coarse, pt, wave, lane, v);
+    uint32_t acc = 0;
+#pragma unroll
+    for (int j = 0; j < kPartSteps; ++j) {
+      FineMasks m;
+      fine_masks(static_cast<uint32_t>(v[j] >> 32), m);
+      acc += static_cast<uint32_t>(__popcll(fine_tile_mask(m, lane)));
+    }
+    s_sum[wave][lane] = acc;
+    __syncthreads();
+    if (wave == 0) {
+      uint32_t t = 0;
+#pragma unroll
+      for (int w = 0; w < kFineWaves; ++w) t += s_sum[w][lane];
+      ftab[static_cast<size_t>(p) * 64 + lane] = t;
+    }
+    __syncthreads();
+  }
+}
+
+// Per super tile s (one workgroup): the counts ftab[p][t] of its parts become
+// exclusive prefixes over the parts, and each tile's total goes to total[]
+// (lanes of tiles outside the frame write nothing).  Wave w takes a quarter
+// of the parts, lane t the tile; the rows are read kScanBatch at a time, all
+// loads in flight together.
+constexpr int kScanBatch = 8;
+__global__ __launch_bounds__(256) void k_fine_scan(const uint32_t* __restrict__ pbase, uint32_t* __restrict__ ftab,
+                                                   int sx, int tiles_x, int tiles_y, uint32_t* __restrict__ total) {
+  __shared__ uint32_t s_sum[4][64];
+  const int s = blockIdx.x, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint32_t p0 = pbase[s], p1 = pbase[s + 1];
+  const uint32_t per = (p1 - p0 + 3u) / 4u;
+  const uint32_t a = min(p1, p0 + static_cast<uint32_t>(wave) * per), b = min(p1, a + per);
+  uint32_t* const col = ftab + lane;
+  uint32_t sum = 0;
+  for (uint32_t p = a; p < b; p += kScanBatch) {
+    uint32_t x[kScanBatch];
+#pragma unroll
+    for (int k = 0; k < kScanBatch; ++k) x[k] = p + k < b ? col[static_cast<size_t>(p + k) * 64] : 0u;
+#pragma unroll
+    for (int k = 0; k < kScanBatch; ++k) sum += x[k];
+  }
+  s_sum[wave][lane] = sum;
+  __syncthreads();
+  uint32_t run = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const uint32_t x = s_sum[w][lane];
+    run += (w < wave) ? x : 0u;
+    all += x;
+  }
+  for (uint32_t p = a; p < b; p += kScanBatch) {
+    uint32_t x[kScanBatch];
+#pragma unroll
+    for (int k = 0; k < kScanBatch; ++k) x[k] = p + k < b ? col[static_cast<size_t>(p + k) * 64] : 0u;
+#pragma unroll
+    for (int k = 0; k < kScanBatch; ++k) {
+      if (p + k < b) col[static_cast<size_t>(p + k) * 64] = run;
+      run += x[k];
+    }
+  }
+  if (wave == 0) {
+    const int tx = (s % sx) * kSuper + (lane & (kSuper - 1)), ty = (s / sx) * kSuper + (lane >> kSuperShift);
+    if (tx < tiles_x && ty < tiles_y) total[ty * tiles_x + tx] = all;
+  }
+}
+
+// Per part p: the point_list entries of its coarse entries.  Lane t of every
+// wave keeps tile t's next position (pos); per step of 256 entries each wave
+// counts its entries per tile, the counts of the earlier waves give its
+// offsets, and then the 64 tiles go out in turn, one store each (exec = the
+// tile's mask).  Nothing is written unless every entry fits (*fits, from
+// k_tile_starts): then every position is below K <= capacity.
+__global__ __launch_bounds__(kFineThreads) void k_fine_emit(const uint32_t* __restrict__ pbase, int ns,
+                                                            const uint32_t* __restrict__ cstart,
+                                                            const uint32_t* __restrict__ ctotal,
+                                                            const unsigned long long* __restrict__ coarse,
+                                                            const uint32_t* __restrict__ ftab,
+                                                            const uint32_t* __restrict__ start, int sx, int tiles_x,
+                                                            int tiles_y, const uint32_t* __restrict__ fits,
+                                                            uint32_t* __restrict__ point_list) {
+  extern __shared__ uint32_t s_pb[];   // pbase[0..ns]
+  __shared__ uint32_t s_cnt[2][kFineWaves][64];   // two steps in flight: one barrier per step
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (*fits == 0u) return;
+  for (int i = threadIdx.x; i <= ns; i += kFineThreads) s_pb[i] = pbase[i];
+  __syncthreads();
+  const uint32_t np = s_pb[ns];
+  int buf = 0;
+  for (uint32_t p = blockIdx.x; p < np; p += gridDim.x) {
+    const Part pt = find_part(s_pb, ns, p, cstart, ctotal);
+    unsigned long long v[kPartSteps];
+    load_part(coarse, pt, wave, lane, v);
+    const int tx = static_cast<int>(pt.s % static_cast<uint32_t>(sx)) * kSuper + (lane & (kSuper - 1));
+    const int ty = static_cast<int>(pt.s / static_cast<uint32_t>(sx)) * kSuper + (lane >> kSuperShift);
+    uint32_t pos = (tx < tiles_x && ty < tiles_y) ? start[ty * tiles_x + tx] + ftab[static_cast<size_t>(p) * 64 + lane]
+                                                  : 0u;
+    const int steps = static_cast<int>((pt.hi - pt.lo + kFineThreads - 1) / kFineThreads);
+#pragma unroll 1
+    for (int j = 0; j < steps; ++j) {
+      const unsigned long long e = v[0];
+#pragma unroll
+      for (int k = 0; k + 1 < kPartSteps; ++k) v[k] = v[k + 1];
+      const uint32_t gid = static_cast<uint32_t>(e);
+      FineMasks m;
+      fine_masks(static_cast<uint32_t>(e >> 32), m);
+      s_cnt[buf][wave][lane] = static_cast<uint32_t>(__popcll(fine_tile_mask(m, lane)));
+      lds_barrier();
+      uint32_t before = pos, all = 0;
+#pragma unroll
+      for (int w = 0; w < kFineWaves; ++w) {
+        const uint32_t c = s_cnt[buf][w][lane];
+        before += (w < wave) ? c : 0u;
+        all += c;
+      }
+      pos += all;
+      buf ^= 1;
+#pragma unroll
+      for (int t = 0; t < 64; ++t) {
+        const uint64_t M = m.col[t & (kSuper - 1)] & m.row[t >> kSuperShift];
+        if (M == 0ull) continue;
+        const uint32_t bt = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(before), t));
+        if (__builtin_amdgcn_inverse_ballot_w64(M))
+          point_list[bt + __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(M >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(M), 0u))] = gid;
+      }
     }
   }
 }
@@ -1189,46 +1555,66 @@ static int bits_for(int64_t values) {  // bits needed to represent 0..values-1
 struct BinWs {
   uint32_t *dk0, *dv0, *dk1, *dv1, *order, *cnt, *offs;
   uint2 *rect, *rect_rank;
-  uint32_t *ek0, *ek1, *ev1;
+  uint32_t *ek0, *ek1, *ev1;      // radix tile sort (no direct emission)
   uint32_t* hist;
   ScanWs scan;
   OsWs os;                        // depth sort state
-  uint32_t* zero;                 // its digit counts and the error flag, cleared by k_depth_keys
+  uint32_t* zero;                 // its digit counts, K, the error flag and kfine, cleared by k_depth_keys
   unsigned long long* readback;   // [0] K, [1] the error flag
-  // direct emission: chunk bounds, chunk x tile table, tile totals and starts
-  uint32_t *bounds, *table, *total, *start;
+  unsigned long long* kfine;      // direct emission: the tile counts' sum
+  // direct emission: chunk bounds, chunk x super-tile table, super-tile
+  // totals and starts, tile totals and starts, the parts, per part x tile
+  // counts, and the coarse list
+  uint32_t *bounds, *table, *ctotal, *cstart, *total, *start;
+  uint32_t *pbase, *ftab, *fits;
+  unsigned long long* coarse;
 };
+
+constexpr int kZeroWords = kOsMaxPasses * 256 + 6;   // digit counts, K, error flag, kfine
 
 static BinWs carve_bin(void* ws, int64_t n, int64_t cap, int tiles_x, int tiles_y, size_t* used) {
   Carver c(ws);
-  BinWs b;
+  BinWs b{};
   const size_t N = static_cast<size_t>(n > 0 ? n : 1), C = static_cast<size_t>(cap > 0 ? cap : 1);
+  const bool direct = direct_ok(tiles_x, tiles_y);
   b.dk0 = c.take<uint32_t>(N); b.dv0 = c.take<uint32_t>(N);
   b.dk1 = c.take<uint32_t>(N); b.dv1 = c.take<uint32_t>(N);
   b.order = c.take<uint32_t>(N);
   b.cnt = c.take<uint32_t>(N); b.offs = c.take<uint32_t>(N);
   b.rect = c.take<uint2>(N); b.rect_rank = c.take<uint2>(N);
-  b.ek0 = c.take<uint32_t>(C); b.ek1 = c.take<uint32_t>(C); b.ev1 = c.take<uint32_t>(C);
-  const size_t hist_words = 256 * static_cast<size_t>(ceil_div(std::max<int64_t>(cap, 1), kRsThreads * kRsItemsK));
-  const int64_t maxn = std::max<int64_t>(std::max<int64_t>(n, cap), 1);
-  b.hist = c.take<uint32_t>(hist_words);
-  b.scan.sums = c.take<uint32_t>(scan_ws_words(std::max<int64_t>(static_cast<int64_t>(hist_words), maxn)));
-  // cleared by k_depth_keys: the onesweep digit counts, then K and the error flag
-  b.zero = c.take<uint32_t>(kOsMaxPasses * 256 + 4);
+  if (direct) {
+    b.scan.sums = c.take<uint32_t>(scan_ws_words(static_cast<int64_t>(N)));
+  } else {
+    b.ek0 = c.take<uint32_t>(C); b.ek1 = c.take<uint32_t>(C); b.ev1 = c.take<uint32_t>(C);
+    const size_t hist_words = 256 * static_cast<size_t>(ceil_div(std::max<int64_t>(cap, 1), kRsThreads * kRsItemsK));
+    const int64_t maxn = std::max<int64_t>(std::max<int64_t>(n, cap), 1);
+    b.hist = c.take<uint32_t>(hist_words);
+    b.scan.sums = c.take<uint32_t>(scan_ws_words(std::max<int64_t>(static_cast<int64_t>(hist_words), maxn)));
+  }
+  // cleared by k_depth_keys: the onesweep digit counts, then K, the error flag and kfine
+  b.zero = c.take<uint32_t>(kZeroWords);
   b.readback = reinterpret_cast<unsigned long long*>(b.zero + kOsMaxPasses * 256);
+  b.kfine = b.readback + 2;
   b.scan.total = b.readback;
   b.os.ghist = b.zero;
   b.os.err = reinterpret_cast<uint32_t*>(b.readback + 1);
   b.os.state = c.take<uint32_t>(os_state_words(n, kOsItemsN, kOsMaxPasses));
   b.os.counters = c.take<uint32_t>(kOsMaxPasses);
-  b.bounds = b.table = b.total = b.start = nullptr;
-  if (direct_ok(tiles_x, tiles_y)) {
+  if (direct) {
     const size_t nt = static_cast<size_t>(tiles_x) * tiles_y;
+    const int ns = super_dim(tiles_x) * super_dim(tiles_y);
     const size_t chunks = static_cast<size_t>(direct_max_chunks(cap));
+    const size_t parts = static_cast<size_t>(direct_max_parts(cap, ns));
     b.bounds = c.take<uint32_t>(chunks + 1);
-    b.table = c.take<uint32_t>(chunks * nt);
+    b.table = c.take<uint32_t>(chunks * ns);
+    b.ctotal = c.take<uint32_t>(ns);
+    b.cstart = c.take<uint32_t>(ns);
     b.total = c.take<uint32_t>(nt);
     b.start = c.take<uint32_t>(nt);
+    b.pbase = c.take<uint32_t>(ns + 1);
+    b.fits = c.take<uint32_t>(1);
+    b.ftab = c.take<uint32_t>(parts * 64);
+    b.coarse = c.take<unsigned long long>(C);
   }
   *used = c.off + 256;
   return b;
@@ -1259,37 +1645,52 @@ gs_status run_bin_sort(int64_t n64, const gs_projected& proj, const DevCam& cam,
   if (n > 0) {
     const unsigned g = static_cast<unsigned>(ceil_div(n, 256));
     { TimedLaunch gs_tl("k_depth_keys", s); k_depth_keys<<<g, 256, 0, s>>>(n, proj.depth, reinterpret_cast<const float4*>(proj.records), proj.radius,
-                                   cam.tiles_x, cam.tiles_y, b.dk0, b.dv0, b.rect, b.zero, kOsMaxPasses * 256 + 4); }
+                                   cam.tiles_x, cam.tiles_y, b.dk0, b.dv0, b.rect, b.zero, kZeroWords); }
     if ((st = check_launch("k_depth_keys")) != GS_OK) return st;
-    // the terminal pass also gathers each rank's rectangle and tile count
+    // the terminal pass also gathers each rank's rectangle and its count of
+    // super tiles (direct emission) or tiles
     if ((st = onesweep_sort_pairs<kOsItemsN>(b.dk0, b.dv0, b.dk1, b.dv1, n, 32, b.os, s, b.order, b.rect,
-                                             b.rect_rank, b.cnt)) != GS_OK)
+                                             b.rect_rank, b.cnt, b.table ? kSuperShift : 0)) != GS_OK)
       return st;
     const uint32_t* order = b.order;
     unsigned long long rb[2] = {0ull, 0ull};
     if (b.table) {
-      // direct emission, sized on the device from the scanned total: no host
-      // wait between the depth sort and the placement; K (and the look-back
-      // flag) are read once at the end
+      // direct emission, sized on the device from the scanned coarse total:
+      // no host wait between the depth sort and the placement; K (and the
+      // look-back flag) are read once at the end
       const int tx = cam.tiles_x, ty = cam.tiles_y;
+      const int sx = super_dim(tx), sy = super_dim(ty), ns = sx * sy;
       const int cmax = static_cast<int>(direct_max_chunks(capacity));
+      const unsigned fgrid = static_cast<unsigned>(std::min<int64_t>(direct_max_parts(capacity, ns), kFineGrid));
+      const uint32_t cap32 = static_cast<uint32_t>(std::min<int64_t>(capacity, UINT32_MAX));
       if ((st = device_chunk_bounds(b.cnt, n, b.scan,
                                     ChunkArgs{b.bounds, cmax, static_cast<unsigned long long>(kDirectMinEntries),
                                               static_cast<unsigned long long>(kDirectChunks), k_dev},
                                     s)) != GS_OK)
         return st;
-      { TimedLaunch gs_tl("k_chunk_count", s); k_chunk_count<<<cmax, kDirectThreads, sizeof(int) * (tx + 1) * (ty + 1), s>>>(b.bounds, b.rect_rank, tx, ty,
-                                                                                   b.table); }
+      { TimedLaunch gs_tl("k_chunk_count", s); k_chunk_count<<<cmax, kDirectThreads, sizeof(int) * (sx + 1) * (sy + 1), s>>>(
+          b.bounds, b.rect_rank, sx, sy, b.table, b.kfine); }
       if ((st = check_launch("k_chunk_count")) != GS_OK) return st;
-      { TimedLaunch gs_tl("k_chunk_colscan", s); k_chunk_colscan<<<static_cast<unsigned>(ceil_div(ntiles, 64)), 1024, 0, s>>>(cmax, ntiles, b.table, b.total); }
+      { TimedLaunch gs_tl("k_chunk_colscan", s); k_chunk_colscan<<<static_cast<unsigned>(ceil_div(ns, 64)), 1024, 0, s>>>(cmax, ns, b.table, b.ctotal); }
       if ((st = check_launch("k_chunk_colscan")) != GS_OK) return st;
-      { TimedLaunch gs_tl("k_tile_starts", s); k_tile_starts<<<1, 1024, 0, s>>>(ntiles, b.total, b.start, reinterpret_cast<uint2*>(ranges),
-                                       static_cast<unsigned long long>(capacity)); }
+      { TimedLaunch gs_tl("k_coarse_parts", s); k_coarse_parts<<<1, 1024, 0, s>>>(ns, b.ctotal, b.cstart, static_cast<unsigned long long>(capacity),
+                                                                                  b.pbase); }
+      if ((st = check_launch("k_coarse_parts")) != GS_OK) return st;
+      { TimedLaunch gs_tl("k_emit_coarse", s); k_emit_coarse<<<cmax, kDirectThreads, emit_dyn_lds(sx, sy), s>>>(
+          b.bounds, order, b.rect_rank, b.table, b.cstart, sx, sy, b.coarse, cap32); }
+      if ((st = check_launch("k_emit_coarse")) != GS_OK) return st;
+      const size_t pb_lds = sizeof(uint32_t) * (static_cast<size_t>(ns) + 1);
+      { TimedLaunch gs_tl("k_fine_count", s); k_fine_count<<<fgrid, kFineThreads, pb_lds, s>>>(b.pbase, ns, b.cstart, b.ctotal, b.coarse, b.ftab); }
+      if ((st = check_launch("k_fine_count")) != GS_OK) return st;
+      { TimedLaunch gs_tl("k_fine_scan", s); k_fine_scan<<<ns, 256, 0, s>>>(b.pbase, b.ftab, sx, tx, ty, b.total); }
+      if ((st = check_launch("k_fine_scan")) != GS_OK) return st;
+      const StartArgs sa{ntiles, b.start, reinterpret_cast<uint2*>(ranges), static_cast<unsigned long long>(capacity),
+                         b.kfine, b.readback, k_dev, b.fits};
+      { TimedLaunch gs_tl("k_tile_starts", s); k_tile_starts<<<1, 1024, 0, s>>>(b.total, sa); }
       if ((st = check_launch("k_tile_starts")) != GS_OK) return st;
-      { TimedLaunch gs_tl("k_emit_direct", s); k_emit_direct<<<cmax, kDirectThreads, emit_dyn_lds(tx, ty), s>>>(
-          b.bounds, order, b.rect_rank, b.table, b.start, tx, ty, point_list,
-          static_cast<uint32_t>(std::min<int64_t>(capacity, UINT32_MAX))); }
-      if ((st = check_launch("k_emit_direct")) != GS_OK) return st;
+      { TimedLaunch gs_tl("k_fine_emit", s); k_fine_emit<<<fgrid, kFineThreads, pb_lds, s>>>(
+          b.pbase, ns, b.cstart, b.ctotal, b.coarse, b.ftab, b.start, sx, tx, ty, b.fits, point_list); }
+      if ((st = check_launch("k_fine_emit")) != GS_OK) return st;
       if (k_dev) return GS_OK;   // the caller checks K and the flag later
     } else if ((st = device_exclusive_scan(b.cnt, b.offs, n, b.scan, s)) != GS_OK) {
       return st;

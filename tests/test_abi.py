@@ -220,7 +220,7 @@ def test_bin_sort_async_argument_checks(gs):
     st = gs._lib.gs_bin_sort_async(10, ctypes.byref(_proj(gs)), ctypes.byref(c), fake, 16, fake, 100, fake, fake,
                                    NULL)
     assert st == gs.GS_ERR_INVALID_ARG
-    wide = gs.camera_struct(scenes.pinhole(2400, 1000, 70.0, np.eye(3), (0.0, 0.0, 3.0)))
+    wide = gs.camera_struct(scenes.pinhole(4800, 1000, 70.0, np.eye(3), (0.0, 0.0, 3.0)))   # 18,900 tiles
     st = gs._lib.gs_bin_sort_async(10, ctypes.byref(_proj(gs)), ctypes.byref(wide), fake, 1 << 40, fake, 100, fake,
                                    fake, NULL)
     assert st == gs.GS_ERR_UNSUPPORTED

@@ -514,13 +514,17 @@ def test_deterministic_backward(gs, name):
         say(f"  schedule {sched}: bit-identical reruns, worst rel err {worst:.2e}")
 
 
-def test_bin_sort_wide_frame_fallback(gs):
-    """A frame whose per-chunk tile tables exceed the LDS budget (150 x 63
-    tiles) takes the two-pass radix tile sort instead of the direct emission;
-    both must give the oracle's lists bit for bit."""
+@pytest.mark.parametrize("width", [2400, 4800])
+def test_bin_sort_wide_frame_fallback(gs, width):
+    """Wide frames: 150 x 63 tiles (9,450: the direct emission, 19 x 8 super
+    tiles with ragged edges) and 300 x 63 (18,900 tiles, more than the direct
+    emission's 16,384: the two-pass radix tile sort, which the no-wait call
+    refuses).  Both must give the oracle's lists bit for bit."""
     scene = scenes.skewed_scene(30000, 91, n_clusters=16, log_scale_mean=-3.6, sh_degree=1)
-    cam = scenes.pinhole(2400, 1000, 70.0, np.eye(3), (0.0, 0.0, 3.0))
+    cam = scenes.pinhole(width, 1000, 70.0, np.eye(3), (0.0, 0.0, 3.0))
     say(f"[bin/sort wide] n={scene.n} {cam.width}x{cam.height}")
+    direct = gs.n_tiles(gs.camera_struct(cam)) <= 16384
+    assert direct == (width == 2400)
     p, g, out = gpu_project(gs, scene, cam)
     h = proj_host(out)
     k, pl, ranges = gpu_bin_sort(gs, scene.n, out, cam)
