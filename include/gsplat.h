@@ -157,10 +157,12 @@ gs_status gs_bin_sort(int64_t n, const gs_projected* proj, const gs_camera* cam,
                       uint32_t* point_list, int64_t capacity, uint32_t* ranges, int64_t* k_out,
                       gs_stream stream);
 
-/* gs_bin_sort without the wait: the same lists, with K written to device
- * memory k_dev[0] and the depth sort's look-back error flag to k_dev[1]
- * (uint64 each, both in stream order), so a caller can queue the rest of the
- * frame at once and check them later.  The lists are valid only if
+/* gs_bin_sort without the wait: the same lists, with K written to k_dev[0]
+ * and the depth sort's look-back error flag to k_dev[1] (uint64 each, both in
+ * stream order), so a caller can queue the rest of the frame at once and
+ * check them later.  k_dev is device memory or pinned host memory that the
+ * device can address (hipHostMalloc): the kernels store to it directly, and
+ * the host reads it once the stream has passed the call (an event).  The lists are valid only if
  * k_dev[0] <= capacity and k_dev[1] == 0 (then they equal gs_bin_sort's);
  * otherwise they are undefined, no out-of-bounds access happens, and the
  * caller grows the buffers and redoes the frame.  Until it knows K the caller

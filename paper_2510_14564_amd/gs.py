@@ -265,10 +265,11 @@ def bin_sort(n: int, proj: ProjectedBuffers, cam: Camera, ws, point_list, ranges
 
 
 def bin_sort_async(n: int, proj: ProjectedBuffers, cam: Camera, ws, point_list, ranges, k_dev, stream=None):
-    """bin_sort without the host wait: K and the look-back flag go to the
-    device tensor k_dev (int64[2]); the lists are valid only if
+    """bin_sort without the host wait: K and the look-back flag go to k_dev
+    (int64[2]: a device tensor, or a pinned host tensor, which the kernels
+    write directly so that no copy is queued); the lists are valid only if
     k_dev[0] <= point_list.numel() and k_dev[1] == 0."""
-    assert k_dev.dtype == torch.int64 and k_dev.numel() >= 2 and k_dev.is_cuda
+    assert k_dev.dtype == torch.int64 and k_dev.numel() >= 2 and (k_dev.is_cuda or k_dev.is_pinned())
     _check(_lib.gs_bin_sort_async(n, ctypes.byref(proj.struct()), ctypes.byref(cam), _ptr(ws),
                                   ws.numel() * ws.element_size(), _ptr(point_list), point_list.numel(), _ptr(ranges),
                                   _ptr(k_dev), _stream(stream)), "gs_bin_sort_async")

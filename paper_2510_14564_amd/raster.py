@@ -56,8 +56,7 @@ class Rasterizer:
         # (or by check_async), which raises GsError if that frame's lists did
         # not fit -- its outputs are then invalid and the capacity has grown
         self.async_k = async_k
-        self.k_dev = None       # int64[2] on the device, K and the look-back flag
-        self.k_host = None      # its pinned host copy
+        self.k_host = None      # int64[2] in pinned host memory: K and the look-back flag
         self._k_event = None
         self._k_cap = 0
         self.last_k = None
@@ -123,14 +122,13 @@ class Rasterizer:
         point_list = None
         if self.async_k and self.last_k is not None:
             self.check_async()
-            if self.k_dev is None:
-                self.k_dev = torch.zeros(2, dtype=torch.int64, device=dev)
+            if self.k_host is None:
+                # pinned: the bin/sort kernels write K and the flag here directly
                 self.k_host = torch.zeros(2, dtype=torch.int64, pin_memory=True)
             point_list = torch.empty(max(self._cap, 1), dtype=torch.int32, device=dev)
             try:
                 with self._stage("bin_sort"):
-                    gs.bin_sort_async(n, proj, cs, self.bin_ws, point_list, ranges, self.k_dev)
-                self.k_host.copy_(self.k_dev, non_blocking=True)
+                    gs.bin_sort_async(n, proj, cs, self.bin_ws, point_list, ranges, self.k_host)
                 self._k_event = torch.cuda.Event()
                 self._k_event.record()
                 k = self._k_cap = self._cap   # an upper bound serves every later layout
