@@ -185,11 +185,17 @@ __device__ __forceinline__ void stage_light(LightStage& ls, const float4* __rest
 // Shared per-batch staging: records (pre-scaled conic), colour + quadrant mask,
 // and each wave's list of the staged slots it must visit, in list order and
 // padded with the null slot to a multiple of kUnroll.
+// One staged record, all fields at one LDS address (a wave-uniform index
+// reads them with one base register and immediate offsets).
+struct StageRec {
+  float4 p;
+  float4 q;
+  float2 c;                             // blue, quadrant mask bits
+  uint32_t gid;
+  uint32_t pad;
+};
 struct Stage {
-  float4 p[kBatch + 1];
-  float4 q[kBatch + 1];
-  float2 c[kBatch + 1];                 // blue, quadrant mask bits
-  uint32_t gid[kBatch + 1];
+  StageRec r[kBatch + 1];
   alignas(16) uint32_t list[4][kListStride];
   int len[4];
 };
@@ -203,15 +209,15 @@ __device__ __forceinline__ void stage_batch(Stage& st, const float4* __restrict_
     const float4 r0 = rec[3 * gid];
     const float4 r1 = rec[3 * gid + 1];
     const float4 r2 = rec[3 * gid + 2];
-    st.p[t] = make_float4(r0.x, r0.y, -0.5f * kLog2e * r0.z, -0.5f * kLog2e * r0.w);
-    st.q[t] = make_float4(-0.5f * kLog2e * r1.x, r1.y, r1.z, r1.w);
-    st.c[t] = make_float2(r2.x, __uint_as_float(quad_mask(r0, r1, r2, x0, y0)));
-    st.gid[t] = gid;
+    st.r[t].p = make_float4(r0.x, r0.y, -0.5f * kLog2e * r0.z, -0.5f * kLog2e * r0.w);
+    st.r[t].q = make_float4(-0.5f * kLog2e * r1.x, r1.y, r1.z, r1.w);
+    st.r[t].c = make_float2(r2.x, __uint_as_float(quad_mask(r0, r1, r2, x0, y0)));
+    st.r[t].gid = gid;
   } else {
-    st.p[t] = make_float4(0.f, 0.f, 0.f, 0.f);
-    st.q[t] = make_float4(0.f, 0.f, 0.f, 0.f);
-    st.c[t] = make_float2(0.f, __uint_as_float(0u));
-    st.gid[t] = 0u;
+    st.r[t].p = make_float4(0.f, 0.f, 0.f, 0.f);
+    st.r[t].q = make_float4(0.f, 0.f, 0.f, 0.f);
+    st.r[t].c = make_float2(0.f, __uint_as_float(0u));
+    st.r[t].gid = 0u;
   }
 }
 
@@ -224,7 +230,7 @@ __device__ __forceinline__ void build_list(Stage& st, int cnt, bool all) {
 #pragma unroll
   for (int r = 0; r < kBatch / 64; ++r) {
     const int j = r * 64 + lane;
-    const bool in = (j < cnt) && (all || ((__float_as_uint(st.c[j].y) >> wave) & 1u));
+    const bool in = (j < cnt) && (all || ((__float_as_uint(st.r[j].c.y) >> wave) & 1u));
     const uint64_t bal = __ballot(in);
     if (in) st.list[wave][L + __popcll(bal & below)] = static_cast<uint32_t>(j);
     L += __popcll(bal);
@@ -312,7 +318,7 @@ template <bool SHARES>
 __device__ ChsSlot chs_group(Stage& st, ChsStage& cs, const float4* __restrict__ rec, int cnt, float x0, float y0) {
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   const bool valid = t < cnt;
-  const uint32_t h = valid ? chs_bucket(st.q[t].z, st.q[t].w, st.c[t].x) : 0u;
+  const uint32_t h = valid ? chs_bucket(st.r[t].q.z, st.r[t].q.w, st.r[t].c.x) : 0u;
   // lanes of this wave whose bucket equals this lane's (12 ballots)
   uint64_t same = __ballot(valid);
 #pragma unroll
@@ -352,10 +358,10 @@ __device__ ChsSlot chs_group(Stage& st, ChsStage& cs, const float4* __restrict__
           while (m) {
             const int j = 64 * w + static_cast<int>(__builtin_ctzll(m));
             m &= m - 1;
-            const float4 q = st.q[j];
+            const float4 q = st.r[j].q;
             s0 += q.z;
             s1 += q.w;
-            s2 += st.c[j].x;
+            s2 += st.r[j].c.x;
             if (SHARES) cs.share_o[j] = keep;   // product over the members before j
             keep *= 1.0f - q.y;
           }
@@ -372,26 +378,26 @@ __device__ ChsSlot chs_group(Stage& st, ChsStage& cs, const float4* __restrict__
               m &= ~(1ull << bit);
               const int j = 64 * w + bit;
               cs.share_o[j] *= suf;
-              suf *= 1.0f - st.q[j].y;
+              suf *= 1.0f - st.r[j].q.y;
             }
           }
         }
         const float inv = 1.0f / static_cast<float>(n);
         const float o_hat = 1.0f - keep;
-        const uint32_t gid = st.gid[t];
+        const uint32_t gid = st.r[t].gid;
         const float4 r0 = rec[3 * gid];
         float4 r1 = rec[3 * gid + 1];
         float4 r2 = rec[3 * gid + 2];
         chs_support(r1.y, o_hat, r0.x, r0.y, r2.z, r2.w);
         r1.y = o_hat;
-        float4 q = st.q[t];
+        float4 q = st.r[t].q;
         q.y = o_hat;
         q.z = s0 * inv;
         q.w = s1 * inv;
-        st.q[t] = q;
-        st.c[t] = make_float2(s2 * inv, __uint_as_float(quad_mask(r0, r1, r2, x0, y0)));
+        st.r[t].q = q;
+        st.r[t].c = make_float2(s2 * inv, __uint_as_float(quad_mask(r0, r1, r2, x0, y0)));
       } else {
-        st.c[t].y = __uint_as_float(0u);  // not composited: no wave visits it
+        st.r[t].c.y = __uint_as_float(0u);  // not composited: no wave visits it
       }
     }
   }
@@ -456,9 +462,9 @@ __global__ __launch_bounds__(256) void k_render_fwd(const uint2* __restrict__ ra
   const uint2 rg = ranges[tile];
   const int wave = threadIdx.x >> 6;
   if (threadIdx.x == 0) {
-    st.p[kNull] = make_float4(0.f, 0.f, 0.f, 0.f);
-    st.q[kNull] = make_float4(0.f, 0.f, 0.f, 0.f);
-    st.c[kNull] = make_float2(0.f, 0.f);
+    st.r[kNull].p = make_float4(0.f, 0.f, 0.f, 0.f);
+    st.r[kNull].q = make_float4(0.f, 0.f, 0.f, 0.f);
+    st.r[kNull].c = make_float2(0.f, 0.f);
     s_work = 0;
   }
 
@@ -489,14 +495,14 @@ __global__ __launch_bounds__(256) void k_render_fwd(const uint2* __restrict__ ra
     const int L = st.len[wave];
     float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
     for (int i0 = 0; i0 < L; i0 += kUnroll) {
-      if (__ballot(!done) == 0) break;  // whole wave finished: leave the batch
+      if (__builtin_amdgcn_ballot_w64(!done) == 0) break;  // whole wave finished: leave the batch
       const uint4 jj = *reinterpret_cast<const uint4*>(&st.list[wave][i0]);
       const uint32_t js[kUnroll] = {uniform(jj.x), uniform(jj.y), uniform(jj.z), uniform(jj.w)};
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
         const uint32_t j = js[u];
         if (COUNT) n_exam += (!done && j != kNull) ? 1u : 0u;
-        const bool blend = fwd_pair(st.p[j], st.q[j], st.c[j].x, px, py, m0 + j, T, s0, s1, s2, contrib, done);
+        const bool blend = fwd_pair(st.r[j].p, st.r[j].q, st.r[j].c.x, px, py, m0 + j, T, s0, s1, s2, contrib, done);
         if (COUNT) n_blend += blend ? 1u : 0u;
       }
     }
@@ -580,7 +586,7 @@ __global__ __launch_bounds__(256) void k_render_fwd_light(const uint2* __restric
   for (int j = 0; j < cnt; ++j) {
     const uint32_t mask = uniform(__float_as_uint(ls.c[j].y));
     if (mask == 0) continue;
-    if (__ballot(!(done[0] && done[1] && done[2] && done[3])) == 0) break;
+    if (__builtin_amdgcn_ballot_w64(!(done[0] && done[1] && done[2] && done[3])) == 0) break;
     const float4 p = ls.p[j];
     const float4 q = ls.q[j];
     const float cb = ls.c[j].x;
@@ -638,7 +644,7 @@ __global__ __launch_bounds__(256) void k_chs_table(const uint2* __restrict__ ran
     __syncthreads();
     const bool valid = t < cnt;
     // the entry's own colour and opacity, before the grouping rewrites the batch
-    const float4 own = valid ? make_float4(st.q[t].z, st.q[t].w, st.c[t].x, st.q[t].y) : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 own = valid ? make_float4(st.r[t].q.z, st.r[t].q.w, st.r[t].c.x, st.r[t].q.y) : make_float4(0.f, 0.f, 0.f, 0.f);
     const ChsSlot sl = chs_group<true>(st, cs, rec, cnt, x0, y0);
     __syncthreads();
     chs_release(cs, sl);
@@ -1041,15 +1047,19 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
       const uint32_t j = uniform(st.list[wave][i]);
       if (j == kNull) continue;
       const uint32_t m = m0 + j;
-      if (__ballot(m < ncon) == 0) continue;  // no lane of this wave reaches entry m yet
-      const float4 p = st.p[j];
-      const float4 q = st.q[j];
-      const float cb = st.c[j].x;
+      const uint64_t reach = __builtin_amdgcn_ballot_w64(m < ncon);
+      if (reach == 0) continue;  // no lane of this wave reaches entry m yet
+      const float4 p = st.r[j].p;
+      const float4 q = st.r[j].q;
+      const float cb = st.r[j].c.x;
       float dx, dy, p2, eg, og, nx, ny;
       eval_pair(p, q, px, py, dx, dy, p2, eg, og, nx, ny);
       const float alpha = fminf(kAlphaMax, og);
       const bool ok = (m < ncon) && (p2 <= 0.0f) && (alpha >= kAlphaMin);
-      if (__ballot(ok) == 0) continue;
+      // the wave's test from the compares' own masks (a ballot of the
+      // combined bool would first turn it into an integer and back)
+      if ((reach & __builtin_amdgcn_ballot_w64(p2 <= 0.0f) & __builtin_amdgcn_ballot_w64(alpha >= kAlphaMin)) == 0)
+        continue;
       float v[9];
       bwd_terms(q, cb, ok, nx, ny, alpha, eg, og, G0, G1, G2, T, GS, v);
       const float red8 = wave_sum8(v, lo8);
@@ -1064,7 +1074,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
           if (to_lds)
             atomicAdd(&s_chs[4 * static_cast<int>(j) + out_slot - 5], lane == 63 ? red9 : red8);
           else
-            unsafeAtomicAdd(&g_out[static_cast<int64_t>(st.gid[j]) * kAccStride], lane == 63 ? red9 : red8);
+            unsafeAtomicAdd(&g_out[static_cast<int64_t>(st.r[j].gid) * kAccStride], lane == 63 ? red9 : red8);
         }
       }
     }
@@ -1078,7 +1088,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
         if (r != kChsNone) {
           const float4 tot = s_chs4[r];
           if (tot.x != 0.0f || tot.y != 0.0f || tot.z != 0.0f || tot.w != 0.0f) {
-            float* const row = acc + static_cast<int64_t>(st.gid[t]) * kAccStride;
+            float* const row = acc + static_cast<int64_t>(st.r[t].gid) * kAccStride;
             const float so = cs.share_o[t], sn = cs.inv_n[t];
             unsafeAtomicAdd(row + 5, tot.x * so);
             unsafeAtomicAdd(row + 6, tot.y * sn);
@@ -1093,7 +1103,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
       __syncthreads();
       const int t = threadIdx.x;
       if (t < cnt) {
-        const uint32_t r = det_row(row_of[st.gid[t]], tx, ty);
+        const uint32_t r = det_row(row_of[st.r[t].gid], tx, ty);
         if (r < rows) {
           float* const dst = part + static_cast<size_t>(r) * kDetRow;
 #pragma unroll
@@ -1180,7 +1190,7 @@ __global__ __launch_bounds__(256) void k_render_bwd_light(const uint2* __restric
       for (int t = 0; t < 9; ++t) vs[t] += v[t];
       any = any || ok;
     }
-    if (__ballot(any) == 0) continue;
+    if (__builtin_amdgcn_ballot_w64(any) == 0) continue;
     const float red8 = wave_sum8(vs, lo8);
     const float red9 = wave_sum_to_lane63(vs[8]);
     if constexpr (DET) {
