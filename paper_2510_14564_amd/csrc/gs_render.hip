@@ -492,11 +492,13 @@ __global__ __launch_bounds__(256) void k_render_fwd(const uint2* __restrict__ ra
     __syncthreads();
     if constexpr (CHS) chs_release(cs, sl);
     const uint32_t m0 = base - rg.x + 1u;
-    const int L = st.len[wave];
+    // the wave's list length and row as scalars: the loop control is scalar
+    const int wave_u = static_cast<int>(uniform(static_cast<uint32_t>(wave)));
+    const int L = static_cast<int>(uniform(static_cast<uint32_t>(st.len[wave_u])));
     float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
     for (int i0 = 0; i0 < L; i0 += kUnroll) {
       if (__builtin_amdgcn_ballot_w64(!done) == 0) break;  // whole wave finished: leave the batch
-      const uint4 jj = *reinterpret_cast<const uint4*>(&st.list[wave][i0]);
+      const uint4 jj = *reinterpret_cast<const uint4*>(&st.list[wave_u][i0]);
       const uint32_t js[kUnroll] = {uniform(jj.x), uniform(jj.y), uniform(jj.z), uniform(jj.w)};
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
@@ -1043,11 +1045,15 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
     build_list(st, cnt, false);
     __syncthreads();
     if constexpr (CHS) chs_release(cs, sl);
-    for (int i = st.len[wave] - 1; i >= 0; --i) {
-      const uint32_t j = uniform(st.list[wave][i]);
+    // the wave's list length and row as scalars: the loop control is scalar
+    const int wave_u = static_cast<int>(uniform(static_cast<uint32_t>(wave)));
+    // entry m0 + j reaches this pixel iff j < ncon - m0 (one compare per entry)
+    const uint32_t nrel = ncon > m0 ? ncon - m0 : 0u;
+    for (int i = static_cast<int>(uniform(static_cast<uint32_t>(st.len[wave_u]))) - 1; i >= 0; --i) {
+      const uint32_t j = uniform(st.list[wave_u][i]);
       if (j == kNull) continue;
-      const uint32_t m = m0 + j;
-      const uint64_t reach = __builtin_amdgcn_ballot_w64(m < ncon);
+      const bool live = j < nrel;
+      const uint64_t reach = __builtin_amdgcn_ballot_w64(live);
       if (reach == 0) continue;  // no lane of this wave reaches entry m yet
       const float4 p = st.r[j].p;
       const float4 q = st.r[j].q;
@@ -1055,7 +1061,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
       float dx, dy, p2, eg, og, nx, ny;
       eval_pair(p, q, px, py, dx, dy, p2, eg, og, nx, ny);
       const float alpha = fminf(kAlphaMax, og);
-      const bool ok = (m < ncon) && (p2 <= 0.0f) && (alpha >= kAlphaMin);
+      const bool ok = live && (p2 <= 0.0f) && (alpha >= kAlphaMin);
       // the wave's test from the compares' own masks (a ballot of the
       // combined bool would first turn it into an integer and back)
       if ((reach & __builtin_amdgcn_ballot_w64(p2 <= 0.0f) & __builtin_amdgcn_ballot_w64(alpha >= kAlphaMin)) == 0)
@@ -1070,11 +1076,14 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
         // CHS: a group's opacity and colour sums wait in LDS for the member pass below
         bool to_lds = false;
         if constexpr (CHS) to_lds = out_slot >= 5 && cs.rep[j] != kChsNone;
+        // the Gaussian's row in scalar registers: the atomics take it as
+        // their base and the lane's slot as a 32-bit offset
+        float* const row = acc + static_cast<int64_t>(uniform(st.r[j].gid)) * kAccStride;
         if (writer) {
           if (to_lds)
             atomicAdd(&s_chs[4 * static_cast<int>(j) + out_slot - 5], lane == 63 ? red9 : red8);
           else
-            unsafeAtomicAdd(&g_out[static_cast<int64_t>(st.r[j].gid) * kAccStride], lane == 63 ? red9 : red8);
+            unsafeAtomicAdd(row + out_slot, lane == 63 ? red9 : red8);
         }
       }
     }
