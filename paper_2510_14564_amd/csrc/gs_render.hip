@@ -813,8 +813,9 @@ __device__ __forceinline__ void bwd_terms(const float4& q, float cb, bool ok, fl
   // rounding stays far below the tolerance of the recovered transmittance
   const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
   const float Tm = ok ? T * inv : T;
-  const float Gc = G0 * q.z + G1 * q.w + G2 * cb;
-  const float dalpha = Tm * Gc - inv * GS;
+  // gradient terms only (alpha itself is not re-derived here): fused
+  const float Gc = fmaf(G2, cb, fmaf(G1, q.w, G0 * q.z));
+  const float dalpha = fmaf(Tm, Gc, -(inv * GS));
   const float w = ok ? alpha * Tm : 0.0f;
   GS = fmaf(w, Gc, GS);
   T = Tm;
