@@ -1352,13 +1352,15 @@ __global__ __launch_bounds__(kDirectThreads) __attribute__((amdgpu_waves_per_eu(
 struct FineMasks {
   uint64_t col[kSuper], row[kSuper];
 };
+// (Each mask is the AND of two compare ballots: a ballot of the combined
+// bool would first turn it into an integer and back.)
 __device__ __forceinline__ void fine_masks(uint32_t lr, FineMasks& m) {
   const uint32_t x0 = lr & 15u, xe = (lr >> 4) & 15u, y0 = (lr >> 8) & 15u, ye = (lr >> 12) & 15u;
 #pragma unroll
   for (int k = 0; k < kSuper; ++k) {
     const uint32_t u = static_cast<uint32_t>(k);
-    m.col[k] = __ballot(x0 <= u && u < xe);
-    m.row[k] = __ballot(y0 <= u && u < ye);
+    m.col[k] = __builtin_amdgcn_ballot_w64(x0 <= u) & __builtin_amdgcn_ballot_w64(u < xe);
+    m.row[k] = __builtin_amdgcn_ballot_w64(y0 <= u) & __builtin_amdgcn_ballot_w64(u < ye);
   }
 }
 // Lane t's tile (t & 7, t >> 3): the mask of the wave's entries covering it.
