@@ -761,14 +761,19 @@ __device__ __forceinline__ float dpp_src(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
 }
 
-// Sum over the 64 lanes of a wave with DPP; the total lands in lane 63.
+// Sum over the 64 lanes of a wave with DPP; the total lands in lane 63 (the
+// only lane whose result is defined).  After the row sums, the two row
+// broadcasts leave the rows outside their masks holding whatever the
+// destination register held: lane 63 reads only rows inside the masks
+// (row 3 takes lane 47, then lane 31, which took lane 15), so no zeroed
+// register is needed for the others.
 __device__ __forceinline__ float wave_sum_to_lane63(float v) {
   v += dpp_src<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
   v += dpp_src<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
   v += dpp_src<0x124, 0xF>(v);  // row_ror:4
   v += dpp_src<0x128, 0xF>(v);  // row_ror:8
-  v += dpp_src<0x142, 0xA>(v);  // row_bcast:15 into rows 1, 3
-  v += dpp_src<0x143, 0xC>(v);  // row_bcast:31 into rows 2, 3
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x142, 0xA, 0xF, false));  // row_bcast:15 into rows 1, 3
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x143, 0xC, 0xF, false));  // row_bcast:31 into rows 2, 3
   return v;
 }
 
