@@ -992,7 +992,6 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
   const bool lo8 = (lane & 8) == 0;
   const int out_slot = (lane == 63) ? 8 : kReduceSlot[((lane >> 4) << 1) | ((lane >> 3) & 1)];
   const bool writer = ((lane & 7) == 0) || lane == 63;
-  float* const g_out = acc + out_slot;
 
   float G0 = 0.f, G1 = 0.f, G2 = 0.f, T = 1.0f;
   uint32_t ncon = 0;
