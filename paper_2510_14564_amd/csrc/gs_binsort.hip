@@ -21,7 +21,8 @@
 namespace gs {
 
 constexpr int kRsThreads = 256;
-constexpr int kOsItemsN = 16;   // depth sort of N keys (onesweep): 4096 keys per workgroup
+constexpr int kOsItemsN = 8;    // depth sort of N keys (onesweep): 4096 keys per workgroup of 8 waves
+constexpr int kOsThreads = 512;
 constexpr int kRsItemsK = 16;   // tile sort of K entries: 4096 keys per block
 constexpr int kScanItems = 16;
 constexpr int kScanChunk = 256 * kScanItems;
@@ -83,6 +84,26 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* l
   const uint32_t w0 = lds[0], w1 = lds[1], w2 = lds[2], w3 = lds[3];
   const uint32_t before = (wave > 0 ? w0 : 0u) + (wave > 1 ? w1 : 0u) + (wave > 2 ? w2 : 0u);
   total = ((w0 + w1) + w2) + w3;
+  __syncthreads();
+  return before + incl - v;
+}
+
+// Exclusive prefix over a workgroup of W waves (lds >= W words; free again
+// on return), the same as block_exclusive_scan for W = 4.
+template <int W>
+__device__ __forceinline__ uint32_t block_exclusive_scan_n(uint32_t v, uint32_t* lds, uint32_t& total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t incl = static_cast<uint32_t>(wave_incl_scan(static_cast<int>(v)));
+  if (lane == 63) lds[wave] = incl;
+  __syncthreads();
+  uint32_t before = 0u, all = 0u;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const uint32_t x = lds[w];
+    before += (w < wave) ? x : 0u;
+    all += x;
+  }
+  total = all;
   __syncthreads();
   return before + incl - v;
 }
@@ -471,8 +492,8 @@ __global__ __launch_bounds__(256) void k_os_hist(const uint32_t* __restrict__ ke
 // the values in their final order to vals_final, with each value's rectangle
 // and tile count when rect != NULL, and no keys; the passes after it return
 // at once.  (All passes trivial: pass 0 is terminal and copies.)
-template <int ITEMS>
-__global__ __launch_bounds__(kRsThreads) void k_os_scatter(const uint32_t* __restrict__ keys_in,
+template <int ITEMS, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_os_scatter(const uint32_t* __restrict__ keys_in,
                                                            const uint32_t* __restrict__ vals_in,
                                                            uint32_t* __restrict__ keys_out,
                                                            uint32_t* __restrict__ vals_out, int64_t count,
@@ -484,8 +505,10 @@ __global__ __launch_bounds__(kRsThreads) void k_os_scatter(const uint32_t* __res
                                                            const uint2* __restrict__ rect,
                                                            uint2* __restrict__ rect_out,
                                                            uint32_t* __restrict__ cnt_out, int cshift) {
-  constexpr int CHUNK = kRsThreads * ITEMS;
-  constexpr int PER_WAVE = CHUNK / 4;
+  constexpr int CHUNK = THREADS * ITEMS;
+  constexpr int WAVES = THREADS / 64;
+  constexpr int PER_WAVE = CHUNK / WAVES;
+  static_assert(THREADS >= 256, "one thread per digit");
   __shared__ uint32_t s_vid, s_whole;
   const int passes = (total_bits + 7) / 8;
   const int shift = 8 * pass, nbits = min(8, total_bits - 8 * pass);
@@ -493,7 +516,7 @@ __global__ __launch_bounds__(kRsThreads) void k_os_scatter(const uint32_t* __res
   // per pass behind a barrier), and the chunk's virtual id is drawn alongside
   uint32_t gh[kOsMaxPasses];
 #pragma unroll
-  for (int q = 0; q < kOsMaxPasses; ++q) gh[q] = q < passes ? ghist[q * 256 + threadIdx.x] : 0u;
+  for (int q = 0; q < kOsMaxPasses; ++q) gh[q] = (q < passes && threadIdx.x < 256) ? ghist[q * 256 + threadIdx.x] : 0u;
   if (threadIdx.x == 0) {
     s_whole = 0u;
     s_vid = atomicAdd(counter, 1u);
@@ -524,11 +547,11 @@ __global__ __launch_bounds__(kRsThreads) void k_os_scatter(const uint32_t* __res
   if (mine) atomicOr(&s_whole, mine);
   __shared__ uint32_t sk[CHUNK];
   __shared__ uint32_t sv[CHUNK];
-  __shared__ uint32_t wrun[4][256];   // per-wave running digit counts
+  __shared__ uint32_t wrun[WAVES][256];   // per-wave running digit counts
   __shared__ uint32_t dstart[256];    // block-local start of each digit
   __shared__ uint32_t gbase[256];     // global start of each digit for this block
-  __shared__ uint32_t scan_tmp[256];
-  wrun[0][tid] = 0; wrun[1][tid] = 0; wrun[2][tid] = 0; wrun[3][tid] = 0;
+  __shared__ uint32_t scan_tmp[WAVES];
+  for (int i = tid; i < WAVES * 256; i += THREADS) (&wrun[0][0])[i] = 0u;
   __syncthreads();
   const uint32_t whole = s_whole;
   int last_changing = 0;
@@ -553,7 +576,7 @@ __global__ __launch_bounds__(kRsThreads) void k_os_scatter(const uint32_t* __res
   // every key has the same digit: the pass keeps the order (a copy)
   if (trivial) {
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * CHUNK + threadIdx.x;
-         i < min(count, static_cast<int64_t>(blockIdx.x + 1) * CHUNK); i += kRsThreads)
+         i < min(count, static_cast<int64_t>(blockIdx.x + 1) * CHUNK); i += THREADS)
       emit(i, keys_in[i], vals_in[i]);
     return;
   }
@@ -570,16 +593,20 @@ __global__ __launch_bounds__(kRsThreads) void k_os_scatter(const uint32_t* __res
     if (valid && (peers & below) == 0) wrun[wave][d] = before + static_cast<uint32_t>(__popcll(peers));
   }
   __syncthreads();
-  // per digit: wave offsets and the block's count, then block-local starts
-  const uint32_t c0 = wrun[0][tid], c1 = wrun[1][tid], c2 = wrun[2][tid], c3 = wrun[3][tid];
-  const uint32_t cnt = c0 + c1 + c2 + c3;
+  // per digit (thread tid < 256): wave offsets and the block's count, then
+  // block-local starts
+  const bool digit = tid < 256;
+  uint32_t cnt = 0u;
+  if (digit)
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) cnt += wrun[w][tid];
   uint32_t tot;
-  const uint32_t ds = block_exclusive_scan(cnt, scan_tmp, tot);
+  const uint32_t ds = block_exclusive_scan_n<WAVES>(cnt, scan_tmp, tot);
   // global digit starts of this pass: exclusive scan of the global counts
   uint32_t ghp = 0u;
 #pragma unroll
   for (int q = 0; q < kOsMaxPasses; ++q) ghp = q == pass ? gh[q] : ghp;
-  const uint32_t gd = block_exclusive_scan(static_cast<uint32_t>(tid) <= mask ? ghp : 0u, scan_tmp, tot);
+  const uint32_t gd = block_exclusive_scan_n<WAVES>(static_cast<uint32_t>(tid) <= mask ? ghp : 0u, scan_tmp, tot);
   // decoupled look-back, one digit per thread
   uint32_t prefix = 0;
   if (static_cast<uint32_t>(tid) <= mask) {
@@ -618,12 +645,17 @@ __global__ __launch_bounds__(kRsThreads) void k_os_scatter(const uint32_t* __res
       os_store(mine, (kOsIncl << 30) | ((prefix + cnt) & kOsCountMask));
     }
   }
-  wrun[0][tid] = ds;
-  wrun[1][tid] = ds + c0;
-  wrun[2][tid] = ds + c0 + c1;
-  wrun[3][tid] = ds + c0 + c1 + c2;
-  dstart[tid] = ds;
-  gbase[tid] = gd + prefix;
+  if (digit) {
+    uint32_t run = ds;
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) {
+      const uint32_t c = wrun[w][tid];
+      wrun[w][tid] = run;
+      run += c;
+    }
+    dstart[tid] = ds;
+    gbase[tid] = gd + prefix;
+  }
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
@@ -645,7 +677,7 @@ __global__ __launch_bounds__(kRsThreads) void k_os_scatter(const uint32_t* __res
     uint2 rc[ITEMS];
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
-      const int p = tid + j * kRsThreads;
+      const int p = tid + j * THREADS;
       if (p < nvalid) {
         const uint32_t d = (sk[p] >> shift) & mask;
         g[j] = gbase[d] + (static_cast<uint32_t>(p) - dstart[d]);
@@ -655,7 +687,7 @@ __global__ __launch_bounds__(kRsThreads) void k_os_scatter(const uint32_t* __res
     }
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
-      if (tid + j * kRsThreads < nvalid) {
+      if (tid + j * THREADS < nvalid) {
         vals_final[g[j]] = val[j];
         rect_out[g[j]] = rc[j];
         cnt_out[g[j]] = rect_count(rect_at(rc[j], cshift));
@@ -663,7 +695,7 @@ __global__ __launch_bounds__(kRsThreads) void k_os_scatter(const uint32_t* __res
     }
     return;
   }
-  for (int p = tid; p < nvalid; p += kRsThreads) {
+  for (int p = tid; p < nvalid; p += THREADS) {
     const uint32_t key = sk[p];
     const uint32_t d = (key >> shift) & mask;
     const uint32_t g = gbase[d] + (static_cast<uint32_t>(p) - dstart[d]);
@@ -678,9 +710,8 @@ struct OsWs {
   uint32_t* err;       // [1]
 };
 
-static size_t os_state_words(int64_t count, int items, int passes) {
-  return static_cast<size_t>(passes) * 256 * static_cast<size_t>(ceil_div(std::max<int64_t>(count, 1),
-                                                                          kRsThreads * items));
+static size_t os_state_words(int64_t count, int chunk, int passes) {
+  return static_cast<size_t>(passes) * 256 * static_cast<size_t>(ceil_div(std::max<int64_t>(count, 1), chunk));
 }
 
 // Sorts `count` pairs over key bits [0, total_bits).  Input in (ka, va),
@@ -689,22 +720,22 @@ static size_t os_state_words(int64_t count, int items, int passes) {
 // rect_out and in cnt_out the count of the blocks of 2^cshift x 2^cshift
 // tiles it touches -- its tile count for cshift 0).
 // w.ghist must be zero on entry (k_depth_keys clears both sorts' counts).
-template <int ITEMS>
+template <int ITEMS, int THREADS>
 static gs_status onesweep_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int64_t count,
                                      int total_bits, OsWs w, hipStream_t s, uint32_t* vals_final,
                                      const uint2* rect = nullptr, uint2* rect_out = nullptr,
                                      uint32_t* cnt_out = nullptr, int cshift = 0) {
-  constexpr int CHUNK = kRsThreads * ITEMS;
+  constexpr int CHUNK = THREADS * ITEMS;
   const int passes = (total_bits + 7) / 8;
   if (count <= 0) return GS_OK;
   const int nblocks = static_cast<int>(ceil_div(count, CHUNK));
   gs_status st;
   const int hb = static_cast<int>(std::min<int64_t>(kOsHistBlocks, ceil_div(count, 256 * 8)));
   { TimedLaunch gs_tl("k_os_hist", s); k_os_hist<<<std::max(hb, 1), 256, 0, s>>>(ka, count, total_bits, w.ghist, w.state,
-                                            static_cast<int64_t>(os_state_words(count, ITEMS, passes)), w.counters); }
+                                            static_cast<int64_t>(os_state_words(count, CHUNK, passes)), w.counters); }
   if ((st = check_launch("k_os_hist")) != GS_OK) return st;
   for (int p = 0; p < passes; ++p) {
-    { TimedLaunch gs_tl("k_os_scatter", s); k_os_scatter<ITEMS><<<nblocks, kRsThreads, 0, s>>>(ka, va, kb, vb, count, p, total_bits, w.ghist,
+    { TimedLaunch gs_tl("k_os_scatter", s); k_os_scatter<ITEMS, THREADS><<<nblocks, THREADS, 0, s>>>(ka, va, kb, vb, count, p, total_bits, w.ghist,
                                                        w.state + static_cast<size_t>(p) * nblocks * 256,
                                                        w.counters + p, w.err, vals_final, rect, rect_out, cnt_out,
                                                        cshift); }
@@ -1600,7 +1631,7 @@ static BinWs carve_bin(void* ws, int64_t n, int64_t cap, int tiles_x, int tiles_
   b.scan.total = b.readback;
   b.os.ghist = b.zero;
   b.os.err = reinterpret_cast<uint32_t*>(b.readback + 1);
-  b.os.state = c.take<uint32_t>(os_state_words(n, kOsItemsN, kOsMaxPasses));
+  b.os.state = c.take<uint32_t>(os_state_words(n, kOsThreads * kOsItemsN, kOsMaxPasses));
   b.os.counters = c.take<uint32_t>(kOsMaxPasses);
   if (direct) {
     const size_t nt = static_cast<size_t>(tiles_x) * tiles_y;
@@ -1651,7 +1682,7 @@ gs_status run_bin_sort(int64_t n64, const gs_projected& proj, const DevCam& cam,
     if ((st = check_launch("k_depth_keys")) != GS_OK) return st;
     // the terminal pass also gathers each rank's rectangle and its count of
     // super tiles (direct emission) or tiles
-    if ((st = onesweep_sort_pairs<kOsItemsN>(b.dk0, b.dv0, b.dk1, b.dv1, n, 32, b.os, s, b.order, b.rect,
+    if ((st = onesweep_sort_pairs<kOsItemsN, kOsThreads>(b.dk0, b.dv0, b.dk1, b.dv1, n, 32, b.os, s, b.order, b.rect,
                                              b.rect_rank, b.cnt, b.table ? kSuperShift : 0)) != GS_OK)
       return st;
     const uint32_t* order = b.order;
