@@ -221,6 +221,13 @@ __device__ __forceinline__ void stage_batch(Stage& st, const float4* __restrict_
   }
 }
 
+// The wave's LDS writes are visible to its own lanes (no workgroup barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Stream compaction of the staged batch for this wave (ballot + prefix count).
 // all = true keeps every staged entry (no culling).
 __device__ __forceinline__ void build_list(Stage& st, int cnt, bool all) {
@@ -489,8 +496,12 @@ __global__ __launch_bounds__(256) void k_render_fwd(const uint2* __restrict__ ra
       __syncthreads();
     }
     build_list(st, cnt, COUNT);
-    __syncthreads();
-    if constexpr (CHS) chs_release(cs, sl);
+    if constexpr (CHS) {
+      __syncthreads();
+      chs_release(cs, sl);
+    } else {
+      wave_lds_sync();   // a wave walks only the list it built
+    }
     const uint32_t m0 = base - rg.x + 1u;
     // the wave's list length and row as scalars: the loop control is scalar
     const int wave_u = static_cast<int>(uniform(static_cast<uint32_t>(wave)));
@@ -1048,8 +1059,12 @@ __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ra
       __syncthreads();
     }
     build_list(st, cnt, false);
-    __syncthreads();
-    if constexpr (CHS) chs_release(cs, sl);
+    if constexpr (CHS) {
+      __syncthreads();
+      chs_release(cs, sl);
+    } else {
+      wave_lds_sync();   // a wave walks only the list it built
+    }
     // the wave's list length and row as scalars: the loop control is scalar
     const int wave_u = static_cast<int>(uniform(static_cast<uint32_t>(wave)));
     // entry m0 + j reaches this pixel iff j < ncon - m0 (one compare per entry)
