@@ -42,7 +42,8 @@ ALU_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # Algorithmic work per unit.  FLOPs count an FMA as 2 and every other FP32
 # operation (including exp and reciprocal) as 1.
 #   projection: read 44 + 12 (D+1)^2 B of parameters, write the 36 B record +
-#               depth + radius + tile count per Gaussian
+#               depth + radius + tile count and the 40 B colour gradient (d
+#               colour / d direction and the clamp mask) per Gaussian
 #   bin/sort:   read u, v, radius, depth (16 B) per Gaussian, write the 4 B
 #               list entry per (tile, Gaussian) pair and 8 B of range per tile
 #   forward compositing: 14 flop per examined pair (offset, quadratic form,
@@ -54,13 +55,14 @@ ALU_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 #               gradient terms and their nine sums over pixels); HBM: the
 #               list, each record once, 32 B per pixel read, 36 B per
 #               Gaussian of record gradients written
-#   projection backward: read parameters + 36 B of record gradients, write
-#               parameter gradients (44 + 12 (D+1)^2 B)
+#   projection backward: read the 44 B of geometry parameters, the 40 B
+#               colour gradient and 36 B of record gradients, write parameter
+#               gradients (44 + 12 (D+1)^2 B)
 #   L1 loss: read image and target, write the gradient (36 B per pixel)
 #   Adam: read parameter, gradient and both moments, write parameter and
 #               moments: 28 B per value, 11 + 3 (D+1)^2 values per Gaussian
-PROJECT_BYTES_PER_G = {d: 44 + 12 * (d + 1) ** 2 + 48 for d in range(4)}
-PROJECT_BWD_BYTES_PER_G = {d: 2 * (44 + 12 * (d + 1) ** 2) + 36 for d in range(4)}
+PROJECT_BYTES_PER_G = {d: 44 + 12 * (d + 1) ** 2 + 48 + 40 for d in range(4)}
+PROJECT_BWD_BYTES_PER_G = {d: 44 + 40 + 36 + 44 + 12 * (d + 1) ** 2 for d in range(4)}
 ADAM_BYTES_PER_G = {d: 28 * (11 + 3 * (d + 1) ** 2) for d in range(4)}
 BIN_BYTES_PER_G, BIN_BYTES_PER_DUP, BIN_BYTES_PER_TILE = 16, 4, 8
 FWD_BYTES_PER_DUP, FWD_BYTES_PER_G, FWD_BYTES_PER_PX = 4, 48, 20

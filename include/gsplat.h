@@ -98,12 +98,20 @@ typedef struct {
  *   depth[n]: camera-space t_z (the sort key: Sec. II-A blends in depth order).
  *   radius[n]: ceil(3 sqrt(lambda_max(Sigma'))) pixels, 0 when culled.
  *   tiles_touched[n]: number of 16x16 tiles met by the square of half-width
- *     radius around (u, v), 0 when culled or off-screen. */
+ *     radius around (u, v), 0 when culled or off-screen.
+ *   colour_grad[10][n] (optional, may be NULL; SH colour only): for the
+ *     backward, the derivative of the colour with respect to the unit view
+ *     direction (rows k = 3 ch + axis, 0..8) and in row 9 a bit mask stored
+ *     in the float's bits: bit ch set when channel ch was not clamped at 0,
+ *     bit 3 when the unclamped colour is finite.  When present gs_project
+ *     writes it and the projection backward reads it instead of the 48 SH
+ *     coefficients; when NULL the backward re-reads them. */
 typedef struct {
   float* records;
   float* depth;
   int32_t* radius;
   uint32_t* tiles_touched;
+  float* colour_grad;
 } gs_projected;
 
 /* Gradients with respect to the raw parameters, same layouts as gs_gaussians,
@@ -330,8 +338,9 @@ gs_status gs_render_bwd_2d(int64_t n, const gs_projected* proj, const uint32_t* 
  * grad->mlp [GS_MLP_PARAMS] FP32 (summed over Gaussians in a fixed order) and
  * adds the view direction's share to grad->means; grad->sh may be NULL.  It
  * reads proj->radius (live = radius > 0, as in gs_project) and needs ws of
- * gs_project_bwd_workspace bytes; colour_mode 0 ignores proj and ws (may be
- * NULL / 0). */
+ * gs_project_bwd_workspace bytes; colour_mode 0 reads only proj->colour_grad
+ * (proj may be NULL: the SH coefficients are then re-read) and ignores ws
+ * (may be NULL / 0). */
 gs_status gs_project_bwd_workspace(const gs_gaussians* g, size_t* bytes);
 gs_status gs_project_bwd(const gs_gaussians* g, const gs_camera* cam, const gs_projected* proj, const float* g2d,
                          gs_gaussians_grad* grad, void* ws, size_t ws_bytes, gs_stream stream);

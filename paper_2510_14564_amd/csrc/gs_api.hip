@@ -396,7 +396,7 @@ gs_status gs_render_bwd(const gs_gaussians* g, const gs_camera* cam, const gs_pr
                          deterministic, schedule, &rows, s);
   if (st != GS_OK) return st;
   return launch_project_bwd(*g, d, proj->radius, f.rows ? rows : f.g2d, f.rows, proj->tiles_touched, stats, *grad,
-                            f.wspb, s);
+                            f.wspb, g->colour_mode == 1 ? nullptr : proj->colour_grad, s);
 }
 
 gs_status gs_project_bwd_workspace(const gs_gaussians* g, size_t* bytes) {
@@ -425,7 +425,7 @@ gs_status gs_project_bwd(const gs_gaussians* g, const gs_camera* cam, const gs_p
   }
   if (g->n == 0) return GS_OK;
   return launch_project_bwd(*g, make_devcam(*cam), mlp ? proj->radius : nullptr, g2d, false, nullptr, nullptr, *grad,
-                            ws, static_cast<hipStream_t>(stream));
+                            ws, (!mlp && proj) ? proj->colour_grad : nullptr, static_cast<hipStream_t>(stream));
 }
 
 gs_status gs_mlp_pack(const uint16_t* params, void* packed, gs_stream stream) {

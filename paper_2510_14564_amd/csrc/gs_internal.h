@@ -151,9 +151,11 @@ inline size_t batch_item_ints(int64_t k, int64_t ntiles) {
 // before grad_scale (rows == true; with the learned colour the decoder's
 // backward reads its colour gradient from them too).  stats (optional) gets
 // |dL/d(u, v)| added per Gaussian and count += 1 where tiles_touched > 0.
+// cgrad (optional, SH colour): the projection's colour_grad, read instead of
+// the SH coefficients.
 gs_status launch_project_bwd(const gs_gaussians& g, const DevCam& cam, const int* radius, const float* g2d, bool rows,
                              const uint32_t* tiles_touched, gs_densify_stats* stats, gs_gaussians_grad& grad,
-                             void* ws, hipStream_t s);
+                             void* ws, const float* cgrad, hipStream_t s);
 size_t binsort_workspace(int64_t n, int64_t capacity, int tiles_x, int tiles_y);
 // Exclusive prefix sum of n uint32 values (out may alias in); sums holds
 // scan_sums_words(n) words, total (optional) receives the 64-bit sum.

@@ -131,7 +131,8 @@ __global__ __launch_bounds__(256) void k_project(int n, const float* __restrict_
                                                  const float* __restrict__ quats, const float* __restrict__ logits,
                                                  const float* __restrict__ sh, DevCam cam,
                                                  float4* __restrict__ records, float* __restrict__ depth,
-                                                 int* __restrict__ radius, uint32_t* __restrict__ tiles_touched) {
+                                                 int* __restrict__ radius, uint32_t* __restrict__ tiles_touched,
+                                                 float* __restrict__ cgrad) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   constexpr int NC = DEG < 0 ? 0 : (DEG + 1) * (DEG + 1);
@@ -150,19 +151,54 @@ __global__ __launch_bounds__(256) void k_project(int n, const float* __restrict_
   Geo g;
   bool live = project_geometry(m, s, q, logit, cam, g);
   float rgb[3] = {0.0f, 0.0f, 0.0f};
+  // for the backward (cgrad): d colour / d direction, stored channel by
+  // channel as it is formed, and the clamp decisions
+  bool jac_done = false;
+  uint32_t cmask = 0u;
   if (live && DEG >= 0) {   // DEG < 0: the learned decoder writes the colour afterwards
     float d[3], len;
     view_dir(m, cam, d, len);
     float Y[16];
     sh_basis(DEG, d[0], d[1], d[2], Y);
+    // one pass over the basis functions: the colour sums and, for the
+    // backward, d colour / d direction (each coefficient used once)
+    float acc[3] = {0.0f, 0.0f, 0.0f};
+    float jac[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) acc[ch] += Y[j] * shv[3 * j + ch];
+      if (cgrad && j > 0) {
+        float gx, gy, gz;
+        sh_grad_j(j, d[0], d[1], d[2], gx, gy, gz);
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+          jac[3 * ch] += gx * shv[3 * j + ch];
+          jac[3 * ch + 1] += gy * shv[3 * j + ch];
+          jac[3 * ch + 2] += gz * shv[3 * j + ch];
+        }
+      }
+    }
+    float raw[3];
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
-      float acc = 0.0f;
-#pragma unroll
-      for (int j = 0; j < NC; ++j) acc += Y[j] * shv[3 * j + ch];
-      rgb[ch] = fmaxf(acc + 0.5f, 0.0f);
+      raw[ch] = acc[ch] + 0.5f;
+      rgb[ch] = fmaxf(raw[ch], 0.0f);
     }
     live = isfinite(rgb[0]) && isfinite(rgb[1]) && isfinite(rgb[2]);
+    if (cgrad) {
+      cmask = (raw[0] >= 0.0f ? 1u : 0u) | (raw[1] >= 0.0f ? 2u : 0u) | (raw[2] >= 0.0f ? 4u : 0u) |
+              ((isfinite(raw[0]) && isfinite(raw[1]) && isfinite(raw[2])) ? 8u : 0u);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) cgrad[k * n + i] = jac[k];
+      jac_done = true;
+    }
+  }
+  if (cgrad) {
+    if (!jac_done)
+#pragma unroll
+      for (int k = 0; k < 9; ++k) cgrad[k * n + i] = 0.0f;
+    cgrad[9 * n + i] = __uint_as_float(cmask);
   }
   float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
   int rad = 0;
@@ -194,20 +230,20 @@ gs_status launch_project(const gs_gaussians& g, const DevCam& cam, gs_projected&
   float4* rec = reinterpret_cast<float4*>(out.records);
   if (g.colour_mode == 1) {
     { TimedLaunch gs_tl("k_project<-1>", s); k_project<-1><<<grid, block, 0, s>>>(n, g.means, g.log_scales, g.quats, g.logits, nullptr, cam, rec, out.depth,
-                                         out.radius, out.tiles_touched); }
+                                         out.radius, out.tiles_touched, nullptr); }
     gs_status st = check_launch("k_project");
     if (st != GS_OK) return st;
     return launch_mlp_render(n, g.latents, g.means, out.radius, cam, g.mlp, out.records, s);
   }
   switch (g.sh_degree) {
     case 0: { TimedLaunch gs_tl("k_project<0>", s); k_project<0><<<grid, block, 0, s>>>(n, g.means, g.log_scales, g.quats, g.logits, g.sh, cam, rec,
-                                                 out.depth, out.radius, out.tiles_touched); } break;
+                                                 out.depth, out.radius, out.tiles_touched, out.colour_grad); } break;
     case 1: { TimedLaunch gs_tl("k_project<1>", s); k_project<1><<<grid, block, 0, s>>>(n, g.means, g.log_scales, g.quats, g.logits, g.sh, cam, rec,
-                                                 out.depth, out.radius, out.tiles_touched); } break;
+                                                 out.depth, out.radius, out.tiles_touched, out.colour_grad); } break;
     case 2: { TimedLaunch gs_tl("k_project<2>", s); k_project<2><<<grid, block, 0, s>>>(n, g.means, g.log_scales, g.quats, g.logits, g.sh, cam, rec,
-                                                 out.depth, out.radius, out.tiles_touched); } break;
+                                                 out.depth, out.radius, out.tiles_touched, out.colour_grad); } break;
     default: { TimedLaunch gs_tl("k_project<3>", s); k_project<3><<<grid, block, 0, s>>>(n, g.means, g.log_scales, g.quats, g.logits, g.sh, cam, rec,
-                                                  out.depth, out.radius, out.tiles_touched); } break;
+                                                  out.depth, out.radius, out.tiles_touched, out.colour_grad); } break;
   }
   return check_launch("k_project");
 }
@@ -240,11 +276,14 @@ __global__ __launch_bounds__(256) void k_project_bwd(int n, const float* __restr
                                                      float* __restrict__ g_logits, float* __restrict__ g_sh,
                                                      const uint32_t* __restrict__ tiles_touched,
                                                      float* __restrict__ stat_grad,
-                                                     uint32_t* __restrict__ stat_count) {
+                                                     uint32_t* __restrict__ stat_count,
+                                                     const float* __restrict__ cgrad) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   // DEG < 0: colour comes from the learned decoder, whose backward adds its
   // share to dL/dmean afterwards; only the geometry is differentiated here.
+  // cgrad (from the projection): d colour / d direction and the clamp
+  // decisions, read instead of the SH coefficients.
   constexpr int NC = DEG < 0 ? 0 : (DEG + 1) * (DEG + 1);
   constexpr int NCA = NC > 0 ? NC : 1;
   float m[3], s[3], q[4];
@@ -259,21 +298,34 @@ __global__ __launch_bounds__(256) void k_project_bwd(int n, const float* __restr
   float Y[16];
   float raw[3] = {0, 0, 0};
   float f[NCA][3];
+  float jac[9];
+  uint32_t cmask = 0u;
+  if (DEG >= 0 && cgrad) {
 #pragma unroll
-  for (int j = 0; j < NC; ++j)
+    for (int k = 0; k < 9; ++k) jac[k] = cgrad[k * n + i];
+    cmask = __float_as_uint(cgrad[9 * n + i]);
+  } else {
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) f[j][ch] = sh[(3 * j + ch) * n + i];
+    for (int j = 0; j < NC; ++j)
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) f[j][ch] = sh[(3 * j + ch) * n + i];
+  }
   if (live && DEG >= 0) {
     view_dir(m, cam, d, len);
     sh_basis(DEG, d[0], d[1], d[2], Y);
+    if (cgrad) {
+      live = (cmask & 8u) != 0u;
+    } else {
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-      float acc = 0.0f;
+      for (int ch = 0; ch < 3; ++ch) {
+        float acc = 0.0f;
 #pragma unroll
-      for (int j = 0; j < NC; ++j) acc += Y[j] * f[j][ch];
-      raw[ch] = acc + 0.5f;
+        for (int j = 0; j < NC; ++j) acc += Y[j] * f[j][ch];
+        raw[ch] = acc + 0.5f;
+      }
+      live = isfinite(raw[0]) && isfinite(raw[1]) && isfinite(raw[2]);
+      cmask = (raw[0] >= 0.0f ? 1u : 0u) | (raw[1] >= 0.0f ? 2u : 0u) | (raw[2] >= 0.0f ? 4u : 0u);
     }
-    live = isfinite(raw[0]) && isfinite(raw[1]) && isfinite(raw[2]);
   }
   if (!live) {
 #pragma unroll
@@ -306,17 +358,23 @@ __global__ __launch_bounds__(256) void k_project_bwd(int n, const float* __restr
   if constexpr (DEG >= 0) {
   float gc[3];
 #pragma unroll
-  for (int ch = 0; ch < 3; ++ch) gc[ch] = raw[ch] >= 0.0f ? G[6 + ch] : 0.0f;
+  for (int ch = 0; ch < 3; ++ch) gc[ch] = ((cmask >> ch) & 1u) ? G[6 + ch] : 0.0f;
   float wj[16];
 #pragma unroll
   for (int j = 0; j < NC; ++j) {
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) g_sh[(3 * j + ch) * n + i] = Y[j] * gc[ch];
-    wj[j] = gc[0] * f[j][0] + gc[1] * f[j][1] + gc[2] * f[j][2];
+    if (!cgrad) wj[j] = gc[0] * f[j][0] + gc[1] * f[j][1] + gc[2] * f[j][2];
   }
   if (DEG > 0) {
     float gd[3];
-    sh_basis_vjp(DEG, d[0], d[1], d[2], wj, gd[0], gd[1], gd[2]);
+    if (cgrad) {
+      // dL/dd = sum over channels of dL/dc times d c / d d
+#pragma unroll
+      for (int k = 0; k < 3; ++k) gd[k] = gc[0] * jac[k] + gc[1] * jac[3 + k] + gc[2] * jac[6 + k];
+    } else {
+      sh_basis_vjp(DEG, d[0], d[1], d[2], wj, gd[0], gd[1], gd[2]);
+    }
     const float dd = d[0] * gd[0] + d[1] * gd[1] + d[2] * gd[2];
     const float il = 1.0f / len;
 #pragma unroll
@@ -414,7 +472,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(int n, const float* __restr
 
 gs_status launch_project_bwd(const gs_gaussians& g, const DevCam& cam, const int* radius, const float* g2d, bool rows,
                              const uint32_t* tiles_touched, gs_densify_stats* stats, gs_gaussians_grad& gr, void* ws,
-                             hipStream_t s) {
+                             const float* cgrad, hipStream_t s) {
   const int n = static_cast<int>(g.n);
   if (n == 0) return GS_OK;
   const dim3 block(256), grid(static_cast<unsigned>(ceil_div(n, 256)));
@@ -423,7 +481,7 @@ gs_status launch_project_bwd(const gs_gaussians& g, const DevCam& cam, const int
 #define GS_PB(D, R)                                                                                               \
   k_project_bwd<D, R><<<grid, block, 0, s>>>(n, g.means, g.log_scales, g.quats, g.logits, g.sh, cam, g2d,          \
                                              gr.means, gr.log_scales, gr.quats, gr.logits, gr.sh, tiles_touched, \
-                                             sg, sc)
+                                             sg, sc, cgrad)
   {
     // the kernel's own template name, as profilers report it
     static const char* const kNames[2][4] = {

@@ -81,6 +81,31 @@ __device__ __forceinline__ void sh_basis_vjp(int deg, float x, float y, float z,
   gy += 6.0f * kSH3a * x * y * w[15];
 }
 
+// grad Y_j(d) of one basis function (j a compile-time constant once the
+// caller's loop is unrolled), the terms of sh_basis_vjp for that j.
+__device__ __forceinline__ void sh_grad_j(int j, float x, float y, float z, float& gx, float& gy, float& gz) {
+  const float xx = x * x, yy = y * y, zz = z * z;
+  gx = gy = gz = 0.0f;
+  switch (j) {
+    case 1: gy = -kSH1; break;
+    case 2: gz = kSH1; break;
+    case 3: gx = -kSH1; break;
+    case 4: gx = kSH2a * y; gy = kSH2a * x; break;
+    case 5: gy = -kSH2a * z; gz = -kSH2a * y; break;
+    case 6: gx = -2.0f * kSH2c * x; gy = -2.0f * kSH2c * y; gz = 4.0f * kSH2c * z; break;
+    case 7: gx = -kSH2a * z; gz = -kSH2a * x; break;
+    case 8: gx = 2.0f * kSH2e * x; gy = -2.0f * kSH2e * y; break;
+    case 9: gx = -6.0f * kSH3a * x * y; gy = -kSH3a * (3.0f * xx - 3.0f * yy); break;
+    case 10: gx = kSH3b * y * z; gy = kSH3b * x * z; gz = kSH3b * x * y; break;
+    case 11: gx = 2.0f * kSH3c * x * y; gy = -kSH3c * (4.0f * zz - xx - 3.0f * yy); gz = -8.0f * kSH3c * y * z; break;
+    case 12: gx = -6.0f * kSH3d * x * z; gy = -6.0f * kSH3d * y * z; gz = kSH3d * (6.0f * zz - 3.0f * xx - 3.0f * yy); break;
+    case 13: gx = -kSH3c * (4.0f * zz - 3.0f * xx - yy); gy = 2.0f * kSH3c * x * y; gz = -8.0f * kSH3c * x * z; break;
+    case 14: gx = 2.0f * kSH3f * x * z; gy = -2.0f * kSH3f * y * z; gz = kSH3f * (xx - yy); break;
+    case 15: gx = -kSH3a * (3.0f * xx - 3.0f * yy); gy = 6.0f * kSH3a * x * y; break;
+    default: break;
+  }
+}
+
 __device__ __forceinline__ void view_dir(const float m[3], const DevCam& cam, float d[3], float& len) {
   const float dx = m[0] - cam.centre[0], dy = m[1] - cam.centre[1], dz = m[2] - cam.centre[2];
   len = sqrtf(dx * dx + dy * dy + dz * dz);

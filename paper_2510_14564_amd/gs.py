@@ -84,7 +84,7 @@ class Gaussians(ctypes.Structure):
 
 class Projected(ctypes.Structure):
     _fields_ = [("records", ctypes.c_void_p), ("depth", ctypes.c_void_p), ("radius", ctypes.c_void_p),
-                ("tiles_touched", ctypes.c_void_p)]
+                ("tiles_touched", ctypes.c_void_p), ("colour_grad", ctypes.c_void_p)]
 
 
 class GaussiansGrad(ctypes.Structure):
@@ -224,17 +224,20 @@ def gaussians_struct(means, log_scales, quats, logits, sh, sh_degree: int) -> Ga
 class ProjectedBuffers:
     """Device buffers written by gs_project."""
 
-    def __init__(self, n: int, device):
+    def __init__(self, n: int, device, colour_grad: bool = True):
         self.n = n
         self.records = torch.empty((n, REC_FLOATS), dtype=torch.float32, device=device)
         self.depth = torch.empty(n, dtype=torch.float32, device=device)
         self.radius = torch.empty(n, dtype=torch.int32, device=device)
         self.tiles_touched = torch.empty(n, dtype=torch.int32, device=device)
+        # d colour / d direction and the clamp mask for the backward (SH colour)
+        self.colour_grad = torch.empty((10, n), dtype=torch.float32, device=device) if colour_grad else None
 
     def struct(self) -> Projected:
         p = Projected()
         p.records, p.depth, p.radius, p.tiles_touched = (_ptr(self.records), _ptr(self.depth), _ptr(self.radius),
                                                          _ptr(self.tiles_touched))
+        p.colour_grad = _ptr(self.colour_grad)
         return p
 
 

@@ -200,6 +200,18 @@ def test_staged_parity(gs, name):
         want = o_gr[kk]
         worst = max(worst, grad_close(got[..., sel], want[..., sel], name=kk, mass=cm[kk][..., sel]))
     say(f"  project bwd: worst rel err {worst:.2e}")
+    # the same from the projection's colour gradient (d colour / d direction
+    # and the clamp mask, written by gs_project) instead of the SH coefficients
+    assert out.colour_grad is not None
+    grads_j = {kk: torch.empty_like(v) for kk, v in p.items()}
+    gs.project_bwd(g, gs.camera_struct(cam), g2d, grads_j, proj=out)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for kk in ("means", "log_scales", "quats", "logits", "sh"):
+        got = grads_j[kk].cpu().numpy()
+        worst = max(worst, grad_close(got[..., sel], o_gr[kk][..., sel], name=f"{kk} (colour_grad)",
+                                      mass=cm[kk][..., sel]))
+    say(f"  project bwd from colour_grad: worst rel err {worst:.2e}")
 
 
 def test_empty_and_fully_culled_scenes(gs):
