@@ -161,7 +161,7 @@ __global__ __launch_bounds__(256) void k_dc_cells(int n, const float* __restrict
                                                   uint32_t* __restrict__ range) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
-  const float x = means[i], y = means[n + i], z = means[2 * n + i];
+  const float x = means[i], y = means[static_cast<int64_t>(n) + i], z = means[2 * static_cast<int64_t>(n) + i];
   const float lim = 262144.0f;
   if (!(fabsf(__fmul_rn(x, inv_h)) < lim && fabsf(__fmul_rn(y, inv_h)) < lim && fabsf(__fmul_rn(z, inv_h)) < lim)) {
     atomicOr(range, 1u);
@@ -184,7 +184,7 @@ __global__ __launch_bounds__(256) void k_dc_scatter(int n, const float* __restri
   const uint32_t b = static_cast<uint32_t>(c.w);
   const uint32_t pos = start[b] + atomicAdd(&fill[b], 1u);
   DcPoint d;
-  d.p = make_float4(means[i], means[n + i], means[2 * n + i], __int_as_float(i));
+  d.p = make_float4(means[i], means[static_cast<int64_t>(n) + i], means[2 * static_cast<int64_t>(n) + i], __int_as_float(i));
   d.c = make_int4(c.x, c.y, c.z, 0);
   pts[pos] = d;
 }
@@ -616,10 +616,10 @@ __global__ __launch_bounds__(256) void k_dc_write(int n, DcArrays A, const uint3
   if (kept && o < cap) {
     if (j < 0) {
       for (int c = 0; c < 3; ++c) {
-        A.o_means[c * cap + o] = A.means[c * n + i];
-        A.o_ls[c * cap + o] = A.ls[c * n + i];
+        A.o_means[c * cap + o] = A.means[c * static_cast<int64_t>(n) + i];
+        A.o_ls[c * cap + o] = A.ls[c * static_cast<int64_t>(n) + i];
       }
-      for (int c = 0; c < 4; ++c) A.o_quats[c * cap + o] = A.quats[c * n + i];
+      for (int c = 0; c < 4; ++c) A.o_quats[c * cap + o] = A.quats[c * static_cast<int64_t>(n) + i];
       A.o_logits[o] = A.logits[i];
       for (int c = 0; c < A.nsh; ++c) A.o_sh[c * cap + o] = A.sh[static_cast<int64_t>(c) * n + i];
     } else {
@@ -629,11 +629,11 @@ __global__ __launch_bounds__(256) void k_dc_write(int n, DcArrays A, const uint3
       const float oi = dc_sigmoid(li), oj = dc_sigmoid(lj);
       const float w = oi + oj;
       for (int c = 0; c < 3; ++c) {
-        A.o_means[c * cap + o] = (oi * A.means[c * n + i] + oj * A.means[c * n + j]) / w;
-        A.o_ls[c * cap + o] = logf(0.5f * (expf(A.ls[c * n + i]) + expf(A.ls[c * n + j])));
+        A.o_means[c * cap + o] = (oi * A.means[c * static_cast<int64_t>(n) + i] + oj * A.means[c * static_cast<int64_t>(n) + j]) / w;
+        A.o_ls[c * cap + o] = logf(0.5f * (expf(A.ls[c * static_cast<int64_t>(n) + i]) + expf(A.ls[c * static_cast<int64_t>(n) + j])));
       }
       const int qs = oj > oi ? j : i;
-      for (int c = 0; c < 4; ++c) A.o_quats[c * cap + o] = A.quats[c * n + qs];
+      for (int c = 0; c < 4; ++c) A.o_quats[c * cap + o] = A.quats[c * static_cast<int64_t>(n) + qs];
       // logit of 1 - (1 - oi)(1 - oj): log(o) + softplus(li) + softplus(lj)
       A.o_logits[o] = logf(oi + oj - oi * oj) + dc_softplus(li) + dc_softplus(lj);
       for (int c = 0; c < A.nsh; ++c) {
@@ -651,12 +651,12 @@ __global__ __launch_bounds__(256) void k_dc_write(int n, DcArrays A, const uint3
     if (q < cap) {
       const float t = __fmul_rn(spread, dbar[i]);
       for (int c = 0; c < 3; ++c) {
-        float p = __fadd_rn(A.means[c * n + i], __fmul_rn(t, noise[c * n + i]));
-        p = __fadd_rn(p, __fmul_rn(jitter, noise[(3 + c) * n + i]));
+        float p = __fadd_rn(A.means[c * static_cast<int64_t>(n) + i], __fmul_rn(t, noise[c * static_cast<int64_t>(n) + i]));
+        p = __fadd_rn(p, __fmul_rn(jitter, noise[(3 + c) * static_cast<int64_t>(n) + i]));
         A.o_means[c * cap + q] = p;
-        A.o_ls[c * cap + q] = A.ls[c * n + i];
+        A.o_ls[c * cap + q] = A.ls[c * static_cast<int64_t>(n) + i];
       }
-      for (int c = 0; c < 4; ++c) A.o_quats[c * cap + q] = A.quats[c * n + i];
+      for (int c = 0; c < 4; ++c) A.o_quats[c * cap + q] = A.quats[c * static_cast<int64_t>(n) + i];
       A.o_logits[q] = A.logits[i];
       for (int c = 0; c < A.nsh; ++c) A.o_sh[c * cap + q] = A.sh[static_cast<int64_t>(c) * n + i];
     }

@@ -105,6 +105,24 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
   return start + local;
 }
 
+// Row k of a [rows][n] structure-of-arrays field, advanced to the first of
+// the THREADS consecutive elements of this workgroup.  The pointer is uniform
+// across the workgroup and is pinned to scalar registers (readfirstlane keeps
+// the compiler from folding the lane offset into it), so each load or store
+// takes the scalar base plus the lane's 32-bit threadIdx.x offset: no per-lane
+// 64-bit address arithmetic, and k * n is formed in 64 bits.
+// The result points into the global address space, as the fields do.
+template <typename T>
+using global_ptr = __attribute__((address_space(1))) T*;
+template <int THREADS, typename T>
+__device__ __forceinline__ global_ptr<T> soa_row(T* base, int k, int64_t n) {
+  const uint64_t a = reinterpret_cast<uint64_t>(base + static_cast<int64_t>(blockIdx.x) * THREADS +
+                                                static_cast<int64_t>(k) * n);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(a));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(a >> 32));
+  return reinterpret_cast<global_ptr<T>>((static_cast<uint64_t>(hi) << 32) | lo);
+}
+
 // Per-Gaussian gradient accumulator rows of the compositing backward (atomic
 // mode): nine sums padded to one 64-byte line.  The sums hold the record
 // gradients up to constant factors (powers of 2 ln 2) that grad_scale applies

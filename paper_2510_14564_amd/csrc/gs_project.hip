@@ -4,7 +4,8 @@
 // Sigma' = J W Sigma W^T J^T and colour from SH coefficients.  One thread per
 // Gaussian; parameters are structure-of-arrays so a wave reads 64 consecutive
 // floats per field (256-byte coalesced loads).  The kernel is HBM-bound: it
-// reads 44 + 12 (D+1)^2 bytes and writes 60 bytes per Gaussian.
+// reads 44 + 12 (D+1)^2 bytes and writes 60 bytes per Gaussian, plus the 40
+// bytes of the colour gradient when the backward asks for it.
 #include "gs_internal.h"
 #include "gs_sh.h"
 
@@ -125,29 +126,34 @@ __device__ __forceinline__ void alpha_support(const Geo& g, float& ex, float& ey
 }
 
 
+constexpr int kProjThreads = 256;
+
 template <int DEG>
-__global__ __launch_bounds__(256) void k_project(int n, const float* __restrict__ means,
+__global__ __launch_bounds__(kProjThreads) void k_project(int n, const float* __restrict__ means,
                                                  const float* __restrict__ log_scales,
                                                  const float* __restrict__ quats, const float* __restrict__ logits,
                                                  const float* __restrict__ sh, DevCam cam,
                                                  float4* __restrict__ records, float* __restrict__ depth,
                                                  int* __restrict__ radius, uint32_t* __restrict__ tiles_touched,
                                                  float* __restrict__ cgrad) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.x * kProjThreads + threadIdx.x;
   if (i >= n) return;
+  const unsigned l = threadIdx.x;
+  // element i of row k of a [rows][n] field
+  auto at = [&](auto* p, int k) -> auto& { return soa_row<kProjThreads>(p, k, n)[l]; };
   constexpr int NC = DEG < 0 ? 0 : (DEG + 1) * (DEG + 1);
   float m[3], s[3], q[4];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) { m[k] = means[k * n + i]; s[k] = log_scales[k * n + i]; }
+  for (int k = 0; k < 3; ++k) { m[k] = at(means, k); s[k] = at(log_scales, k); }
 #pragma unroll
-  for (int k = 0; k < 4; ++k) q[k] = quats[k * n + i];
-  const float logit = logits[i];
+  for (int k = 0; k < 4; ++k) q[k] = at(quats, k);
+  const float logit = at(logits, 0);
   // the colour coefficients (most of the bytes read) are loaded with the
   // geometry, before it is known whether the Gaussian is live, so that their
   // latency overlaps the projection arithmetic
   float shv[3 * (NC > 0 ? NC : 1)];
 #pragma unroll
-  for (int j = 0; j < 3 * NC; ++j) shv[j] = sh[j * n + i];
+  for (int j = 0; j < 3 * NC; ++j) shv[j] = at(sh, j);
   Geo g;
   bool live = project_geometry(m, s, q, logit, cam, g);
   float rgb[3] = {0.0f, 0.0f, 0.0f};
@@ -190,15 +196,15 @@ __global__ __launch_bounds__(256) void k_project(int n, const float* __restrict_
       cmask = (raw[0] >= 0.0f ? 1u : 0u) | (raw[1] >= 0.0f ? 2u : 0u) | (raw[2] >= 0.0f ? 4u : 0u) |
               ((isfinite(raw[0]) && isfinite(raw[1]) && isfinite(raw[2])) ? 8u : 0u);
 #pragma unroll
-      for (int k = 0; k < 9; ++k) cgrad[k * n + i] = jac[k];
+      for (int k = 0; k < 9; ++k) at(cgrad, k) = jac[k];
       jac_done = true;
     }
   }
   if (cgrad) {
     if (!jac_done)
 #pragma unroll
-      for (int k = 0; k < 9; ++k) cgrad[k * n + i] = 0.0f;
-    cgrad[9 * n + i] = __uint_as_float(cmask);
+      for (int k = 0; k < 9; ++k) at(cgrad, k) = 0.0f;
+    at(cgrad, 9) = __uint_as_float(cmask);
   }
   float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
   int rad = 0;
@@ -215,18 +221,19 @@ __global__ __launch_bounds__(256) void k_project(int n, const float* __restrict_
     int x0, x1, y0, y1;
     cnt = static_cast<uint32_t>(tile_rect(g.u, g.v, rad, cam.tiles_x, cam.tiles_y, x0, x1, y0, y1));
   }
-  records[3 * i] = r0;
-  records[3 * i + 1] = r1;
-  records[3 * i + 2] = r2;
-  depth[i] = dep;
-  radius[i] = rad;
-  tiles_touched[i] = cnt;
+  float4* rec = records + 3 * static_cast<int64_t>(blockIdx.x) * kProjThreads;
+  rec[3 * l] = r0;
+  rec[3 * l + 1] = r1;
+  rec[3 * l + 2] = r2;
+  at(depth, 0) = dep;
+  at(radius, 0) = rad;
+  at(tiles_touched, 0) = cnt;
 }
 
 gs_status launch_project(const gs_gaussians& g, const DevCam& cam, gs_projected& out, hipStream_t s) {
   const int n = static_cast<int>(g.n);
   if (n == 0) return GS_OK;
-  const dim3 block(256), grid(static_cast<unsigned>(ceil_div(n, 256)));
+  const dim3 block(kProjThreads), grid(static_cast<unsigned>(ceil_div(n, kProjThreads)));
   float4* rec = reinterpret_cast<float4*>(out.records);
   if (g.colour_mode == 1) {
     { TimedLaunch gs_tl("k_project<-1>", s); k_project<-1><<<grid, block, 0, s>>>(n, g.means, g.log_scales, g.quats, g.logits, nullptr, cam, rec, out.depth,
@@ -266,7 +273,7 @@ gs_status launch_project(const gs_gaussians& g, const DevCam& cam, gs_projected&
 // stat_grad[i] += |(dL/du, dL/dv)| (pixel units) and stat_count[i] += 1 for
 // every Gaussian whose footprint meets a tile.
 template <int DEG, bool ROWS>
-__global__ __launch_bounds__(256) void k_project_bwd(int n, const float* __restrict__ means,
+__global__ __launch_bounds__(kProjThreads) void k_project_bwd(int n, const float* __restrict__ means,
                                                      const float* __restrict__ log_scales,
                                                      const float* __restrict__ quats,
                                                      const float* __restrict__ logits,
@@ -278,8 +285,11 @@ __global__ __launch_bounds__(256) void k_project_bwd(int n, const float* __restr
                                                      float* __restrict__ stat_grad,
                                                      uint32_t* __restrict__ stat_count,
                                                      const float* __restrict__ cgrad) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.x * kProjThreads + threadIdx.x;
   if (i >= n) return;
+  const unsigned l = threadIdx.x;
+  // element i of row k of a [rows][n] field
+  auto at = [&](auto* p, int k) -> auto& { return soa_row<kProjThreads>(p, k, n)[l]; };
   // DEG < 0: colour comes from the learned decoder, whose backward adds its
   // share to dL/dmean afterwards; only the geometry is differentiated here.
   // cgrad (from the projection): d colour / d direction and the clamp
@@ -288,10 +298,10 @@ __global__ __launch_bounds__(256) void k_project_bwd(int n, const float* __restr
   constexpr int NCA = NC > 0 ? NC : 1;
   float m[3], s[3], q[4];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) { m[k] = means[k * n + i]; s[k] = log_scales[k * n + i]; }
+  for (int k = 0; k < 3; ++k) { m[k] = at(means, k); s[k] = at(log_scales, k); }
 #pragma unroll
-  for (int k = 0; k < 4; ++k) q[k] = quats[k * n + i];
-  const float logit = logits[i];
+  for (int k = 0; k < 4; ++k) q[k] = at(quats, k);
+  const float logit = at(logits, 0);
   Geo g;
   bool live = project_geometry(m, s, q, logit, cam, g);
   float d[3] = {0, 0, 0}, len = 1.0f;
@@ -302,13 +312,13 @@ __global__ __launch_bounds__(256) void k_project_bwd(int n, const float* __restr
   uint32_t cmask = 0u;
   if (DEG >= 0 && cgrad) {
 #pragma unroll
-    for (int k = 0; k < 9; ++k) jac[k] = cgrad[k * n + i];
-    cmask = __float_as_uint(cgrad[9 * n + i]);
+    for (int k = 0; k < 9; ++k) jac[k] = at(cgrad, k);
+    cmask = __float_as_uint(at(cgrad, 9));
   } else {
 #pragma unroll
     for (int j = 0; j < NC; ++j)
 #pragma unroll
-      for (int ch = 0; ch < 3; ++ch) f[j][ch] = sh[(3 * j + ch) * n + i];
+      for (int ch = 0; ch < 3; ++ch) f[j][ch] = at(sh, 3 * j + ch);
   }
   if (live && DEG >= 0) {
     view_dir(m, cam, d, len);
@@ -329,28 +339,29 @@ __global__ __launch_bounds__(256) void k_project_bwd(int n, const float* __restr
   }
   if (!live) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) { g_means[k * n + i] = 0.0f; g_scales[k * n + i] = 0.0f; }
+    for (int k = 0; k < 3; ++k) { at(g_means, k) = 0.0f; at(g_scales, k) = 0.0f; }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) g_quats[k * n + i] = 0.0f;
-    g_logits[i] = 0.0f;
+    for (int k = 0; k < 4; ++k) at(g_quats, k) = 0.0f;
+    at(g_logits, 0) = 0.0f;
 #pragma unroll
-    for (int j = 0; j < 3 * NC; ++j) g_sh[j * n + i] = 0.0f;
+    for (int j = 0; j < 3 * NC; ++j) at(g_sh, j) = 0.0f;
     return;
   }
   float G[GS_G2D];
   if constexpr (ROWS) {
-    const float4* row = reinterpret_cast<const float4*>(g2d + static_cast<int64_t>(i) * kAccStride);
+    const float4* row = reinterpret_cast<const float4*>(g2d + static_cast<int64_t>(blockIdx.x) * kProjThreads * kAccStride) +
+                        l * (kAccStride / 4);
     const float4 a = row[0], b = row[1], c = row[2];
     const float v[GS_G2D] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x};
 #pragma unroll
     for (int k = 0; k < GS_G2D; ++k) G[k] = v[k] * grad_scale(k);
   } else {
 #pragma unroll
-    for (int k = 0; k < GS_G2D; ++k) G[k] = g2d[k * n + i];
+    for (int k = 0; k < GS_G2D; ++k) G[k] = at(g2d, k);
   }
-  if (stat_grad && tiles_touched[i] > 0) {
-    stat_grad[i] += sqrtf(G[0] * G[0] + G[1] * G[1]);
-    stat_count[i] += 1u;
+  if (stat_grad && at(tiles_touched, 0) > 0) {
+    at(stat_grad, 0) += sqrtf(G[0] * G[0] + G[1] * G[1]);
+    at(stat_count, 0) += 1u;
   }
   float gm[3] = {0.0f, 0.0f, 0.0f};
 
@@ -363,7 +374,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(int n, const float* __restr
 #pragma unroll
   for (int j = 0; j < NC; ++j) {
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) g_sh[(3 * j + ch) * n + i] = Y[j] * gc[ch];
+    for (int ch = 0; ch < 3; ++ch) at(g_sh, 3 * j + ch) = Y[j] * gc[ch];
     if (!cgrad) wj[j] = gc[0] * f[j][0] + gc[1] * f[j][1] + gc[2] * f[j][2];
   }
   if (DEG > 0) {
@@ -383,7 +394,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(int n, const float* __restr
   }
 
   // ---- opacity
-  g_logits[i] = G[5] * g.o * (1.0f - g.o);
+  at(g_logits, 0) = G[5] * g.o * (1.0f - g.o);
 
   // ---- Sigma' gradient: the render backward already converted it from the
   // conic pair by pair; G[3] counts both off-diagonal entries.
@@ -451,7 +462,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(int n, const float* __restr
       gM[3 * a + b] = 2.0f * (gS[3 * a] * M[b] + gS[3 * a + 1] * M[3 + b] + gS[3 * a + 2] * M[6 + b]);
 #pragma unroll
   for (int k = 0; k < 3; ++k)
-    g_scales[k * n + i] = g.S[k] * (R[k] * gM[k] + R[3 + k] * gM[3 + k] + R[6 + k] * gM[6 + k]);
+    at(g_scales, k) = g.S[k] * (R[k] * gM[k] + R[3 + k] * gM[3 + k] + R[6 + k] * gM[6 + k]);
   float gR[9];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
@@ -465,9 +476,9 @@ __global__ __launch_bounds__(256) void k_project_bwd(int n, const float* __restr
   gq[3] = 2.0f * (w * (gR[3] - gR[1]) + x * (gR[6] + gR[2]) + y * (gR[7] + gR[5])) - 4.0f * z * (gR[0] + gR[4]);
   const float qd = w * gq[0] + x * gq[1] + y * gq[2] + z * gq[3];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) g_quats[k * n + i] = (gq[k] - g.qn[k] * qd) * g.qinv;
+  for (int k = 0; k < 4; ++k) at(g_quats, k) = (gq[k] - g.qn[k] * qd) * g.qinv;
 #pragma unroll
-  for (int k = 0; k < 3; ++k) g_means[k * n + i] = gm[k];
+  for (int k = 0; k < 3; ++k) at(g_means, k) = gm[k];
 }
 
 gs_status launch_project_bwd(const gs_gaussians& g, const DevCam& cam, const int* radius, const float* g2d, bool rows,
@@ -475,7 +486,7 @@ gs_status launch_project_bwd(const gs_gaussians& g, const DevCam& cam, const int
                              const float* cgrad, hipStream_t s) {
   const int n = static_cast<int>(g.n);
   if (n == 0) return GS_OK;
-  const dim3 block(256), grid(static_cast<unsigned>(ceil_div(n, 256)));
+  const dim3 block(kProjThreads), grid(static_cast<unsigned>(ceil_div(n, kProjThreads)));
   float* sg = stats ? stats->grad_norm_sum : nullptr;
   uint32_t* sc = stats ? stats->visible_count : nullptr;
 #define GS_PB(D, R)                                                                                               \

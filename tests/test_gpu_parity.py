@@ -311,6 +311,57 @@ def _sampled_compositing(gs, scene, cam, p, g, out, h, o, pl, ranges, k, o_pl, o
     say(f"  render bwd + project bwd: worst rel err {worst:.2e}")
 
 
+def test_projection_row_offsets_beyond_int32(gs):
+    """Projection and its backward (both colour paths) at n = 48M, SH degree
+    3: the last SH rows start beyond 2^31 elements (47 n > 2^31), so row
+    offsets must be formed in 64 bits.  The scene is a 20k-Gaussian scene
+    repeated 2,400 times, and every Gaussian's work depends only on its own
+    parameters, so each output must equal bit for bit that of its copy in a
+    run on the small scene, whose projection is checked against the oracle
+    here and whose backward the staged test checks."""
+    small, cam = _case("ragged")
+    n0, reps = small.n, 2400
+    n = n0 * reps
+    assert small.sh_degree == 3 and 47 * n > 2 ** 31
+    say(f"[large n] n={n}")
+    p0, g0, out0, _, _ = _project_stage(gs, small, cam)
+    cs = gs.camera_struct(cam)
+    rng = torch.Generator(device=DEV).manual_seed(4242)
+    g2d0 = torch.randn((9, n0), generator=rng, device=DEV, dtype=torch.float32)
+    want = {}
+    for path, proj in (("sh", None), ("jacobian", out0)):
+        gr = {k: torch.empty_like(v) for k, v in p0.items()}
+        gs.project_bwd(g0, cs, g2d0, gr, proj=proj)
+        want[path] = gr
+    torch.cuda.synchronize()
+
+    def tile(v):
+        return v.repeat(*([1] * (v.dim() - 1)), reps)
+
+    p = {k: tile(v) for k, v in p0.items()}
+    g = gs.gaussians_struct(p["means"], p["log_scales"], p["quats"], p["logits"], p["sh"], 3)
+    out = gs.ProjectedBuffers(n, DEV)
+    gs.project(g, cs, out)
+    torch.cuda.synchronize()
+    # the last two copies in full and 100k Gaussians drawn over the whole range
+    idx = torch.cat([torch.arange(n - 2 * n0, n, device=DEV),
+                     torch.randint(0, n, (100000,), generator=rng, device=DEV)])
+    src = idx % n0
+    assert torch.equal(out.records[idx], out0.records[src]), "records"
+    for name in ("depth", "radius", "tiles_touched"):
+        assert torch.equal(getattr(out, name)[idx], getattr(out0, name)[src]), name
+    assert torch.equal(out.colour_grad[:, idx], out0.colour_grad[:, src]), "colour_grad"
+    g2d = tile(g2d0)
+    for path, proj in (("sh", None), ("jacobian", out)):
+        gr = {k: torch.empty_like(v) for k, v in p.items()}
+        gs.project_bwd(g, cs, g2d, gr, proj=proj)
+        torch.cuda.synchronize()
+        for k in gr:
+            assert torch.equal(gr[k][..., idx], want[path][k][..., src]), (path, k)
+        del gr
+    say(f"  projection and backward at n={n}: bit-equal to the small scene's run")
+
+
 def test_heavy_workload_parity(gs):
     """Heavy workload (3M anisotropic Gaussians, 1920x1080, about 2.7e8
     entries) in the bench's launch configuration.  The whole bin/sort is
