@@ -124,11 +124,14 @@ __device__ __forceinline__ global_ptr<T> soa_row(T* base, int k, int64_t n) {
 }
 
 // Per-Gaussian gradient accumulator rows of the compositing backward (atomic
-// mode): nine sums padded to one 64-byte line.  The sums hold the record
+// mode): nine sums padded to 48 bytes (three float4s; a row lies within one
+// 128-byte L2 line for six Gaussians in eight and straddles two for the
+// rest; 64-byte rows, one line each, cost a third more HBM traffic to clear
+// and re-read and measured slower).  The sums hold the record
 // gradients up to constant factors (powers of 2 ln 2) that grad_scale applies
 // once per Gaussian: u, v, Sigma'_xx, Sigma'_xy (both entries), Sigma'_yy,
 // opacity, r, g, b.
-constexpr int kAccStride = 16;
+constexpr int kAccStride = 12;
 constexpr float kLn2 = 0.6931471805599453f;
 __device__ __forceinline__ float grad_scale(int c) {
   constexpr float l1 = 2.0f * kLn2, l2 = 2.0f * kLn2 * kLn2;

@@ -857,13 +857,15 @@ __device__ __forceinline__ void bwd_terms(const float4& q, float cb, bool ok, fl
   v[8] = G2 * w;                             // dL/db
 }
 
-// g2d[k][i] = acc[i][k]: the [9][n] output from the line-per-Gaussian rows.
+// g2d[k][i] = acc[i][k]: the [9][n] output from the per-Gaussian rows.
 __global__ __launch_bounds__(256) void k_acc_to_g2d(int n, const float4* __restrict__ acc, float* __restrict__ g2d) {
+  static_assert(kAccStride % 4 == 0 && kAccStride >= GS_G2D, "rows of whole float4s holding the nine sums");
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
-  const float4 a = acc[4 * static_cast<int64_t>(i)];
-  const float4 b = acc[4 * static_cast<int64_t>(i) + 1];
-  const float4 c = acc[4 * static_cast<int64_t>(i) + 2];
+  const float4* row = acc + static_cast<int64_t>(kAccStride / 4) * i;
+  const float4 a = row[0];
+  const float4 b = row[1];
+  const float4 c = row[2];
   const float v[9] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x};
 #pragma unroll
   for (int k = 0; k < GS_G2D; ++k) g2d[static_cast<int64_t>(k) * n + i] = v[k] * grad_scale(k);
@@ -948,9 +950,9 @@ __global__ __launch_bounds__(256) void k_det_reduce(int n, const uint32_t* __res
 // n_contrib are never touched; a wave visits only the entries whose
 // alpha-support box meets its quadrant.  The nine per-pair gradients are summed
 // over the wave and added by nine lanes at once to the Gaussian's row of the
-// accumulator acc[n][kAccStride]: one 64-byte line per Gaussian, so the nine
-// atomics of an instruction meet in one line (the [9][n] output is written
-// from it afterwards).  DET: the sums go to the entry's row of `part` instead
+// accumulator acc[n][kAccStride]: a 48-byte row per Gaussian, so the nine
+// atomics of an instruction meet in one or two L2 lines (the [9][n] output
+// is written from it afterwards).  DET: the sums go to the entry's row of `part` instead
 // (deterministic reduction above).
 template <bool DET, bool CHS = false>
 __global__ __launch_bounds__(256) void k_render_bwd(const uint2* __restrict__ ranges,
