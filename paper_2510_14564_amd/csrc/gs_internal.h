@@ -161,8 +161,9 @@ constexpr int kPlanHeader = 16;
 size_t plan_ints(int ntiles);
 gs_status launch_tile_plan(int ntiles, const uint32_t* ranges, const uint32_t* counts, float heavy_factor,
                            int light_max, int32_t* plan, hipStream_t s);
+// Also clears zero[0, zero_n4) (float4s) in the same launch when zero_n4 > 0.
 gs_status launch_batch_plan(int ntiles, const uint32_t* ranges, const uint32_t* work, int light_max, int32_t* items,
-                            int32_t* light, hipStream_t s);
+                            int32_t* light, float4* zero, int64_t zero_n4, hipStream_t s);
 // Backward work items (pairs) for K entries over ntiles tiles, with header.
 inline size_t batch_item_ints(int64_t k, int64_t ntiles) {
   return 16 + 2 * static_cast<size_t>(k / 256 + ntiles + 1);

@@ -128,10 +128,20 @@ __global__ __launch_bounds__(kPlanThreads) void k_tile_plan(int ntiles, const ui
 // light list instead (a plan with H = M = 0), or nowhere when light is NULL
 // (with light_max = 0: the tiles whose pixels blend nothing).
 // items: [0] item count, from kPlanHeader pairs (tile, batch).
+// Workgroup 0 builds the plan; the others, if any, clear zero[0, zero_n4)
+// meanwhile (the backward's accumulator rows), so that the fill runs under
+// the one-workgroup plan instead of after it.
 __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(int ntiles, const uint2* __restrict__ ranges,
                                                              const uint32_t* __restrict__ work, int light_max,
                                                              int32_t* __restrict__ items,
-                                                             int32_t* __restrict__ light) {
+                                                             int32_t* __restrict__ light,
+                                                             float4* __restrict__ zero, int64_t zero_n4) {
+  if (blockIdx.x > 0) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x - 1) * kPlanThreads;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x - 1) * kPlanThreads + threadIdx.x; i < zero_n4; i += stride)
+      zero[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    return;
+  }
   __shared__ uint32_t s_scan[2][kPlanThreads / 64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int per = (ntiles + kPlanThreads - 1) / kPlanThreads;
@@ -213,9 +223,10 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(int ntiles, const u
 }
 
 gs_status launch_batch_plan(int ntiles, const uint32_t* ranges, const uint32_t* work, int light_max, int32_t* items,
-                            int32_t* light, hipStream_t s) {
-  { TimedLaunch gs_tl("k_batch_plan", s); k_batch_plan<<<1, kPlanThreads, 0, s>>>(ntiles, reinterpret_cast<const uint2*>(ranges), work, light_max, items,
-                                          light); }
+                            int32_t* light, float4* zero, int64_t zero_n4, hipStream_t s) {
+  const unsigned fill = zero_n4 > 0 ? static_cast<unsigned>(std::min<int64_t>(ceil_div(zero_n4, kPlanThreads), 1024)) : 0u;
+  { TimedLaunch gs_tl("k_batch_plan", s); k_batch_plan<<<1 + fill, kPlanThreads, 0, s>>>(ntiles, reinterpret_cast<const uint2*>(ranges), work, light_max, items,
+                                          light, zero, zero_n4); }
   return check_launch("k_batch_plan");
 }
 

@@ -1307,8 +1307,9 @@ gs_status launch_render_bwd(int64_t n, const gs_projected& proj, const uint32_t*
           reinterpret_cast<float4*>(det.part), n4); }
       if ((st = check_launch("k_zero4")) != GS_OK) return st;
     }
-  } else {
-    // a fill kernel rather than a memset node, so that the call can be captured in a graph
+  } else if (schedule == 0) {
+    // a fill kernel rather than a memset node, so that the call can be captured
+    // in a graph (the other schedules clear the rows under the batch plan)
     const int64_t n4 = static_cast<int64_t>(kAccStride / 4) * n;
     { TimedLaunch gs_tl("k_zero4", s); k_zero4<<<static_cast<unsigned>(std::min<int64_t>(ceil_div(n4, 256), 8192)), 256, 0, s>>>(
         reinterpret_cast<float4*>(acc), n4); }
@@ -1340,7 +1341,9 @@ gs_status launch_render_bwd(int64_t n, const gs_projected& proj, const uint32_t*
     const float* c_ckpt = tail + plan_ints(ntiles) + ntiles;
     int32_t* light = schedule == 2 ? reinterpret_cast<int32_t*>(w + 256) : nullptr;
     int32_t* items = reinterpret_cast<int32_t*>(w + bwd_items_offset(ntiles));
-    st = launch_batch_plan(ntiles, ranges, tile_work, schedule == 2 ? kLightMax : 0, items, light, s);
+    st = launch_batch_plan(ntiles, ranges, tile_work, schedule == 2 ? kLightMax : 0, items, light,
+                           deterministic ? nullptr : reinterpret_cast<float4*>(acc),
+                           deterministic ? 0 : static_cast<int64_t>(kAccStride / 4) * n, s);
     if (st != GS_OK) return st;
     if (light) {
       const unsigned lg = static_cast<unsigned>(ceil_div(ntiles, 4));
