@@ -201,11 +201,10 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(int ntiles, const u
     ex[k] += before;
     tot[k] = all;
   }
+  // (tile, batch) pairs as one 8-byte store each (items is 8-byte aligned)
+  int2* const pairs = reinterpret_cast<int2*>(items + kPlanHeader);
   auto put = [&](int t, uint32_t nb, bool lt) {
-    for (uint32_t j = 0; j < nb; ++j) {
-      items[kPlanHeader + 2 * (ex[0] + j)] = t;
-      items[kPlanHeader + 2 * (ex[0] + j) + 1] = static_cast<int32_t>(j);
-    }
+    for (uint32_t j = 0; j < nb; ++j) pairs[ex[0] + j] = make_int2(t, static_cast<int32_t>(j));
     ex[0] += nb;
     if (light && lt) light[kPlanHeader + ex[1]++] = t;
   };

@@ -1235,7 +1235,7 @@ __global__ __launch_bounds__(256) void k_render_bwd_light(const uint2* __restric
 
 // Workspace: 256 reserved bytes, the light-tile list (plan layout), the batch
 // items, then the accumulator rows (256-byte aligned).
-static size_t bwd_items_offset(int ntiles) { return 256 + sizeof(int32_t) * plan_ints(ntiles); }
+static size_t bwd_items_offset(int ntiles) { return (256 + sizeof(int32_t) * plan_ints(ntiles) + 15) / 16 * 16; }
 static size_t bwd_acc_offset(int64_t k, int ntiles) {
   return (bwd_items_offset(ntiles) + sizeof(int32_t) * batch_item_ints(k, ntiles) + 255) / 256 * 256;
 }
