@@ -201,11 +201,17 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(int ntiles, const u
     ex[k] += before;
     tot[k] = all;
   }
-  // (tile, batch) pairs as one 8-byte store each (items is 8-byte aligned)
+  // (tile, batch) pairs, two per 16-byte store where they pair up (items
+  // is 16-byte aligned)
   int2* const pairs = reinterpret_cast<int2*>(items + kPlanHeader);
+  int4* const quads = reinterpret_cast<int4*>(items + kPlanHeader);
   auto put = [&](int t, uint32_t nb, bool lt) {
-    for (uint32_t j = 0; j < nb; ++j) pairs[ex[0] + j] = make_int2(t, static_cast<int32_t>(j));
-    ex[0] += nb;
+    uint32_t e = ex[0], j = 0;
+    if ((e & 1u) && j < nb) pairs[e++] = make_int2(t, static_cast<int32_t>(j++));
+    for (; j + 1 < nb; j += 2, e += 2)
+      quads[e >> 1] = make_int4(t, static_cast<int32_t>(j), t, static_cast<int32_t>(j + 1));
+    if (j < nb) pairs[e++] = make_int2(t, static_cast<int32_t>(j++));
+    ex[0] = e;
     if (light && lt) light[kPlanHeader + ex[1]++] = t;
   };
   if (regs) {
