@@ -1065,14 +1065,19 @@ struct StartArgs {
 constexpr int kStartRegs = kDirectMaxTiles / 1024;   // a thread's totals, all loads in flight at once
 __global__ __launch_bounds__(1024) void k_tile_starts(const uint32_t* __restrict__ total, StartArgs a) {
   __shared__ unsigned long long s_w[16];
+  // the tile totals, then the tile starts: read and written tile by tile
+  // across the lanes (coalesced), scanned in runs of consecutive tiles
+  __shared__ uint32_t s_t[kDirectMaxTiles];
   const int tid = threadIdx.x;
+  for (int t = tid; t < a.ntiles; t += 1024) s_t[t] = total[t];
+  __syncthreads();
   const int per = (a.ntiles + 1023) / 1024;   // at most kStartRegs: direct_ok bounds the tiles
   const int t0 = min(a.ntiles, tid * per), t1 = min(a.ntiles, t0 + per);
   uint32_t v[kStartRegs];
   unsigned long long sum = 0;
 #pragma unroll
   for (int k = 0; k < kStartRegs; ++k) {
-    v[k] = t0 + k < t1 ? total[t0 + k] : 0u;
+    v[k] = t0 + k < t1 ? s_t[t0 + k] : 0u;
     sum += v[k];
   }
   unsigned long long all;
@@ -1085,15 +1090,19 @@ __global__ __launch_bounds__(1024) void k_tile_starts(const uint32_t* __restrict
     if (a.k_dev) a.k_dev[0] = K;
     *a.fits = fits ? 1u : 0u;
   }
+  __syncthreads();   // every thread has read its totals
 #pragma unroll
   for (int k = 0; k < kStartRegs; ++k) {
-    const int t = t0 + k;
-    if (t < t1) {
-      a.start[t] = static_cast<uint32_t>(run);
-      a.ranges[t] = fits ? make_uint2(static_cast<uint32_t>(run), static_cast<uint32_t>(run + v[k]))
-                         : make_uint2(0u, 0u);
-    }
+    if (t0 + k < t1) s_t[t0 + k] = static_cast<uint32_t>(run);
     run += v[k];
+  }
+  __syncthreads();
+  // tile t ends where tile t + 1 starts (the last one at the total)
+  for (int t = tid; t < a.ntiles; t += 1024) {
+    const uint32_t st = s_t[t];
+    const uint32_t en = t + 1 < a.ntiles ? s_t[t + 1] : static_cast<uint32_t>(all);
+    a.start[t] = st;
+    a.ranges[t] = fits ? make_uint2(st, en) : make_uint2(0u, 0u);
   }
 }
 
